@@ -1,0 +1,296 @@
+"""ctypes binding of the CPU reference (test infrastructure only).
+
+Only the test-suite, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` import this package. The product path (``paper_2311_12973_amd``) never
+does: it must fail loudly when its HIP library is missing instead of falling back
+here.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB, build_oracle
+
+DMAX = 8
+NFIXED = 32
+
+SIR, SEIR, AGE_SEIR = 0, 1, 2
+OBS_POIS_PREV, OBS_POIS_INC, OBS_NB_INC = 0, 1, 2
+PREC_FP32, PREC_FP64 = 0, 1
+PRIOR_UNIFORM, PRIOR_LOGNORMAL, PRIOR_LOGITNORMAL, PRIOR_NORMAL = 0, 1, 2, 3
+L_FORWARD, L_GAUSS_OPT = 0, 1
+PROP_RW, PROP_MLP = 0, 1
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("model", ctypes.c_int32), ("obs", ctypes.c_int32), ("D", ctypes.c_int32),
+        ("prec", ctypes.c_int32), ("pf_always", ctypes.c_int32), ("lkernel", ctypes.c_int32),
+        ("proposal", ctypes.c_int32), ("n_fixed", ctypes.c_int32), ("n_pop", ctypes.c_double),
+        ("prior", (ctypes.c_double * 3) * DMAX), ("rw_cov", (ctypes.c_double * DMAX) * DMAX),
+        ("fixed", ctypes.c_double * NFIXED),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build_oracle()
+        _lib = ctypes.CDLL(LIB)
+        _declare(_lib)
+    return _lib
+
+
+def _p(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+def _declare(L):
+    c = ctypes
+    P = c.POINTER
+    L.or_philox.argtypes = [P(c.c_uint32), P(c.c_uint32), P(c.c_uint32)]
+    L.or_u24.restype = c.c_float
+    L.or_u24.argtypes = [c.c_uint32]
+    L.or_u53.restype = c.c_double
+    L.or_u53.argtypes = [c.c_uint32, c.c_uint32]
+    L.or_normal_call.restype = c.c_double
+    L.or_normal_call.argtypes = [c.c_uint64, P(c.c_uint32)]
+    L.or_binomial.restype = c.c_int32
+    L.or_binomial.argtypes = [c.c_int, c.c_int32, c.c_double, c.c_uint64] + [c.c_uint32] * 5
+    L.or_binomial_batch.argtypes = [c.c_int, c.c_int32, c.c_double, c.c_uint64] + [c.c_uint32] * 4 + [
+        c.c_int, P(c.c_int32)]
+    L.or_obs_logpmf.restype = c.c_double
+    L.or_obs_logpmf.argtypes = [c.c_int, c.c_int32, c.c_int32, c.c_double]
+    L.or_resample_trigger.restype = c.c_int
+    L.or_resample_trigger.argtypes = [P(c.c_uint64), c.c_int]
+    L.or_resample_ancestors.argtypes = [P(c.c_uint64), c.c_int, c.c_uint64, P(c.c_int32)]
+    L.or_cholesky.restype = c.c_int
+    L.or_cholesky.argtypes = [c.c_int, P(c.c_double), P(c.c_double)]
+    L.or_mvn_logpdf_chol.restype = c.c_double
+    L.or_mvn_logpdf_chol.argtypes = [c.c_int, P(c.c_double), P(c.c_double), P(c.c_double)]
+    L.or_lkernel_fit.restype = c.c_int
+    L.or_lkernel_fit.argtypes = [c.c_int, c.c_int] + [P(c.c_double)] * 6
+    L.or_prior_logpdf.restype = c.c_double
+    L.or_prior_logpdf.argtypes = [P(Config), P(c.c_double)]
+    L.or_theta_of_phi.argtypes = [P(Config), P(c.c_double), P(c.c_double)]
+    L.or_recycle.argtypes = [c.c_int, c.c_int, P(c.c_double), P(c.c_double), P(c.c_double), P(c.c_double)]
+    L.or_pf_loglik.restype = c.c_double
+    L.or_pf_loglik.argtypes = [P(Config), P(c.c_double), P(c.c_int32), c.c_int, c.c_int, c.c_uint64,
+                               c.c_uint32, c.c_uint32, P(c.c_double), P(c.c_int32)]
+    L.or_prior_draw.argtypes = [P(Config), c.c_int, c.c_uint64, P(c.c_double), P(c.c_double)]
+    L.or_propose_rw.argtypes = [P(Config), c.c_int, c.c_uint64, c.c_uint32, P(c.c_double),
+                                P(c.c_double), P(c.c_double)]
+    L.or_outer_update.restype = c.c_int
+    L.or_outer_update.argtypes = [P(Config), c.c_int, c.c_uint32, c.c_uint64] + [P(c.c_double)] * 7 + [
+        P(c.c_double), P(c.c_int32), P(c.c_double)]
+    L.or_smc2_run.restype = c.c_int
+    L.or_smc2_run.argtypes = [P(Config), P(c.c_int32), c.c_int, c.c_int, c.c_uint64, c.c_int, c.c_int,
+                              c.c_int, P(c.c_double), P(c.c_double), P(c.c_double), P(c.c_double),
+                              P(c.c_double), P(c.c_int32)]
+    L.or_record_len.restype = c.c_int
+    L.or_record_len.argtypes = [c.c_int]
+
+
+def make_config(model, obs, D, prec, n_pop, prior, rw_cov, fixed=(), lkernel=L_GAUSS_OPT,
+                proposal=PROP_RW, pf_always=0):
+    cfg = Config()
+    cfg.model, cfg.obs, cfg.D, cfg.prec = model, obs, D, prec
+    cfg.pf_always, cfg.lkernel, cfg.proposal = pf_always, lkernel, proposal
+    cfg.n_pop = float(n_pop)
+    prior = np.asarray(prior, dtype=np.float64).reshape(D, 3)
+    rw = np.asarray(rw_cov, dtype=np.float64).reshape(D, D)
+    for d in range(D):
+        for e in range(3):
+            cfg.prior[d][e] = prior[d, e]
+        for e in range(D):
+            cfg.rw_cov[d][e] = rw[d, e]
+    fixed = list(fixed)
+    cfg.n_fixed = len(fixed)
+    for a, v in enumerate(fixed):
+        cfg.fixed[a] = float(v)
+    return cfg
+
+
+def config_from_workload(w, prec=None):
+    """Oracle config from a workload description (paper_2311_12973_amd.workloads)."""
+    return make_config(w["model"], w["obs"], w["D"], w["prec"] if prec is None else prec, w["n_pop"],
+                       w["prior"], w["rw_cov"], w.get("fixed", ()), w.get("lkernel", L_GAUSS_OPT),
+                       w.get("proposal", PROP_RW), w.get("pf_always", 0))
+
+
+def philox(ctr, key):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    lib().or_philox(_p(c, ctypes.c_uint32), _p(k, ctypes.c_uint32), _p(out, ctypes.c_uint32))
+    return out
+
+
+def u24(x):
+    return lib().or_u24(int(x))
+
+
+def u53(lo, hi):
+    return lib().or_u53(int(lo), int(hi))
+
+
+def normal_call(seed, ctr):
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    return lib().or_normal_call(int(seed), _p(c, ctypes.c_uint32))
+
+
+def binomial(prec, n, p, seed, j, i, k, t, b):
+    return lib().or_binomial(prec, int(n), float(p), int(seed), int(j), int(i), int(k), int(t), int(b))
+
+
+def binomial_batch(prec, n, p, seed, count, i=0, k=1, t=1, b=0):
+    out = np.zeros(count, dtype=np.int32)
+    lib().or_binomial_batch(prec, int(n), float(p), int(seed), int(i), int(k), int(t), int(b), int(count),
+                            _p(out, ctypes.c_int32))
+    return out
+
+
+def obs_logpmf(obs, y, count, r=0.0):
+    return lib().or_obs_logpmf(obs, int(y), int(count), float(r))
+
+
+def resample_trigger(q):
+    q = np.ascontiguousarray(q, dtype=np.uint64)
+    return bool(lib().or_resample_trigger(_p(q, ctypes.c_uint64), len(q)))
+
+
+def resample_ancestors(q, x64):
+    q = np.ascontiguousarray(q, dtype=np.uint64)
+    anc = np.zeros(len(q), dtype=np.int32)
+    lib().or_resample_ancestors(_p(q, ctypes.c_uint64), len(q), int(x64), _p(anc, ctypes.c_int32))
+    return anc
+
+
+def cholesky(A):
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    L = np.zeros((n, n))
+    st = lib().or_cholesky(n, _p(A, ctypes.c_double), _p(L, ctypes.c_double))
+    return st, L
+
+
+def mvn_logpdf_chol(x, mu, L):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    return lib().or_mvn_logpdf_chol(len(x), _p(x, ctypes.c_double), _p(mu, ctypes.c_double),
+                                    _p(L, ctypes.c_double))
+
+
+def lkernel_fit(phi, phi_new, omega):
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    phi_new = np.ascontiguousarray(phi_new, dtype=np.float64)
+    omega = np.ascontiguousarray(omega, dtype=np.float64)
+    N, D = phi.shape
+    mu = np.zeros(2 * D)
+    A = np.zeros((D, D))
+    LS = np.zeros((D, D))
+    st = lib().or_lkernel_fit(N, D, _p(phi, ctypes.c_double), _p(phi_new, ctypes.c_double),
+                              _p(omega, ctypes.c_double), _p(mu, ctypes.c_double), _p(A, ctypes.c_double),
+                              _p(LS, ctypes.c_double))
+    return st, mu, A, LS
+
+
+def prior_logpdf(cfg, phi):
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    return lib().or_prior_logpdf(ctypes.byref(cfg), _p(phi, ctypes.c_double))
+
+
+def theta_of_phi(cfg, phi):
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    th = np.zeros_like(phi)
+    lib().or_theta_of_phi(ctypes.byref(cfg), _p(phi, ctypes.c_double), _p(th, ctypes.c_double))
+    return th
+
+
+def record_len(D):
+    return lib().or_record_len(D)
+
+
+def recycle(rec, D):
+    rec = np.ascontiguousarray(rec, dtype=np.float64)
+    K = rec.shape[0]
+    mean = np.zeros(D)
+    cov = np.zeros((D, D))
+    c = np.zeros(K)
+    lib().or_recycle(K, D, _p(rec, ctypes.c_double), _p(mean, ctypes.c_double), _p(cov, ctypes.c_double),
+                     _p(c, ctypes.c_double))
+    return mean, cov, c
+
+
+def pf_loglik(cfg, theta, y, nx, seed, filt, k, trace=False):
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    T = y.shape[0]
+    inc = np.zeros(T) if trace else None
+    rs = np.zeros(T, dtype=np.int32) if trace else None
+    ll = lib().or_pf_loglik(ctypes.byref(cfg), _p(theta, ctypes.c_double), _p(y, ctypes.c_int32), T, nx,
+                            int(seed), int(filt), int(k),
+                            _p(inc, ctypes.c_double) if trace else None,
+                            _p(rs, ctypes.c_int32) if trace else None)
+    return (ll, inc, rs) if trace else ll
+
+
+def prior_draw(cfg, N, seed):
+    phi = np.zeros((N, cfg.D))
+    lp = np.zeros(N)
+    lib().or_prior_draw(ctypes.byref(cfg), N, int(seed), _p(phi, ctypes.c_double), _p(lp, ctypes.c_double))
+    return phi, lp
+
+
+def propose_rw(cfg, seed, k, phi):
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    N = phi.shape[0]
+    phi_new = np.zeros_like(phi)
+    lp_new = np.zeros(N)
+    lib().or_propose_rw(ctypes.byref(cfg), N, int(seed), int(k), _p(phi, ctypes.c_double),
+                        _p(phi_new, ctypes.c_double), _p(lp_new, ctypes.c_double))
+    return phi_new, lp_new
+
+
+def outer_update(cfg, k, seed, state, phi_new, lp_new, ll_new):
+    """state = dict(phi, lp, ll, logw) (updated in place). Returns (status, logw_pre, anc, rec)."""
+    N = phi_new.shape[0]
+    for key in ("phi", "lp", "ll", "logw"):
+        state[key] = np.ascontiguousarray(state[key], dtype=np.float64)
+    phi_new = np.ascontiguousarray(phi_new, dtype=np.float64)
+    lp_new = np.ascontiguousarray(lp_new, dtype=np.float64)
+    ll_new = np.ascontiguousarray(ll_new, dtype=np.float64)
+    logw_pre = np.zeros(N)
+    anc = np.zeros(N, dtype=np.int32)
+    rec = np.zeros(record_len(cfg.D))
+    d = ctypes.c_double
+    st = lib().or_outer_update(ctypes.byref(cfg), N, int(k), int(seed), _p(state["phi"], d), _p(state["lp"], d),
+                               _p(state["ll"], d), _p(state["logw"], d), _p(phi_new, d), _p(lp_new, d),
+                               _p(ll_new, d), _p(logw_pre, d), _p(anc, ctypes.c_int32), _p(rec, d))
+    return st, logw_pre, anc, rec
+
+
+def smc2_run(cfg, y, nx, seed, N, K, n_threads=0, dumps=False):
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    T = y.shape[0]
+    D = cfg.D
+    rec = np.zeros((K, record_len(D)))
+    out = {}
+    d = ctypes.c_double
+    if dumps:
+        out = dict(phi=np.zeros((K, N, D)), ll=np.zeros((K, N)), lp=np.zeros((K, N)), logw=np.zeros((K, N)),
+                   anc=np.zeros((K, N), dtype=np.int32))
+    st = lib().or_smc2_run(ctypes.byref(cfg), _p(y, ctypes.c_int32), T, nx, int(seed), N, K, n_threads,
+                           _p(rec, d),
+                           _p(out["phi"], d) if dumps else None, _p(out["ll"], d) if dumps else None,
+                           _p(out["lp"], d) if dumps else None, _p(out["logw"], d) if dumps else None,
+                           _p(out["anc"], ctypes.c_int32) if dumps else None)
+    out["rec"] = rec
+    out["status"] = st
+    return out

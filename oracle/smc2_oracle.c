@@ -1,0 +1,588 @@
+/*
+ * smc2_oracle.c — plain, slow CPU reference of the SMC^2 sampler of Rosato, Varsi,
+ * Murphy and Maskell (arXiv 2311.12973). TEST INFRASTRUCTURE ONLY: the tests, the
+ * smoke check and the CPU-baseline leg of the benchmark are its only users; the
+ * product path never loads it. It shares no code with the GPU library.
+ *
+ * Conventions both implementations follow (the paper leaves them open):
+ *
+ *  Random numbers. Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
+ *  numbers: as easy as 1, 2, 3", SC'11), key = (seed low word, seed high word),
+ *  counter (c0, c1, c2, c3):
+ *    particle-filter flows : (j particle, i filter, k<<16 | t, 1<<24 | b<<16 | call)
+ *    particle-filter resampling : (0, i, k<<16 | t, 2<<24)
+ *    prior draw           : (i sample, 0, 1<<16, 3<<24 | d)
+ *    random-walk normal   : (i sample, 0, k<<16, 4<<24 | d)
+ *    outer resampling     : (0, 0, k<<16, 5<<24)
+ *  Uniforms: u24(x) = (2*(x>>9)+1) * 2^-24 (exact in FP32), u53(lo,hi) =
+ *  (2*((hi:lo)>>12)+1) * 2^-53. Normals: Box-Muller on (u53(w0,w1), u53(w2,w3)),
+ *  first output only.
+ *
+ *  Integer systematic resampling (Sec. IV-B, Eq. cdf / ncopies, used for the
+ *  particle filter too): q_j = floor(2^32 * exp(a_j - max a)), C_j = sum_{l<=j} q_l,
+ *  Q = C_{n-1}, U = floor(x64 * Q / 2^64) with x64 a 64-bit Philox output, and
+ *  ancestor(m) = min{ j : n*C_j > m*Q + U }. This is the paper's ceil form with
+ *  cdf_j = n*C_j/Q and u = U/Q in [0,1): ncopies_j = #{m : n*C_{j-1} <= m*Q+U < n*C_j}
+ *  (a point on a boundary goes to the upper index).
+ *  Trigger ESS < n/2 evaluated exactly on q'_j = q_j >> 8: 2*(sum q')^2 < n*sum q'^2.
+ *
+ *  L-kernel (Sec. IV-D): Gaussian fitted to the pairs (phi_{k-1}^i, phi_k^i) with the
+ *  normalised weights of iteration k-1, then conditioned (textbook Gaussian
+ *  conditioning): L = N(phi_{k-1}; mu_1 + A (phi_k - mu_2), S), A = S12 S22^-1,
+ *  S = S11 - A S21. A failed Cholesky falls back to the forward kernel.
+ *
+ *  Parameters live on sampler coordinates phi (identity for a uniform prior, log for
+ *  a log-normal prior, logit for a logit-normal prior); the proposal, the L-kernel
+ *  and the prior density are all on phi; the model sees theta(phi).
+ */
+#include "smc2_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define LOG_2PI 1.8378770664093453
+
+int or_record_len(int D) { return 6 + 2 * D + D * D; }
+int or_n_obs(int model) { return model == OR_AGE_SEIR ? 4 : 1; }
+
+/* ------------------------------------------------------------------ random numbers */
+
+void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+float or_u24(uint32_t x) { return (float)((double)(2u * (x >> 9) + 1u) * 0x1p-24); }
+
+double or_u53(uint32_t lo, uint32_t hi)
+{
+    uint64_t x = ((uint64_t)hi << 32) | lo;
+    return (double)(2u * (x >> 12) + 1u) * 0x1p-53;
+}
+
+double or_normal_call(uint64_t seed, const uint32_t ctr[4])
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    or_philox(ctr, key, w);
+    double u1 = or_u53(w[0], w[1]);
+    double u2 = or_u53(w[2], w[3]);
+    double rad = sqrt(-2.0 * log(u1));
+    return rad * cos(6.283185307179586 * u2);
+}
+
+/* ------------------------------------------------------------------ observations */
+
+/* Per-day constant of the observation log-pmf (FP64):
+ *   Poisson: lgamma(y+1); negative binomial: lgamma(y+r) - lgamma(r) - lgamma(y+1) + r log r. */
+static double or_obs_const(int obs, int32_t y, double r)
+{
+    if (obs == OR_OBS_NB_INC)
+        return ((lgamma((double)y + r) - lgamma(r)) - lgamma((double)y + 1.0)) + r * log(r);
+    return lgamma((double)y + 1.0);
+}
+
+/* log g(y | count) in FP64 (Sec. V-A: Poisson; the negative binomial has mean `count`
+ * and dispersion r). A zero mean gives 0 for y = 0 and -inf otherwise. */
+static double or_obs_logpmf_c(int obs, int32_t y, int32_t cnt, double r, double cst)
+{
+    if (cnt <= 0) return (y == 0) ? 0.0 : -INFINITY;
+    double mu = (double)cnt;
+    if (obs == OR_OBS_NB_INC)
+        return (cst + (double)y * log(mu)) - (r + (double)y) * log(r + mu);
+    return ((double)y * log(mu) - mu) - cst;
+}
+
+double or_obs_logpmf(int obs, int32_t y, int32_t count, double r)
+{
+    return or_obs_logpmf_c(obs, y, count, r, or_obs_const(obs, y, r));
+}
+
+/* ------------------------------------------------------------------ resampling */
+
+int or_resample_trigger(const uint64_t* q, int n)
+{
+    uint64_t s1 = 0, s2 = 0;
+    for (int j = 0; j < n; ++j) {
+        uint64_t v = q[j] >> 8;
+        s1 += v;
+        s2 += v * v;
+    }
+    unsigned __int128 lhs = (unsigned __int128)s1 * s1 * 2u;
+    unsigned __int128 rhs = (unsigned __int128)s2 * (unsigned)n;
+    return lhs < rhs;
+}
+
+/* Systematic resampling (Eq. ncopies: ncopies^i = ceil(cdf^i - u) - ceil(cdf^{i-1} - u),
+ * i.e. sample i receives the points m + u lying in [cdf^{i-1}, cdf^i)), then sequential
+ * redistribution (Alg. 1). In integers: cdf^i = n*C_i/Q, u = U/Q, and the sorted points
+ * m*Q + U are walked against the scaled cumulative sums n*C_j. */
+void or_resample_ancestors(const uint64_t* q, int n, uint64_t x64, int32_t* anc)
+{
+    uint64_t* C = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
+    uint64_t acc = 0;
+    for (int j = 0; j < n; ++j) {
+        acc += q[j];
+        C[j] = acc;
+    }
+    uint64_t Q = acc;
+    uint64_t U = (uint64_t)(((unsigned __int128)x64 * Q) >> 64);
+    int j = 0;
+    for (int m = 0; m < n; ++m) {
+        uint64_t target = (uint64_t)m * Q + U;
+        while ((uint64_t)n * C[j] <= target) ++j;
+        anc[m] = j;
+    }
+    free(C);
+}
+
+/* ------------------------------------------------------------------ linear algebra */
+
+/* Unpivoted lower Cholesky of the n x n matrix A (lower triangle read). Returns 0 on
+ * success, -1 if a pivot is not strictly positive. */
+int or_cholesky(int n, const double* A, double* L)
+{
+    memset(L, 0, sizeof(double) * (size_t)n * n);
+    for (int j = 0; j < n; ++j) {
+        double s = A[j * n + j];
+        for (int k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
+        if (!(s > 0.0)) return -1;
+        L[j * n + j] = sqrt(s);
+        for (int i = j + 1; i < n; ++i) {
+            double v = A[i * n + j];
+            for (int k = 0; k < j; ++k) v -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = v / L[j * n + j];
+        }
+    }
+    return 0;
+}
+
+/* log N(x; mu, L L^T). */
+double or_mvn_logpdf_chol(int n, const double* x, const double* mu, const double* L)
+{
+    double v[2 * OR_DMAX];
+    double quad = 0.0, logdet = 0.0;
+    for (int i = 0; i < n; ++i) {
+        double s = x[i] - mu[i];
+        for (int k = 0; k < i; ++k) s -= L[i * n + k] * v[k];
+        v[i] = s / L[i * n + i];
+        quad += v[i] * v[i];
+        logdet += log(L[i * n + i]);
+    }
+    return -0.5 * quad - logdet - 0.5 * n * LOG_2PI;
+}
+
+/* Solve (L L^T) x = b in place. */
+static void chol_solve(int n, const double* L, double* b)
+{
+    for (int i = 0; i < n; ++i) {
+        double s = b[i];
+        for (int k = 0; k < i; ++k) s -= L[i * n + k] * b[k];
+        b[i] = s / L[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double s = b[i];
+        for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * b[k];
+        b[i] = s / L[i * n + i];
+    }
+}
+
+/*
+ * Approximately optimal L-kernel (Sec. IV-D, Eq. Gauss_joint and the conditional that
+ * follows it, read as textbook Gaussian conditioning). Fits mean mu (2D) and
+ * covariance (2D x 2D) of z_i = (phi_i, phi_new_i) with weights omega (summing to 1),
+ * then returns A = S12 S22^{-1} and the Cholesky factor LS of S = S11 - A S21.
+ * Returns 0, or -1 when a Cholesky factorisation fails.
+ */
+int or_lkernel_fit(int N, int D, const double* phi, const double* phi_new, const double* omega,
+                   double* mu, double* A, double* LS)
+{
+    const int D2 = 2 * D;
+    double cov[4 * OR_DMAX * OR_DMAX];
+    for (int a = 0; a < D2; ++a) mu[a] = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int a = 0; a < D2; ++a) {
+            double z = a < D ? phi[i * D + a] : phi_new[i * D + a - D];
+            mu[a] += omega[i] * z;
+        }
+    for (int a = 0; a < D2 * D2; ++a) cov[a] = 0.0;
+    for (int i = 0; i < N; ++i) {
+        double z[2 * OR_DMAX];
+        for (int a = 0; a < D2; ++a) z[a] = (a < D ? phi[i * D + a] : phi_new[i * D + a - D]) - mu[a];
+        for (int a = 0; a < D2; ++a)
+            for (int c = 0; c < D2; ++c) cov[a * D2 + c] += omega[i] * z[a] * z[c];
+    }
+    double S22[OR_DMAX * OR_DMAX] = {0}, L22[OR_DMAX * OR_DMAX], S[OR_DMAX * OR_DMAX];
+    for (int a = 0; a < D; ++a)
+        for (int c = 0; c < D; ++c) S22[a * D + c] = cov[(D + a) * D2 + D + c];
+    if (or_cholesky(D, S22, L22) != 0) return -1;
+    /* row r of A solves S22 a = S21[:, r] (S22 symmetric) */
+    for (int r = 0; r < D; ++r) {
+        double b[OR_DMAX];
+        for (int c = 0; c < D; ++c) b[c] = cov[(D + c) * D2 + r];
+        chol_solve(D, L22, b);
+        for (int c = 0; c < D; ++c) A[r * D + c] = b[c];
+    }
+    for (int a = 0; a < D; ++a)
+        for (int c = 0; c < D; ++c) {
+            double s = cov[a * D2 + c];
+            for (int e = 0; e < D; ++e) s -= A[a * D + e] * cov[(D + e) * D2 + c];
+            S[a * D + c] = s;
+        }
+    if (or_cholesky(D, S, LS) != 0) return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------ prior */
+
+double or_prior_logpdf(const or_config* cfg, const double* phi)
+{
+    double lp = 0.0;
+    for (int d = 0; d < cfg->D; ++d) {
+        int fam = (int)cfg->prior[d][0];
+        double a = cfg->prior[d][1], b = cfg->prior[d][2];
+        if (fam == OR_PRIOR_UNIFORM) {
+            if (!(phi[d] >= a && phi[d] <= b)) return -INFINITY;
+            lp += -log(b - a);
+        } else {
+            double z = (phi[d] - a) / b;
+            lp += (-0.5 * z * z - log(b)) - 0.5 * LOG_2PI;
+        }
+    }
+    return lp;
+}
+
+void or_theta_of_phi(const or_config* cfg, const double* phi, double* theta)
+{
+    for (int d = 0; d < cfg->D; ++d) {
+        int fam = (int)cfg->prior[d][0];
+        if (fam == OR_PRIOR_LOGNORMAL) theta[d] = exp(phi[d]);
+        else if (fam == OR_PRIOR_LOGITNORMAL) theta[d] = 1.0 / (1.0 + exp(-phi[d]));
+        else theta[d] = phi[d];
+    }
+}
+
+/* k = 1 importance sampling from q_1 = prior (Sec. IV-A, Eq. init_sample). */
+void or_prior_draw(const or_config* cfg, int N, uint64_t seed, double* phi, double* lp)
+{
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int i = 0; i < N; ++i) {
+        for (int d = 0; d < cfg->D; ++d) {
+            uint32_t ctr[4] = {(uint32_t)i, 0u, 1u << 16, ((uint32_t)OR_S_PRIOR << 24) | (uint32_t)d};
+            uint32_t w[4];
+            or_philox(ctr, key, w);
+            double u1 = or_u53(w[0], w[1]), u2 = or_u53(w[2], w[3]);
+            int fam = (int)cfg->prior[d][0];
+            double a = cfg->prior[d][1], b = cfg->prior[d][2];
+            if (fam == OR_PRIOR_UNIFORM) {
+                phi[i * cfg->D + d] = a + (b - a) * u1;
+            } else {
+                double z = sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+                phi[i * cfg->D + d] = a + b * z;
+            }
+        }
+        lp[i] = or_prior_logpdf(cfg, phi + (size_t)i * cfg->D);
+    }
+}
+
+/* k > 1 Gaussian random-walk proposal (Sec. IV-A, Eq. proposal): phi' = phi + L z. */
+void or_propose_rw(const or_config* cfg, int N, uint64_t seed, uint32_t k, const double* phi,
+                   double* phi_new, double* lp_new)
+{
+    const int D = cfg->D;
+    double C[OR_DMAX * OR_DMAX], L[OR_DMAX * OR_DMAX];
+    for (int a = 0; a < D; ++a)
+        for (int c = 0; c < D; ++c) C[a * D + c] = cfg->rw_cov[a][c];
+    or_cholesky(D, C, L);
+    for (int i = 0; i < N; ++i) {
+        double z[OR_DMAX];
+        for (int d = 0; d < D; ++d) {
+            uint32_t ctr[4] = {(uint32_t)i, 0u, k << 16, ((uint32_t)OR_S_RW << 24) | (uint32_t)d};
+            z[d] = or_normal_call(seed, ctr);
+        }
+        for (int d = 0; d < D; ++d) {
+            double acc = 0.0;
+            for (int e = 0; e <= d; ++e) acc += L[d * D + e] * z[e];
+            phi_new[i * D + d] = phi[i * D + d] + acc;
+        }
+        lp_new[i] = or_prior_logpdf(cfg, phi_new + (size_t)i * D);
+    }
+}
+
+/* ------------------------------------------------------------------ particle filters */
+
+#define REAL float
+#define FN(x) x##_f32
+#include "pf_real.inc"
+#undef REAL
+#undef FN
+#define REAL double
+#define FN(x) x##_f64
+#include "pf_real.inc"
+#undef REAL
+#undef FN
+
+int32_t or_binomial(int prec, int32_t n, double p, uint64_t seed, uint32_t j, uint32_t i,
+                    uint32_t k, uint32_t t, uint32_t b)
+{
+    uint32_t kt = (k << 16) | t;
+    if (prec == OR_PREC_FP32) return binom_f32(n, (float)p, seed, j, i, kt, b);
+    return binom_f64(n, p, seed, j, i, kt, b);
+}
+
+/* count draws at particle coordinates j = 0..count-1 (same filter, iteration, day, draw). */
+void or_binomial_batch(int prec, int32_t n, double p, uint64_t seed, uint32_t i, uint32_t k,
+                       uint32_t t, uint32_t b, int count, int32_t* out)
+{
+    for (int j = 0; j < count; ++j) out[j] = or_binomial(prec, n, p, seed, (uint32_t)j, i, k, t, b);
+}
+
+double or_pf_loglik(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx,
+                    uint64_t seed, uint32_t filt, uint32_t k, double* inc_out, int32_t* rs_out)
+{
+    if (cfg->prec == OR_PREC_FP32) return pf_f32(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out);
+    return pf_f64(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out);
+}
+
+/* ------------------------------------------------------------------ outer sampler */
+
+static double logsumexp(int n, const double* v)
+{
+    double m = -INFINITY;
+    for (int i = 0; i < n; ++i)
+        if (v[i] > m) m = v[i];
+    if (m == -INFINITY) return -INFINITY;
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += exp(v[i] - m);
+    return m + log(s);
+}
+
+/*
+ * One outer update at iteration k, given the proposals phi_new with their prior
+ * log-densities and particle-filter log-likelihoods:
+ *   k = 1:  log w = ll_new                                   (Sec. IV-A, Eq. init_weights)
+ *   k > 1:  log w = log w_{k-1} + log pi(new) - log pi(old) + log L - log q
+ *                                                            (Sec. IV-A, Eq. l_weights)
+ * with pi = prior x likelihood estimate (pseudo-marginal: the estimate travels with
+ * its sample). Then normalisation (Eq. normalise_smc2), the estimate (Eq.
+ * realised_estimates), l_k = (sum w)^2 / sum w^2 (Eq. recycling_I) = ESS (Eq.
+ * ess_smc2), and, if ESS < N/2, systematic resampling with redistribution and reset
+ * (Sec. IV-B). The state arrays (phi, lp, ll, logw) are replaced by the new
+ * population. Returns 0, or -4 when every weight is zero.
+ */
+int or_outer_update(const or_config* cfg, int N, uint32_t k, uint64_t seed,
+                    double* phi, double* lp, double* ll, double* logw,
+                    const double* phi_new, const double* lp_new, const double* ll_new,
+                    double* logw_pre, int32_t* anc, double* rec)
+{
+    const int D = cfg->D;
+    int fallback = 0;
+    if (k == 1) {
+        for (int i = 0; i < N; ++i) logw_pre[i] = ll_new[i];
+    } else {
+        double* logL = (double*)calloc((size_t)N, sizeof(double));
+        int use_ratio_only = (cfg->lkernel == OR_L_FORWARD);
+        if (cfg->lkernel == OR_L_GAUSS_OPT) {
+            double* omega = (double*)malloc(sizeof(double) * (size_t)N);
+            double W0 = logsumexp(N, logw);
+            for (int i = 0; i < N; ++i) omega[i] = exp(logw[i] - W0);
+            double mu[2 * OR_DMAX], A[OR_DMAX * OR_DMAX], LS[OR_DMAX * OR_DMAX];
+            if (or_lkernel_fit(N, D, phi, phi_new, omega, mu, A, LS) == 0) {
+                double C[OR_DMAX * OR_DMAX], Lq[OR_DMAX * OR_DMAX];
+                for (int a = 0; a < D; ++a)
+                    for (int c = 0; c < D; ++c) C[a * D + c] = cfg->rw_cov[a][c];
+                or_cholesky(D, C, Lq);
+                for (int i = 0; i < N; ++i) {
+                    double m[OR_DMAX];
+                    for (int a = 0; a < D; ++a) {
+                        double s = mu[a];
+                        for (int c = 0; c < D; ++c) s += A[a * D + c] * (phi_new[i * D + c] - mu[D + c]);
+                        m[a] = s;
+                    }
+                    double lL = or_mvn_logpdf_chol(D, phi + (size_t)i * D, m, LS);
+                    double lq = or_mvn_logpdf_chol(D, phi_new + (size_t)i * D, phi + (size_t)i * D, Lq);
+                    logL[i] = lL - lq;
+                }
+            } else {
+                fallback = 1;
+                use_ratio_only = 1;
+            }
+            free(omega);
+        }
+        for (int i = 0; i < N; ++i) {
+            double pin = lp_new[i] + ll_new[i];
+            if (logw[i] == -INFINITY || pin == -INFINITY) {
+                logw_pre[i] = -INFINITY;
+            } else {
+                double v = (logw[i] + pin) - (lp[i] + ll[i]);
+                if (!use_ratio_only) v = v + logL[i];
+                logw_pre[i] = v;
+            }
+        }
+        free(logL);
+    }
+
+    /* normalise, ESS, estimates */
+    const int RL = or_record_len(D);
+    for (int a = 0; a < RL; ++a) rec[a] = 0.0;
+    rec[0] = (double)k;
+    rec[4] = (double)fallback;
+    int n_dead = 0;
+    for (int i = 0; i < N; ++i) n_dead += (logw_pre[i] == -INFINITY);
+    rec[3] = (double)n_dead;
+    double W = logsumexp(N, logw_pre);
+    rec[5] = W;
+    for (int i = 0; i < N; ++i) anc[i] = i;
+    if (W == -INFINITY) {
+        for (int i = 0; i < N; ++i) logw[i] = -INFINITY;
+        return -4;
+    }
+    double* wn = (double*)malloc(sizeof(double) * (size_t)N);
+    double s2 = 0.0;
+    for (int i = 0; i < N; ++i) {
+        wn[i] = exp(logw_pre[i] - W);
+        s2 += wn[i] * wn[i];
+    }
+    rec[1] = 1.0 / s2;
+    double* mth = rec + 6;
+    double* cth = rec + 6 + D;
+    double* mph = rec + 6 + D + D * D;
+    double th[OR_DMAX];
+    for (int i = 0; i < N; ++i) {
+        or_theta_of_phi(cfg, phi_new + (size_t)i * D, th);
+        for (int a = 0; a < D; ++a) {
+            mth[a] += wn[i] * th[a];
+            mph[a] += wn[i] * phi_new[i * D + a];
+        }
+    }
+    for (int i = 0; i < N; ++i) {
+        or_theta_of_phi(cfg, phi_new + (size_t)i * D, th);
+        for (int a = 0; a < D; ++a)
+            for (int c = 0; c < D; ++c) cth[a * D + c] += wn[i] * (th[a] - mth[a]) * (th[c] - mth[c]);
+    }
+
+    /* resampling (Sec. IV-B) */
+    double M = -INFINITY;
+    for (int i = 0; i < N; ++i)
+        if (logw_pre[i] > M) M = logw_pre[i];
+    uint64_t* q = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)N);
+    for (int i = 0; i < N; ++i) q[i] = (uint64_t)floor(exp(logw_pre[i] - M) * 4294967296.0);
+    int rs = or_resample_trigger(q, N);
+    rec[2] = (double)rs;
+    if (rs) {
+        uint32_t ctr[4] = {0u, 0u, k << 16, (uint32_t)OR_S_OUTER_RS << 24};
+        uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+        uint32_t wd[4];
+        or_philox(ctr, key, wd);
+        or_resample_ancestors(q, N, (uint64_t)wd[0] | ((uint64_t)wd[1] << 32), anc);
+    }
+    for (int i = 0; i < N; ++i) {
+        int s = anc[i];
+        for (int a = 0; a < D; ++a) phi[i * D + a] = phi_new[s * D + a];
+        lp[i] = lp_new[s];
+        ll[i] = ll_new[s];
+        logw[i] = rs ? 0.0 : logw_pre[i];
+    }
+    free(q);
+    free(wn);
+    return 0;
+}
+
+/* Recycled estimate (Sec. IV-C): c_k = l_k / sum l, mean = sum c_k f_k; the covariance
+ * combines the per-iteration second moments with the same constants. */
+void or_recycle(int K, int D, const double* rec, double* mean, double* cov, double* c_out)
+{
+    const int RL = or_record_len(D);
+    double lsum = 0.0;
+    for (int k = 0; k < K; ++k) lsum += rec[k * RL + 1];
+    for (int a = 0; a < D; ++a) mean[a] = 0.0;
+    for (int a = 0; a < D * D; ++a) cov[a] = 0.0;
+    for (int k = 0; k < K; ++k) {
+        double c = rec[k * RL + 1] / lsum;
+        if (c_out) c_out[k] = c;
+        const double* m = rec + k * RL + 6;
+        const double* C = rec + k * RL + 6 + D;
+        for (int a = 0; a < D; ++a) mean[a] += c * m[a];
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) cov[a * D + b] += c * (C[a * D + b] + m[a] * m[b]);
+    }
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) cov[a * D + b] -= mean[a] * mean[b];
+}
+
+/*
+ * A whole SMC^2 run (Sec. IV): K iterations over N samples, each sample's
+ * likelihood estimated by a particle filter with nx particles. Per-iteration dumps
+ * (pre-resampling proposals, their log-likelihoods, log-priors, log-weights and the
+ * ancestors chosen) are written when the pointers are not NULL; each holds K
+ * consecutive blocks. Returns 0, or the first non-zero status of an update.
+ */
+int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t seed, int N, int K,
+                int n_threads, double* rec, double* phi_dump, double* ll_dump, double* lp_dump,
+                double* logw_dump, int32_t* anc_dump)
+{
+    const int D = cfg->D;
+    const int RL = or_record_len(D);
+    double* phi = (double*)calloc((size_t)N * D, sizeof(double));
+    double* lp = (double*)calloc((size_t)N, sizeof(double));
+    double* ll = (double*)calloc((size_t)N, sizeof(double));
+    double* logw = (double*)calloc((size_t)N, sizeof(double));
+    double* phin = (double*)calloc((size_t)N * D, sizeof(double));
+    double* lpn = (double*)calloc((size_t)N, sizeof(double));
+    double* lln = (double*)calloc((size_t)N, sizeof(double));
+    double* lwp = (double*)calloc((size_t)N, sizeof(double));
+    int32_t* anc = (int32_t*)calloc((size_t)N, sizeof(int32_t));
+    int status = 0;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+    for (int k = 1; k <= K; ++k) {
+        if (k == 1) or_prior_draw(cfg, N, seed, phin, lpn);
+        else or_propose_rw(cfg, N, seed, (uint32_t)k, phi, phin, lpn);
+#pragma omp parallel for schedule(dynamic, 1)
+        for (int i = 0; i < N; ++i) {
+            int run = (k == 1) || (logw[i] != -INFINITY && lpn[i] != -INFINITY);
+            if (run) {
+                double th[OR_DMAX];
+                or_theta_of_phi(cfg, phin + (size_t)i * D, th);
+                lln[i] = or_pf_loglik(cfg, th, y, T, nx, seed, (uint32_t)i, (uint32_t)k, NULL, NULL);
+            } else {
+                lln[i] = -INFINITY;
+            }
+        }
+        int st = or_outer_update(cfg, N, (uint32_t)k, seed, phi, lp, ll, logw, phin, lpn, lln, lwp,
+                                 anc, rec + (size_t)(k - 1) * RL);
+        if (phi_dump) memcpy(phi_dump + (size_t)(k - 1) * N * D, phin, sizeof(double) * (size_t)N * D);
+        if (ll_dump) memcpy(ll_dump + (size_t)(k - 1) * N, lln, sizeof(double) * (size_t)N);
+        if (lp_dump) memcpy(lp_dump + (size_t)(k - 1) * N, lpn, sizeof(double) * (size_t)N);
+        if (logw_dump) memcpy(logw_dump + (size_t)(k - 1) * N, lwp, sizeof(double) * (size_t)N);
+        if (anc_dump) memcpy(anc_dump + (size_t)(k - 1) * N, anc, sizeof(int32_t) * (size_t)N);
+        if (st != 0) {
+            status = st;
+            break;
+        }
+    }
+    free(phi); free(lp); free(ll); free(logw); free(phin); free(lpn); free(lln); free(lwp); free(anc);
+    return status;
+}

@@ -1,0 +1,100 @@
+/*
+ * smc2_oracle.h — plain CPU reference of the SMC^2 sampler (test infrastructure only).
+ *
+ * This library exists to check the GPU implementation. Only the test-suite, the
+ * smoke check and the CPU-baseline leg of the benchmark load it. It shares no code,
+ * header, table or constant generator with the GPU library: both sides implement the
+ * same published definitions (the paper's equations plus the conventions written in
+ * the comments of smc2_oracle.c) independently.
+ *
+ * Paper: Rosato, Varsi, Murphy, Maskell, "An O(log2 N) SMC^2 Algorithm on Distributed
+ * Memory with an Approx. Optimal L-Kernel" (arXiv 2311.12973).
+ *   - particle filter: Sec. II (weight recursion, likelihood estimate, ESS, resampling)
+ *   - SMC^2 outer sampler: Sec. IV-A (IS, RW proposal, weight update, recycling),
+ *     Sec. IV-B (ESS, systematic resampling, Alg. 1), Sec. IV-D (L-kernels)
+ *   - SIR model: Sec. V-A.
+ *
+ * All floating-point outside the particle filter is FP64. The particle filter runs
+ * in the precision selected by `prec` (OR_PREC_FP32 or OR_PREC_FP64); the cross-time
+ * log-likelihood accumulation is FP64 in both.
+ */
+#ifndef SMC2_ORACLE_H
+#define SMC2_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_SIR = 0, OR_SEIR = 1, OR_AGE_SEIR = 2 };
+enum { OR_OBS_POIS_PREV = 0, OR_OBS_POIS_INC = 1, OR_OBS_NB_INC = 2 };
+enum { OR_PREC_FP32 = 0, OR_PREC_FP64 = 1 };
+enum { OR_PRIOR_UNIFORM = 0, OR_PRIOR_LOGNORMAL = 1, OR_PRIOR_LOGITNORMAL = 2, OR_PRIOR_NORMAL = 3 };
+enum { OR_L_FORWARD = 0, OR_L_GAUSS_OPT = 1 };
+enum { OR_PROP_RW = 0, OR_PROP_MLP = 1 };
+
+/* Philox stream identifiers (bits 24..31 of the fourth counter word). */
+enum { OR_S_PF_PROP = 1, OR_S_PF_RS = 2, OR_S_PRIOR = 3, OR_S_RW = 4, OR_S_OUTER_RS = 5,
+       OR_S_MLP_INIT = 6, OR_S_MLP_PERM = 7 };
+
+#define OR_DMAX 8
+#define OR_NFIXED 32
+
+typedef struct {
+    int32_t model, obs, D, prec;
+    int32_t pf_always;  /* 1: resample the particle filter at every step; 0: when ESS < Nx/2 */
+    int32_t lkernel;    /* OR_L_FORWARD or OR_L_GAUSS_OPT */
+    int32_t proposal;   /* OR_PROP_RW or OR_PROP_MLP */
+    int32_t n_fixed;
+    double n_pop;
+    double prior[OR_DMAX][3];      /* {family, a, b} per sampler coordinate */
+    double rw_cov[OR_DMAX][OR_DMAX];
+    double fixed[OR_NFIXED];       /* model constants (see smc2_oracle.c, "Models") */
+} or_config;
+
+/* Number of doubles in one per-iteration record. */
+int or_record_len(int D);
+int or_n_obs(int model);
+
+/* ---- building blocks (exported for the pins) ---- */
+void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+float or_u24(uint32_t x);
+double or_u53(uint32_t lo, uint32_t hi);
+double or_normal_call(uint64_t seed, const uint32_t ctr[4]);
+/* One binomial draw at particle-filter coordinates (j, i, k, t, b). p is rounded to
+ * the working precision first when prec == OR_PREC_FP32. */
+int32_t or_binomial(int prec, int32_t n, double p, uint64_t seed, uint32_t j, uint32_t i,
+                    uint32_t k, uint32_t t, uint32_t b);
+void or_binomial_batch(int prec, int32_t n, double p, uint64_t seed, uint32_t i, uint32_t k,
+                       uint32_t t, uint32_t b, int count, int32_t* out);
+double or_obs_logpmf(int obs, int32_t y, int32_t count, double r);
+int or_resample_trigger(const uint64_t* q, int n);
+void or_resample_ancestors(const uint64_t* q, int n, uint64_t x64, int32_t* anc);
+int or_cholesky(int n, const double* A, double* L);
+double or_mvn_logpdf_chol(int n, const double* x, const double* mu, const double* L);
+int or_lkernel_fit(int N, int D, const double* phi, const double* phi_new, const double* omega,
+                   double* mu /*2D*/, double* A /*DxD*/, double* LS /*DxD*/);
+double or_prior_logpdf(const or_config* cfg, const double* phi);
+void or_theta_of_phi(const or_config* cfg, const double* phi, double* theta);
+void or_recycle(int K, int D, const double* rec, double* mean, double* cov, double* c_out);
+
+/* ---- the particle filter (Sec. II) ---- */
+double or_pf_loglik(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx,
+                    uint64_t seed, uint32_t filt, uint32_t k, double* inc_out, int32_t* rs_out);
+
+/* ---- the outer sampler (Sec. IV) ---- */
+void or_prior_draw(const or_config* cfg, int N, uint64_t seed, double* phi, double* lp);
+void or_propose_rw(const or_config* cfg, int N, uint64_t seed, uint32_t k, const double* phi,
+                   double* phi_new, double* lp_new);
+int or_outer_update(const or_config* cfg, int N, uint32_t k, uint64_t seed,
+                    double* phi, double* lp, double* ll, double* logw,
+                    const double* phi_new, const double* lp_new, const double* ll_new,
+                    double* logw_pre, int32_t* anc, double* rec);
+int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t seed, int N, int K,
+                int n_threads, double* rec, double* phi_dump, double* ll_dump, double* lp_dump,
+                double* logw_dump, int32_t* anc_dump);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
