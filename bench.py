@@ -1,0 +1,127 @@
+"""Benchmark: SMC^2 iterations (particle-filter batch + outer step) on one MI355X.
+
+A step is one SMC^2 iteration over the whole population: propose, N particle
+filters of N_x particles over T days, L-kernel weights, normalisation, estimates,
+resampling. Workload (default): SEIR, N_pop = 1e6, negative-binomial observations of
+new cases, T = 100, D = 4, N = 1024 parameter samples, N_x = 512 particles, FP32
+propagation with FP64 log-likelihood and outer step; synthetic observations
+simulated from a fixed seed.
+
+Prints one JSON line. value = particle-steps per second (theta x particle x day)
+of whole iterations, inputs resident in HBM. roofline: the particle-filter kernel
+(VALU-bound) -- its VALU lane-instruction rate against the MI355X issue peak, from
+the kernel's instruction count per particle-step (rocprofv3 SQ_INSTS_VALU) and its
+event-timed duration in this run. cpu_baseline: the CPU reference on a bounded
+sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# VALU instructions (wave64) issued by the particle-filter kernel per particle-step
+# on this workload, from `rocprofv3 --pmc SQ_INSTS_VALU` (profiles/pf_kernel_seir_valu.txt):
+# SQ_INSTS_VALU summed over the kernel's dispatches / (N * N_x * T).
+VALU_WAVE_INSTR_PER_PSTEP = None
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 3.93e13 lane-instructions/s
+VALU_PEAK_LANE_INSTR = 256 * 64 * 2.4e9
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="seir")
+    ap.add_argument("--graph", type=int, default=0)
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the sampler is not sharded across GPUs); "
+              "run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2311_12973_amd as G
+    from paper_2311_12973_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.preset(args.workload)
+    y = W.observations(w)
+    N, nx, T = w["N"], w["nx"], w["T"]
+    K = args.warmup + args.steps
+    s = G.Sampler(w, [dict(T=T, nx=nx, seed=w["seed"], y=y)], N=N, K=K, use_graph=args.graph, block=args.block)
+    for _ in range(args.warmup):
+        s.step()
+    torch.cuda.synchronize()
+    s.timing()  # reset the per-iteration event timers
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_pf, ms_step_dev, n_timed = s.timing()
+    rec = s.records()
+    s.close()
+
+    ms = (t1 - t0) * 1e3 / args.steps
+    psteps = float(N) * nx * T
+    value = psteps / (ms * 1e-3)
+    dead = float(rec[args.warmup:, 3].mean())
+
+    roofline = None
+    if not args.graph:
+        launch_s = ms_pf * 1e-3
+        if VALU_WAVE_INSTR_PER_PSTEP is not None:
+            achieved = VALU_WAVE_INSTR_PER_PSTEP * 64 * psteps / launch_s
+            roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_INSTR / 1e12,
+                        "unit": "T VALU lane-instr/s", "frac": achieved / VALU_PEAK_LANE_INSTR, "traffic": None,
+                        "kernel": "k_pf", "kernel_ms": ms_pf, "pf_particle_steps_per_s": psteps / launch_s}
+        else:
+            roofline = {"bound": "alu", "achieved": None, "peak": VALU_PEAK_LANE_INSTR / 1e12,
+                        "unit": "T VALU lane-instr/s", "frac": None, "traffic": None, "kernel": "k_pf",
+                        "kernel_ms": ms_pf, "pf_particle_steps_per_s": psteps / launch_s}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w, y)
+
+    out = {
+        "metric": "PF particle-steps/s (theta x x x t), whole SMC^2 iterations",
+        "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (SEIR observations simulated from a fixed seed)",
+        "config": {"workload": "seir N=%d Nx=%d T=%d D=%d FP32 propagation, FP64 outer" % (N, nx, T, w["D"]),
+                   "N": N, "n_x": nx, "T": T, "global_batch": N, "parallelism": "single GPU",
+                   "graph": bool(args.graph), "dead_samples_per_step": dead, "device_ms_per_step": ms_step_dev},
+        "roofline": roofline, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+def cpu_baseline(w, y):
+    """The CPU reference (all host cores) on a bounded sample: N = 256 parameter
+    samples, 3 SMC^2 iterations, the same N_x, T, model and data."""
+    import oracle as O
+
+    cfg = O.config_from_workload(w)
+    n_sample, k_sample = 256, 3
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    t = time.perf_counter()
+    O.smc2_run(cfg, y, w["nx"], w["seed"], n_sample, k_sample, n_threads=threads)
+    dt = time.perf_counter() - t
+    ps = float(n_sample) * k_sample * w["nx"] * w["T"]
+    return {"value": ps / dt, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
+            "sample": "N=%d samples x %d iterations of the same SEIR workload (N_x=%d, T=%d), %.1f s"
+                      % (n_sample, k_sample, w["nx"], w["T"], dt)}
+
+
+if __name__ == "__main__":
+    main()

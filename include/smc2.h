@@ -1,0 +1,175 @@
+/*
+ * smc2.h — C ABI of the MI355X SMC^2 library (libsmc2.so).
+ *
+ * The library runs the sampler of Rosato, Varsi, Murphy and Maskell, "An O(log2 N)
+ * SMC^2 Algorithm on Distributed Memory with an Approx. Optimal L-Kernel"
+ * (arXiv 2311.12973) on one AMD Instinct MI355X (gfx950):
+ *
+ *   - For every parameter sample theta^i (i < N) a particle filter with N_x particles
+ *     estimates the likelihood p(y_{1:T} | theta^i) (Sec. II: weight recursion,
+ *     likelihood estimate as the mean unnormalised weight, ESS-triggered resampling
+ *     with the mean-weight reset).
+ *   - The outer SMC sampler (Sec. IV) draws theta_1 from the prior (Eq. init_sample),
+ *     moves theta with a Gaussian random walk (Eq. proposal), weights with an
+ *     L-kernel (Eq. l_weights; forward kernel, Eq. aimplified_l_weights, or the
+ *     approximately optimal Gaussian kernel, Eq. Gauss_joint and the conditional that
+ *     follows), normalises (Eq. normalise_smc2), estimates (Eq. realised_estimates),
+ *     computes l_k (Eq. recycling_I) and ESS (Eq. ess_smc2), resamples
+ *     systematically when ESS < N/2 (Eq. cdf, ncopies; Alg. 1 as a prefix-sum
+ *     scatter) and recycles the per-iteration estimates (Sec. IV-C).
+ *
+ * Several independent runs (one data series, seed, T and N_x each, same config)
+ * can share one context; each iteration then advances all of them together.
+ *
+ * Ownership: the caller owns every argument. smc2_init deep-copies the config, the
+ * run descriptions and the observations, which may be freed after it returns. The
+ * caller also owns the device workspace (at least smc2_workspace_bytes bytes of
+ * device memory, 256-byte aligned) and the HIP stream; both must outlive the
+ * context. The library never allocates device memory; every device buffer is
+ * carved out of the workspace. smc2_destroy frees host state only.
+ *
+ * Synchronisation: smc2_step enqueues one iteration on the stream and returns
+ * without waiting. smc2_estimate, smc2_records and smc2_dump synchronise the stream.
+ *
+ * Errors: every function returns a status (SMC2_OK = 0 or a negative code) and
+ * never throws. Arguments are checked before anything is enqueued. A failed HIP
+ * call poisons the context: every later call returns SMC2_E_DEVICE.
+ * smc2_last_error gives a message for the last failure of a context (or of the
+ * calling thread when ctx is NULL). A context is used by one thread at a time;
+ * separate contexts on separate streams are independent.
+ */
+#ifndef SMC2_H
+#define SMC2_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define SMC2_OK 0
+#define SMC2_E_ARG (-1)         /* invalid argument or workspace too small */
+#define SMC2_E_DEVICE (-2)      /* a HIP call failed; the context is poisoned */
+#define SMC2_E_STATE (-3)       /* call out of order (e.g. more than K steps) */
+#define SMC2_E_NUMERIC (-4)     /* every weight of a run is zero */
+#define SMC2_E_UNSUPPORTED (-5) /* valid but not supported combination */
+
+/* model (Sec. V-A chain-binomial SIR and its SEIR extensions) */
+#define SMC2_SIR 0      /* theta = (beta, gamma); fixed[0] = initially infected I_0 */
+#define SMC2_SEIR 1     /* theta = (beta, sigma, gamma, iota[, r]); I_0 = round(iota N_pop);
+                           fixed[0] = negative-binomial dispersion r when D == 4 */
+#define SMC2_AGE_SEIR 2 /* theta = (beta, sigma, gamma, iota, r, s_2, s_3, s_4), four groups;
+                           fixed[0..15] contact matrix (row-major), fixed[16..19] group fractions */
+
+/* observation model of y_t */
+#define SMC2_OBS_POIS_PREV 0 /* Poisson(I_t)            (Sec. V-A)                      */
+#define SMC2_OBS_POIS_INC 1  /* Poisson(new infections) (S->I for SIR, E->I for SEIR)   */
+#define SMC2_OBS_NB_INC 2    /* negative binomial(mean = new infections, dispersion r)  */
+
+/* precision of the particle-filter propagation and per-step weights. The
+ * log-likelihood accumulation and everything in the outer sampler are FP64. */
+#define SMC2_PREC_FP32 0
+#define SMC2_PREC_FP64 1
+
+/* prior family per sampler coordinate phi_d (the sampler moves on phi) */
+#define SMC2_PRIOR_UNIFORM 0     /* theta_d = phi_d ~ U[a, b]                   */
+#define SMC2_PRIOR_LOGNORMAL 1   /* theta_d = exp(phi_d),     phi_d ~ N(a, b^2) */
+#define SMC2_PRIOR_LOGITNORMAL 2 /* theta_d = logistic(phi_d), phi_d ~ N(a, b^2) */
+#define SMC2_PRIOR_NORMAL 3      /* theta_d = phi_d ~ N(a, b^2)                 */
+
+#define SMC2_L_FORWARD 0   /* L = forward proposal (Sec. IV-D, Eq. aimplified_l_weights) */
+#define SMC2_L_GAUSS_OPT 1 /* approximately optimal Gaussian L-kernel (Sec. IV-D)        */
+
+#define SMC2_PROP_RW 0 /* Gaussian random walk on phi (Eq. proposal) */
+
+#define SMC2_DMAX 8
+#define SMC2_NFIXED 32
+
+typedef struct smc2_ctx smc2_ctx;
+
+typedef struct {
+    int32_t model;     /* SMC2_SIR / SMC2_SEIR / SMC2_AGE_SEIR                          */
+    int32_t obs;       /* SMC2_OBS_*                                                    */
+    int32_t D;         /* number of parameters, 1..SMC2_DMAX (fixed by the model)       */
+    int32_t N;         /* parameter samples per run, 2..65536                           */
+    int32_t K;         /* iterations, >= 1 (k = 1 is the prior importance-sampling step) */
+    int32_t precision; /* SMC2_PREC_FP32 or SMC2_PREC_FP64                              */
+    int32_t proposal;  /* SMC2_PROP_RW                                                  */
+    int32_t lkernel;   /* SMC2_L_FORWARD or SMC2_L_GAUSS_OPT                            */
+    int32_t pf_always; /* 1: resample the particle filter at every step                 */
+    int32_t use_graph; /* 1: replay each iteration as one captured HIP graph            */
+    int32_t block;     /* particle-filter workgroup size override (0: tuned default)    */
+    int32_t ppt;       /* particles per thread override (0: tuned default)              */
+    double n_pop;      /* population size, integer, 1 .. 2^24                           */
+    const double* prior;  /* host, D x 3 row-major: {family, a, b} per coordinate        */
+    const double* rw_cov; /* host, D x D row-major, symmetric positive definite          */
+    const double* fixed;  /* host, n_fixed model constants (see the model codes)         */
+    int32_t n_fixed;
+} smc2_config;
+
+typedef struct {
+    int32_t T;          /* number of observations, 1..1024                             */
+    int32_t n_x;        /* particles per filter, 1..4096 (1..2048 for SMC2_AGE_SEIR)   */
+    uint64_t seed;      /* Philox key of this run                                      */
+    const int32_t* y;   /* host, T x n_obs row-major, non-negative (n_obs = 4 for AGE) */
+} smc2_run;
+
+/* Per-iteration record, SMC2_RECORD_LEN(D) doubles:
+ *   [0] k   [1] ESS = l_k   [2] resampled (0/1)   [3] samples with zero weight
+ *   [4] L-kernel fell back to the forward kernel (0/1)   [5] log sum_i w_k^i
+ *   [6 .. 6+D)            posterior mean of theta at iteration k (Eq. realised_estimates)
+ *   [6+D .. 6+D+D*D)      weighted covariance of theta
+ *   [6+D+D*D .. 6+2D+D*D) weighted mean of the sampler coordinates phi            */
+#define SMC2_RECORD_LEN(D) (6 + 2 * (D) + (D) * (D))
+
+/* what smc2_dump copies (run r's slice, host_dst must hold the stated size) */
+#define SMC2_DUMP_PHI 0      /* N x D  doubles: population after the last step            */
+#define SMC2_DUMP_LP 1       /* N      doubles: its log-prior                              */
+#define SMC2_DUMP_LL 2       /* N      doubles: its log-likelihood estimates               */
+#define SMC2_DUMP_LOGW 3     /* N      doubles: its log-weights (0 after a resampling)     */
+#define SMC2_DUMP_PHI_NEW 4  /* N x D  doubles: samples proposed in the last step          */
+#define SMC2_DUMP_LP_NEW 5   /* N      doubles                                             */
+#define SMC2_DUMP_LL_NEW 6   /* N      doubles: their particle-filter log-likelihoods      */
+#define SMC2_DUMP_LOGW_PRE 7 /* N      doubles: log-weights before resampling              */
+#define SMC2_DUMP_ANC 8      /* N      int32:   ancestors chosen (identity if no resampling) */
+
+/* Bytes of device workspace needed for this config and these runs (0 on bad input). */
+size_t smc2_workspace_bytes(const smc2_config* cfg, int32_t n_runs, const smc2_run* runs);
+
+/* Validate, copy the inputs to the workspace and prepare iteration k = 1.
+ * hip_stream is a hipStream_t (NULL = the null stream). */
+int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run* runs, void* d_workspace,
+              size_t ws_bytes, void* hip_stream, smc2_ctx** out);
+
+/* Enqueue iteration k = (number of previous steps) + 1 for every run. Returns
+ * SMC2_E_STATE after K iterations. A run whose weights all vanish reports
+ * SMC2_E_NUMERIC from the next synchronising call and keeps its previous population. */
+int smc2_step(smc2_ctx* ctx);
+
+/* Copy run `run`'s records of the completed iterations (k_done x SMC2_RECORD_LEN(D)
+ * doubles) to host_dst; *k_done receives the number of completed iterations. */
+int smc2_records(smc2_ctx* ctx, int32_t run, double* host_dst, size_t n_doubles, int32_t* k_done);
+
+/* Posterior estimate of theta for run `run`: recycled over all completed iterations
+ * with c_k = l_k / sum_j l_j (Sec. IV-C) when recycled != 0, else the last
+ * iteration's. mean: D doubles; cov: D x D doubles or NULL. */
+int smc2_estimate(smc2_ctx* ctx, int32_t run, int32_t recycled, double* mean, double* cov);
+
+/* Copy one of the SMC2_DUMP_* arrays of run `run` to host memory (for tests). */
+int smc2_dump(smc2_ctx* ctx, int32_t what, int32_t run, void* host_dst, size_t bytes);
+
+/* Mean device time per iteration of the particle-filter kernels and of the whole
+ * iteration, in milliseconds, over the steps since the last call (events on the
+ * context's stream). Synchronises the stream. */
+int smc2_timing(smc2_ctx* ctx, double* ms_pf, double* ms_step, int32_t* n_steps);
+
+int smc2_destroy(smc2_ctx* ctx);
+
+const char* smc2_last_error(const smc2_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,56 @@
+/*
+ * smc2_kernels.h — kernel-level entry points of libsmc2.so.
+ *
+ * They run single building blocks of the sampler on device arrays so that each can
+ * be compared element by element with an independent implementation; the sampler
+ * itself (smc2.h) uses the same device code. All pointers prefixed d_ are device
+ * memory owned by the caller; nothing is allocated. Calls are asynchronous on the
+ * given HIP stream (NULL = null stream). Return SMC2_OK or a negative SMC2_E_* code
+ * (see smc2.h); smc2_last_error(NULL) describes the last failure of the thread.
+ */
+#ifndef SMC2_KERNELS_H
+#define SMC2_KERNELS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "smc2.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Philox4x32-10 block function (Salmon et al., SC'11): d_out[4e..4e+3] = Philox(counter
+ * d_ctr[4e..4e+3], key = (seed low word, seed high word)) for e < n. */
+int smc2_philox_batch(int32_t n, const uint32_t* d_ctr, uint64_t seed, uint32_t* d_out, void* hip_stream);
+
+/* Binomial(d_n[j], d_p[j]) draws of the particle-filter sampler (the flows of the
+ * chain-binomial model, Sec. V-A) at coordinates (particle j, filter i, iteration k,
+ * day t, draw b), j < count, in precision SMC2_PREC_FP32 (d_p rounded to FP32) or
+ * SMC2_PREC_FP64. d_n: int32[count]; d_p: double[count]; d_out: int32[count]. */
+int smc2_binomial_batch(int32_t precision, int32_t count, const int32_t* d_n, const double* d_p, uint64_t seed,
+                        uint32_t i, uint32_t k, uint32_t t, uint32_t b, int32_t* d_out, void* hip_stream);
+
+/* Integer systematic resampling (Sec. IV-B, Eq. cdf and ncopies, Alg. 1) of n_sets
+ * independent sets of n quantised weights (d_q: uint64[n_sets][n], each set with a
+ * positive total below 2^47): d_anc[s][m] = min{ j : n C_j > m Q + U } with C the
+ * inclusive cumulative sum, Q the total and U = floor(d_x64[s] Q / 2^64);
+ * d_trigger[s] = 1 when ESS < n/2 on q >> 8 (exact integer test). 1 <= n <= 4096. */
+int smc2_resample_batch(int32_t n_sets, int32_t n, const uint64_t* d_q, const uint64_t* d_x64, int32_t* d_anc,
+                        int32_t* d_trigger, void* hip_stream);
+
+/* Device workspace bytes for smc2_pf_loglik. */
+size_t smc2_pf_workspace_bytes(const smc2_config* cfg, const smc2_run* run);
+
+/* Particle-filter log-likelihood estimates (Sec. II) for n_theta model parameter
+ * vectors d_theta (double[n_theta][D], natural parameters, not sampler coordinates)
+ * on the observations of `run`: filter index i = row of d_theta, iteration index k
+ * (selects the random streams). d_ll: double[n_theta]. Uses cfg's model, obs,
+ * precision, pf_always, n_pop, fixed and block; N, K, prior and proposal are ignored. */
+int smc2_pf_loglik(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
+                   uint32_t k, double* d_ll, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,299 @@
+"""Python binding of libsmc2.so (include/smc2.h, include/smc2_kernels.h).
+
+Argument marshalling only: every step of the sampler runs in the HIP library.
+torch provides device memory (uint8 buffers) and the current HIP stream; nothing
+else is taken from it. Importing works without a GPU; using the library needs the
+built ``libsmc2.so`` (``python -m paper_2311_12973_amd.build``) and raises if it is
+missing -- there is no fallback implementation.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsmc2.so")
+
+OK, E_ARG, E_DEVICE, E_STATE, E_NUMERIC, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+SIR, SEIR, AGE_SEIR = 0, 1, 2
+OBS_POIS_PREV, OBS_POIS_INC, OBS_NB_INC = 0, 1, 2
+PREC_FP32, PREC_FP64 = 0, 1
+PRIOR_UNIFORM, PRIOR_LOGNORMAL, PRIOR_LOGITNORMAL, PRIOR_NORMAL = 0, 1, 2, 3
+L_FORWARD, L_GAUSS_OPT = 0, 1
+PROP_RW = 0
+DUMP = dict(phi=0, lp=1, ll=2, logw=3, phi_new=4, lp_new=5, ll_new=6, logw_pre=7, anc=8)
+NFIXED = 32
+
+
+def record_len(D):
+    return 6 + 2 * D + D * D
+
+
+class Smc2Error(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("smc2 error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("model", ctypes.c_int32), ("obs", ctypes.c_int32), ("D", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("K", ctypes.c_int32), ("precision", ctypes.c_int32), ("proposal", ctypes.c_int32),
+                ("lkernel", ctypes.c_int32), ("pf_always", ctypes.c_int32), ("use_graph", ctypes.c_int32),
+                ("block", ctypes.c_int32), ("ppt", ctypes.c_int32), ("n_pop", ctypes.c_double),
+                ("prior", ctypes.POINTER(ctypes.c_double)), ("rw_cov", ctypes.POINTER(ctypes.c_double)),
+                ("fixed", ctypes.POINTER(ctypes.c_double)), ("n_fixed", ctypes.c_int32)]
+
+
+class Run(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_int32), ("n_x", ctypes.c_int32), ("seed", ctypes.c_uint64),
+                ("y", ctypes.POINTER(ctypes.c_int32))]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsmc2.so; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsmc2.so is not built (run __graft_entry__.build() or "
+                               "python -m paper_2311_12973_amd.build); no fallback exists")
+        L = ctypes.CDLL(LIB_PATH)
+        c, P = ctypes, ctypes.POINTER
+        vp = c.c_void_p
+        L.smc2_workspace_bytes.restype = c.c_size_t
+        L.smc2_workspace_bytes.argtypes = [P(Config), c.c_int32, P(Run)]
+        L.smc2_init.restype = c.c_int
+        L.smc2_init.argtypes = [P(Config), c.c_int32, P(Run), vp, c.c_size_t, vp, P(vp)]
+        L.smc2_step.restype = c.c_int
+        L.smc2_step.argtypes = [vp]
+        L.smc2_records.restype = c.c_int
+        L.smc2_records.argtypes = [vp, c.c_int32, P(c.c_double), c.c_size_t, P(c.c_int32)]
+        L.smc2_estimate.restype = c.c_int
+        L.smc2_estimate.argtypes = [vp, c.c_int32, c.c_int32, P(c.c_double), P(c.c_double)]
+        L.smc2_dump.restype = c.c_int
+        L.smc2_dump.argtypes = [vp, c.c_int32, c.c_int32, vp, c.c_size_t]
+        L.smc2_timing.restype = c.c_int
+        L.smc2_timing.argtypes = [vp, P(c.c_double), P(c.c_double), P(c.c_int32)]
+        L.smc2_destroy.restype = c.c_int
+        L.smc2_destroy.argtypes = [vp]
+        L.smc2_last_error.restype = c.c_char_p
+        L.smc2_last_error.argtypes = [vp]
+        L.smc2_philox_batch.restype = c.c_int
+        L.smc2_philox_batch.argtypes = [c.c_int32, vp, c.c_uint64, vp, vp]
+        L.smc2_binomial_batch.restype = c.c_int
+        L.smc2_binomial_batch.argtypes = [c.c_int32, c.c_int32, vp, vp, c.c_uint64, c.c_uint32, c.c_uint32,
+                                          c.c_uint32, c.c_uint32, vp, vp]
+        L.smc2_resample_batch.restype = c.c_int
+        L.smc2_resample_batch.argtypes = [c.c_int32, c.c_int32, vp, vp, vp, vp, vp]
+        L.smc2_pf_workspace_bytes.restype = c.c_size_t
+        L.smc2_pf_workspace_bytes.argtypes = [P(Config), P(Run)]
+        L.smc2_pf_loglik.restype = c.c_int
+        L.smc2_pf_loglik.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp, c.c_size_t, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc, ctx=None):
+    if rc != OK:
+        msg = lib().smc2_last_error(ctx)
+        raise Smc2Error(rc, msg.decode() if msg else "")
+    return rc
+
+
+# ------------------------------------------------------------------ device buffers (torch)
+def _torch():
+    import torch
+    return torch
+
+
+def device_buffer(nbytes, device="cuda"):
+    """A 256-byte aligned uint8 device buffer: (tensor, pointer)."""
+    t = _torch().empty(int(nbytes) + 256, dtype=_torch().uint8, device=device)
+    p = t.data_ptr()
+    return t, p + ((-p) % 256)
+
+
+def to_device(arr, device="cuda"):
+    a = np.ascontiguousarray(arr)
+    t = _torch().from_numpy(a.view(np.uint8).reshape(-1).copy()).to(device)
+    return t, t.data_ptr()
+
+
+def from_device(t, ptr, dtype, count):
+    torch = _torch()
+    nbytes = np.dtype(dtype).itemsize * count
+    off = ptr - t.data_ptr()
+    host = t[off:off + nbytes].cpu().numpy()
+    return host.view(dtype).copy()
+
+
+def current_stream():
+    return _torch().cuda.current_stream().cuda_stream
+
+
+# ------------------------------------------------------------------ configs
+class _Keep:
+    """Host arrays referenced by a Config / Run array (kept alive with them)."""
+
+
+def make_config(w, N=None, K=None, precision=None, use_graph=0, block=0, lkernel=None, pf_always=None):
+    keep = _Keep()
+    D = int(w["D"])
+    keep.prior = np.ascontiguousarray(np.asarray(w["prior"], dtype=np.float64).reshape(D, 3))
+    keep.rw = np.ascontiguousarray(np.asarray(w["rw_cov"], dtype=np.float64).reshape(D, D))
+    keep.fixed = np.zeros(NFIXED, dtype=np.float64)
+    fx = list(w.get("fixed", []))
+    keep.fixed[:len(fx)] = fx
+    c = Config()
+    c.model, c.obs, c.D = int(w["model"]), int(w["obs"]), D
+    c.N = int(N if N is not None else w["N"])
+    c.K = int(K if K is not None else w["K"])
+    c.precision = int(precision if precision is not None else w["prec"])
+    c.proposal = PROP_RW
+    c.lkernel = int(lkernel if lkernel is not None else w.get("lkernel", L_GAUSS_OPT))
+    c.pf_always = int(pf_always if pf_always is not None else w.get("pf_always", 0))
+    c.use_graph, c.block, c.ppt = int(use_graph), int(block), 0
+    c.n_pop = float(w["n_pop"])
+    dp = ctypes.POINTER(ctypes.c_double)
+    c.prior = keep.prior.ctypes.data_as(dp)
+    c.rw_cov = keep.rw.ctypes.data_as(dp)
+    c.fixed = keep.fixed.ctypes.data_as(dp)
+    c.n_fixed = len(fx)
+    c._keep = keep
+    return c
+
+
+def make_runs(runs):
+    """runs: list of dict(T, nx, seed, y)."""
+    arr = (Run * len(runs))()
+    keep = []
+    for r, d in enumerate(runs):
+        y = np.ascontiguousarray(np.asarray(d["y"], dtype=np.int32))
+        keep.append(y)
+        arr[r].T = int(d.get("T", y.shape[0]))
+        arr[r].n_x = int(d["nx"])
+        arr[r].seed = int(d["seed"])
+        arr[r].y = y.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    arr._keep = keep
+    return arr
+
+
+# ------------------------------------------------------------------ the sampler
+class Sampler:
+    """One SMC^2 context (smc2_init / smc2_step / smc2_estimate) on the current HIP stream."""
+
+    def __init__(self, w, runs, device="cuda", **cfg_over):
+        self.cfg = make_config(w, **cfg_over)
+        self.runs = make_runs(runs)
+        self.R = len(runs)
+        L = lib()
+        nbytes = L.smc2_workspace_bytes(ctypes.byref(self.cfg), self.R, self.runs)
+        if nbytes == 0:
+            _check(E_ARG)
+        self.ws, self.ws_ptr = device_buffer(nbytes, device)
+        self.stream = current_stream()
+        h = ctypes.c_void_p()
+        _check(L.smc2_init(ctypes.byref(self.cfg), self.R, self.runs, ctypes.c_void_p(self.ws_ptr), nbytes,
+                           ctypes.c_void_p(self.stream), ctypes.byref(h)))
+        self.h = h
+        self.D = self.cfg.D
+        self.N = self.cfg.N
+
+    def step(self):
+        _check(lib().smc2_step(self.h), self.h)
+
+    def records(self, run=0):
+        RL = record_len(self.D)
+        buf = np.zeros((self.cfg.K, RL))
+        kd = ctypes.c_int32()
+        _check(lib().smc2_records(self.h, run, buf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), buf.size,
+                                  ctypes.byref(kd)), self.h)
+        return buf[:kd.value]
+
+    def estimate(self, run=0, recycled=True):
+        mean = np.zeros(self.D)
+        cov = np.zeros((self.D, self.D))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().smc2_estimate(self.h, run, int(recycled), mean.ctypes.data_as(dp), cov.ctypes.data_as(dp)),
+               self.h)
+        return mean, cov
+
+    def dump(self, what, run=0):
+        code = DUMP[what]
+        if what in ("phi", "phi_new"):
+            out = np.zeros((self.N, self.D))
+        elif what == "anc":
+            out = np.zeros(self.N, dtype=np.int32)
+        else:
+            out = np.zeros(self.N)
+        _check(lib().smc2_dump(self.h, code, run, out.ctypes.data_as(ctypes.c_void_p), out.nbytes), self.h)
+        return out
+
+    def timing(self):
+        a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        _check(lib().smc2_timing(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)), self.h)
+        return a.value, b.value, n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().smc2_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ kernel-level entry points
+def philox_batch(ctr, seed, device="cuda"):
+    ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
+    n = ctr.shape[0]
+    tc, pc = to_device(ctr, device)
+    to, po = device_buffer(16 * n, device)
+    _check(lib().smc2_philox_batch(n, pc, int(seed), po, current_stream()))
+    return from_device(to, po, np.uint32, 4 * n).reshape(n, 4)
+
+
+def binomial_batch(precision, n, p, seed, i=0, k=1, t=1, b=0, device="cuda"):
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    cnt = n.size
+    tn, pn = to_device(n, device)
+    tp, pp = to_device(p, device)
+    to, po = device_buffer(4 * cnt, device)
+    _check(lib().smc2_binomial_batch(precision, cnt, pn, pp, int(seed), i, k, t, b, po, current_stream()))
+    return from_device(to, po, np.int32, cnt)
+
+
+def resample_batch(q, x64, device="cuda"):
+    q = np.ascontiguousarray(q, dtype=np.uint64)
+    if q.ndim == 1:
+        q = q[None, :]
+    S, n = q.shape
+    x64 = np.ascontiguousarray(x64, dtype=np.uint64).reshape(S)
+    tq, pq = to_device(q, device)
+    tx, px = to_device(x64, device)
+    ta, pa = device_buffer(4 * S * n, device)
+    tt, pt = device_buffer(4 * S, device)
+    _check(lib().smc2_resample_batch(S, n, pq, px, pa, pt, current_stream()))
+    return from_device(ta, pa, np.int32, S * n).reshape(S, n), from_device(tt, pt, np.int32, S)
+
+
+def pf_loglik(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0, device="cuda"):
+    """Particle-filter log-likelihoods for the rows of theta (natural parameters)."""
+    cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, pf_always=pf_always, block=block)
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
+    runs = make_runs([dict(T=y.shape[0], nx=nx, seed=seed, y=y)])
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    n = theta.shape[0]
+    L = lib()
+    wsb = L.smc2_pf_workspace_bytes(ctypes.byref(cfg), runs)
+    tws, pws = device_buffer(wsb, device)
+    tth, pth = to_device(theta, device)
+    tll, pll = device_buffer(8 * n, device)
+    _check(L.smc2_pf_loglik(ctypes.byref(cfg), n, pth, runs, int(k), pll, pws, wsb, current_stream()))
+    return from_device(tll, pll, np.float64, n)

@@ -1,0 +1,246 @@
+// device_common.h — device building blocks of the particle filter (gfx950).
+//
+// Random numbers: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by the
+// run seed; every draw is a pure function of its logical coordinates, so results
+// do not depend on the launch shape. Counter layout:
+//   flows       (particle j, filter i, k<<16 | t, 1<<24 | draw b<<16 | call a)
+//   PF resample (0, filter i, k<<16 | t, 2<<24)
+//   prior       (sample i, 0, 1<<16, 3<<24 | coordinate d)
+//   RW normal   (sample i, 0, k<<16, 4<<24 | coordinate d)
+//   outer resample (0, 0, k<<16, 5<<24)
+// Uniforms: u24(x) = (2(x>>9)+1) 2^-24 (exact in FP32); u53 = (2(x64>>12)+1) 2^-53.
+//
+// Precision: the particle filter works in `real` (float or double). Every
+// transcendental is evaluated in FP64 and rounded to `real`, every other
+// operation is one IEEE operation in `real` (the library is built with
+// -ffp-contract=off), so a reimplementation that follows the same definitions
+// reproduces each integer decision.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smc2 {
+
+enum : uint32_t { S_PF_PROP = 1u, S_PF_RS = 2u, S_PRIOR = 3u, S_RW = 4u, S_OUTER_RS = 5u };
+
+struct W4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                       uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return W4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ float u24(uint32_t x) { return (float)(2u * (x >> 9) + 1u) * 0x1p-24f; }
+
+__device__ __forceinline__ double u53(uint32_t lo, uint32_t hi)
+{
+    const uint64_t x = ((uint64_t)hi << 32) | lo;
+    return (double)(2ull * (x >> 12) + 1ull) * 0x1p-53;
+}
+
+// Box-Muller on one Philox call, first output.
+__device__ __forceinline__ double normal_call(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint64_t seed)
+{
+    const W4 w = philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double r = sqrt(-2.0 * log(u53(w.x, w.y)));
+    return r * cos(6.283185307179586 * u53(w.z, w.w));
+}
+
+// ----------------------------------------------------------- precision helpers
+template <typename real> __device__ __forceinline__ real rdiv(real a, real b);
+template <> __device__ __forceinline__ float rdiv<float>(float a, float b) { return __fdiv_rn(a, b); }
+template <> __device__ __forceinline__ double rdiv<double>(double a, double b) { return a / b; }
+template <typename real> __device__ __forceinline__ real rsqrt_rn(real a);
+template <> __device__ __forceinline__ float rsqrt_rn<float>(float a) { return __fsqrt_rn(a); }
+template <> __device__ __forceinline__ double rsqrt_rn<double>(double a) { return __dsqrt_rn(a); }
+
+// Stream of one binomial draw: flows counter without the call index.
+struct DrawStream {
+    uint32_t j, i, kt, b;
+    uint32_t k0, k1;
+    __device__ __forceinline__ W4 call(uint32_t a) const
+    {
+        return philox10(j, i, kt, (S_PF_PROP << 24) | (b << 16) | a, k0, k1);
+    }
+};
+
+// ----------------------------------------------------------- binomial sampler
+// Sequential-search inversion of the Binomial(n, p) CDF for p <= 1/2, n p < 10:
+// f_0 = (1-p)^n, f_{k+1} = f_k ((n-k) r) / (k+1), r = p/(1-p); stops at the first k
+// whose running sum reaches u, when adding a term no longer changes the sum, or
+// at k = min(n, 127).
+template <typename real>
+__device__ __forceinline__ int32_t binom_inversion(int32_t n, real p, uint32_t word)
+{
+    const real u = (real)u24(word);
+    const real q = (real)1 - p;
+    const real r = rdiv<real>(p, q);
+    real f = (real)exp((double)n * log1p(-(double)p));
+    real F = f;
+    int32_t k = 0;
+    const int32_t kcap = n < 127 ? n : 127;
+    while (u > F && k < kcap) {
+        real t = (real)(n - k) * r;
+        t = t * rdiv<real>((real)1, (real)(k + 1));
+        f = f * t;
+        k = k + 1;
+        const real Fn = F + f;
+        if (Fn == F) break;
+        F = Fn;
+    }
+    return k;
+}
+
+// log(x!) for integer-valued x >= 0 in FP64: exact table below 16, Stirling's series
+// for log Gamma(x+1) with terms up to (x+1)^-7 above (truncation error < 1e-14).
+static __constant__ double c_lfact_tab[16] = {
+    0.0, 0.0, 0.69314718055994530942, 1.7917594692280550008, 3.1780538303479456196, 4.7874917427820459942,
+    6.5792512120101009951, 8.5251613610654143002, 10.604602902745250228, 12.801827480081469611,
+    15.104412573075515295, 17.502307845873885839, 19.98721449566188615, 22.552163853123422886,
+    25.1912211827386815, 27.899271383840891566};
+
+__device__ __forceinline__ double lfact(double x)
+{
+    if (x < 16.0) return c_lfact_tab[(int)x];
+    const double z = x + 1.0;
+    const double r = 1.0 / z, r2 = r * r;
+    const double series = r * (1.0 / 12.0 - r2 * (1.0 / 360.0 - r2 * (1.0 / 1260.0 - r2 * (1.0 / 1680.0))));
+    return ((x + 0.5) * log(z) - z) + 0.91893853320467274178 + series;
+}
+
+// BTRS transformed rejection (W. Hoermann, J. Stat. Comput. Simul. 46, 1993) for
+// p <= 1/2, n p >= 10. Constants, proposal index and squeeze in `real`; the centre
+// n p + 1/2 split in FP64 into integer and fraction; the final acceptance test in
+// FP64 on log-factorials. Attempt e uses words 2(e&1), 2(e&1)+1 of call e>>1.
+template <typename real>
+__device__ __forceinline__ int32_t binom_btrs(int32_t n, real p, const DrawStream& s)
+{
+    const real nr = (real)n;
+    const real q = (real)1 - p;
+    const real spq = rsqrt_rn<real>((nr * p) * q);
+    const real bb = (real)1.15 + (real)2.53 * spq;
+    const real aa = ((real)-0.0873 + (real)0.0248 * bb) + (real)0.01 * p;
+    const real vr = (real)0.92 - rdiv<real>((real)4.2, bb);
+    const double c = (double)n * (double)p + 0.5;
+    const double cfl = floor(c);
+    const int64_t ci = (int64_t)cfl;
+    const real cf = (real)(c - cfl);
+    W4 w{0u, 0u, 0u, 0u};
+    for (int e = 0; e < 256; ++e) {
+        if ((e & 1) == 0) w = s.call((uint32_t)(e >> 1));
+        const uint32_t wu = (e & 1) ? w.z : w.x;
+        const uint32_t wv = (e & 1) ? w.w : w.y;
+        const real u = (real)u24(wu) - (real)0.5;
+        const real v = (real)u24(wv);
+        const real us = (real)0.5 - (real)fabs((double)u);
+        real t = (real)2 * aa;
+        t = rdiv<real>(t, us);
+        t = t + bb;
+        t = t * u;
+        t = t + cf;
+        const int64_t k = ci + (int64_t)floor((double)t);
+        if (k < 0 || k > n) continue;
+        if (us >= (real)0.07 && v <= vr) return (int32_t)k;
+        const double alpha = (2.83 + 5.1 / (double)bb) * (double)spq;
+        const double lpq = log((double)p / (double)q);
+        const double m = floor((double)(n + 1) * (double)p);
+        const double h = lfact(m) + lfact((double)n - m);
+        const double lhs = log((double)v * alpha / ((double)aa / ((double)us * (double)us) + (double)bb));
+        const double rhs = ((h - lfact((double)k)) - lfact((double)(n - k))) + ((double)k - m) * lpq;
+        if (lhs <= rhs) return (int32_t)k;
+    }
+    return (int32_t)floor((double)(n + 1) * (double)p);
+}
+
+template <typename real>
+__device__ __forceinline__ int32_t binomial(int32_t n, real p, const DrawStream& s)
+{
+    if (n <= 0 || !(p > (real)0)) return 0;
+    if (p >= (real)1) return n;
+    const bool flip = p > (real)0.5;
+    const real pp = flip ? (real)1 - p : p;
+    int32_t k;
+    if ((real)n * pp < (real)10) {
+        k = binom_inversion<real>(n, pp, s.call(0u).x);
+    } else {
+        k = binom_btrs<real>(n, pp, s);
+    }
+    return flip ? n - k : k;
+}
+
+// Probability 1 - exp(-x) of leaving a compartment within a day at hazard x.
+template <typename real> __device__ __forceinline__ real leave_prob(real x)
+{
+    return (real)(-expm1(-(double)x));
+}
+
+// ----------------------------------------------------------- observations (FP64)
+enum : int { OBS_POIS_PREV = 0, OBS_POIS_INC = 1, OBS_NB_INC = 2 };
+
+// per-day constant: Poisson lgamma(y+1); NB lgamma(y+r) - lgamma(r) - lgamma(y+1) + r log r
+__device__ __forceinline__ double obs_const(int obs, int32_t y, double r)
+{
+    if (obs == OBS_NB_INC) return ((lgamma((double)y + r) - lgamma(r)) - lgamma((double)y + 1.0)) + r * log(r);
+    return lgamma((double)y + 1.0);
+}
+
+template <int OBS>
+__device__ __forceinline__ double obs_logpmf(int32_t y, int32_t cnt, double r, double cst)
+{
+    if (cnt <= 0) return (y == 0) ? 0.0 : -INFINITY;
+    const double mu = (double)cnt;
+    if (OBS == OBS_NB_INC) return (cst + (double)y * log(mu)) - (r + (double)y) * log(r + mu);
+    return ((double)y * log(mu) - mu) - cst;
+}
+
+// ----------------------------------------------------------- wave / block primitives
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
+
+template <typename T> __device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const T u = __shfl_xor(v, o, 64);
+        v = u > v ? u : v;
+    }
+    return v;
+}
+
+template <typename T> __device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// inclusive scan within a wave
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v)
+{
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t u = __shfl_up(v, o, 64);
+        if (l >= o) v += u;
+    }
+    return v;
+}
+
+}  // namespace smc2

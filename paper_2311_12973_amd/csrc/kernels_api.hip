@@ -1,0 +1,169 @@
+// kernels_api.hip — kernel-level entry points (include/smc2_kernels.h): the
+// building blocks of the sampler on caller-provided device arrays.
+#include <string>
+
+#include "../../include/smc2_kernels.h"
+#include "block_ops.h"
+#include "pf_kernel.h"
+
+namespace smc2 {
+
+__global__ void k_philox_batch(int n, const uint32_t* ctr, uint32_t k0, uint32_t k1, uint32_t* out)
+{
+    const int e = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (e >= n) return;
+    const W4 w = philox10(ctr[4 * e], ctr[4 * e + 1], ctr[4 * e + 2], ctr[4 * e + 3], k0, k1);
+    out[4 * e] = w.x;
+    out[4 * e + 1] = w.y;
+    out[4 * e + 2] = w.z;
+    out[4 * e + 3] = w.w;
+}
+
+template <typename real>
+__global__ void k_binomial_batch(int count, const int32_t* n, const double* p, uint32_t i, uint32_t kt, uint32_t b,
+                                 uint32_t k0, uint32_t k1, int32_t* out)
+{
+    const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (j >= count) return;
+    out[j] = binomial<real>(n[j], (real)p[j], DrawStream{(uint32_t)j, i, kt, b, k0, k1});
+}
+
+__global__ void __launch_bounds__(256) k_resample_batch(int n, const uint64_t* q, const uint64_t* x64, int32_t* anc,
+                                                        int32_t* trig)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ RedLds red;
+    uint64_t* C = reinterpret_cast<uint64_t*>(smem);
+    const int s = (int)blockIdx.x;
+    const uint64_t* qs = q + (size_t)s * n;
+    double dz = 0.0;
+    uint64_t q1 = 0, q2 = 0;
+    for (int j = (int)threadIdx.x; j < n; j += (int)blockDim.x) {
+        const uint64_t v = qs[j];
+        C[j] = v;
+        const uint64_t h = v >> 8;
+        q1 += h;
+        q2 += h * h;
+    }
+    block_sum3(dz, q1, q2, &red);
+    const uint64_t Q = block_scan_lds(C, n, &red);
+    block_ancestors(C, n, Q, x64[s], anc + (size_t)s * n);
+    if (threadIdx.x == 0) trig[s] = ess_below_half(q1, q2, n) ? 1 : 0;
+}
+
+}  // namespace smc2
+
+using namespace smc2;
+
+// defined in smc2_api.cpp: the thread's message for smc2_last_error(NULL)
+void smc2_set_thread_error(const std::string& m);
+
+namespace {
+int kfail(int code, const std::string& m)
+{
+    smc2_set_thread_error(m);
+    return code;
+}
+int n_obs_of(int model) { return model == SMC2_AGE_SEIR ? 4 : 1; }
+}  // namespace
+
+extern "C" int smc2_philox_batch(int32_t n, const uint32_t* d_ctr, uint64_t seed, uint32_t* d_out, void* stream)
+{
+    if (n < 0 || (n > 0 && (!d_ctr || !d_out))) return kfail(SMC2_E_ARG, "bad philox arguments");
+    if (n == 0) return SMC2_OK;
+    hipLaunchKernelGGL(k_philox_batch, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream, n, d_ctr,
+                       (uint32_t)seed, (uint32_t)(seed >> 32), d_out);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SMC2_OK : kfail(SMC2_E_DEVICE, hipGetErrorString(e));
+}
+
+extern "C" int smc2_binomial_batch(int32_t precision, int32_t count, const int32_t* d_n, const double* d_p,
+                                   uint64_t seed, uint32_t i, uint32_t k, uint32_t t, uint32_t b, int32_t* d_out,
+                                   void* stream)
+{
+    if (count < 0 || (count > 0 && (!d_n || !d_p || !d_out))) return kfail(SMC2_E_ARG, "bad binomial arguments");
+    if (precision != SMC2_PREC_FP32 && precision != SMC2_PREC_FP64) return kfail(SMC2_E_ARG, "bad precision");
+    if (k > 65535 || t > 65535 || b > 255) return kfail(SMC2_E_ARG, "k, t or b out of range");
+    if (count == 0) return SMC2_OK;
+    const dim3 g((unsigned)((count + 255) / 256)), blk(256);
+    const uint32_t kt = (k << 16) | t, k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (precision == SMC2_PREC_FP32)
+        hipLaunchKernelGGL(k_binomial_batch<float>, g, blk, 0, (hipStream_t)stream, count, d_n, d_p, i, kt, b, k0, k1,
+                           d_out);
+    else
+        hipLaunchKernelGGL(k_binomial_batch<double>, g, blk, 0, (hipStream_t)stream, count, d_n, d_p, i, kt, b, k0, k1,
+                           d_out);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SMC2_OK : kfail(SMC2_E_DEVICE, hipGetErrorString(e));
+}
+
+extern "C" int smc2_resample_batch(int32_t n_sets, int32_t n, const uint64_t* d_q, const uint64_t* d_x64,
+                                   int32_t* d_anc, int32_t* d_trigger, void* stream)
+{
+    if (n_sets < 0 || n < 1 || n > 4096) return kfail(SMC2_E_ARG, "n must be in [1, 4096]");
+    if (n_sets > 0 && (!d_q || !d_x64 || !d_anc || !d_trigger)) return kfail(SMC2_E_ARG, "null pointer");
+    if (n_sets == 0) return SMC2_OK;
+    hipLaunchKernelGGL(k_resample_batch, dim3((unsigned)n_sets), dim3(256), (size_t)n * 8, (hipStream_t)stream, n,
+                       d_q, d_x64, d_anc, d_trigger);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? SMC2_OK : kfail(SMC2_E_DEVICE, hipGetErrorString(e));
+}
+
+extern "C" size_t smc2_pf_workspace_bytes(const smc2_config* cfg, const smc2_run* run)
+{
+    if (!cfg || !run || run->T < 1) return 0;
+    const size_t y = ((size_t)run->T * n_obs_of(cfg->model) * 4 + 255) & ~(size_t)255;
+    return 256 + y;
+}
+
+extern "C" int smc2_pf_loglik(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
+                              uint32_t k, double* d_ll, void* d_ws, size_t ws_bytes, void* stream)
+{
+    if (!cfg || !run || !run->y) return kfail(SMC2_E_ARG, "null config or run");
+    if (!pf_supported(cfg->model, cfg->obs)) return kfail(SMC2_E_UNSUPPORTED, "model/observation not supported");
+    if (cfg->precision != SMC2_PREC_FP32 && cfg->precision != SMC2_PREC_FP64) return kfail(SMC2_E_ARG, "precision");
+    if (cfg->D < 1 || cfg->D > SMC2_DMAX) return kfail(SMC2_E_ARG, "bad D");
+    if (run->T < 1 || run->T > 1024 || run->n_x < 1 || run->n_x > (cfg->model == SMC2_AGE_SEIR ? 2048 : 4096))
+        return kfail(SMC2_E_ARG, "T or n_x out of range");
+    if (!(cfg->n_pop >= 1.0 && cfg->n_pop <= 16777216.0)) return kfail(SMC2_E_ARG, "n_pop out of range");
+    if (k > 65535) return kfail(SMC2_E_ARG, "k out of range");
+    if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 256 || cfg->block % 64)) return kfail(SMC2_E_ARG, "block");
+    if (n_theta < 0 || (n_theta > 0 && (!d_theta || !d_ll))) return kfail(SMC2_E_ARG, "bad theta/ll");
+    if (!d_ws || ws_bytes < smc2_pf_workspace_bytes(cfg, run) || ((uintptr_t)d_ws & 255u))
+        return kfail(SMC2_E_ARG, "workspace missing, too small or not 256-byte aligned");
+    if (cfg->n_fixed < 0 || cfg->n_fixed > SMC2_NFIXED || (cfg->n_fixed > 0 && !cfg->fixed))
+        return kfail(SMC2_E_ARG, "bad fixed constants");
+    const int no = n_obs_of(cfg->model);
+    for (int e = 0; e < run->T * no; ++e)
+        if (run->y[e] < 0) return kfail(SMC2_E_ARG, "negative observation");
+    if (n_theta == 0) return SMC2_OK;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char* w = (unsigned char*)d_ws;
+    RunDev rd{run->T, run->n_x, 0, 0, (uint32_t)run->seed, (uint32_t)(run->seed >> 32)};
+    hipError_t e = hipMemcpyAsync(w, &rd, sizeof(rd), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(w + 256, run->y, (size_t)run->T * no * 4, hipMemcpyHostToDevice, s);
+    PFArgs a{};
+    a.theta = d_theta;
+    a.active = nullptr;
+    a.ll = d_ll;
+    a.y = (const int32_t*)(w + 256);
+    a.runs = (const RunDev*)w;
+    a.items = nullptr;
+    a.k_dev = nullptr;
+    a.k_const = k;
+    a.n_items = n_theta;
+    a.N = n_theta;
+    a.D = cfg->D;
+    a.pf_always = cfg->pf_always;
+    a.n_pop = cfg->n_pop;
+    for (int i = 0; i < SMC2_NFIXED; ++i) a.fx[i] = i < cfg->n_fixed ? cfg->fixed[i] : 0.0;
+    const int block = cfg->block ? cfg->block : (run->n_x >= 256 ? 256 : ((run->n_x + 63) / 64) * 64);
+    const size_t lds = pf_lds_bytes(cfg->model, cfg->precision, block, run->n_x, run->T);
+    if (lds > 160 * 1024) return kfail(SMC2_E_ARG, "particle filter does not fit in LDS");
+    if (e == hipSuccess) e = pf_prepare(cfg->precision, cfg->model, cfg->obs, lds);
+    if (e == hipSuccess) e = launch_pf(cfg->precision, cfg->model, cfg->obs, block, lds, a, s);
+    // the host copies of rd and y must stay valid until the copies have run
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? SMC2_OK : kfail(SMC2_E_DEVICE, hipGetErrorString(e));
+}

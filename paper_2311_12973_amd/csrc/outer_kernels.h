@@ -1,0 +1,46 @@
+// outer_kernels.h — launch interface of the outer SMC^2 step (FP64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace smc2 {
+
+enum : int { PRIOR_UNIFORM = 0, PRIOR_LOGNORMAL = 1, PRIOR_LOGITNORMAL = 2, PRIOR_NORMAL = 3 };
+enum : int { L_FORWARD = 0, L_GAUSS_OPT = 1 };
+constexpr int OUTER_BLOCK = 256;
+constexpr int DMAX = 8;
+
+// Per-run device arrays of the outer sampler (each run holds N samples).
+struct OuterArrays {
+    double* phi;       // [R][N][D] current population (sampler coordinates)
+    double* lp;        // [R][N]    its log-prior
+    double* ll;        // [R][N]    its log-likelihood estimate
+    double* logw;      // [R][N]    its log-weight
+    double* phi_new;   // [R][N][D] proposals of this iteration
+    double* lp_new;    // [R][N]
+    double* ll_new;    // [R][N]    particle-filter output
+    double* theta_new; // [R][N][D] model parameters of the proposals
+    double* logw_pre;  // [R][N]    weights before resampling
+    double* scratch;   // [R][N]    normalised weights
+    uint64_t* qc;      // [R][N]    quantised weights / cumulative sums
+    int32_t* anc;      // [R][N]
+    uint8_t* active;   // [R][N]    run the particle filter for this proposal
+    double* records;   // [R][K][record_len]
+    int32_t* status;   // [R]       0, or -4 when every weight of the run vanished
+    int32_t* k_dev;    // iteration counter
+};
+
+struct OuterParams {
+    int32_t N, D, K, R;
+    int32_t lkernel;
+    int32_t rec_len;
+    const double* prior; // [D][3] {family, a, b} (device)
+    const double* lrw;   // [D][D] lower Cholesky factor of the RW covariance (device)
+};
+
+hipError_t launch_begin_iteration(const OuterArrays& o, hipStream_t s);
+hipError_t launch_propose(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds, hipStream_t s);
+hipError_t launch_outer_update(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds,
+                               hipStream_t s);
+
+}  // namespace smc2

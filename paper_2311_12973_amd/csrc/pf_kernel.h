@@ -1,0 +1,45 @@
+// pf_kernel.h — launch interface of the particle-filter batch kernel.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace smc2 {
+
+enum : int { MODEL_SIR = 0, MODEL_SEIR = 1, MODEL_AGE = 2 };
+
+// One run of the batch: its observation series starts at y_off (T x n_obs int32).
+struct RunDev {
+    int32_t T;
+    int32_t nx;
+    int32_t y_off;
+    int32_t pad;
+    uint32_t k0, k1; // Philox key (run seed)
+};
+
+struct PFArgs {
+    const double* theta;    // [G][D] model parameters of the G filters
+    const uint8_t* active;  // [G] 0 = skip (log-likelihood -inf); NULL = all active
+    double* ll;             // [G] log-likelihood estimates (out)
+    const int32_t* y;       // concatenated observations of all runs
+    const RunDev* runs;     // [n_runs]
+    const int32_t* items;   // [n_items] global filter indices g, or NULL for g = item
+    const int32_t* k_dev;   // iteration counter in device memory, or NULL to use k_const
+    uint32_t k_const;
+    int32_t n_items;
+    int32_t N;              // filters per run: g = run * N + filter
+    int32_t D;
+    int32_t pf_always;
+    int32_t pad;
+    double n_pop;
+    double fx[32];          // model constants
+};
+
+// Dynamic LDS bytes of one filter workgroup.
+size_t pf_lds_bytes(int model, int prec, int block, int nx, int T);
+bool pf_supported(int model, int obs);
+// Raise the dynamic-LDS limit of the kernel when a launch needs more than 64 KiB.
+hipError_t pf_prepare(int prec, int model, int obs, size_t lds);
+hipError_t launch_pf(int prec, int model, int obs, int block, size_t lds, const PFArgs& a, hipStream_t s);
+
+}  // namespace smc2

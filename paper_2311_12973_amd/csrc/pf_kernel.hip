@@ -1,0 +1,333 @@
+// pf_kernel.hip — the batch of particle filters (Sec. II) on gfx950.
+//
+// One workgroup runs one particle filter: it owns the filter's N_x particles for
+// all T days. Thread t holds particles t*PPT .. t*PPT+PPT-1 (compartment counts and
+// log-weights in registers), so the only HBM traffic is theta, the observations
+// (L2-resident, shared by all filters) and one log-likelihood per filter. Per day:
+//   1. propagate every particle through the chain-binomial model (Sec. V-A),
+//      flows drawn from counter-based Philox streams (particle, filter, k, t, draw);
+//   2. weight update a = lw + log g(y_t | x_t) (Sec. II, bootstrap proposal);
+//   3. block max m, then w = exp(a - m) in FP64; the FP64 block sum S gives the
+//      likelihood increment m + log S - log S_prev (the mean unnormalised weight of
+//      Sec. II, accumulated in FP64);
+//   4. if ESS < N_x/2 (exact integer test on the quantised weights) and t < T:
+//      integer systematic resampling (LDS scan + search), gather of the counts
+//      through LDS, log-weights reset (every particle gets the mean weight).
+#include "block_ops.h"
+#include "pf_kernel.h"
+
+namespace smc2 {
+
+template <int MODEL> struct ModelShape;
+template <> struct ModelShape<MODEL_SIR> { static constexpr int NC = 2, NG = 1; };
+template <> struct ModelShape<MODEL_SEIR> { static constexpr int NC = 3, NG = 1; };
+template <> struct ModelShape<MODEL_AGE> { static constexpr int NC = 12, NG = 4; };
+
+// Per-filter constants of the transition kernel, rounded once to `real`.
+template <typename real> struct MConst {
+    real cinf;      // beta / N_pop
+    real p_ei;      // 1 - exp(-sigma)
+    real p_ir;      // 1 - exp(-gamma)
+    real cs[4][4];  // beta s_g C_gh / N_h  (age-structured)
+    double r;       // negative-binomial dispersion
+    int32_t x0[12]; // initial compartment counts
+};
+
+template <typename real, int MODEL>
+__device__ __forceinline__ void model_setup(const PFArgs& a, const double* th, MConst<real>& mc)
+{
+    if (MODEL == MODEL_SIR) {
+        const int32_t i0 = (int32_t)a.fx[0];
+        mc.cinf = (real)(th[0] / a.n_pop);
+        mc.p_ir = (real)(-expm1(-th[1]));
+        mc.p_ei = (real)0;
+        mc.r = 0.0;
+        mc.x0[0] = (int32_t)a.n_pop - i0;
+        mc.x0[1] = i0;
+    } else if (MODEL == MODEL_SEIR) {
+        mc.r = (a.D >= 5) ? th[4] : a.fx[0];
+        mc.cinf = (real)(th[0] / a.n_pop);
+        mc.p_ei = (real)(-expm1(-th[1]));
+        mc.p_ir = (real)(-expm1(-th[2]));
+        double i0 = floor(th[3] * a.n_pop + 0.5);
+        i0 = i0 < 1.0 ? 1.0 : (i0 > a.n_pop ? a.n_pop : i0);
+        mc.x0[0] = (int32_t)(a.n_pop - i0);
+        mc.x0[1] = 0;
+        mc.x0[2] = (int32_t)i0;
+    } else {
+        mc.r = th[4];
+        mc.cinf = (real)0;
+        mc.p_ei = (real)(-expm1(-th[1]));
+        mc.p_ir = (real)(-expm1(-th[2]));
+        const double s[4] = {1.0, th[5], th[6], th[7]};
+        double ng[4];
+        for (int g = 0; g < 4; ++g) ng[g] = floor(a.fx[16 + g] * a.n_pop + 0.5);
+        for (int g = 0; g < 4; ++g)
+            for (int h = 0; h < 4; ++h) mc.cs[g][h] = (real)(((th[0] * s[g]) * a.fx[4 * g + h]) / ng[h]);
+        for (int g = 0; g < 4; ++g) {
+            double i0 = floor(th[3] * ng[g] + 0.5);
+            i0 = i0 < 1.0 ? 1.0 : (i0 > ng[g] ? ng[g] : i0);
+            mc.x0[3 * g] = (int32_t)(ng[g] - i0);
+            mc.x0[3 * g + 1] = 0;
+            mc.x0[3 * g + 2] = (int32_t)i0;
+        }
+    }
+}
+
+// One day of the chain-binomial model for particle j, whose counts live in LDS
+// (st[c * cap + j]); flows drawn from the previous day's state. Draw index b:
+// SIR (S->I, I->R) = (0, 1); SEIR (S->E, E->I, I->R) = (0, 1, 2); age-structured
+// group g: 3g, 3g+1, 3g+2 (the draw index equals the index of the compartment the
+// flow leaves). One copy of the sampler per model: the draws of a day run in a
+// loop. Returns log g(y_t | x_t) in FP64.
+template <typename real, int MODEL, int OBS>
+__device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* st, int cap, int j,
+                                               DrawStream ds, const int32_t* yt, const double* ct)
+{
+    if (MODEL == MODEL_SIR) {
+        const int32_t S = st[j], I = st[cap + j];
+        const real p_si = leave_prob<real>(mc.cinf * (real)I);
+        int32_t nsi = 0, nir = 0;
+#pragma nounroll
+        for (int b = 0; b < 2; ++b) {
+            ds.b = (uint32_t)b;
+            const int32_t v = binomial<real>(b == 0 ? S : I, b == 0 ? p_si : mc.p_ir, ds);
+            nsi = b == 0 ? v : nsi;
+            nir = b == 1 ? v : nir;
+        }
+        const int32_t I1 = I + nsi - nir;
+        st[j] = S - nsi;
+        st[cap + j] = I1;
+        return obs_logpmf<OBS>(yt[0], OBS == OBS_POIS_PREV ? I1 : nsi, mc.r, ct[0]);
+    } else if (MODEL == MODEL_SEIR) {
+        const int32_t S = st[j], E = st[cap + j], I = st[2 * cap + j];
+        const real p_se = leave_prob<real>(mc.cinf * (real)I);
+        int32_t nse = 0, nei = 0, nir = 0;
+#pragma nounroll
+        for (int b = 0; b < 3; ++b) {
+            ds.b = (uint32_t)b;
+            const int32_t n = b == 0 ? S : (b == 1 ? E : I);
+            const real p = b == 0 ? p_se : (b == 1 ? mc.p_ei : mc.p_ir);
+            const int32_t v = binomial<real>(n, p, ds);
+            nse = b == 0 ? v : nse;
+            nei = b == 1 ? v : nei;
+            nir = b == 2 ? v : nir;
+        }
+        const int32_t I1 = I + nei - nir;
+        st[j] = S - nse;
+        st[cap + j] = E + nse - nei;
+        st[2 * cap + j] = I1;
+        return obs_logpmf<OBS>(yt[0], OBS == OBS_POIS_PREV ? I1 : nei, mc.r, ct[0]);
+    } else {
+        // forces of infection from the previous day's infected counts
+        real pse0, pse1, pse2, pse3;
+        {
+            real acc[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) {
+                acc[g] = (real)0;
+#pragma unroll
+                for (int h = 0; h < 4; ++h) acc[g] = acc[g] + mc.cs[g][h] * (real)st[(3 * h + 2) * cap + j];
+            }
+            pse0 = leave_prob<real>(acc[0]);
+            pse1 = leave_prob<real>(acc[1]);
+            pse2 = leave_prob<real>(acc[2]);
+            pse3 = leave_prob<real>(acc[3]);
+        }
+        double lg = 0.0;
+#pragma nounroll
+        for (int g = 0; g < 4; ++g) {
+            const int32_t S = st[(3 * g) * cap + j], E = st[(3 * g + 1) * cap + j], I = st[(3 * g + 2) * cap + j];
+            const real p_se = g == 0 ? pse0 : (g == 1 ? pse1 : (g == 2 ? pse2 : pse3));
+            int32_t nse = 0, nei = 0, nir = 0;
+#pragma nounroll
+            for (int b = 0; b < 3; ++b) {
+                ds.b = (uint32_t)(3 * g + b);
+                const int32_t n = b == 0 ? S : (b == 1 ? E : I);
+                const real p = b == 0 ? p_se : (b == 1 ? mc.p_ei : mc.p_ir);
+                const int32_t v = binomial<real>(n, p, ds);
+                nse = b == 0 ? v : nse;
+                nei = b == 1 ? v : nei;
+                nir = b == 2 ? v : nir;
+            }
+            const int32_t I1 = I + nei - nir;
+            st[(3 * g) * cap + j] = S - nse;
+            st[(3 * g + 1) * cap + j] = E + nse - nei;
+            st[(3 * g + 2) * cap + j] = I1;
+            lg = lg + obs_logpmf<OBS>(yt[g], OBS == OBS_POIS_PREV ? I1 : nei, mc.r, ct[g]);
+        }
+        return lg;
+    }
+}
+
+// LDS layout of one filter (cap = particles rounded up to the block size):
+//   C   u64[cap]     quantised weights, then their inclusive scan
+//   red RedLds       reduction slots
+//   cst f64[T*NG]    per-day observation constants
+//   lw  real[cap]    log-weights (relative to the last maximum)
+//   st  i32[NC*cap]  compartment counts
+//   tmp i32[cap]     gather staging
+//   anc i32[cap]     ancestors
+template <typename real, int MODEL, int OBS>
+__global__ void __launch_bounds__(1024) k_pf(PFArgs a)
+{
+    constexpr int NC = ModelShape<MODEL>::NC;
+    constexpr int NG = ModelShape<MODEL>::NG;
+    const int item = (int)blockIdx.x;
+    if (item >= a.n_items) return;
+    const int g = a.items ? a.items[item] : item;
+    const int tid = (int)threadIdx.x;
+    const int nthr = (int)blockDim.x;
+    if (a.active && !a.active[g]) {
+        if (tid == 0) a.ll[g] = -INFINITY;
+        return;
+    }
+    const int run_i = g / a.N;
+    const uint32_t filt = (uint32_t)(g - run_i * a.N);
+    const RunDev run = a.runs[run_i];
+    const int T = run.T, nx = run.nx;
+    const uint32_t kit = a.k_dev ? (uint32_t)(*a.k_dev) : a.k_const;
+    const int cap = ((nx + nthr - 1) / nthr) * nthr;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    uint64_t* C = reinterpret_cast<uint64_t*>(smem);
+    RedLds* red = reinterpret_cast<RedLds*>(C + cap);
+    double* cst = reinterpret_cast<double*>(red + 1);
+    real* lw = reinterpret_cast<real*>(cst + (size_t)T * NG);
+    int32_t* st = reinterpret_cast<int32_t*>(lw + cap);
+    int32_t* tmp = st + NC * cap;
+    int32_t* anc = tmp + cap;
+
+    const double* th = a.theta + (size_t)g * a.D;
+    MConst<real> mc;
+    model_setup<real, MODEL>(a, th, mc);
+    const int32_t* y = a.y + run.y_off;
+    for (int e = tid; e < T * NG; e += nthr) cst[e] = obs_const(OBS, y[e], mc.r);
+    for (int j = tid; j < nx; j += nthr) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) st[c * cap + j] = mc.x0[c];
+        lw[j] = (real)0;
+    }
+    __syncthreads();
+
+    double ll = 0.0;
+    double s_prev = (double)nx;
+    for (int t = 1; t <= T; ++t) {
+        const uint32_t kt = (kit << 16) | (uint32_t)t;
+        const int32_t* yt = y + (size_t)(t - 1) * NG;
+        const double* ct = cst + (size_t)(t - 1) * NG;
+        // 1. propagate and weight: lw[j] <- a_j = lw_j + log g(y_t | x_t^j)
+        real amax = (real)-INFINITY;
+        for (int j = tid; j < nx; j += nthr) {
+            const double lg = particle_day<real, MODEL, OBS>(
+                mc, st, cap, j, DrawStream{(uint32_t)j, filt, kt, 0u, run.k0, run.k1}, yt, ct);
+            const real av = lw[j] + (real)lg;
+            lw[j] = av;
+            amax = av > amax ? av : amax;
+        }
+        const real m = block_max<real>(amax, red);
+        if (m == (real)-INFINITY) {
+            ll = -INFINITY;
+            break;
+        }
+        // 2. normalise by the maximum; FP64 sum and quantised weights
+        double sl = 0.0;
+        uint64_t q1 = 0, q2 = 0;
+        for (int j = tid; j < nx; j += nthr) {
+            const real av = lw[j];
+            const double w = exp((double)av - (double)m);
+            sl += w;
+            const uint64_t q = (uint64_t)floor(w * 4294967296.0);
+            C[j] = q;
+            const uint64_t h = q >> 8;
+            q1 += h;
+            q2 += h * h;
+            lw[j] = av - m;
+        }
+        block_sum3(sl, q1, q2, red);
+        ll = ll + (((double)m + log(sl)) - log(s_prev));
+        s_prev = sl;
+        // 3. resample when ESS < N_x / 2 (never after the last observation)
+        if (t < T && (a.pf_always || ess_below_half(q1, q2, nx))) {
+            const uint64_t Q = block_scan_lds(C, nx, red);
+            const W4 wd = philox10(0u, filt, kt, S_PF_RS << 24, run.k0, run.k1);
+            block_ancestors(C, nx, Q, (uint64_t)wd.x | ((uint64_t)wd.y << 32), anc);
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                int32_t* sc = st + c * cap;
+                for (int j = tid; j < nx; j += nthr) tmp[j] = sc[anc[j]];
+                __syncthreads();
+                for (int j = tid; j < nx; j += nthr) sc[j] = tmp[j];
+            }
+            for (int j = tid; j < nx; j += nthr) lw[j] = (real)0;
+            s_prev = (double)nx;
+        }
+    }
+    if (tid == 0) a.ll[g] = ll;
+}
+
+// ---------------------------------------------------------------- host side
+
+size_t pf_lds_bytes(int model, int prec, int block, int nx, int T)
+{
+    const int nc = model == MODEL_SIR ? 2 : (model == MODEL_SEIR ? 3 : 12);
+    const int ng = model == MODEL_AGE ? 4 : 1;
+    const size_t cap = (size_t)((nx + block - 1) / block) * block;
+    const size_t rb = prec == 0 ? 4 : 8;
+    return cap * 8 + sizeof(RedLds) + (size_t)T * ng * 8 + cap * rb + (size_t)(nc + 2) * cap * 4;
+}
+
+template <typename real, int MODEL, int OBS>
+static hipError_t launch_one(int block, size_t lds, const PFArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_pf<real, MODEL, OBS>), dim3((unsigned)a.n_items), dim3((unsigned)block), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename real, int MODEL, int OBS> static const void* kernel_ptr()
+{
+    return reinterpret_cast<const void*>(&k_pf<real, MODEL, OBS>);
+}
+
+template <typename real>
+static hipError_t launch_model(int model, int obs, int block, size_t lds, const PFArgs& a, hipStream_t s)
+{
+    if (model == MODEL_SIR && obs == OBS_POIS_PREV) return launch_one<real, MODEL_SIR, OBS_POIS_PREV>(block, lds, a, s);
+    if (model == MODEL_SIR && obs == OBS_POIS_INC) return launch_one<real, MODEL_SIR, OBS_POIS_INC>(block, lds, a, s);
+    if (model == MODEL_SEIR && obs == OBS_NB_INC) return launch_one<real, MODEL_SEIR, OBS_NB_INC>(block, lds, a, s);
+    if (model == MODEL_AGE && obs == OBS_NB_INC) return launch_one<real, MODEL_AGE, OBS_NB_INC>(block, lds, a, s);
+    return hipErrorInvalidValue;
+}
+
+template <typename real> static const void* kernel_of(int model, int obs)
+{
+    if (model == MODEL_SIR && obs == OBS_POIS_PREV) return kernel_ptr<real, MODEL_SIR, OBS_POIS_PREV>();
+    if (model == MODEL_SIR && obs == OBS_POIS_INC) return kernel_ptr<real, MODEL_SIR, OBS_POIS_INC>();
+    if (model == MODEL_SEIR && obs == OBS_NB_INC) return kernel_ptr<real, MODEL_SEIR, OBS_NB_INC>();
+    if (model == MODEL_AGE && obs == OBS_NB_INC) return kernel_ptr<real, MODEL_AGE, OBS_NB_INC>();
+    return nullptr;
+}
+
+bool pf_supported(int model, int obs)
+{
+    return (model == MODEL_SIR && (obs == OBS_POIS_PREV || obs == OBS_POIS_INC)) ||
+           (model == MODEL_SEIR && obs == OBS_NB_INC) || (model == MODEL_AGE && obs == OBS_NB_INC);
+}
+
+hipError_t pf_prepare(int prec, int model, int obs, size_t lds)
+{
+    const void* f = prec == 0 ? kernel_of<float>(model, obs) : kernel_of<double>(model, obs);
+    if (!f) return hipErrorInvalidValue;
+    if (lds <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t launch_pf(int prec, int model, int obs, int block, size_t lds, const PFArgs& a, hipStream_t s)
+{
+    if (a.n_items <= 0) return hipSuccess;
+    if (prec == 0) return launch_model<float>(model, obs, block, lds, a, s);
+    return launch_model<double>(model, obs, block, lds, a, s);
+}
+
+}  // namespace smc2

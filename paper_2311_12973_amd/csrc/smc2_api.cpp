@@ -1,0 +1,539 @@
+// smc2_api.cpp — host side of the C ABI declared in include/smc2.h.
+//
+// Owns validation, the carving of the caller's device workspace, the work list of
+// particle filters, the per-iteration launch sequence (optionally replayed as one
+// captured HIP graph) and the host-side recycling of the per-iteration records
+// (Sec. IV-C). Everything per sample and per particle runs in the device kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/smc2.h"
+#include "outer_kernels.h"
+#include "pf_kernel.h"
+
+using namespace smc2;
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+int n_obs_of(int model) { return model == SMC2_AGE_SEIR ? 4 : 1; }
+
+int expected_D(int model, int D)
+{
+    if (model == SMC2_SIR) return 2;
+    if (model == SMC2_SEIR) return (D == 5) ? 5 : 4;
+    if (model == SMC2_AGE_SEIR) return 8;
+    return -1;
+}
+
+// Lower Cholesky factor (row-major); false when not positive definite.
+bool host_cholesky(int n, const double* A, double* L)
+{
+    for (int i = 0; i < n * n; ++i) L[i] = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double s = A[j * n + j];
+        for (int k = 0; k < j; ++k) s -= L[j * n + k] * L[j * n + k];
+        if (!(s > 0.0)) return false;
+        L[j * n + j] = std::sqrt(s);
+        for (int i = j + 1; i < n; ++i) {
+            double v = A[i * n + j];
+            for (int k = 0; k < j; ++k) v -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = v / L[j * n + j];
+        }
+    }
+    return true;
+}
+
+struct Layout {
+    size_t total = 0;
+    size_t off_k, off_status, off_seeds, off_runs, off_y, off_prior, off_lrw, off_phi, off_phin, off_thn, off_lp,
+        off_ll, off_logw, off_lpn, off_lln, off_lwp, off_scr, off_qc, off_anc, off_active, off_rec, off_items;
+    size_t take(size_t bytes)
+    {
+        const size_t o = total;
+        total += (bytes + 255) & ~(size_t)255;
+        return o;
+    }
+};
+
+Layout make_layout(const smc2_config* c, int R, const smc2_run* runs)
+{
+    Layout L;
+    const size_t N = (size_t)c->N, D = (size_t)c->D, RN = (size_t)R * N;
+    size_t ytot = 0;
+    for (int r = 0; r < R; ++r) ytot += (size_t)runs[r].T * n_obs_of(c->model);
+    L.off_k = L.take(sizeof(int32_t));
+    L.off_status = L.take(sizeof(int32_t) * R);
+    L.off_seeds = L.take(sizeof(uint64_t) * R);
+    L.off_runs = L.take(sizeof(RunDev) * R);
+    L.off_y = L.take(sizeof(int32_t) * ytot);
+    L.off_prior = L.take(sizeof(double) * D * 3);
+    L.off_lrw = L.take(sizeof(double) * D * D);
+    L.off_phi = L.take(sizeof(double) * RN * D);
+    L.off_phin = L.take(sizeof(double) * RN * D);
+    L.off_thn = L.take(sizeof(double) * RN * D);
+    L.off_lp = L.take(sizeof(double) * RN);
+    L.off_ll = L.take(sizeof(double) * RN);
+    L.off_logw = L.take(sizeof(double) * RN);
+    L.off_lpn = L.take(sizeof(double) * RN);
+    L.off_lln = L.take(sizeof(double) * RN);
+    L.off_lwp = L.take(sizeof(double) * RN);
+    L.off_scr = L.take(sizeof(double) * RN);
+    L.off_qc = L.take(sizeof(uint64_t) * RN);
+    L.off_anc = L.take(sizeof(int32_t) * RN);
+    L.off_active = L.take(RN);
+    L.off_rec = L.take(sizeof(double) * R * (size_t)c->K * SMC2_RECORD_LEN(c->D));
+    L.off_items = L.take(sizeof(int32_t) * RN);
+    return L;
+}
+
+// One launch of the particle-filter kernel over a group of filters sharing a block size.
+struct PFGroup {
+    int block;
+    size_t lds;
+    int first_item, n_items;
+};
+
+}  // namespace
+
+void smc2_set_thread_error(const std::string& m) { g_thread_error = m; }
+
+struct smc2_ctx {
+    smc2_config cfg{};
+    std::vector<double> prior, rw_cov, fixed;
+    std::vector<smc2_run> runs;
+    std::vector<std::vector<int32_t>> ys;
+    int R = 0;
+    int k_host = 0;
+    bool poisoned = false;
+    std::string err;
+    hipStream_t stream = nullptr;
+    unsigned char* ws = nullptr;
+    Layout lay;
+    OuterArrays oa{};
+    OuterParams op{};
+    PFArgs pa{};
+    const uint64_t* d_seeds = nullptr;
+    std::vector<PFGroup> groups;
+    bool graph_ready = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<hipEvent_t> ev;  // 4 per iteration: step start, pf start, pf end, step end
+    int timed_from = 0;
+
+    int fail(int code, const std::string& m)
+    {
+        err = m;
+        g_thread_error = m;
+        return code;
+    }
+    int device_fail(hipError_t e, const char* where)
+    {
+        poisoned = true;
+        return fail(SMC2_E_DEVICE, std::string(where) + ": " + hipGetErrorString(e));
+    }
+};
+
+static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::string& m)
+{
+    if (!c || !runs || R < 1) return m = "null config/runs or n_runs < 1", SMC2_E_ARG;
+    if (c->model < SMC2_SIR || c->model > SMC2_AGE_SEIR) return m = "unknown model", SMC2_E_ARG;
+    if (c->obs < SMC2_OBS_POIS_PREV || c->obs > SMC2_OBS_NB_INC) return m = "unknown observation model", SMC2_E_ARG;
+    if (!pf_supported(c->model, c->obs)) return m = "model/observation combination not supported", SMC2_E_UNSUPPORTED;
+    if (c->D < 1 || c->D > SMC2_DMAX || expected_D(c->model, c->D) != c->D)
+        return m = "D does not match the model", SMC2_E_ARG;
+    if (c->N < 2 || c->N > 32768) return m = "N must be in [2, 32768]", SMC2_E_ARG;
+    if (c->K < 1 || c->K > 65535) return m = "K must be in [1, 65535]", SMC2_E_ARG;
+    if (c->precision != SMC2_PREC_FP32 && c->precision != SMC2_PREC_FP64) return m = "bad precision", SMC2_E_ARG;
+    if (c->proposal != SMC2_PROP_RW) return m = "unknown proposal", SMC2_E_UNSUPPORTED;
+    if (c->lkernel != SMC2_L_FORWARD && c->lkernel != SMC2_L_GAUSS_OPT) return m = "unknown L-kernel", SMC2_E_ARG;
+    if (!(c->n_pop >= 1.0 && c->n_pop <= 16777216.0 && c->n_pop == std::floor(c->n_pop)))
+        return m = "n_pop must be an integer in [1, 2^24]", SMC2_E_ARG;
+    if (c->block != 0 && (c->block < 64 || c->block > 256 || c->block % 64 != 0))
+        return m = "block must be 0 or a multiple of 64 up to 256", SMC2_E_ARG;
+    if (!c->prior || !c->rw_cov) return m = "prior and rw_cov are required", SMC2_E_ARG;
+    if (c->n_fixed < 0 || c->n_fixed > SMC2_NFIXED || (c->n_fixed > 0 && !c->fixed))
+        return m = "bad fixed constants", SMC2_E_ARG;
+    for (int d = 0; d < c->D; ++d) {
+        const int fam = (int)c->prior[3 * d];
+        if (fam < SMC2_PRIOR_UNIFORM || fam > SMC2_PRIOR_NORMAL || (double)fam != c->prior[3 * d])
+            return m = "bad prior family", SMC2_E_ARG;
+        if (fam == SMC2_PRIOR_UNIFORM && !(c->prior[3 * d + 2] > c->prior[3 * d + 1]))
+            return m = "uniform prior needs a < b", SMC2_E_ARG;
+        if (fam != SMC2_PRIOR_UNIFORM && !(c->prior[3 * d + 2] > 0.0))
+            return m = "Gaussian prior needs b > 0", SMC2_E_ARG;
+    }
+    double L[SMC2_DMAX * SMC2_DMAX];
+    if (!host_cholesky(c->D, c->rw_cov, L)) return m = "rw_cov is not positive definite", SMC2_E_ARG;
+    const int need_fixed = c->model == SMC2_SIR ? 1 : (c->model == SMC2_SEIR ? (c->D == 4 ? 1 : 0) : 20);
+    if (c->n_fixed < need_fixed) return m = "missing model constants in fixed", SMC2_E_ARG;
+    if (c->model == SMC2_SIR && !(c->fixed[0] >= 0 && c->fixed[0] <= c->n_pop))
+        return m = "I_0 out of range", SMC2_E_ARG;
+    if (c->model == SMC2_SEIR && c->D == 4 && !(c->fixed[0] > 0)) return m = "dispersion r must be > 0", SMC2_E_ARG;
+    const int nxmax = c->model == SMC2_AGE_SEIR ? 2048 : 4096;
+    for (int r = 0; r < R; ++r) {
+        if (runs[r].T < 1 || runs[r].T > 1024) return m = "T must be in [1, 1024]", SMC2_E_ARG;
+        if (runs[r].n_x < 1 || runs[r].n_x > nxmax) return m = "n_x out of range", SMC2_E_ARG;
+        if (!runs[r].y) return m = "null observations", SMC2_E_ARG;
+        const int no = n_obs_of(c->model);
+        for (int e = 0; e < runs[r].T * no; ++e)
+            if (runs[r].y[e] < 0) return m = "negative observation", SMC2_E_ARG;
+    }
+    return SMC2_OK;
+}
+
+static int default_block(int nx)
+{
+    const int b = ((nx + 63) / 64) * 64;
+    return b < 256 ? b : 256;
+}
+
+extern "C" size_t smc2_workspace_bytes(const smc2_config* cfg, int32_t n_runs, const smc2_run* runs)
+{
+    std::string m;
+    if (validate(cfg, n_runs, runs, m) != SMC2_OK) {
+        g_thread_error = m;
+        return 0;
+    }
+    return make_layout(cfg, n_runs, runs).total;
+}
+
+extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run* runs, void* d_workspace,
+                         size_t ws_bytes, void* hip_stream, smc2_ctx** out)
+{
+    if (!out) return g_thread_error = "out is NULL", SMC2_E_ARG;
+    *out = nullptr;
+    std::string m;
+    const int v = validate(cfg, n_runs, runs, m);
+    if (v != SMC2_OK) return g_thread_error = m, v;
+    const Layout lay = make_layout(cfg, n_runs, runs);
+    if (!d_workspace || ws_bytes < lay.total || ((uintptr_t)d_workspace & 255u) != 0)
+        return g_thread_error = "workspace missing, too small or not 256-byte aligned", SMC2_E_ARG;
+
+    smc2_ctx* c = new smc2_ctx();
+    c->cfg = *cfg;
+    c->R = n_runs;
+    c->prior.assign(cfg->prior, cfg->prior + 3 * cfg->D);
+    c->rw_cov.assign(cfg->rw_cov, cfg->rw_cov + cfg->D * cfg->D);
+    c->fixed.assign(SMC2_NFIXED, 0.0);
+    for (int i = 0; i < cfg->n_fixed; ++i) c->fixed[i] = cfg->fixed[i];
+    c->cfg.prior = c->prior.data();
+    c->cfg.rw_cov = c->rw_cov.data();
+    c->cfg.fixed = c->fixed.data();
+    c->stream = (hipStream_t)hip_stream;
+    c->ws = (unsigned char*)d_workspace;
+    c->lay = lay;
+    const int no = n_obs_of(cfg->model);
+    c->runs.assign(runs, runs + n_runs);
+    std::vector<int32_t> yall;
+    std::vector<RunDev> rd(n_runs);
+    std::vector<uint64_t> seeds(n_runs);
+    for (int r = 0; r < n_runs; ++r) {
+        c->ys.emplace_back(runs[r].y, runs[r].y + (size_t)runs[r].T * no);
+        c->runs[r].y = c->ys.back().data();
+        rd[r].T = runs[r].T;
+        rd[r].nx = runs[r].n_x;
+        rd[r].y_off = (int32_t)yall.size();
+        rd[r].pad = 0;
+        rd[r].k0 = (uint32_t)runs[r].seed;
+        rd[r].k1 = (uint32_t)(runs[r].seed >> 32);
+        seeds[r] = runs[r].seed;
+        yall.insert(yall.end(), c->ys.back().begin(), c->ys.back().end());
+    }
+    std::vector<double> lrw(cfg->D * cfg->D);
+    host_cholesky(cfg->D, cfg->rw_cov, lrw.data());
+
+    // work list: filters grouped by workgroup size, longest filters first in each group
+    const size_t N = (size_t)cfg->N;
+    std::vector<int32_t> items;
+    std::vector<int> blk(n_runs);
+    for (int r = 0; r < n_runs; ++r) blk[r] = cfg->block ? cfg->block : default_block(runs[r].n_x);
+    std::vector<int> run_order(n_runs);
+    for (int r = 0; r < n_runs; ++r) run_order[r] = r;
+    std::stable_sort(run_order.begin(), run_order.end(), [&](int a, int b) {
+        if (blk[a] != blk[b]) return blk[a] > blk[b];
+        return (int64_t)runs[a].T * runs[a].n_x > (int64_t)runs[b].T * runs[b].n_x;
+    });
+    for (size_t idx = 0; idx < run_order.size();) {
+        const int b = blk[run_order[idx]];
+        PFGroup gr{b, 0, (int)items.size(), 0};
+        for (; idx < run_order.size() && blk[run_order[idx]] == b; ++idx) {
+            const int r = run_order[idx];
+            for (size_t i = 0; i < N; ++i) items.push_back((int32_t)(r * N + i));
+            gr.lds = std::max(gr.lds, pf_lds_bytes(cfg->model, cfg->precision, b, runs[r].n_x, runs[r].T));
+        }
+        gr.n_items = (int)items.size() - gr.first_item;
+        c->groups.push_back(gr);
+    }
+    for (const PFGroup& gr : c->groups) {
+        if (gr.lds > 160 * 1024) {
+            delete c;
+            return g_thread_error = "particle filter does not fit in LDS (n_x or T too large)", SMC2_E_ARG;
+        }
+        const hipError_t e = pf_prepare(cfg->precision, cfg->model, cfg->obs, gr.lds);
+        if (e != hipSuccess) {
+            const int rc = c->device_fail(e, "pf_prepare");
+            g_thread_error = c->err;
+            delete c;
+            return rc;
+        }
+    }
+
+    unsigned char* w = c->ws;
+    OuterArrays& o = c->oa;
+    o.phi = (double*)(w + lay.off_phi);
+    o.lp = (double*)(w + lay.off_lp);
+    o.ll = (double*)(w + lay.off_ll);
+    o.logw = (double*)(w + lay.off_logw);
+    o.phi_new = (double*)(w + lay.off_phin);
+    o.lp_new = (double*)(w + lay.off_lpn);
+    o.ll_new = (double*)(w + lay.off_lln);
+    o.theta_new = (double*)(w + lay.off_thn);
+    o.logw_pre = (double*)(w + lay.off_lwp);
+    o.scratch = (double*)(w + lay.off_scr);
+    o.qc = (uint64_t*)(w + lay.off_qc);
+    o.anc = (int32_t*)(w + lay.off_anc);
+    o.active = (uint8_t*)(w + lay.off_active);
+    o.records = (double*)(w + lay.off_rec);
+    o.status = (int32_t*)(w + lay.off_status);
+    o.k_dev = (int32_t*)(w + lay.off_k);
+    OuterParams& p = c->op;
+    p.N = cfg->N;
+    p.D = cfg->D;
+    p.K = cfg->K;
+    p.R = n_runs;
+    p.lkernel = cfg->lkernel;
+    p.rec_len = SMC2_RECORD_LEN(cfg->D);
+    p.prior = (const double*)(w + lay.off_prior);
+    p.lrw = (const double*)(w + lay.off_lrw);
+    c->d_seeds = (const uint64_t*)(w + lay.off_seeds);
+    PFArgs& a = c->pa;
+    a.theta = o.theta_new;
+    a.active = o.active;
+    a.ll = o.ll_new;
+    a.y = (const int32_t*)(w + lay.off_y);
+    a.runs = (const RunDev*)(w + lay.off_runs);
+    a.items = (const int32_t*)(w + lay.off_items);
+    a.k_dev = o.k_dev;
+    a.k_const = 0;
+    a.N = cfg->N;
+    a.D = cfg->D;
+    a.pf_always = cfg->pf_always;
+    a.n_pop = cfg->n_pop;
+    for (int i = 0; i < SMC2_NFIXED; ++i) a.fx[i] = c->fixed[i];
+
+    hipStream_t s = c->stream;
+    hipError_t e = hipSuccess;
+    auto H2D = [&](size_t off, const void* src, size_t bytes) {
+        if (e == hipSuccess && bytes) e = hipMemcpyAsync(w + off, src, bytes, hipMemcpyHostToDevice, s);
+    };
+    H2D(lay.off_seeds, seeds.data(), sizeof(uint64_t) * n_runs);
+    H2D(lay.off_runs, rd.data(), sizeof(RunDev) * n_runs);
+    H2D(lay.off_y, yall.data(), sizeof(int32_t) * yall.size());
+    H2D(lay.off_prior, c->prior.data(), sizeof(double) * c->prior.size());
+    H2D(lay.off_lrw, lrw.data(), sizeof(double) * lrw.size());
+    H2D(lay.off_items, items.data(), sizeof(int32_t) * items.size());
+    if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_k, 0, sizeof(int32_t), s);
+    if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_status, 0, sizeof(int32_t) * n_runs, s);
+    if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_logw, 0, sizeof(double) * n_runs * N, s);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(w + lay.off_rec, 0, sizeof(double) * n_runs * cfg->K * SMC2_RECORD_LEN(cfg->D), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
+        c->ev.resize(4 * (size_t)cfg->K, nullptr);
+        for (auto& ev : c->ev)
+            if (e == hipSuccess) e = hipEventCreate(&ev);
+    }
+    if (e != hipSuccess) {
+        const int rc = c->device_fail(e, "smc2_init");
+        g_thread_error = c->err;
+        smc2_destroy(c);
+        return rc;
+    }
+    *out = c;
+    return SMC2_OK;
+}
+
+static hipError_t enqueue_iteration(smc2_ctx* c, hipEvent_t pf0, hipEvent_t pf1)
+{
+    hipStream_t s = c->stream;
+    hipError_t e = launch_begin_iteration(c->oa, s);
+    if (e == hipSuccess) e = launch_propose(c->oa, c->op, c->d_seeds, s);
+    if (e == hipSuccess && pf0) e = hipEventRecord(pf0, s);
+    for (const PFGroup& gr : c->groups) {
+        if (e != hipSuccess) break;
+        PFArgs a = c->pa;
+        a.items = c->pa.items + gr.first_item;
+        a.n_items = gr.n_items;
+        e = launch_pf(c->cfg.precision, c->cfg.model, c->cfg.obs, gr.block, gr.lds, a, s);
+    }
+    if (e == hipSuccess && pf1) e = hipEventRecord(pf1, s);
+    if (e == hipSuccess) e = launch_outer_update(c->oa, c->op, c->d_seeds, s);
+    return e;
+}
+
+extern "C" int smc2_step(smc2_ctx* c)
+{
+    if (!c) return g_thread_error = "ctx is NULL", SMC2_E_ARG;
+    if (c->poisoned) return c->fail(SMC2_E_DEVICE, "context poisoned by an earlier device error");
+    if (c->k_host >= c->cfg.K) return c->fail(SMC2_E_STATE, "all K iterations have run");
+    const int k = c->k_host + 1;
+    hipEvent_t* ev = &c->ev[4 * (size_t)(k - 1)];
+    hipError_t e = hipEventRecord(ev[0], c->stream);
+    if (e == hipSuccess) {
+        if (c->cfg.use_graph) {
+            if (!c->graph_ready) {
+                e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    const hipError_t e1 = enqueue_iteration(c, nullptr, nullptr);
+                    e = hipStreamEndCapture(c->stream, &c->graph);
+                    if (e1 != hipSuccess) e = e1;
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
+                if (e == hipSuccess) c->graph_ready = true;
+            }
+            if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
+            if (e == hipSuccess) e = hipGraphLaunch(c->graph_exec, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
+        } else {
+            e = enqueue_iteration(c, ev[1], ev[2]);
+        }
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
+    if (e != hipSuccess) return c->device_fail(e, "smc2_step");
+    c->k_host = k;
+    return SMC2_OK;
+}
+
+static int sync_and_status(smc2_ctx* c, int32_t run)
+{
+    if (c->poisoned) return c->fail(SMC2_E_DEVICE, "context poisoned by an earlier device error");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->device_fail(e, "synchronize");
+    int32_t st = 0;
+    e = hipMemcpy(&st, c->oa.status + run, sizeof(int32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return c->device_fail(e, "status readback");
+    return st == 0 ? SMC2_OK : c->fail(SMC2_E_NUMERIC, "every weight of the run vanished");
+}
+
+extern "C" int smc2_records(smc2_ctx* c, int32_t run, double* host_dst, size_t n_doubles, int32_t* k_done)
+{
+    if (!c) return g_thread_error = "ctx is NULL", SMC2_E_ARG;
+    if (run < 0 || run >= c->R || !host_dst) return c->fail(SMC2_E_ARG, "bad run or destination");
+    const size_t RL = SMC2_RECORD_LEN(c->cfg.D);
+    if (n_doubles < (size_t)c->k_host * RL) return c->fail(SMC2_E_ARG, "destination too small");
+    const int st = sync_and_status(c, run);
+    if (st == SMC2_E_DEVICE) return st;
+    const hipError_t e = hipMemcpy(host_dst, c->oa.records + (size_t)run * c->cfg.K * RL,
+                                   sizeof(double) * RL * c->k_host, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return c->device_fail(e, "records readback");
+    if (k_done) *k_done = c->k_host;
+    return st;
+}
+
+extern "C" int smc2_estimate(smc2_ctx* c, int32_t run, int32_t recycled, double* mean, double* cov)
+{
+    if (!c) return g_thread_error = "ctx is NULL", SMC2_E_ARG;
+    if (!mean) return c->fail(SMC2_E_ARG, "mean is NULL");
+    if (c->k_host < 1) return c->fail(SMC2_E_STATE, "no iteration has run");
+    const int D = c->cfg.D;
+    const size_t RL = SMC2_RECORD_LEN(D);
+    std::vector<double> rec(RL * c->k_host);
+    int32_t kd = 0;
+    const int st = smc2_records(c, run, rec.data(), rec.size(), &kd);
+    if (st != SMC2_OK) return st;
+    // c_k = l_k / sum_j l_j over the completed iterations (Sec. IV-C); mean = sum c_k f_k,
+    // covariance = sum c_k (C_k + f_k f_k^T) - mean mean^T.
+    const int k0 = recycled ? 0 : kd - 1;
+    double lsum = 0.0;
+    for (int k = k0; k < kd; ++k) lsum += rec[k * RL + 1];
+    std::vector<double> m(D, 0.0), C(D * D, 0.0);
+    for (int k = k0; k < kd; ++k) {
+        const double ck = rec[k * RL + 1] / lsum;
+        const double* fk = &rec[k * RL + 6];
+        const double* Ck = &rec[k * RL + 6 + D];
+        for (int a = 0; a < D; ++a) m[a] += ck * fk[a];
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) C[a * D + b] += ck * (Ck[a * D + b] + fk[a] * fk[b]);
+    }
+    for (int a = 0; a < D; ++a) mean[a] = m[a];
+    if (cov)
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) cov[a * D + b] = C[a * D + b] - m[a] * m[b];
+    return SMC2_OK;
+}
+
+extern "C" int smc2_dump(smc2_ctx* c, int32_t what, int32_t run, void* host_dst, size_t bytes)
+{
+    if (!c) return g_thread_error = "ctx is NULL", SMC2_E_ARG;
+    if (run < 0 || run >= c->R || !host_dst) return c->fail(SMC2_E_ARG, "bad run or destination");
+    const size_t N = (size_t)c->cfg.N, D = (size_t)c->cfg.D, base = (size_t)run * N;
+    const void* src = nullptr;
+    size_t need = 0;
+    switch (what) {
+    case SMC2_DUMP_PHI: src = c->oa.phi + base * D; need = N * D * 8; break;
+    case SMC2_DUMP_LP: src = c->oa.lp + base; need = N * 8; break;
+    case SMC2_DUMP_LL: src = c->oa.ll + base; need = N * 8; break;
+    case SMC2_DUMP_LOGW: src = c->oa.logw + base; need = N * 8; break;
+    case SMC2_DUMP_PHI_NEW: src = c->oa.phi_new + base * D; need = N * D * 8; break;
+    case SMC2_DUMP_LP_NEW: src = c->oa.lp_new + base; need = N * 8; break;
+    case SMC2_DUMP_LL_NEW: src = c->oa.ll_new + base; need = N * 8; break;
+    case SMC2_DUMP_LOGW_PRE: src = c->oa.logw_pre + base; need = N * 8; break;
+    case SMC2_DUMP_ANC: src = c->oa.anc + base; need = N * 4; break;
+    default: return c->fail(SMC2_E_ARG, "unknown dump");
+    }
+    if (bytes < need) return c->fail(SMC2_E_ARG, "destination too small");
+    if (c->poisoned) return c->fail(SMC2_E_DEVICE, "context poisoned by an earlier device error");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(host_dst, src, need, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return c->device_fail(e, "dump");
+    return SMC2_OK;
+}
+
+extern "C" int smc2_timing(smc2_ctx* c, double* ms_pf, double* ms_step, int32_t* n_steps)
+{
+    if (!c) return g_thread_error = "ctx is NULL", SMC2_E_ARG;
+    if (c->poisoned) return c->fail(SMC2_E_DEVICE, "context poisoned by an earlier device error");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return c->device_fail(e, "synchronize");
+    double pf = 0.0, st = 0.0;
+    const int n = c->k_host - c->timed_from;
+    for (int k = c->timed_from; k < c->k_host; ++k) {
+        float a = 0.f, b = 0.f;
+        e = hipEventElapsedTime(&a, c->ev[4 * k + 1], c->ev[4 * k + 2]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, c->ev[4 * k + 0], c->ev[4 * k + 3]);
+        if (e != hipSuccess) return c->device_fail(e, "event timing");
+        pf += a;
+        st += b;
+    }
+    c->timed_from = c->k_host;
+    if (ms_pf) *ms_pf = n > 0 ? pf / n : 0.0;
+    if (ms_step) *ms_step = n > 0 ? st / n : 0.0;
+    if (n_steps) *n_steps = n;
+    return SMC2_OK;
+}
+
+extern "C" int smc2_destroy(smc2_ctx* c)
+{
+    if (!c) return SMC2_OK;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    for (hipEvent_t e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete c;
+    return SMC2_OK;
+}
+
+extern "C" const char* smc2_last_error(const smc2_ctx* c)
+{
+    if (c) return c->err.c_str();
+    return g_thread_error.c_str();
+}

@@ -1,0 +1,85 @@
+"""The C ABI without a GPU: the library loads, exports every function the headers
+declare, and rejects bad arguments before touching the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2311_12973_amd as G
+from paper_2311_12973_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in ("smc2.h", "smc2_kernels.h"):
+        src = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*(smc2_[a-z_0-9]+)\s*\(", src, re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    names = _declared()
+    assert {"smc2_init", "smc2_step", "smc2_estimate", "smc2_dump", "smc2_destroy", "smc2_workspace_bytes",
+            "smc2_pf_loglik", "smc2_resample_batch", "smc2_binomial_batch", "smc2_philox_batch"} <= names
+    L = G.lib()
+    for n in sorted(names):
+        assert hasattr(L, n), n
+
+
+def _w():
+    return W.preset("seir")
+
+
+def test_workspace_bytes_and_validation():
+    L = G.lib()
+    w = _w()
+    y = W.observations(w)
+    runs = G.make_runs([dict(T=100, nx=512, seed=1, y=y)])
+    cfg = G.make_config(w)
+    nb = L.smc2_workspace_bytes(ctypes.byref(cfg), 1, runs)
+    assert 3 * 1024 * 4 * 8 < nb < 1 << 20  # O(N D) doubles: particles never leave the chip
+    bad = [dict(N=1), dict(N=40000), dict(K=0), dict(precision=3), dict(block=96), dict(block=512)]
+    for over in bad:
+        c = G.make_config(w, **over)
+        assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == 0, over
+    c = G.make_config(dict(w, D=3, prior=w["prior"][:3], rw_cov=np.eye(3).tolist()))
+    assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == 0
+    c = G.make_config(dict(w, rw_cov=(-np.eye(4)).tolist()))
+    assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == 0
+    assert b"positive definite" in L.smc2_last_error(None)
+    for r in [dict(T=100, nx=0, seed=1, y=y), dict(T=0, nx=512, seed=1, y=y[:0]), dict(T=100, nx=5000, seed=1, y=y)]:
+        assert L.smc2_workspace_bytes(ctypes.byref(cfg), 1, G.make_runs([r])) == 0, r
+    yneg = y.copy()
+    yneg[3] = -1
+    assert L.smc2_workspace_bytes(ctypes.byref(cfg), 1, G.make_runs([dict(T=100, nx=512, seed=1, y=yneg)])) == 0
+
+
+def test_init_rejects_before_device_use():
+    L = G.lib()
+    w = _w()
+    y = W.observations(w)
+    runs = G.make_runs([dict(T=100, nx=512, seed=1, y=y)])
+    cfg = G.make_config(w)
+    h = ctypes.c_void_p()
+    # no workspace / too small / misaligned
+    assert L.smc2_init(ctypes.byref(cfg), 1, runs, None, 0, None, ctypes.byref(h)) == G.E_ARG
+    assert L.smc2_init(ctypes.byref(cfg), 1, runs, ctypes.c_void_p(4096), 16, None, ctypes.byref(h)) == G.E_ARG
+    assert L.smc2_init(ctypes.byref(cfg), 1, runs, ctypes.c_void_p(4097), 1 << 30, None, ctypes.byref(h)) == G.E_ARG
+    assert h.value is None
+    c = G.make_config(dict(w, obs=W.OBS_POIS_PREV))
+    assert L.smc2_init(ctypes.byref(c), 1, runs, ctypes.c_void_p(4096), 1 << 30, None,
+                       ctypes.byref(h)) == G.E_UNSUPPORTED
+    assert L.smc2_step(None) == G.E_ARG
+    assert L.smc2_destroy(None) == G.OK
+
+
+def test_kernel_entry_points_reject_bad_arguments():
+    L = G.lib()
+    assert L.smc2_resample_batch(1, 0, None, None, None, None, None) == G.E_ARG
+    assert L.smc2_resample_batch(1, 5000, None, None, None, None, None) == G.E_ARG
+    assert L.smc2_binomial_batch(7, 1, None, None, 0, 0, 1, 1, 0, None, None) == G.E_ARG
+    assert L.smc2_philox_batch(-1, None, 0, None, None) == G.E_ARG

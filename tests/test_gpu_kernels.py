@@ -1,0 +1,143 @@
+"""GPU parity of the building blocks against the CPU reference (through the C ABI).
+
+* Philox words: bit-exact.
+* Binomial draws (FP32 and FP64 sampler, inversion and BTRS regimes): identical
+  integers at the same (n, p, counter coordinates).
+* Integer systematic resampling: identical ancestors and ESS decisions for the same
+  quantised weights and 64-bit uniform, including ragged sizes.
+* Particle-filter log-likelihoods: FP64 within 1e-12 relative, FP32 within the 1e-4
+  relative tolerance of the FP32 path (identical integer decisions give ~1e-12), for
+  several workgroup sizes (results must not depend on the tiling).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2311_12973_amd as G
+from paper_2311_12973_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def test_philox_bit_exact():
+    rng = np.random.default_rng(5)
+    ctr = rng.integers(0, 2**32, size=(4096, 4), dtype=np.uint64).astype(np.uint32)
+    ctr[0] = 0
+    for seed in [0, 1, 0xDEADBEEFCAFEBABE]:
+        got = G.philox_batch(ctr, seed)
+        key = [seed & 0xFFFFFFFF, seed >> 32]
+        for e in range(0, 4096, 7):
+            assert np.array_equal(got[e], O.philox(ctr[e], key)), (seed, e)
+
+
+CELLS = [(0, 0.3), (1, 0.3), (17, 0.0), (17, 1.0), (5, 0.5), (30, 0.2), (30, 0.9), (100, 0.099), (100, 0.101),
+         (1000, 1e-3), (1000, 0.5), (1000, 0.97), (40000, 0.0003), (40000, 0.2), (10**6, 1e-6), (10**6, 2e-5),
+         (10**6, 0.003), (10**6, 0.22), (10**6, 0.5), (250000, 0.6), (16777216, 0.01)]
+
+
+@pytest.mark.parametrize("prec", [G.PREC_FP64, G.PREC_FP32])
+def test_binomial_bit_exact(prec):
+    count = 4096
+    total = 0
+    for (n, p) in CELLS:
+        _log("binomial prec=%d n=%d p=%g" % (prec, n, p))
+        p_eff = float(np.float32(p)) if prec == G.PREC_FP32 else p
+        got = G.binomial_batch(prec, np.full(count, n), np.full(count, p_eff), seed=77, i=5, k=3, t=11, b=2)
+        want = O.binomial_batch(prec, n, p_eff, 77, count, i=5, k=3, t=11, b=2)
+        mism = np.flatnonzero(got != want)
+        assert len(mism) == 0, (n, p, mism[:10], got[mism[:10]], want[mism[:10]])
+        total += count
+    # heterogeneous lanes in one launch (divergent regimes inside a wave)
+    rng = np.random.default_rng(9)
+    n = rng.integers(0, 200000, size=8192)
+    p = rng.random(8192) ** 3
+    if prec == G.PREC_FP32:
+        p = p.astype(np.float32).astype(np.float64)
+    got = G.binomial_batch(prec, n, p, seed=3, i=1, k=1, t=1, b=0)
+    want = np.array([O.binomial(prec, n[j], p[j], 3, j, 1, 1, 1, 0) for j in range(len(n))])
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 500, 1000, 2048, 4096])
+def test_resample_bit_exact(n):
+    rng = np.random.default_rng(n)
+    S = 24
+    q = np.zeros((S, n), dtype=np.uint64)
+    for s in range(S):
+        kind = s % 4
+        if kind == 0:
+            w = rng.random(n)
+        elif kind == 1:
+            w = np.exp(rng.normal(0, 5, n))
+        elif kind == 2:
+            w = np.where(rng.random(n) < 0.05, rng.random(n), 0.0)
+            w[rng.integers(n)] = 1.0
+        else:
+            w = np.ones(n)
+        q[s] = np.floor(w / w.max() * 2.0**32).astype(np.uint64)
+    x64 = rng.integers(0, 2**63, size=S, dtype=np.uint64) * np.uint64(2)
+    x64[0] = 0
+    x64[1] = np.uint64(2**64 - 1)
+    anc, trig = G.resample_batch(q, x64)
+    for s in range(S):
+        assert np.array_equal(anc[s], O.resample_ancestors(q[s], int(x64[s]))), s
+        assert bool(trig[s]) == O.resample_trigger(q[s]), s
+
+
+def _pf_case(name, prec, nx, n_theta, T=None, pf_always=0, seed=11, k=2):
+    w = W.preset(name)
+    if T is not None:
+        w["T"] = T
+    y = W.observations(w)
+    rng = np.random.default_rng(seed)
+    truth = np.array(w["truth"])
+    theta = truth * np.exp(rng.normal(0, 0.15, size=(n_theta, w["D"])))
+    if w["model"] == W.SEIR:
+        theta[:, 3] = np.clip(theta[:, 3], 1e-7, 1e-3)
+    return w, y, theta
+
+
+@pytest.mark.parametrize("name,prec,nx,T", [("sir_fp64", G.PREC_FP64, 64, None), ("sir_fp64", G.PREC_FP32, 100, None),
+                                            ("paper_sir", G.PREC_FP64, 500, None), ("seir", G.PREC_FP32, 512, 60),
+                                            ("seir", G.PREC_FP64, 300, 40)])
+@pytest.mark.parametrize("block", [0, 64, 128])
+def test_pf_loglik_matches_oracle(name, prec, nx, T, block):
+    _log("pf %s prec=%d nx=%d block=%d" % (name, prec, nx, block))
+    w, y, theta = _pf_case(name, prec, nx, 24, T)
+    got = G.pf_loglik(w, theta, y, nx, seed=9, k=2, precision=prec, block=block)
+    cfg = O.config_from_workload(w, prec=prec)
+    want = np.array([O.pf_loglik(cfg, theta[i], y, nx, 9, i, 2) for i in range(len(theta))])
+    fin = np.isfinite(want)
+    assert np.array_equal(np.isfinite(got), fin)
+    rel = np.abs(got[fin] - want[fin]) / np.abs(want[fin])
+    _log("  max rel err %.3g" % rel.max())
+    assert rel.max() <= (1e-12 if prec == G.PREC_FP64 else 1e-4)
+    # identical integer decisions leave only FP64 summation-order noise
+    assert np.mean(rel < 1e-11) >= 0.95
+
+
+def test_pf_resample_every_step_and_ragged():
+    w = W.preset("sir_fp64")
+    y = W.observations(w)
+    theta = np.array([w["truth"]] * 10) * np.linspace(0.8, 1.2, 10)[:, None]
+    for nx in [1, 7, 65, 129]:
+        got = G.pf_loglik(w, theta, y, nx, seed=4, k=1, pf_always=1)
+        cfg = O.config_from_workload(w)
+        cfg.pf_always = 1
+        want = np.array([O.pf_loglik(cfg, theta[i], y, nx, 4, i, 1) for i in range(10)])
+        fin = np.isfinite(want)
+        assert np.array_equal(np.isfinite(got), fin)
+        assert np.allclose(got[fin], want[fin], rtol=1e-12, atol=0)
+
+
+def test_pf_dead_filter_is_minus_inf():
+    w = W.preset("paper_sir")
+    y = np.zeros((5, 1), dtype=np.int32)
+    y[2, 0] = 3
+    w = dict(w, fixed=[0])  # nobody infected: Poisson(I_t = 0) cannot produce y = 3
+    ll = G.pf_loglik(w, np.array([[0.5, 0.2]] * 3), y, 64, seed=1, k=1)
+    assert np.all(ll == -np.inf)

@@ -1,0 +1,199 @@
+"""GPU parity of the whole SMC^2 iteration (smc2_init / smc2_step / smc2_estimate).
+
+Small shapes run free against the CPU reference with the same seeds: every
+iteration's proposals, particle-filter log-likelihoods, pre-resampling log-weights,
+ancestors and records must match (FP64 path: 1e-10 relative, ancestors identical;
+FP32 path: 1e-4 relative on log-likelihoods and posterior means, ancestors
+identical). At the full benchmark shape the GPU run is checked on sampled filters
+(the reference recomputes their log-likelihoods one by one) and on the outer step
+(the reference recomputes each iteration's weights, records and ancestors from the
+GPU's inputs).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_2311_12973_amd as G
+from paper_2311_12973_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _run_pair(w, N, K, nx, T=None, seed=1, use_graph=0, block=0, lkernel=None):
+    w = dict(w)
+    if T is not None:
+        w["T"] = T
+    if lkernel is not None:
+        w["lkernel"] = lkernel
+    y = W.observations(w)
+    s = G.Sampler(w, [dict(T=y.shape[0], nx=nx, seed=seed, y=y)], N=N, K=K, use_graph=use_graph, block=block)
+    gpu = dict(phi=[], ll=[], lp=[], logw=[], anc=[])
+    for k in range(K):
+        s.step()
+        gpu["phi"].append(s.dump("phi_new"))
+        gpu["ll"].append(s.dump("ll_new"))
+        gpu["lp"].append(s.dump("lp_new"))
+        gpu["logw"].append(s.dump("logw_pre"))
+        gpu["anc"].append(s.dump("anc"))
+    gpu = {k: np.array(v) for k, v in gpu.items()}
+    gpu["rec"] = s.records()
+    gpu["est"] = s.estimate(recycled=True)
+    s.close()
+    cfg = O.config_from_workload(w)
+    ref = O.smc2_run(cfg, y, nx, seed, N, K, dumps=True)
+    return gpu, ref, cfg
+
+
+def _compare(gpu, ref, D, tol_ll, tol_outer):
+    assert ref["status"] == 0
+    K = gpu["ll"].shape[0]
+    for k in range(K):
+        assert np.allclose(gpu["phi"][k], ref["phi"][k], rtol=1e-12, atol=1e-12), k
+        assert np.allclose(gpu["lp"][k], ref["lp"][k], rtol=1e-12, atol=1e-12), k
+        fin = np.isfinite(ref["ll"][k])
+        assert np.array_equal(np.isfinite(gpu["ll"][k]), fin), k
+        rel = np.abs(gpu["ll"][k][fin] - ref["ll"][k][fin]) / np.abs(ref["ll"][k][fin])
+        _log("  k=%d  ll max rel %.3g" % (k + 1, rel.max() if rel.size else 0.0))
+        assert rel.max() <= tol_ll, k
+        fin = np.isfinite(ref["logw"][k])
+        assert np.array_equal(np.isfinite(gpu["logw"][k]), fin), k
+        assert np.allclose(gpu["logw"][k][fin], ref["logw"][k][fin], rtol=tol_outer, atol=tol_outer * 10), k
+        assert np.array_equal(gpu["anc"][k], ref["anc"][k]), k
+    RL = G.record_len(D)
+    assert gpu["rec"].shape == (K, RL)
+    for col in [0, 2, 3, 4]:
+        assert np.array_equal(gpu["rec"][:, col], ref["rec"][:, col]), col
+    assert np.allclose(gpu["rec"][:, 1], ref["rec"][:, 1], rtol=tol_outer)
+    assert np.allclose(gpu["rec"][:, 6:], ref["rec"][:, 6:], rtol=tol_outer, atol=1e-12)
+    m_ref, c_ref, _ = O.recycle(ref["rec"], D)
+    assert np.allclose(gpu["est"][0], m_ref, rtol=tol_outer)
+    assert np.allclose(gpu["est"][1], c_ref, rtol=max(tol_outer, 1e-8), atol=1e-14)
+
+
+def test_sir_fp64_end_to_end():
+    """The FP64 SIR shape (N=64, N_x=64, T=50, K=5): free-running parity."""
+    w = W.preset("sir_fp64")
+    gpu, ref, _ = _run_pair(w, 64, 5, 64)
+    _compare(gpu, ref, 2, 1e-10, 1e-9)
+
+
+@pytest.mark.parametrize("lkernel", [G.L_GAUSS_OPT, G.L_FORWARD])
+def test_paper_sir_end_to_end(lkernel):
+    w = W.preset("paper_sir")
+    gpu, ref, _ = _run_pair(w, 128, 4, 100, lkernel=lkernel)
+    _compare(gpu, ref, 2, 1e-10, 1e-9)
+
+
+def test_seir_fp32_end_to_end():
+    """SEIR, FP32 propagation: N=96, N_x=256, T=60, K=4."""
+    w = W.preset("seir")
+    gpu, ref, _ = _run_pair(w, 96, 4, 256, T=60, block=128)
+    _compare(gpu, ref, 4, 1e-4, 1e-8)
+
+
+def test_graph_replay_matches_direct_launches():
+    w = W.preset("sir_fp64")
+    a, _, _ = _run_pair(w, 64, 5, 64, use_graph=0)
+    b, _, _ = _run_pair(w, 64, 5, 64, use_graph=1)
+    for key in ("phi", "ll", "logw", "anc", "rec"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+def test_determinism_and_tiling_invariance():
+    w = W.preset("seir")
+    a, _, _ = _run_pair(w, 64, 3, 200, T=40, block=64)
+    b, _, _ = _run_pair(w, 64, 3, 200, T=40, block=64)
+    c, _, _ = _run_pair(w, 64, 3, 200, T=40, block=256)
+    for key in ("phi", "ll", "logw", "anc"):
+        assert np.array_equal(a[key], b[key]), key
+    assert np.array_equal(a["anc"], c["anc"])
+    assert np.allclose(a["ll"], c["ll"], rtol=1e-13)
+
+
+def test_multiple_runs_share_a_context():
+    w = W.preset("sir_fp64")
+    y1 = W.observations(w)
+    y2 = W.simulate(w["model"], w["obs"], w["n_pop"], [0.35, 0.12], 40, seed=9, fixed=w["fixed"])
+    runs = [dict(T=50, nx=64, seed=1, y=y1), dict(T=40, nx=100, seed=5, y=y2)]
+    s = G.Sampler(w, runs, N=64, K=3)
+    for _ in range(3):
+        s.step()
+    recs = [s.records(r) for r in range(2)]
+    s.close()
+    cfg = O.config_from_workload(w)
+    r1 = O.smc2_run(cfg, y1, 64, 1, 64, 3)
+    r2 = O.smc2_run(cfg, y2, 100, 5, 64, 3)
+    assert np.allclose(recs[0], r1["rec"], rtol=1e-9, atol=1e-12)
+    assert np.allclose(recs[1], r2["rec"], rtol=1e-9, atol=1e-12)
+
+
+def test_step_after_k_and_errors():
+    w = W.preset("sir_fp64")
+    y = W.observations(w)
+    s = G.Sampler(w, [dict(T=50, nx=64, seed=1, y=y)], N=16, K=1)
+    s.step()
+    with pytest.raises(G.Smc2Error) as e:
+        s.step()
+    assert e.value.code == G.E_STATE
+    s.close()
+
+
+def test_all_dead_reports_numeric():
+    w = dict(W.preset("paper_sir"), fixed=[0], T=5)
+    y = np.zeros((5, 1), dtype=np.int32)
+    y[3] = 4
+    s = G.Sampler(w, [dict(T=5, nx=32, seed=1, y=y)], N=16, K=2)
+    s.step()
+    with pytest.raises(G.Smc2Error) as e:
+        s.records()
+    assert e.value.code == G.E_NUMERIC
+    s.close()
+
+
+@pytest.mark.slow
+def test_full_size_seir_sampled_parity():
+    """The benchmark shape (SEIR, N=1024, N_x=512, T=100, FP32), in the launch
+    configuration the benchmark times: sampled filters and the outer step of every
+    iteration checked against the reference."""
+    w = W.preset("seir")
+    y = W.observations(w)
+    N, nx, K = w["N"], w["nx"], 4
+    s = G.Sampler(w, [dict(T=w["T"], nx=nx, seed=w["seed"], y=y)], N=N, K=K)
+    cfg = O.config_from_workload(w)
+    state = None
+    rng = np.random.default_rng(0)
+    for k in range(1, K + 1):
+        before = {key: s.dump(key) for key in ("phi", "lp", "ll", "logw")} if k > 1 else None
+        s.step()
+        phin, lpn, lln = s.dump("phi_new"), s.dump("lp_new"), s.dump("ll_new")
+        lwp, anc = s.dump("logw_pre"), s.dump("anc")
+        # proposals
+        if k == 1:
+            ph_ref, lp_ref = O.prior_draw(cfg, N, w["seed"])
+        else:
+            ph_ref, lp_ref = O.propose_rw(cfg, w["seed"], k, before["phi"])
+        assert np.allclose(phin, ph_ref, rtol=1e-12, atol=1e-12)
+        assert np.allclose(lpn, lp_ref, rtol=1e-12, atol=1e-12)
+        # sampled particle filters
+        idx = rng.choice(N, size=6, replace=False)
+        for i in idx:
+            th = O.theta_of_phi(cfg, phin[i])
+            ref = O.pf_loglik(cfg, th, y, nx, w["seed"], int(i), k)
+            _log("  k=%d filter %d gpu %.10f ref %.10f" % (k, i, lln[i], ref))
+            if np.isfinite(ref):
+                assert abs(lln[i] - ref) <= 1e-4 * abs(ref)
+            else:
+                assert lln[i] == ref
+        # outer step from the GPU's inputs
+        st = dict(phi=np.zeros((N, w["D"])), lp=np.zeros(N), ll=np.zeros(N), logw=np.zeros(N)) if k == 1 else before
+        status, lwp_ref, anc_ref, rec_ref = O.outer_update(cfg, k, w["seed"], st, phin, lpn, lln)
+        assert status == 0
+        assert np.allclose(lwp, lwp_ref, rtol=1e-9, atol=1e-9)
+        assert np.array_equal(anc, anc_ref)
+        rec = s.records()[k - 1]
+        assert np.allclose(rec, rec_ref, rtol=1e-8, atol=1e-12)
+    s.close()
