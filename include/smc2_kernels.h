@@ -50,6 +50,19 @@ size_t smc2_pf_workspace_bytes(const smc2_config* cfg, const smc2_run* run);
 int smc2_pf_loglik(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
                    uint32_t k, double* d_ll, void* d_workspace, size_t ws_bytes, void* hip_stream);
 
+/* As smc2_pf_loglik, and also writes every filter's per-day log-likelihood
+ * increments (d_inc: double[n_theta][T]) and resampling flags (d_rs:
+ * int32[n_theta][T]); a filter that dies at day t records -inf at t and 0 after. */
+int smc2_pf_trace(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run, uint32_t k,
+                  double* d_ll, double* d_inc, int32_t* d_rs, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
+/* As smc2_pf_trace, and also writes every filter's particle counts of each day
+ * before resampling (d_state: int32[n_theta][T][n_counts][n_x], n_counts = 2 / 3 / 12
+ * for SIR / SEIR / age-structured SEIR). */
+int smc2_pf_trace_state(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
+                        uint32_t k, double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, void* d_workspace,
+                        size_t ws_bytes, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

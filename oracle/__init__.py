@@ -64,6 +64,8 @@ def _declare(L):
     L.or_binomial.argtypes = [c.c_int, c.c_int32, c.c_double, c.c_uint64] + [c.c_uint32] * 5
     L.or_binomial_batch.argtypes = [c.c_int, c.c_int32, c.c_double, c.c_uint64] + [c.c_uint32] * 4 + [
         c.c_int, P(c.c_int32)]
+    L.or_binomial_many.argtypes = [c.c_int, c.c_int, P(c.c_int32), P(c.c_double), c.c_uint64] + [
+        c.c_uint32] * 4 + [P(c.c_int32)]
     L.or_obs_logpmf.restype = c.c_double
     L.or_obs_logpmf.argtypes = [c.c_int, c.c_int32, c.c_int32, c.c_double]
     L.or_resample_trigger.restype = c.c_int
@@ -82,6 +84,9 @@ def _declare(L):
     L.or_pf_loglik.restype = c.c_double
     L.or_pf_loglik.argtypes = [P(Config), P(c.c_double), P(c.c_int32), c.c_int, c.c_int, c.c_uint64,
                                c.c_uint32, c.c_uint32, P(c.c_double), P(c.c_int32)]
+    L.or_pf_trace_state.restype = c.c_double
+    L.or_pf_trace_state.argtypes = [P(Config), P(c.c_double), P(c.c_int32), c.c_int, c.c_int, c.c_uint64,
+                                    c.c_uint32, c.c_uint32, P(c.c_double), P(c.c_int32), P(c.c_int32)]
     L.or_prior_draw.argtypes = [P(Config), c.c_int, c.c_uint64, P(c.c_double), P(c.c_double)]
     L.or_propose_rw.argtypes = [P(Config), c.c_int, c.c_uint64, c.c_uint32, P(c.c_double),
                                 P(c.c_double), P(c.c_double)]
@@ -152,6 +157,15 @@ def binomial_batch(prec, n, p, seed, count, i=0, k=1, t=1, b=0):
     out = np.zeros(count, dtype=np.int32)
     lib().or_binomial_batch(prec, int(n), float(p), int(seed), int(i), int(k), int(t), int(b), int(count),
                             _p(out, ctypes.c_int32))
+    return out
+
+
+def binomial_many(prec, n, p, seed, i=0, k=1, t=1, b=0):
+    n = np.ascontiguousarray(n, dtype=np.int32)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    out = np.zeros(n.size, dtype=np.int32)
+    lib().or_binomial_many(prec, n.size, _p(n, ctypes.c_int32), _p(p, ctypes.c_double), int(seed), int(i), int(k),
+                           int(t), int(b), _p(out, ctypes.c_int32))
     return out
 
 
@@ -239,6 +253,21 @@ def pf_loglik(cfg, theta, y, nx, seed, filt, k, trace=False):
                             _p(inc, ctypes.c_double) if trace else None,
                             _p(rs, ctypes.c_int32) if trace else None)
     return (ll, inc, rs) if trace else ll
+
+
+def pf_trace_state(cfg, theta, y, nx, seed, filt, k):
+    """(ll, inc[T], rs[T], state[T][n_counts][nx]) of one filter."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    T = y.shape[0]
+    nc = {SIR: 2, SEIR: 3, AGE_SEIR: 12}[cfg.model]
+    inc = np.zeros(T)
+    rs = np.zeros(T, dtype=np.int32)
+    st = np.zeros((T, nc, nx), dtype=np.int32)
+    ll = lib().or_pf_trace_state(ctypes.byref(cfg), _p(theta, ctypes.c_double), _p(y, ctypes.c_int32), T, nx,
+                                 int(seed), int(filt), int(k), _p(inc, ctypes.c_double), _p(rs, ctypes.c_int32),
+                                 _p(st, ctypes.c_int32))
+    return ll, inc, rs, st
 
 
 def prior_draw(cfg, N, seed):

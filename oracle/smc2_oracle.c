@@ -92,29 +92,32 @@ double or_normal_call(uint64_t seed, const uint32_t ctr[4])
 
 /* ------------------------------------------------------------------ observations */
 
-/* Per-day constant of the observation log-pmf (FP64):
- *   Poisson: lgamma(y+1); negative binomial: lgamma(y+r) - lgamma(r) - lgamma(y+1) + r log r. */
+/* The observation log-pmf (Sec. V-A: Poisson; the negative binomial has mean `count`
+ * and dispersion r) split into a per-day constant that does not depend on the
+ * particle and a per-particle part, both in FP64:
+ *   Poisson:  log g = [y log(lambda) - lambda]                          + [-lgamma(y+1)]
+ *   NB:       log g = -[y log1p(r/mu) + r log1p(mu/r)]
+ *                     + [lgamma(y+r) - lgamma(r) - lgamma(y+1)]
+ * The per-particle parts have no cancellation (the NB part is a sum of two
+ * non-negative terms), so their rounding to the filter precision is well defined.
+ * A zero mean gives 0 for y = 0 and -inf otherwise. */
 static double or_obs_const(int obs, int32_t y, double r)
 {
-    if (obs == OR_OBS_NB_INC)
-        return ((lgamma((double)y + r) - lgamma(r)) - lgamma((double)y + 1.0)) + r * log(r);
-    return lgamma((double)y + 1.0);
+    if (obs == OR_OBS_NB_INC) return (lgamma((double)y + r) - lgamma(r)) - lgamma((double)y + 1.0);
+    return -lgamma((double)y + 1.0);
 }
 
-/* log g(y | count) in FP64 (Sec. V-A: Poisson; the negative binomial has mean `count`
- * and dispersion r). A zero mean gives 0 for y = 0 and -inf otherwise. */
-static double or_obs_logpmf_c(int obs, int32_t y, int32_t cnt, double r, double cst)
+static double or_obs_part(int obs, int32_t y, int32_t cnt, double r)
 {
     if (cnt <= 0) return (y == 0) ? 0.0 : -INFINITY;
-    double mu = (double)cnt;
-    if (obs == OR_OBS_NB_INC)
-        return (cst + (double)y * log(mu)) - (r + (double)y) * log(r + mu);
-    return ((double)y * log(mu) - mu) - cst;
+    const double mu = (double)cnt;
+    if (obs == OR_OBS_NB_INC) return -((double)y * log1p(r / mu) + r * log1p(mu / r));
+    return (double)y * log(mu) - mu;
 }
 
 double or_obs_logpmf(int obs, int32_t y, int32_t count, double r)
 {
-    return or_obs_logpmf_c(obs, y, count, r, or_obs_const(obs, y, r));
+    return or_obs_part(obs, y, count, r) + or_obs_const(obs, y, r);
 }
 
 /* ------------------------------------------------------------------ resampling */
@@ -356,11 +359,26 @@ void or_binomial_batch(int prec, int32_t n, double p, uint64_t seed, uint32_t i,
     for (int j = 0; j < count; ++j) out[j] = or_binomial(prec, n, p, seed, (uint32_t)j, i, k, t, b);
 }
 
+/* count draws with per-draw (n[j], p[j]) at particle coordinates j = 0..count-1. */
+void or_binomial_many(int prec, int count, const int32_t* n, const double* p, uint64_t seed, uint32_t i,
+                      uint32_t k, uint32_t t, uint32_t b, int32_t* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int j = 0; j < count; ++j) out[j] = or_binomial(prec, n[j], p[j], seed, (uint32_t)j, i, k, t, b);
+}
+
 double or_pf_loglik(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx,
                     uint64_t seed, uint32_t filt, uint32_t k, double* inc_out, int32_t* rs_out)
 {
-    if (cfg->prec == OR_PREC_FP32) return pf_f32(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out);
-    return pf_f64(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out);
+    return or_pf_trace_state(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out, NULL);
+}
+
+double or_pf_trace_state(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx,
+                         uint64_t seed, uint32_t filt, uint32_t k, double* inc_out, int32_t* rs_out,
+                         int32_t* state_out)
+{
+    if (cfg->prec == OR_PREC_FP32) return pf_f32(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out, state_out);
+    return pf_f64(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out, state_out);
 }
 
 /* ------------------------------------------------------------------ outer sampler */

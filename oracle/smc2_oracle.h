@@ -67,6 +67,8 @@ int32_t or_binomial(int prec, int32_t n, double p, uint64_t seed, uint32_t j, ui
                     uint32_t k, uint32_t t, uint32_t b);
 void or_binomial_batch(int prec, int32_t n, double p, uint64_t seed, uint32_t i, uint32_t k,
                        uint32_t t, uint32_t b, int count, int32_t* out);
+void or_binomial_many(int prec, int count, const int32_t* n, const double* p, uint64_t seed, uint32_t i,
+                      uint32_t k, uint32_t t, uint32_t b, int32_t* out);
 double or_obs_logpmf(int obs, int32_t y, int32_t count, double r);
 int or_resample_trigger(const uint64_t* q, int n);
 void or_resample_ancestors(const uint64_t* q, int n, uint64_t x64, int32_t* anc);
@@ -81,6 +83,12 @@ void or_recycle(int K, int D, const double* rec, double* mean, double* cov, doub
 /* ---- the particle filter (Sec. II) ---- */
 double or_pf_loglik(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx,
                     uint64_t seed, uint32_t filt, uint32_t k, double* inc_out, int32_t* rs_out);
+
+/* As or_pf_loglik, also writing every day's particle counts before resampling
+ * (state_out: int32[T][n_counts][nx], n_counts = 2 / 3 / 12 for SIR / SEIR / age). */
+double or_pf_trace_state(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx,
+                         uint64_t seed, uint32_t filt, uint32_t k, double* inc_out, int32_t* rs_out,
+                         int32_t* state_out);
 
 /* ---- the outer sampler (Sec. IV) ---- */
 void or_prior_draw(const or_config* cfg, int N, uint64_t seed, double* phi, double* lp);

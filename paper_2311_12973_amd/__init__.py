@@ -56,6 +56,10 @@ def lib():
     """Load libsmc2.so; raises when it has not been built."""
     global _lib
     if _lib is None:
+        # torch ships its own HIP runtime under the same soname as the system one;
+        # loading torch first makes libsmc2.so bind to that runtime, so the library and
+        # torch share one HIP runtime (and torch's streams are valid for the library).
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libsmc2.so is not built (run __graft_entry__.build() or "
                                "python -m paper_2311_12973_amd.build); no fallback exists")
@@ -89,6 +93,11 @@ def lib():
         L.smc2_resample_batch.argtypes = [c.c_int32, c.c_int32, vp, vp, vp, vp, vp]
         L.smc2_pf_workspace_bytes.restype = c.c_size_t
         L.smc2_pf_workspace_bytes.argtypes = [P(Config), P(Run)]
+        L.smc2_pf_trace.restype = c.c_int
+        L.smc2_pf_trace.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp, vp, vp, c.c_size_t, vp]
+        L.smc2_pf_trace_state.restype = c.c_int
+        L.smc2_pf_trace_state.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp, vp, vp, vp,
+                                          c.c_size_t, vp]
         L.smc2_pf_loglik.restype = c.c_int
         L.smc2_pf_loglik.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp, c.c_size_t, vp]
         _lib = L
@@ -283,8 +292,32 @@ def resample_batch(q, x64, device="cuda"):
     return from_device(ta, pa, np.int32, S * n).reshape(S, n), from_device(tt, pt, np.int32, S)
 
 
-def pf_loglik(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0, device="cuda"):
-    """Particle-filter log-likelihoods for the rows of theta (natural parameters)."""
+def pf_trace_state(w, theta, y, nx, seed, k, precision=None, block=0, device="cuda"):
+    """(ll, inc[n][T], rs[n][T], state[n][T][n_counts][nx]) for the rows of theta."""
+    cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, block=block)
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
+    runs = make_runs([dict(T=y.shape[0], nx=nx, seed=seed, y=y)])
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    n, T = theta.shape[0], y.shape[0]
+    nc = {SIR: 2, SEIR: 3, AGE_SEIR: 12}[cfg.model]
+    L = lib()
+    wsb = L.smc2_pf_workspace_bytes(ctypes.byref(cfg), runs)
+    tws, pws = device_buffer(wsb, device)
+    tth, pth = to_device(theta, device)
+    tll, pll = device_buffer(8 * n, device)
+    tinc, pinc = device_buffer(8 * n * T, device)
+    trs, prs = device_buffer(4 * n * T, device)
+    tst, pst = device_buffer(4 * n * T * nc * nx, device)
+    _check(L.smc2_pf_trace_state(ctypes.byref(cfg), n, pth, runs, int(k), pll, pinc, prs, pst, pws, wsb,
+                                 current_stream()))
+    return (from_device(tll, pll, np.float64, n), from_device(tinc, pinc, np.float64, n * T).reshape(n, T),
+            from_device(trs, prs, np.int32, n * T).reshape(n, T),
+            from_device(tst, pst, np.int32, n * T * nc * nx).reshape(n, T, nc, nx))
+
+
+def pf_loglik(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0, device="cuda", trace=False):
+    """Particle-filter log-likelihoods for the rows of theta (natural parameters);
+    with trace=True also the per-day increments and resampling flags."""
     cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, pf_always=pf_always, block=block)
     y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
     runs = make_runs([dict(T=y.shape[0], nx=nx, seed=seed, y=y)])
@@ -295,5 +328,12 @@ def pf_loglik(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0,
     tws, pws = device_buffer(wsb, device)
     tth, pth = to_device(theta, device)
     tll, pll = device_buffer(8 * n, device)
-    _check(L.smc2_pf_loglik(ctypes.byref(cfg), n, pth, runs, int(k), pll, pws, wsb, current_stream()))
-    return from_device(tll, pll, np.float64, n)
+    if not trace:
+        _check(L.smc2_pf_loglik(ctypes.byref(cfg), n, pth, runs, int(k), pll, pws, wsb, current_stream()))
+        return from_device(tll, pll, np.float64, n)
+    T = y.shape[0]
+    tinc, pinc = device_buffer(8 * n * T, device)
+    trs, prs = device_buffer(4 * n * T, device)
+    _check(L.smc2_pf_trace(ctypes.byref(cfg), n, pth, runs, int(k), pll, pinc, prs, pws, wsb, current_stream()))
+    return (from_device(tll, pll, np.float64, n), from_device(tinc, pinc, np.float64, n * T).reshape(n, T),
+            from_device(trs, prs, np.int32, n * T).reshape(n, T))

@@ -68,7 +68,10 @@ template <typename real> __device__ __forceinline__ real rdiv(real a, real b);
 template <> __device__ __forceinline__ float rdiv<float>(float a, float b) { return __fdiv_rn(a, b); }
 template <> __device__ __forceinline__ double rdiv<double>(double a, double b) { return a / b; }
 template <typename real> __device__ __forceinline__ real rsqrt_rn(real a);
-template <> __device__ __forceinline__ float rsqrt_rn<float>(float a) { return __fsqrt_rn(a); }
+// Correctly rounded FP32 square root: the FP64 square root of a float, rounded to
+// float, is the correctly rounded result (53 > 2*24 + 2 bits); the FP32 hardware
+// square root is only accurate to 1 ulp.
+template <> __device__ __forceinline__ float rsqrt_rn<float>(float a) { return (float)__dsqrt_rn((double)a); }
 template <> __device__ __forceinline__ double rsqrt_rn<double>(double a) { return __dsqrt_rn(a); }
 
 // Stream of one binomial draw: flows counter without the call index.
@@ -194,20 +197,26 @@ template <typename real> __device__ __forceinline__ real leave_prob(real x)
 // ----------------------------------------------------------- observations (FP64)
 enum : int { OBS_POIS_PREV = 0, OBS_POIS_INC = 1, OBS_NB_INC = 2 };
 
-// per-day constant: Poisson lgamma(y+1); NB lgamma(y+r) - lgamma(r) - lgamma(y+1) + r log r
+// The observation log-pmf split into a per-day constant (no particle dependence)
+// and a per-particle part, both FP64:
+//   Poisson  log g = [y log(lambda) - lambda] + [-lgamma(y+1)]
+//   NB       log g = -[y log1p(r/mu) + r log1p(mu/r)] + [lgamma(y+r) - lgamma(r) - lgamma(y+1)]
+// The constant scales every weight equally: it leaves the normalised weights
+// unchanged and enters the likelihood increment once per day. The per-particle
+// parts have no cancellation, so their rounding to the filter precision is well
+// defined. A zero mean gives 0 for y = 0 and -inf otherwise.
 __device__ __forceinline__ double obs_const(int obs, int32_t y, double r)
 {
-    if (obs == OBS_NB_INC) return ((lgamma((double)y + r) - lgamma(r)) - lgamma((double)y + 1.0)) + r * log(r);
-    return lgamma((double)y + 1.0);
+    if (obs == OBS_NB_INC) return (lgamma((double)y + r) - lgamma(r)) - lgamma((double)y + 1.0);
+    return -lgamma((double)y + 1.0);
 }
 
-template <int OBS>
-__device__ __forceinline__ double obs_logpmf(int32_t y, int32_t cnt, double r, double cst)
+template <int OBS> __device__ __forceinline__ double obs_part(int32_t y, int32_t cnt, double r)
 {
     if (cnt <= 0) return (y == 0) ? 0.0 : -INFINITY;
     const double mu = (double)cnt;
-    if (OBS == OBS_NB_INC) return (cst + (double)y * log(mu)) - (r + (double)y) * log(r + mu);
-    return ((double)y * log(mu) - mu) - cst;
+    if (OBS == OBS_NB_INC) return -((double)y * log1p(r / mu) + r * log1p(mu / r));
+    return (double)y * log(mu) - mu;
 }
 
 // ----------------------------------------------------------- wave / block primitives

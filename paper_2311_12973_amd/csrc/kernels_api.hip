@@ -119,6 +119,33 @@ extern "C" size_t smc2_pf_workspace_bytes(const smc2_config* cfg, const smc2_run
 extern "C" int smc2_pf_loglik(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
                               uint32_t k, double* d_ll, void* d_ws, size_t ws_bytes, void* stream)
 {
+    return smc2_pf_trace(cfg, n_theta, d_theta, run, k, d_ll, nullptr, nullptr, d_ws, ws_bytes, stream);
+}
+
+static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run, uint32_t k,
+                  double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, void* d_ws, size_t ws_bytes,
+                  void* stream);
+
+extern "C" int smc2_pf_trace(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
+                             uint32_t k, double* d_ll, double* d_inc, int32_t* d_rs, void* d_ws, size_t ws_bytes,
+                             void* stream)
+{
+    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, d_inc, d_rs, nullptr, d_ws, ws_bytes, stream);
+}
+
+extern "C" int smc2_pf_trace_state(const smc2_config* cfg, int32_t n_theta, const double* d_theta,
+                                   const smc2_run* run, uint32_t k, double* d_ll, double* d_inc, int32_t* d_rs,
+                                   int32_t* d_state, void* d_ws, size_t ws_bytes, void* stream)
+{
+    if (!d_state) return kfail(SMC2_E_ARG, "d_state is NULL");
+    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, d_inc, d_rs, d_state, d_ws, ws_bytes, stream);
+}
+
+static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run, uint32_t k,
+                  double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, void* d_ws, size_t ws_bytes,
+                  void* stream)
+{
+    if ((d_inc == nullptr) != (d_rs == nullptr)) return kfail(SMC2_E_ARG, "trace needs both d_inc and d_rs");
     if (!cfg || !run || !run->y) return kfail(SMC2_E_ARG, "null config or run");
     if (!pf_supported(cfg->model, cfg->obs)) return kfail(SMC2_E_UNSUPPORTED, "model/observation not supported");
     if (cfg->precision != SMC2_PREC_FP32 && cfg->precision != SMC2_PREC_FP64) return kfail(SMC2_E_ARG, "precision");
@@ -151,6 +178,9 @@ extern "C" int smc2_pf_loglik(const smc2_config* cfg, int32_t n_theta, const dou
     a.runs = (const RunDev*)w;
     a.items = nullptr;
     a.k_dev = nullptr;
+    a.trace_inc = d_inc;
+    a.trace_rs = d_rs;
+    a.trace_state = d_state;
     a.k_const = k;
     a.n_items = n_theta;
     a.N = n_theta;

@@ -25,6 +25,9 @@ struct PFArgs {
     const RunDev* runs;     // [n_runs]
     const int32_t* items;   // [n_items] global filter indices g, or NULL for g = item
     const int32_t* k_dev;   // iteration counter in device memory, or NULL to use k_const
+    double* trace_inc;      // [G][T] per-day likelihood increments, or NULL (diagnostics)
+    int32_t* trace_rs;      // [G][T] per-day resampling flags, or NULL
+    int32_t* trace_state;   // [G][T][NC][nx] per-day counts before resampling, or NULL
     uint32_t k_const;
     int32_t n_items;
     int32_t N;              // filters per run: g = run * N + filter

@@ -1,15 +1,17 @@
 // pf_kernel.hip — the batch of particle filters (Sec. II) on gfx950.
 //
 // One workgroup runs one particle filter: it owns the filter's N_x particles for
-// all T days. Thread t holds particles t*PPT .. t*PPT+PPT-1 (compartment counts and
-// log-weights in registers), so the only HBM traffic is theta, the observations
-// (L2-resident, shared by all filters) and one log-likelihood per filter. Per day:
+// all T days. Thread t works on particles t, t + blockDim, ... whose compartment
+// counts and log-weights stay in LDS, so the only HBM traffic is theta, the
+// observations (L2-resident, shared by all filters) and one log-likelihood per
+// filter. Per day:
 //   1. propagate every particle through the chain-binomial model (Sec. V-A),
 //      flows drawn from counter-based Philox streams (particle, filter, k, t, draw);
-//   2. weight update a = lw + log g(y_t | x_t) (Sec. II, bootstrap proposal);
+//   2. weight update a = lw + log g(y_t | x_t) - c_t (Sec. II, bootstrap proposal;
+//      c_t, the particle-independent part of log g, is carried separately);
 //   3. block max m, then w = exp(a - m) in FP64; the FP64 block sum S gives the
-//      likelihood increment m + log S - log S_prev (the mean unnormalised weight of
-//      Sec. II, accumulated in FP64);
+//      likelihood increment m + log S - log S_prev + c_t (the mean unnormalised
+//      weight of Sec. II, accumulated in FP64);
 //   4. if ESS < N_x/2 (exact integer test on the quantised weights) and t < T:
 //      integer systematic resampling (LDS scan + search), gather of the counts
 //      through LDS, log-weights reset (every particle gets the mean weight).
@@ -79,10 +81,10 @@ __device__ __forceinline__ void model_setup(const PFArgs& a, const double* th, M
 // SIR (S->I, I->R) = (0, 1); SEIR (S->E, E->I, I->R) = (0, 1, 2); age-structured
 // group g: 3g, 3g+1, 3g+2 (the draw index equals the index of the compartment the
 // flow leaves). One copy of the sampler per model: the draws of a day run in a
-// loop. Returns log g(y_t | x_t) in FP64.
+// loop. Returns the per-particle part of log g(y_t | x_t) in FP64.
 template <typename real, int MODEL, int OBS>
 __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* st, int cap, int j,
-                                               DrawStream ds, const int32_t* yt, const double* ct)
+                                               DrawStream ds, const int32_t* yt)
 {
     if (MODEL == MODEL_SIR) {
         const int32_t S = st[j], I = st[cap + j];
@@ -98,7 +100,7 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
         const int32_t I1 = I + nsi - nir;
         st[j] = S - nsi;
         st[cap + j] = I1;
-        return obs_logpmf<OBS>(yt[0], OBS == OBS_POIS_PREV ? I1 : nsi, mc.r, ct[0]);
+        return obs_part<OBS>(yt[0], OBS == OBS_POIS_PREV ? I1 : nsi, mc.r);
     } else if (MODEL == MODEL_SEIR) {
         const int32_t S = st[j], E = st[cap + j], I = st[2 * cap + j];
         const real p_se = leave_prob<real>(mc.cinf * (real)I);
@@ -117,7 +119,7 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
         st[j] = S - nse;
         st[cap + j] = E + nse - nei;
         st[2 * cap + j] = I1;
-        return obs_logpmf<OBS>(yt[0], OBS == OBS_POIS_PREV ? I1 : nei, mc.r, ct[0]);
+        return obs_part<OBS>(yt[0], OBS == OBS_POIS_PREV ? I1 : nei, mc.r);
     } else {
         // forces of infection from the previous day's infected counts
         real pse0, pse1, pse2, pse3;
@@ -154,7 +156,7 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
             st[(3 * g) * cap + j] = S - nse;
             st[(3 * g + 1) * cap + j] = E + nse - nei;
             st[(3 * g + 2) * cap + j] = I1;
-            lg = lg + obs_logpmf<OBS>(yt[g], OBS == OBS_POIS_PREV ? I1 : nei, mc.r, ct[g]);
+            lg = lg + obs_part<OBS>(yt[g], OBS == OBS_POIS_PREV ? I1 : nei, mc.r);
         }
         return lg;
     }
@@ -163,7 +165,7 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
 // LDS layout of one filter (cap = particles rounded up to the block size):
 //   C   u64[cap]     quantised weights, then their inclusive scan
 //   red RedLds       reduction slots
-//   cst f64[T*NG]    per-day observation constants
+//   cst f64[T]       per-day observation constants
 //   lw  real[cap]    log-weights (relative to the last maximum)
 //   st  i32[NC*cap]  compartment counts
 //   tmp i32[cap]     gather staging
@@ -193,7 +195,7 @@ __global__ void __launch_bounds__(1024) k_pf(PFArgs a)
     uint64_t* C = reinterpret_cast<uint64_t*>(smem);
     RedLds* red = reinterpret_cast<RedLds*>(C + cap);
     double* cst = reinterpret_cast<double*>(red + 1);
-    real* lw = reinterpret_cast<real*>(cst + (size_t)T * NG);
+    real* lw = reinterpret_cast<real*>(cst + T);
     int32_t* st = reinterpret_cast<int32_t*>(lw + cap);
     int32_t* tmp = st + NC * cap;
     int32_t* anc = tmp + cap;
@@ -202,7 +204,12 @@ __global__ void __launch_bounds__(1024) k_pf(PFArgs a)
     MConst<real> mc;
     model_setup<real, MODEL>(a, th, mc);
     const int32_t* y = a.y + run.y_off;
-    for (int e = tid; e < T * NG; e += nthr) cst[e] = obs_const(OBS, y[e], mc.r);
+    for (int t = tid; t < T; t += nthr) {
+        double c = 0.0;
+#pragma unroll
+        for (int gi = 0; gi < NG; ++gi) c = c + obs_const(OBS, y[t * NG + gi], mc.r);
+        cst[t] = c;
+    }
     for (int j = tid; j < nx; j += nthr) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) st[c * cap + j] = mc.x0[c];
@@ -215,19 +222,30 @@ __global__ void __launch_bounds__(1024) k_pf(PFArgs a)
     for (int t = 1; t <= T; ++t) {
         const uint32_t kt = (kit << 16) | (uint32_t)t;
         const int32_t* yt = y + (size_t)(t - 1) * NG;
-        const double* ct = cst + (size_t)(t - 1) * NG;
         // 1. propagate and weight: lw[j] <- a_j = lw_j + log g(y_t | x_t^j)
         real amax = (real)-INFINITY;
         for (int j = tid; j < nx; j += nthr) {
             const double lg = particle_day<real, MODEL, OBS>(
-                mc, st, cap, j, DrawStream{(uint32_t)j, filt, kt, 0u, run.k0, run.k1}, yt, ct);
+                mc, st, cap, j, DrawStream{(uint32_t)j, filt, kt, 0u, run.k0, run.k1}, yt);
             const real av = lw[j] + (real)lg;
             lw[j] = av;
             amax = av > amax ? av : amax;
         }
+        if (a.trace_state) {
+            for (int j = tid; j < nx; j += nthr)
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+                    a.trace_state[(((size_t)g * T + (t - 1)) * NC + c) * nx + j] = st[c * cap + j];
+        }
         const real m = block_max<real>(amax, red);
         if (m == (real)-INFINITY) {
             ll = -INFINITY;
+            if (a.trace_inc && tid == 0) {
+                for (int tt = t; tt <= T; ++tt) {
+                    a.trace_inc[(size_t)g * T + tt - 1] = tt == t ? -INFINITY : 0.0;
+                    a.trace_rs[(size_t)g * T + tt - 1] = 0;
+                }
+            }
             break;
         }
         // 2. normalise by the maximum; FP64 sum and quantised weights
@@ -245,10 +263,16 @@ __global__ void __launch_bounds__(1024) k_pf(PFArgs a)
             lw[j] = av - m;
         }
         block_sum3(sl, q1, q2, red);
-        ll = ll + (((double)m + log(sl)) - log(s_prev));
+        const double inc = (((double)m + log(sl)) - log(s_prev)) + cst[t - 1];
+        ll = ll + inc;
         s_prev = sl;
         // 3. resample when ESS < N_x / 2 (never after the last observation)
-        if (t < T && (a.pf_always || ess_below_half(q1, q2, nx))) {
+        const bool rs = t < T && (a.pf_always || ess_below_half(q1, q2, nx));
+        if (a.trace_inc && tid == 0) {
+            a.trace_inc[(size_t)g * T + t - 1] = inc;
+            a.trace_rs[(size_t)g * T + t - 1] = rs ? 1 : 0;
+        }
+        if (rs) {
             const uint64_t Q = block_scan_lds(C, nx, red);
             const W4 wd = philox10(0u, filt, kt, S_PF_RS << 24, run.k0, run.k1);
             block_ancestors(C, nx, Q, (uint64_t)wd.x | ((uint64_t)wd.y << 32), anc);
@@ -275,7 +299,8 @@ size_t pf_lds_bytes(int model, int prec, int block, int nx, int T)
     const int ng = model == MODEL_AGE ? 4 : 1;
     const size_t cap = (size_t)((nx + block - 1) / block) * block;
     const size_t rb = prec == 0 ? 4 : 8;
-    return cap * 8 + sizeof(RedLds) + (size_t)T * ng * 8 + cap * rb + (size_t)(nc + 2) * cap * 4;
+    (void)ng;
+    return cap * 8 + sizeof(RedLds) + (size_t)T * 8 + cap * rb + (size_t)(nc + 2) * cap * 4;
 }
 
 template <typename real, int MODEL, int OBS>

@@ -125,6 +125,7 @@ struct smc2_ctx {
     bool graph_ready = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture the graph
     std::vector<hipEvent_t> ev;  // 4 per iteration: step start, pf start, pf end, step end
     int timed_from = 0;
 
@@ -361,9 +362,8 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     return SMC2_OK;
 }
 
-static hipError_t enqueue_iteration(smc2_ctx* c, hipEvent_t pf0, hipEvent_t pf1)
+static hipError_t enqueue_iteration(smc2_ctx* c, hipStream_t s, hipEvent_t pf0, hipEvent_t pf1)
 {
-    hipStream_t s = c->stream;
     hipError_t e = launch_begin_iteration(c->oa, s);
     if (e == hipSuccess) e = launch_propose(c->oa, c->op, c->d_seeds, s);
     if (e == hipSuccess && pf0) e = hipEventRecord(pf0, s);
@@ -390,10 +390,13 @@ extern "C" int smc2_step(smc2_ctx* c)
     if (e == hipSuccess) {
         if (c->cfg.use_graph) {
             if (!c->graph_ready) {
-                e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+                // capture on a private stream (the caller's may be the null stream, which
+                // cannot be captured); the graph is then replayed on the caller's stream
+                if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
+                if (e == hipSuccess) e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
                 if (e == hipSuccess) {
-                    const hipError_t e1 = enqueue_iteration(c, nullptr, nullptr);
-                    e = hipStreamEndCapture(c->stream, &c->graph);
+                    const hipError_t e1 = enqueue_iteration(c, c->cap_stream, nullptr, nullptr);
+                    e = hipStreamEndCapture(c->cap_stream, &c->graph);
                     if (e1 != hipSuccess) e = e1;
                 }
                 if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
@@ -403,7 +406,7 @@ extern "C" int smc2_step(smc2_ctx* c)
             if (e == hipSuccess) e = hipGraphLaunch(c->graph_exec, c->stream);
             if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
         } else {
-            e = enqueue_iteration(c, ev[1], ev[2]);
+            e = enqueue_iteration(c, c->stream, ev[1], ev[2]);
         }
     }
     if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
@@ -526,6 +529,7 @@ extern "C" int smc2_destroy(smc2_ctx* c)
     (void)hipStreamSynchronize(c->stream);
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (hipEvent_t e : c->ev)
         if (e) (void)hipEventDestroy(e);
     delete c;

@@ -62,6 +62,23 @@ def test_binomial_bit_exact(prec):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("prec", [G.PREC_FP64, G.PREC_FP32])
+def test_binomial_bit_exact_many(prec):
+    """About a million draws over random (n, p) in both regimes: rare rounding
+    differences (an FP32 operation that is not correctly rounded, a fused
+    multiply-add) show up here."""
+    rng = np.random.default_rng(17 + prec)
+    M = 1 << 20
+    n = np.floor(10 ** rng.uniform(0, 6.3, M)).astype(np.int32)
+    p = 10 ** rng.uniform(-6, np.log10(0.95), M)
+    if prec == G.PREC_FP32:
+        p = p.astype(np.float32).astype(np.float64)
+    got = G.binomial_batch(prec, n, p, seed=123, i=7, k=4, t=33, b=1)
+    want = O.binomial_many(prec, n, p, 123, i=7, k=4, t=33, b=1)
+    bad = np.flatnonzero(got != want)
+    assert len(bad) == 0, [(int(n[j]), float(p[j]), int(got[j]), int(want[j])) for j in bad[:8]]
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 500, 1000, 2048, 4096])
 def test_resample_bit_exact(n):
     rng = np.random.default_rng(n)
