@@ -40,6 +40,9 @@ def main():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="run one plain device copy of this many MiB before the timed region (calibrates "
+                         "the FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the sampler is not sharded across GPUs); "
@@ -53,6 +56,12 @@ def main():
     from paper_2311_12973_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calib_mb:
+        src = torch.ones(args.copy_calib_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = W.preset(args.workload)
     y = W.observations(w)
     N, nx, T = w["N"], w["nx"], w["T"]

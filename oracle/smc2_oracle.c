@@ -234,10 +234,19 @@ int or_lkernel_fit(int N, int D, const double* phi, const double* phi_new, const
         for (int a = 0; a < D2; ++a)
             for (int c = 0; c < D2; ++c) cov[a * D2 + c] += omega[i] * z[a] * z[c];
     }
+    /* Numerical-rank floor: a Cholesky pivot of coordinate a must exceed
+       OR_LK_REL_FLOOR times that coordinate's raw second moment cov_aa + mu_a^2 (the
+       scale of the rounding error of a variance computed from the samples); a fit
+       of a (numerically) degenerate population is rejected instead of being
+       conditioned on rounding noise. */
+    double floor_[2 * OR_DMAX];
+    for (int a = 0; a < D2; ++a) floor_[a] = OR_LK_REL_FLOOR * (cov[a * D2 + a] + mu[a] * mu[a]);
     double S22[OR_DMAX * OR_DMAX] = {0}, L22[OR_DMAX * OR_DMAX], S[OR_DMAX * OR_DMAX];
     for (int a = 0; a < D; ++a)
         for (int c = 0; c < D; ++c) S22[a * D + c] = cov[(D + a) * D2 + D + c];
     if (or_cholesky(D, S22, L22) != 0) return -1;
+    for (int a = 0; a < D; ++a)
+        if (!(L22[a * D + a] * L22[a * D + a] > floor_[D + a])) return -1;
     /* row r of A solves S22 a = S21[:, r] (S22 symmetric) */
     for (int r = 0; r < D; ++r) {
         double b[OR_DMAX];
@@ -252,6 +261,8 @@ int or_lkernel_fit(int N, int D, const double* phi, const double* phi_new, const
             S[a * D + c] = s;
         }
     if (or_cholesky(D, S, LS) != 0) return -1;
+    for (int a = 0; a < D; ++a)
+        if (!(LS[a * D + a] * LS[a * D + a] > floor_[a])) return -1;
     return 0;
 }
 

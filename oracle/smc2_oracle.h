@@ -38,6 +38,8 @@ enum { OR_S_PF_PROP = 1, OR_S_PF_RS = 2, OR_S_PRIOR = 3, OR_S_RW = 4, OR_S_OUTER
        OR_S_MLP_INIT = 6, OR_S_MLP_PERM = 7 };
 
 #define OR_DMAX 8
+/* relative numerical-rank floor of the L-kernel fit (see or_lkernel_fit) */
+#define OR_LK_REL_FLOOR 1e-12
 #define OR_NFIXED 32
 
 typedef struct {

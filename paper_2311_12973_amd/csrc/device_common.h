@@ -85,23 +85,38 @@ struct DrawStream {
 };
 
 // ----------------------------------------------------------- binomial sampler
+// 1/m for m = 1..128, correctly rounded in each precision (compile-time division).
+template <typename real> struct RcpTable {
+    real v[128];
+    constexpr RcpTable() : v()
+    {
+        for (int i = 0; i < 128; ++i) v[i] = (real)1 / (real)(i + 1);
+    }
+};
+static __constant__ RcpTable<float> c_rcp_f32;
+static __constant__ RcpTable<double> c_rcp_f64;
+template <typename real> __device__ __forceinline__ real rcp_int(int m);
+template <> __device__ __forceinline__ float rcp_int<float>(int m) { return c_rcp_f32.v[m - 1]; }
+template <> __device__ __forceinline__ double rcp_int<double>(int m) { return c_rcp_f64.v[m - 1]; }
+
 // Sequential-search inversion of the Binomial(n, p) CDF for p <= 1/2, n p < 10:
 // f_0 = (1-p)^n, f_{k+1} = f_k ((n-k) r) / (k+1), r = p/(1-p); stops at the first k
 // whose running sum reaches u, when adding a term no longer changes the sum, or
 // at k = min(n, 127).
+// l1p = log1p(-p) in FP64 (hoisted by callers whose p is fixed per filter).
 template <typename real>
-__device__ __forceinline__ int32_t binom_inversion(int32_t n, real p, uint32_t word)
+__device__ __forceinline__ int32_t binom_inversion(int32_t n, real p, double l1p, uint32_t word)
 {
     const real u = (real)u24(word);
     const real q = (real)1 - p;
     const real r = rdiv<real>(p, q);
-    real f = (real)exp((double)n * log1p(-(double)p));
+    real f = (real)exp((double)n * l1p);
     real F = f;
     int32_t k = 0;
     const int32_t kcap = n < 127 ? n : 127;
     while (u > F && k < kcap) {
         real t = (real)(n - k) * r;
-        t = t * rdiv<real>((real)1, (real)(k + 1));
+        t = t * rcp_int<real>(k + 1);
         f = f * t;
         k = k + 1;
         const real Fn = F + f;
@@ -146,6 +161,9 @@ __device__ __forceinline__ int32_t binom_btrs(int32_t n, real p, const DrawStrea
     const int64_t ci = (int64_t)cfl;
     const real cf = (real)(c - cfl);
     W4 w{0u, 0u, 0u, 0u};
+    // per-draw constants of the final test, computed on the first attempt that needs them
+    bool have = false;
+    double alpha = 0.0, lpq = 0.0, m = 0.0, h = 0.0;
     for (int e = 0; e < 256; ++e) {
         if ((e & 1) == 0) w = s.call((uint32_t)(e >> 1));
         const uint32_t wu = (e & 1) ? w.z : w.x;
@@ -161,10 +179,13 @@ __device__ __forceinline__ int32_t binom_btrs(int32_t n, real p, const DrawStrea
         const int64_t k = ci + (int64_t)floor((double)t);
         if (k < 0 || k > n) continue;
         if (us >= (real)0.07 && v <= vr) return (int32_t)k;
-        const double alpha = (2.83 + 5.1 / (double)bb) * (double)spq;
-        const double lpq = log((double)p / (double)q);
-        const double m = floor((double)(n + 1) * (double)p);
-        const double h = lfact(m) + lfact((double)n - m);
+        if (!have) {
+            alpha = (2.83 + 5.1 / (double)bb) * (double)spq;
+            lpq = log((double)p / (double)q);
+            m = floor((double)(n + 1) * (double)p);
+            h = lfact(m) + lfact((double)n - m);
+            have = true;
+        }
         const double lhs = log((double)v * alpha / ((double)aa / ((double)us * (double)us) + (double)bb));
         const double rhs = ((h - lfact((double)k)) - lfact((double)(n - k))) + ((double)k - m) * lpq;
         if (lhs <= rhs) return (int32_t)k;
@@ -172,8 +193,9 @@ __device__ __forceinline__ int32_t binom_btrs(int32_t n, real p, const DrawStrea
     return (int32_t)floor((double)(n + 1) * (double)p);
 }
 
+// Binomial(n, p). l1p, when not NaN, is log1p(-min(p, 1-p)) precomputed in FP64.
 template <typename real>
-__device__ __forceinline__ int32_t binomial(int32_t n, real p, const DrawStream& s)
+__device__ __forceinline__ int32_t binomial(int32_t n, real p, const DrawStream& s, double l1p = NAN)
 {
     if (n <= 0 || !(p > (real)0)) return 0;
     if (p >= (real)1) return n;
@@ -181,7 +203,8 @@ __device__ __forceinline__ int32_t binomial(int32_t n, real p, const DrawStream&
     const real pp = flip ? (real)1 - p : p;
     int32_t k;
     if ((real)n * pp < (real)10) {
-        k = binom_inversion<real>(n, pp, s.call(0u).x);
+        const double lq = (l1p == l1p) ? l1p : log1p(-(double)pp);
+        k = binom_inversion<real>(n, pp, lq, s.call(0u).x);
     } else {
         k = binom_btrs<real>(n, pp, s);
     }

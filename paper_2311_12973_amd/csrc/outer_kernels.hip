@@ -10,31 +10,18 @@
 //             ESS = l_k (Eq. ess_smc2, recycling_I), estimates (Eq. realised_estimates),
 //             integer systematic resampling (Eq. cdf, ncopies) as a prefix-sum search and
 //             redistribution (Alg. 1) as a gather, reset (log w = 0), and the record.
-// Moment sums over samples run sequentially in sample order, one thread per matrix
-// entry, so they do not depend on the launch shape.
+// k_propose and k_outer are instantiated per parameter dimension D (1..8), so the
+// per-sample vectors live in registers. Moment sums over samples are workgroup
+// reductions in a fixed order (a fixed 256-thread workgroup), so the result does not
+// depend on anything but N.
 #include "block_ops.h"
 #include "outer_kernels.h"
 
 namespace smc2 {
 
 #define LOG_2PI 1.8378770664093453
-
-__device__ __forceinline__ double prior_logpdf(const OuterParams& p, const double* phi)
-{
-    double lp = 0.0;
-    for (int d = 0; d < p.D; ++d) {
-        const int fam = (int)p.prior[3 * d];
-        const double a = p.prior[3 * d + 1], b = p.prior[3 * d + 2];
-        if (fam == PRIOR_UNIFORM) {
-            if (!(phi[d] >= a && phi[d] <= b)) return -INFINITY;
-            lp += -log(b - a);
-        } else {
-            const double z = (phi[d] - a) / b;
-            lp += (-0.5 * z * z - log(b)) - 0.5 * LOG_2PI;
-        }
-    }
-    return lp;
-}
+// relative numerical-rank floor of the L-kernel fit
+#define LK_REL_FLOOR 1e-12
 
 __device__ __forceinline__ double theta_of(int fam, double v)
 {
@@ -45,17 +32,18 @@ __device__ __forceinline__ double theta_of(int fam, double v)
 
 __global__ void k_begin(int32_t* k_dev) { *k_dev += 1; }
 
+template <int D>
 __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, const uint64_t* seeds)
 {
     const int g = (int)(blockIdx.x * blockDim.x + threadIdx.x);
     if (g >= p.R * p.N) return;
-    const int D = p.D;
     const int r = g / p.N;
     const uint32_t i = (uint32_t)(g - r * p.N);
     const uint64_t seed = seeds[r];
     const uint32_t k = (uint32_t)(*o.k_dev);
-    double phin[DMAX];
+    double phin[D];
     if (k == 1) {
+#pragma unroll
         for (int d = 0; d < D; ++d) {
             const W4 w = philox10(i, 0u, 1u << 16, (S_PRIOR << 24) | (uint32_t)d, (uint32_t)seed,
                                   (uint32_t)(seed >> 32));
@@ -69,16 +57,31 @@ __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, c
             }
         }
     } else {
-        double z[DMAX];
+        double z[D];
+#pragma unroll
         for (int d = 0; d < D; ++d) z[d] = normal_call(i, 0u, k << 16, (S_RW << 24) | (uint32_t)d, seed);
         const double* ph = o.phi + (size_t)g * D;
+#pragma unroll
         for (int d = 0; d < D; ++d) {
             double acc = 0.0;
+#pragma unroll
             for (int e = 0; e <= d; ++e) acc += p.lrw[d * D + e] * z[e];
             phin[d] = ph[d] + acc;
         }
     }
-    const double lpn = prior_logpdf(p, phin);
+    double lpn = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const int fam = (int)p.prior[3 * d];
+        const double a = p.prior[3 * d + 1], b = p.prior[3 * d + 2];
+        if (fam == PRIOR_UNIFORM) {
+            lpn = (phin[d] >= a && phin[d] <= b && lpn != -INFINITY) ? lpn + -log(b - a) : -INFINITY;
+        } else {
+            const double zz = (phin[d] - a) / b;
+            lpn = lpn + ((-0.5 * zz * zz - log(b)) - 0.5 * LOG_2PI);
+        }
+    }
+#pragma unroll
     for (int d = 0; d < D; ++d) {
         o.phi_new[(size_t)g * D + d] = phin[d];
         o.theta_new[(size_t)g * D + d] = theta_of((int)p.prior[3 * d], phin[d]);
@@ -119,26 +122,96 @@ __device__ void chol_solve(int n, const double* L, double* b)
     }
 }
 
-// log N(x; mu, L L^T)
-__device__ double mvn_logpdf(int n, const double* x, const double* mu, const double* L, int ldl)
+// log N(x; mu, L L^T), L row-major D x D
+template <int D> __device__ __forceinline__ double mvn_logpdf(const double* x, const double* mu, const double* L)
 {
-    double v[DMAX];
+    double v[D];
     double quad = 0.0, logdet = 0.0;
-    for (int i = 0; i < n; ++i) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
         double s = x[i] - mu[i];
-        for (int k = 0; k < i; ++k) s -= L[i * ldl + k] * v[k];
-        v[i] = s / L[i * ldl + i];
+#pragma unroll
+        for (int k = 0; k < i; ++k) s -= L[i * D + k] * v[k];
+        v[i] = s / L[i * D + i];
         quad += v[i] * v[i];
-        logdet += log(L[i * ldl + i]);
+        logdet += log(L[i * D + i]);
     }
-    return -0.5 * quad - logdet - 0.5 * n * LOG_2PI;
+    return -0.5 * quad - logdet - 0.5 * D * LOG_2PI;
 }
 
+constexpr int OUTER_WAVES = OUTER_BLOCK / 64;
+constexpr int VSUM_MAX = 17;  // widest block_sum_vec: 2 D + 1 for D = 8
+
+// Sum of E per-thread values over the block, in a fixed order (butterfly inside each
+// wave, then the waves in index order); every thread then reads the E sums from out[]
+// (LDS). lds holds OUTER_WAVES x E doubles.
+template <int E>
+__device__ __forceinline__ void block_sum_vec(double (&v)[E], double* lds, double* out)
+{
+    static_assert(E <= VSUM_MAX, "block_sum_vec width");
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = wave_sum(v[e]);
+    if (lane_id() == 0)
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds[wave_id() * E + e] = v[e];
+    __syncthreads();
+    if ((int)threadIdx.x < E) {
+        double s = 0.0;
+        for (int w = 0; w < OUTER_WAVES; ++w) s += lds[w * E + threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+// out (NV x NV, symmetric) = sum_i w_i (z_i - m)(z_i - m)^T, z_i loaded by load(i, z).
+// The NV (NV + 1) / 2 upper-triangle entries are accumulated eight at a time so a
+// thread never holds more than eight partial sums.
+template <int NV, class Load>
+__device__ __forceinline__ void block_weighted_cov(int N, const double* w, const double* m, Load load, double* out,
+                                                   double* vlds, double* tmp)
+{
+    constexpr int NE = NV * (NV + 1) / 2;
+    const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
+    for (int c0 = 0; c0 < NE; c0 += 8) {
+        int ea[8], ec[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            int t = c0 + e < NE ? c0 + e : NE - 1, r0 = 0;
+            while (t >= NV - r0) {
+                t -= NV - r0;
+                ++r0;
+            }
+            ea[e] = r0;
+            ec[e] = r0 + t;
+        }
+        double acc[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) acc[e] = 0.0;
+        for (int i = tid; i < N; i += nthr) {
+            double z[NV];
+            load(i, z);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) z[v] -= m[v];
+            const double wi = w[i];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) acc[e] += wi * z[ea[e]] * z[ec[e]];
+        }
+        block_sum_vec<8>(acc, vlds, tmp);
+        if (tid < 8 && c0 + tid < NE) {
+            out[ea[tid] * NV + ec[tid]] = tmp[tid];
+            out[ec[tid] * NV + ea[tid]] = tmp[tid];
+        }
+        __syncthreads();
+    }
+}
+
+template <int D>
 __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParams p, const uint64_t* seeds)
 {
+    constexpr int D2 = 2 * D;
     const int r = (int)blockIdx.x;
     const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
-    const int N = p.N, D = p.D, D2 = 2 * D;
+    const int N = p.N;
     const size_t base = (size_t)r * N;
     const uint32_t k = (uint32_t)(*o.k_dev);
     double* phi = o.phi + base * D;
@@ -156,9 +229,12 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
     double* rec = o.records + ((size_t)r * p.K + (k - 1)) * p.rec_len;
 
     __shared__ RedLds red;
-    __shared__ double mu[2 * DMAX], cov[4 * DMAX * DMAX], A[DMAX * DMAX], LS[DMAX * DMAX];
-    __shared__ double mth[DMAX], mph[DMAX];
+    __shared__ double vlds[OUTER_WAVES * VSUM_MAX];
+    __shared__ double mu[D2], cov[D2 * D2], A[D * D], LS[D * D], Lq[D * D], cth[D * D];
+    __shared__ double est[VSUM_MAX];
     __shared__ int fit_ok;
+    for (int e = tid; e < D * D; e += nthr) Lq[e] = p.lrw[e];
+    __syncthreads();
 
     // ---------------- approximately optimal L-kernel (k > 1)
     bool ratio_only = (p.lkernel == L_FORWARD);
@@ -172,34 +248,44 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
         for (int i = tid; i < N; i += nthr) s0 += exp(logw[i] - M0);
         block_sum3(s0, z0, z1, &red);
         const double W0 = M0 + log(s0);
-        for (int i = tid; i < N; i += nthr) wsc[i] = exp(logw[i] - W0);
-        __syncthreads();
-        if (tid < D2) {
-            double acc = 0.0;
-            for (int i = 0; i < N; ++i) {
-                const double z = tid < D ? phi[(size_t)i * D + tid] : phin[(size_t)i * D + tid - D];
-                acc += wsc[i] * z;
+        // weighted mean of z_i = (phi_i, phi_new_i)
+        {
+            double acc[D2];
+#pragma unroll
+            for (int e = 0; e < D2; ++e) acc[e] = 0.0;
+            for (int i = tid; i < N; i += nthr) {
+                const double om = exp(logw[i] - W0);
+                wsc[i] = om;
+#pragma unroll
+                for (int e = 0; e < D; ++e) {
+                    acc[e] += om * phi[(size_t)i * D + e];
+                    acc[D + e] += om * phin[(size_t)i * D + e];
+                }
             }
-            mu[tid] = acc;
+            block_sum_vec<D2>(acc, vlds, mu);
         }
-        __syncthreads();
-        if (tid < D2 * D2) {
-            const int ea = tid / D2, ec = tid % D2;
-            double acc = 0.0;
-            for (int i = 0; i < N; ++i) {
-                const double za = (ea < D ? phi[(size_t)i * D + ea] : phin[(size_t)i * D + ea - D]) - mu[ea];
-                const double zc = (ec < D ? phi[(size_t)i * D + ec] : phin[(size_t)i * D + ec - D]) - mu[ec];
-                acc += wsc[i] * za * zc;
-            }
-            cov[ea * D2 + ec] = acc;
-        }
-        __syncthreads();
+        // weighted covariance of the joint (phi_{k-1}, phi_k)
+        block_weighted_cov<D2>(
+            N, wsc, mu,
+            [&](int i, double* z) {
+#pragma unroll
+                for (int e = 0; e < D; ++e) {
+                    z[e] = phi[(size_t)i * D + e];
+                    z[D + e] = phin[(size_t)i * D + e];
+                }
+            },
+            cov, vlds, est);
         if (tid == 0) {
-            double L22[DMAX * DMAX], S[DMAX * DMAX];
+            // numerical-rank floor: every Cholesky pivot must exceed LK_REL_FLOOR times
+            // its coordinate's raw second moment, else the population is degenerate
+            // to rounding and the fit is rejected
+            double L22[D * D], S[D * D], fl[D2];
+            for (int a2 = 0; a2 < D2; ++a2) fl[a2] = LK_REL_FLOOR * (cov[a2 * D2 + a2] + mu[a2] * mu[a2]);
             int ok = chol_lower(D, cov + D * D2 + D, D2, L22) == 0;
+            for (int a2 = 0; ok && a2 < D; ++a2) ok = L22[a2 * D + a2] * L22[a2 * D + a2] > fl[D + a2];
             if (ok) {
                 for (int rr = 0; rr < D; ++rr) {
-                    double b[DMAX];
+                    double b[D];
                     for (int c = 0; c < D; ++c) b[c] = cov[(D + c) * D2 + rr];
                     chol_solve(D, L22, b);
                     for (int c = 0; c < D; ++c) A[rr * D + c] = b[c];
@@ -211,6 +297,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
                         S[a2 * D + c] = s;
                     }
                 ok = chol_lower(D, S, D, LS) == 0;
+                for (int a2 = 0; ok && a2 < D; ++a2) ok = LS[a2 * D + a2] * LS[a2 * D + a2] > fl[a2];
             }
             fit_ok = ok;
         }
@@ -221,8 +308,9 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
         }
     }
 
-    // ---------------- weight update
+    // ---------------- weight update (Eq. l_weights)
     uint64_t dead = 0;
+    double mloc = -INFINITY;
     for (int i = tid; i < N; i += nthr) {
         double v;
         if (k == 1) {
@@ -234,23 +322,29 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
             } else {
                 v = (logw[i] + pin) - (lp[i] + ll[i]);
                 if (!ratio_only) {
-                    double m[DMAX];
+                    double xo[D], xn[D], m[D];
+#pragma unroll
+                    for (int a2 = 0; a2 < D; ++a2) {
+                        xo[a2] = phi[(size_t)i * D + a2];
+                        xn[a2] = phin[(size_t)i * D + a2];
+                    }
+#pragma unroll
                     for (int a2 = 0; a2 < D; ++a2) {
                         double s = mu[a2];
-                        for (int c = 0; c < D; ++c) s += A[a2 * D + c] * (phin[(size_t)i * D + c] - mu[D + c]);
+#pragma unroll
+                        for (int c = 0; c < D; ++c) s += A[a2 * D + c] * (xn[c] - mu[D + c]);
                         m[a2] = s;
                     }
-                    const double lL = mvn_logpdf(D, phi + (size_t)i * D, m, LS, D);
-                    const double lq = mvn_logpdf(D, phin + (size_t)i * D, phi + (size_t)i * D, p.lrw, D);
+                    const double lL = mvn_logpdf<D>(xo, m, LS);
+                    const double lq = mvn_logpdf<D>(xn, xo, Lq);
                     v = v + (lL - lq);
                 }
             }
         }
         lwp[i] = v;
         dead += (v == -INFINITY);
+        mloc = v > mloc ? v : mloc;
     }
-    double mloc = -INFINITY;
-    for (int i = tid; i < N; i += nthr) mloc = lwp[i] > mloc ? lwp[i] : mloc;
     const double M = block_max<double>(mloc, &red);
     {
         double zz = 0.0;
@@ -273,7 +367,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
         return;
     }
 
-    // ---------------- normalisation, quantised weights, ESS trigger
+    // ---------------- normalisation (Eq. normalise_smc2), quantised weights, ESS
     double S = 0.0;
     uint64_t q1 = 0, q2 = 0;
     for (int i = tid; i < N; i += nthr) {
@@ -287,36 +381,39 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
     }
     block_sum3(S, q1, q2, &red);
     const double W = M + log(S);
-    double s2 = 0.0;
-    for (int i = tid; i < N; i += nthr) {
-        const double wn = exp(lwp[i] - W);
-        wsc[i] = wn;
-        s2 += wn * wn;
-    }
+    // ESS (Eq. ess_smc2) and the estimates at iteration k (Eq. realised_estimates)
     {
-        uint64_t z1 = 0, z2 = 0;
-        block_sum3(s2, z1, z2, &red);
+        double acc[2 * D + 1];
+#pragma unroll
+        for (int e = 0; e < 2 * D + 1; ++e) acc[e] = 0.0;
+        for (int i = tid; i < N; i += nthr) {
+            const double wn = exp(lwp[i] - W);
+            wsc[i] = wn;
+            acc[2 * D] += wn * wn;
+#pragma unroll
+            for (int e = 0; e < D; ++e) {
+                acc[e] += wn * thn[(size_t)i * D + e];
+                acc[D + e] += wn * phin[(size_t)i * D + e];
+            }
+        }
+        block_sum_vec<2 * D + 1>(acc, vlds, est);
     }
-    const bool rs = ess_below_half(q1, q2, N);
-
-    // ---------------- estimates at iteration k
-    if (tid < D) {
-        double acc = 0.0;
-        for (int i = 0; i < N; ++i) acc += wsc[i] * thn[(size_t)i * D + tid];
-        mth[tid] = acc;
-    } else if (tid < D2) {
-        double acc = 0.0;
-        for (int i = 0; i < N; ++i) acc += wsc[i] * phin[(size_t)i * D + tid - D];
-        mph[tid - D] = acc;
+    const double s2 = est[2 * D];
+    double mth[D], mph[D];
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+        mth[e] = est[e];
+        mph[e] = est[D + e];
     }
     __syncthreads();
-    if (tid < D * D) {
-        const int ea = tid / D, ec = tid % D;
-        double acc = 0.0;
-        for (int i = 0; i < N; ++i)
-            acc += wsc[i] * (thn[(size_t)i * D + ea] - mth[ea]) * (thn[(size_t)i * D + ec] - mth[ec]);
-        rec[6 + D + tid] = acc;
-    }
+    block_weighted_cov<D>(
+        N, wsc, mth,
+        [&](int i, double* z) {
+#pragma unroll
+            for (int e = 0; e < D; ++e) z[e] = thn[(size_t)i * D + e];
+        },
+        cth, vlds, est);
+    const bool rs = ess_below_half(q1, q2, N);
     if (tid == 0) {
         rec[0] = (double)k;
         rec[1] = 1.0 / s2;
@@ -328,10 +425,11 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
             rec[6 + a2] = mth[a2];
             rec[6 + D + D * D + a2] = mph[a2];
         }
+        for (int e = 0; e < D * D; ++e) rec[6 + D + e] = cth[e];
         o.status[r] = 0;
     }
 
-    // ---------------- resampling (Sec. IV-B) and redistribution
+    // ---------------- resampling (Sec. IV-B) and redistribution (Alg. 1)
     if (rs) {
         __syncthreads();
         const uint64_t Q = block_scan_lds(qc, N, &red);
@@ -343,6 +441,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
     __syncthreads();
     for (int m = tid; m < N; m += nthr) {
         const int s = anc[m];
+#pragma unroll
         for (int d = 0; d < D; ++d) phi[(size_t)m * D + d] = phin[(size_t)s * D + d];
         lp[m] = lpn[s];
         ll[m] = lln[s];
@@ -356,18 +455,43 @@ hipError_t launch_begin_iteration(const OuterArrays& o, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int D> static hipError_t launch_d(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds,
+                                            hipStream_t s, bool outer)
+{
+    if (outer) {
+        hipLaunchKernelGGL(k_outer<D>, dim3((unsigned)p.R), dim3(OUTER_BLOCK), 0, s, o, p, d_seeds);
+    } else {
+        const int total = p.R * p.N;
+        hipLaunchKernelGGL(k_propose<D>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, o, p, d_seeds);
+    }
+    return hipGetLastError();
+}
+
+static hipError_t dispatch(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds, hipStream_t s,
+                           bool outer)
+{
+    switch (p.D) {
+    case 1: return launch_d<1>(o, p, d_seeds, s, outer);
+    case 2: return launch_d<2>(o, p, d_seeds, s, outer);
+    case 3: return launch_d<3>(o, p, d_seeds, s, outer);
+    case 4: return launch_d<4>(o, p, d_seeds, s, outer);
+    case 5: return launch_d<5>(o, p, d_seeds, s, outer);
+    case 6: return launch_d<6>(o, p, d_seeds, s, outer);
+    case 7: return launch_d<7>(o, p, d_seeds, s, outer);
+    case 8: return launch_d<8>(o, p, d_seeds, s, outer);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_propose(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds, hipStream_t s)
 {
-    const int total = p.R * p.N;
-    hipLaunchKernelGGL(k_propose, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, o, p, d_seeds);
-    return hipGetLastError();
+    return dispatch(o, p, d_seeds, s, false);
 }
 
 hipError_t launch_outer_update(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_outer, dim3((unsigned)p.R), dim3(OUTER_BLOCK), 0, s, o, p, d_seeds);
-    return hipGetLastError();
+    return dispatch(o, p, d_seeds, s, true);
 }
 
 }  // namespace smc2

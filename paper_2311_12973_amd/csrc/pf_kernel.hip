@@ -31,9 +31,17 @@ template <typename real> struct MConst {
     real p_ei;      // 1 - exp(-sigma)
     real p_ir;      // 1 - exp(-gamma)
     real cs[4][4];  // beta s_g C_gh / N_h  (age-structured)
+    double l1p_ei;  // log1p(-min(p_ei, 1-p_ei)), log1p(-min(p_ir, 1-p_ir)) in FP64
+    double l1p_ir;
     double r;       // negative-binomial dispersion
     int32_t x0[12]; // initial compartment counts
 };
+
+template <typename real> __device__ __forceinline__ double l1p_of(real p)
+{
+    const real pp = p > (real)0.5 ? (real)1 - p : p;
+    return log1p(-(double)pp);
+}
 
 template <typename real, int MODEL>
 __device__ __forceinline__ void model_setup(const PFArgs& a, const double* th, MConst<real>& mc)
@@ -74,6 +82,8 @@ __device__ __forceinline__ void model_setup(const PFArgs& a, const double* th, M
             mc.x0[3 * g + 2] = (int32_t)i0;
         }
     }
+    mc.l1p_ei = l1p_of<real>(mc.p_ei);
+    mc.l1p_ir = l1p_of<real>(mc.p_ir);
 }
 
 // One day of the chain-binomial model for particle j, whose counts live in LDS
@@ -93,7 +103,7 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
 #pragma nounroll
         for (int b = 0; b < 2; ++b) {
             ds.b = (uint32_t)b;
-            const int32_t v = binomial<real>(b == 0 ? S : I, b == 0 ? p_si : mc.p_ir, ds);
+            const int32_t v = binomial<real>(b == 0 ? S : I, b == 0 ? p_si : mc.p_ir, ds, b == 0 ? NAN : mc.l1p_ir);
             nsi = b == 0 ? v : nsi;
             nir = b == 1 ? v : nir;
         }
@@ -110,7 +120,8 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
             ds.b = (uint32_t)b;
             const int32_t n = b == 0 ? S : (b == 1 ? E : I);
             const real p = b == 0 ? p_se : (b == 1 ? mc.p_ei : mc.p_ir);
-            const int32_t v = binomial<real>(n, p, ds);
+            const double l1p = b == 0 ? NAN : (b == 1 ? mc.l1p_ei : mc.l1p_ir);
+            const int32_t v = binomial<real>(n, p, ds, l1p);
             nse = b == 0 ? v : nse;
             nei = b == 1 ? v : nei;
             nir = b == 2 ? v : nir;
@@ -147,7 +158,8 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
                 ds.b = (uint32_t)(3 * g + b);
                 const int32_t n = b == 0 ? S : (b == 1 ? E : I);
                 const real p = b == 0 ? p_se : (b == 1 ? mc.p_ei : mc.p_ir);
-                const int32_t v = binomial<real>(n, p, ds);
+                const double l1p = b == 0 ? NAN : (b == 1 ? mc.l1p_ei : mc.l1p_ir);
+                const int32_t v = binomial<real>(n, p, ds, l1p);
                 nse = b == 0 ? v : nse;
                 nei = b == 1 ? v : nei;
                 nir = b == 2 ? v : nir;
@@ -171,7 +183,9 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
 //   tmp i32[cap]     gather staging
 //   anc i32[cap]     ancestors
 template <typename real, int MODEL, int OBS>
-__global__ void __launch_bounds__(1024) k_pf(PFArgs a)
+// 256 threads, at least 4 waves per SIMD (at most 128 VGPRs): occupancy hides the
+// latency of the FP64 transcendental sequences better than a larger register budget.
+__global__ void __launch_bounds__(256, 4) k_pf(PFArgs a)
 {
     constexpr int NC = ModelShape<MODEL>::NC;
     constexpr int NG = ModelShape<MODEL>::NG;

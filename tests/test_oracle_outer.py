@@ -236,3 +236,35 @@ def test_recycling_constants():
     rec[:, 1] = 42.0
     mean, _, c = O.recycle(rec, D)
     assert np.allclose(c, 1 / K) and mean == pytest.approx(means.mean(0), rel=1e-13)
+
+
+def test_lkernel_fit_rejects_rounding_level_spread():
+    """A population whose (phi_{k-1}) values coincide is degenerate even when the
+    weighted sums leave rounding noise in the covariance; the fit must be rejected
+    (not conditioned on that noise). So must a rank-deficient phi_{k-1} block."""
+    rng = np.random.default_rng(3)
+    N = 200
+    phi = np.full((N, 2), [0.1234567, -2.71828])
+    phi_new = phi + 0.3 * rng.normal(size=(N, 2))
+    omega = rng.random(N)
+    omega /= omega.sum()
+    st, *_ = O.lkernel_fit(phi, phi_new, omega)
+    assert st == -1
+    x = rng.normal(size=N)
+    phi = np.stack([x, 3.0 * x + 0.7], axis=1)
+    st, *_ = O.lkernel_fit(phi, phi + 0.3 * rng.normal(size=(N, 2)), omega)
+    assert st == -1
+
+
+@pytest.mark.parametrize("spread", [1e-3, 1e-4])
+def test_lkernel_fit_accepts_small_genuine_spread(spread):
+    """A narrow but genuine population (relative spread far above the floor) is fitted."""
+    rng = np.random.default_rng(4)
+    N = 300
+    phi = np.array([-11.5, 0.4]) + spread * rng.normal(size=(N, 2))
+    phi_new = phi + spread * rng.normal(size=(N, 2))
+    omega = np.full(N, 1.0 / N)
+    st, mu, A, LS = O.lkernel_fit(phi, phi_new, omega)
+    assert st == 0
+    # conditional variance of phi_{k-1} given phi_k: half the marginal for equal variances
+    assert np.allclose(np.diag(LS @ LS.T), 0.5 * spread**2, rtol=0.3)
