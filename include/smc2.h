@@ -84,6 +84,12 @@ extern "C" {
 
 #define SMC2_PROP_RW 0 /* Gaussian random walk on phi (Eq. proposal) */
 
+/* particle-filter draw schedule (smc2_config.schedule); both give identical results */
+#define SMC2_SCHED_AUTO 0     /* pooled where supported and it fits in LDS, else per draw */
+#define SMC2_SCHED_PER_DRAW 1 /* each lane finishes its draws one after another          */
+#define SMC2_SCHED_POOLED 2   /* SIR/SEIR: a wave pools its draws and runs the FP64 final
+                                 acceptance tests of the BTRS sampler 64 at a time        */
+
 #define SMC2_DMAX 8
 #define SMC2_NFIXED 32
 
@@ -93,7 +99,7 @@ typedef struct {
     int32_t model;     /* SMC2_SIR / SMC2_SEIR / SMC2_AGE_SEIR                          */
     int32_t obs;       /* SMC2_OBS_*                                                    */
     int32_t D;         /* number of parameters, 1..SMC2_DMAX (fixed by the model)       */
-    int32_t N;         /* parameter samples per run, 2..65536                           */
+    int32_t N;         /* parameter samples per run, 2..32768                           */
     int32_t K;         /* iterations, >= 1 (k = 1 is the prior importance-sampling step) */
     int32_t precision; /* SMC2_PREC_FP32 or SMC2_PREC_FP64                              */
     int32_t proposal;  /* SMC2_PROP_RW                                                  */
@@ -101,7 +107,7 @@ typedef struct {
     int32_t pf_always; /* 1: resample the particle filter at every step                 */
     int32_t use_graph; /* 1: replay each iteration as one captured HIP graph            */
     int32_t block;     /* particle-filter workgroup size override (0: tuned default)    */
-    int32_t ppt;       /* particles per thread override (0: tuned default)              */
+    int32_t schedule;  /* SMC2_SCHED_*: particle-filter draw schedule (same results)     */
     double n_pop;      /* population size, integer, 1 .. 2^24                           */
     const double* prior;  /* host, D x 3 row-major: {family, a, b} per coordinate        */
     const double* rw_cov; /* host, D x D row-major, symmetric positive definite          */

@@ -21,6 +21,7 @@ PREC_FP32, PREC_FP64 = 0, 1
 PRIOR_UNIFORM, PRIOR_LOGNORMAL, PRIOR_LOGITNORMAL, PRIOR_NORMAL = 0, 1, 2, 3
 L_FORWARD, L_GAUSS_OPT = 0, 1
 PROP_RW = 0
+SCHED_AUTO, SCHED_PER_DRAW, SCHED_POOLED = 0, 1, 2
 DUMP = dict(phi=0, lp=1, ll=2, logw=3, phi_new=4, lp_new=5, ll_new=6, logw_pre=7, anc=8)
 NFIXED = 32
 
@@ -39,7 +40,7 @@ class Config(ctypes.Structure):
     _fields_ = [("model", ctypes.c_int32), ("obs", ctypes.c_int32), ("D", ctypes.c_int32), ("N", ctypes.c_int32),
                 ("K", ctypes.c_int32), ("precision", ctypes.c_int32), ("proposal", ctypes.c_int32),
                 ("lkernel", ctypes.c_int32), ("pf_always", ctypes.c_int32), ("use_graph", ctypes.c_int32),
-                ("block", ctypes.c_int32), ("ppt", ctypes.c_int32), ("n_pop", ctypes.c_double),
+                ("block", ctypes.c_int32), ("schedule", ctypes.c_int32), ("n_pop", ctypes.c_double),
                 ("prior", ctypes.POINTER(ctypes.c_double)), ("rw_cov", ctypes.POINTER(ctypes.c_double)),
                 ("fixed", ctypes.POINTER(ctypes.c_double)), ("n_fixed", ctypes.c_int32)]
 
@@ -147,7 +148,8 @@ class _Keep:
     """Host arrays referenced by a Config / Run array (kept alive with them)."""
 
 
-def make_config(w, N=None, K=None, precision=None, use_graph=0, block=0, lkernel=None, pf_always=None):
+def make_config(w, N=None, K=None, precision=None, use_graph=0, block=0, lkernel=None, pf_always=None,
+                schedule=0):
     keep = _Keep()
     D = int(w["D"])
     keep.prior = np.ascontiguousarray(np.asarray(w["prior"], dtype=np.float64).reshape(D, 3))
@@ -163,7 +165,7 @@ def make_config(w, N=None, K=None, precision=None, use_graph=0, block=0, lkernel
     c.proposal = PROP_RW
     c.lkernel = int(lkernel if lkernel is not None else w.get("lkernel", L_GAUSS_OPT))
     c.pf_always = int(pf_always if pf_always is not None else w.get("pf_always", 0))
-    c.use_graph, c.block, c.ppt = int(use_graph), int(block), 0
+    c.use_graph, c.block, c.schedule = int(use_graph), int(block), int(schedule)
     c.n_pop = float(w["n_pop"])
     dp = ctypes.POINTER(ctypes.c_double)
     c.prior = keep.prior.ctypes.data_as(dp)
@@ -292,9 +294,9 @@ def resample_batch(q, x64, device="cuda"):
     return from_device(ta, pa, np.int32, S * n).reshape(S, n), from_device(tt, pt, np.int32, S)
 
 
-def pf_trace_state(w, theta, y, nx, seed, k, precision=None, block=0, device="cuda"):
+def pf_trace_state(w, theta, y, nx, seed, k, precision=None, block=0, device="cuda", schedule=0):
     """(ll, inc[n][T], rs[n][T], state[n][T][n_counts][nx]) for the rows of theta."""
-    cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, block=block)
+    cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, block=block, schedule=schedule)
     y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
     runs = make_runs([dict(T=y.shape[0], nx=nx, seed=seed, y=y)])
     theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
@@ -315,10 +317,12 @@ def pf_trace_state(w, theta, y, nx, seed, k, precision=None, block=0, device="cu
             from_device(tst, pst, np.int32, n * T * nc * nx).reshape(n, T, nc, nx))
 
 
-def pf_loglik(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0, device="cuda", trace=False):
+def pf_loglik(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0, device="cuda", trace=False,
+              schedule=0):
     """Particle-filter log-likelihoods for the rows of theta (natural parameters);
     with trace=True also the per-day increments and resampling flags."""
-    cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, pf_always=pf_always, block=block)
+    cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, pf_always=pf_always, block=block,
+                      schedule=schedule)
     y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
     runs = make_runs([dict(T=y.shape[0], nx=nx, seed=seed, y=y)])
     theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))

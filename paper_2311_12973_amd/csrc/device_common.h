@@ -147,50 +147,94 @@ __device__ __forceinline__ double lfact(double x)
 // p <= 1/2, n p >= 10. Constants, proposal index and squeeze in `real`; the centre
 // n p + 1/2 split in FP64 into integer and fraction; the final acceptance test in
 // FP64 on log-factorials. Attempt e uses words 2(e&1), 2(e&1)+1 of call e>>1.
+// The three pieces below are shared by the per-draw sampler (binom_btrs) and the
+// particle filter's pooled schedule, which defers final tests; both take identical
+// decisions because each piece is a pure function of (n, p, k, words).
+template <typename real> struct BtrsConst {
+    real spq, bb, aa, vr, cf;
+    int64_t ci;
+};
+
+template <typename real> __device__ __forceinline__ BtrsConst<real> btrs_setup(int32_t n, real p)
+{
+    BtrsConst<real> c;
+    const real nr = (real)n;
+    const real q = (real)1 - p;
+    c.spq = rsqrt_rn<real>((nr * p) * q);
+    c.bb = (real)1.15 + (real)2.53 * c.spq;
+    c.aa = ((real)-0.0873 + (real)0.0248 * c.bb) + (real)0.01 * p;
+    c.vr = (real)0.92 - rdiv<real>((real)4.2, c.bb);
+    const double cc = (double)n * (double)p + 0.5;
+    const double cfl = floor(cc);
+    c.ci = (int64_t)cfl;
+    c.cf = (real)(cc - cfl);
+    return c;
+}
+
+enum : int { BTRS_OUT = 0, BTRS_ACCEPT = 1, BTRS_FINAL = 2 };
+
+// One attempt from the uniform words (wu, wv): the candidate k, and whether it lies
+// outside [0, n], is accepted by the squeeze, or needs the final test.
+template <typename real>
+__device__ __forceinline__ int btrs_try(const BtrsConst<real>& c, int32_t n, uint32_t wu, uint32_t wv, int64_t& k)
+{
+    const real u = (real)u24(wu) - (real)0.5;
+    const real v = (real)u24(wv);
+    const real us = (real)0.5 - (real)fabs((double)u);
+    real t = (real)2 * c.aa;
+    t = rdiv<real>(t, us);
+    t = t + c.bb;
+    t = t * u;
+    t = t + c.cf;
+    k = c.ci + (int64_t)floor((double)t);
+    if (k < 0 || k > n) return BTRS_OUT;
+    if (us >= (real)0.07 && v <= c.vr) return BTRS_ACCEPT;
+    return BTRS_FINAL;
+}
+
+// The final acceptance test of candidate k (FP64).
+template <typename real>
+__device__ __forceinline__ bool btrs_final(const BtrsConst<real>& c, int32_t n, real p, int64_t k, uint32_t wu,
+                                           uint32_t wv)
+{
+    const real u = (real)u24(wu) - (real)0.5;
+    const real v = (real)u24(wv);
+    const real us = (real)0.5 - (real)fabs((double)u);
+    const real q = (real)1 - p;
+    const double alpha = (2.83 + 5.1 / (double)c.bb) * (double)c.spq;
+    const double lpq = log((double)p / (double)q);
+    const double m = floor((double)(n + 1) * (double)p);
+    const double h = lfact(m) + lfact((double)n - m);
+    const double lhs = log((double)v * alpha / ((double)c.aa / ((double)us * (double)us) + (double)c.bb));
+    const double rhs = ((h - lfact((double)k)) - lfact((double)(n - k))) + ((double)k - m) * lpq;
+    return lhs <= rhs;
+}
+
+// the value returned when 256 attempts were all rejected: the mode
+template <typename real> __device__ __forceinline__ int32_t btrs_mode(int32_t n, real p)
+{
+    return (int32_t)floor((double)(n + 1) * (double)p);
+}
+
 template <typename real>
 __device__ __forceinline__ int32_t binom_btrs(int32_t n, real p, const DrawStream& s)
 {
-    const real nr = (real)n;
-    const real q = (real)1 - p;
-    const real spq = rsqrt_rn<real>((nr * p) * q);
-    const real bb = (real)1.15 + (real)2.53 * spq;
-    const real aa = ((real)-0.0873 + (real)0.0248 * bb) + (real)0.01 * p;
-    const real vr = (real)0.92 - rdiv<real>((real)4.2, bb);
-    const double c = (double)n * (double)p + 0.5;
-    const double cfl = floor(c);
-    const int64_t ci = (int64_t)cfl;
-    const real cf = (real)(c - cfl);
+    const BtrsConst<real> c = btrs_setup<real>(n, p);
     W4 w{0u, 0u, 0u, 0u};
-    // per-draw constants of the final test, computed on the first attempt that needs them
-    bool have = false;
-    double alpha = 0.0, lpq = 0.0, m = 0.0, h = 0.0;
     for (int e = 0; e < 256; ++e) {
         if ((e & 1) == 0) w = s.call((uint32_t)(e >> 1));
         const uint32_t wu = (e & 1) ? w.z : w.x;
         const uint32_t wv = (e & 1) ? w.w : w.y;
-        const real u = (real)u24(wu) - (real)0.5;
-        const real v = (real)u24(wv);
-        const real us = (real)0.5 - (real)fabs((double)u);
-        real t = (real)2 * aa;
-        t = rdiv<real>(t, us);
-        t = t + bb;
-        t = t * u;
-        t = t + cf;
-        const int64_t k = ci + (int64_t)floor((double)t);
-        if (k < 0 || k > n) continue;
-        if (us >= (real)0.07 && v <= vr) return (int32_t)k;
-        if (!have) {
-            alpha = (2.83 + 5.1 / (double)bb) * (double)spq;
-            lpq = log((double)p / (double)q);
-            m = floor((double)(n + 1) * (double)p);
-            h = lfact(m) + lfact((double)n - m);
-            have = true;
-        }
-        const double lhs = log((double)v * alpha / ((double)aa / ((double)us * (double)us) + (double)bb));
-        const double rhs = ((h - lfact((double)k)) - lfact((double)(n - k))) + ((double)k - m) * lpq;
-        if (lhs <= rhs) return (int32_t)k;
+        int64_t k = 0;
+        const int r = btrs_try<real>(c, n, wu, wv, k);
+        // The acceptance is merged as a flag and k is returned after the branch: the
+        // form "if (quick || final(...)) return k" was miscompiled for gfx950 (the
+        // register holding k was reused inside the final test on the accepting path).
+        bool acc = r == BTRS_ACCEPT;
+        if (r == BTRS_FINAL) acc = btrs_final<real>(c, n, p, k, wu, wv);
+        if (acc) return (int32_t)k;
     }
-    return (int32_t)floor((double)(n + 1) * (double)p);
+    return btrs_mode<real>(n, p);
 }
 
 // Binomial(n, p). l1p, when not NaN, is log1p(-min(p, 1-p)) precomputed in FP64.

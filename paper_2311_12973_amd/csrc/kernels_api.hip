@@ -189,10 +189,13 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     a.n_pop = cfg->n_pop;
     for (int i = 0; i < SMC2_NFIXED; ++i) a.fx[i] = i < cfg->n_fixed ? cfg->fixed[i] : 0.0;
     const int block = cfg->block ? cfg->block : (run->n_x >= 256 ? 256 : ((run->n_x + 63) / 64) * 64);
-    const size_t lds = pf_lds_bytes(cfg->model, cfg->precision, block, run->n_x, run->T);
-    if (lds > 160 * 1024) return kfail(SMC2_E_ARG, "particle filter does not fit in LDS");
-    if (e == hipSuccess) e = pf_prepare(cfg->precision, cfg->model, cfg->obs, lds);
-    if (e == hipSuccess) e = launch_pf(cfg->precision, cfg->model, cfg->obs, block, lds, a, s);
+    if (cfg->schedule < 0 || cfg->schedule > 2) return kfail(SMC2_E_ARG, "schedule must be 0, 1 or 2");
+    const int sched = pf_pick_schedule(cfg->model, cfg->precision, block, run->n_x, run->T, cfg->schedule);
+    if (sched < 0) return kfail(SMC2_E_ARG, "the pooled schedule cannot run this model, n_x and T");
+    const size_t lds = pf_lds_bytes(cfg->model, cfg->precision, block, run->n_x, run->T, sched);
+    if (lds > PF_LDS_MAX) return kfail(SMC2_E_ARG, "particle filter does not fit in LDS");
+    if (e == hipSuccess) e = pf_prepare(cfg->precision, cfg->model, cfg->obs, sched, lds);
+    if (e == hipSuccess) e = launch_pf(cfg->precision, cfg->model, cfg->obs, sched, block, lds, a, s);
     // the host copies of rd and y must stay valid until the copies have run
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e == hipSuccess ? SMC2_OK : kfail(SMC2_E_DEVICE, hipGetErrorString(e));

@@ -38,11 +38,21 @@ struct PFArgs {
     double fx[32];          // model constants
 };
 
+// How a workgroup schedules the binomial draws of a day: every lane finishes its own
+// draws in turn, or (SIR, SEIR) the wave pools the draws and batches the FP64 final
+// acceptance tests of the BTRS sampler. Both give identical flows.
+enum : int { PF_SCHED_AUTO = 0, PF_SCHED_PER_DRAW = 1, PF_SCHED_POOLED = 2 };
+constexpr size_t PF_LDS_MAX = 160 * 1024;
+
 // Dynamic LDS bytes of one filter workgroup.
-size_t pf_lds_bytes(int model, int prec, int block, int nx, int T);
+size_t pf_lds_bytes(int model, int prec, int block, int nx, int T, int sched);
+// The schedule to run: the requested one (PF_SCHED_AUTO: pooled where supported and
+// it fits in LDS), or -1 when the pooled schedule was requested but cannot run.
+int pf_pick_schedule(int model, int prec, int block, int nx, int T, int requested);
 bool pf_supported(int model, int obs);
 // Raise the dynamic-LDS limit of the kernel when a launch needs more than 64 KiB.
-hipError_t pf_prepare(int prec, int model, int obs, size_t lds);
-hipError_t launch_pf(int prec, int model, int obs, int block, size_t lds, const PFArgs& a, hipStream_t s);
+hipError_t pf_prepare(int prec, int model, int obs, int sched, size_t lds);
+hipError_t launch_pf(int prec, int model, int obs, int sched, int block, size_t lds, const PFArgs& a,
+                     hipStream_t s);
 
 }  // namespace smc2

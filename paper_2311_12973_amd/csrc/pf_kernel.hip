@@ -174,15 +174,250 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
     }
 }
 
+// ---------------------------------------------------------------- pooled schedule
+// SIR and SEIR draw a day's flows as a per-wave work pool instead of one particle
+// after another. The flows of a day depend only on the previous day's counts, so
+// the draws of the wave's particles are independent items (particle j, draw b).
+// Every round each free lane takes the next item (inversion draws and trivial
+// cases finish at once), and every lane with a BTRS item makes one attempt. An
+// attempt that passes neither the squeeze nor the range check is retried next
+// round; one that needs the FP64 final test is appended to the wave's queue in LDS
+// and the lane moves on. When 64 tests are queued (or nothing else is left) the
+// wave runs them with all lanes busy; a rejected candidate continues with its next
+// attempt in that lane. A 64-wide wave otherwise pays for the final test whenever
+// any one lane needs it, which is nearly every round. Every attempt is a pure
+// function of its Philox coordinates, so the flows equal the per-draw schedule's.
+// Flows go to flows[b * cap + j] (the quantised-weight and gather buffers, free
+// during propagation); the counts are updated once all draws of the day are done.
+constexpr int POOL_CAP = 128;  // a flush runs at 64 entries; one round adds at most 64
+
+template <typename real> struct WavePool {
+    uint32_t id[POOL_CAP];  // j | b << 12 | flip << 15 | attempt << 16
+    int32_t n[POOL_CAP];
+    int32_t k[POOL_CAP];
+    uint32_t wu[POOL_CAP];
+    uint32_t wv[POOL_CAP];
+    real p[POOL_CAP];
+};
+
+template <typename real> __device__ __forceinline__ void pool_store(WavePool<real>* q, int s, uint32_t id,
+                                                                     int32_t n, int32_t k, uint32_t wu,
+                                                                     uint32_t wv, real p)
+{
+    q->id[s] = id;
+    q->n[s] = n;
+    q->k[s] = k;
+    q->wu[s] = wu;
+    q->wv[s] = wv;
+    q->p[s] = p;
+}
+
+__device__ __forceinline__ uint64_t lanes_below() { return __lanemask_lt(); }
+
+// Starts item (j, b): n and p from the day-start counts. Returns true with the flow
+// in res when the draw finishes without BTRS (n = 0, p in {0, 1}, inversion).
+template <typename real, int MODEL>
+__device__ __forceinline__ bool item_begin(const MConst<real>& mc, const int32_t* st, int cap, int j, int b,
+                                           const DrawStream& ds, int32_t& n, real& pp, bool& flip,
+                                           BtrsConst<real>& c, int32_t& res)
+{
+    constexpr int ND = ModelShape<MODEL>::NC;
+    n = st[b * cap + j];
+    real p;
+    double l1p;
+    if (b == 0) {
+        p = leave_prob<real>(mc.cinf * (real)st[(ND - 1) * cap + j]);
+        l1p = NAN;
+    } else if (b == ND - 1) {
+        p = mc.p_ir;
+        l1p = mc.l1p_ir;
+    } else {
+        p = mc.p_ei;
+        l1p = mc.l1p_ei;
+    }
+    if (n <= 0 || !(p > (real)0)) {
+        res = 0;
+        return true;
+    }
+    if (p >= (real)1) {
+        res = n;
+        return true;
+    }
+    flip = p > (real)0.5;
+    pp = flip ? (real)1 - p : p;
+    if ((real)n * pp < (real)10) {
+        const double lq = (l1p == l1p) ? l1p : log1p(-(double)pp);
+        const int32_t k = binom_inversion<real>(n, pp, lq, ds.call(0u).x);
+        res = flip ? n - k : k;
+        return true;
+    }
+    c = btrs_setup<real>(n, pp);
+    return false;
+}
+
+template <typename real, int MODEL>
+__device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t* flows, int cap, int nx,
+                             WavePool<real>* q, uint32_t filt, uint32_t kt, uint32_t k0, uint32_t k1)
+{
+    constexpr int ND = ModelShape<MODEL>::NC;
+    const int nthr = (int)blockDim.x;
+    const int lane = lane_id();
+    const int wbase = wave_id() * 64;
+    const int P = 64 * (cap / nthr);  // particle slots of this wave
+    const int F = ND * P;             // items of this wave (b-major: one draw type at a time)
+    const uint64_t below = lanes_below();
+    int next = 0, fq = 0;             // wave-uniform: next fresh item, queued final tests
+    bool busy = false;
+    int32_t j = 0, b = 0, n = 0, e = 0;
+    bool flip = false;
+    real pp = (real)0;
+    BtrsConst<real> c{};
+    for (;;) {
+        // 1. free lanes take the next items
+        const uint64_t freem = __ballot(!busy);
+        if (!busy) {
+            const int f = next + __popcll(freem & below);
+            if (f < F) {
+                b = f / P;
+                const int jl = f - b * P;
+                j = wbase + (jl & 63) + (jl >> 6) * nthr;
+                if (j < nx) {
+                    int32_t res;
+                    const DrawStream ds{(uint32_t)j, filt, kt, (uint32_t)b, k0, k1};
+                    if (item_begin<real, MODEL>(mc, st, cap, j, b, ds, n, pp, flip, c, res)) {
+                        flows[b * cap + j] = res;
+                    } else {
+                        busy = true;
+                        e = 0;
+                    }
+                }
+            }
+        }
+        next += __popcll(freem);
+        // 2. one BTRS attempt per busy lane
+        bool push = false;
+        int64_t kk = 0;
+        uint32_t wu = 0, wv = 0;
+        if (busy) {
+            if (e >= 256) {
+                const int32_t r = btrs_mode<real>(n, pp);
+                flows[b * cap + j] = flip ? n - r : r;
+                busy = false;
+            } else {
+                const W4 w = DrawStream{(uint32_t)j, filt, kt, (uint32_t)b, k0, k1}.call((uint32_t)(e >> 1));
+                wu = (e & 1) ? w.z : w.x;
+                wv = (e & 1) ? w.w : w.y;
+                const int r = btrs_try<real>(c, n, wu, wv, kk);
+                if (r == BTRS_ACCEPT) {
+                    flows[b * cap + j] = flip ? n - (int32_t)kk : (int32_t)kk;
+                    busy = false;
+                } else if (r == BTRS_OUT) {
+                    ++e;
+                } else {
+                    push = true;
+                    busy = false;
+                }
+            }
+        }
+        const uint64_t pushm = __ballot(push);
+        if (push)
+            pool_store<real>(q, fq + __popcll(pushm & below),
+                             (uint32_t)j | ((uint32_t)b << 12) | ((uint32_t)flip << 15) | ((uint32_t)e << 16), n,
+                             (int32_t)kk, wu, wv, pp);
+        fq += __popcll(pushm);
+        const bool more = next < F || __ballot(busy) != 0ull;
+        if (fq >= 64 || (!more && fq > 0)) {
+            // 3. final tests of the newest min(64, fq) entries, one per lane
+            const int m = fq < 64 ? fq : 64;
+            const int base = fq - m;
+            const bool mine = lane < m;
+            uint32_t id2 = 0, wu2 = 0, wv2 = 0;
+            int32_t n2 = 0, k2 = 0;
+            real p2 = (real)0;
+            if (mine) {
+                const int s = base + lane;
+                id2 = q->id[s];
+                n2 = q->n[s];
+                k2 = q->k[s];
+                wu2 = q->wu[s];
+                wv2 = q->wv[s];
+                p2 = q->p[s];
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            fq = base;
+            bool push2 = false;
+            int e2 = (int)(id2 >> 16);
+            int64_t kk2 = k2;
+            if (mine) {
+                const int j2 = (int)(id2 & 0xFFFu), b2 = (int)((id2 >> 12) & 7u);
+                const bool flip2 = ((id2 >> 15) & 1u) != 0u;
+                const BtrsConst<real> c2 = btrs_setup<real>(n2, p2);
+                int32_t res = -1;
+                if (btrs_final<real>(c2, n2, p2, kk2, wu2, wv2)) {
+                    res = k2;
+                } else {
+                    const DrawStream ds2{(uint32_t)j2, filt, kt, (uint32_t)b2, k0, k1};
+                    for (++e2;; ++e2) {
+                        if (e2 >= 256) {
+                            res = btrs_mode<real>(n2, p2);
+                            break;
+                        }
+                        const W4 w = ds2.call((uint32_t)(e2 >> 1));
+                        wu2 = (e2 & 1) ? w.z : w.x;
+                        wv2 = (e2 & 1) ? w.w : w.y;
+                        const int r = btrs_try<real>(c2, n2, wu2, wv2, kk2);
+                        if (r == BTRS_OUT) continue;
+                        if (r == BTRS_ACCEPT) res = (int32_t)kk2;
+                        else push2 = true;
+                        break;
+                    }
+                }
+                if (res >= 0) flows[b2 * cap + j2] = flip2 ? n2 - res : res;
+                id2 = (id2 & 0xFFFFu) | ((uint32_t)e2 << 16);
+            }
+            const uint64_t pm = __ballot(push2);
+            if (push2) pool_store<real>(q, fq + __popcll(pm & below), id2, n2, (int32_t)kk2, wu2, wv2, p2);
+            fq += __popcll(pm);
+        } else if (!more) {
+            break;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+}
+
+// The day's count update and the per-particle part of log g from the drawn flows.
+template <typename real, int MODEL, int OBS>
+__device__ __forceinline__ double particle_update(const MConst<real>& mc, int32_t* st, const int32_t* flows,
+                                                  int cap, int j, const int32_t* yt)
+{
+    if (MODEL == MODEL_SIR) {
+        const int32_t nsi = flows[j], nir = flows[cap + j];
+        const int32_t S = st[j], I = st[cap + j];
+        const int32_t I1 = I + nsi - nir;
+        st[j] = S - nsi;
+        st[cap + j] = I1;
+        return obs_part<OBS>(yt[0], OBS == OBS_POIS_PREV ? I1 : nsi, mc.r);
+    } else {
+        const int32_t nse = flows[j], nei = flows[cap + j], nir = flows[2 * cap + j];
+        const int32_t S = st[j], E = st[cap + j], I = st[2 * cap + j];
+        const int32_t I1 = I + nei - nir;
+        st[j] = S - nse;
+        st[cap + j] = E + nse - nei;
+        st[2 * cap + j] = I1;
+        return obs_part<OBS>(yt[0], OBS == OBS_POIS_PREV ? I1 : nei, mc.r);
+    }
+}
+
 // LDS layout of one filter (cap = particles rounded up to the block size):
 //   C   u64[cap]     quantised weights, then their inclusive scan
+//   tmp i32[cap]     gather staging
+//   anc i32[cap]     ancestors            (C, tmp, anc hold the flows while drawing)
 //   red RedLds       reduction slots
 //   cst f64[T]       per-day observation constants
 //   lw  real[cap]    log-weights (relative to the last maximum)
 //   st  i32[NC*cap]  compartment counts
-//   tmp i32[cap]     gather staging
-//   anc i32[cap]     ancestors
-template <typename real, int MODEL, int OBS>
+//   pool WavePool[blockDim / 64]   (pooled schedule only)
+template <typename real, int MODEL, int OBS, int SCHED>
 // 256 threads, at least 4 waves per SIMD (at most 128 VGPRs): occupancy hides the
 // latency of the FP64 transcendental sequences better than a larger register budget.
 __global__ void __launch_bounds__(256, 4) k_pf(PFArgs a)
@@ -207,12 +442,15 @@ __global__ void __launch_bounds__(256, 4) k_pf(PFArgs a)
 
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t* C = reinterpret_cast<uint64_t*>(smem);
-    RedLds* red = reinterpret_cast<RedLds*>(C + cap);
+    int32_t* tmp = reinterpret_cast<int32_t*>(C + cap);
+    int32_t* anc = tmp + cap;
+    int32_t* flows = reinterpret_cast<int32_t*>(C);
+    RedLds* red = reinterpret_cast<RedLds*>(anc + cap);
     double* cst = reinterpret_cast<double*>(red + 1);
     real* lw = reinterpret_cast<real*>(cst + T);
     int32_t* st = reinterpret_cast<int32_t*>(lw + cap);
-    int32_t* tmp = st + NC * cap;
-    int32_t* anc = tmp + cap;
+    WavePool<real>* pool = reinterpret_cast<WavePool<real>*>(
+        (reinterpret_cast<uintptr_t>(st + NC * cap) + 15) & ~(uintptr_t)15) + wave_id();
 
     const double* th = a.theta + (size_t)g * a.D;
     MConst<real> mc;
@@ -238,12 +476,22 @@ __global__ void __launch_bounds__(256, 4) k_pf(PFArgs a)
         const int32_t* yt = y + (size_t)(t - 1) * NG;
         // 1. propagate and weight: lw[j] <- a_j = lw_j + log g(y_t | x_t^j)
         real amax = (real)-INFINITY;
-        for (int j = tid; j < nx; j += nthr) {
-            const double lg = particle_day<real, MODEL, OBS>(
-                mc, st, cap, j, DrawStream{(uint32_t)j, filt, kt, 0u, run.k0, run.k1}, yt);
-            const real av = lw[j] + (real)lg;
-            lw[j] = av;
-            amax = av > amax ? av : amax;
+        if constexpr (SCHED == PF_SCHED_POOLED && MODEL != MODEL_AGE) {
+            draws_pooled<real, MODEL>(mc, st, flows, cap, nx, pool, filt, kt, run.k0, run.k1);
+            for (int j = tid; j < nx; j += nthr) {
+                const double lg = particle_update<real, MODEL, OBS>(mc, st, flows, cap, j, yt);
+                const real av = lw[j] + (real)lg;
+                lw[j] = av;
+                amax = av > amax ? av : amax;
+            }
+        } else {
+            for (int j = tid; j < nx; j += nthr) {
+                const double lg = particle_day<real, MODEL, OBS>(
+                    mc, st, cap, j, DrawStream{(uint32_t)j, filt, kt, 0u, run.k0, run.k1}, yt);
+                const real av = lw[j] + (real)lg;
+                lw[j] = av;
+                amax = av > amax ? av : amax;
+            }
         }
         if (a.trace_state) {
             for (int j = tid; j < nx; j += nthr)
@@ -307,44 +555,58 @@ __global__ void __launch_bounds__(256, 4) k_pf(PFArgs a)
 
 // ---------------------------------------------------------------- host side
 
-size_t pf_lds_bytes(int model, int prec, int block, int nx, int T)
+size_t pf_lds_bytes(int model, int prec, int block, int nx, int T, int sched)
 {
     const int nc = model == MODEL_SIR ? 2 : (model == MODEL_SEIR ? 3 : 12);
-    const int ng = model == MODEL_AGE ? 4 : 1;
     const size_t cap = (size_t)((nx + block - 1) / block) * block;
     const size_t rb = prec == 0 ? 4 : 8;
-    (void)ng;
-    return cap * 8 + sizeof(RedLds) + (size_t)T * 8 + cap * rb + (size_t)(nc + 2) * cap * 4;
+    size_t bytes = cap * 8 + 2 * cap * 4 + sizeof(RedLds) + (size_t)T * 8 + cap * rb + (size_t)nc * cap * 4;
+    if (sched == PF_SCHED_POOLED) {
+        const size_t pool = prec == 0 ? sizeof(WavePool<float>) : sizeof(WavePool<double>);
+        bytes = ((bytes + 15) & ~(size_t)15) + (size_t)(block / 64) * pool;
+    }
+    return bytes;
 }
 
-template <typename real, int MODEL, int OBS>
+int pf_pick_schedule(int model, int prec, int block, int nx, int T, int requested)
+{
+    const bool pooled_ok = model != MODEL_AGE && pf_lds_bytes(model, prec, block, nx, T, PF_SCHED_POOLED) <= PF_LDS_MAX;
+    if (requested == PF_SCHED_PER_DRAW) return PF_SCHED_PER_DRAW;
+    if (requested == PF_SCHED_POOLED) return pooled_ok ? PF_SCHED_POOLED : -1;
+    return pooled_ok ? PF_SCHED_POOLED : PF_SCHED_PER_DRAW;
+}
+
+template <typename real, int MODEL, int OBS, int SCHED>
 static hipError_t launch_one(int block, size_t lds, const PFArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_pf<real, MODEL, OBS>), dim3((unsigned)a.n_items), dim3((unsigned)block), lds, s, a);
+    hipLaunchKernelGGL((k_pf<real, MODEL, OBS, SCHED>), dim3((unsigned)a.n_items), dim3((unsigned)block), lds, s, a);
     return hipGetLastError();
 }
 
-template <typename real, int MODEL, int OBS> static const void* kernel_ptr()
+template <typename real, int MODEL, int OBS, int SCHED> static const void* kernel_ptr()
 {
-    return reinterpret_cast<const void*>(&k_pf<real, MODEL, OBS>);
+    return reinterpret_cast<const void*>(&k_pf<real, MODEL, OBS, SCHED>);
 }
 
-template <typename real>
+template <typename real, int SCHED>
 static hipError_t launch_model(int model, int obs, int block, size_t lds, const PFArgs& a, hipStream_t s)
 {
-    if (model == MODEL_SIR && obs == OBS_POIS_PREV) return launch_one<real, MODEL_SIR, OBS_POIS_PREV>(block, lds, a, s);
-    if (model == MODEL_SIR && obs == OBS_POIS_INC) return launch_one<real, MODEL_SIR, OBS_POIS_INC>(block, lds, a, s);
-    if (model == MODEL_SEIR && obs == OBS_NB_INC) return launch_one<real, MODEL_SEIR, OBS_NB_INC>(block, lds, a, s);
-    if (model == MODEL_AGE && obs == OBS_NB_INC) return launch_one<real, MODEL_AGE, OBS_NB_INC>(block, lds, a, s);
+    if (model == MODEL_SIR && obs == OBS_POIS_PREV)
+        return launch_one<real, MODEL_SIR, OBS_POIS_PREV, SCHED>(block, lds, a, s);
+    if (model == MODEL_SIR && obs == OBS_POIS_INC) return launch_one<real, MODEL_SIR, OBS_POIS_INC, SCHED>(block, lds, a, s);
+    if (model == MODEL_SEIR && obs == OBS_NB_INC) return launch_one<real, MODEL_SEIR, OBS_NB_INC, SCHED>(block, lds, a, s);
+    if (model == MODEL_AGE && obs == OBS_NB_INC && SCHED == PF_SCHED_PER_DRAW)
+        return launch_one<real, MODEL_AGE, OBS_NB_INC, PF_SCHED_PER_DRAW>(block, lds, a, s);
     return hipErrorInvalidValue;
 }
 
-template <typename real> static const void* kernel_of(int model, int obs)
+template <typename real, int SCHED> static const void* kernel_of(int model, int obs)
 {
-    if (model == MODEL_SIR && obs == OBS_POIS_PREV) return kernel_ptr<real, MODEL_SIR, OBS_POIS_PREV>();
-    if (model == MODEL_SIR && obs == OBS_POIS_INC) return kernel_ptr<real, MODEL_SIR, OBS_POIS_INC>();
-    if (model == MODEL_SEIR && obs == OBS_NB_INC) return kernel_ptr<real, MODEL_SEIR, OBS_NB_INC>();
-    if (model == MODEL_AGE && obs == OBS_NB_INC) return kernel_ptr<real, MODEL_AGE, OBS_NB_INC>();
+    if (model == MODEL_SIR && obs == OBS_POIS_PREV) return kernel_ptr<real, MODEL_SIR, OBS_POIS_PREV, SCHED>();
+    if (model == MODEL_SIR && obs == OBS_POIS_INC) return kernel_ptr<real, MODEL_SIR, OBS_POIS_INC, SCHED>();
+    if (model == MODEL_SEIR && obs == OBS_NB_INC) return kernel_ptr<real, MODEL_SEIR, OBS_NB_INC, SCHED>();
+    if (model == MODEL_AGE && obs == OBS_NB_INC && SCHED == PF_SCHED_PER_DRAW)
+        return kernel_ptr<real, MODEL_AGE, OBS_NB_INC, PF_SCHED_PER_DRAW>();
     return nullptr;
 }
 
@@ -354,19 +616,30 @@ bool pf_supported(int model, int obs)
            (model == MODEL_SEIR && obs == OBS_NB_INC) || (model == MODEL_AGE && obs == OBS_NB_INC);
 }
 
-hipError_t pf_prepare(int prec, int model, int obs, size_t lds)
+static const void* kernel_for(int prec, int model, int obs, int sched)
 {
-    const void* f = prec == 0 ? kernel_of<float>(model, obs) : kernel_of<double>(model, obs);
+    if (sched == PF_SCHED_POOLED)
+        return prec == 0 ? kernel_of<float, PF_SCHED_POOLED>(model, obs) : kernel_of<double, PF_SCHED_POOLED>(model, obs);
+    return prec == 0 ? kernel_of<float, PF_SCHED_PER_DRAW>(model, obs) : kernel_of<double, PF_SCHED_PER_DRAW>(model, obs);
+}
+
+hipError_t pf_prepare(int prec, int model, int obs, int sched, size_t lds)
+{
+    const void* f = kernel_for(prec, model, obs, sched);
     if (!f) return hipErrorInvalidValue;
     if (lds <= 65536) return hipSuccess;
     return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
-hipError_t launch_pf(int prec, int model, int obs, int block, size_t lds, const PFArgs& a, hipStream_t s)
+hipError_t launch_pf(int prec, int model, int obs, int sched, int block, size_t lds, const PFArgs& a, hipStream_t s)
 {
     if (a.n_items <= 0) return hipSuccess;
-    if (prec == 0) return launch_model<float>(model, obs, block, lds, a, s);
-    return launch_model<double>(model, obs, block, lds, a, s);
+    if (sched == PF_SCHED_POOLED) {
+        if (prec == 0) return launch_model<float, PF_SCHED_POOLED>(model, obs, block, lds, a, s);
+        return launch_model<double, PF_SCHED_POOLED>(model, obs, block, lds, a, s);
+    }
+    if (prec == 0) return launch_model<float, PF_SCHED_PER_DRAW>(model, obs, block, lds, a, s);
+    return launch_model<double, PF_SCHED_PER_DRAW>(model, obs, block, lds, a, s);
 }
 
 }  // namespace smc2

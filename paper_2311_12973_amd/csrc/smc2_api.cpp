@@ -99,6 +99,7 @@ struct PFGroup {
     int block;
     size_t lds;
     int first_item, n_items;
+    int sched;  // PF_SCHED_PER_DRAW or PF_SCHED_POOLED
 };
 
 }  // namespace
@@ -159,6 +160,9 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
         return m = "n_pop must be an integer in [1, 2^24]", SMC2_E_ARG;
     if (c->block != 0 && (c->block < 64 || c->block > 256 || c->block % 64 != 0))
         return m = "block must be 0 or a multiple of 64 up to 256", SMC2_E_ARG;
+    if (c->schedule < 0 || c->schedule > 2) return m = "schedule must be 0, 1 or 2", SMC2_E_ARG;
+    if (c->schedule == 2 && c->model == SMC2_AGE_SEIR)
+        return m = "the pooled schedule supports SIR and SEIR only", SMC2_E_UNSUPPORTED;
     if (!c->prior || !c->rw_cov) return m = "prior and rw_cov are required", SMC2_E_ARG;
     if (c->n_fixed < 0 || c->n_fixed > SMC2_NFIXED || (c->n_fixed > 0 && !c->fixed))
         return m = "bad fixed constants", SMC2_E_ARG;
@@ -264,21 +268,32 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     });
     for (size_t idx = 0; idx < run_order.size();) {
         const int b = blk[run_order[idx]];
-        PFGroup gr{b, 0, (int)items.size(), 0};
+        PFGroup gr{b, 0, (int)items.size(), 0, PF_SCHED_POOLED};
+        const size_t g0 = idx;
+        // the pooled schedule when every run of the group fits in LDS with it
+        for (size_t x = g0; x < run_order.size() && blk[run_order[x]] == b; ++x) {
+            const int r = run_order[x];
+            const int sc = pf_pick_schedule(cfg->model, cfg->precision, b, runs[r].n_x, runs[r].T, cfg->schedule);
+            if (sc < 0) {
+                delete c;
+                return g_thread_error = "the pooled schedule does not fit in LDS for this n_x and T", SMC2_E_ARG;
+            }
+            if (sc == PF_SCHED_PER_DRAW) gr.sched = PF_SCHED_PER_DRAW;
+        }
         for (; idx < run_order.size() && blk[run_order[idx]] == b; ++idx) {
             const int r = run_order[idx];
             for (size_t i = 0; i < N; ++i) items.push_back((int32_t)(r * N + i));
-            gr.lds = std::max(gr.lds, pf_lds_bytes(cfg->model, cfg->precision, b, runs[r].n_x, runs[r].T));
+            gr.lds = std::max(gr.lds, pf_lds_bytes(cfg->model, cfg->precision, b, runs[r].n_x, runs[r].T, gr.sched));
         }
         gr.n_items = (int)items.size() - gr.first_item;
         c->groups.push_back(gr);
     }
     for (const PFGroup& gr : c->groups) {
-        if (gr.lds > 160 * 1024) {
+        if (gr.lds > PF_LDS_MAX) {
             delete c;
             return g_thread_error = "particle filter does not fit in LDS (n_x or T too large)", SMC2_E_ARG;
         }
-        const hipError_t e = pf_prepare(cfg->precision, cfg->model, cfg->obs, gr.lds);
+        const hipError_t e = pf_prepare(cfg->precision, cfg->model, cfg->obs, gr.sched, gr.lds);
         if (e != hipSuccess) {
             const int rc = c->device_fail(e, "pf_prepare");
             g_thread_error = c->err;
@@ -372,7 +387,7 @@ static hipError_t enqueue_iteration(smc2_ctx* c, hipStream_t s, hipEvent_t pf0, 
         PFArgs a = c->pa;
         a.items = c->pa.items + gr.first_item;
         a.n_items = gr.n_items;
-        e = launch_pf(c->cfg.precision, c->cfg.model, c->cfg.obs, gr.block, gr.lds, a, s);
+        e = launch_pf(c->cfg.precision, c->cfg.model, c->cfg.obs, gr.sched, gr.block, gr.lds, a, s);
     }
     if (e == hipSuccess && pf1) e = hipEventRecord(pf1, s);
     if (e == hipSuccess) e = launch_outer_update(c->oa, c->op, c->d_seeds, s);

@@ -42,7 +42,8 @@ def test_workspace_bytes_and_validation():
     cfg = G.make_config(w)
     nb = L.smc2_workspace_bytes(ctypes.byref(cfg), 1, runs)
     assert 3 * 1024 * 4 * 8 < nb < 1 << 20  # O(N D) doubles: particles never leave the chip
-    bad = [dict(N=1), dict(N=40000), dict(K=0), dict(precision=3), dict(block=96), dict(block=512)]
+    bad = [dict(N=1), dict(N=40000), dict(K=0), dict(precision=3), dict(block=96), dict(block=512),
+           dict(schedule=3), dict(schedule=-1)]
     for over in bad:
         c = G.make_config(w, **over)
         assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == 0, over
@@ -53,6 +54,12 @@ def test_workspace_bytes_and_validation():
     assert b"positive definite" in L.smc2_last_error(None)
     for r in [dict(T=100, nx=0, seed=1, y=y), dict(T=0, nx=512, seed=1, y=y[:0]), dict(T=100, nx=5000, seed=1, y=y)]:
         assert L.smc2_workspace_bytes(ctypes.byref(cfg), 1, G.make_runs([r])) == 0, r
+    wa = W.preset("age_seir")
+    ya = W.observations(dict(wa, T=10))
+    ca = G.make_config(wa, schedule=G.SCHED_POOLED)
+    ra = G.make_runs([dict(T=10, nx=256, seed=1, y=ya)])
+    assert L.smc2_workspace_bytes(ctypes.byref(ca), 1, ra) == 0
+    assert b"pooled" in L.smc2_last_error(None)
     yneg = y.copy()
     yneg[3] = -1
     assert L.smc2_workspace_bytes(ctypes.byref(cfg), 1, G.make_runs([dict(T=100, nx=512, seed=1, y=yneg)])) == 0

@@ -122,10 +122,11 @@ def _pf_case(name, prec, nx, n_theta, T=None, pf_always=0, seed=11, k=2):
                                             ("paper_sir", G.PREC_FP64, 500, None), ("seir", G.PREC_FP32, 512, 60),
                                             ("seir", G.PREC_FP64, 300, 40)])
 @pytest.mark.parametrize("block", [0, 64, 128])
-def test_pf_loglik_matches_oracle(name, prec, nx, T, block):
-    _log("pf %s prec=%d nx=%d block=%d" % (name, prec, nx, block))
+@pytest.mark.parametrize("schedule", [G.SCHED_PER_DRAW, G.SCHED_POOLED])
+def test_pf_loglik_matches_oracle(name, prec, nx, T, block, schedule):
+    _log("pf %s prec=%d nx=%d block=%d schedule=%d" % (name, prec, nx, block, schedule))
     w, y, theta = _pf_case(name, prec, nx, 24, T)
-    got = G.pf_loglik(w, theta, y, nx, seed=9, k=2, precision=prec, block=block)
+    got = G.pf_loglik(w, theta, y, nx, seed=9, k=2, precision=prec, block=block, schedule=schedule)
     cfg = O.config_from_workload(w, prec=prec)
     want = np.array([O.pf_loglik(cfg, theta[i], y, nx, 9, i, 2) for i in range(len(theta))])
     fin = np.isfinite(want)
@@ -137,12 +138,13 @@ def test_pf_loglik_matches_oracle(name, prec, nx, T, block):
     assert np.mean(rel < 1e-11) >= 0.95
 
 
-def test_pf_resample_every_step_and_ragged():
+@pytest.mark.parametrize("schedule", [G.SCHED_PER_DRAW, G.SCHED_POOLED])
+def test_pf_resample_every_step_and_ragged(schedule):
     w = W.preset("sir_fp64")
     y = W.observations(w)
     theta = np.array([w["truth"]] * 10) * np.linspace(0.8, 1.2, 10)[:, None]
     for nx in [1, 7, 65, 129]:
-        got = G.pf_loglik(w, theta, y, nx, seed=4, k=1, pf_always=1)
+        got = G.pf_loglik(w, theta, y, nx, seed=4, k=1, pf_always=1, schedule=schedule)
         cfg = O.config_from_workload(w)
         cfg.pf_always = 1
         want = np.array([O.pf_loglik(cfg, theta[i], y, nx, 4, i, 1) for i in range(10)])
@@ -158,3 +160,29 @@ def test_pf_dead_filter_is_minus_inf():
     w = dict(w, fixed=[0])  # nobody infected: Poisson(I_t = 0) cannot produce y = 3
     ll = G.pf_loglik(w, np.array([[0.5, 0.2]] * 3), y, 64, seed=1, k=1)
     assert np.all(ll == -np.inf)
+
+
+@pytest.mark.parametrize("name,prec,nx,T", [("seir", G.PREC_FP32, 512, 100), ("seir", G.PREC_FP64, 512, 100),
+                                            ("paper_sir", G.PREC_FP64, 500, 30), ("sir_fp64", G.PREC_FP32, 300, 50)])
+def test_pf_schedules_identical(name, prec, nx, T):
+    """The pooled schedule (final acceptance tests batched per wave) and the per-draw
+    schedule draw identical flows, so the log-likelihoods and the per-day states agree
+    to the last bit, here at the benchmark's filter shape."""
+    _log("schedules %s prec=%d nx=%d T=%d" % (name, prec, nx, T))
+    w, y, theta = _pf_case(name, prec, nx, 64, T)
+    a = G.pf_loglik(w, theta, y, nx, seed=21, k=3, precision=prec, schedule=G.SCHED_PER_DRAW)
+    b = G.pf_loglik(w, theta, y, nx, seed=21, k=3, precision=prec, schedule=G.SCHED_POOLED)
+    assert np.array_equal(a, b)
+    sa = G.pf_trace_state(w, theta[:4], y, nx, seed=21, k=3, precision=prec, schedule=G.SCHED_PER_DRAW)
+    sb = G.pf_trace_state(w, theta[:4], y, nx, seed=21, k=3, precision=prec, schedule=G.SCHED_POOLED)
+    assert len(sa) == len(sb)
+    for xa, xb in zip(sa, sb):
+        assert np.array_equal(xa, xb)
+
+
+def test_pooled_schedule_rejected_for_age_model():
+    w = W.preset("age_seir")
+    w["T"] = 5
+    y = W.observations(w)
+    with pytest.raises(RuntimeError):
+        G.pf_loglik(w, np.array([w["truth"]] * 2), y, 64, seed=1, k=1, schedule=G.SCHED_POOLED)
