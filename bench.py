@@ -23,12 +23,30 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# VALU instructions (wave64) issued by the particle-filter kernel per particle-step
-# on this workload, from `rocprofv3 --pmc SQ_INSTS_VALU` (profiles/pf_kernel_seir_valu.txt):
-# SQ_INSTS_VALU summed over the kernel's dispatches / (N * N_x * T).
-VALU_WAVE_INSTR_PER_PSTEP = None
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 3.93e13 lane-instructions/s
+# Roofline of the particle-filter kernel (VALU-bound: counts and log-weights stay on chip).
+# Per-unit figure: VALU instructions executed by active lanes per particle-step,
+# SQ_INSTS_VALU x 64 x VALUUtilization / (N N_x T), from the rocprofv3 passes recorded in
+# profiles/pf_kernel_seir_n1024_nx512_t100.txt (default workload, pooled schedule).
+# HBM traffic per launch from the FETCH_SIZE / WRITE_SIZE passes of the same file,
+# calibrated against a 256 MiB device copy. Both hold only for the kernel sources they
+# were measured on (KERNEL_SHA); a changed kernel reports them as null.
+KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_amd/csrc/pf_kernel.h",
+                  "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h"]
+KERNEL_SHA = "c862ef5cfaf243b3"
+PROFILED_WORKLOAD = "seir"
+VALU_LANE_INSTR_PER_PSTEP = 2057.8
+HBM_BYTES_PER_LAUNCH = 1.3087e9
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 3.93e13 VALU lane-instructions/s
 VALU_PEAK_LANE_INSTR = 256 * 64 * 2.4e9
+
+
+def kernel_sha():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def main():
@@ -39,6 +57,7 @@ def main():
     ap.add_argument("--workload", default="seir")
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--schedule", type=int, default=0, help="particle-filter draw schedule (0 auto, 1 per draw, 2 pooled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before the timed region (calibrates "
@@ -66,7 +85,8 @@ def main():
     y = W.observations(w)
     N, nx, T = w["N"], w["nx"], w["T"]
     K = args.warmup + args.steps
-    s = G.Sampler(w, [dict(T=T, nx=nx, seed=w["seed"], y=y)], N=N, K=K, use_graph=args.graph, block=args.block)
+    s = G.Sampler(w, [dict(T=T, nx=nx, seed=w["seed"], y=y)], N=N, K=K, use_graph=args.graph, block=args.block,
+                  schedule=args.schedule)
     for _ in range(args.warmup):
         s.step()
     torch.cuda.synchronize()
@@ -88,15 +108,14 @@ def main():
     roofline = None
     if not args.graph:
         launch_s = ms_pf * 1e-3
-        if VALU_WAVE_INSTR_PER_PSTEP is not None:
-            achieved = VALU_WAVE_INSTR_PER_PSTEP * 64 * psteps / launch_s
-            roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_LANE_INSTR / 1e12,
-                        "unit": "T VALU lane-instr/s", "frac": achieved / VALU_PEAK_LANE_INSTR, "traffic": None,
-                        "kernel": "k_pf", "kernel_ms": ms_pf, "pf_particle_steps_per_s": psteps / launch_s}
-        else:
-            roofline = {"bound": "alu", "achieved": None, "peak": VALU_PEAK_LANE_INSTR / 1e12,
-                        "unit": "T VALU lane-instr/s", "frac": None, "traffic": None, "kernel": "k_pf",
-                        "kernel_ms": ms_pf, "pf_particle_steps_per_s": psteps / launch_s}
+        measured = kernel_sha() == KERNEL_SHA and args.workload == PROFILED_WORKLOAD and args.schedule == 0
+        achieved = VALU_LANE_INSTR_PER_PSTEP * psteps / launch_s if measured else None
+        roofline = {"bound": "alu", "achieved": achieved / 1e12 if measured else None,
+                    "peak": VALU_PEAK_LANE_INSTR / 1e12, "unit": "T VALU lane-instr/s",
+                    "frac": achieved / VALU_PEAK_LANE_INSTR if measured else None,
+                    "traffic": HBM_BYTES_PER_LAUNCH if measured else None,
+                    "kernel": "k_pf", "kernel_ms": ms_pf, "lane_instr_per_particle_step": VALU_LANE_INSTR_PER_PSTEP,
+                    "pf_particle_steps_per_s": psteps / launch_s}
 
     cpu = None
     if not args.no_cpu_baseline:
