@@ -135,12 +135,12 @@ def main():
 
 
 def cpu_baseline(w, y):
-    """The CPU reference (all host cores) on a bounded sample: N = 256 parameter
-    samples, 3 SMC^2 iterations, the same N_x, T, model and data."""
+    """The CPU reference (all host threads) on a bounded sample of the same workload:
+    the full population of N parameter samples for the first 6 SMC^2 iterations."""
     import oracle as O
 
     cfg = O.config_from_workload(w)
-    n_sample, k_sample = 256, 3
+    n_sample, k_sample = w["N"], 6
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     t = time.perf_counter()
     O.smc2_run(cfg, y, w["nx"], w["seed"], n_sample, k_sample, n_threads=threads)
