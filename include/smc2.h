@@ -106,7 +106,8 @@ typedef struct {
     int32_t lkernel;   /* SMC2_L_FORWARD or SMC2_L_GAUSS_OPT                            */
     int32_t pf_always; /* 1: resample the particle filter at every step                 */
     int32_t use_graph; /* 1: replay each iteration as one captured HIP graph            */
-    int32_t block;     /* particle-filter workgroup size override (0: tuned default)    */
+    int32_t block;     /* particle-filter workgroup size, a multiple of 64 up to 1024
+                          (0: chosen from the filter's LDS footprint)                   */
     int32_t schedule;  /* SMC2_SCHED_*: particle-filter draw schedule (same results)     */
     double n_pop;      /* population size, integer, 1 .. 2^24                           */
     const double* prior;  /* host, D x 3 row-major: {family, a, b} per coordinate        */

@@ -154,7 +154,6 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
         return kfail(SMC2_E_ARG, "T or n_x out of range");
     if (!(cfg->n_pop >= 1.0 && cfg->n_pop <= 16777216.0)) return kfail(SMC2_E_ARG, "n_pop out of range");
     if (k > 65535) return kfail(SMC2_E_ARG, "k out of range");
-    if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 256 || cfg->block % 64)) return kfail(SMC2_E_ARG, "block");
     if (n_theta < 0 || (n_theta > 0 && (!d_theta || !d_ll))) return kfail(SMC2_E_ARG, "bad theta/ll");
     if (!d_ws || ws_bytes < smc2_pf_workspace_bytes(cfg, run) || ((uintptr_t)d_ws & 255u))
         return kfail(SMC2_E_ARG, "workspace missing, too small or not 256-byte aligned");
@@ -188,7 +187,10 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     a.pf_always = cfg->pf_always;
     a.n_pop = cfg->n_pop;
     for (int i = 0; i < SMC2_NFIXED; ++i) a.fx[i] = i < cfg->n_fixed ? cfg->fixed[i] : 0.0;
-    const int block = cfg->block ? cfg->block : (run->n_x >= 256 ? 256 : ((run->n_x + 63) / 64) * 64);
+    if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64 != 0))
+        return kfail(SMC2_E_ARG, "block must be 0 or a multiple of 64 up to 1024");
+    const int block = cfg->block ? cfg->block
+                                 : pf_default_block(cfg->model, cfg->precision, run->n_x, run->T, cfg->schedule);
     if (cfg->schedule < 0 || cfg->schedule > 2) return kfail(SMC2_E_ARG, "schedule must be 0, 1 or 2");
     const int sched = pf_pick_schedule(cfg->model, cfg->precision, block, run->n_x, run->T, cfg->schedule);
     if (sched < 0) return kfail(SMC2_E_ARG, "the pooled schedule cannot run this model, n_x and T");

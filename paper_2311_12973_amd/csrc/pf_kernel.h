@@ -49,6 +49,8 @@ size_t pf_lds_bytes(int model, int prec, int block, int nx, int T, int sched);
 // The schedule to run: the requested one (PF_SCHED_AUTO: pooled where supported and
 // it fits in LDS), or -1 when the pooled schedule was requested but cannot run.
 int pf_pick_schedule(int model, int prec, int block, int nx, int T, int requested);
+// Default workgroup size for a filter of this shape (64 .. 1024 threads).
+int pf_default_block(int model, int prec, int nx, int T, int requested_sched);
 bool pf_supported(int model, int obs);
 // Raise the dynamic-LDS limit of the kernel when a launch needs more than 64 KiB.
 hipError_t pf_prepare(int prec, int model, int obs, int sched, size_t lds);

@@ -418,9 +418,11 @@ __device__ __forceinline__ double particle_update(const MConst<real>& mc, int32_
 //   st  i32[NC*cap]  compartment counts
 //   pool WavePool[blockDim / 64]   (pooled schedule only)
 template <typename real, int MODEL, int OBS, int SCHED>
-// 256 threads, at least 4 waves per SIMD (at most 128 VGPRs): occupancy hides the
-// latency of the FP64 transcendental sequences better than a larger register budget.
-__global__ void __launch_bounds__(256, 4) k_pf(PFArgs a)
+// Up to 1024 threads (16 waves) per workgroup, which caps the kernel at 128 VGPRs, i.e.
+// 4 waves per SIMD: occupancy hides the latency of the FP64 transcendental sequences
+// better than a larger register budget. Filters with a large LDS footprint run one
+// wide workgroup per CU; small ones run several 256-thread workgroups.
+__global__ void __launch_bounds__(1024) k_pf(PFArgs a)
 {
     constexpr int NC = ModelShape<MODEL>::NC;
     constexpr int NG = ModelShape<MODEL>::NG;
@@ -566,6 +568,31 @@ size_t pf_lds_bytes(int model, int prec, int block, int nx, int T, int sched)
         bytes = ((bytes + 15) & ~(size_t)15) + (size_t)(block / 64) * pool;
     }
     return bytes;
+}
+
+int pf_default_block(int model, int prec, int nx, int T, int requested_sched)
+{
+    // the workgroup size that keeps the most waves resident per CU (LDS allowing,
+    // at most 16 at 128 VGPRs), preferring the pooled schedule by its measured gain
+    const int full = ((nx + 63) / 64) * 64;
+    int best = full < 256 ? full : 256;
+    double best_score = -1.0;
+    for (int b = best; b <= 1024; b *= 2) {
+        const int sc = pf_pick_schedule(model, prec, b, nx, T, requested_sched);
+        if (sc < 0) continue;
+        const size_t lds = pf_lds_bytes(model, prec, b, nx, T, sc);
+        if (lds > PF_LDS_MAX) continue;
+        const int per_cu = (int)(PF_LDS_MAX / (lds ? lds : 1));
+        int waves = per_cu * (b / 64);
+        waves = waves > 16 ? 16 : waves;
+        const double score = waves * (sc == PF_SCHED_POOLED ? 1.4 : 1.0);
+        if (score > best_score + 1e-9) {
+            best_score = score;
+            best = b;
+        }
+        if (b >= full) break;
+    }
+    return best;
 }
 
 int pf_pick_schedule(int model, int prec, int block, int nx, int T, int requested)

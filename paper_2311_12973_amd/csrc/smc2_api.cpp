@@ -158,8 +158,8 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
     if (c->lkernel != SMC2_L_FORWARD && c->lkernel != SMC2_L_GAUSS_OPT) return m = "unknown L-kernel", SMC2_E_ARG;
     if (!(c->n_pop >= 1.0 && c->n_pop <= 16777216.0 && c->n_pop == std::floor(c->n_pop)))
         return m = "n_pop must be an integer in [1, 2^24]", SMC2_E_ARG;
-    if (c->block != 0 && (c->block < 64 || c->block > 256 || c->block % 64 != 0))
-        return m = "block must be 0 or a multiple of 64 up to 256", SMC2_E_ARG;
+    if (c->block != 0 && (c->block < 64 || c->block > 1024 || c->block % 64 != 0))
+        return m = "block must be 0 or a multiple of 64 up to 1024", SMC2_E_ARG;
     if (c->schedule < 0 || c->schedule > 2) return m = "schedule must be 0, 1 or 2", SMC2_E_ARG;
     if (c->schedule == 2 && c->model == SMC2_AGE_SEIR)
         return m = "the pooled schedule supports SIR and SEIR only", SMC2_E_UNSUPPORTED;
@@ -194,11 +194,6 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
     return SMC2_OK;
 }
 
-static int default_block(int nx)
-{
-    const int b = ((nx + 63) / 64) * 64;
-    return b < 256 ? b : 256;
-}
 
 extern "C" size_t smc2_workspace_bytes(const smc2_config* cfg, int32_t n_runs, const smc2_run* runs)
 {
@@ -259,7 +254,9 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     const size_t N = (size_t)cfg->N;
     std::vector<int32_t> items;
     std::vector<int> blk(n_runs);
-    for (int r = 0; r < n_runs; ++r) blk[r] = cfg->block ? cfg->block : default_block(runs[r].n_x);
+    for (int r = 0; r < n_runs; ++r)
+        blk[r] = cfg->block ? cfg->block
+                            : pf_default_block(cfg->model, cfg->precision, runs[r].n_x, runs[r].T, cfg->schedule);
     std::vector<int> run_order(n_runs);
     for (int r = 0; r < n_runs; ++r) run_order[r] = r;
     std::stable_sort(run_order.begin(), run_order.end(), [&](int a, int b) {

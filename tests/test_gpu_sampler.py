@@ -95,6 +95,13 @@ def test_seir_fp32_end_to_end():
     _compare(gpu, ref, 4, 1e-4, 1e-8)
 
 
+def test_age_seir_fp32_end_to_end():
+    """Four-group age-structured SEIR, FP32 propagation: N=64, N_x=192, T=50, K=3."""
+    w = dict(W.preset("age_seir"), proposal=W.PROP_RW)
+    gpu, ref, _ = _run_pair(w, 64, 3, 192, T=50)
+    _compare(gpu, ref, 8, 1e-4, 1e-8)
+
+
 def test_graph_replay_matches_direct_launches():
     w = W.preset("sir_fp64")
     a, _, _ = _run_pair(w, 64, 5, 64, use_graph=0)
@@ -196,4 +203,40 @@ def test_full_size_seir_sampled_parity():
         assert np.array_equal(anc, anc_ref)
         rec = s.records()[k - 1]
         assert np.allclose(rec, rec_ref, rtol=1e-8, atol=1e-12)
+    s.close()
+
+
+@pytest.mark.slow
+def test_full_size_age_seir_sampled_parity():
+    """The age-structured stress shape (N=16384, N_x=2048, T=365, D=8, FP32), random-walk
+    proposal: sampled filters and the outer step of two iterations against the reference."""
+    w = dict(W.preset("age_seir"), proposal=W.PROP_RW)
+    y = W.observations(w)
+    N, nx, K = w["N"], w["nx"], 2
+    s = G.Sampler(w, [dict(T=w["T"], nx=nx, seed=w["seed"], y=y)], N=N, K=K)
+    cfg = O.config_from_workload(w)
+    rng = np.random.default_rng(1)
+    for k in range(1, K + 1):
+        before = {key: s.dump(key) for key in ("phi", "lp", "ll", "logw")} if k > 1 else None
+        _log("age k=%d step" % k)
+        s.step()
+        phin, lpn, lln = s.dump("phi_new"), s.dump("lp_new"), s.dump("ll_new")
+        lwp, anc = s.dump("logw_pre"), s.dump("anc")
+        fin = np.flatnonzero(np.isfinite(lln))
+        idx = rng.choice(fin if len(fin) >= 3 else np.arange(N), size=3, replace=False)
+        for i in idx:
+            th = O.theta_of_phi(cfg, phin[i])
+            ref = O.pf_loglik(cfg, th, y, nx, w["seed"], int(i), k)
+            _log("  k=%d filter %d gpu %.10f ref %.10f" % (k, i, lln[i], ref))
+            if np.isfinite(ref):
+                assert abs(lln[i] - ref) <= 1e-4 * abs(ref)
+            else:
+                assert lln[i] == ref
+        st = dict(phi=np.zeros((N, w["D"])), lp=np.zeros(N), ll=np.zeros(N), logw=np.zeros(N)) if k == 1 else before
+        status, lwp_ref, anc_ref, rec_ref = O.outer_update(cfg, k, w["seed"], st, phin, lpn, lln)
+        assert status == 0
+        fw = np.isfinite(lwp_ref)
+        assert np.array_equal(np.isfinite(lwp), fw)
+        assert np.allclose(lwp[fw], lwp_ref[fw], rtol=1e-9, atol=1e-9)
+        assert np.array_equal(anc, anc_ref)
     s.close()
