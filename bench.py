@@ -82,11 +82,13 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     w = W.preset(args.workload)
-    y = W.observations(w)
-    N, nx, T = w["N"], w["nx"], w["T"]
+    if w.get("runs"):
+        runs = W.batched_runs(w)
+    else:
+        runs = [dict(T=w["T"], nx=w["nx"], seed=w["seed"], y=W.observations(w))]
+    N = w["N"]
     K = args.warmup + args.steps
-    s = G.Sampler(w, [dict(T=T, nx=nx, seed=w["seed"], y=y)], N=N, K=K, use_graph=args.graph, block=args.block,
-                  schedule=args.schedule)
+    s = G.Sampler(w, runs, N=N, K=K, use_graph=args.graph, block=args.block, schedule=args.schedule)
     for _ in range(args.warmup):
         s.step()
     torch.cuda.synchronize()
@@ -97,13 +99,12 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_pf, ms_step_dev, n_timed = s.timing()
-    rec = s.records()
+    dead = float(np.mean([s.records(r)[args.warmup:, 3].mean() for r in range(len(runs))]))
     s.close()
 
     ms = (t1 - t0) * 1e3 / args.steps
-    psteps = float(N) * nx * T
+    psteps = float(N) * sum(r["nx"] * r["T"] for r in runs)
     value = psteps / (ms * 1e-3)
-    dead = float(rec[args.warmup:, 3].mean())
 
     roofline = None
     if not args.graph:
@@ -119,36 +120,47 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w, y)
+        cpu = cpu_baseline(w, runs)
+    if len(runs) == 1:
+        desc = "%s N=%d Nx=%d T=%d D=%d %s propagation, FP64 outer" % (
+            args.workload, N, runs[0]["nx"], runs[0]["T"], w["D"], "FP32" if w["prec"] == 0 else "FP64")
+    else:
+        desc = "%s: %d runs, N=%d each, T in [%d, %d], Nx in %s, D=%d %s propagation, FP64 outer" % (
+            args.workload, len(runs), N, min(r["T"] for r in runs), max(r["T"] for r in runs),
+            sorted({r["nx"] for r in runs}), w["D"], "FP32" if w["prec"] == 0 else "FP64")
 
     out = {
         "metric": "PF particle-steps/s (theta x x x t), whole SMC^2 iterations",
         "value": value, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic (SEIR observations simulated from a fixed seed)",
-        "config": {"workload": "seir N=%d Nx=%d T=%d D=%d FP32 propagation, FP64 outer" % (N, nx, T, w["D"]),
-                   "N": N, "n_x": nx, "T": T, "global_batch": N, "parallelism": "single GPU",
-                   "graph": bool(args.graph), "dead_samples_per_step": dead, "device_ms_per_step": ms_step_dev},
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32" if w["prec"] == 0 else "f64",
+        "data": "synthetic (observations simulated from the model at fixed seeds)",
+        "config": {"workload": desc, "runs": len(runs), "N": N, "global_batch": N * len(runs),
+                   "particle_steps_per_iteration": psteps, "parallelism": "single GPU", "graph": bool(args.graph),
+                   "dead_samples_per_step": dead, "device_ms_per_step": ms_step_dev},
         "roofline": roofline, "cpu_baseline": cpu,
     }
     print(json.dumps(out))
 
 
-def cpu_baseline(w, y):
+def cpu_baseline(w, runs):
     """The CPU reference (all host threads) on a bounded sample of the same workload:
-    the full population of N parameter samples for the first 6 SMC^2 iterations."""
+    the full population of N parameter samples for the first SMC^2 iterations of the
+    first run(s), about ten seconds of work."""
     import oracle as O
 
     cfg = O.config_from_workload(w)
-    n_sample, k_sample = w["N"], 6
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    n_sample = w["N"]
+    k_sample = 6 if len(runs) == 1 else 2
+    sample = runs[:1] if len(runs) == 1 else runs[:8]
     t = time.perf_counter()
-    O.smc2_run(cfg, y, w["nx"], w["seed"], n_sample, k_sample, n_threads=threads)
+    for r in sample:
+        O.smc2_run(cfg, r["y"], r["nx"], r["seed"], n_sample, k_sample, n_threads=threads)
     dt = time.perf_counter() - t
-    ps = float(n_sample) * k_sample * w["nx"] * w["T"]
+    ps = float(n_sample) * k_sample * sum(r["nx"] * r["T"] for r in sample)
     return {"value": ps / dt, "unit": "particle-steps/s", "cores": threads, "kind": "oracle",
-            "sample": "N=%d samples x %d iterations of the same SEIR workload (N_x=%d, T=%d), %.1f s"
-                      % (n_sample, k_sample, w["nx"], w["T"], dt)}
+            "sample": "%d run(s) of the workload, N=%d samples x %d iterations each, %.1f s"
+                      % (len(sample), n_sample, k_sample, dt)}
 
 
 if __name__ == "__main__":

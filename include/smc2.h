@@ -114,6 +114,12 @@ typedef struct {
     const double* rw_cov; /* host, D x D row-major, symmetric positive definite          */
     const double* fixed;  /* host, n_fixed model constants (see the model codes)         */
     int32_t n_fixed;
+    int32_t tune;       /* 1: smc2_init times the candidate particle-filter launch
+                           configurations (workgroup size, draw schedule, persistent grid)
+                           of every launch group on a sample of its filters and keeps the
+                           fastest; 0: defaults from the LDS footprint. Same results.     */
+    int32_t persistent; /* with tune = 0: 1 launches a persistent grid whose workgroups
+                           pull filters from the cost-sorted work list (atomic counter)   */
 } smc2_config;
 
 typedef struct {
@@ -175,6 +181,15 @@ int smc2_timing(smc2_ctx* ctx, double* ms_pf, double* ms_step, int32_t* n_steps)
 int smc2_destroy(smc2_ctx* ctx);
 
 const char* smc2_last_error(const smc2_ctx* ctx);
+
+/* The particle-filter launch groups of a context (filters sharing a workgroup size,
+ * longest filters first) and the configuration each runs with. n_groups receives the
+ * number of groups; for g < max_groups, desc[6g .. 6g+5] = {workgroup size, draw
+ * schedule (SMC2_SCHED_PER_DRAW / SMC2_SCHED_POOLED), persistent (0/1), workgroups
+ * launched, filters, dynamic LDS bytes per workgroup}, and tuned_ms[g] (may be NULL)
+ * the time of the chosen configuration on the tuning sample (0 when not tuned).
+ * Host-only; does not touch the device. */
+int smc2_groups(const smc2_ctx* ctx, int32_t max_groups, int32_t* n_groups, int32_t* desc, float* tuned_ms);
 
 #ifdef __cplusplus
 }

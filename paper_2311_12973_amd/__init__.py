@@ -42,7 +42,8 @@ class Config(ctypes.Structure):
                 ("lkernel", ctypes.c_int32), ("pf_always", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("block", ctypes.c_int32), ("schedule", ctypes.c_int32), ("n_pop", ctypes.c_double),
                 ("prior", ctypes.POINTER(ctypes.c_double)), ("rw_cov", ctypes.POINTER(ctypes.c_double)),
-                ("fixed", ctypes.POINTER(ctypes.c_double)), ("n_fixed", ctypes.c_int32)]
+                ("fixed", ctypes.POINTER(ctypes.c_double)), ("n_fixed", ctypes.c_int32),
+                ("tune", ctypes.c_int32), ("persistent", ctypes.c_int32)]
 
 
 class Run(ctypes.Structure):
@@ -84,6 +85,8 @@ def lib():
         L.smc2_destroy.restype = c.c_int
         L.smc2_destroy.argtypes = [vp]
         L.smc2_last_error.restype = c.c_char_p
+        L.smc2_groups.restype = c.c_int
+        L.smc2_groups.argtypes = [vp, c.c_int32, P(c.c_int32), P(c.c_int32), P(c.c_float)]
         L.smc2_last_error.argtypes = [vp]
         L.smc2_philox_batch.restype = c.c_int
         L.smc2_philox_batch.argtypes = [c.c_int32, vp, c.c_uint64, vp, vp]
@@ -149,7 +152,7 @@ class _Keep:
 
 
 def make_config(w, N=None, K=None, precision=None, use_graph=0, block=0, lkernel=None, pf_always=None,
-                schedule=0):
+                schedule=0, tune=0, persistent=0):
     keep = _Keep()
     D = int(w["D"])
     keep.prior = np.ascontiguousarray(np.asarray(w["prior"], dtype=np.float64).reshape(D, 3))
@@ -166,6 +169,7 @@ def make_config(w, N=None, K=None, precision=None, use_graph=0, block=0, lkernel
     c.lkernel = int(lkernel if lkernel is not None else w.get("lkernel", L_GAUSS_OPT))
     c.pf_always = int(pf_always if pf_always is not None else w.get("pf_always", 0))
     c.use_graph, c.block, c.schedule = int(use_graph), int(block), int(schedule)
+    c.tune, c.persistent = int(tune), int(persistent)
     c.n_pop = float(w["n_pop"])
     dp = ctypes.POINTER(ctypes.c_double)
     c.prior = keep.prior.ctypes.data_as(dp)
@@ -246,6 +250,17 @@ class Sampler:
         a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
         _check(lib().smc2_timing(self.h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)), self.h)
         return a.value, b.value, n.value
+
+    def groups(self):
+        """Launch groups of the particle-filter batch and their configuration."""
+        L = lib()
+        n = ctypes.c_int32()
+        _check(L.smc2_groups(self.h, 0, ctypes.byref(n), None, None), self.h)
+        desc = (ctypes.c_int32 * (6 * max(n.value, 1)))()
+        ms = (ctypes.c_float * max(n.value, 1))()
+        _check(L.smc2_groups(self.h, n.value, ctypes.byref(n), desc, ms), self.h)
+        keys = ("block", "schedule", "persistent", "grid", "filters", "lds")
+        return [dict(zip(keys, desc[6 * g:6 * g + 6]), tuned_ms=float(ms[g])) for g in range(n.value)]
 
     def close(self):
         if getattr(self, "h", None):

@@ -14,6 +14,7 @@ struct RedLds {
     uint64_t sum_a[16];
     uint64_t sum_b[16];
     uint64_t scan[16];
+    double chunk[64];  // per-64-particle partial sums (at most 4096 particles)
 };
 
 template <typename real> __device__ __forceinline__ real* red_max_slot(RedLds* r);

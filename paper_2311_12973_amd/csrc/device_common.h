@@ -287,6 +287,31 @@ template <int OBS> __device__ __forceinline__ double obs_part(int32_t y, int32_t
 }
 
 // ----------------------------------------------------------- wave / block primitives
+// Values that every thread of a workgroup computes identically (block reductions,
+// items read from LDS) live in vector registers, so the compiler cannot tell that a
+// branch on them is uniform; around workgroup barriers it may then restructure the
+// control flow per lane (a persistent work loop was split so that threads other than
+// the one that fetches the next item looped without it). Reading such a value through
+// readfirstlane makes it a scalar, and branches on it uniform.
+__device__ __forceinline__ int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ bool uniform_bool(bool v) { return __builtin_amdgcn_readfirstlane((int)v) != 0; }
+__device__ __forceinline__ float uniform_f32(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double uniform_f64(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+// true in every lane of the workgroup's first wave, as a scalar (uniform) condition
+__device__ __forceinline__ bool first_wave() { return __builtin_amdgcn_readfirstlane((int)threadIdx.x) == 0; }
+template <typename real> __device__ __forceinline__ real uniform_real(real v);
+template <> __device__ __forceinline__ float uniform_real<float>(float v) { return uniform_f32(v); }
+template <> __device__ __forceinline__ double uniform_real<double>(double v) { return uniform_f64(v); }
+
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & 63u); }
 __device__ __forceinline__ int wave_id() { return (int)(threadIdx.x >> 6); }
 

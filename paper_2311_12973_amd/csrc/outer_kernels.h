@@ -38,7 +38,7 @@ struct OuterParams {
     const double* lrw;   // [D][D] lower Cholesky factor of the RW covariance (device)
 };
 
-hipError_t launch_begin_iteration(const OuterArrays& o, hipStream_t s);
+hipError_t launch_begin_iteration(const OuterArrays& o, int32_t* queues, int n_queues, hipStream_t s);
 hipError_t launch_propose(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds, hipStream_t s);
 hipError_t launch_outer_update(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds,
                                hipStream_t s);

@@ -30,7 +30,13 @@ __device__ __forceinline__ double theta_of(int fam, double v)
     return v;
 }
 
-__global__ void k_begin(int32_t* k_dev) { *k_dev += 1; }
+// Advances the device iteration counter and zeroes the particle filter's work-list
+// counters (a kernel, so that a captured iteration holds no memset node).
+__global__ void k_begin(int32_t* k_dev, int32_t* queues, int n_queues)
+{
+    if (threadIdx.x == 0) *k_dev += 1;
+    for (int i = (int)threadIdx.x; i < n_queues; i += (int)blockDim.x) queues[i] = 0;
+}
 
 template <int D>
 __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, const uint64_t* seeds)
@@ -302,7 +308,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
             fit_ok = ok;
         }
         __syncthreads();
-        if (!fit_ok) {
+        if (!uniform_bool(fit_ok != 0)) {
             ratio_only = true;
             fallback = 1;
         }
@@ -345,7 +351,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
         dead += (v == -INFINITY);
         mloc = v > mloc ? v : mloc;
     }
-    const double M = block_max<double>(mloc, &red);
+    const double M = uniform_f64(block_max<double>(mloc, &red));
     {
         double zz = 0.0;
         uint64_t z2 = 0;
@@ -413,7 +419,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
             for (int e = 0; e < D; ++e) z[e] = thn[(size_t)i * D + e];
         },
         cth, vlds, est);
-    const bool rs = ess_below_half(q1, q2, N);
+    const bool rs = uniform_bool(ess_below_half(q1, q2, N));
     if (tid == 0) {
         rec[0] = (double)k;
         rec[1] = 1.0 / s2;
@@ -449,9 +455,9 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
     }
 }
 
-hipError_t launch_begin_iteration(const OuterArrays& o, hipStream_t s)
+hipError_t launch_begin_iteration(const OuterArrays& o, int32_t* queues, int n_queues, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, s, o.k_dev);
+    hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, o.k_dev, queues, n_queues);
     return hipGetLastError();
 }
 

@@ -28,6 +28,7 @@ struct PFArgs {
     double* trace_inc;      // [G][T] per-day likelihood increments, or NULL (diagnostics)
     int32_t* trace_rs;      // [G][T] per-day resampling flags, or NULL
     int32_t* trace_state;   // [G][T][NC][nx] per-day counts before resampling, or NULL
+    int32_t* queue;         // work-list counter (zero at launch) for a persistent grid, or NULL
     uint32_t k_const;
     int32_t n_items;
     int32_t N;              // filters per run: g = run * N + filter
@@ -42,7 +43,8 @@ struct PFArgs {
 // draws in turn, or (SIR, SEIR) the wave pools the draws and batches the FP64 final
 // acceptance tests of the BTRS sampler. Both give identical flows.
 enum : int { PF_SCHED_AUTO = 0, PF_SCHED_PER_DRAW = 1, PF_SCHED_POOLED = 2 };
-constexpr size_t PF_LDS_MAX = 160 * 1024;
+// dynamic LDS budget of one workgroup (the kernel adds a few bytes of static LDS)
+constexpr size_t PF_LDS_MAX = 160 * 1024 - 256;
 
 // Dynamic LDS bytes of one filter workgroup.
 size_t pf_lds_bytes(int model, int prec, int block, int nx, int T, int sched);
@@ -55,6 +57,8 @@ bool pf_supported(int model, int obs);
 // Raise the dynamic-LDS limit of the kernel when a launch needs more than 64 KiB.
 hipError_t pf_prepare(int prec, int model, int obs, int sched, size_t lds);
 hipError_t launch_pf(int prec, int model, int obs, int sched, int block, size_t lds, const PFArgs& a,
-                     hipStream_t s);
+                     hipStream_t s, int grid = 0);
+// Workgroups of this configuration resident per CU (for sizing a persistent grid).
+hipError_t pf_occupancy(int prec, int model, int obs, int sched, int block, size_t lds, int* per_cu);
 
 }  // namespace smc2

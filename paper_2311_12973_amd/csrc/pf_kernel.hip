@@ -15,6 +15,9 @@
 //   4. if ESS < N_x/2 (exact integer test on the quantised weights) and t < T:
 //      integer systematic resampling (LDS scan + search), gather of the counts
 //      through LDS, log-weights reset (every particle gets the mean weight).
+#include <map>
+#include <mutex>
+
 #include "block_ops.h"
 #include "pf_kernel.h"
 
@@ -189,7 +192,7 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
 // function of its Philox coordinates, so the flows equal the per-draw schedule's.
 // Flows go to flows[b * cap + j] (the quantised-weight and gather buffers, free
 // during propagation); the counts are updated once all draws of the day are done.
-constexpr int POOL_CAP = 128;  // a flush runs at 64 entries; one round adds at most 64
+constexpr int POOL_CAP = 128;  // < 64 entries remain after the flushes; one round adds at most 64
 
 template <typename real> struct WavePool {
     uint32_t id[POOL_CAP];  // j | b << 12 | flip << 15 | attempt << 16
@@ -326,7 +329,9 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
                              (int32_t)kk, wu, wv, pp);
         fq += __popcll(pushm);
         const bool more = next < F || __ballot(busy) != 0ull;
-        if (fq >= 64 || (!more && fq > 0)) {
+        // flush while a full batch is queued (so the queue holds < 64 entries before the
+        // next round adds at most 64), and everything once no new attempts remain
+        while (fq >= 64 || (!more && fq > 0)) {
             // 3. final tests of the newest min(64, fq) entries, one per lane
             const int m = fq < 64 ? fq : 64;
             const int base = fq - m;
@@ -378,9 +383,8 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
             const uint64_t pm = __ballot(push2);
             if (push2) pool_store<real>(q, fq + __popcll(pm & below), id2, n2, (int32_t)kk2, wu2, wv2, p2);
             fq += __popcll(pm);
-        } else if (!more) {
-            break;
         }
+        if (!more && fq == 0) break;
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
@@ -418,21 +422,15 @@ __device__ __forceinline__ double particle_update(const MConst<real>& mc, int32_
 //   st  i32[NC*cap]  compartment counts
 //   pool WavePool[blockDim / 64]   (pooled schedule only)
 template <typename real, int MODEL, int OBS, int SCHED>
-// Up to 1024 threads (16 waves) per workgroup, which caps the kernel at 128 VGPRs, i.e.
-// 4 waves per SIMD: occupancy hides the latency of the FP64 transcendental sequences
-// better than a larger register budget. Filters with a large LDS footprint run one
-// wide workgroup per CU; small ones run several 256-thread workgroups.
-__global__ void __launch_bounds__(1024) k_pf(PFArgs a)
+__device__ void pf_filter(const PFArgs& a, int item)
 {
     constexpr int NC = ModelShape<MODEL>::NC;
     constexpr int NG = ModelShape<MODEL>::NG;
-    const int item = (int)blockIdx.x;
-    if (item >= a.n_items) return;
     const int g = a.items ? a.items[item] : item;
     const int tid = (int)threadIdx.x;
     const int nthr = (int)blockDim.x;
     if (a.active && !a.active[g]) {
-        if (tid == 0) a.ll[g] = -INFINITY;
+        if (first_wave()) a.ll[g] = -INFINITY;
         return;
     }
     const int run_i = g / a.N;
@@ -501,10 +499,10 @@ __global__ void __launch_bounds__(1024) k_pf(PFArgs a)
                 for (int c = 0; c < NC; ++c)
                     a.trace_state[(((size_t)g * T + (t - 1)) * NC + c) * nx + j] = st[c * cap + j];
         }
-        const real m = block_max<real>(amax, red);
+        const real m = uniform_real<real>(block_max<real>(amax, red));
         if (m == (real)-INFINITY) {
             ll = -INFINITY;
-            if (a.trace_inc && tid == 0) {
+            if (a.trace_inc && first_wave()) {
                 for (int tt = t; tt <= T; ++tt) {
                     a.trace_inc[(size_t)g * T + tt - 1] = tt == t ? -INFINITY : 0.0;
                     a.trace_rs[(size_t)g * T + tt - 1] = 0;
@@ -512,27 +510,37 @@ __global__ void __launch_bounds__(1024) k_pf(PFArgs a)
             }
             break;
         }
-        // 2. normalise by the maximum; FP64 sum and quantised weights
-        double sl = 0.0;
+        // 2. normalise by the maximum; FP64 sum and quantised weights. At step s wave w
+        //    holds the 64 consecutive particles of chunk s W + w; each chunk is summed by
+        //    a wave butterfly and the chunk sums in chunk order, so the sum (and the
+        //    likelihood) does not depend on the workgroup size.
         uint64_t q1 = 0, q2 = 0;
-        for (int j = tid; j < nx; j += nthr) {
-            const real av = lw[j];
-            const double w = exp((double)av - (double)m);
-            sl += w;
-            const uint64_t q = (uint64_t)floor(w * 4294967296.0);
-            C[j] = q;
-            const uint64_t h = q >> 8;
-            q1 += h;
-            q2 += h * h;
-            lw[j] = av - m;
+        const int nwv = nthr >> 6;
+        for (int j = tid, step = 0; j < cap; j += nthr, ++step) {
+            double w = 0.0;
+            if (j < nx) {
+                const real av = lw[j];
+                w = exp((double)av - (double)m);
+                const uint64_t q = (uint64_t)floor(w * 4294967296.0);
+                C[j] = q;
+                const uint64_t h = q >> 8;
+                q1 += h;
+                q2 += h * h;
+                lw[j] = av - m;
+            }
+            const double cs = wave_sum(w);
+            if (lane_id() == 0) red->chunk[step * nwv + wave_id()] = cs;
         }
+        double sl = 0.0;
         block_sum3(sl, q1, q2, red);
+        sl = 0.0;
+        for (int c = 0; c < (cap >> 6); ++c) sl += red->chunk[c];
         const double inc = (((double)m + log(sl)) - log(s_prev)) + cst[t - 1];
         ll = ll + inc;
         s_prev = sl;
         // 3. resample when ESS < N_x / 2 (never after the last observation)
-        const bool rs = t < T && (a.pf_always || ess_below_half(q1, q2, nx));
-        if (a.trace_inc && tid == 0) {
+        const bool rs = uniform_bool(t < T && (a.pf_always || ess_below_half(q1, q2, nx)));
+        if (a.trace_inc && first_wave()) {
             a.trace_inc[(size_t)g * T + t - 1] = inc;
             a.trace_rs[(size_t)g * T + t - 1] = rs ? 1 : 0;
         }
@@ -552,7 +560,40 @@ __global__ void __launch_bounds__(1024) k_pf(PFArgs a)
             s_prev = (double)nx;
         }
     }
-    if (tid == 0) a.ll[g] = ll;
+    if (first_wave()) a.ll[g] = ll;
+}
+
+// One filter per workgroup (a.queue == NULL: filter blockIdx.x), or a persistent grid
+// whose workgroups pull the next filter of the work list from an atomic counter until
+// the list is exhausted (the list is sorted by cost, longest first).
+// Up to 1024 threads (16 waves) per workgroup, which caps the kernel at 128 VGPRs, i.e.
+// 4 waves per SIMD: occupancy hides the latency of the FP64 transcendental sequences
+// better than a larger register budget. Filters with a large LDS footprint run one
+// wide workgroup per CU; small ones run several 256-thread workgroups.
+template <typename real, int MODEL, int OBS, int SCHED>
+__global__ void __launch_bounds__(1024) k_pf(PFArgs a)
+{
+    if (!a.queue) {
+        if ((int)blockIdx.x < a.n_items) pf_filter<real, MODEL, OBS, SCHED>(a, (int)blockIdx.x);
+        return;
+    }
+    // No branch on the thread index may sit at the top or the bottom of this loop: with
+    // one, the compiler moved that lane's work outside a loop the other lanes re-entered
+    // through the barrier, and they re-read the old item forever. The first wave fetches
+    // (a scalar branch; every lane adds, only lane 0 adds one) and every lane of it stores
+    // the same value; pf_filter writes its results the same way.
+    __shared__ int next_item;
+    for (;;) {
+        if (first_wave()) {
+            const int got = atomicAdd(a.queue, lane_id() == 0 ? 1 : 0);
+            next_item = uniform_i32(got);
+        }
+        __syncthreads();
+        const int item = uniform_i32(next_item);  // scalar: the loop exit is uniform
+        __syncthreads();  // every thread has read the item before it is replaced
+        if (item >= a.n_items) break;
+        pf_filter<real, MODEL, OBS, SCHED>(a, item);
+    }
 }
 
 // ---------------------------------------------------------------- host side
@@ -604,9 +645,10 @@ int pf_pick_schedule(int model, int prec, int block, int nx, int T, int requeste
 }
 
 template <typename real, int MODEL, int OBS, int SCHED>
-static hipError_t launch_one(int block, size_t lds, const PFArgs& a, hipStream_t s)
+static hipError_t launch_one(int block, size_t lds, const PFArgs& a, hipStream_t s, int grid)
 {
-    hipLaunchKernelGGL((k_pf<real, MODEL, OBS, SCHED>), dim3((unsigned)a.n_items), dim3((unsigned)block), lds, s, a);
+    const unsigned g = (unsigned)(a.queue ? grid : a.n_items);
+    hipLaunchKernelGGL((k_pf<real, MODEL, OBS, SCHED>), dim3(g), dim3((unsigned)block), lds, s, a);
     return hipGetLastError();
 }
 
@@ -616,14 +658,16 @@ template <typename real, int MODEL, int OBS, int SCHED> static const void* kerne
 }
 
 template <typename real, int SCHED>
-static hipError_t launch_model(int model, int obs, int block, size_t lds, const PFArgs& a, hipStream_t s)
+static hipError_t launch_model(int model, int obs, int block, size_t lds, const PFArgs& a, hipStream_t s, int grid)
 {
     if (model == MODEL_SIR && obs == OBS_POIS_PREV)
-        return launch_one<real, MODEL_SIR, OBS_POIS_PREV, SCHED>(block, lds, a, s);
-    if (model == MODEL_SIR && obs == OBS_POIS_INC) return launch_one<real, MODEL_SIR, OBS_POIS_INC, SCHED>(block, lds, a, s);
-    if (model == MODEL_SEIR && obs == OBS_NB_INC) return launch_one<real, MODEL_SEIR, OBS_NB_INC, SCHED>(block, lds, a, s);
+        return launch_one<real, MODEL_SIR, OBS_POIS_PREV, SCHED>(block, lds, a, s, grid);
+    if (model == MODEL_SIR && obs == OBS_POIS_INC)
+        return launch_one<real, MODEL_SIR, OBS_POIS_INC, SCHED>(block, lds, a, s, grid);
+    if (model == MODEL_SEIR && obs == OBS_NB_INC)
+        return launch_one<real, MODEL_SEIR, OBS_NB_INC, SCHED>(block, lds, a, s, grid);
     if (model == MODEL_AGE && obs == OBS_NB_INC && SCHED == PF_SCHED_PER_DRAW)
-        return launch_one<real, MODEL_AGE, OBS_NB_INC, PF_SCHED_PER_DRAW>(block, lds, a, s);
+        return launch_one<real, MODEL_AGE, OBS_NB_INC, PF_SCHED_PER_DRAW>(block, lds, a, s, grid);
     return hipErrorInvalidValue;
 }
 
@@ -655,18 +699,39 @@ hipError_t pf_prepare(int prec, int model, int obs, int sched, size_t lds)
     const void* f = kernel_for(prec, model, obs, sched);
     if (!f) return hipErrorInvalidValue;
     if (lds <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    // the attribute belongs to the kernel, shared by every launch group and context of
+    // the process: only ever raise it to the largest size asked for
+    static std::mutex mu;
+    static std::map<const void*, size_t> raised;
+    std::lock_guard<std::mutex> lock(mu);
+    size_t& cur = raised[f];
+    if (lds <= cur) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess) cur = lds;
+    return e;
 }
 
-hipError_t launch_pf(int prec, int model, int obs, int sched, int block, size_t lds, const PFArgs& a, hipStream_t s)
+hipError_t launch_pf(int prec, int model, int obs, int sched, int block, size_t lds, const PFArgs& a, hipStream_t s,
+                     int grid)
 {
     if (a.n_items <= 0) return hipSuccess;
+    if (a.queue && grid <= 0) return hipErrorInvalidValue;
     if (sched == PF_SCHED_POOLED) {
-        if (prec == 0) return launch_model<float, PF_SCHED_POOLED>(model, obs, block, lds, a, s);
-        return launch_model<double, PF_SCHED_POOLED>(model, obs, block, lds, a, s);
+        if (prec == 0) return launch_model<float, PF_SCHED_POOLED>(model, obs, block, lds, a, s, grid);
+        return launch_model<double, PF_SCHED_POOLED>(model, obs, block, lds, a, s, grid);
     }
-    if (prec == 0) return launch_model<float, PF_SCHED_PER_DRAW>(model, obs, block, lds, a, s);
-    return launch_model<double, PF_SCHED_PER_DRAW>(model, obs, block, lds, a, s);
+    if (prec == 0) return launch_model<float, PF_SCHED_PER_DRAW>(model, obs, block, lds, a, s, grid);
+    return launch_model<double, PF_SCHED_PER_DRAW>(model, obs, block, lds, a, s, grid);
+}
+
+hipError_t pf_occupancy(int prec, int model, int obs, int sched, int block, size_t lds, int* per_cu)
+{
+    const void* f = kernel_for(prec, model, obs, sched);
+    if (!f) return hipErrorInvalidValue;
+    int n = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, f, block, lds);
+    *per_cu = n;
+    return e;
 }
 
 }  // namespace smc2

@@ -51,10 +51,14 @@ bool host_cholesky(int n, const double* A, double* L)
     return true;
 }
 
+// work-list counters in the workspace: one per launch group, plus one for tuning
+constexpr int MAX_GROUPS = 64;
+
 struct Layout {
     size_t total = 0;
     size_t off_k, off_status, off_seeds, off_runs, off_y, off_prior, off_lrw, off_phi, off_phin, off_thn, off_lp,
-        off_ll, off_logw, off_lpn, off_lln, off_lwp, off_scr, off_qc, off_anc, off_active, off_rec, off_items;
+        off_ll, off_logw, off_lpn, off_lln, off_lwp, off_scr, off_qc, off_anc, off_active, off_rec, off_items,
+        off_queues, off_tune_items;
     size_t take(size_t bytes)
     {
         const size_t o = total;
@@ -91,6 +95,8 @@ Layout make_layout(const smc2_config* c, int R, const smc2_run* runs)
     L.off_active = L.take(RN);
     L.off_rec = L.take(sizeof(double) * R * (size_t)c->K * SMC2_RECORD_LEN(c->D));
     L.off_items = L.take(sizeof(int32_t) * RN);
+    L.off_queues = L.take(sizeof(int32_t) * MAX_GROUPS);
+    L.off_tune_items = L.take(sizeof(int32_t) * RN);
     return L;
 }
 
@@ -99,7 +105,11 @@ struct PFGroup {
     int block;
     size_t lds;
     int first_item, n_items;
-    int sched;  // PF_SCHED_PER_DRAW or PF_SCHED_POOLED
+    int sched;       // PF_SCHED_PER_DRAW or PF_SCHED_POOLED
+    int persistent;  // 1: resident workgroups pull filters from the work list
+    int grid;        // workgroups launched when persistent
+    int max_nx, max_T;
+    float tuned_ms;  // time of the chosen configuration on the tuning sample (0: not tuned)
 };
 
 }  // namespace
@@ -127,6 +137,8 @@ struct smc2_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     hipStream_t cap_stream = nullptr;  // private stream used only to capture the graph
+    int n_cu = 0;
+    std::vector<int32_t> host_items;  // the work list (filter indices), grouped and cost-sorted
     std::vector<hipEvent_t> ev;  // 4 per iteration: step start, pf start, pf end, step end
     int timed_from = 0;
 
@@ -161,6 +173,8 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
     if (c->block != 0 && (c->block < 64 || c->block > 1024 || c->block % 64 != 0))
         return m = "block must be 0 or a multiple of 64 up to 1024", SMC2_E_ARG;
     if (c->schedule < 0 || c->schedule > 2) return m = "schedule must be 0, 1 or 2", SMC2_E_ARG;
+    if (c->tune < 0 || c->tune > 1) return m = "tune must be 0 or 1", SMC2_E_ARG;
+    if (c->persistent < 0 || c->persistent > 1) return m = "persistent must be 0 or 1", SMC2_E_ARG;
     if (c->schedule == 2 && c->model == SMC2_AGE_SEIR)
         return m = "the pooled schedule supports SIR and SEIR only", SMC2_E_UNSUPPORTED;
     if (!c->prior || !c->rw_cov) return m = "prior and rw_cov are required", SMC2_E_ARG;
@@ -203,6 +217,119 @@ extern "C" size_t smc2_workspace_bytes(const smc2_config* cfg, int32_t n_runs, c
         return 0;
     }
     return make_layout(cfg, n_runs, runs).total;
+}
+
+// Persistent grid of a group: every workgroup that can be resident at once, at most one
+// per filter.
+static hipError_t set_grid(smc2_ctx* c, PFGroup& gr)
+{
+    int per_cu = 0;
+    const hipError_t e = pf_occupancy(c->cfg.precision, c->cfg.model, c->cfg.obs, gr.sched, gr.block, gr.lds, &per_cu);
+    if (e != hipSuccess) return e;
+    const long cap = (long)(per_cu > 0 ? per_cu : 1) * (c->n_cu > 0 ? c->n_cu : 1);
+    gr.grid = (int)std::min<long>(cap, gr.n_items);
+    return hipSuccess;
+}
+
+// Autotuner: for every launch group, time each candidate (workgroup size, draw
+// schedule, persistent or one-filter-per-workgroup grid) on a sample of the group's
+// filters at the first iteration's parameters (prior draws) and keep the fastest.
+// Results do not depend on the choice (every draw is a function of its coordinates),
+// only the time does. Leaves the sampler state as smc2_init found it (k = 0).
+static hipError_t autotune(smc2_ctx* c)
+{
+    const smc2_config& cfg = c->cfg;
+    hipStream_t s = c->stream;
+    unsigned char* w = c->ws;
+    const int32_t one = 1;
+    hipError_t e = hipMemcpyAsync(w + c->lay.off_k, &one, sizeof(int32_t), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_propose(c->oa, c->op, c->d_seeds, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    if (e == hipSuccess) e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    int32_t* d_tune = (int32_t*)(w + c->lay.off_tune_items);
+    int32_t* d_queue = (int32_t*)(w + c->lay.off_queues) + (MAX_GROUPS - 1);
+    const std::vector<int32_t>& host_items = c->host_items;
+    for (PFGroup& gr : c->groups) {
+        if (e != hipSuccess) break;
+        // sample: about two resident waves of workgroups, strided over the cost-sorted list
+        int per_cu = 1;
+        e = pf_occupancy(cfg.precision, cfg.model, cfg.obs, gr.sched, gr.block, gr.lds, &per_cu);
+        if (e != hipSuccess) break;
+        const int S = std::min(gr.n_items, std::max(64, 2 * std::max(per_cu, 1) * std::max(c->n_cu, 1)));
+        std::vector<int32_t> sample(S);
+        for (int i = 0; i < S; ++i) sample[i] = host_items[gr.first_item + (int)((long)i * gr.n_items / S)];
+        e = hipMemcpyAsync(d_tune, sample.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice, s);
+        PFGroup best = gr;
+        float best_ms = -1.f;
+        const int full = ((gr.max_nx + 63) / 64) * 64;
+        for (int b = 64; b <= 1024 && e == hipSuccess; b *= 2) {
+            if (b > std::max(64, full)) break;
+            for (int sc = PF_SCHED_PER_DRAW; sc <= PF_SCHED_POOLED && e == hipSuccess; ++sc) {
+                if (cfg.schedule != SMC2_SCHED_AUTO && sc != cfg.schedule) continue;
+                if (sc == PF_SCHED_POOLED && cfg.model == SMC2_AGE_SEIR) continue;
+                const size_t lds = pf_lds_bytes(cfg.model, cfg.precision, b, gr.max_nx, gr.max_T, sc);
+                if (lds > PF_LDS_MAX) continue;
+                e = pf_prepare(cfg.precision, cfg.model, cfg.obs, sc, lds);
+                for (int pers = 0; pers <= 1 && e == hipSuccess; ++pers) {
+                    PFGroup cand = gr;
+                    cand.block = b;
+                    cand.sched = sc;
+                    cand.lds = lds;
+                    cand.persistent = pers;
+                    if (pers) e = set_grid(c, cand);
+                    if (e != hipSuccess) break;
+                    PFArgs a = c->pa;
+                    a.items = d_tune;
+                    a.n_items = S;
+                    a.k_dev = nullptr;
+                    a.k_const = 1;
+                    a.queue = pers ? d_queue : nullptr;
+                    int grid = pers ? std::min(cand.grid, S) : 0;
+                    float ms = -1.f;
+                    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // rep 0 warms up
+                        if (pers) e = hipMemsetAsync(d_queue, 0, sizeof(int32_t), s);
+                        if (e == hipSuccess) e = hipEventRecord(t0, s);
+                        if (e == hipSuccess) e = launch_pf(cfg.precision, cfg.model, cfg.obs, sc, b, lds, a, s, grid);
+                        if (e == hipSuccess) e = hipEventRecord(t1, s);
+                        if (e == hipSuccess) e = hipEventSynchronize(t1);
+                        float t = 0.f;
+                        if (e == hipSuccess) e = hipEventElapsedTime(&t, t0, t1);
+                        if (rep > 0 && (ms < 0.f || t < ms)) ms = t;
+                    }
+                    if (e == hipSuccess && (best_ms < 0.f || ms < best_ms)) {
+                        best_ms = ms;
+                        best = cand;
+                    }
+                }
+            }
+        }
+        if (e == hipSuccess && best_ms >= 0.f) {
+            // the chosen size must hold every run of the group
+            best.lds = 0;
+            gr = best;
+            gr.tuned_ms = best_ms;
+        }
+    }
+    // recompute the LDS of each group for all its runs under the chosen configuration
+    for (PFGroup& gr : c->groups) {
+        if (e != hipSuccess) break;
+        if (gr.lds == 0) {
+            for (int i = 0; i < gr.n_items; ++i) {
+                const int r = host_items[gr.first_item + i] / cfg.N;
+                gr.lds = std::max(gr.lds, pf_lds_bytes(cfg.model, cfg.precision, gr.block, c->runs[r].n_x,
+                                                       c->runs[r].T, gr.sched));
+            }
+            if (gr.lds > PF_LDS_MAX) return hipErrorInvalidValue;
+            e = pf_prepare(cfg.precision, cfg.model, cfg.obs, gr.sched, gr.lds);
+        }
+    }
+    if (t0) hipEventDestroy(t0);
+    if (t1) hipEventDestroy(t1);
+    if (e == hipSuccess) e = hipMemsetAsync(w + c->lay.off_k, 0, sizeof(int32_t), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e;
 }
 
 extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run* runs, void* d_workspace,
@@ -265,7 +392,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     });
     for (size_t idx = 0; idx < run_order.size();) {
         const int b = blk[run_order[idx]];
-        PFGroup gr{b, 0, (int)items.size(), 0, PF_SCHED_POOLED};
+        PFGroup gr{b, 0, (int)items.size(), 0, PF_SCHED_POOLED, cfg->persistent, 0, 0, 0, 0.f};
         const size_t g0 = idx;
         // the pooled schedule when every run of the group fits in LDS with it
         for (size_t x = g0; x < run_order.size() && blk[run_order[x]] == b; ++x) {
@@ -281,9 +408,16 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
             const int r = run_order[idx];
             for (size_t i = 0; i < N; ++i) items.push_back((int32_t)(r * N + i));
             gr.lds = std::max(gr.lds, pf_lds_bytes(cfg->model, cfg->precision, b, runs[r].n_x, runs[r].T, gr.sched));
+            gr.max_nx = std::max(gr.max_nx, runs[r].n_x);
+            gr.max_T = std::max(gr.max_T, runs[r].T);
         }
         gr.n_items = (int)items.size() - gr.first_item;
         c->groups.push_back(gr);
+    }
+    c->host_items = items;
+    if ((int)c->groups.size() > MAX_GROUPS - 1) {
+        delete c;
+        return g_thread_error = "too many distinct workgroup sizes", SMC2_E_ARG;
     }
     for (const PFGroup& gr : c->groups) {
         if (gr.lds > PF_LDS_MAX) {
@@ -359,6 +493,12 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     if (e == hipSuccess)
         e = hipMemsetAsync(w + lay.off_rec, 0, sizeof(double) * n_runs * cfg->K * SMC2_RECORD_LEN(cfg->D), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, 0);
+    if (e == hipSuccess && cfg->tune) e = autotune(c);
+    for (PFGroup& gr : c->groups) {
+        if (e != hipSuccess) break;
+        if (gr.persistent) e = set_grid(c, gr);
+    }
     if (e == hipSuccess) {
         c->ev.resize(4 * (size_t)cfg->K, nullptr);
         for (auto& ev : c->ev)
@@ -376,15 +516,18 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
 
 static hipError_t enqueue_iteration(smc2_ctx* c, hipStream_t s, hipEvent_t pf0, hipEvent_t pf1)
 {
-    hipError_t e = launch_begin_iteration(c->oa, s);
+    int32_t* queues = (int32_t*)(c->ws + c->lay.off_queues);
+    hipError_t e = launch_begin_iteration(c->oa, queues, (int)c->groups.size(), s);
     if (e == hipSuccess) e = launch_propose(c->oa, c->op, c->d_seeds, s);
     if (e == hipSuccess && pf0) e = hipEventRecord(pf0, s);
-    for (const PFGroup& gr : c->groups) {
+    for (size_t gi = 0; gi < c->groups.size(); ++gi) {
         if (e != hipSuccess) break;
+        const PFGroup& gr = c->groups[gi];
         PFArgs a = c->pa;
         a.items = c->pa.items + gr.first_item;
         a.n_items = gr.n_items;
-        e = launch_pf(c->cfg.precision, c->cfg.model, c->cfg.obs, gr.sched, gr.block, gr.lds, a, s);
+        a.queue = gr.persistent ? queues + gi : nullptr;
+        e = launch_pf(c->cfg.precision, c->cfg.model, c->cfg.obs, gr.sched, gr.block, gr.lds, a, s, gr.grid);
     }
     if (e == hipSuccess && pf1) e = hipEventRecord(pf1, s);
     if (e == hipSuccess) e = launch_outer_update(c->oa, c->op, c->d_seeds, s);
@@ -552,4 +695,23 @@ extern "C" const char* smc2_last_error(const smc2_ctx* c)
 {
     if (c) return c->err.c_str();
     return g_thread_error.c_str();
+}
+
+extern "C" int smc2_groups(const smc2_ctx* c, int32_t max_groups, int32_t* n_groups, int32_t* desc, float* tuned_ms)
+{
+    if (!c || !n_groups) return g_thread_error = "ctx or n_groups is NULL", SMC2_E_ARG;
+    *n_groups = (int32_t)c->groups.size();
+    if (max_groups < 0 || (max_groups > 0 && !desc)) return g_thread_error = "bad desc buffer", SMC2_E_ARG;
+    for (int g = 0; g < (int)c->groups.size() && g < max_groups; ++g) {
+        const PFGroup& gr = c->groups[g];
+        int32_t* d = desc + 6 * g;
+        d[0] = gr.block;
+        d[1] = gr.sched;
+        d[2] = gr.persistent;
+        d[3] = gr.persistent ? gr.grid : gr.n_items;
+        d[4] = gr.n_items;
+        d[5] = (int32_t)gr.lds;
+        if (tuned_ms) tuned_ms[g] = gr.tuned_ms;
+    }
+    return SMC2_OK;
 }

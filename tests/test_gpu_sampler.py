@@ -117,8 +117,10 @@ def test_determinism_and_tiling_invariance():
     c, _, _ = _run_pair(w, 64, 3, 200, T=40, block=256)
     for key in ("phi", "ll", "logw", "anc"):
         assert np.array_equal(a[key], b[key]), key
-    assert np.array_equal(a["anc"], c["anc"])
-    assert np.allclose(a["ll"], c["ll"], rtol=1e-13)
+    # the per-day weight sums run over fixed 64-particle chunks, so even the FP64
+    # log-likelihoods are identical for every workgroup size
+    for key in ("phi", "ll", "logw", "anc"):
+        assert np.array_equal(a[key], c[key]), key
 
 
 def test_multiple_runs_share_a_context():
@@ -240,3 +242,56 @@ def test_full_size_age_seir_sampled_parity():
         assert np.allclose(lwp[fw], lwp_ref[fw], rtol=1e-9, atol=1e-9)
         assert np.array_equal(anc, anc_ref)
     s.close()
+
+
+def _batched_dumps(w, runs, N, K, **over):
+    _log("batched config %s" % over)
+    s = G.Sampler(w, runs, N=N, K=K, **over)
+    out = dict(ll=[], logw=[], anc=[])
+    for _ in range(K):
+        s.step()
+        for key, what in (("ll", "ll_new"), ("logw", "logw_pre"), ("anc", "anc")):
+            out[key].append(np.concatenate([s.dump(what, r) for r in range(len(runs))]))
+    out = {k: np.array(v) for k, v in out.items()}
+    out["rec"] = np.array([s.records(r) for r in range(len(runs))])
+    groups = s.groups()
+    s.close()
+    return out, groups
+
+
+def test_batched_runs_identical_under_every_launch_configuration():
+    """Uneven runs (T in [30, 200], N_x in {128, ..., 1024}) in one context: one filter per
+    workgroup, a persistent grid pulling filters from the cost-sorted work list, the
+    autotuned configuration and a replayed graph of the persistent grid all give
+    identical results (every draw is a function of its counter coordinates)."""
+    w = W.preset("seir_batched")
+    runs = W.batched_runs(w, n_runs=6)
+    _log("runs: " + ", ".join("T=%d nx=%d" % (r["T"], r["nx"]) for r in runs))
+    base, g0 = _batched_dumps(w, runs, 32, 3)
+    pers, g1 = _batched_dumps(w, runs, 32, 3, persistent=1)
+    tuned, g2 = _batched_dumps(w, runs, 32, 3, tune=1)
+    graph, g3 = _batched_dumps(w, runs, 32, 3, persistent=1, use_graph=1)
+    _log("default groups %s" % g0)
+    _log("tuned groups %s" % g2)
+    assert all(g["persistent"] == 1 and 0 < g["grid"] <= g["filters"] for g in g1)
+    assert all(g["tuned_ms"] > 0 for g in g2)
+    assert sum(g["filters"] for g in g2) == 32 * len(runs)
+    for other in (pers, tuned, graph):
+        for key in ("ll", "logw", "anc", "rec"):
+            assert np.array_equal(np.nan_to_num(base[key], neginf=-1e300), np.nan_to_num(other[key], neginf=-1e300)), key
+
+
+def test_batched_matches_reference_per_run():
+    """Two uneven runs of the batched workload against the reference run by run."""
+    w = W.preset("seir_batched")
+    runs = W.batched_runs(w, n_runs=2)
+    s = G.Sampler(w, runs, N=32, K=2, persistent=1)
+    for _ in range(2):
+        s.step()
+    recs = [s.records(r) for r in range(2)]
+    s.close()
+    cfg = O.config_from_workload(w)
+    for r, run in enumerate(runs):
+        ref = O.smc2_run(cfg, run["y"], run["nx"], run["seed"], 32, 2)
+        assert np.array_equal(recs[r][:, [0, 2, 3, 4]], ref["rec"][:, [0, 2, 3, 4]])
+        assert np.allclose(recs[r][:, 6:], ref["rec"][:, 6:], rtol=1e-4, atol=1e-10)
