@@ -134,8 +134,11 @@ typedef struct {
  *   [4] L-kernel fell back to the forward kernel (0/1)   [5] log sum_i w_k^i
  *   [6 .. 6+D)            posterior mean of theta at iteration k (Eq. realised_estimates)
  *   [6+D .. 6+D+D*D)      weighted covariance of theta
- *   [6+D+D*D .. 6+2D+D*D) weighted mean of the sampler coordinates phi            */
-#define SMC2_RECORD_LEN(D) (6 + 2 * (D) + (D) * (D))
+ *   [6+D+D*D .. 6+2D+D*D) weighted mean of the sampler coordinates phi
+ *   [6+2D+D*D]            proposal used at iteration k (0 random walk, 1 learned)
+ *   [7+2D+D*D]            learned proposal trained after iteration k: held-out mean
+ *                         weighted NLL minus the random walk's (0 without training)    */
+#define SMC2_RECORD_LEN(D) (8 + 2 * (D) + (D) * (D))
 
 /* what smc2_dump copies (run r's slice, host_dst must hold the stated size) */
 #define SMC2_DUMP_PHI 0      /* N x D  doubles: population after the last step            */

@@ -29,7 +29,8 @@ class Config(ctypes.Structure):
         ("prec", ctypes.c_int32), ("pf_always", ctypes.c_int32), ("lkernel", ctypes.c_int32),
         ("proposal", ctypes.c_int32), ("n_fixed", ctypes.c_int32), ("n_pop", ctypes.c_double),
         ("prior", (ctypes.c_double * 3) * DMAX), ("rw_cov", (ctypes.c_double * DMAX) * DMAX),
-        ("fixed", ctypes.c_double * NFIXED),
+        ("fixed", ctypes.c_double * NFIXED), ("mlp_epochs", ctypes.c_int32), ("mlp_batch", ctypes.c_int32),
+        ("mlp_lr", ctypes.c_double),
     ]
 
 
@@ -91,8 +92,31 @@ def _declare(L):
     L.or_propose_rw.argtypes = [P(Config), c.c_int, c.c_uint64, c.c_uint32, P(c.c_double),
                                 P(c.c_double), P(c.c_double)]
     L.or_outer_update.restype = c.c_int
-    L.or_outer_update.argtypes = [P(Config), c.c_int, c.c_uint32, c.c_uint64] + [P(c.c_double)] * 7 + [
+    L.or_outer_update.argtypes = [P(Config), c.c_int, c.c_uint32, c.c_uint64] + [P(c.c_double)] * 8 + [
         P(c.c_double), P(c.c_int32), P(c.c_double)]
+    L.or_mlp_nout.restype = c.c_int
+    L.or_mlp_nout.argtypes = [c.c_int]
+    L.or_mlp_nparams.restype = c.c_int
+    L.or_mlp_nparams.argtypes = [c.c_int]
+    L.or_mlp_init.argtypes = [c.c_int, c.c_uint64, P(c.c_float)]
+    L.or_mlp_forward.argtypes = [c.c_int, P(c.c_float), P(c.c_double), c.c_int, P(c.c_double), P(c.c_double),
+                                 P(c.c_double)]
+    L.or_mlp_nll.restype = c.c_double
+    L.or_mlp_nll.argtypes = [c.c_int, P(c.c_double), P(c.c_double), P(c.c_double)]
+    L.or_mlp_backward.argtypes = [c.c_int, P(c.c_float), P(c.c_double), P(c.c_double), P(c.c_double),
+                                  P(c.c_double), c.c_int, P(c.c_double)]
+    L.or_adam_step.argtypes = [c.c_int, P(c.c_float), P(c.c_float), P(c.c_float), P(c.c_double), c.c_int,
+                               c.c_double]
+    L.or_mlp_perm.argtypes = [c.c_uint64, c.c_uint32, c.c_uint32, c.c_uint32, c.c_int, P(c.c_uint64),
+                              P(c.c_uint64)]
+    L.or_mlp_frame.argtypes = [c.c_int, c.c_int, P(c.c_double), P(c.c_double), P(c.c_double)]
+    L.or_mlp_train.restype = c.c_int
+    L.or_mlp_train.argtypes = [P(Config), c.c_int, P(c.c_double), P(c.c_double), c.c_uint64, c.c_uint32, c.c_int,
+                               c.c_int, c.c_double, P(c.c_float), P(c.c_float), P(c.c_float), P(c.c_int32),
+                               P(c.c_double), P(c.c_double), P(c.c_double)]
+    L.or_mlp_propose_one.restype = c.c_double
+    L.or_mlp_propose_one.argtypes = [c.c_int, P(c.c_double), P(c.c_double), c.c_uint64, c.c_uint32, c.c_int,
+                                     P(c.c_double)]
     L.or_smc2_run.restype = c.c_int
     L.or_smc2_run.argtypes = [P(Config), P(c.c_int32), c.c_int, c.c_int, c.c_uint64, c.c_int, c.c_int,
                               c.c_int, P(c.c_double), P(c.c_double), P(c.c_double), P(c.c_double),
@@ -102,8 +126,9 @@ def _declare(L):
 
 
 def make_config(model, obs, D, prec, n_pop, prior, rw_cov, fixed=(), lkernel=L_GAUSS_OPT,
-                proposal=PROP_RW, pf_always=0):
+                proposal=PROP_RW, pf_always=0, mlp_epochs=4, mlp_batch=256, mlp_lr=1e-3):
     cfg = Config()
+    cfg.mlp_epochs, cfg.mlp_batch, cfg.mlp_lr = int(mlp_epochs), int(mlp_batch), float(mlp_lr)
     cfg.model, cfg.obs, cfg.D, cfg.prec = model, obs, D, prec
     cfg.pf_always, cfg.lkernel, cfg.proposal = pf_always, lkernel, proposal
     cfg.n_pop = float(n_pop)
@@ -125,7 +150,8 @@ def config_from_workload(w, prec=None):
     """Oracle config from a workload description (paper_2311_12973_amd.workloads)."""
     return make_config(w["model"], w["obs"], w["D"], w["prec"] if prec is None else prec, w["n_pop"],
                        w["prior"], w["rw_cov"], w.get("fixed", ()), w.get("lkernel", L_GAUSS_OPT),
-                       w.get("proposal", PROP_RW), w.get("pf_always", 0))
+                       w.get("proposal", PROP_RW), w.get("pf_always", 0), w.get("mlp_epochs", 4),
+                       w.get("mlp_batch", 256), w.get("mlp_lr", 1e-3))
 
 
 def philox(ctr, key):
@@ -287,21 +313,25 @@ def propose_rw(cfg, seed, k, phi):
     return phi_new, lp_new
 
 
-def outer_update(cfg, k, seed, state, phi_new, lp_new, ll_new):
-    """state = dict(phi, lp, ll, logw) (updated in place). Returns (status, logw_pre, anc, rec)."""
+def outer_update(cfg, k, seed, state, phi_new, lp_new, ll_new, logq=None):
+    """state = dict(phi, lp, ll, logw) (updated in place); logq: log q(phi_new | phi) of a
+    learned proposal (None: the random walk). Returns (status, logw_pre, anc, rec)."""
     N = phi_new.shape[0]
     for key in ("phi", "lp", "ll", "logw"):
         state[key] = np.ascontiguousarray(state[key], dtype=np.float64)
     phi_new = np.ascontiguousarray(phi_new, dtype=np.float64)
     lp_new = np.ascontiguousarray(lp_new, dtype=np.float64)
     ll_new = np.ascontiguousarray(ll_new, dtype=np.float64)
+    if logq is not None:
+        logq = np.ascontiguousarray(logq, dtype=np.float64)
     logw_pre = np.zeros(N)
     anc = np.zeros(N, dtype=np.int32)
     rec = np.zeros(record_len(cfg.D))
     d = ctypes.c_double
     st = lib().or_outer_update(ctypes.byref(cfg), N, int(k), int(seed), _p(state["phi"], d), _p(state["lp"], d),
                                _p(state["ll"], d), _p(state["logw"], d), _p(phi_new, d), _p(lp_new, d),
-                               _p(ll_new, d), _p(logw_pre, d), _p(anc, ctypes.c_int32), _p(rec, d))
+                               _p(ll_new, d), _p(logq, d) if logq is not None else None, _p(logw_pre, d),
+                               _p(anc, ctypes.c_int32), _p(rec, d))
     return st, logw_pre, anc, rec
 
 
@@ -323,3 +353,97 @@ def smc2_run(cfg, y, nx, seed, N, K, n_threads=0, dumps=False):
     out["rec"] = rec
     out["status"] = st
     return out
+
+
+# ------------------------------------------------------------------ learned proposal
+MLP_H = 64
+
+
+def mlp_nout(D):
+    return lib().or_mlp_nout(D)
+
+
+def mlp_nparams(D):
+    return lib().or_mlp_nparams(D)
+
+
+def mlp_init(D, seed):
+    w = np.zeros(mlp_nparams(D), dtype=np.float32)
+    lib().or_mlp_init(D, int(seed), _p(w, ctypes.c_float))
+    return w
+
+
+def mlp_forward(D, w, u, bf16=True):
+    """Outputs o[P] and the hidden activations (h1, h2) of one input row u[D]."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    u = np.ascontiguousarray(u, dtype=np.float64)
+    h1, h2, o = np.zeros(MLP_H), np.zeros(MLP_H), np.zeros(mlp_nout(D))
+    d = ctypes.c_double
+    lib().or_mlp_forward(D, _p(w, ctypes.c_float), _p(u, d), int(bf16), _p(h1, d), _p(h2, d), _p(o, d))
+    return o, h1, h2
+
+
+def mlp_nll(D, o, ut, grad=False):
+    o = np.ascontiguousarray(o, dtype=np.float64)
+    ut = np.ascontiguousarray(ut, dtype=np.float64)
+    g = np.zeros(len(o)) if grad else None
+    v = lib().or_mlp_nll(D, _p(o, ctypes.c_double), _p(ut, ctypes.c_double), _p(g, ctypes.c_double) if grad else None)
+    return (v, g) if grad else v
+
+
+def mlp_backward(D, w, u, h1, h2, go, bf16=True):
+    """Parameter gradient of one row given d loss / d o."""
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    arr = [np.ascontiguousarray(x, dtype=np.float64) for x in (u, h1, h2, go)]
+    g = np.zeros(mlp_nparams(D))
+    d = ctypes.c_double
+    lib().or_mlp_backward(D, _p(w, ctypes.c_float), *[_p(x, d) for x in arr], int(bf16), _p(g, d))
+    return g
+
+
+def adam_step(p, m, v, g, t, lr):
+    """In place on float32 p, m, v."""
+    g = np.ascontiguousarray(g, dtype=np.float64)
+    lib().or_adam_step(len(p), _p(p, ctypes.c_float), _p(m, ctypes.c_float), _p(v, ctypes.c_float),
+                       _p(g, ctypes.c_double), int(t), float(lr))
+
+
+def mlp_perm(seed, k, e, which, N):
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    lib().or_mlp_perm(int(seed), int(k), int(e), int(which), int(N), ctypes.byref(a), ctypes.byref(b))
+    return a.value, b.value
+
+
+def mlp_frame(phi, wn):
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    wn = np.ascontiguousarray(wn, dtype=np.float64)
+    N, D = phi.shape
+    fr = np.zeros(2 * D)
+    lib().or_mlp_frame(N, D, _p(phi, ctypes.c_double), _p(wn, ctypes.c_double), _p(fr, ctypes.c_double))
+    return fr
+
+
+def mlp_train(cfg, phi, logw, seed, k, params, adam_m, adam_v, adam_t, epochs=None, batch=None, lr=None):
+    """One iteration's training (in place on params, adam_m, adam_v). Returns
+    (use_mlp, adam_t, frame, nll_mlp, nll_rw)."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    logw = np.ascontiguousarray(logw, dtype=np.float64)
+    N, D = phi.shape
+    t = ctypes.c_int32(adam_t)
+    fr = np.zeros(2 * D)
+    nm, nr = ctypes.c_double(), ctypes.c_double()
+    use = lib().or_mlp_train(ctypes.byref(cfg), N, _p(phi, ctypes.c_double), _p(logw, ctypes.c_double), int(seed),
+                             int(k), cfg.mlp_epochs if epochs is None else epochs,
+                             cfg.mlp_batch if batch is None else batch, cfg.mlp_lr if lr is None else lr,
+                             _p(params, ctypes.c_float), _p(adam_m, ctypes.c_float), _p(adam_v, ctypes.c_float),
+                             ctypes.byref(t), _p(fr, ctypes.c_double), ctypes.byref(nm), ctypes.byref(nr))
+    return use, t.value, fr, nm.value, nr.value
+
+
+def mlp_propose_one(D, frame, o, seed, k, i):
+    frame = np.ascontiguousarray(frame, dtype=np.float64)
+    o = np.ascontiguousarray(o, dtype=np.float64)
+    phn = np.zeros(D)
+    lq = lib().or_mlp_propose_one(D, _p(frame, ctypes.c_double), _p(o, ctypes.c_double), int(seed), int(k), int(i),
+                                  _p(phn, ctypes.c_double))
+    return phn, lq

@@ -46,7 +46,7 @@
 
 #define LOG_2PI 1.8378770664093453
 
-int or_record_len(int D) { return 6 + 2 * D + D * D; }
+int or_record_len(int D) { return 8 + 2 * D + D * D; }
 int or_n_obs(int model) { return model == OR_AGE_SEIR ? 4 : 1; }
 
 /* ------------------------------------------------------------------ random numbers */
@@ -405,6 +405,8 @@ static double logsumexp(int n, const double* v)
     return m + log(s);
 }
 
+#include "mlp.inc"
+
 /*
  * One outer update at iteration k, given the proposals phi_new with their prior
  * log-densities and particle-filter log-likelihoods:
@@ -416,12 +418,17 @@ static double logsumexp(int n, const double* v)
  * realised_estimates), l_k = (sum w)^2 / sum w^2 (Eq. recycling_I) = ESS (Eq.
  * ess_smc2), and, if ESS < N/2, systematic resampling with redistribution and reset
  * (Sec. IV-B). The state arrays (phi, lp, ll, logw) are replaced by the new
- * population. Returns 0, or -4 when every weight is zero.
+ * population. logq (may be NULL: the random walk, whose density the function
+ * evaluates) holds log q(phi_new | phi) of a learned proposal; with the forward
+ * L-kernel the proposal must be symmetric (the random walk). Records carry, after
+ * the estimates, the proposal used (0 random walk, 1 learned) and a slot for the
+ * caller (the learned proposal's held-out score). Returns 0, or -4 when every
+ * weight is zero.
  */
 int or_outer_update(const or_config* cfg, int N, uint32_t k, uint64_t seed,
                     double* phi, double* lp, double* ll, double* logw,
                     const double* phi_new, const double* lp_new, const double* ll_new,
-                    double* logw_pre, int32_t* anc, double* rec)
+                    const double* logq, double* logw_pre, int32_t* anc, double* rec)
 {
     const int D = cfg->D;
     int fallback = 0;
@@ -448,7 +455,7 @@ int or_outer_update(const or_config* cfg, int N, uint32_t k, uint64_t seed,
                         m[a] = s;
                     }
                     double lL = or_mvn_logpdf_chol(D, phi + (size_t)i * D, m, LS);
-                    double lq = or_mvn_logpdf_chol(D, phi_new + (size_t)i * D, phi + (size_t)i * D, Lq);
+                    double lq = logq ? logq[i] : or_mvn_logpdf_chol(D, phi_new + (size_t)i * D, phi + (size_t)i * D, Lq);
                     logL[i] = lL - lq;
                 }
             } else {
@@ -580,6 +587,16 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
     double* lln = (double*)calloc((size_t)N, sizeof(double));
     double* lwp = (double*)calloc((size_t)N, sizeof(double));
     int32_t* anc = (int32_t*)calloc((size_t)N, sizeof(int32_t));
+    double* lq = (double*)calloc((size_t)N, sizeof(double));
+    const int mlp = cfg->proposal == OR_PROP_MLP;
+    const int np = or_mlp_nparams(D);
+    float* params = mlp ? (float*)calloc((size_t)np, sizeof(float)) : NULL;
+    float* am = mlp ? (float*)calloc((size_t)np, sizeof(float)) : NULL;
+    float* av = mlp ? (float*)calloc((size_t)np, sizeof(float)) : NULL;
+    int32_t adam_t = 0;
+    double frame[2 * OR_DMAX];
+    int use_mlp = 0;
+    if (mlp) or_mlp_init(D, seed, params);
     int status = 0;
 #ifdef _OPENMP
     if (n_threads > 0) omp_set_num_threads(n_threads);
@@ -587,8 +604,20 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
     (void)n_threads;
 #endif
     for (int k = 1; k <= K; ++k) {
-        if (k == 1) or_prior_draw(cfg, N, seed, phin, lpn);
-        else or_propose_rw(cfg, N, seed, (uint32_t)k, phi, phin, lpn);
+        const int learned = (k > 1) && use_mlp;
+        if (k == 1) {
+            or_prior_draw(cfg, N, seed, phin, lpn);
+        } else if (learned) {
+            for (int i = 0; i < N; ++i) {
+                double u[OR_DMAX], h1[OR_MLP_H], h2[OR_MLP_H], o[OR_DMAX + OR_DMAX * (OR_DMAX + 1) / 2];
+                for (int d = 0; d < D; ++d) u[d] = (phi[i * D + d] - frame[d]) / frame[D + d];
+                or_mlp_forward(D, params, u, 1, h1, h2, o);
+                lq[i] = or_mlp_propose_one(D, frame, o, seed, (uint32_t)k, i, phin + (size_t)i * D);
+                lpn[i] = or_prior_logpdf(cfg, phin + (size_t)i * D);
+            }
+        } else {
+            or_propose_rw(cfg, N, seed, (uint32_t)k, phi, phin, lpn);
+        }
 #pragma omp parallel for schedule(dynamic, 1)
         for (int i = 0; i < N; ++i) {
             int run = (k == 1) || (logw[i] != -INFINITY && lpn[i] != -INFINITY);
@@ -600,8 +629,16 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
                 lln[i] = -INFINITY;
             }
         }
-        int st = or_outer_update(cfg, N, (uint32_t)k, seed, phi, lp, ll, logw, phin, lpn, lln, lwp,
-                                 anc, rec + (size_t)(k - 1) * RL);
+        double* rk = rec + (size_t)(k - 1) * RL;
+        int st = or_outer_update(cfg, N, (uint32_t)k, seed, phi, lp, ll, logw, phin, lpn, lln,
+                                 learned ? lq : NULL, lwp, anc, rk);
+        rk[RL - 2] = learned ? 1.0 : 0.0;
+        if (mlp && st == 0) {
+            double nm, nr;
+            use_mlp = or_mlp_train(cfg, N, phi, logw, seed, (uint32_t)k, cfg->mlp_epochs, cfg->mlp_batch, cfg->mlp_lr,
+                                   params, am, av, &adam_t, frame, &nm, &nr);
+            rk[RL - 1] = nm - nr;
+        }
         if (phi_dump) memcpy(phi_dump + (size_t)(k - 1) * N * D, phin, sizeof(double) * (size_t)N * D);
         if (ll_dump) memcpy(ll_dump + (size_t)(k - 1) * N, lln, sizeof(double) * (size_t)N);
         if (lp_dump) memcpy(lp_dump + (size_t)(k - 1) * N, lpn, sizeof(double) * (size_t)N);
@@ -613,5 +650,6 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
         }
     }
     free(phi); free(lp); free(ll); free(logw); free(phin); free(lpn); free(lln); free(lwp); free(anc);
+    free(lq); free(params); free(am); free(av);
     return status;
 }

@@ -52,6 +52,8 @@ typedef struct {
     double prior[OR_DMAX][3];      /* {family, a, b} per sampler coordinate */
     double rw_cov[OR_DMAX][OR_DMAX];
     double fixed[OR_NFIXED];       /* model constants (see smc2_oracle.c, "Models") */
+    int32_t mlp_epochs, mlp_batch; /* learned proposal: epochs and minibatch rows per iteration */
+    double mlp_lr;                 /* learned proposal: Adam learning rate */
 } or_config;
 
 /* Number of doubles in one per-iteration record. */
@@ -99,7 +101,24 @@ void or_propose_rw(const or_config* cfg, int N, uint64_t seed, uint32_t k, const
 int or_outer_update(const or_config* cfg, int N, uint32_t k, uint64_t seed,
                     double* phi, double* lp, double* ll, double* logw,
                     const double* phi_new, const double* lp_new, const double* ll_new,
-                    double* logw_pre, int32_t* anc, double* rec);
+                    const double* logq, double* logw_pre, int32_t* anc, double* rec);
+/* learned proposal (mlp.inc) */
+int or_mlp_nout(int D);
+int or_mlp_nparams(int D);
+void or_mlp_init(int D, uint64_t seed, float* w);
+void or_mlp_forward(int D, const float* w, const double* u, int bf16, double* h1, double* h2, double* o);
+double or_mlp_nll(int D, const double* o, const double* ut, double* grad);
+void or_mlp_backward(int D, const float* w, const double* u, const double* h1, const double* h2, const double* go,
+                     int bf16, double* grad);
+void or_adam_step(int n, float* p, float* m, float* v, const double* g, int t, double lr);
+void or_mlp_perm(uint64_t seed, uint32_t k, uint32_t e, uint32_t which, int N, uint64_t* a, uint64_t* b);
+void or_mlp_frame(int N, int D, const double* phi, const double* wn, double* frame);
+int or_mlp_train(const or_config* cfg, int N, const double* phi, const double* logw, uint64_t seed, uint32_t k,
+                 int epochs, int batch, double lr, float* params, float* adam_m, float* adam_v, int32_t* adam_t,
+                 double* frame, double* nll_mlp, double* nll_rw);
+double or_mlp_propose_one(int D, const double* frame, const double* o, uint64_t seed, uint32_t k, int i,
+                          double* phi_new);
+
 int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t seed, int N, int K,
                 int n_threads, double* rec, double* phi_dump, double* ll_dump, double* lp_dump,
                 double* logw_dump, int32_t* anc_dump);

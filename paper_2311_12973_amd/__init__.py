@@ -27,7 +27,7 @@ NFIXED = 32
 
 
 def record_len(D):
-    return 6 + 2 * D + D * D
+    return 8 + 2 * D + D * D
 
 
 class Smc2Error(RuntimeError):

@@ -176,7 +176,8 @@ def test_record_ess_estimates_and_resampling():
     assert rec[6:6 + D] == pytest.approx(wn @ th, rel=1e-12)
     cov = np.cov(th.T, aweights=wn, bias=True)
     assert rec[6 + D:6 + D + D * D] == pytest.approx(cov.ravel(), rel=1e-10)
-    assert rec[6 + D + D * D:] == pytest.approx(wn @ phi_new, rel=1e-12, abs=1e-14)
+    assert rec[6 + D + D * D:6 + 2 * D + D * D] == pytest.approx(wn @ phi_new, rel=1e-12, abs=1e-14)
+    assert rec[-2] == 0 and rec[-1] == 0  # random-walk proposal, no learned score
     resampled = rec[1] < N / 2
     assert bool(rec[2]) == resampled
     if resampled:
