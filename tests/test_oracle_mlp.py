@@ -96,10 +96,12 @@ def test_bf16_mode_is_exact_on_representable_operands():
     rounding is the identity; tanh outputs are not, so a network whose hidden layers
     are saturated (|tanh| = 1 exactly in FP64) gives identical outputs in both modes."""
     D = 3
-    w = O.mlp_init(D, 5)
     H = O.MLP_H
-    w = _bf16(w * 64)  # large weights: saturated tanh, BF16-representable parameters
-    w[H * D:H * D + H] = 0
+    rng = np.random.default_rng(4)
+    w = _bf16(O.mlp_init(D, 5) + 0.1 * rng.standard_normal(O.mlp_nparams(D)))  # BF16-representable
+    sgn = np.where(np.arange(H) % 2 == 0, 32.0, -32.0).astype(np.float32)
+    w[H * D:H * D + H] = sgn                      # b1 = +-32: every |tanh| is 1 in FP64
+    w[H * D + H + H * H:H * D + 2 * H + H * H] = -sgn  # b2 likewise
     u = _bf16(np.array([1.5, -2.0, 0.75]))
     o1, h1, g1 = O.mlp_forward(D, w, u, bf16=True)
     o0, h0, g0 = O.mlp_forward(D, w, u, bf16=False)
