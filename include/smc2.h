@@ -82,7 +82,13 @@ extern "C" {
 #define SMC2_L_FORWARD 0   /* L = forward proposal (Sec. IV-D, Eq. aimplified_l_weights) */
 #define SMC2_L_GAUSS_OPT 1 /* approximately optimal Gaussian L-kernel (Sec. IV-D)        */
 
-#define SMC2_PROP_RW 0 /* Gaussian random walk on phi (Eq. proposal) */
+#define SMC2_PROP_RW 0  /* Gaussian random walk on phi (Eq. proposal) */
+#define SMC2_PROP_MLP 1 /* learned Gaussian proposal: a D -> 64 -> 64 -> (mean, Cholesky)
+                           network, BF16 matrix-core products, trained after every
+                           iteration on the weighted population; its exact density
+                           enters the weights (Eq. l_weights, approximately optimal
+                           L-kernel only); the random walk whenever the network does not
+                           beat it on held-out pairs                                     */
 
 /* particle-filter draw schedule (smc2_config.schedule); both give identical results */
 #define SMC2_SCHED_AUTO 0     /* pooled where supported and it fits in LDS, else per draw */
@@ -102,7 +108,7 @@ typedef struct {
     int32_t N;         /* parameter samples per run, 2..32768                           */
     int32_t K;         /* iterations, >= 1 (k = 1 is the prior importance-sampling step) */
     int32_t precision; /* SMC2_PREC_FP32 or SMC2_PREC_FP64                              */
-    int32_t proposal;  /* SMC2_PROP_RW                                                  */
+    int32_t proposal;  /* SMC2_PROP_RW or SMC2_PROP_MLP                                 */
     int32_t lkernel;   /* SMC2_L_FORWARD or SMC2_L_GAUSS_OPT                            */
     int32_t pf_always; /* 1: resample the particle filter at every step                 */
     int32_t use_graph; /* 1: replay each iteration as one captured HIP graph            */
@@ -120,6 +126,9 @@ typedef struct {
                            fastest; 0: defaults from the LDS footprint. Same results.     */
     int32_t persistent; /* with tune = 0: 1 launches a persistent grid whose workgroups
                            pull filters from the cost-sorted work list (atomic counter)   */
+    int32_t mlp_epochs; /* learned proposal: training epochs per iteration (0 .. 1000)     */
+    int32_t mlp_batch;  /* learned proposal: minibatch rows (0: the whole population)      */
+    double mlp_lr;      /* learned proposal: Adam learning rate (> 0)                      */
 } smc2_config;
 
 typedef struct {
@@ -150,6 +159,17 @@ typedef struct {
 #define SMC2_DUMP_LL_NEW 6   /* N      doubles: their particle-filter log-likelihoods      */
 #define SMC2_DUMP_LOGW_PRE 7 /* N      doubles: log-weights before resampling              */
 #define SMC2_DUMP_ANC 8      /* N      int32:   ancestors chosen (identity if no resampling) */
+/* learned proposal (SMC2_PROP_MLP only) */
+#define SMC2_DUMP_MLP_OUT 9     /* N x P  float: network outputs at the population the
+                                   last step proposed from (P = D + D(D+1)/2)            */
+#define SMC2_DUMP_LOGQ 10       /* N      doubles: log q(phi_new | phi) of the last step   */
+#define SMC2_DUMP_MLP_PARAMS 11 /* NP     float: FP32 master weights W1[64][D] b1[64]
+                                   W2[64][64] b2[64] W3[P][64] b3[P] (after training)    */
+#define SMC2_DUMP_MLP_FRAME 12  /* D+D*D  doubles: input frame of the current network: the
+                                   weighted mean c and the lower Cholesky factor F of the
+                                   weighted covariance (row-major); inputs are F^-1(phi-c) */
+#define SMC2_DUMP_MLP_STATE 13  /* 4      doubles: {use next iteration (0/1), Adam steps,
+                                   held-out NLL of the network, of the random walk}      */
 
 /* Bytes of device workspace needed for this config and these runs (0 on bad input). */
 size_t smc2_workspace_bytes(const smc2_config* cfg, int32_t n_runs, const smc2_run* runs);

@@ -63,6 +63,24 @@ int smc2_pf_trace_state(const smc2_config* cfg, int32_t n_theta, const double* d
                         uint32_t k, double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, void* d_workspace,
                         size_t ws_bytes, void* hip_stream);
 
+/* Learned proposal, network outputs (SMC2_PROP_MLP). d_params: FP32 weights in the
+ * layout of SMC2_DUMP_MLP_PARAMS for dimension D (1..8); d_frame: D + D*D doubles
+ * (mean c, lower Cholesky factor F row-major; the inputs are F^-1 (phi - c)); d_phi:
+ * n x D doubles (sampler coordinates); d_out: n x P floats, P = D +
+ * D(D+1)/2, the outputs a (mean) and the packed Cholesky entries before the softplus
+ * of the diagonal. Matrix products take BF16-rounded operands with FP32 accumulation.
+ * All pointers are device memory owned by the caller. Asynchronous on the stream;
+ * SMC2_E_ARG on bad sizes or null pointers. */
+int smc2_mlp_forward(int32_t D, int32_t n, const float* d_params, const double* d_frame, const double* d_phi,
+                     float* d_out, void* hip_stream);
+
+/* Learned proposal, gradient of one minibatch: d_grad (NP floats) receives the
+ * parameter gradient and d_loss (1 double) the value of sum_r w_r NLL(u_t,r | u_in,r)
+ * over the n rows (inputs d_phi_in, targets d_phi_t, n x D doubles; row weights d_w,
+ * n doubles), as the training step computes it (no clipping, no update). n <= 32768. */
+int smc2_mlp_grad(int32_t D, int32_t n, const float* d_params, const double* d_frame, const double* d_phi_in,
+                  const double* d_phi_t, const double* d_w, float* d_grad, double* d_loss, void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

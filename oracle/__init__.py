@@ -110,6 +110,8 @@ def _declare(L):
     L.or_mlp_perm.argtypes = [c.c_uint64, c.c_uint32, c.c_uint32, c.c_uint32, c.c_int, P(c.c_uint64),
                               P(c.c_uint64)]
     L.or_mlp_frame.argtypes = [c.c_int, c.c_int, P(c.c_double), P(c.c_double), P(c.c_double)]
+    L.or_mlp_frame_len.restype = c.c_int
+    L.or_mlp_frame_len.argtypes = [c.c_int]
     L.or_mlp_train.restype = c.c_int
     L.or_mlp_train.argtypes = [P(Config), c.c_int, P(c.c_double), P(c.c_double), c.c_uint64, c.c_uint32, c.c_int,
                                c.c_int, c.c_double, P(c.c_float), P(c.c_float), P(c.c_float), P(c.c_int32),
@@ -418,7 +420,7 @@ def mlp_frame(phi, wn):
     phi = np.ascontiguousarray(phi, dtype=np.float64)
     wn = np.ascontiguousarray(wn, dtype=np.float64)
     N, D = phi.shape
-    fr = np.zeros(2 * D)
+    fr = np.zeros(D + D * D)
     lib().or_mlp_frame(N, D, _p(phi, ctypes.c_double), _p(wn, ctypes.c_double), _p(fr, ctypes.c_double))
     return fr
 
@@ -430,7 +432,7 @@ def mlp_train(cfg, phi, logw, seed, k, params, adam_m, adam_v, adam_t, epochs=No
     logw = np.ascontiguousarray(logw, dtype=np.float64)
     N, D = phi.shape
     t = ctypes.c_int32(adam_t)
-    fr = np.zeros(2 * D)
+    fr = np.zeros(D + D * D)
     nm, nr = ctypes.c_double(), ctypes.c_double()
     use = lib().or_mlp_train(ctypes.byref(cfg), N, _p(phi, ctypes.c_double), _p(logw, ctypes.c_double), int(seed),
                              int(k), cfg.mlp_epochs if epochs is None else epochs,

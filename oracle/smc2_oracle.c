@@ -594,7 +594,7 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
     float* am = mlp ? (float*)calloc((size_t)np, sizeof(float)) : NULL;
     float* av = mlp ? (float*)calloc((size_t)np, sizeof(float)) : NULL;
     int32_t adam_t = 0;
-    double frame[2 * OR_DMAX];
+    double frame[OR_DMAX + OR_DMAX * OR_DMAX];
     int use_mlp = 0;
     if (mlp) or_mlp_init(D, seed, params);
     int status = 0;
@@ -610,7 +610,7 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
         } else if (learned) {
             for (int i = 0; i < N; ++i) {
                 double u[OR_DMAX], h1[OR_MLP_H], h2[OR_MLP_H], o[OR_DMAX + OR_DMAX * (OR_DMAX + 1) / 2];
-                for (int d = 0; d < D; ++d) u[d] = (phi[i * D + d] - frame[d]) / frame[D + d];
+                mlp_whiten(D, frame, phi + (size_t)i * D, u);
                 or_mlp_forward(D, params, u, 1, h1, h2, o);
                 lq[i] = or_mlp_propose_one(D, frame, o, seed, (uint32_t)k, i, phin + (size_t)i * D);
                 lpn[i] = or_prior_logpdf(cfg, phin + (size_t)i * D);

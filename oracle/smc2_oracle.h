@@ -112,6 +112,7 @@ void or_mlp_backward(int D, const float* w, const double* u, const double* h1, c
                      int bf16, double* grad);
 void or_adam_step(int n, float* p, float* m, float* v, const double* g, int t, double lr);
 void or_mlp_perm(uint64_t seed, uint32_t k, uint32_t e, uint32_t which, int N, uint64_t* a, uint64_t* b);
+int or_mlp_frame_len(int D);
 void or_mlp_frame(int N, int D, const double* phi, const double* wn, double* frame);
 int or_mlp_train(const or_config* cfg, int N, const double* phi, const double* logw, uint64_t seed, uint32_t k,
                  int epochs, int batch, double lr, float* params, float* adam_m, float* adam_v, int32_t* adam_t,

@@ -20,9 +20,20 @@ OBS_POIS_PREV, OBS_POIS_INC, OBS_NB_INC = 0, 1, 2
 PREC_FP32, PREC_FP64 = 0, 1
 PRIOR_UNIFORM, PRIOR_LOGNORMAL, PRIOR_LOGITNORMAL, PRIOR_NORMAL = 0, 1, 2, 3
 L_FORWARD, L_GAUSS_OPT = 0, 1
-PROP_RW = 0
+PROP_RW, PROP_MLP = 0, 1
 SCHED_AUTO, SCHED_PER_DRAW, SCHED_POOLED = 0, 1, 2
-DUMP = dict(phi=0, lp=1, ll=2, logw=3, phi_new=4, lp_new=5, ll_new=6, logw_pre=7, anc=8)
+DUMP = dict(phi=0, lp=1, ll=2, logw=3, phi_new=4, lp_new=5, ll_new=6, logw_pre=7, anc=8, mlp_out=9, logq=10,
+            mlp_params=11, mlp_frame=12, mlp_state=13)
+MLP_H = 64
+
+
+def mlp_nout(D):
+    return D + D * (D + 1) // 2
+
+
+def mlp_nparams(D):
+    P = mlp_nout(D)
+    return MLP_H * D + MLP_H + MLP_H * MLP_H + MLP_H + P * MLP_H + P
 NFIXED = 32
 
 
@@ -43,7 +54,8 @@ class Config(ctypes.Structure):
                 ("block", ctypes.c_int32), ("schedule", ctypes.c_int32), ("n_pop", ctypes.c_double),
                 ("prior", ctypes.POINTER(ctypes.c_double)), ("rw_cov", ctypes.POINTER(ctypes.c_double)),
                 ("fixed", ctypes.POINTER(ctypes.c_double)), ("n_fixed", ctypes.c_int32),
-                ("tune", ctypes.c_int32), ("persistent", ctypes.c_int32)]
+                ("tune", ctypes.c_int32), ("persistent", ctypes.c_int32), ("mlp_epochs", ctypes.c_int32),
+                ("mlp_batch", ctypes.c_int32), ("mlp_lr", ctypes.c_double)]
 
 
 class Run(ctypes.Structure):
@@ -85,6 +97,10 @@ def lib():
         L.smc2_destroy.restype = c.c_int
         L.smc2_destroy.argtypes = [vp]
         L.smc2_last_error.restype = c.c_char_p
+        L.smc2_mlp_forward.restype = c.c_int
+        L.smc2_mlp_forward.argtypes = [c.c_int32, c.c_int32, vp, vp, vp, vp, vp]
+        L.smc2_mlp_grad.restype = c.c_int
+        L.smc2_mlp_grad.argtypes = [c.c_int32, c.c_int32, vp, vp, vp, vp, vp, vp, vp, vp]
         L.smc2_groups.restype = c.c_int
         L.smc2_groups.argtypes = [vp, c.c_int32, P(c.c_int32), P(c.c_int32), P(c.c_float)]
         L.smc2_last_error.argtypes = [vp]
@@ -152,7 +168,7 @@ class _Keep:
 
 
 def make_config(w, N=None, K=None, precision=None, use_graph=0, block=0, lkernel=None, pf_always=None,
-                schedule=0, tune=0, persistent=0):
+                schedule=0, tune=0, persistent=0, proposal=None):
     keep = _Keep()
     D = int(w["D"])
     keep.prior = np.ascontiguousarray(np.asarray(w["prior"], dtype=np.float64).reshape(D, 3))
@@ -165,7 +181,10 @@ def make_config(w, N=None, K=None, precision=None, use_graph=0, block=0, lkernel
     c.N = int(N if N is not None else w["N"])
     c.K = int(K if K is not None else w["K"])
     c.precision = int(precision if precision is not None else w["prec"])
-    c.proposal = PROP_RW
+    c.proposal = int(proposal if proposal is not None else w.get("proposal", PROP_RW))
+    c.mlp_epochs = int(w.get("mlp_epochs", 4))
+    c.mlp_batch = int(w.get("mlp_batch", 256))
+    c.mlp_lr = float(w.get("mlp_lr", 1e-3))
     c.lkernel = int(lkernel if lkernel is not None else w.get("lkernel", L_GAUSS_OPT))
     c.pf_always = int(pf_always if pf_always is not None else w.get("pf_always", 0))
     c.use_graph, c.block, c.schedule = int(use_graph), int(block), int(schedule)
@@ -241,6 +260,14 @@ class Sampler:
             out = np.zeros((self.N, self.D))
         elif what == "anc":
             out = np.zeros(self.N, dtype=np.int32)
+        elif what == "mlp_out":
+            out = np.zeros((self.N, mlp_nout(self.D)), dtype=np.float32)
+        elif what == "mlp_params":
+            out = np.zeros(mlp_nparams(self.D), dtype=np.float32)
+        elif what == "mlp_frame":
+            out = np.zeros(self.D + self.D * self.D)
+        elif what == "mlp_state":
+            out = np.zeros(4)
         else:
             out = np.zeros(self.N)
         _check(lib().smc2_dump(self.h, code, run, out.ctypes.data_as(ctypes.c_void_p), out.nbytes), self.h)
@@ -356,3 +383,29 @@ def pf_loglik(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0,
     _check(L.smc2_pf_trace(ctypes.byref(cfg), n, pth, runs, int(k), pll, pinc, prs, pws, wsb, current_stream()))
     return (from_device(tll, pll, np.float64, n), from_device(tinc, pinc, np.float64, n * T).reshape(n, T),
             from_device(trs, prs, np.int32, n * T).reshape(n, T))
+
+
+# ------------------------------------------------------------------ learned proposal, kernel level
+def mlp_forward(D, params, frame, phi, device="cuda"):
+    """Network outputs (n x P, float32) of rows phi (n x D) on the GPU."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1, D)
+    n = phi.shape[0]
+    tp, pp = to_device(np.ascontiguousarray(params, dtype=np.float32), device)
+    tf, pf = to_device(np.ascontiguousarray(frame, dtype=np.float64), device)
+    tx, px = to_device(phi, device)
+    to, po = device_buffer(4 * max(n, 1) * mlp_nout(D), device)
+    _check(lib().smc2_mlp_forward(D, n, pp, pf, px, po, current_stream()))
+    return from_device(to, po, np.float32, n * mlp_nout(D)).reshape(n, mlp_nout(D))
+
+
+def mlp_grad(D, params, frame, phi_in, phi_t, w, device="cuda"):
+    """(gradient (NP float32), loss) of sum_r w_r NLL(target_r | input_r) on the GPU."""
+    phi_in = np.ascontiguousarray(phi_in, dtype=np.float64).reshape(-1, D)
+    phi_t = np.ascontiguousarray(phi_t, dtype=np.float64).reshape(-1, D)
+    n = phi_in.shape[0]
+    bufs = [to_device(np.ascontiguousarray(x, dtype=dt), device) for x, dt in
+            ((params, np.float32), (frame, np.float64), (phi_in, np.float64), (phi_t, np.float64), (w, np.float64))]
+    tg, pg = device_buffer(4 * mlp_nparams(D), device)
+    tl, pl = device_buffer(8, device)
+    _check(lib().smc2_mlp_grad(D, n, *[b[1] for b in bufs], pg, pl, current_stream()))
+    return from_device(tg, pg, np.float32, mlp_nparams(D)), float(from_device(tl, pl, np.float64, 1)[0])

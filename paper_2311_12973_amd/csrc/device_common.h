@@ -8,6 +8,8 @@
 //   prior       (sample i, 0, 1<<16, 3<<24 | coordinate d)
 //   RW normal   (sample i, 0, k<<16, 4<<24 | coordinate d)
 //   outer resample (0, 0, k<<16, 5<<24)
+//   learned proposal: initial parameter p (p, 0, 0, 6<<24); training permutation
+//   (k, epoch, which, 7<<24)
 // Uniforms: u24(x) = (2(x>>9)+1) 2^-24 (exact in FP32); u53 = (2(x64>>12)+1) 2^-53.
 //
 // Precision: the particle filter works in `real` (float or double). Every
@@ -21,14 +23,15 @@
 
 namespace smc2 {
 
-enum : uint32_t { S_PF_PROP = 1u, S_PF_RS = 2u, S_PRIOR = 3u, S_RW = 4u, S_OUTER_RS = 5u };
+enum : uint32_t { S_PF_PROP = 1u, S_PF_RS = 2u, S_PRIOR = 3u, S_RW = 4u, S_OUTER_RS = 5u, S_MLP_INIT = 6u,
+                  S_MLP_PERM = 7u };
 
 struct W4 {
     uint32_t x, y, z, w;
 };
 
-__device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
-                                       uint32_t k1)
+__host__ __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
@@ -48,7 +51,7 @@ __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, ui
 
 __device__ __forceinline__ float u24(uint32_t x) { return (float)(2u * (x >> 9) + 1u) * 0x1p-24f; }
 
-__device__ __forceinline__ double u53(uint32_t lo, uint32_t hi)
+__host__ __device__ __forceinline__ double u53(uint32_t lo, uint32_t hi)
 {
     const uint64_t x = ((uint64_t)hi << 32) | lo;
     return (double)(2ull * (x >> 12) + 1ull) * 0x1p-53;

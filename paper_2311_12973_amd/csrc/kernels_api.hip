@@ -4,6 +4,7 @@
 
 #include "../../include/smc2_kernels.h"
 #include "block_ops.h"
+#include "mlp_kernels.h"
 #include "pf_kernel.h"
 
 namespace smc2 {
@@ -200,5 +201,27 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     if (e == hipSuccess) e = launch_pf(cfg->precision, cfg->model, cfg->obs, sched, block, lds, a, s);
     // the host copies of rd and y must stay valid until the copies have run
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return e == hipSuccess ? SMC2_OK : kfail(SMC2_E_DEVICE, hipGetErrorString(e));
+}
+
+extern "C" int smc2_mlp_forward(int32_t D, int32_t n, const float* d_params, const double* d_frame, const double* d_phi,
+                                float* d_out, void* stream)
+{
+    if (D < 1 || D > 8 || n < 0) return kfail(SMC2_E_ARG, "D must be in [1, 8] and n >= 0");
+    if (n > 0 && (!d_params || !d_frame || !d_phi || !d_out)) return kfail(SMC2_E_ARG, "null pointer");
+    hipError_t e = mlp_prepare(D);
+    if (e == hipSuccess) e = launch_mlp_rows_forward(D, n, d_params, d_frame, d_phi, d_out, (hipStream_t)stream);
+    return e == hipSuccess ? SMC2_OK : kfail(SMC2_E_DEVICE, hipGetErrorString(e));
+}
+
+extern "C" int smc2_mlp_grad(int32_t D, int32_t n, const float* d_params, const double* d_frame, const double* d_phi_in,
+                             const double* d_phi_t, const double* d_w, float* d_grad, double* d_loss, void* stream)
+{
+    if (D < 1 || D > 8 || n < 1 || n > 32768) return kfail(SMC2_E_ARG, "D must be in [1, 8] and n in [1, 32768]");
+    if (!d_params || !d_frame || !d_phi_in || !d_phi_t || !d_w || !d_grad || !d_loss)
+        return kfail(SMC2_E_ARG, "null pointer");
+    hipError_t e = mlp_prepare(D);
+    if (e == hipSuccess)
+        e = launch_mlp_rows_grad(D, n, d_params, d_frame, d_phi_in, d_phi_t, d_w, d_grad, d_loss, (hipStream_t)stream);
     return e == hipSuccess ? SMC2_OK : kfail(SMC2_E_DEVICE, hipGetErrorString(e));
 }

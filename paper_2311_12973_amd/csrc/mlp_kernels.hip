@@ -1,0 +1,855 @@
+// mlp_kernels.hip — the learned Gaussian proposal: forward, backward, Adam and the
+// held-out check on gfx950 matrix cores.
+//
+// The random-walk proposal of Sec. IV-A (Eq. proposal) is one choice of q; any q
+// whose density is evaluated exactly keeps the weights of Eq. l_weights valid. The
+// network maps a sample, whitened by the population's weighted mean c and covariance
+// Cholesky factor F (u = F^{-1} (phi - c)), to a Gaussian: mean a and lower Cholesky
+// factor L (softplus diagonal + 1e-3), and the proposal is phi' = c + F (a + L z); the
+// untrained network (a = 0, L = I) proposes the population's Gaussian fit. It is trained after every outer update on the
+// weighted population: the loss of a minibatch is the mean over its rows of
+// N w_j NLL(u_j | u_i) for a target j and a randomly paired input i (two random affine
+// permutations per epoch), minimised with Adam (0.9, 0.999, 1e-8) after clipping the
+// gradient's global norm to 100. The next iteration proposes with the network only if
+// its mean weighted NLL on a further pairing is finite and below the random walk's.
+//
+// Tiling: a wave owns 16 rows of a 64-row sub-batch. Every matrix product is a chain
+// of v_mfma_f32_16x16x16_bf16 (lane l: A row l%16, B column l%16, k = 4(l/16)..+3;
+// result rows 4(l/16)..+3, column l%16). Forward and activation gradients are
+// row-local per wave; the weight-gradient tiles (dW3 12, dW2 16, dW1 4) are split over
+// the four waves with the sub-batch's 64 rows as the reduction dimension.
+#include <math.h>
+
+#include "block_ops.h"
+#include "mlp_kernels.h"
+
+namespace smc2 {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+#define MLP_LOG_2PI 1.8378770664093453
+constexpr float MLP_EPS = 1e-3f;
+constexpr double MLP_CLIP = 100.0;
+
+// LDS row strides, padded so that the 16 rows one MFMA operand reads fall in
+// different banks
+constexpr int LD16 = 20, LD64 = 68, LD48 = 52;
+
+__device__ __forceinline__ short f2bf(float f)
+{
+    uint32_t b = __float_as_uint(f);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (short)(b >> 16);
+}
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct MlpW {                    // one network in BF16 (biases FP32)
+    short W1[MLP_H * 16];        // [h][d], d >= D zero
+    short W2[MLP_H * MLP_H];     // [h][g]
+    short W3[MLP_PPAD * MLP_H];  // [p][g], p >= P zero
+    float b1[MLP_H], b2[MLP_H], b3[MLP_PPAD];
+};
+
+struct MlpAct {                  // one sub-batch of 64 rows (FP32)
+    float U[MLP_SUB * LD16];     // inputs u (d >= D zero)
+    float H1[MLP_SUB * LD64];
+    float H2[MLP_SUB * LD64];
+    float O[MLP_SUB * LD48];     // outputs, then d loss / d outputs
+    float Z2[MLP_SUB * LD64];    // d loss / d (W2 h1 + b2)
+    float Z1[MLP_SUB * LD64];    // d loss / d (W1 u + b1)
+    float UT[MLP_SUB * 8];       // targets
+    float wr[MLP_SUB];           // row weights of the loss
+};
+
+// u = F^{-1} (x - c) for the frame (c[D], F[D][D] lower, row-major), as floats
+template <int D> __device__ __forceinline__ void mlp_whiten(const double* fr, const double* x, float* u)
+{
+    double v[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        double s = x[a] - fr[a];
+#pragma unroll
+        for (int b = 0; b < a; ++b) s -= fr[D + a * D + b] * v[b];
+        v[a] = s / fr[D + a * D + a];
+        u[a] = (float)v[a];
+    }
+}
+
+// bytes of the forward-only part (W, U, H1, H2, O)
+constexpr size_t MLP_LDS_FWD = sizeof(MlpW) + offsetof(MlpAct, Z2);
+constexpr size_t MLP_LDS_TRAIN = sizeof(MlpW) + sizeof(MlpAct);
+
+__device__ void mlp_load_weights(int D, const float* w, MlpW* L)
+{
+    const int P = mlp_nout(D);
+    const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
+    const float* W1 = w;
+    const float* b1 = W1 + MLP_H * D;
+    const float* W2 = b1 + MLP_H;
+    const float* b2 = W2 + MLP_H * MLP_H;
+    const float* W3 = b2 + MLP_H;
+    const float* b3 = W3 + P * MLP_H;
+    for (int i = tid; i < MLP_H * 16; i += nthr) {
+        const int h = i >> 4, d = i & 15;
+        L->W1[i] = d < D ? f2bf(W1[h * D + d]) : (short)0;
+    }
+    for (int i = tid; i < MLP_H * MLP_H; i += nthr) L->W2[i] = f2bf(W2[i]);
+    for (int i = tid; i < MLP_PPAD * MLP_H; i += nthr) L->W3[i] = (i / MLP_H) < P ? f2bf(W3[i]) : (short)0;
+    for (int i = tid; i < MLP_H; i += nthr) {
+        L->b1[i] = b1[i];
+        L->b2[i] = b2[i];
+    }
+    for (int i = tid; i < MLP_PPAD; i += nthr) L->b3[i] = i < P ? b3[i] : 0.f;
+}
+
+// acc += A[16 x K] W^T: A rows FP32 (stride lda), W[n][k] BF16 (stride ldw) from the
+// tile's first output column
+__device__ __forceinline__ f32x4 mm_a_wt(const float* A, int lda, const short* W, int ldw, int K, f32x4 acc)
+{
+    const int l = lane_id(), i = l & 15, kq = (l >> 4) << 2;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            a[c] = f2bf(A[i * lda + k0 + kq + c]);
+            b[c] = W[i * ldw + k0 + kq + c];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// acc += A[16 x K] W: W[k][n] BF16 (stride ldw) from the tile's first output column
+__device__ __forceinline__ f32x4 mm_a_w(const float* A, int lda, const short* W, int ldw, int K, f32x4 acc)
+{
+    const int l = lane_id(), i = l & 15, kq = (l >> 4) << 2;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            a[c] = f2bf(A[i * lda + k0 + kq + c]);
+            b[c] = W[(k0 + kq + c) * ldw + i];
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// acc += X^T Y over K rows: X[rows][m] and Y[rows][n] FP32, from the tile's first
+// output row / column
+__device__ __forceinline__ f32x4 mm_xt_y(const float* X, int ldx, const float* Y, int ldy, int K, f32x4 acc)
+{
+    const int l = lane_id(), i = l & 15, kq = (l >> 4) << 2;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        bf16x4 a, b;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            a[c] = f2bf(X[(k0 + kq + c) * ldx + i]);
+            b[c] = f2bf(Y[(k0 + kq + c) * ldy + i]);
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// forward pass of the wave's 16 rows (from row r0 of the sub-batch)
+__device__ void mlp_fwd16(const MlpW* W, MlpAct* A, int r0)
+{
+    const int l = lane_id(), j = l & 15, rq = (l >> 4) << 2;
+    for (int jb = 0; jb < 4; ++jb) {
+        const float bb = W->b1[jb * 16 + j];
+        f32x4 acc = {bb, bb, bb, bb};
+        acc = mm_a_wt(A->U + r0 * LD16, LD16, W->W1 + jb * 16 * 16, 16, 16, acc);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) A->H1[(r0 + rq + c) * LD64 + jb * 16 + j] = tanhf(acc[c]);
+    }
+    wave_sync();
+    for (int jb = 0; jb < 4; ++jb) {
+        const float bb = W->b2[jb * 16 + j];
+        f32x4 acc = {bb, bb, bb, bb};
+        acc = mm_a_wt(A->H1 + r0 * LD64, LD64, W->W2 + jb * 16 * MLP_H, MLP_H, MLP_H, acc);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) A->H2[(r0 + rq + c) * LD64 + jb * 16 + j] = tanhf(acc[c]);
+    }
+    wave_sync();
+    for (int pb = 0; pb < 3; ++pb) {
+        const float bb = W->b3[pb * 16 + j];
+        f32x4 acc = {bb, bb, bb, bb};
+        acc = mm_a_wt(A->H2 + r0 * LD64, LD64, W->W3 + pb * 16 * MLP_H, MLP_H, MLP_H, acc);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) A->O[(r0 + rq + c) * LD48 + pb * 16 + j] = acc[c];
+    }
+    wave_sync();
+}
+
+// activation gradients of the wave's 16 rows from d loss / d outputs (in A->O)
+__device__ void mlp_bwd16(const MlpW* W, MlpAct* A, int r0)
+{
+    const int l = lane_id(), j = l & 15, rq = (l >> 4) << 2;
+    for (int jb = 0; jb < 4; ++jb) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mm_a_w(A->O + r0 * LD48, LD48, W->W3 + jb * 16, MLP_H, MLP_PPAD, acc);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int at = (r0 + rq + c) * LD64 + jb * 16 + j;
+            const float h = A->H2[at];
+            A->Z2[at] = acc[c] * (1.f - h * h);
+        }
+    }
+    wave_sync();
+    for (int jb = 0; jb < 4; ++jb) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+        acc = mm_a_w(A->Z2 + r0 * LD64, LD64, W->W2 + jb * 16, MLP_H, MLP_H, acc);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int at = (r0 + rq + c) * LD64 + jb * 16 + j;
+            const float h = A->H1[at];
+            A->Z1[at] = acc[c] * (1.f - h * h);
+        }
+    }
+    wave_sync();
+}
+
+// weight-gradient tiles of the sub-batch accumulated in acc[] (wave w: tiles w + 4q)
+__device__ void mlp_wgrad(const MlpAct* A, f32x4 (&acc)[8])
+{
+    const int w = wave_id();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int t = w + 4 * q;
+        if (t < 12) {
+            acc[q] = mm_xt_y(A->O + (t >> 2) * 16, LD48, A->H2 + (t & 3) * 16, LD64, MLP_SUB, acc[q]);
+        } else if (t < 28) {
+            acc[q] = mm_xt_y(A->Z2 + ((t - 12) >> 2) * 16, LD64, A->H1 + ((t - 12) & 3) * 16, LD64, MLP_SUB, acc[q]);
+        } else {
+            acc[q] = mm_xt_y(A->Z1 + (t - 28) * 16, LD64, A->U, LD16, MLP_SUB, acc[q]);
+        }
+    }
+}
+
+// adds the tiles to grad[] (parameter layout)
+template <int D> __device__ void mlp_scatter_wgrad(const f32x4 (&acc)[8], float* grad)
+{
+    constexpr int P = D + D * (D + 1) / 2;
+    float* gW1 = grad;
+    float* gW2 = gW1 + MLP_H * D + MLP_H;
+    float* gW3 = gW2 + MLP_H * MLP_H + MLP_H;
+    const int l = lane_id(), j = l & 15, rq = (l >> 4) << 2, w = wave_id();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int t = w + 4 * q;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int i = rq + c;
+            if (t < 12) {
+                const int p = (t >> 2) * 16 + i, g = (t & 3) * 16 + j;
+                if (p < P) gW3[p * MLP_H + g] = acc[q][c];
+            } else if (t < 28) {
+                const int h = ((t - 12) >> 2) * 16 + i, g = ((t - 12) & 3) * 16 + j;
+                gW2[h * MLP_H + g] = acc[q][c];
+            } else {
+                const int h = (t - 28) * 16 + i;
+                if (j < D) gW1[h * D + j] = acc[q][c];
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ float softplus_f(float x) { return x > 30.f ? x : log1pf(expf(x)); }
+
+// NLL of row r (targets A->UT) from its outputs; with grad, replaces the outputs by
+// scale * d NLL / d o (padding columns stay zero).
+template <int D> __device__ float mlp_row_nll(MlpAct* A, int r, float scale, bool grad)
+{
+    float* o = A->O + r * LD48;
+    const float* ut = A->UT + r * 8;
+    float L[D * (D + 1) / 2], v[D], w[D];
+    float quad = 0.f, logdet = 0.f;
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+#pragma unroll
+        for (int jj = 0; jj <= i; ++jj) {
+            const float x = o[D + i * (i + 1) / 2 + jj];
+            L[i * (i + 1) / 2 + jj] = (i == jj) ? softplus_f(x) + MLP_EPS : x;
+        }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        float s = ut[i] - o[i];
+#pragma unroll
+        for (int jj = 0; jj < i; ++jj) s -= L[i * (i + 1) / 2 + jj] * v[jj];
+        v[i] = s / L[i * (i + 1) / 2 + i];
+        quad += v[i] * v[i];
+        logdet += logf(L[i * (i + 1) / 2 + i]);
+    }
+    const float nll = 0.5f * quad + logdet + 0.5f * (float)D * (float)MLP_LOG_2PI;
+    if (grad) {
+#pragma unroll
+        for (int i = D - 1; i >= 0; --i) {
+            float s = v[i];
+#pragma unroll
+            for (int jj = i + 1; jj < D; ++jj) s -= L[jj * (jj + 1) / 2 + i] * w[jj];
+            w[i] = s / L[i * (i + 1) / 2 + i];
+        }
+        float od[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) od[i] = o[D + i * (i + 1) / 2 + i];
+#pragma unroll
+        for (int i = 0; i < D; ++i) o[i] = scale * -w[i];
+#pragma unroll
+        for (int i = 0; i < D; ++i)
+#pragma unroll
+            for (int jj = 0; jj <= i; ++jj) {
+                float g = -w[i] * v[jj];
+                if (i == jj) g = (g + 1.f / L[i * (i + 1) / 2 + i]) * (1.f / (1.f + expf(-od[i])));
+                o[D + i * (i + 1) / 2 + jj] = scale * g;
+            }
+    }
+    return nll;
+}
+
+// the random affine permutation of (k, epoch, which): a, b with gcd(a, N) = 1
+__device__ __forceinline__ void mlp_perm_dev(uint64_t seed, uint32_t k, uint32_t e, uint32_t which, int N,
+                                             uint64_t& a, uint64_t& b)
+{
+    const W4 x = philox10(k, e, which, S_MLP_PERM << 24, (uint32_t)seed, (uint32_t)(seed >> 32));
+    a = 1;
+    b = 0;
+    if (N > 1) {
+        a = 1 + (uint64_t)x.x % (uint64_t)(N - 1);
+        for (;;) {
+            uint64_t p = a, q = (uint64_t)N;
+            while (q) {
+                const uint64_t t = p % q;
+                p = q;
+                q = t;
+            }
+            if (p == 1) break;
+            a = a % (uint64_t)(N - 1) + 1;
+        }
+        b = (uint64_t)x.y % (uint64_t)N;
+    }
+}
+
+// Fixed-order block sum of E doubles per thread (butterfly per wave, waves in order);
+// every thread gets the totals. lds holds 16 x E doubles.
+template <int E> __device__ void mlp_block_sum(double (&v)[E], double* lds)
+{
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = wave_sum(v[e]);
+    __syncthreads();
+    if (lane_id() == 0)
+#pragma unroll
+        for (int e = 0; e < E; ++e) lds[wave_id() * E + e] = v[e];
+    __syncthreads();
+    const int nw = (int)(blockDim.x >> 6);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += lds[w * E + e];
+        v[e] = s;
+    }
+}
+
+// ------------------------------------------------------------------ forward over a population
+template <int D>
+__global__ void __launch_bounds__(256) k_mlp_forward(MlpArrays m, MlpParams p, OuterArrays o)
+{
+    constexpr int P = D + D * (D + 1) / 2;
+    const int r = (int)blockIdx.y;
+    const int k = *o.k_dev;
+    if (k < 2 || !m.use[r]) return;
+    extern __shared__ __align__(16) unsigned char smem[];
+    MlpW* W = reinterpret_cast<MlpW*>(smem);
+    MlpAct* A = reinterpret_cast<MlpAct*>(smem + sizeof(MlpW));
+    const int NP = mlp_nparams(D);
+    mlp_load_weights(D, m.params + (size_t)r * NP, W);
+    const double* fr = m.frame + (size_t)r * (D + D * D);
+    const int row0 = (int)blockIdx.x * MLP_SUB;
+    const int tid = (int)threadIdx.x;
+    if (tid < MLP_SUB) {
+        const int i = row0 + tid;
+        float u[16];
+#pragma unroll
+        for (int d = 0; d < 16; ++d) u[d] = 0.f;
+        if (i < p.N) mlp_whiten<D>(fr, o.phi + ((size_t)r * p.N + i) * D, u);
+#pragma unroll
+        for (int d = 0; d < 16; ++d) A->U[tid * LD16 + d] = u[d];
+    }
+    __syncthreads();
+    mlp_fwd16(W, A, wave_id() * 16);
+    __syncthreads();
+    for (int e = tid; e < MLP_SUB * P; e += (int)blockDim.x) {
+        const int rr = e / P, pp = e - rr * P, i = row0 + rr;
+        if (i < p.N) m.out[((size_t)r * p.N + i) * P + pp] = A->O[rr * LD48 + pp];
+    }
+}
+
+// ------------------------------------------------------------------ training
+template <int D>
+__global__ void __launch_bounds__(256) k_mlp_train(MlpArrays m, MlpParams p, OuterArrays o, const uint64_t* seeds)
+{
+    constexpr int P = D + D * (D + 1) / 2;
+    const int r = (int)blockIdx.x;
+    const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
+    const int N = p.N;
+    const int k = *o.k_dev;
+    if (o.status[r] != 0) return;  // every weight vanished: nothing to learn from
+    extern __shared__ __align__(16) unsigned char smem[];
+    MlpW* W = reinterpret_cast<MlpW*>(smem);
+    MlpAct* A = reinterpret_cast<MlpAct*>(smem + sizeof(MlpW));
+    __shared__ double red[16 * (2 * DMAX + 1)];
+    __shared__ double frs[DMAX + DMAX * DMAX];
+    const int NP = mlp_nparams(D);
+    float* prm = m.params + (size_t)r * NP;
+    float* am = m.adam_m + (size_t)r * NP;
+    float* av = m.adam_v + (size_t)r * NP;
+    float* grad = m.grad + (size_t)r * NP;
+    const double* phi = o.phi + (size_t)r * N * D;
+    const double* logw = o.logw + (size_t)r * N;
+    const uint64_t seed = seeds[r];
+
+    // weights of the population: W = log sum exp (log w)
+    double mx = -INFINITY;
+    for (int i = tid; i < N; i += nthr) mx = logw[i] > mx ? logw[i] : mx;
+    {
+        RedLds* rl = reinterpret_cast<RedLds*>(A);  // the activation area is free here
+        mx = uniform_f64(block_max<double>(mx, rl));
+    }
+    double sw[1] = {0.0};
+    for (int i = tid; i < N; i += nthr) sw[0] += exp(logw[i] - mx);
+    mlp_block_sum<1>(sw, red);
+    const double LW = mx + log(sw[0]);
+    // frame: weighted mean c and the Cholesky factor F of the weighted covariance
+    // (diagonal of the standard deviations when a pivot is not above 1e-12 of its
+    // coordinate's raw second moment)
+    {
+        double acc[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc[d] = 0.0;
+        for (int i = tid; i < N; i += nthr) {
+            const double wn = exp(logw[i] - LW);
+#pragma unroll
+            for (int d = 0; d < D; ++d) acc[d] += wn * phi[(size_t)i * D + d];
+        }
+        mlp_block_sum<D>(acc, red);
+        double c[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) c[d] = acc[d];
+        // covariance rows one at a time (D sums per pass)
+        for (int a = 0; a < D; ++a) {
+            double cv[D];
+#pragma unroll
+            for (int b = 0; b < D; ++b) cv[b] = 0.0;
+            for (int i = tid; i < N; i += nthr) {
+                const double wn = exp(logw[i] - LW);
+                const double za = phi[(size_t)i * D + a] - c[a];
+#pragma unroll
+                for (int b = 0; b < D; ++b) cv[b] += wn * za * (phi[(size_t)i * D + b] - c[b]);
+            }
+            mlp_block_sum<D>(cv, red);
+            if (tid == 0)
+#pragma unroll
+                for (int b = 0; b < D; ++b) frs[D + a * D + b] = cv[b];  // covariance, factored below
+        }
+        if (tid == 0) {
+            double C[D * D], F[D * D];
+#pragma unroll
+            for (int e = 0; e < D * D; ++e) {
+                C[e] = frs[D + e];
+                F[e] = 0.0;
+            }
+            bool ok = true;
+            for (int j = 0; j < D && ok; ++j) {
+                double sj = C[j * D + j];
+                for (int q = 0; q < j; ++q) sj -= F[j * D + q] * F[j * D + q];
+                ok = sj > 1e-12 * (C[j * D + j] + c[j] * c[j]);
+                if (!ok) break;
+                F[j * D + j] = sqrt(sj);
+                for (int i2 = j + 1; i2 < D; ++i2) {
+                    double v = C[i2 * D + j];
+                    for (int q = 0; q < j; ++q) v -= F[i2 * D + q] * F[j * D + q];
+                    F[i2 * D + j] = v / F[j * D + j];
+                }
+            }
+            if (!ok) {
+#pragma unroll
+                for (int e = 0; e < D * D; ++e) F[e] = 0.0;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    const double sd = sqrt(C[a * D + a]);
+                    F[a * D + a] = sd > 1e-6 ? sd : 1e-6;
+                }
+            }
+#pragma unroll
+            for (int d = 0; d < D; ++d) frs[d] = c[d];
+#pragma unroll
+            for (int e = 0; e < D * D; ++e) frs[D + e] = F[e];
+        }
+        __syncthreads();
+    }
+    double* fr_out = m.frame + (size_t)r * (D + D * D);
+    for (int d = tid; d < D + D * D; d += nthr) fr_out[d] = frs[d];
+
+    const int B = (p.batch < 1 || p.batch > N) ? N : p.batch;
+    int t_adam = m.adam_t[r];
+    mlp_load_weights(D, prm, W);
+    __syncthreads();
+    for (int ep = 0; ep < p.epochs; ++ep) {
+        uint64_t ta, tb, ia, ib;
+        mlp_perm_dev(seed, (uint32_t)k, (uint32_t)ep, 0u, N, ta, tb);
+        mlp_perm_dev(seed, (uint32_t)k, (uint32_t)ep, 1u, N, ia, ib);
+        for (int b0 = 0; b0 < N; b0 += B) {
+            const int nb = (N - b0) < B ? (N - b0) : B;
+            f32x4 acc[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+            float bacc = 0.f;  // bias gradient of column tid (< 176)
+            for (int s0 = 0; s0 < nb; s0 += MLP_SUB) {
+                // rows of the sub-batch
+                if (tid < MLP_SUB) {
+                    const int rr = b0 + s0 + tid;
+                    const bool valid = s0 + tid < nb;
+                    const int jt = valid ? (int)((ta * (uint64_t)rr + tb) % (uint64_t)N) : 0;
+                    const int ii = valid ? (int)((ia * (uint64_t)rr + ib) % (uint64_t)N) : 0;
+                    float ui[16], ut[8];
+#pragma unroll
+                    for (int d = 0; d < 16; ++d) ui[d] = 0.f;
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) ut[d] = 0.f;
+                    if (valid) {
+                        mlp_whiten<D>(frs, phi + (size_t)ii * D, ui);
+                        mlp_whiten<D>(frs, phi + (size_t)jt * D, ut);
+                    }
+#pragma unroll
+                    for (int d = 0; d < 16; ++d) A->U[tid * LD16 + d] = ui[d];
+#pragma unroll
+                    for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = ut[d];
+                    A->wr[tid] = valid ? (float)((double)N * exp(logw[jt] - LW) / (double)nb) : 0.f;
+                }
+                __syncthreads();
+                mlp_fwd16(W, A, wave_id() * 16);
+                if (lane_id() < 16) mlp_row_nll<D>(A, wave_id() * 16 + lane_id(), A->wr[wave_id() * 16 + lane_id()], true);
+                wave_sync();
+                mlp_bwd16(W, A, wave_id() * 16);
+                __syncthreads();
+                mlp_wgrad(A, acc);
+                if (tid < 176) {
+                    float s = 0.f;
+                    if (tid < 48) {
+                        for (int rr = 0; rr < MLP_SUB; ++rr) s += A->O[rr * LD48 + tid];
+                    } else if (tid < 112) {
+                        for (int rr = 0; rr < MLP_SUB; ++rr) s += A->Z2[rr * LD64 + tid - 48];
+                    } else {
+                        for (int rr = 0; rr < MLP_SUB; ++rr) s += A->Z1[rr * LD64 + tid - 112];
+                    }
+                    bacc += s;
+                }
+                __syncthreads();  // the next sub-batch overwrites the activations
+            }
+            // minibatch gradient in parameter layout
+            mlp_scatter_wgrad<D>(acc, grad);
+            if (tid < 176) {
+                if (tid < 48) {
+                    if (tid < P) grad[NP - P + tid] = bacc;
+                } else if (tid < 112) {
+                    grad[MLP_H * D + MLP_H + MLP_H * MLP_H + tid - 48] = bacc;
+                } else {
+                    grad[MLP_H * D + tid - 112] = bacc;
+                }
+            }
+            __syncthreads();
+            double nn[1] = {0.0};
+            for (int i = tid; i < NP; i += nthr) nn[0] += (double)grad[i] * (double)grad[i];
+            mlp_block_sum<1>(nn, red);
+            const double nrm = sqrt(nn[0]);
+            const double clip = nrm > MLP_CLIP ? MLP_CLIP / nrm : 1.0;
+            ++t_adam;
+            const float c1 = 1.f - powf(0.9f, (float)t_adam), c2 = 1.f - powf(0.999f, (float)t_adam);
+            for (int i = tid; i < NP; i += nthr) {
+                const float g = (float)((double)grad[i] * clip);
+                const float mi = 0.9f * am[i] + 0.1f * g;
+                const float vi = 0.999f * av[i] + 0.001f * g * g;
+                am[i] = mi;
+                av[i] = vi;
+                prm[i] = prm[i] - p.lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+            }
+            __syncthreads();
+            mlp_load_weights(D, prm, W);
+            __syncthreads();
+        }
+    }
+    if (tid == 0) m.adam_t[r] = t_adam;
+
+    // held-out comparison on the pairing of "epoch" E
+    {
+        uint64_t ta, tb, ia, ib;
+        mlp_perm_dev(seed, (uint32_t)k, (uint32_t)p.epochs, 0u, N, ta, tb);
+        mlp_perm_dev(seed, (uint32_t)k, (uint32_t)p.epochs, 1u, N, ia, ib);
+        double sls = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; ++d) sls += log(frs[D + d * D + d]);
+        double sums[2] = {0.0, 0.0};
+        for (int s0 = 0; s0 < N; s0 += MLP_SUB) {
+            int jt = 0, ii = 0;
+            double wt = 0.0;
+            if (tid < MLP_SUB) {
+                const int rr = s0 + tid;
+                const bool valid = rr < N;
+                jt = valid ? (int)((ta * (uint64_t)rr + tb) % (uint64_t)N) : 0;
+                ii = valid ? (int)((ia * (uint64_t)rr + ib) % (uint64_t)N) : 0;
+                wt = valid ? (double)N * exp(logw[jt] - LW) : 0.0;
+                float ui[16], ut[8];
+#pragma unroll
+                for (int d = 0; d < 16; ++d) ui[d] = 0.f;
+#pragma unroll
+                for (int d = 0; d < 8; ++d) ut[d] = 0.f;
+                if (valid) {
+                    mlp_whiten<D>(frs, phi + (size_t)ii * D, ui);
+                    mlp_whiten<D>(frs, phi + (size_t)jt * D, ut);
+                }
+#pragma unroll
+                for (int d = 0; d < 16; ++d) A->U[tid * LD16 + d] = ui[d];
+#pragma unroll
+                for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = ut[d];
+            }
+            __syncthreads();
+            mlp_fwd16(W, A, wave_id() * 16);
+            __syncthreads();
+            if (tid < MLP_SUB && wt > 0.0) {
+                const float nll = mlp_row_nll<D>(A, tid, 0.f, false);
+                sums[0] += wt * ((double)nll + sls);
+                // random walk: -log N(phi_j; phi_i, L L^T)
+                double v[D], quad = 0.0, ld = 0.0;
+#pragma unroll
+                for (int a2 = 0; a2 < D; ++a2) {
+                    double sa = phi[(size_t)jt * D + a2] - phi[(size_t)ii * D + a2];
+#pragma unroll
+                    for (int b2 = 0; b2 < a2; ++b2) sa -= p.lrw[a2 * D + b2] * v[b2];
+                    v[a2] = sa / p.lrw[a2 * D + a2];
+                    quad += v[a2] * v[a2];
+                    ld += log(p.lrw[a2 * D + a2]);
+                }
+                sums[1] += wt * (0.5 * quad + ld + 0.5 * D * MLP_LOG_2PI);
+            }
+            __syncthreads();
+        }
+        mlp_block_sum<2>(sums, red);
+        const double nm = sums[0] / N, nr = sums[1] / N;
+        if (tid == 0) {
+            m.score[2 * r] = nm;
+            m.score[2 * r + 1] = nr;
+            m.use[r] = (isfinite(nm) && nm < nr) ? 1 : 0;
+            o.records[((size_t)r * p.K + (k - 1)) * p.rec_len + p.rec_len - 1] = nm - nr;
+        }
+    }
+}
+
+// ------------------------------------------------------------------ kernel-level entry points
+template <int D>
+__global__ void __launch_bounds__(256) k_mlp_rows_forward(int n, const float* params, const double* frame,
+                                                          const double* phi, float* out)
+{
+    constexpr int P = D + D * (D + 1) / 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    MlpW* W = reinterpret_cast<MlpW*>(smem);
+    MlpAct* A = reinterpret_cast<MlpAct*>(smem + sizeof(MlpW));
+    mlp_load_weights(D, params, W);
+    const int row0 = (int)blockIdx.x * MLP_SUB, tid = (int)threadIdx.x;
+    if (tid < MLP_SUB) {
+        const int i = row0 + tid;
+        float u[16];
+#pragma unroll
+        for (int d = 0; d < 16; ++d) u[d] = 0.f;
+        if (i < n) mlp_whiten<D>(frame, phi + (size_t)i * D, u);
+#pragma unroll
+        for (int d = 0; d < 16; ++d) A->U[tid * LD16 + d] = u[d];
+    }
+    __syncthreads();
+    mlp_fwd16(W, A, wave_id() * 16);
+    __syncthreads();
+    for (int e = tid; e < MLP_SUB * P; e += (int)blockDim.x) {
+        const int rr = e / P, pp = e - rr * P, i = row0 + rr;
+        if (i < n) out[(size_t)i * P + pp] = A->O[rr * LD48 + pp];
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_mlp_rows_grad(int n, const float* params, const double* frame,
+                                                       const double* phi_in, const double* phi_t, const double* wrow,
+                                                       float* grad, double* loss)
+{
+    constexpr int P = D + D * (D + 1) / 2;
+    extern __shared__ __align__(16) unsigned char smem[];
+    MlpW* W = reinterpret_cast<MlpW*>(smem);
+    MlpAct* A = reinterpret_cast<MlpAct*>(smem + sizeof(MlpW));
+    __shared__ double red[16 * 2];
+    const int NP = mlp_nparams(D);
+    const int tid = (int)threadIdx.x;
+    mlp_load_weights(D, params, W);
+    f32x4 acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+    double ls[1] = {0.0};
+    __syncthreads();
+    for (int s0 = 0; s0 < n; s0 += MLP_SUB) {
+        if (tid < MLP_SUB) {
+            const int i = s0 + tid;
+            const bool valid = i < n;
+            float ui[16], ut[8];
+#pragma unroll
+            for (int d = 0; d < 16; ++d) ui[d] = 0.f;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) ut[d] = 0.f;
+            if (valid) {
+                mlp_whiten<D>(frame, phi_in + (size_t)i * D, ui);
+                mlp_whiten<D>(frame, phi_t + (size_t)i * D, ut);
+            }
+#pragma unroll
+            for (int d = 0; d < 16; ++d) A->U[tid * LD16 + d] = ui[d];
+#pragma unroll
+            for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = ut[d];
+            A->wr[tid] = valid ? (float)wrow[i] : 0.f;
+        }
+        __syncthreads();
+        mlp_fwd16(W, A, wave_id() * 16);
+        if (lane_id() < 16) {
+            const int rr = wave_id() * 16 + lane_id();
+            const float wv = A->wr[rr];
+            const float nll = mlp_row_nll<D>(A, rr, wv, true);
+            if (wv != 0.f) ls[0] += (double)wv * (double)nll;
+        }
+        wave_sync();
+        mlp_bwd16(W, A, wave_id() * 16);
+        __syncthreads();
+        mlp_wgrad(A, acc);
+        if (tid < 176) {
+            float s = 0.f;
+            if (tid < 48) {
+                for (int rr = 0; rr < MLP_SUB; ++rr) s += A->O[rr * LD48 + tid];
+            } else if (tid < 112) {
+                for (int rr = 0; rr < MLP_SUB; ++rr) s += A->Z2[rr * LD64 + tid - 48];
+            } else {
+                for (int rr = 0; rr < MLP_SUB; ++rr) s += A->Z1[rr * LD64 + tid - 112];
+            }
+            bacc += s;
+        }
+        __syncthreads();
+    }
+    mlp_scatter_wgrad<D>(acc, grad);
+    if (tid < 176) {
+        if (tid < 48) {
+            if (tid < P) grad[NP - P + tid] = bacc;
+        } else if (tid < 112) {
+            grad[MLP_H * D + MLP_H + MLP_H * MLP_H + tid - 48] = bacc;
+        } else {
+            grad[MLP_H * D + tid - 112] = bacc;
+        }
+    }
+    mlp_block_sum<1>(ls, red);
+    if (tid == 0) *loss = ls[0];
+}
+
+// ------------------------------------------------------------------ host side
+template <typename Kern> static hipError_t raise_lds(Kern f, size_t bytes)
+{
+    return hipFuncSetAttribute(reinterpret_cast<const void*>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+#define MLP_DISPATCH(D, CALL)                                                                                   \
+    switch (D) {                                                                                                \
+    case 1: CALL(1); break;                                                                                     \
+    case 2: CALL(2); break;                                                                                     \
+    case 3: CALL(3); break;                                                                                     \
+    case 4: CALL(4); break;                                                                                     \
+    case 5: CALL(5); break;                                                                                     \
+    case 6: CALL(6); break;                                                                                     \
+    case 7: CALL(7); break;                                                                                     \
+    case 8: CALL(8); break;                                                                                     \
+    default: return hipErrorInvalidValue;                                                                       \
+    }
+
+hipError_t launch_mlp_forward(const MlpArrays& m, const MlpParams& p, const OuterArrays& o, hipStream_t s)
+{
+    const dim3 grid((unsigned)((p.N + MLP_SUB - 1) / MLP_SUB), (unsigned)p.R);
+    hipError_t e = hipSuccess;
+#define CALL_FWD(DD) hipLaunchKernelGGL(k_mlp_forward<DD>, grid, dim3(256), MLP_LDS_FWD, s, m, p, o);
+    MLP_DISPATCH(p.D, CALL_FWD)
+#undef CALL_FWD
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_mlp_train(const MlpArrays& m, const MlpParams& p, const OuterArrays& o, const uint64_t* seeds,
+                            hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+#define CALL_TRAIN(DD)                                                                                          \
+    hipLaunchKernelGGL(k_mlp_train<DD>, dim3((unsigned)p.R), dim3(256), MLP_LDS_TRAIN, s, m, p, o, seeds);
+    MLP_DISPATCH(p.D, CALL_TRAIN)
+#undef CALL_TRAIN
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_mlp_rows_forward(int D, int n, const float* params, const double* frame, const double* phi,
+                                   float* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((n + MLP_SUB - 1) / MLP_SUB));
+    hipError_t e = hipSuccess;
+#define CALL_RF(DD) hipLaunchKernelGGL(k_mlp_rows_forward<DD>, grid, dim3(256), MLP_LDS_FWD, s, n, params, frame, phi, out);
+    MLP_DISPATCH(D, CALL_RF)
+#undef CALL_RF
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t launch_mlp_rows_grad(int D, int n, const float* params, const double* frame, const double* phi_in,
+                                const double* phi_t, const double* wrow, float* grad, double* loss, hipStream_t s)
+{
+    hipError_t e = hipSuccess;
+#define CALL_RG(DD)                                                                                             \
+    hipLaunchKernelGGL(k_mlp_rows_grad<DD>, dim3(1), dim3(256), MLP_LDS_TRAIN, s, n, params, frame, phi_in, phi_t, \
+                       wrow, grad, loss);
+    MLP_DISPATCH(D, CALL_RG)
+#undef CALL_RG
+    return e != hipSuccess ? e : hipGetLastError();
+}
+
+hipError_t mlp_prepare(int D)
+{
+    hipError_t e = hipSuccess;
+#define CALL_PREP(DD)                                                                                           \
+    e = raise_lds(k_mlp_forward<DD>, MLP_LDS_FWD);                                                              \
+    if (e == hipSuccess) e = raise_lds(k_mlp_train<DD>, MLP_LDS_TRAIN);                                         \
+    if (e == hipSuccess) e = raise_lds(k_mlp_rows_forward<DD>, MLP_LDS_FWD);                                    \
+    if (e == hipSuccess) e = raise_lds(k_mlp_rows_grad<DD>, MLP_LDS_TRAIN);
+    MLP_DISPATCH(D, CALL_PREP)
+#undef CALL_PREP
+    return e;
+}
+
+void mlp_init_host(int D, uint64_t seed, float* w)
+{
+    const int H = MLP_H, P = mlp_nout(D), n = mlp_nparams(D);
+    for (int i = 0; i < n; ++i) {
+        const W4 x = philox10((uint32_t)i, 0u, 0u, S_MLP_INIT << 24, (uint32_t)seed, (uint32_t)(seed >> 32));
+        const double u = u53(x.x, x.y);
+        double bound = 0.0;
+        if (i < H * D) bound = 1.0 / sqrt((double)D);
+        else if (i >= H * D + H && i < H * D + H + H * H) bound = 1.0 / sqrt((double)H);
+        else if (i >= H * D + 2 * H + H * H && i < H * D + 2 * H + H * H + P * H) bound = 0.01 / sqrt((double)H);
+        w[i] = (float)((2.0 * u - 1.0) * bound);
+    }
+    float* b3 = w + (H * D + 2 * H + H * H + P * H);
+    const double diag0 = log(expm1(1.0 - (double)MLP_EPS));
+    for (int i = 0; i < D; ++i) b3[D + i * (i + 1) / 2 + i] = (float)diag0;
+}
+
+}  // namespace smc2

@@ -28,6 +28,11 @@ struct OuterArrays {
     double* records;   // [R][K][record_len]
     int32_t* status;   // [R]       0, or -4 when every weight of the run vanished
     int32_t* k_dev;    // iteration counter
+    // learned proposal (NULL unless the configuration uses it)
+    const int32_t* mlp_use;   // [R]        1: this iteration proposes with the network
+    const float* mlp_out;     // [R][N][P]  network outputs at the current population
+    const double* mlp_frame;  // [R][D+D*D] input frame of the network: mean c, Cholesky factor F
+    double* logq;             // [R][N]     log q(phi_new | phi) of the learned proposal
 };
 
 struct OuterParams {
@@ -36,6 +41,7 @@ struct OuterParams {
     int32_t rec_len;
     const double* prior; // [D][3] {family, a, b} (device)
     const double* lrw;   // [D][D] lower Cholesky factor of the RW covariance (device)
+    int32_t mlp;         // 1: the learned proposal is configured
 };
 
 hipError_t launch_begin_iteration(const OuterArrays& o, int32_t* queues, int n_queues, hipStream_t s);

@@ -66,13 +66,46 @@ __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, c
         double z[D];
 #pragma unroll
         for (int d = 0; d < D; ++d) z[d] = normal_call(i, 0u, k << 16, (S_RW << 24) | (uint32_t)d, seed);
-        const double* ph = o.phi + (size_t)g * D;
+        if (p.mlp && o.mlp_use[r]) {
+            // learned proposal: phi' = c + F (a + L z) from the network outputs at phi,
+            // with its exact log-density (normalisation Jacobian included)
+            constexpr int P = D + D * (D + 1) / 2;
+            const float* out = o.mlp_out + (size_t)g * P;
+            const double* fr = o.mlp_frame + (size_t)r * (D + D * D);
+            double L[D * (D + 1) / 2];
 #pragma unroll
-        for (int d = 0; d < D; ++d) {
-            double acc = 0.0;
+            for (int a = 0; a < D; ++a)
 #pragma unroll
-            for (int e = 0; e <= d; ++e) acc += p.lrw[d * D + e] * z[e];
-            phin[d] = ph[d] + acc;
+                for (int b = 0; b <= a; ++b) {
+                    const double x = (double)out[D + a * (a + 1) / 2 + b];
+                    L[a * (a + 1) / 2 + b] = (a == b) ? (x > 30.0 ? x : log1p(exp(x))) + 1e-3 : x;
+                }
+            double lq = -0.5 * D * LOG_2PI, u[D];
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                double sa = (double)out[a];
+#pragma unroll
+                for (int b = 0; b <= a; ++b) sa += L[a * (a + 1) / 2 + b] * z[b];
+                u[a] = sa;
+                lq -= 0.5 * z[a] * z[a] + log(L[a * (a + 1) / 2 + a]) + log(fr[D + a * D + a]);
+            }
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                double sa = fr[a];
+#pragma unroll
+                for (int b = 0; b <= a; ++b) sa += fr[D + a * D + b] * u[b];
+                phin[a] = sa;
+            }
+            o.logq[g] = lq;
+        } else {
+            const double* ph = o.phi + (size_t)g * D;
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                double acc = 0.0;
+#pragma unroll
+                for (int e = 0; e <= d; ++e) acc += p.lrw[d * D + e] * z[e];
+                phin[d] = ph[d] + acc;
+            }
         }
     }
     double lpn = 0.0;
@@ -242,6 +275,9 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
     for (int e = tid; e < D * D; e += nthr) Lq[e] = p.lrw[e];
     __syncthreads();
 
+    // proposal of this iteration: the learned one (then its density is in o.logq)
+    const bool learned = p.mlp && k >= 2 && uniform_bool(o.mlp_use[r] != 0);
+
     // ---------------- approximately optimal L-kernel (k > 1)
     bool ratio_only = (p.lkernel == L_FORWARD);
     int fallback = 0;
@@ -342,7 +378,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
                         m[a2] = s;
                     }
                     const double lL = mvn_logpdf<D>(xo, m, LS);
-                    const double lq = mvn_logpdf<D>(xn, xo, Lq);
+                    const double lq = learned ? o.logq[base + i] : mvn_logpdf<D>(xn, xo, Lq);
                     v = v + (lL - lq);
                 }
             }
@@ -427,6 +463,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
         rec[3] = (double)dead;
         rec[4] = (double)fallback;
         rec[5] = W;
+        rec[p.rec_len - 2] = learned ? 1.0 : 0.0;
         for (int a2 = 0; a2 < D; ++a2) {
             rec[6 + a2] = mth[a2];
             rec[6 + D + D * D + a2] = mph[a2];

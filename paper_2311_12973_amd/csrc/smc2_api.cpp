@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/smc2.h"
+#include "mlp_kernels.h"
 #include "outer_kernels.h"
 #include "pf_kernel.h"
 
@@ -58,7 +59,8 @@ struct Layout {
     size_t total = 0;
     size_t off_k, off_status, off_seeds, off_runs, off_y, off_prior, off_lrw, off_phi, off_phin, off_thn, off_lp,
         off_ll, off_logw, off_lpn, off_lln, off_lwp, off_scr, off_qc, off_anc, off_active, off_rec, off_items,
-        off_queues, off_tune_items;
+        off_queues, off_tune_items, off_mlp_params, off_mlp_m, off_mlp_v, off_mlp_grad, off_mlp_t, off_mlp_frame,
+        off_mlp_use, off_mlp_out, off_mlp_logq, off_mlp_score;
     size_t take(size_t bytes)
     {
         const size_t o = total;
@@ -97,6 +99,19 @@ Layout make_layout(const smc2_config* c, int R, const smc2_run* runs)
     L.off_items = L.take(sizeof(int32_t) * RN);
     L.off_queues = L.take(sizeof(int32_t) * MAX_GROUPS);
     L.off_tune_items = L.take(sizeof(int32_t) * RN);
+    const bool mlp = c->proposal == SMC2_PROP_MLP;
+    const size_t NP = mlp ? (size_t)mlp_nparams(c->D) : 0, P = mlp ? (size_t)mlp_nout(c->D) : 0;
+    const size_t Rm = mlp ? (size_t)R : 0;
+    L.off_mlp_params = L.take(sizeof(float) * Rm * NP);
+    L.off_mlp_m = L.take(sizeof(float) * Rm * NP);
+    L.off_mlp_v = L.take(sizeof(float) * Rm * NP);
+    L.off_mlp_grad = L.take(sizeof(float) * Rm * NP);
+    L.off_mlp_t = L.take(sizeof(int32_t) * Rm);
+    L.off_mlp_frame = L.take(sizeof(double) * Rm * (D + D * D));
+    L.off_mlp_use = L.take(sizeof(int32_t) * Rm);
+    L.off_mlp_out = L.take(sizeof(float) * Rm * N * P);
+    L.off_mlp_logq = L.take(sizeof(double) * Rm * N);
+    L.off_mlp_score = L.take(sizeof(double) * Rm * 2);
     return L;
 }
 
@@ -130,6 +145,8 @@ struct smc2_ctx {
     Layout lay;
     OuterArrays oa{};
     OuterParams op{};
+    MlpArrays ma{};
+    MlpParams mp{};
     PFArgs pa{};
     const uint64_t* d_seeds = nullptr;
     std::vector<PFGroup> groups;
@@ -166,7 +183,14 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
     if (c->N < 2 || c->N > 32768) return m = "N must be in [2, 32768]", SMC2_E_ARG;
     if (c->K < 1 || c->K > 65535) return m = "K must be in [1, 65535]", SMC2_E_ARG;
     if (c->precision != SMC2_PREC_FP32 && c->precision != SMC2_PREC_FP64) return m = "bad precision", SMC2_E_ARG;
-    if (c->proposal != SMC2_PROP_RW) return m = "unknown proposal", SMC2_E_UNSUPPORTED;
+    if (c->proposal != SMC2_PROP_RW && c->proposal != SMC2_PROP_MLP) return m = "unknown proposal", SMC2_E_UNSUPPORTED;
+    if (c->proposal == SMC2_PROP_MLP) {
+        if (c->lkernel != SMC2_L_GAUSS_OPT)
+            return m = "the learned proposal needs the approximately optimal L-kernel", SMC2_E_UNSUPPORTED;
+        if (c->mlp_epochs < 0 || c->mlp_epochs > 1000) return m = "mlp_epochs must be in [0, 1000]", SMC2_E_ARG;
+        if (c->mlp_batch < 0) return m = "mlp_batch must be >= 0", SMC2_E_ARG;
+        if (!(c->mlp_lr > 0.0 && c->mlp_lr < 1.0)) return m = "mlp_lr must be in (0, 1)", SMC2_E_ARG;
+    }
     if (c->lkernel != SMC2_L_FORWARD && c->lkernel != SMC2_L_GAUSS_OPT) return m = "unknown L-kernel", SMC2_E_ARG;
     if (!(c->n_pop >= 1.0 && c->n_pop <= 16777216.0 && c->n_pop == std::floor(c->n_pop)))
         return m = "n_pop must be an integer in [1, 2^24]", SMC2_E_ARG;
@@ -451,6 +475,23 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     o.records = (double*)(w + lay.off_rec);
     o.status = (int32_t*)(w + lay.off_status);
     o.k_dev = (int32_t*)(w + lay.off_k);
+    const bool mlp = cfg->proposal == SMC2_PROP_MLP;
+    if (mlp) {
+        MlpArrays& ma = c->ma;
+        ma.params = (float*)(w + lay.off_mlp_params);
+        ma.adam_m = (float*)(w + lay.off_mlp_m);
+        ma.adam_v = (float*)(w + lay.off_mlp_v);
+        ma.grad = (float*)(w + lay.off_mlp_grad);
+        ma.adam_t = (int32_t*)(w + lay.off_mlp_t);
+        ma.frame = (double*)(w + lay.off_mlp_frame);
+        ma.use = (int32_t*)(w + lay.off_mlp_use);
+        ma.out = (float*)(w + lay.off_mlp_out);
+        ma.score = (double*)(w + lay.off_mlp_score);
+        o.mlp_use = ma.use;
+        o.mlp_out = ma.out;
+        o.mlp_frame = ma.frame;
+        o.logq = (double*)(w + lay.off_mlp_logq);
+    }
     OuterParams& p = c->op;
     p.N = cfg->N;
     p.D = cfg->D;
@@ -460,6 +501,19 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     p.rec_len = SMC2_RECORD_LEN(cfg->D);
     p.prior = (const double*)(w + lay.off_prior);
     p.lrw = (const double*)(w + lay.off_lrw);
+    p.mlp = mlp ? 1 : 0;
+    {
+        MlpParams& q = c->mp;
+        q.D = cfg->D;
+        q.N = cfg->N;
+        q.R = n_runs;
+        q.K = cfg->K;
+        q.epochs = cfg->mlp_epochs;
+        q.batch = cfg->mlp_batch;
+        q.lr = (float)cfg->mlp_lr;
+        q.rec_len = SMC2_RECORD_LEN(cfg->D);
+        q.lrw = p.lrw;
+    }
     c->d_seeds = (const uint64_t*)(w + lay.off_seeds);
     PFArgs& a = c->pa;
     a.theta = o.theta_new;
@@ -487,6 +541,17 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     H2D(lay.off_prior, c->prior.data(), sizeof(double) * c->prior.size());
     H2D(lay.off_lrw, lrw.data(), sizeof(double) * lrw.size());
     H2D(lay.off_items, items.data(), sizeof(int32_t) * items.size());
+    std::vector<float> init_params;
+    if (mlp && e == hipSuccess) e = mlp_prepare(cfg->D);
+    if (mlp) {
+        const size_t NP = (size_t)mlp_nparams(cfg->D);
+        init_params.resize(NP * n_runs);
+        for (int r = 0; r < n_runs; ++r) mlp_init_host(cfg->D, runs[r].seed, init_params.data() + NP * r);
+        H2D(lay.off_mlp_params, init_params.data(), sizeof(float) * init_params.size());
+        const size_t zero_from = lay.off_mlp_m, zero_to = lay.off_mlp_out;  // moments, grad, steps, frame, use
+        if (e == hipSuccess) e = hipMemsetAsync(w + zero_from, 0, zero_to - zero_from, s);
+        if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_mlp_score, 0, sizeof(double) * 2 * n_runs, s);
+    }
     if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_k, 0, sizeof(int32_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_status, 0, sizeof(int32_t) * n_runs, s);
     if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_logw, 0, sizeof(double) * n_runs * N, s);
@@ -518,6 +583,7 @@ static hipError_t enqueue_iteration(smc2_ctx* c, hipStream_t s, hipEvent_t pf0, 
 {
     int32_t* queues = (int32_t*)(c->ws + c->lay.off_queues);
     hipError_t e = launch_begin_iteration(c->oa, queues, (int)c->groups.size(), s);
+    if (e == hipSuccess && c->op.mlp) e = launch_mlp_forward(c->ma, c->mp, c->oa, s);
     if (e == hipSuccess) e = launch_propose(c->oa, c->op, c->d_seeds, s);
     if (e == hipSuccess && pf0) e = hipEventRecord(pf0, s);
     for (size_t gi = 0; gi < c->groups.size(); ++gi) {
@@ -531,6 +597,7 @@ static hipError_t enqueue_iteration(smc2_ctx* c, hipStream_t s, hipEvent_t pf0, 
     }
     if (e == hipSuccess && pf1) e = hipEventRecord(pf1, s);
     if (e == hipSuccess) e = launch_outer_update(c->oa, c->op, c->d_seeds, s);
+    if (e == hipSuccess && c->op.mlp) e = launch_mlp_train(c->ma, c->mp, c->oa, c->d_seeds, s);
     return e;
 }
 
@@ -645,6 +712,36 @@ extern "C" int smc2_dump(smc2_ctx* c, int32_t what, int32_t run, void* host_dst,
     case SMC2_DUMP_LL_NEW: src = c->oa.ll_new + base; need = N * 8; break;
     case SMC2_DUMP_LOGW_PRE: src = c->oa.logw_pre + base; need = N * 8; break;
     case SMC2_DUMP_ANC: src = c->oa.anc + base; need = N * 4; break;
+    case SMC2_DUMP_MLP_OUT:
+    case SMC2_DUMP_LOGQ:
+    case SMC2_DUMP_MLP_PARAMS:
+    case SMC2_DUMP_MLP_FRAME:
+    case SMC2_DUMP_MLP_STATE: {
+        if (!c->op.mlp) return c->fail(SMC2_E_ARG, "the context has no learned proposal");
+        const size_t NP = (size_t)mlp_nparams((int)D), P = (size_t)mlp_nout((int)D);
+        if (what == SMC2_DUMP_MLP_OUT) src = c->ma.out + base * P, need = N * P * 4;
+        if (what == SMC2_DUMP_LOGQ) src = c->oa.logq + base, need = N * 8;
+        if (what == SMC2_DUMP_MLP_PARAMS) src = c->ma.params + (size_t)run * NP, need = NP * 4;
+        if (what == SMC2_DUMP_MLP_FRAME) src = c->ma.frame + (size_t)run * (D + D * D), need = (D + D * D) * 8;
+        if (what == SMC2_DUMP_MLP_STATE) {
+            if (bytes < 4 * 8) return c->fail(SMC2_E_ARG, "destination too small");
+            if (c->poisoned) return c->fail(SMC2_E_DEVICE, "context poisoned by an earlier device error");
+            int32_t ut[2] = {0, 0};
+            double sc[2] = {0.0, 0.0};
+            hipError_t e = hipStreamSynchronize(c->stream);
+            if (e == hipSuccess) e = hipMemcpy(&ut[0], c->ma.use + run, 4, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) e = hipMemcpy(&ut[1], c->ma.adam_t + run, 4, hipMemcpyDeviceToHost);
+            if (e == hipSuccess) e = hipMemcpy(sc, c->ma.score + 2 * (size_t)run, 16, hipMemcpyDeviceToHost);
+            if (e != hipSuccess) return c->device_fail(e, "dump");
+            double* d = (double*)host_dst;
+            d[0] = ut[0];
+            d[1] = ut[1];
+            d[2] = sc[0];
+            d[3] = sc[1];
+            return SMC2_OK;
+        }
+        break;
+    }
     default: return c->fail(SMC2_E_ARG, "unknown dump");
     }
     if (bytes < need) return c->fail(SMC2_E_ARG, "destination too small");

@@ -15,7 +15,7 @@
 """
 import numpy as np
 import pytest
-from scipy import stats
+from scipy import linalg, stats
 
 import oracle as O
 from paper_2311_12973_amd import workloads as W
@@ -159,32 +159,57 @@ def test_training_learns_a_gaussian_population():
         use, t, frame, nm, nr = O.mlp_train(cfg, phi, np.zeros(N), 7, k, w, m, v, t)
     assert use == 1 and nm < nr
     # outputs at a few inputs: a Gaussian close to the population's
-    c, s = frame[:D], frame[D:]
+    c, F = frame[:D], frame[D:].reshape(D, D)
     for x in phi[:5]:
-        o, _, _ = O.mlp_forward(D, w, (x - c) / s)
+        o, _, _ = O.mlp_forward(D, w, linalg.solve_triangular(F, x - c, lower=True))
         L = np.zeros((D, D))
         for i in range(D):
             for j in range(i + 1):
                 y = o[D + i * (i + 1) // 2 + j]
                 L[i, j] = np.log1p(np.exp(y)) + 1e-3 if i == j else y
-        mean = c + s * o[:D]
-        cov = np.diag(s) @ L @ L.T @ np.diag(s)
+        mean = c + F @ o[:D]
+        cov = F @ L @ L.T @ F.T
         assert np.allclose(mean, mu, atol=0.1)
         assert np.allclose(cov, A @ A.T, atol=0.04)
+
+
+def _random_frame(rng, D):
+    F = np.tril(rng.normal(scale=0.5, size=(D, D)), -1) + np.diag(rng.uniform(0.1, 3.0, D))
+    return np.concatenate([rng.normal(size=D), F.ravel()])
+
+
+def test_frame_is_the_weighted_gaussian_fit():
+    """The frame holds the weighted mean and the lower Cholesky factor of the weighted
+    covariance; a population with a constant coordinate falls back to the diagonal of
+    standard deviations (floored at 1e-6)."""
+    rng = np.random.default_rng(11)
+    N, D = 500, 4
+    phi = rng.normal(size=(N, D)) @ rng.normal(size=(D, D)) + rng.normal(size=D)
+    wn = rng.uniform(0, 1, N)
+    wn /= wn.sum()
+    fr = O.mlp_frame(phi, wn)
+    F = fr[D:].reshape(D, D)
+    assert np.allclose(fr[:D], np.average(phi, axis=0, weights=wn), rtol=1e-12, atol=1e-12)
+    assert np.array_equal(F, np.tril(F)) and np.all(np.diag(F) > 0)
+    assert np.allclose(F @ F.T, np.cov(phi.T, aweights=wn, bias=True), rtol=1e-10, atol=1e-12)
+    phi[:, 2] = 0.7
+    fr = O.mlp_frame(phi, wn)
+    sd = np.sqrt(np.maximum(np.diag(np.cov(phi.T, aweights=wn, bias=True)), 0))
+    assert np.allclose(fr[D:].reshape(D, D), np.diag(np.maximum(sd, 1e-6)), rtol=1e-10, atol=1e-15)
 
 
 def test_proposal_density_with_normalisation_jacobian():
     D = 4
     rng = np.random.default_rng(5)
-    frame = np.concatenate([rng.normal(size=D), rng.uniform(0.1, 3.0, D)])
+    frame = _random_frame(rng, D)
     o = rng.normal(size=O.mlp_nout(D))
     L = np.zeros((D, D))
     for i in range(D):
         for j in range(i + 1):
             x = o[D + i * (i + 1) // 2 + j]
             L[i, j] = np.log1p(np.exp(x)) + 1e-3 if i == j else x
-    S = np.diag(frame[D:])
-    dist = stats.multivariate_normal(frame[:D] + frame[D:] * o[:D], S @ L @ L.T @ S)
+    F = frame[D:].reshape(D, D)
+    dist = stats.multivariate_normal(frame[:D] + F @ o[:D], F @ L @ L.T @ F.T)
     draws = []
     for i in range(4000):
         phn, lq = O.mlp_propose_one(D, frame, o, 9, 3, i)
