@@ -213,6 +213,121 @@ __device__ __forceinline__ bool btrs_final(const BtrsConst<real>& c, int32_t n, 
     return lhs <= rhs;
 }
 
+// The same test evaluated in FP32 with a bound on its distance from the FP64
+// evaluation above; returns 1 (accept), -1 (reject), or 0 when the FP32 value is
+// too close to the boundary to decide (then the FP64 test decides). Exact algebra
+// on the test: with m = floor((n+1)p), d = k - m, A = k+1, B = n-k+1 and
+// lfact(x) = (x+1/2) log(x+1) - (x+1) + log(2 pi)/2 + fc(x), the FP64 right-hand side is
+//   (m+1/2) log((m+1)/A) + (n-m+1/2) log((n-m+1)/B) + d log(p B / (q A))
+//     + fc(m) + fc(n-m) - fc(k) - fc(n-k),
+// whose first two terms are each about +-d and cancel. With x1 = -d/A, x2 = d/B,
+// log((m+1)/A) = log1p(x1) and log((n-m+1)/B) = log1p(x2); for |x| <= 1/8,
+// log1p(x) = x + g(x) with g from its alternating series (terms to x^10, truncation
+// below 2^-28 |g|), and when both are that small the two linear parts add up to the
+// cancellation-free d [(d - 1/2)/B + (d + 1/2)/A]. Larger |x| take the logarithm of
+// the ratio, which is then at least 0.11 in magnitude. In the third term
+// p B - q A = ((n+1)p - m) + p - d - 1 + ((1-p) - q) A (q is 1 - p rounded to FP32,
+// as in the FP64 test) is formed in FP64 without cancellation. Reciprocals and
+// base-2 logarithms are the hardware instructions (relative error below 2^-22 on
+// gfx950), so every piece carries a relative error of a few tens of FP32 units at
+// most and 2^-17 times the sum of the magnitudes bounds the FP32 error;
+// 2^-46 (n+1)(1 + log2(n+2)) bounds the FP64 evaluation's own error (terms of size n ln n, a
+// few roundings each). A decision taken outside both bounds is the FP64 decision.
+// Needs n < 2^23 (integers exact in FP32).
+static __constant__ float c_fc_tab[16] = {
+    0.081061466795327f, 0.041340695955409f, 0.027677925684998f, 0.020790672103766f,
+    0.016644691189821f, 0.013876128823073f, 0.011896709945893f, 0.010411265261974f,
+    0.009255462182709f, 0.008330563433359f, 0.007573675487949f, 0.006942840107207f,
+    0.006408994188003f, 0.005951370112758f, 0.005554733551964f, 0.005207655919605f};
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_ln(float x) { return __builtin_amdgcn_logf(x) * 0.693147181f; }
+
+// fc(x): the table below 16, else the Stirling series 1/(12z) - 1/(360z^3), z = x+1
+// (the next term, 1/(1260 z^5) < 6e-10, and rounding stay below 1e-8)
+__device__ __forceinline__ float btrs_fc(int32_t x)
+{
+    if (x < 16) return c_fc_tab[x];
+    const float r = fast_rcp((float)(x + 1));
+    return r * (0.0833333333f - (r * r) * 0.00277777778f);
+}
+
+// g(x) = log1p(x) - x for |x| <= 1/8, alternating series through x^10
+__device__ __forceinline__ float log1p_minus_x(float x)
+{
+    float h = -0.1f;
+    h = fmaf(h, x, 0.11111111f);
+    h = fmaf(h, x, -0.125f);
+    h = fmaf(h, x, 0.14285714f);
+    h = fmaf(h, x, -0.16666667f);
+    h = fmaf(h, x, 0.2f);
+    h = fmaf(h, x, -0.25f);
+    h = fmaf(h, x, 0.33333333f);
+    h = fmaf(h, x, -0.5f);
+    return (x * x) * h;
+}
+
+template <typename real>
+__device__ __forceinline__ int btrs_final_fast(const BtrsConst<real>& c, int32_t n, real p, int64_t k, uint32_t wu,
+                                               uint32_t wv)
+{
+    if constexpr (sizeof(real) != 4) {
+        return 0;
+    } else {
+        if (n >= (1 << 23)) return 0;
+        const float u = u24(wu) - 0.5f;
+        const float v = u24(wv);
+        const float us = 0.5f - fabsf(u);
+        const float q = 1.0f - p;
+        const double mp = (double)(n + 1) * (double)p;  // exact: 24-bit times 24-bit
+        const double mfl = floor(mp);
+        const int32_t m = (int32_t)mfl;
+        const int32_t ki = (int32_t)k;
+        const int32_t d = ki - m;
+        const float df = (float)d;
+        const float A = (float)(ki + 1), B = (float)(n - ki + 1);
+        const float rA = fast_rcp(A), rB = fast_rcp(B);
+        const float mh = (float)m + 0.5f, nmh = (float)(n - m) + 0.5f;
+        // (m+1/2) log((m+1)/A) + (n-m+1/2) log((n-m+1)/B)
+        const float x1 = -df * rA, x2 = df * rB;
+        const bool s1 = fabsf(x1) <= 0.125f, s2 = fabsf(x2) <= 0.125f;
+        const float lin = (s1 && s2) ? df * ((df - 0.5f) * rB + (df + 0.5f) * rA)
+                                     : (s1 ? mh * x1 : 0.0f) + (s2 ? nmh * x2 : 0.0f);
+        const float b1 = mh * (s1 ? log1p_minus_x(x1) : fast_ln((float)(m + 1) * rA));
+        const float b2 = nmh * (s2 ? log1p_minus_x(x2) : fast_ln((float)(n - m + 1) * rB));
+        // d log(p B / (q A)), q = fl(1 - p) as in the FP64 test:
+        // p B - q A = (fr + p - d - 1) + ((1 - p) - q) A
+        const double dq = (1.0 - (double)p) - (double)q;  // exact
+        const float num = (float)((((mp - mfl) + (double)p) - (double)(d + 1)) + dq * (double)A);
+        const float y3 = num * fast_rcp(q * A);
+        const float l3 = fabsf(y3) <= 0.125f ? y3 + log1p_minus_x(y3)
+                         : (y3 < -0.5f ? -fast_ln(1.0f - num * fast_rcp(p * B)) : fast_ln(1.0f + y3));
+        const float t3 = df * l3;
+        const float f = (btrs_fc(m) + btrs_fc(n - m)) - (btrs_fc(ki) + btrs_fc(n - ki));
+        // left-hand side log(v alpha / (aa / us^2 + bb))
+        const float alpha = (2.83f + 5.1f * fast_rcp(c.bb)) * c.spq;
+        const float den = c.aa * fast_rcp(us * us) + c.bb;
+        const float lhs = fast_ln((v * alpha) * fast_rcp(den));
+        const float D = (((lin + b1) + b2) + t3 + f) - lhs;
+        const float nf = (float)(n + 1);
+        const float E = 0x1p-17f * (((((fabsf(lin) + fabsf(b1)) + fabsf(b2)) + fabsf(t3)) + fabsf(f)) + fabsf(lhs) + 1.0f) +
+                        0x1p-46f * nf * (1.0f + __builtin_amdgcn_logf(nf + 1.0f));
+        return D > E ? 1 : (D < -E ? -1 : 0);
+    }
+}
+
+// The acceptance decision of a candidate that needs the final test: FP32 first, the
+// FP64 test only when the FP32 value cannot decide.
+template <typename real>
+__device__ __forceinline__ bool btrs_decide(const BtrsConst<real>& c, int32_t n, real p, int64_t k, uint32_t wu,
+                                            uint32_t wv)
+{
+    const int f = btrs_final_fast<real>(c, n, p, k, wu, wv);
+    bool acc = f > 0;
+    if (f == 0) acc = btrs_final<real>(c, n, p, k, wu, wv);
+    return acc;
+}
+
 // the value returned when 256 attempts were all rejected: the mode
 template <typename real> __device__ __forceinline__ int32_t btrs_mode(int32_t n, real p)
 {
@@ -234,7 +349,7 @@ __device__ __forceinline__ int32_t binom_btrs(int32_t n, real p, const DrawStrea
         // form "if (quick || final(...)) return k" was miscompiled for gfx950 (the
         // register holding k was reused inside the final test on the accepting path).
         bool acc = r == BTRS_ACCEPT;
-        if (r == BTRS_FINAL) acc = btrs_final<real>(c, n, p, k, wu, wv);
+        if (r == BTRS_FINAL) acc = btrs_decide<real>(c, n, p, k, wu, wv);
         if (acc) return (int32_t)k;
     }
     return btrs_mode<real>(n, p);

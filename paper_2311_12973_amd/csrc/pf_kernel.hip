@@ -358,7 +358,7 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
                 const bool flip2 = ((id2 >> 15) & 1u) != 0u;
                 const BtrsConst<real> c2 = btrs_setup<real>(n2, p2);
                 int32_t res = -1;
-                if (btrs_final<real>(c2, n2, p2, kk2, wu2, wv2)) {
+                if (btrs_decide<real>(c2, n2, p2, kk2, wu2, wv2)) {
                     res = k2;
                 } else {
                     const DrawStream ds2{(uint32_t)j2, filt, kt, (uint32_t)b2, k0, k1};

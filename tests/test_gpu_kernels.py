@@ -79,6 +79,26 @@ def test_binomial_bit_exact_many(prec):
     assert len(bad) == 0, [(int(n[j]), float(p[j]), int(got[j]), int(want[j])) for j in bad[:8]]
 
 
+def test_binomial_btrs_final_test_decisions():
+    """Four million FP32 draws in the transformed-rejection regime (n p >= 10), where
+    about a third of the attempts reach the final acceptance test: the kernels decide
+    it in FP32 with an error bound and fall back to FP64 near the boundary, and every
+    draw must equal the reference's (which always takes the FP64 test). The sizes
+    cover both sides of n = 2^23, above which the FP64 test always decides."""
+    rng = np.random.default_rng(2311)
+    M = 1 << 22
+    n = np.floor(10 ** rng.uniform(1.3, 7.4, M)).astype(np.int64)
+    n[: M // 16] = rng.integers((1 << 23) - 4096, (1 << 23) + 4096, M // 16)
+    n = np.minimum(n, (1 << 31) - 1).astype(np.int32)
+    lo = np.log10(10.0 / n)
+    p = 10 ** (lo + (np.log10(0.5) - lo) * rng.random(M))
+    p = p.astype(np.float32).astype(np.float64)
+    got = G.binomial_batch(G.PREC_FP32, n, p, seed=99, i=3, k=2, t=17, b=0)
+    want = O.binomial_many(G.PREC_FP32, n, p, 99, i=3, k=2, t=17, b=0)
+    bad = np.flatnonzero(got != want)
+    assert len(bad) == 0, [(int(n[j]), float(p[j]), int(got[j]), int(want[j])) for j in bad[:8]]
+
+
 @pytest.mark.parametrize("n", [1, 2, 63, 64, 65, 255, 256, 257, 500, 1000, 2048, 4096])
 def test_resample_bit_exact(n):
     rng = np.random.default_rng(n)
