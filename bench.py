@@ -9,10 +9,11 @@ simulated from a fixed seed.
 
 Prints one JSON line. value = particle-steps per second (theta x particle x day)
 of whole iterations, inputs resident in HBM. roofline: the particle-filter kernel
-(VALU-bound) -- its VALU lane-instruction rate against the MI355X issue peak, from
-the kernel's instruction count per particle-step (rocprofv3 SQ_INSTS_VALU) and its
-event-timed duration in this run. cpu_baseline: the CPU reference on a bounded
-sample of the same workload.
+(ALU-bound) -- algorithmic operations per second (the method's operation count per
+particle-step times the particle-steps of a launch, over the kernel's event-timed
+duration in this run) against the MI355X VALU peak; beside it the VALU issue rate
+the kernel actually sustains, from its rocprofv3 instruction counts.
+cpu_baseline: the CPU reference on a bounded sample of the same workload.
 """
 import argparse
 import json
@@ -23,21 +24,25 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Roofline of the particle-filter kernel (VALU-bound: counts and log-weights stay on chip).
-# Per-unit figure: VALU instructions executed by active lanes per particle-step,
-# SQ_INSTS_VALU x 64 x VALUUtilization / (N N_x T), from the rocprofv3 passes recorded in
-# profiles/pf_kernel_seir_n1024_nx512_t100.txt (default workload, pooled schedule).
-# HBM traffic per launch from the FETCH_SIZE / WRITE_SIZE passes of the same file,
-# calibrated against a 256 MiB device copy. Both hold only for the kernel sources they
-# were measured on (KERNEL_SHA); a changed kernel reports them as null.
+# Roofline of the particle-filter kernel: ALU-bound (counts and log-weights stay on
+# chip; its algorithmic HBM traffic is theta, y and one log-likelihood per filter).
+# Unit of work: algorithmic operations per particle-step -- the reference sampler's
+# event counts on this workload (whole run, N = 1024, K = 12) priced by the cost table
+# of oracle/opcount.py (`python -m oracle.opcount --workload seir --N 1024 --K 12`).
+# Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-operations/s.
+ALGO_OPS_PER_PSTEP = {"seir": 708.8}
+VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
+# Measured on the kernel sources with hash KERNEL_SHA (rocprofv3 passes recorded in
+# profiles/pf_kernel_seir_n1024_nx512_t100.txt, default workload and launch): VALU
+# instructions executed by active lanes per particle-step (SQ_INSTS_VALU x 64 x VALU
+# utilisation / particle-steps) and HBM bytes per launch (FETCH_SIZE / WRITE_SIZE,
+# calibrated on a 256 MiB device copy). Changed sources report them as null.
 KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_amd/csrc/pf_kernel.h",
                   "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h"]
-KERNEL_SHA = "c862ef5cfaf243b3"
+KERNEL_SHA = "440c00b7162630b0"
 PROFILED_WORKLOAD = "seir"
-VALU_LANE_INSTR_PER_PSTEP = 2057.8
-HBM_BYTES_PER_LAUNCH = 1.3087e9
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz = 3.93e13 VALU lane-instructions/s
-VALU_PEAK_LANE_INSTR = 256 * 64 * 2.4e9
+VALU_LANE_INSTR_PER_PSTEP = 1547.5
+HBM_BYTES_PER_LAUNCH = 1.2853e9
 
 
 def kernel_sha():
@@ -109,13 +114,17 @@ def main():
     roofline = None
     if not args.graph:
         launch_s = ms_pf * 1e-3
+        algo = ALGO_OPS_PER_PSTEP.get(args.workload)
+        achieved = algo * psteps / launch_s if algo else None
         measured = kernel_sha() == KERNEL_SHA and args.workload == PROFILED_WORKLOAD and args.schedule == 0
-        achieved = VALU_LANE_INSTR_PER_PSTEP * psteps / launch_s if measured else None
-        roofline = {"bound": "alu", "achieved": achieved / 1e12 if measured else None,
-                    "peak": VALU_PEAK_LANE_INSTR / 1e12, "unit": "T VALU lane-instr/s",
-                    "frac": achieved / VALU_PEAK_LANE_INSTR if measured else None,
+        issue = VALU_LANE_INSTR_PER_PSTEP * psteps / launch_s if measured else None
+        roofline = {"bound": "alu", "achieved": achieved / 1e12 if algo else None,
+                    "peak": VALU_PEAK_LANE_OPS / 1e12, "unit": "T lane-ops/s",
+                    "frac": achieved / VALU_PEAK_LANE_OPS if algo else None,
                     "traffic": HBM_BYTES_PER_LAUNCH if measured else None,
-                    "kernel": "k_pf", "kernel_ms": ms_pf, "lane_instr_per_particle_step": VALU_LANE_INSTR_PER_PSTEP,
+                    "kernel": "k_pf", "kernel_ms": ms_pf, "algorithmic_ops_per_particle_step": algo,
+                    "valu_lane_instr_per_particle_step": VALU_LANE_INSTR_PER_PSTEP if measured else None,
+                    "valu_issue_frac": issue / VALU_PEAK_LANE_OPS if measured else None,
                     "pf_particle_steps_per_s": psteps / launch_s}
 
     cpu = None

@@ -67,6 +67,8 @@ def _declare(L):
         c.c_int, P(c.c_int32)]
     L.or_binomial_many.argtypes = [c.c_int, c.c_int, P(c.c_int32), P(c.c_double), c.c_uint64] + [
         c.c_uint32] * 4 + [P(c.c_int32)]
+    L.or_events_get.argtypes = [P(c.c_double)]
+    L.or_events_reset.argtypes = []
     L.or_obs_logpmf.restype = c.c_double
     L.or_obs_logpmf.argtypes = [c.c_int, c.c_int32, c.c_int32, c.c_double]
     L.or_resample_trigger.restype = c.c_int
@@ -335,6 +337,20 @@ def outer_update(cfg, k, seed, state, phi_new, lp_new, ll_new, logq=None):
                                _p(ll_new, d), _p(logq, d) if logq is not None else None, _p(logw_pre, d),
                                _p(anc, ctypes.c_int32), _p(rec, d))
     return st, logw_pre, anc, rec
+
+
+# event counters of the particle filter (order of the OR_EV_* enumeration)
+EVENTS = ("pstep", "draw", "philox", "inv", "inv_iter", "btrs", "attempt", "final", "t64", "rs_particle")
+
+
+def events_reset():
+    lib().or_events_reset()
+
+
+def events_get():
+    out = np.zeros(len(EVENTS))
+    lib().or_events_get(_p(out, ctypes.c_double))
+    return dict(zip(EVENTS, out))
 
 
 def smc2_run(cfg, y, nx, seed, N, K, n_threads=0, dumps=False):

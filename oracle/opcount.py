@@ -1,0 +1,91 @@
+"""Algorithmic operation count per particle-step of the particle filter.
+
+Test infrastructure: this fixes the unit of work of the particle-filter kernel's
+roofline. The reference sampler counts how often its particle filter performs each
+primitive of the method (events below) over a whole SMC^2 run on a workload; each
+primitive is priced at the elementary operations (one IEEE or integer operation per
+lane: add, multiply, divide, compare, convert, logical) that its definition takes,
+with an FP64 transcendental (exp, log, log1p, expm1) counted as 20, the size of a
+range reduction plus a degree-12 polynomial. The result is the mean number of
+operations one particle-step needs, independent of how a kernel schedules them.
+
+    python -m oracle.opcount [--workload seir] [--N 128] [--K 12]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+import oracle as O  # noqa: E402
+from paper_2311_12973_amd import workloads as W  # noqa: E402
+
+# elementary operations per event (comments: what they are)
+COST = {
+    # hazard argument (2), count updates (5), observation-part arithmetic (7), weight
+    # update and running maximum (3), normalisation a - m and the FP64 weight's
+    # quantisation (3), the ESS sums of q>>8 and its square (4), log-weight store (1)
+    "pstep": 25,
+    # classification: n <= 0, p in (0, 1), flip to p <= 1/2, n p < 10 (cvt, mul, cmp),
+    # flip of the result
+    "draw": 8,
+    # 10 rounds x (two 32x32->64 products = 4 multiplies, two 3-input XORs = 4)
+    "philox": 80,
+    # inversion set-up: uniform (3), q, r = p/q, n * log1p(-p) (2), rounding (1)
+    "inv": 8,
+    # inversion step: (n-k) and its conversion, two products and the reciprocal
+    # table, f * t, k + 1, F + f, the stop and loop tests
+    "inv_iter": 11,
+    # BTRS set-up: n p q (4), sqrt, bb (2), aa (4), vr (2), centre n p + 1/2 in FP64
+    # split into integer and fraction (7), conversion (1)
+    "btrs": 21,
+    # attempt: two uniforms (7), us (2), index t (5), floor and conversion (2), k (1),
+    # range test (2), squeeze (2), word selection (1)
+    "attempt": 22,
+    # final test besides its six FP64 transcendentals (counted in t64): alpha (3),
+    # p/q (1), m (4), four log-factorials by Stirling's series (4 x 12), lhs (5),
+    # rhs (5)
+    "final": 66,
+    "t64": 20,
+    # resampled particle: 64-bit scan (2), binary search over N_x = 512 (9 x 4),
+    # gather of the counts (3), log-weight reset (1)
+    "rs_particle": 42,
+}
+
+
+def count(w, N, K, nx=None, T=None, seed=None):
+    cfg = O.config_from_workload(w)
+    y = W.observations(w)
+    if T is not None:
+        y = y[:T]
+    O.events_reset()
+    t0 = time.time()
+    out = O.smc2_run(cfg, y, nx or w["nx"], seed if seed is not None else w["seed"], N, K)
+    ev = O.events_get()
+    per = {k: v / ev["pstep"] for k, v in ev.items()}
+    ops = sum(COST[k] * per[k] for k in COST)
+    return dict(per_pstep=per, ops_per_pstep=ops, psteps=ev["pstep"], seconds=time.time() - t0,
+                status=int(out["status"]))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="seir")
+    ap.add_argument("--N", type=int, default=128)
+    ap.add_argument("--K", type=int, default=12)
+    a = ap.parse_args()
+    w = W.preset(a.workload)
+    r = count(w, a.N, a.K)
+    print(json.dumps(dict(workload=a.workload, N=a.N, nx=w["nx"], T=w["T"], K=a.K, cost=COST,
+                          per_pstep={k: round(v, 5) for k, v in r["per_pstep"].items()},
+                          ops_per_pstep=round(r["ops_per_pstep"], 1), psteps=r["psteps"],
+                          seconds=round(r["seconds"], 1)), indent=1))
+
+
+if __name__ == "__main__":
+    main()

@@ -342,6 +342,35 @@ void or_propose_rw(const or_config* cfg, int N, uint64_t seed, uint32_t k, const
     }
 }
 
+/* ------------------------------------------------------------------ event counts
+ * How often the particle filter performs each primitive of the method (particle-step,
+ * binomial draw, inversion step, BTRS set-up, attempt and final test, Philox call,
+ * FP64 transcendental, particle resampled). They feed the algorithmic operation count
+ * per particle-step (the roofline's unit of work); counting changes no result. Each
+ * thread counts in its own slots and adds them to the totals once per filter. */
+static _Thread_local double tl_ev[OR_EV_N];
+static double g_ev[OR_EV_N];
+#define OR_EV(i, v) (tl_ev[(i)] += (v))
+
+static void or_events_flush(void)
+{
+#pragma omp critical(or_events)
+    for (int e = 0; e < OR_EV_N; ++e) {
+        g_ev[e] += tl_ev[e];
+        tl_ev[e] = 0.0;
+    }
+}
+
+void or_events_get(double* out)
+{
+    for (int e = 0; e < OR_EV_N; ++e) out[e] = g_ev[e];
+}
+
+void or_events_reset(void)
+{
+    for (int e = 0; e < OR_EV_N; ++e) g_ev[e] = 0.0;
+}
+
 /* ------------------------------------------------------------------ particle filters */
 
 #define REAL float

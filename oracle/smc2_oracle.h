@@ -38,6 +38,10 @@ enum { OR_S_PF_PROP = 1, OR_S_PF_RS = 2, OR_S_PRIOR = 3, OR_S_RW = 4, OR_S_OUTER
        OR_S_MLP_INIT = 6, OR_S_MLP_PERM = 7 };
 
 #define OR_DMAX 8
+
+/* Event counters of the particle filter (see or_events_get). */
+enum { OR_EV_PSTEP = 0, OR_EV_DRAW, OR_EV_PHILOX, OR_EV_INV, OR_EV_INV_ITER, OR_EV_BTRS, OR_EV_ATTEMPT,
+       OR_EV_FINAL, OR_EV_T64, OR_EV_RS_PARTICLE, OR_EV_N };
 /* relative numerical-rank floor of the L-kernel fit (see or_lkernel_fit) */
 #define OR_LK_REL_FLOOR 1e-12
 #define OR_NFIXED 32
@@ -123,6 +127,11 @@ double or_mlp_propose_one(int D, const double* frame, const double* o, uint64_t 
 int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t seed, int N, int K,
                 int n_threads, double* rec, double* phi_dump, double* ll_dump, double* lp_dump,
                 double* logw_dump, int32_t* anc_dump);
+
+/* Totals of the event counters over every particle filter run since the last reset
+ * (out[OR_EV_N], indexed by OR_EV_*). */
+void or_events_get(double* out);
+void or_events_reset(void);
 
 #ifdef __cplusplus
 }
