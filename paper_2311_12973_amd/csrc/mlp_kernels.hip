@@ -5,13 +5,14 @@
 // whose density is evaluated exactly keeps the weights of Eq. l_weights valid. The
 // network maps a sample, whitened by the population's weighted mean c and covariance
 // Cholesky factor F (u = F^{-1} (phi - c)), to a Gaussian: mean a and lower Cholesky
-// factor L (softplus diagonal + 1e-3), and the proposal is phi' = c + F (a + L z); the
-// untrained network (a = 0, L = I) proposes the population's Gaussian fit. It is trained after every outer update on the
-// weighted population: the loss of a minibatch is the mean over its rows of
-// N w_j NLL(u_j | u_i) for a target j and a randomly paired input i (two random affine
-// permutations per epoch), minimised with Adam (0.9, 0.999, 1e-8) after clipping the
-// gradient's global norm to 100. The next iteration proposes with the network only if
-// its mean weighted NLL on a further pairing is finite and below the random walk's.
+// factor L (softplus diagonal + 1e-3), and the proposal is phi' = c + F (a + L z); an
+// output of a = 0, L = I proposes the population's Gaussian fit. The network is trained
+// after every outer update on the weighted population: the loss of a minibatch is the
+// mean over its rows of N w_j NLL(u_j | u_i) for a target j and a randomly paired
+// input i (two random affine permutations per epoch), minimised with Adam (0.9, 0.999,
+// 1e-8) after clipping the gradient's global norm to 100. The next iteration proposes
+// with the network only if its mean weighted NLL on a further pairing is finite and
+// below the random walk's.
 //
 // Tiling: a wave owns 16 rows of a 64-row sub-batch. Every matrix product is a chain
 // of v_mfma_f32_16x16x16_bf16 (lane l: A row l%16, B column l%16, k = 4(l/16)..+3;
