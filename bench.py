@@ -32,17 +32,18 @@ sys.path.insert(0, ROOT)
 # Peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-operations/s.
 ALGO_OPS_PER_PSTEP = {"seir": 708.8}
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
-# Measured on the kernel sources with hash KERNEL_SHA (rocprofv3 passes recorded in
+# Measured on the kernel sources and build flags with hash KERNEL_SHA (rocprofv3 passes recorded in
 # profiles/pf_kernel_seir_n1024_nx512_t100.txt, default workload and launch): VALU
 # instructions executed by active lanes per particle-step (SQ_INSTS_VALU x 64 x VALU
 # utilisation / particle-steps) and HBM bytes per launch (FETCH_SIZE / WRITE_SIZE,
 # calibrated on a 256 MiB device copy). Changed sources report them as null.
 KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_amd/csrc/pf_kernel.h",
-                  "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h"]
-KERNEL_SHA = "440c00b7162630b0"
+                  "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h",
+                  "paper_2311_12973_amd/build.py"]
+KERNEL_SHA = "43dcc84fe2ad747e"
 PROFILED_WORKLOAD = "seir"
-VALU_LANE_INSTR_PER_PSTEP = 1547.5
-HBM_BYTES_PER_LAUNCH = 1.2853e9
+VALU_LANE_INSTR_PER_PSTEP = 1596.6
+HBM_BYTES_PER_LAUNCH = 1.0116e6
 
 
 def kernel_sha():

@@ -18,14 +18,22 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
          "-Wno-pass-failed", "-Wno-unused-function"]
 
 
+# Per-source additions. pf_kernel.hip: MachineLICM hoists the materialisation of the
+# FP64 polynomial constants of every inlined transcendental out of the filter's loops;
+# under the 128-VGPR budget they are then spilled to scratch and reloaded each round.
+# Without that pass the constants are rematerialised where used and the kernel does
+# not spill.
+EXTRA = {"pf_kernel.hip": ["-mllvm", "-disable-machine-licm"]}
+
+
 def hipcc():
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [hipcc()] + FLAGS + (["-x", "hip"] if src.endswith(".cpp") else []) + ["-c", os.path.join(CSRC, src),
-                                                                              "-o", obj]
+    cmd = [hipcc()] + FLAGS + EXTRA.get(src, []) + (["-x", "hip"] if src.endswith(".cpp") else []) + [
+        "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s" % (src, r.stderr[-6000:]))
