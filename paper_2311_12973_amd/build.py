@@ -22,8 +22,8 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
 # FP64 polynomial constants of every inlined transcendental out of the filter's loops;
 # under the 128-VGPR budget they are then spilled to scratch and reloaded each round.
 # Without that pass the constants are rematerialised where used and the kernel does
-# not spill.
-EXTRA = {"pf_kernel.hip": ["-mllvm", "-disable-machine-licm"]}
+# not spill. The learned-proposal kernels spill the same way at D = 8.
+EXTRA = {"pf_kernel.hip": ["-mllvm", "-disable-machine-licm"], "mlp_kernels.hip": ["-mllvm", "-disable-machine-licm"]}
 
 
 def hipcc():

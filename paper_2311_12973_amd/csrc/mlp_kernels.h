@@ -16,6 +16,7 @@ namespace smc2 {
 constexpr int MLP_H = 64;
 constexpr int MLP_PPAD = 48;  // outputs padded to three 16-wide tiles (P <= 44)
 constexpr int MLP_SUB = 64;   // rows per sub-batch: four waves of 16
+constexpr int MLP_ROW = 8;    // floats per whitened population row (D <= 8)
 
 inline __host__ __device__ int mlp_nout(int D) { return D + D * (D + 1) / 2; }
 inline __host__ __device__ int mlp_nparams(int D)
@@ -35,6 +36,8 @@ struct MlpArrays {
     int32_t* use;     // [R] 1: the next iteration proposes with the network
     float* out;       // [R][N][P] outputs at the current population
     double* score;    // [R][2] held-out mean weighted NLL (network, random walk)
+    float* rows;      // [R][N][MLP_ROW] the population whitened in the current frame (training scratch)
+    double* wfull;    // [R][N] N w_i, the normalised weights times N (training scratch)
 };
 
 struct MlpParams {

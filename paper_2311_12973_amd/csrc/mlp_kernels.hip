@@ -112,9 +112,11 @@ __device__ void mlp_load_weights(int D, const float* w, MlpW* L)
 
 // acc += A[16 x K] W^T: A rows FP32 (stride lda), W[n][k] BF16 (stride ldw) from the
 // tile's first output column
-__device__ __forceinline__ f32x4 mm_a_wt(const float* A, int lda, const short* W, int ldw, int K, f32x4 acc)
+template <int K>
+__device__ __forceinline__ f32x4 mm_a_wt(const float* A, int lda, const short* W, int ldw, f32x4 acc)
 {
     const int l = lane_id(), i = l & 15, kq = (l >> 4) << 2;
+#pragma unroll
     for (int k0 = 0; k0 < K; k0 += 16) {
         bf16x4 a, b;
 #pragma unroll
@@ -128,9 +130,11 @@ __device__ __forceinline__ f32x4 mm_a_wt(const float* A, int lda, const short* W
 }
 
 // acc += A[16 x K] W: W[k][n] BF16 (stride ldw) from the tile's first output column
-__device__ __forceinline__ f32x4 mm_a_w(const float* A, int lda, const short* W, int ldw, int K, f32x4 acc)
+template <int K>
+__device__ __forceinline__ f32x4 mm_a_w(const float* A, int lda, const short* W, int ldw, f32x4 acc)
 {
     const int l = lane_id(), i = l & 15, kq = (l >> 4) << 2;
+#pragma unroll
     for (int k0 = 0; k0 < K; k0 += 16) {
         bf16x4 a, b;
 #pragma unroll
@@ -145,9 +149,11 @@ __device__ __forceinline__ f32x4 mm_a_w(const float* A, int lda, const short* W,
 
 // acc += X^T Y over K rows: X[rows][m] and Y[rows][n] FP32, from the tile's first
 // output row / column
-__device__ __forceinline__ f32x4 mm_xt_y(const float* X, int ldx, const float* Y, int ldy, int K, f32x4 acc)
+template <int K>
+__device__ __forceinline__ f32x4 mm_xt_y(const float* X, int ldx, const float* Y, int ldy, f32x4 acc)
 {
     const int l = lane_id(), i = l & 15, kq = (l >> 4) << 2;
+#pragma unroll
     for (int k0 = 0; k0 < K; k0 += 16) {
         bf16x4 a, b;
 #pragma unroll
@@ -167,7 +173,7 @@ __device__ void mlp_fwd16(const MlpW* W, MlpAct* A, int r0)
     for (int jb = 0; jb < 4; ++jb) {
         const float bb = W->b1[jb * 16 + j];
         f32x4 acc = {bb, bb, bb, bb};
-        acc = mm_a_wt(A->U + r0 * LD16, LD16, W->W1 + jb * 16 * 16, 16, 16, acc);
+        acc = mm_a_wt<16>(A->U + r0 * LD16, LD16, W->W1 + jb * 16 * 16, 16, acc);
 #pragma unroll
         for (int c = 0; c < 4; ++c) A->H1[(r0 + rq + c) * LD64 + jb * 16 + j] = tanhf(acc[c]);
     }
@@ -175,7 +181,7 @@ __device__ void mlp_fwd16(const MlpW* W, MlpAct* A, int r0)
     for (int jb = 0; jb < 4; ++jb) {
         const float bb = W->b2[jb * 16 + j];
         f32x4 acc = {bb, bb, bb, bb};
-        acc = mm_a_wt(A->H1 + r0 * LD64, LD64, W->W2 + jb * 16 * MLP_H, MLP_H, MLP_H, acc);
+        acc = mm_a_wt<MLP_H>(A->H1 + r0 * LD64, LD64, W->W2 + jb * 16 * MLP_H, MLP_H, acc);
 #pragma unroll
         for (int c = 0; c < 4; ++c) A->H2[(r0 + rq + c) * LD64 + jb * 16 + j] = tanhf(acc[c]);
     }
@@ -183,7 +189,7 @@ __device__ void mlp_fwd16(const MlpW* W, MlpAct* A, int r0)
     for (int pb = 0; pb < 3; ++pb) {
         const float bb = W->b3[pb * 16 + j];
         f32x4 acc = {bb, bb, bb, bb};
-        acc = mm_a_wt(A->H2 + r0 * LD64, LD64, W->W3 + pb * 16 * MLP_H, MLP_H, MLP_H, acc);
+        acc = mm_a_wt<MLP_H>(A->H2 + r0 * LD64, LD64, W->W3 + pb * 16 * MLP_H, MLP_H, acc);
 #pragma unroll
         for (int c = 0; c < 4; ++c) A->O[(r0 + rq + c) * LD48 + pb * 16 + j] = acc[c];
     }
@@ -196,7 +202,7 @@ __device__ void mlp_bwd16(const MlpW* W, MlpAct* A, int r0)
     const int l = lane_id(), j = l & 15, rq = (l >> 4) << 2;
     for (int jb = 0; jb < 4; ++jb) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mm_a_w(A->O + r0 * LD48, LD48, W->W3 + jb * 16, MLP_H, MLP_PPAD, acc);
+        acc = mm_a_w<MLP_PPAD>(A->O + r0 * LD48, LD48, W->W3 + jb * 16, MLP_H, acc);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int at = (r0 + rq + c) * LD64 + jb * 16 + j;
@@ -207,7 +213,7 @@ __device__ void mlp_bwd16(const MlpW* W, MlpAct* A, int r0)
     wave_sync();
     for (int jb = 0; jb < 4; ++jb) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mm_a_w(A->Z2 + r0 * LD64, LD64, W->W2 + jb * 16, MLP_H, MLP_H, acc);
+        acc = mm_a_w<MLP_H>(A->Z2 + r0 * LD64, LD64, W->W2 + jb * 16, MLP_H, acc);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             const int at = (r0 + rq + c) * LD64 + jb * 16 + j;
@@ -226,11 +232,11 @@ __device__ void mlp_wgrad(const MlpAct* A, f32x4 (&acc)[8])
     for (int q = 0; q < 8; ++q) {
         const int t = w + 4 * q;
         if (t < 12) {
-            acc[q] = mm_xt_y(A->O + (t >> 2) * 16, LD48, A->H2 + (t & 3) * 16, LD64, MLP_SUB, acc[q]);
+            acc[q] = mm_xt_y<MLP_SUB>(A->O + (t >> 2) * 16, LD48, A->H2 + (t & 3) * 16, LD64, acc[q]);
         } else if (t < 28) {
-            acc[q] = mm_xt_y(A->Z2 + ((t - 12) >> 2) * 16, LD64, A->H1 + ((t - 12) & 3) * 16, LD64, MLP_SUB, acc[q]);
+            acc[q] = mm_xt_y<MLP_SUB>(A->Z2 + ((t - 12) >> 2) * 16, LD64, A->H1 + ((t - 12) & 3) * 16, LD64, acc[q]);
         } else {
-            acc[q] = mm_xt_y(A->Z1 + (t - 28) * 16, LD64, A->U, LD16, MLP_SUB, acc[q]);
+            acc[q] = mm_xt_y<MLP_SUB>(A->Z1 + (t - 28) * 16, LD64, A->U, LD16, acc[q]);
         }
     }
 }
@@ -498,6 +504,19 @@ __global__ void __launch_bounds__(256) k_mlp_train(MlpArrays m, MlpParams p, Out
     double* fr_out = m.frame + (size_t)r * (D + D * D);
     for (int d = tid; d < D + D * D; d += nthr) fr_out[d] = frs[d];
 
+    // the population once in the network's frame: whitened rows and N w_i (FP64), read
+    // by the sub-batches below in their random pairing order
+    float* rows = m.rows + (size_t)r * N * MLP_ROW;
+    double* wfull = m.wfull + (size_t)r * N;
+    for (int i = tid; i < N; i += nthr) {
+        float u[16];
+        mlp_whiten<D>(frs, phi + (size_t)i * D, u);
+#pragma unroll
+        for (int d = 0; d < MLP_ROW; ++d) rows[(size_t)i * MLP_ROW + d] = d < D ? u[d] : 0.f;
+        wfull[i] = (double)N * exp(logw[i] - LW);
+    }
+    __syncthreads();
+
     const int B = (p.batch < 1 || p.batch > N) ? N : p.batch;
     int t_adam = m.adam_t[r];
     mlp_load_weights(D, prm, W);
@@ -506,33 +525,41 @@ __global__ void __launch_bounds__(256) k_mlp_train(MlpArrays m, MlpParams p, Out
         uint64_t ta, tb, ia, ib;
         mlp_perm_dev(seed, (uint32_t)k, (uint32_t)ep, 0u, N, ta, tb);
         mlp_perm_dev(seed, (uint32_t)k, (uint32_t)ep, 1u, N, ia, ib);
+        // rows of sub-batch (b0, s0) of a minibatch of nb rows (threads < MLP_SUB)
+        auto fetch = [&](int b0, int s0, int nb, float* fu, float* ft, float& fw) {
+            const int rr = b0 + s0 + tid;
+#pragma unroll
+            for (int d = 0; d < MLP_ROW; ++d) fu[d] = ft[d] = 0.f;
+            fw = 0.f;
+            if (s0 + tid < nb) {
+                const int jt = (int)((ta * (uint64_t)rr + tb) % (uint64_t)N);
+                const int ii = (int)((ia * (uint64_t)rr + ib) % (uint64_t)N);
+#pragma unroll
+                for (int d = 0; d < MLP_ROW; ++d) {
+                    fu[d] = rows[(size_t)ii * MLP_ROW + d];
+                    ft[d] = rows[(size_t)jt * MLP_ROW + d];
+                }
+                fw = (float)(wfull[jt] / (double)nb);
+            }
+        };
         for (int b0 = 0; b0 < N; b0 += B) {
             const int nb = (N - b0) < B ? (N - b0) : B;
             f32x4 acc[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
             float bacc = 0.f;  // bias gradient of column tid (< 176)
+            float cu[MLP_ROW], ct[MLP_ROW], cw = 0.f;  // the next sub-batch's rows (threads < MLP_SUB)
+            if (tid < MLP_SUB) fetch(b0, 0, nb, cu, ct, cw);
             for (int s0 = 0; s0 < nb; s0 += MLP_SUB) {
-                // rows of the sub-batch
+                // rows of the sub-batch, then the loads of the following one, which
+                // complete while this one is computed
                 if (tid < MLP_SUB) {
-                    const int rr = b0 + s0 + tid;
-                    const bool valid = s0 + tid < nb;
-                    const int jt = valid ? (int)((ta * (uint64_t)rr + tb) % (uint64_t)N) : 0;
-                    const int ii = valid ? (int)((ia * (uint64_t)rr + ib) % (uint64_t)N) : 0;
-                    float ui[16], ut[8];
 #pragma unroll
-                    for (int d = 0; d < 16; ++d) ui[d] = 0.f;
+                    for (int d = 0; d < 16; ++d) A->U[tid * LD16 + d] = d < MLP_ROW ? cu[d] : 0.f;
 #pragma unroll
-                    for (int d = 0; d < 8; ++d) ut[d] = 0.f;
-                    if (valid) {
-                        mlp_whiten<D>(frs, phi + (size_t)ii * D, ui);
-                        mlp_whiten<D>(frs, phi + (size_t)jt * D, ut);
-                    }
-#pragma unroll
-                    for (int d = 0; d < 16; ++d) A->U[tid * LD16 + d] = ui[d];
-#pragma unroll
-                    for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = ut[d];
-                    A->wr[tid] = valid ? (float)((double)N * exp(logw[jt] - LW) / (double)nb) : 0.f;
+                    for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = ct[d];
+                    A->wr[tid] = cw;
+                    if (s0 + MLP_SUB < nb) fetch(b0, s0 + MLP_SUB, nb, cu, ct, cw);
                 }
                 __syncthreads();
                 mlp_fwd16(W, A, wave_id() * 16);
@@ -605,20 +632,12 @@ __global__ void __launch_bounds__(256) k_mlp_train(MlpArrays m, MlpParams p, Out
                 const bool valid = rr < N;
                 jt = valid ? (int)((ta * (uint64_t)rr + tb) % (uint64_t)N) : 0;
                 ii = valid ? (int)((ia * (uint64_t)rr + ib) % (uint64_t)N) : 0;
-                wt = valid ? (double)N * exp(logw[jt] - LW) : 0.0;
-                float ui[16], ut[8];
+                wt = valid ? wfull[jt] : 0.0;
 #pragma unroll
-                for (int d = 0; d < 16; ++d) ui[d] = 0.f;
+                for (int d = 0; d < 16; ++d)
+                    A->U[tid * LD16 + d] = (valid && d < MLP_ROW) ? rows[(size_t)ii * MLP_ROW + d] : 0.f;
 #pragma unroll
-                for (int d = 0; d < 8; ++d) ut[d] = 0.f;
-                if (valid) {
-                    mlp_whiten<D>(frs, phi + (size_t)ii * D, ui);
-                    mlp_whiten<D>(frs, phi + (size_t)jt * D, ut);
-                }
-#pragma unroll
-                for (int d = 0; d < 16; ++d) A->U[tid * LD16 + d] = ui[d];
-#pragma unroll
-                for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = ut[d];
+                for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = valid ? rows[(size_t)jt * MLP_ROW + d] : 0.f;
             }
             __syncthreads();
             mlp_fwd16(W, A, wave_id() * 16);

@@ -60,7 +60,7 @@ struct Layout {
     size_t off_k, off_status, off_seeds, off_runs, off_y, off_prior, off_lrw, off_phi, off_phin, off_thn, off_lp,
         off_ll, off_logw, off_lpn, off_lln, off_lwp, off_scr, off_qc, off_anc, off_active, off_rec, off_items,
         off_queues, off_tune_items, off_mlp_params, off_mlp_m, off_mlp_v, off_mlp_grad, off_mlp_t, off_mlp_frame,
-        off_mlp_use, off_mlp_out, off_mlp_logq, off_mlp_score;
+        off_mlp_use, off_mlp_out, off_mlp_logq, off_mlp_score, off_mlp_rows, off_mlp_wfull;
     size_t take(size_t bytes)
     {
         const size_t o = total;
@@ -112,6 +112,8 @@ Layout make_layout(const smc2_config* c, int R, const smc2_run* runs)
     L.off_mlp_out = L.take(sizeof(float) * Rm * N * P);
     L.off_mlp_logq = L.take(sizeof(double) * Rm * N);
     L.off_mlp_score = L.take(sizeof(double) * Rm * 2);
+    L.off_mlp_rows = L.take(sizeof(float) * Rm * N * MLP_ROW);
+    L.off_mlp_wfull = L.take(sizeof(double) * Rm * N);
     return L;
 }
 
@@ -487,6 +489,8 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
         ma.use = (int32_t*)(w + lay.off_mlp_use);
         ma.out = (float*)(w + lay.off_mlp_out);
         ma.score = (double*)(w + lay.off_mlp_score);
+        ma.rows = (float*)(w + lay.off_mlp_rows);
+        ma.wfull = (double*)(w + lay.off_mlp_wfull);
         o.mlp_use = ma.use;
         o.mlp_out = ma.out;
         o.mlp_frame = ma.frame;
