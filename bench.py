@@ -14,6 +14,8 @@ particle-step times the particle-steps of a launch, over the kernel's event-time
 duration in this run) against the MI355X VALU peak; beside it the VALU issue rate
 the kernel actually sustains, from its rocprofv3 instruction counts.
 cpu_baseline: the CPU reference on a bounded sample of the same workload.
+ess_per_s: the metric's second part -- ESS per second at the same posterior, learned
+proposal against the random walk (see ess_per_second).
 """
 import argparse
 import json
@@ -65,6 +67,7 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0, help="particle-filter draw schedule (0 auto, 1 per draw, 2 pooled)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ess", action="store_true", help="skip the learned-proposal vs random-walk ESS/s comparison")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before the timed region (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
@@ -128,6 +131,10 @@ def main():
                     "valu_issue_frac": issue / VALU_PEAK_LANE_OPS if measured else None,
                     "pf_particle_steps_per_s": psteps / launch_s}
 
+    ess = None
+    if not args.no_ess:
+        ess = ess_per_second(G, W, np)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(w, runs)
@@ -147,9 +154,46 @@ def main():
         "config": {"workload": desc, "runs": len(runs), "N": N, "global_batch": N * len(runs),
                    "particle_steps_per_iteration": psteps, "parallelism": "single GPU", "graph": bool(args.graph),
                    "dead_samples_per_step": dead, "device_ms_per_step": ms_step_dev},
-        "roofline": roofline, "cpu_baseline": cpu,
+        "roofline": roofline, "cpu_baseline": cpu, "ess_per_s": ess,
     }
     print(json.dumps(out))
+
+
+def ess_per_second(G, W, np):
+    """ESS per second at the same posterior, learned proposal vs random walk: SEIR with
+    the dispersion estimated (D = 5), T = 40, N_x = 256, K = 6; 16 independent runs of
+    each form (one batched sampler per form), the learned proposal with N = 512, the
+    random walk with N = 4096. Replicate ESS = posterior variance / variance of the
+    recycled posterior mean across runs (averaged over coordinates); per second of the
+    whole batch's iterations, per run."""
+    import torch
+
+    w = dict(W.preset("seir_learned"), T=40, mlp_epochs=4, mlp_batch=128, mlp_lr=3e-3)
+    y = W.observations(w)
+    seeds = list(range(1, 17))
+    out = {}
+    for name, prop, N in (("learned", G.PROP_MLP, 512), ("random_walk", G.PROP_RW, 4096)):
+        K = 6
+        s = G.Sampler(dict(w, proposal=prop), [dict(T=y.shape[0], nx=256, seed=sd, y=y) for sd in seeds], N=N, K=K)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(K):
+            s.step()
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        est = [s.estimate(r, recycled=True) for r in range(len(seeds))]
+        s.close()
+        means = np.array([m for m, _ in est])
+        post_var = np.mean([np.diag(c) for _, c in est], 0)
+        ess = 1.0 / float(np.mean(means.var(0, ddof=1) / post_var))
+        out[name] = {"N": N, "replicate_ess": ess, "seconds": sec, "ess_per_s_per_run": ess / (sec / len(seeds)),
+                     "posterior_mean": means.mean(0).tolist(), "posterior_sd": np.sqrt(post_var).tolist()}
+    sd = 0.5 * (np.array(out["learned"]["posterior_sd"]) + np.array(out["random_walk"]["posterior_sd"]))
+    out["mean_difference_in_sd"] = ((np.array(out["learned"]["posterior_mean"]) -
+                                     np.array(out["random_walk"]["posterior_mean"])) / sd).tolist()
+    out["speedup"] = out["learned"]["ess_per_s_per_run"] / out["random_walk"]["ess_per_s_per_run"]
+    out["workload"] = "seir_learned at T=40, N_x=256, K=6, 16 runs per form"
+    return out
 
 
 def cpu_baseline(w, runs):
