@@ -67,6 +67,9 @@ def _declare(L):
         c.c_int, P(c.c_int32)]
     L.or_binomial_many.argtypes = [c.c_int, c.c_int, P(c.c_int32), P(c.c_double), c.c_uint64] + [
         c.c_uint32] * 4 + [P(c.c_int32)]
+    L.or_pf_lg.restype = c.c_double
+    L.or_pf_lg.argtypes = [c.c_double] * 5 + [P(c.c_double), c.c_int, c.c_int, c.c_uint64, c.c_uint32, c.c_int,
+                                              P(c.c_double), P(c.c_int32)]
     L.or_events_get.argtypes = [P(c.c_double)]
     L.or_events_reset.argtypes = []
     L.or_obs_logpmf.restype = c.c_double
@@ -337,6 +340,18 @@ def outer_update(cfg, k, seed, state, phi_new, lp_new, ll_new, logq=None):
                                _p(ll_new, d), _p(logq, d) if logq is not None else None, _p(logw_pre, d),
                                _p(anc, ctypes.c_int32), _p(rec, d))
     return st, logw_pre, anc, rec
+
+
+def pf_lg(phi, sq, sr, m0, s0, y, nx, seed, filt=0, pf_always=0, trace=False):
+    """Log of the particle filter's likelihood estimate on the scalar linear-Gaussian
+    model x_t = phi x_{t-1} + sq e_t, y_t = x_t + sr d_t, x_0 ~ N(m0, s0^2)."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    T = y.shape[0]
+    inc = np.zeros(T) if trace else None
+    rs = np.zeros(T, dtype=np.int32) if trace else None
+    ll = lib().or_pf_lg(phi, sq, sr, m0, s0, _p(y, ctypes.c_double), T, nx, int(seed), int(filt), int(pf_always),
+                        _p(inc, ctypes.c_double) if trace else None, _p(rs, ctypes.c_int32) if trace else None)
+    return (ll, inc, rs) if trace else ll
 
 
 # event counters of the particle filter (order of the OR_EV_* enumeration)

@@ -124,15 +124,14 @@ double or_obs_logpmf(int obs, int32_t y, int32_t count, double r)
 
 int or_resample_trigger(const uint64_t* q, int n)
 {
-    uint64_t s1 = 0, s2 = 0;
+    /* q >> 8 <= 2^24, so for n < 2^31: s1 < 2^55, 2 s1^2 < 2^111 and n s2 < 2^110 -- exact in 128 bits */
+    unsigned __int128 s1 = 0, s2 = 0;
     for (int j = 0; j < n; ++j) {
-        uint64_t v = q[j] >> 8;
+        const uint64_t v = q[j] >> 8;
         s1 += v;
-        s2 += v * v;
+        s2 += (unsigned __int128)v * v;
     }
-    unsigned __int128 lhs = (unsigned __int128)s1 * s1 * 2u;
-    unsigned __int128 rhs = (unsigned __int128)s2 * (unsigned)n;
-    return lhs < rhs;
+    return s1 * s1 * 2u < s2 * (unsigned)n;
 }
 
 /* Systematic resampling (Eq. ncopies: ncopies^i = ceil(cdf^i - u) - ceil(cdf^{i-1} - u),
@@ -151,8 +150,8 @@ void or_resample_ancestors(const uint64_t* q, int n, uint64_t x64, int32_t* anc)
     uint64_t U = (uint64_t)(((unsigned __int128)x64 * Q) >> 64);
     int j = 0;
     for (int m = 0; m < n; ++m) {
-        uint64_t target = (uint64_t)m * Q + U;
-        while ((uint64_t)n * C[j] <= target) ++j;
+        const unsigned __int128 target = (unsigned __int128)m * Q + U;
+        while ((unsigned __int128)n * C[j] <= target) ++j;
         anc[m] = j;
     }
     free(C);
@@ -405,6 +404,58 @@ void or_binomial_many(int prec, int count, const int32_t* n, const double* p, ui
 {
 #pragma omp parallel for schedule(static)
     for (int j = 0; j < count; ++j) out[j] = or_binomial(prec, n[j], p[j], seed, (uint32_t)j, i, k, t, b);
+}
+
+/*
+ * The same particle filter on a scalar linear-Gaussian state-space model, whose exact
+ * log-likelihood the Kalman filter gives in closed form (a pin of the filter's weight
+ * recursion, likelihood increments, mean-weight reset, trigger and ancestors, which
+ * this model shares with the epidemic models through weigh_f64):
+ *   x_0 ~ N(m0, s0^2),  x_t = phi x_{t-1} + sq e_t,  y_t = x_t + sr d_t,  e, d ~ N(0, 1).
+ * Bootstrap proposal; normals from Box-Muller on the Philox counter
+ * (particle j, filter, t, 8<<24) -- t = 0 draws x_0. FP64 throughout.
+ */
+double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const double* y, int T, int nx,
+                uint64_t seed, uint32_t filt, int pf_always, double* inc_out, int32_t* rs_out)
+{
+    double* x = (double*)malloc(sizeof(double) * (size_t)nx);
+    double* xs = (double*)malloc(sizeof(double) * (size_t)nx);
+    double* lw = (double*)malloc(sizeof(double) * (size_t)nx);
+    double* a = (double*)malloc(sizeof(double) * (size_t)nx);
+    double* w = (double*)malloc(sizeof(double) * (size_t)nx);
+    uint64_t* qq = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)nx);
+    int32_t* anc = (int32_t*)malloc(sizeof(int32_t) * (size_t)nx);
+    for (int j = 0; j < nx; ++j) {
+        uint32_t ctr[4] = {(uint32_t)j, filt, 0u, 8u << 24};
+        x[j] = m0 + s0 * or_normal_call(seed, ctr);
+        lw[j] = 0.0;
+    }
+    double s_prev = (double)nx, ll = 0.0;
+    const double cst = -log(sr) - 0.5 * log(2.0 * M_PI);
+    for (int t = 1; t <= T; ++t) {
+        for (int j = 0; j < nx; ++j) {
+            uint32_t ctr[4] = {(uint32_t)j, filt, (uint32_t)t, 8u << 24};
+            x[j] = phi * x[j] + sq * or_normal_call(seed, ctr);
+            const double z = (y[t - 1] - x[j]) / sr;
+            a[j] = lw[j] + -0.5 * z * z;
+        }
+        double inc;
+        const int rs = weigh_f64(nx, a, lw, w, qq, anc, &s_prev, cst, t < T, pf_always, seed, filt, (uint32_t)t,
+                                 &inc);
+        if (inc_out) inc_out[t - 1] = inc;
+        if (rs_out) rs_out[t - 1] = rs > 0;
+        if (rs < 0) {
+            ll = -INFINITY;
+            break;
+        }
+        ll = ll + inc;
+        if (rs) {
+            for (int j = 0; j < nx; ++j) xs[j] = x[anc[j]];
+            memcpy(x, xs, sizeof(double) * (size_t)nx);
+        }
+    }
+    free(x); free(xs); free(lw); free(a); free(w); free(qq); free(anc);
+    return ll;
 }
 
 double or_pf_loglik(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx,

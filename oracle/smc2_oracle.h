@@ -133,6 +133,12 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
 void or_events_get(double* out);
 void or_events_reset(void);
 
+/* Particle filter on a scalar linear-Gaussian model (a pin against the Kalman filter):
+ * x_0 ~ N(m0, s0^2), x_t = phi x_{t-1} + sq e_t, y_t = x_t + sr d_t; returns the log of
+ * the likelihood estimate; inc_out / rs_out (T entries, optional) as or_pf_loglik. */
+double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const double* y, int T, int nx,
+                uint64_t seed, uint32_t filt, int pf_always, double* inc_out, int32_t* rs_out);
+
 #ifdef __cplusplus
 }
 #endif

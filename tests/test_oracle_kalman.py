@@ -1,0 +1,72 @@
+"""The reference particle filter against the Kalman filter on a scalar linear-Gaussian
+model, where the log-likelihood has a closed form. The model shares with the epidemic
+models every model-independent part of the filter (Sec. II): the weight recursion, the
+likelihood increment with the mean-weight reset after resampling, the exact ESS trigger
+and the integer systematic ancestors. A mistake in any of them (a dropped log S_prev,
+no reset of the weights, a biased ancestor rule) biases the estimate of the likelihood,
+which these tests see."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+PHI, SQ, SR, M0, S0 = 0.9, 1.0, 1.0, 0.0, 1.0
+
+
+def kalman_loglik(phi, sq, sr, m0, s0, y):
+    """Exact log p(y_1:T) of x_0 ~ N(m0, s0^2), x_t = phi x_{t-1} + sq e_t,
+    y_t = x_t + sr d_t (prediction-error decomposition)."""
+    m, P, ll = m0, s0 * s0, 0.0
+    for yt in y:
+        m, P = phi * m, phi * phi * P + sq * sq
+        S = P + sr * sr
+        v = yt - m
+        ll += -0.5 * (np.log(2.0 * np.pi * S) + v * v / S)
+        K = P / S
+        m, P = m + K * v, (1.0 - K) * P
+    return ll
+
+
+def simulate(T, seed):
+    rng = np.random.default_rng(seed)
+    x = M0 + S0 * rng.standard_normal()
+    y = np.empty(T)
+    for t in range(T):
+        x = PHI * x + SQ * rng.standard_normal()
+        y[t] = x + SR * rng.standard_normal()
+    return y
+
+
+def test_kalman_reference_on_a_hand_case():
+    # one observation: y_1 ~ N(phi m0, phi^2 s0^2 + sq^2 + sr^2)
+    ll = kalman_loglik(0.5, 2.0, 1.5, 1.0, 3.0, [0.7])
+    var = 0.25 * 9.0 + 4.0 + 2.25
+    assert ll == pytest.approx(-0.5 * (np.log(2 * np.pi * var) + (0.7 - 0.5) ** 2 / var), rel=1e-14)
+
+
+@pytest.mark.parametrize("pf_always", [0, 1])
+def test_likelihood_estimate_is_unbiased(pf_always):
+    y = simulate(25, 11)
+    ref = kalman_loglik(PHI, SQ, SR, M0, S0, y)
+    M = 2000
+    r = np.array([np.exp(O.pf_lg(PHI, SQ, SR, M0, S0, y, 64, 7, filt=f, pf_always=pf_always) - ref)
+                  for f in range(M)])
+    se = r.std(ddof=1) / np.sqrt(M)
+    assert abs(r.mean() - 1.0) < 4 * se + 1e-3, (r.mean(), se)
+
+
+def test_large_filter_converges_to_the_exact_likelihood():
+    y = simulate(25, 12)
+    ref = kalman_loglik(PHI, SQ, SR, M0, S0, y)
+    est = np.array([O.pf_lg(PHI, SQ, SR, M0, S0, y, 40000, 3, filt=f) for f in range(4)])
+    assert abs(est.mean() - ref) < 0.02, (est, ref)
+    assert est.std() < 0.08
+
+
+def test_increments_sum_to_the_estimate_and_resampling_is_adaptive():
+    y = simulate(40, 13)
+    ll, inc, rs = O.pf_lg(PHI, SQ, SR, M0, S0, y, 256, 5, trace=True)
+    assert ll == pytest.approx(inc.sum(), rel=1e-12)
+    assert rs[-1] == 0 and 0 < rs.sum() < len(y) - 1
+    _, _, rs1 = O.pf_lg(PHI, SQ, SR, M0, S0, y, 256, 5, pf_always=1, trace=True)
+    assert rs1[:-1].all() and rs1[-1] == 0
