@@ -19,6 +19,10 @@ constexpr int MLP_SUB = 64;   // rows per sub-batch: four waves of 16
 constexpr int MLP_ROW = 8;    // floats per whitened population row (D <= 8)
 
 inline __host__ __device__ int mlp_nout(int D) { return D + D * (D + 1) / 2; }
+constexpr int mlp_np_const(int D)
+{
+    return MLP_H * D + MLP_H + MLP_H * MLP_H + MLP_H + (D + D * (D + 1) / 2) * MLP_H + D + D * (D + 1) / 2;
+}
 inline __host__ __device__ int mlp_nparams(int D)
 {
     const int P = mlp_nout(D);

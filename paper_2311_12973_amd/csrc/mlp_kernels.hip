@@ -36,6 +36,8 @@ constexpr double MLP_CLIP = 100.0;
 // LDS row strides, padded so that the 16 rows one MFMA operand reads fall in
 // different banks
 constexpr int LD16 = 20, LD64 = 68, LD48 = 52;
+constexpr int LDT = MLP_SUB + 8;  // transposed BF16 rows
+constexpr int LW1 = 24, LWH = MLP_H + 8;  // BF16 weight rows (W1; W2 and W3), padded the same way
 
 __device__ __forceinline__ short f2bf(float f)
 {
@@ -52,9 +54,9 @@ __device__ __forceinline__ void wave_sync()
 }
 
 struct MlpW {                    // one network in BF16 (biases FP32)
-    short W1[MLP_H * 16];        // [h][d], d >= D zero
-    short W2[MLP_H * MLP_H];     // [h][g]
-    short W3[MLP_PPAD * MLP_H];  // [p][g], p >= P zero
+    short W1[MLP_H * LW1];       // [h][d], d >= D zero
+    short W2[MLP_H * LWH];       // [h][g]
+    short W3[MLP_PPAD * LWH];    // [p][g], p >= P zero
     float b1[MLP_H], b2[MLP_H], b3[MLP_PPAD];
 };
 
@@ -67,6 +69,14 @@ struct MlpAct {                  // one sub-batch of 64 rows (FP32)
     float Z1[MLP_SUB * LD64];    // d loss / d (W1 u + b1)
     float UT[MLP_SUB * 8];       // targets
     float wr[MLP_SUB];           // row weights of the loss
+    // BF16 copies, transposed ([column][row], stride LDT), of the operands of the
+    // weight-gradient products: converted once when the value is written
+    short TU[16 * LDT];
+    short TH1[MLP_H * LDT];
+    short TH2[MLP_H * LDT];
+    short TO[MLP_PPAD * LDT];
+    short TZ2[MLP_H * LDT];
+    short TZ1[MLP_H * LDT];
 };
 
 // u = F^{-1} (x - c) for the frame (c[D], F[D][D] lower, row-major), as floats
@@ -99,10 +109,11 @@ __device__ void mlp_load_weights(int D, const float* w, MlpW* L)
     const float* b3 = W3 + P * MLP_H;
     for (int i = tid; i < MLP_H * 16; i += nthr) {
         const int h = i >> 4, d = i & 15;
-        L->W1[i] = d < D ? f2bf(W1[h * D + d]) : (short)0;
+        L->W1[h * LW1 + d] = d < D ? f2bf(W1[h * D + d]) : (short)0;
     }
-    for (int i = tid; i < MLP_H * MLP_H; i += nthr) L->W2[i] = f2bf(W2[i]);
-    for (int i = tid; i < MLP_PPAD * MLP_H; i += nthr) L->W3[i] = (i / MLP_H) < P ? f2bf(W3[i]) : (short)0;
+    for (int i = tid; i < MLP_H * MLP_H; i += nthr) L->W2[(i / MLP_H) * LWH + (i % MLP_H)] = f2bf(W2[i]);
+    for (int i = tid; i < MLP_PPAD * MLP_H; i += nthr)
+        L->W3[(i / MLP_H) * LWH + (i % MLP_H)] = (i / MLP_H) < P ? f2bf(W3[i]) : (short)0;
     for (int i = tid; i < MLP_H; i += nthr) {
         L->b1[i] = b1[i];
         L->b2[i] = b2[i];
@@ -110,56 +121,60 @@ __device__ void mlp_load_weights(int D, const float* w, MlpW* L)
     for (int i = tid; i < MLP_PPAD; i += nthr) L->b3[i] = i < P ? b3[i] : 0.f;
 }
 
-// acc += A[16 x K] W^T: A rows FP32 (stride lda), W[n][k] BF16 (stride ldw) from the
-// tile's first output column
-template <int K>
-__device__ __forceinline__ f32x4 mm_a_wt(const float* A, int lda, const short* W, int ldw, f32x4 acc)
+// acc[t] += A[16 x K] W_t^T for NT output tiles: A rows FP32 (stride lda), rounded to
+// BF16 once per k-step and shared by the tiles; W[n][k] BF16 (stride ldw), tile t from
+// row 16 t. The tiles' independent chains interleave; each accumulates over k in order.
+template <int K, int NT>
+__device__ __forceinline__ void mm_a_wt(const float* A, int lda, const short* W, int ldw, f32x4 (&acc)[NT])
 {
     const int l = lane_id(), i = l & 15, kq = (l >> 4) << 2;
 #pragma unroll
     for (int k0 = 0; k0 < K; k0 += 16) {
-        bf16x4 a, b;
+        bf16x4 a;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            a[c] = f2bf(A[i * lda + k0 + kq + c]);
-            b[c] = W[i * ldw + k0 + kq + c];
+        for (int c = 0; c < 4; ++c) a[c] = f2bf(A[i * lda + k0 + kq + c]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            bf16x4 b;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = W[(t * 16 + i) * ldw + k0 + kq + c];
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
     }
-    return acc;
 }
 
-// acc += A[16 x K] W: W[k][n] BF16 (stride ldw) from the tile's first output column
-template <int K>
-__device__ __forceinline__ f32x4 mm_a_w(const float* A, int lda, const short* W, int ldw, f32x4 acc)
+// acc[t] += A[16 x K] W[:, 16 t .. 16 t + 15]: W[k][n] BF16 (stride ldw)
+template <int K, int NT>
+__device__ __forceinline__ void mm_a_w(const float* A, int lda, const short* W, int ldw, f32x4 (&acc)[NT])
 {
     const int l = lane_id(), i = l & 15, kq = (l >> 4) << 2;
 #pragma unroll
     for (int k0 = 0; k0 < K; k0 += 16) {
-        bf16x4 a, b;
+        bf16x4 a;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            a[c] = f2bf(A[i * lda + k0 + kq + c]);
-            b[c] = W[(k0 + kq + c) * ldw + i];
+        for (int c = 0; c < 4; ++c) a[c] = f2bf(A[i * lda + k0 + kq + c]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            bf16x4 b;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) b[c] = W[(k0 + kq + c) * ldw + t * 16 + i];
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
     }
-    return acc;
 }
 
-// acc += X^T Y over K rows: X[rows][m] and Y[rows][n] FP32, from the tile's first
-// output row / column
-template <int K>
-__device__ __forceinline__ f32x4 mm_xt_y(const float* X, int ldx, const float* Y, int ldy, f32x4 acc)
+// acc += X^T Y over the sub-batch's rows, from the transposed BF16 copies XT[m][row] and
+// YT[n][row] (stride LDT) of the tile's first output row / column
+__device__ __forceinline__ f32x4 mm_t(const short* XT, const short* YT, f32x4 acc)
 {
     const int l = lane_id(), i = l & 15, kq = (l >> 4) << 2;
 #pragma unroll
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int k0 = 0; k0 < MLP_SUB; k0 += 16) {
         bf16x4 a, b;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            a[c] = f2bf(X[(k0 + kq + c) * ldx + i]);
-            b[c] = f2bf(Y[(k0 + kq + c) * ldy + i]);
+            a[c] = XT[i * LDT + k0 + kq + c];
+            b[c] = YT[i * LDT + k0 + kq + c];
         }
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
     }
@@ -182,62 +197,139 @@ __device__ __forceinline__ float tanh_fast(float x)
     return copysignf(r, x);
 }
 
-// forward pass of the wave's 16 rows (from row r0 of the sub-batch)
-__device__ void mlp_fwd16(const MlpW* W, MlpAct* A, int r0)
+// forward pass of the wave's 16 rows (from row r0 of the sub-batch); with TRAIN the
+// hidden layers also go to their transposed BF16 copies
+template <bool TRAIN> __device__ void mlp_fwd16(const MlpW* W, MlpAct* A, int r0)
 {
     const int l = lane_id(), j = l & 15, rq = (l >> 4) << 2;
-    for (int jb = 0; jb < 4; ++jb) {
-        const float bb = W->b1[jb * 16 + j];
-        f32x4 acc = {bb, bb, bb, bb};
-        acc = mm_a_wt<16>(A->U + r0 * LD16, LD16, W->W1 + jb * 16 * 16, 16, acc);
+    f32x4 acc[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) A->H1[(r0 + rq + c) * LD64 + jb * 16 + j] = tanh_fast(acc[c]);
-    }
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{W->b1[t * 16 + j], W->b1[t * 16 + j], W->b1[t * 16 + j], W->b1[t * 16 + j]};
+    mm_a_wt<16, 4>(A->U + r0 * LD16, LD16, W->W1, LW1, acc);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float h = tanh_fast(acc[t][c]);
+            A->H1[(r0 + rq + c) * LD64 + t * 16 + j] = h;
+            if (TRAIN) A->TH1[(t * 16 + j) * LDT + r0 + rq + c] = f2bf(h);
+        }
     wave_sync();
-    for (int jb = 0; jb < 4; ++jb) {
-        const float bb = W->b2[jb * 16 + j];
-        f32x4 acc = {bb, bb, bb, bb};
-        acc = mm_a_wt<MLP_H>(A->H1 + r0 * LD64, LD64, W->W2 + jb * 16 * MLP_H, MLP_H, acc);
 #pragma unroll
-        for (int c = 0; c < 4; ++c) A->H2[(r0 + rq + c) * LD64 + jb * 16 + j] = tanh_fast(acc[c]);
-    }
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{W->b2[t * 16 + j], W->b2[t * 16 + j], W->b2[t * 16 + j], W->b2[t * 16 + j]};
+    mm_a_wt<MLP_H, 4>(A->H1 + r0 * LD64, LD64, W->W2, LWH, acc);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const float h = tanh_fast(acc[t][c]);
+            A->H2[(r0 + rq + c) * LD64 + t * 16 + j] = h;
+            if (TRAIN) A->TH2[(t * 16 + j) * LDT + r0 + rq + c] = f2bf(h);
+        }
     wave_sync();
-    for (int pb = 0; pb < 3; ++pb) {
-        const float bb = W->b3[pb * 16 + j];
-        f32x4 acc = {bb, bb, bb, bb};
-        acc = mm_a_wt<MLP_H>(A->H2 + r0 * LD64, LD64, W->W3 + pb * 16 * MLP_H, MLP_H, acc);
+    f32x4 ao[3];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) A->O[(r0 + rq + c) * LD48 + pb * 16 + j] = acc[c];
+    for (int t = 0; t < 3; ++t) ao[t] = f32x4{W->b3[t * 16 + j], W->b3[t * 16 + j], W->b3[t * 16 + j], W->b3[t * 16 + j]};
+    mm_a_wt<MLP_H, 3>(A->H2 + r0 * LD64, LD64, W->W3, LWH, ao);
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) A->O[(r0 + rq + c) * LD48 + t * 16 + j] = ao[t][c];
+    wave_sync();
+}
+
+// activation gradients of the wave's 16 rows from d loss / d outputs (in A->O), with
+// their transposed BF16 copies
+__device__ void mlp_bwd16(const MlpW* W, MlpAct* A, int r0)
+{
+    const int l = lane_id(), j = l & 15, rq = (l >> 4) << 2;
+    f32x4 acc[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    mm_a_w<MLP_PPAD, 4>(A->O + r0 * LD48, LD48, W->W3, LWH, acc);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int at = (r0 + rq + c) * LD64 + t * 16 + j;
+            const float h = A->H2[at];
+            const float z = acc[t][c] * (1.f - h * h);
+            A->Z2[at] = z;
+            A->TZ2[(t * 16 + j) * LDT + r0 + rq + c] = f2bf(z);
+        }
+    wave_sync();
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+    mm_a_w<MLP_H, 4>(A->Z2 + r0 * LD64, LD64, W->W2, LWH, acc);
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int at = (r0 + rq + c) * LD64 + t * 16 + j;
+            const float h = A->H1[at];
+            const float z = acc[t][c] * (1.f - h * h);
+            A->Z1[at] = z;
+            A->TZ1[(t * 16 + j) * LDT + r0 + rq + c] = f2bf(z);
+        }
+    wave_sync();
+}
+
+// transposed BF16 copy of the output gradients of the wave's 16 rows
+__device__ __forceinline__ void mlp_copy_ograd(MlpAct* A, int r0)
+{
+    const int l = lane_id();
+    for (int e = l; e < 16 * MLP_PPAD; e += 64) {
+        const int rr = r0 + (e & 15), pp = e >> 4;
+        A->TO[pp * LDT + rr] = f2bf(A->O[rr * LD48 + pp]);
     }
     wave_sync();
 }
 
-// activation gradients of the wave's 16 rows from d loss / d outputs (in A->O)
-__device__ void mlp_bwd16(const MlpW* W, MlpAct* A, int r0)
+// bias gradients of the wave's 16 rows, added to the lane's partial sums (lane l:
+// column l of the output gradients (l < 48), of Z2 and of Z1)
+__device__ __forceinline__ void mlp_bias16(const MlpAct* A, int r0, float& b3, float& b2, float& b1)
 {
-    const int l = lane_id(), j = l & 15, rq = (l >> 4) << 2;
-    for (int jb = 0; jb < 4; ++jb) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mm_a_w<MLP_PPAD>(A->O + r0 * LD48, LD48, W->W3 + jb * 16, MLP_H, acc);
+    const int l = lane_id();
+    float s3 = 0.f, s2 = 0.f, s1 = 0.f;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int at = (r0 + rq + c) * LD64 + jb * 16 + j;
-            const float h = A->H2[at];
-            A->Z2[at] = acc[c] * (1.f - h * h);
+    for (int rr = 0; rr < 16; ++rr) {
+        if (l < MLP_PPAD) s3 += A->O[(r0 + rr) * LD48 + l];
+        s2 += A->Z2[(r0 + rr) * LD64 + l];
+        s1 += A->Z1[(r0 + rr) * LD64 + l];
+    }
+    b3 += s3;
+    b2 += s2;
+    b1 += s1;
+}
+
+// the four waves' bias partial sums in wave order, into grad[] (parameter layout);
+// part is LDS scratch of 4 x 176 floats; every thread of the block calls it
+template <int D> __device__ double mlp_bias_write(float* part, float b3, float b2, float b1, float* grad)
+{
+    constexpr int P = D + D * (D + 1) / 2;
+    const int l = lane_id(), w = wave_id(), tid = (int)threadIdx.x;
+    if (l < MLP_PPAD) part[w * 176 + l] = b3;
+    part[w * 176 + 48 + l] = b2;
+    part[w * 176 + 112 + l] = b1;
+    __syncthreads();
+    double ss = 0.0;  // squares of the entries written (for the gradient norm)
+    if (tid < 176) {
+        const float s = ((part[tid] + part[176 + tid]) + part[352 + tid]) + part[528 + tid];
+        if (tid < 48) {
+            if (tid < P) {
+                grad[mlp_nparams(D) - P + tid] = s;
+                ss = (double)s * (double)s;
+            }
+        } else if (tid < 112) {
+            grad[MLP_H * D + MLP_H + MLP_H * MLP_H + tid - 48] = s;
+            ss = (double)s * (double)s;
+        } else {
+            grad[MLP_H * D + tid - 112] = s;
+            ss = (double)s * (double)s;
         }
     }
-    wave_sync();
-    for (int jb = 0; jb < 4; ++jb) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-        acc = mm_a_w<MLP_H>(A->Z2 + r0 * LD64, LD64, W->W2 + jb * 16, MLP_H, acc);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int at = (r0 + rq + c) * LD64 + jb * 16 + j;
-            const float h = A->H1[at];
-            A->Z1[at] = acc[c] * (1.f - h * h);
-        }
-    }
-    wave_sync();
+    __syncthreads();
+    return ss;
 }
 
 // weight-gradient tiles of the sub-batch accumulated in acc[] (wave w: tiles w + 4q)
@@ -248,19 +340,20 @@ __device__ void mlp_wgrad(const MlpAct* A, f32x4 (&acc)[8])
     for (int q = 0; q < 8; ++q) {
         const int t = w + 4 * q;
         if (t < 12) {
-            acc[q] = mm_xt_y<MLP_SUB>(A->O + (t >> 2) * 16, LD48, A->H2 + (t & 3) * 16, LD64, acc[q]);
+            acc[q] = mm_t(A->TO + (t >> 2) * 16 * LDT, A->TH2 + (t & 3) * 16 * LDT, acc[q]);
         } else if (t < 28) {
-            acc[q] = mm_xt_y<MLP_SUB>(A->Z2 + ((t - 12) >> 2) * 16, LD64, A->H1 + ((t - 12) & 3) * 16, LD64, acc[q]);
+            acc[q] = mm_t(A->TZ2 + ((t - 12) >> 2) * 16 * LDT, A->TH1 + ((t - 12) & 3) * 16 * LDT, acc[q]);
         } else {
-            acc[q] = mm_xt_y<MLP_SUB>(A->Z1 + (t - 28) * 16, LD64, A->U, LD16, acc[q]);
+            acc[q] = mm_t(A->TZ1 + (t - 28) * 16 * LDT, A->TU, acc[q]);
         }
     }
 }
 
 // adds the tiles to grad[] (parameter layout)
-template <int D> __device__ void mlp_scatter_wgrad(const f32x4 (&acc)[8], float* grad)
+template <int D> __device__ double mlp_scatter_wgrad(const f32x4 (&acc)[8], float* grad)
 {
     constexpr int P = D + D * (D + 1) / 2;
+    double ss = 0.0;  // squares of the entries written (for the gradient norm)
     float* gW1 = grad;
     float* gW2 = gW1 + MLP_H * D + MLP_H;
     float* gW3 = gW2 + MLP_H * MLP_H + MLP_H;
@@ -273,16 +366,56 @@ template <int D> __device__ void mlp_scatter_wgrad(const f32x4 (&acc)[8], float*
             const int i = rq + c;
             if (t < 12) {
                 const int p = (t >> 2) * 16 + i, g = (t & 3) * 16 + j;
-                if (p < P) gW3[p * MLP_H + g] = acc[q][c];
+                if (p < P) {
+                    gW3[p * MLP_H + g] = acc[q][c];
+                    ss += (double)acc[q][c] * (double)acc[q][c];
+                }
             } else if (t < 28) {
                 const int h = ((t - 12) >> 2) * 16 + i, g = ((t - 12) & 3) * 16 + j;
                 gW2[h * MLP_H + g] = acc[q][c];
+                ss += (double)acc[q][c] * (double)acc[q][c];
             } else {
                 const int h = (t - 28) * 16 + i;
-                if (j < D) gW1[h * D + j] = acc[q][c];
+                if (j < D) {
+                    gW1[h * D + j] = acc[q][c];
+                    ss += (double)acc[q][c] * (double)acc[q][c];
+                }
             }
         }
     }
+    return ss;
+}
+
+// parameter i (layout W1 b1 W2 b2 W3 b3) into the LDS copy of the network
+template <int D> __device__ __forceinline__ void mlp_store_weight(MlpW* L, int i, float v)
+{
+    constexpr int P = D + D * (D + 1) / 2;
+    if (i < MLP_H * D) {
+        const int h = i / D;
+        L->W1[h * LW1 + (i - h * D)] = f2bf(v);
+        return;
+    }
+    i -= MLP_H * D;
+    if (i < MLP_H) {
+        L->b1[i] = v;
+        return;
+    }
+    i -= MLP_H;
+    if (i < MLP_H * MLP_H) {
+        L->W2[(i >> 6) * LWH + (i & 63)] = f2bf(v);
+        return;
+    }
+    i -= MLP_H * MLP_H;
+    if (i < MLP_H) {
+        L->b2[i] = v;
+        return;
+    }
+    i -= MLP_H;
+    if (i < P * MLP_H) {
+        L->W3[(i >> 6) * LWH + (i & 63)] = f2bf(v);
+        return;
+    }
+    L->b3[i - P * MLP_H] = v;
 }
 
 __device__ __forceinline__ float softplus_f(float x) { return x > 30.f ? x : log1pf(expf(x)); }
@@ -406,7 +539,7 @@ __global__ void __launch_bounds__(256) k_mlp_forward(MlpArrays m, MlpParams p, O
         for (int d = 0; d < 16; ++d) A->U[tid * LD16 + d] = u[d];
     }
     __syncthreads();
-    mlp_fwd16(W, A, wave_id() * 16);
+    mlp_fwd16<false>(W, A, wave_id() * 16);
     __syncthreads();
     for (int e = tid; e < MLP_SUB * P; e += (int)blockDim.x) {
         const int rr = e / P, pp = e - rr * P, i = row0 + rr;
@@ -563,7 +696,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(MlpArrays m, MlpParams p, Out
             f32x4 acc[8];
 #pragma unroll
             for (int q = 0; q < 8; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-            float bacc = 0.f;  // bias gradient of column tid (< 176)
+            float bb3 = 0.f, bb2 = 0.f, bb1 = 0.f;  // bias-gradient partial sums of this wave's rows
             float cu[MLP_ROW], ct[MLP_ROW], cw = 0.f;  // the next sub-batch's rows (threads < MLP_SUB)
             if (tid < MLP_SUB) fetch(b0, 0, nb, cu, ct, cw);
             for (int s0 = 0; s0 < nb; s0 += MLP_SUB) {
@@ -571,61 +704,70 @@ __global__ void __launch_bounds__(256) k_mlp_train(MlpArrays m, MlpParams p, Out
                 // complete while this one is computed
                 if (tid < MLP_SUB) {
 #pragma unroll
-                    for (int d = 0; d < 16; ++d) A->U[tid * LD16 + d] = d < MLP_ROW ? cu[d] : 0.f;
+                    for (int d = 0; d < 16; ++d) {
+                        const float ud = d < MLP_ROW ? cu[d] : 0.f;
+                        A->U[tid * LD16 + d] = ud;
+                        A->TU[d * LDT + tid] = f2bf(ud);
+                    }
 #pragma unroll
                     for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = ct[d];
                     A->wr[tid] = cw;
                     if (s0 + MLP_SUB < nb) fetch(b0, s0 + MLP_SUB, nb, cu, ct, cw);
                 }
                 __syncthreads();
-                mlp_fwd16(W, A, wave_id() * 16);
+                mlp_fwd16<true>(W, A, wave_id() * 16);
                 if (lane_id() < 16) mlp_row_nll<D>(A, wave_id() * 16 + lane_id(), A->wr[wave_id() * 16 + lane_id()], true);
                 wave_sync();
+                mlp_copy_ograd(A, wave_id() * 16);
                 mlp_bwd16(W, A, wave_id() * 16);
+                mlp_bias16(A, wave_id() * 16, bb3, bb2, bb1);
                 __syncthreads();
                 mlp_wgrad(A, acc);
-                if (tid < 176) {
-                    float s = 0.f;
-                    if (tid < 48) {
-                        for (int rr = 0; rr < MLP_SUB; ++rr) s += A->O[rr * LD48 + tid];
-                    } else if (tid < 112) {
-                        for (int rr = 0; rr < MLP_SUB; ++rr) s += A->Z2[rr * LD64 + tid - 48];
-                    } else {
-                        for (int rr = 0; rr < MLP_SUB; ++rr) s += A->Z1[rr * LD64 + tid - 112];
-                    }
-                    bacc += s;
-                }
                 __syncthreads();  // the next sub-batch overwrites the activations
             }
-            // minibatch gradient in parameter layout
-            mlp_scatter_wgrad<D>(acc, grad);
-            if (tid < 176) {
-                if (tid < 48) {
-                    if (tid < P) grad[NP - P + tid] = bacc;
-                } else if (tid < 112) {
-                    grad[MLP_H * D + MLP_H + MLP_H * MLP_H + tid - 48] = bacc;
-                } else {
-                    grad[MLP_H * D + tid - 112] = bacc;
-                }
-            }
-            __syncthreads();
-            double nn[1] = {0.0};
-            for (int i = tid; i < NP; i += nthr) nn[0] += (double)grad[i] * (double)grad[i];
+            // minibatch gradient in parameter layout; its squared norm from the values
+            // as they are written
+            double nn[1] = {mlp_scatter_wgrad<D>(acc, grad)};
+            nn[0] += mlp_bias_write<D>(A->H1, bb3, bb2, bb1, grad);
             mlp_block_sum<1>(nn, red);
             const double nrm = sqrt(nn[0]);
             const double clip = nrm > MLP_CLIP ? MLP_CLIP / nrm : 1.0;
             ++t_adam;
             const float c1 = 1.f - powf(0.9f, (float)t_adam), c2 = 1.f - powf(0.999f, (float)t_adam);
-            for (int i = tid; i < NP; i += nthr) {
-                const float g = (float)((double)grad[i] * clip);
-                const float mi = 0.9f * am[i] + 0.1f * g;
-                const float vi = 0.999f * av[i] + 0.001f * g * g;
-                am[i] = mi;
-                av[i] = vi;
-                prm[i] = prm[i] - p.lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+            // Adam, each updated weight also written to the network's LDS copy: the
+            // thread's parameters i = tid + 256 e in chunks of 8 whose loads are all
+            // issued before the first update, so they overlap
+            {
+                constexpr int PER = (mlp_np_const(D) + 255) / 256, CH = 8;
+#pragma nounroll
+                for (int e0 = 0; e0 < PER; e0 += CH) {
+                    float g[CH], mo[CH], vo[CH], po[CH];
+#pragma unroll
+                    for (int e = 0; e < CH; ++e) {
+                        const int i = tid + 256 * (e0 + e);
+                        if (e0 + e < PER && i < NP) {
+                            g[e] = grad[i];
+                            mo[e] = am[i];
+                            vo[e] = av[i];
+                            po[e] = prm[i];
+                        }
+                    }
+#pragma unroll
+                    for (int e = 0; e < CH; ++e) {
+                        const int i = tid + 256 * (e0 + e);
+                        if (e0 + e < PER && i < NP) {
+                            const float gi = (float)((double)g[e] * clip);
+                            const float mi = 0.9f * mo[e] + 0.1f * gi;
+                            const float vi = 0.999f * vo[e] + 0.001f * gi * gi;
+                            const float pn = po[e] - p.lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+                            am[i] = mi;
+                            av[i] = vi;
+                            prm[i] = pn;
+                            mlp_store_weight<D>(W, i, pn);
+                        }
+                    }
+                }
             }
-            __syncthreads();
-            mlp_load_weights(D, prm, W);
             __syncthreads();
         }
     }
@@ -656,7 +798,7 @@ __global__ void __launch_bounds__(256) k_mlp_train(MlpArrays m, MlpParams p, Out
                 for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = valid ? rows[(size_t)jt * MLP_ROW + d] : 0.f;
             }
             __syncthreads();
-            mlp_fwd16(W, A, wave_id() * 16);
+            mlp_fwd16<false>(W, A, wave_id() * 16);
             __syncthreads();
             if (tid < MLP_SUB && wt > 0.0) {
                 const float nll = mlp_row_nll<D>(A, tid, 0.f, false);
@@ -708,7 +850,7 @@ __global__ void __launch_bounds__(256) k_mlp_rows_forward(int n, const float* pa
         for (int d = 0; d < 16; ++d) A->U[tid * LD16 + d] = u[d];
     }
     __syncthreads();
-    mlp_fwd16(W, A, wave_id() * 16);
+    mlp_fwd16<false>(W, A, wave_id() * 16);
     __syncthreads();
     for (int e = tid; e < MLP_SUB * P; e += (int)blockDim.x) {
         const int rr = e / P, pp = e - rr * P, i = row0 + rr;
@@ -732,7 +874,7 @@ __global__ void __launch_bounds__(256) k_mlp_rows_grad(int n, const float* param
     f32x4 acc[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bacc = 0.f;
+    float bb3 = 0.f, bb2 = 0.f, bb1 = 0.f;
     double ls[1] = {0.0};
     __syncthreads();
     for (int s0 = 0; s0 < n; s0 += MLP_SUB) {
@@ -749,13 +891,16 @@ __global__ void __launch_bounds__(256) k_mlp_rows_grad(int n, const float* param
                 mlp_whiten<D>(frame, phi_t + (size_t)i * D, ut);
             }
 #pragma unroll
-            for (int d = 0; d < 16; ++d) A->U[tid * LD16 + d] = ui[d];
+            for (int d = 0; d < 16; ++d) {
+                A->U[tid * LD16 + d] = ui[d];
+                A->TU[d * LDT + tid] = f2bf(ui[d]);
+            }
 #pragma unroll
             for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = ut[d];
             A->wr[tid] = valid ? (float)wrow[i] : 0.f;
         }
         __syncthreads();
-        mlp_fwd16(W, A, wave_id() * 16);
+        mlp_fwd16<true>(W, A, wave_id() * 16);
         if (lane_id() < 16) {
             const int rr = wave_id() * 16 + lane_id();
             const float wv = A->wr[rr];
@@ -763,32 +908,15 @@ __global__ void __launch_bounds__(256) k_mlp_rows_grad(int n, const float* param
             if (wv != 0.f) ls[0] += (double)wv * (double)nll;
         }
         wave_sync();
+        mlp_copy_ograd(A, wave_id() * 16);
         mlp_bwd16(W, A, wave_id() * 16);
+        mlp_bias16(A, wave_id() * 16, bb3, bb2, bb1);
         __syncthreads();
         mlp_wgrad(A, acc);
-        if (tid < 176) {
-            float s = 0.f;
-            if (tid < 48) {
-                for (int rr = 0; rr < MLP_SUB; ++rr) s += A->O[rr * LD48 + tid];
-            } else if (tid < 112) {
-                for (int rr = 0; rr < MLP_SUB; ++rr) s += A->Z2[rr * LD64 + tid - 48];
-            } else {
-                for (int rr = 0; rr < MLP_SUB; ++rr) s += A->Z1[rr * LD64 + tid - 112];
-            }
-            bacc += s;
-        }
         __syncthreads();
     }
     mlp_scatter_wgrad<D>(acc, grad);
-    if (tid < 176) {
-        if (tid < 48) {
-            if (tid < P) grad[NP - P + tid] = bacc;
-        } else if (tid < 112) {
-            grad[MLP_H * D + MLP_H + MLP_H * MLP_H + tid - 48] = bacc;
-        } else {
-            grad[MLP_H * D + tid - 112] = bacc;
-        }
-    }
+    mlp_bias_write<D>(A->H1, bb3, bb2, bb1, grad);
     mlp_block_sum<1>(ls, red);
     if (tid == 0) *loss = ls[0];
 }
