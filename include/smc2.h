@@ -96,6 +96,14 @@ extern "C" {
 #define SMC2_SCHED_POOLED 2   /* SIR/SEIR: a wave pools its draws and runs the FP64 final
                                  acceptance tests of the BTRS sampler 64 at a time        */
 
+/* Particle-filter resampling (Sec. II; both from the quantised weights q_j and their
+ * inclusive scan C, Q = C_{N_x - 1}, in exact integers):
+ *   SYSTEMATIC  one uniform U per filter-step, ancestor of slot m = min{j : N_x C_j > m Q + U}
+ *   MULTINOMIAL one uniform U_m per slot, ancestor of slot m = min{j : C_j > U_m}, i.e.
+ *               probability q_j / Q independently per slot (the paper's filter)          */
+#define SMC2_PF_RS_SYSTEMATIC 0
+#define SMC2_PF_RS_MULTINOMIAL 1
+
 #define SMC2_DMAX 8
 #define SMC2_NFIXED 32
 
@@ -129,6 +137,8 @@ typedef struct {
     int32_t mlp_epochs; /* learned proposal: training epochs per iteration (0 .. 1000)     */
     int32_t mlp_batch;  /* learned proposal: minibatch rows (0: the whole population)      */
     double mlp_lr;      /* learned proposal: Adam learning rate (> 0)                      */
+    int32_t pf_resampling; /* SMC2_PF_RS_*: the particle filters' resampling scheme       */
+    int32_t reserved;      /* 0                                                           */
 } smc2_config;
 
 typedef struct {

@@ -21,6 +21,7 @@ PREC_FP32, PREC_FP64 = 0, 1
 PRIOR_UNIFORM, PRIOR_LOGNORMAL, PRIOR_LOGITNORMAL, PRIOR_NORMAL = 0, 1, 2, 3
 L_FORWARD, L_GAUSS_OPT = 0, 1
 PROP_RW, PROP_MLP = 0, 1
+RS_SYSTEMATIC, RS_MULTINOMIAL = 0, 1
 
 
 class Config(ctypes.Structure):
@@ -30,7 +31,7 @@ class Config(ctypes.Structure):
         ("proposal", ctypes.c_int32), ("n_fixed", ctypes.c_int32), ("n_pop", ctypes.c_double),
         ("prior", (ctypes.c_double * 3) * DMAX), ("rw_cov", (ctypes.c_double * DMAX) * DMAX),
         ("fixed", ctypes.c_double * NFIXED), ("mlp_epochs", ctypes.c_int32), ("mlp_batch", ctypes.c_int32),
-        ("mlp_lr", ctypes.c_double),
+        ("mlp_lr", ctypes.c_double), ("pf_resampling", ctypes.c_int32), ("pad", ctypes.c_int32),
     ]
 
 
@@ -69,7 +70,8 @@ def _declare(L):
         c.c_uint32] * 4 + [P(c.c_int32)]
     L.or_pf_lg.restype = c.c_double
     L.or_pf_lg.argtypes = [c.c_double] * 5 + [P(c.c_double), c.c_int, c.c_int, c.c_uint64, c.c_uint32, c.c_int,
-                                              P(c.c_double), P(c.c_int32)]
+                                              c.c_int, P(c.c_double), P(c.c_int32)]
+    L.or_resample_multinomial.argtypes = [P(c.c_uint64), c.c_int, c.c_uint64, c.c_uint32, c.c_uint32, P(c.c_int32)]
     L.or_events_get.argtypes = [P(c.c_double)]
     L.or_events_reset.argtypes = []
     L.or_obs_logpmf.restype = c.c_double
@@ -133,11 +135,13 @@ def _declare(L):
 
 
 def make_config(model, obs, D, prec, n_pop, prior, rw_cov, fixed=(), lkernel=L_GAUSS_OPT,
-                proposal=PROP_RW, pf_always=0, mlp_epochs=4, mlp_batch=256, mlp_lr=1e-3):
+                proposal=PROP_RW, pf_always=0, mlp_epochs=4, mlp_batch=256, mlp_lr=1e-3,
+                pf_resampling=RS_SYSTEMATIC):
     cfg = Config()
     cfg.mlp_epochs, cfg.mlp_batch, cfg.mlp_lr = int(mlp_epochs), int(mlp_batch), float(mlp_lr)
     cfg.model, cfg.obs, cfg.D, cfg.prec = model, obs, D, prec
     cfg.pf_always, cfg.lkernel, cfg.proposal = pf_always, lkernel, proposal
+    cfg.pf_resampling = int(pf_resampling)
     cfg.n_pop = float(n_pop)
     prior = np.asarray(prior, dtype=np.float64).reshape(D, 3)
     rw = np.asarray(rw_cov, dtype=np.float64).reshape(D, D)
@@ -158,7 +162,7 @@ def config_from_workload(w, prec=None):
     return make_config(w["model"], w["obs"], w["D"], w["prec"] if prec is None else prec, w["n_pop"],
                        w["prior"], w["rw_cov"], w.get("fixed", ()), w.get("lkernel", L_GAUSS_OPT),
                        w.get("proposal", PROP_RW), w.get("pf_always", 0), w.get("mlp_epochs", 4),
-                       w.get("mlp_batch", 256), w.get("mlp_lr", 1e-3))
+                       w.get("mlp_batch", 256), w.get("mlp_lr", 1e-3), w.get("pf_resampling", RS_SYSTEMATIC))
 
 
 def philox(ctr, key):
@@ -342,7 +346,14 @@ def outer_update(cfg, k, seed, state, phi_new, lp_new, ll_new, logq=None):
     return st, logw_pre, anc, rec
 
 
-def pf_lg(phi, sq, sr, m0, s0, y, nx, seed, filt=0, pf_always=0, trace=False):
+def resample_multinomial(q, seed, filt, kt):
+    q = np.ascontiguousarray(q, dtype=np.uint64)
+    anc = np.zeros(q.size, dtype=np.int32)
+    lib().or_resample_multinomial(_p(q, ctypes.c_uint64), q.size, int(seed), int(filt), int(kt), _p(anc, ctypes.c_int32))
+    return anc
+
+
+def pf_lg(phi, sq, sr, m0, s0, y, nx, seed, filt=0, pf_always=0, trace=False, resampling=RS_SYSTEMATIC):
     """Log of the particle filter's likelihood estimate on the scalar linear-Gaussian
     model x_t = phi x_{t-1} + sq e_t, y_t = x_t + sr d_t, x_0 ~ N(m0, s0^2)."""
     y = np.ascontiguousarray(y, dtype=np.float64)
@@ -350,7 +361,8 @@ def pf_lg(phi, sq, sr, m0, s0, y, nx, seed, filt=0, pf_always=0, trace=False):
     inc = np.zeros(T) if trace else None
     rs = np.zeros(T, dtype=np.int32) if trace else None
     ll = lib().or_pf_lg(phi, sq, sr, m0, s0, _p(y, ctypes.c_double), T, nx, int(seed), int(filt), int(pf_always),
-                        _p(inc, ctypes.c_double) if trace else None, _p(rs, ctypes.c_int32) if trace else None)
+                        int(resampling), _p(inc, ctypes.c_double) if trace else None,
+                        _p(rs, ctypes.c_int32) if trace else None)
     return (ll, inc, rs) if trace else ll
 
 

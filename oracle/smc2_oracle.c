@@ -341,6 +341,36 @@ void or_propose_rw(const or_config* cfg, int N, uint64_t seed, uint32_t k, const
     }
 }
 
+/* Multinomial resampling, the particle filter's scheme in Sec. II: every slot draws its
+ * ancestor independently with probability q_j / Q, from its own 64-bit uniform
+ * U_m = floor(x64_m Q / 2^64) and the first j with C_j > U_m (exact integers). */
+void or_resample_multinomial(const uint64_t* q, int n, uint64_t seed, uint32_t filt, uint32_t kt, int32_t* anc)
+{
+    uint64_t* C = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
+    uint64_t acc = 0;
+    for (int j = 0; j < n; ++j) {
+        acc += q[j];
+        C[j] = acc;
+    }
+    const uint64_t Q = acc;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int m = 0; m < n; ++m) {
+        const uint32_t ctr[4] = {(uint32_t)(m >> 1), filt, kt, ((uint32_t)OR_S_PF_RS << 24) | (1u << 16)};
+        uint32_t w[4];
+        or_philox(ctr, key, w);
+        const uint64_t x64 = (m & 1) ? ((uint64_t)w[2] | ((uint64_t)w[3] << 32)) : ((uint64_t)w[0] | ((uint64_t)w[1] << 32));
+        const uint64_t U = (uint64_t)(((unsigned __int128)x64 * Q) >> 64);
+        int lo = 0, hi = n - 1; /* first j with C_j > U (exists: U < Q = C_{n-1}) */
+        while (lo < hi) {
+            const int mid = (lo + hi) / 2;
+            if (C[mid] > U) hi = mid;
+            else lo = mid + 1;
+        }
+        anc[m] = lo;
+    }
+    free(C);
+}
+
 /* ------------------------------------------------------------------ event counts
  * How often the particle filter performs each primitive of the method (particle-step,
  * binomial draw, inversion step, BTRS set-up, attempt and final test, Philox call,
@@ -416,7 +446,7 @@ void or_binomial_many(int prec, int count, const int32_t* n, const double* p, ui
  * (particle j, filter, t, 8<<24) -- t = 0 draws x_0. FP64 throughout.
  */
 double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const double* y, int T, int nx,
-                uint64_t seed, uint32_t filt, int pf_always, double* inc_out, int32_t* rs_out)
+                uint64_t seed, uint32_t filt, int pf_always, int resampling, double* inc_out, int32_t* rs_out)
 {
     double* x = (double*)malloc(sizeof(double) * (size_t)nx);
     double* xs = (double*)malloc(sizeof(double) * (size_t)nx);
@@ -440,8 +470,8 @@ double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const do
             a[j] = lw[j] + -0.5 * z * z;
         }
         double inc;
-        const int rs = weigh_f64(nx, a, lw, w, qq, anc, &s_prev, cst, t < T, pf_always, seed, filt, (uint32_t)t,
-                                 &inc);
+        const int rs = weigh_f64(nx, a, lw, w, qq, anc, &s_prev, cst, t < T, pf_always, resampling, seed, filt,
+                                 (uint32_t)t, &inc);
         if (inc_out) inc_out[t - 1] = inc;
         if (rs_out) rs_out[t - 1] = rs > 0;
         if (rs < 0) {

@@ -39,6 +39,9 @@ enum { OR_S_PF_PROP = 1, OR_S_PF_RS = 2, OR_S_PRIOR = 3, OR_S_RW = 4, OR_S_OUTER
 
 #define OR_DMAX 8
 
+/* particle-filter resampling schemes */
+enum { OR_RS_SYSTEMATIC = 0, OR_RS_MULTINOMIAL = 1 };
+
 /* Event counters of the particle filter (see or_events_get). */
 enum { OR_EV_PSTEP = 0, OR_EV_DRAW, OR_EV_PHILOX, OR_EV_INV, OR_EV_INV_ITER, OR_EV_BTRS, OR_EV_ATTEMPT,
        OR_EV_FINAL, OR_EV_T64, OR_EV_RS_PARTICLE, OR_EV_N };
@@ -58,6 +61,8 @@ typedef struct {
     double fixed[OR_NFIXED];       /* model constants (see smc2_oracle.c, "Models") */
     int32_t mlp_epochs, mlp_batch; /* learned proposal: epochs and minibatch rows per iteration */
     double mlp_lr;                 /* learned proposal: Adam learning rate */
+    int32_t pf_resampling;         /* OR_RS_SYSTEMATIC or OR_RS_MULTINOMIAL (the particle filter's) */
+    int32_t pad;
 } or_config;
 
 /* Number of doubles in one per-iteration record. */
@@ -137,7 +142,11 @@ void or_events_reset(void);
  * x_0 ~ N(m0, s0^2), x_t = phi x_{t-1} + sq e_t, y_t = x_t + sr d_t; returns the log of
  * the likelihood estimate; inc_out / rs_out (T entries, optional) as or_pf_loglik. */
 double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const double* y, int T, int nx,
-                uint64_t seed, uint32_t filt, int pf_always, double* inc_out, int32_t* rs_out);
+                uint64_t seed, uint32_t filt, int pf_always, int resampling, double* inc_out, int32_t* rs_out);
+/* Multinomial ancestors from quantised weights: slot m draws U_m = floor(x64_m Q / 2^64)
+ * (x64_m: 64-bit word m&1 of the Philox call (m>>1, filt, kt, 2<<24 | 1<<16)) and takes
+ * the first j whose inclusive scan C_j exceeds U_m. */
+void or_resample_multinomial(const uint64_t* q, int n, uint64_t seed, uint32_t filt, uint32_t kt, int32_t* anc);
 
 #ifdef __cplusplus
 }

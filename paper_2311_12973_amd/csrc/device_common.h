@@ -4,7 +4,8 @@
 // run seed; every draw is a pure function of its logical coordinates, so results
 // do not depend on the launch shape. Counter layout:
 //   flows       (particle j, filter i, k<<16 | t, 1<<24 | draw b<<16 | call a)
-//   PF resample (0, filter i, k<<16 | t, 2<<24)
+//   PF resample (0, filter i, k<<16 | t, 2<<24); multinomial: slots 2p, 2p+1 from
+//                (p, filter i, k<<16 | t, 2<<24 | 1<<16)
 //   prior       (sample i, 0, 1<<16, 3<<24 | coordinate d)
 //   RW normal   (sample i, 0, k<<16, 4<<24 | coordinate d)
 //   outer resample (0, 0, k<<16, 5<<24)

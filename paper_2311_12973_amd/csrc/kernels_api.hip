@@ -155,6 +155,8 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
         return kfail(SMC2_E_ARG, "T or n_x out of range");
     if (!(cfg->n_pop >= 1.0 && cfg->n_pop <= 16777216.0)) return kfail(SMC2_E_ARG, "n_pop out of range");
     if (k > 65535) return kfail(SMC2_E_ARG, "k out of range");
+    if (cfg->pf_resampling != SMC2_PF_RS_SYSTEMATIC && cfg->pf_resampling != SMC2_PF_RS_MULTINOMIAL)
+        return kfail(SMC2_E_ARG, "pf_resampling must be SMC2_PF_RS_SYSTEMATIC or SMC2_PF_RS_MULTINOMIAL");
     if (n_theta < 0 || (n_theta > 0 && (!d_theta || !d_ll))) return kfail(SMC2_E_ARG, "bad theta/ll");
     if (!d_ws || ws_bytes < smc2_pf_workspace_bytes(cfg, run) || ((uintptr_t)d_ws & 255u))
         return kfail(SMC2_E_ARG, "workspace missing, too small or not 256-byte aligned");
@@ -186,6 +188,7 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     a.N = n_theta;
     a.D = cfg->D;
     a.pf_always = cfg->pf_always;
+    a.multinomial = cfg->pf_resampling;
     a.n_pop = cfg->n_pop;
     for (int i = 0; i < SMC2_NFIXED; ++i) a.fx[i] = i < cfg->n_fixed ? cfg->fixed[i] : 0.0;
     if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64 != 0))

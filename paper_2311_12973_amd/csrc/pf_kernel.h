@@ -34,7 +34,7 @@ struct PFArgs {
     int32_t N;              // filters per run: g = run * N + filter
     int32_t D;
     int32_t pf_always;
-    int32_t pad;
+    int32_t multinomial;    // 1: multinomial resampling, 0: systematic
     double n_pop;
     double fx[32];          // model constants
 };

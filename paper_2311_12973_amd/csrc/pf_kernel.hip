@@ -412,6 +412,27 @@ __device__ __forceinline__ double particle_update(const MConst<real>& mc, int32_
     }
 }
 
+// Multinomial resampling (the paper's particle filter): slot m draws its own uniform
+// U_m = floor(x64_m Q / 2^64), x64_m the 64-bit word m & 1 of the Philox call
+// (m >> 1, filter, k<<16 | t, 2<<24 | 1<<16), and takes the first j whose inclusive scan
+// C_j (in LDS) exceeds it: ancestor j with probability q_j / Q, independently per slot.
+__device__ __forceinline__ void multinomial_ancestors(const uint64_t* C, int n, uint64_t Q, uint32_t filt,
+                                                      uint32_t kt, uint32_t k0, uint32_t k1, int32_t* anc)
+{
+    for (int m = (int)threadIdx.x; m < n; m += (int)blockDim.x) {
+        const W4 w = philox10((uint32_t)(m >> 1), filt, kt, (S_PF_RS << 24) | (1u << 16), k0, k1);
+        const uint64_t x64 = (m & 1) ? ((uint64_t)w.z | ((uint64_t)w.w << 32)) : ((uint64_t)w.x | ((uint64_t)w.y << 32));
+        const uint64_t U = __umul64hi(x64, Q);
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (C[mid] > U) hi = mid;
+            else lo = mid + 1;
+        }
+        anc[m] = lo;
+    }
+}
+
 // LDS layout of one filter (cap = particles rounded up to the block size):
 //   C   u64[cap]     quantised weights, then their inclusive scan
 //   tmp i32[cap]     gather staging
@@ -546,8 +567,12 @@ __device__ void pf_filter(const PFArgs& a, int item)
         }
         if (rs) {
             const uint64_t Q = block_scan_lds(C, nx, red);
-            const W4 wd = philox10(0u, filt, kt, S_PF_RS << 24, run.k0, run.k1);
-            block_ancestors(C, nx, Q, (uint64_t)wd.x | ((uint64_t)wd.y << 32), anc);
+            if (a.multinomial) {
+                multinomial_ancestors(C, nx, Q, filt, kt, run.k0, run.k1, anc);
+            } else {
+                const W4 wd = philox10(0u, filt, kt, S_PF_RS << 24, run.k0, run.k1);
+                block_ancestors(C, nx, Q, (uint64_t)wd.x | ((uint64_t)wd.y << 32), anc);
+            }
             __syncthreads();
 #pragma unroll
             for (int c = 0; c < NC; ++c) {

@@ -201,6 +201,8 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
     if (c->schedule < 0 || c->schedule > 2) return m = "schedule must be 0, 1 or 2", SMC2_E_ARG;
     if (c->tune < 0 || c->tune > 1) return m = "tune must be 0 or 1", SMC2_E_ARG;
     if (c->persistent < 0 || c->persistent > 1) return m = "persistent must be 0 or 1", SMC2_E_ARG;
+    if (c->pf_resampling != SMC2_PF_RS_SYSTEMATIC && c->pf_resampling != SMC2_PF_RS_MULTINOMIAL)
+        return m = "pf_resampling must be SMC2_PF_RS_SYSTEMATIC or SMC2_PF_RS_MULTINOMIAL", SMC2_E_ARG;
     if (c->schedule == 2 && c->model == SMC2_AGE_SEIR)
         return m = "the pooled schedule supports SIR and SEIR only", SMC2_E_UNSUPPORTED;
     if (!c->prior || !c->rw_cov) return m = "prior and rw_cov are required", SMC2_E_ARG;
@@ -531,6 +533,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     a.N = cfg->N;
     a.D = cfg->D;
     a.pf_always = cfg->pf_always;
+    a.multinomial = cfg->pf_resampling;
     a.n_pop = cfg->n_pop;
     for (int i = 0; i < SMC2_NFIXED; ++i) a.fx[i] = c->fixed[i];
 

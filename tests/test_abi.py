@@ -67,6 +67,12 @@ def test_workspace_bytes_and_validation():
     ra = G.make_runs([dict(T=10, nx=256, seed=1, y=ya)])
     assert L.smc2_workspace_bytes(ctypes.byref(ca), 1, ra) == 0
     assert b"pooled" in L.smc2_last_error(None)
+    for v in (2, -1):
+        c = G.make_config(dict(w, pf_resampling=v))
+        assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == 0
+        assert b"pf_resampling" in L.smc2_last_error(None)
+    c = G.make_config(dict(w, pf_resampling=G.PF_RS_MULTINOMIAL))
+    assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == nb
     yneg = y.copy()
     yneg[3] = -1
     assert L.smc2_workspace_bytes(ctypes.byref(cfg), 1, G.make_runs([dict(T=100, nx=512, seed=1, y=yneg)])) == 0

@@ -176,6 +176,36 @@ def test_pf_resample_every_step_and_ragged(schedule):
         assert np.allclose(got[fin], want[fin], rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("name,prec,nx,T", [("sir_fp64", G.PREC_FP64, 129, None), ("seir", G.PREC_FP32, 512, 60),
+                                            ("seir", G.PREC_FP64, 200, 30), ("age_seir", G.PREC_FP32, 300, 40)])
+@pytest.mark.parametrize("pf_always", [0, 1])
+def test_pf_multinomial_resampling_matches_oracle(name, prec, nx, T, pf_always):
+    """Multinomial resampling (one uniform per slot): log-likelihoods against the
+    reference, and every day's counts of two filters bit-identical to the reference's
+    (the ancestors are identical)."""
+    _log("pf multinomial %s prec=%d nx=%d pf_always=%d" % (name, prec, nx, pf_always))
+    w, y, theta = _pf_case(name, prec, nx, 16, T)
+    w = dict(w, pf_resampling=G.PF_RS_MULTINOMIAL)
+    got = G.pf_loglik(w, theta, y, nx, seed=9, k=2, precision=prec, pf_always=pf_always)
+    cfg = O.config_from_workload(w, prec=prec)
+    cfg.pf_always = pf_always
+    want = np.array([O.pf_loglik(cfg, theta[i], y, nx, 9, i, 2) for i in range(len(theta))])
+    fin = np.isfinite(want)
+    assert np.array_equal(np.isfinite(got), fin)
+    rel = np.abs(got[fin] - want[fin]) / np.abs(want[fin])
+    assert rel.max() <= (1e-12 if prec == G.PREC_FP64 else 1e-4)
+    assert np.mean(rel < 1e-11) >= 0.95
+    sys_ll = G.pf_loglik(dict(w, pf_resampling=G.PF_RS_SYSTEMATIC), theta, y, nx, seed=9, k=2, precision=prec,
+                         pf_always=pf_always)
+    assert not np.array_equal(got, sys_ll)
+    if pf_always:
+        _, _, rs, st = G.pf_trace_state(dict(w, pf_always=1), theta[:2], y, nx, seed=9, k=2, precision=prec)
+        for i in range(2):
+            _, _, rs_ref, st_ref = O.pf_trace_state(cfg, theta[i], y, nx, 9, i, 2)
+            assert np.array_equal(rs[i], rs_ref)
+            assert np.array_equal(st[i], st_ref)
+
+
 def test_pf_dead_filter_is_minus_inf():
     w = W.preset("paper_sir")
     y = np.zeros((5, 1), dtype=np.int32)

@@ -102,3 +102,52 @@ def test_trigger_is_exact_ess_half(n):
     q = np.zeros(n, dtype=np.uint64)
     q[0] = 2**32
     assert O.resample_trigger(q) == (n > 2)
+
+
+def test_multinomial_ancestors_have_the_weight_marginals():
+    """Multinomial resampling (the particle filter's scheme in Sec. II): every slot's
+    ancestor is j with probability q_j / Q, over independent streams (chi-square)."""
+    from scipy import stats
+    q = np.array([5, 1, 0, 9, 3, 2, 12], dtype=np.uint64) << np.uint64(20)
+    p = q.astype(float) / q.sum()
+    n = q.size
+    counts = np.zeros(n)
+    for filt in range(20000):
+        anc = O.resample_multinomial(q, 7, filt, 3)
+        counts += np.bincount(anc, minlength=n)
+    assert counts[2] == 0  # zero weight, never chosen
+    nz = p > 0
+    chi2 = (((counts - counts.sum() * p) ** 2)[nz] / (counts.sum() * p[nz])).sum()
+    assert stats.chi2.sf(chi2, nz.sum() - 1) > 1e-3
+
+
+def test_multinomial_copies_vary_like_a_multinomial():
+    """The number of copies of particle j is Binomial(n, q_j / Q): its variance
+    n p (1 - p) is far above systematic resampling's (< 1/4)."""
+    rng = np.random.default_rng(4)
+    n = 64
+    q = (rng.uniform(0.2, 1.0, n) * 2**32).astype(np.uint64)
+    p = q.astype(float) / q.astype(float).sum()
+    R = 4000
+    copies = np.array([np.bincount(O.resample_multinomial(q, 11, f, 5), minlength=n) for f in range(R)])
+    var = copies.var(0)
+    expect = n * p * (1 - p)
+    assert np.all(np.abs(copies.mean(0) - n * p) < 5 * np.sqrt(expect / R))
+    assert np.mean(var / expect) == pytest.approx(1.0, abs=0.06)
+    sys_copies = np.array([np.bincount(O.resample_ancestors(q, (f * 0x9E3779B97F4A7C15) % 2**64), minlength=n)
+                           for f in range(200)])
+    assert sys_copies.var(0).max() <= 0.25 + 1e-12
+
+
+def test_multinomial_ancestor_is_the_first_scan_entry_above_its_uniform():
+    """Brute force on a tiny case: the ancestor of slot m is min{j : C_j > U_m}."""
+    q = np.array([3, 0, 7, 1, 4], dtype=np.uint64) << np.uint64(28)
+    C = np.cumsum(q.astype(object))
+    Q = int(C[-1])
+    for filt in range(50):
+        anc = O.resample_multinomial(q, 13, filt, 9)
+        for m in range(q.size):
+            w = O.philox([m >> 1, filt, 9, (2 << 24) | (1 << 16)], [13, 0])
+            x64 = int(w[2]) | (int(w[3]) << 32) if m & 1 else int(w[0]) | (int(w[1]) << 32)
+            U = (x64 * Q) >> 64
+            assert anc[m] == next(j for j in range(q.size) if C[j] > U)
