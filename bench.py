@@ -45,7 +45,7 @@ KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_a
 KERNEL_SHA = "a4b0f1e59faeac37"
 PROFILED_WORKLOAD = "seir"
 VALU_LANE_INSTR_PER_PSTEP = 1574.9
-HBM_BYTES_PER_LAUNCH = 1.0116e6
+HBM_BYTES_PER_LAUNCH = 1.0086e6
 
 
 def kernel_sha():
