@@ -42,18 +42,27 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_amd/csrc/pf_kernel.h",
                   "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h",
                   "paper_2311_12973_amd/build.py"]
-KERNEL_SHA = "a4b0f1e59faeac37"
+KERNEL_SHA = "40961ce125e84f7c"
 PROFILED_WORKLOAD = "seir"
 VALU_LANE_INSTR_PER_PSTEP = 1574.9
 HBM_BYTES_PER_LAUNCH = 1.0086e6
 
 
 def kernel_sha():
+    """Hash of the kernel sources and build flags with comments and whitespace removed
+    (a documentation edit leaves it unchanged)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            text = fh.read()
+        if f.endswith(".py"):
+            text = re.sub(r"#[^\n]*", "", text)
+        else:
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+        h.update(re.sub(r"\s+", "", text).encode())
     return h.hexdigest()[:16]
 
 

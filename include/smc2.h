@@ -93,7 +93,7 @@ extern "C" {
 /* particle-filter draw schedule (smc2_config.schedule); both give identical results */
 #define SMC2_SCHED_AUTO 0     /* pooled where supported and it fits in LDS, else per draw */
 #define SMC2_SCHED_PER_DRAW 1 /* each lane finishes its draws one after another          */
-#define SMC2_SCHED_POOLED 2   /* SIR/SEIR: a wave pools its draws and runs the FP64 final
+#define SMC2_SCHED_POOLED 2   /* SIR/SEIR: a wave pools its draws and runs the final
                                  acceptance tests of the BTRS sampler 64 at a time        */
 
 /* Particle-filter resampling (Sec. II; both from the quantised weights q_j and their

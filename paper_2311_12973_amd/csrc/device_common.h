@@ -14,10 +14,12 @@
 // Uniforms: u24(x) = (2(x>>9)+1) 2^-24 (exact in FP32); u53 = (2(x64>>12)+1) 2^-53.
 //
 // Precision: the particle filter works in `real` (float or double). Every
-// transcendental is evaluated in FP64 and rounded to `real`, every other
+// transcendental is defined as its FP64 value rounded to `real`, every other
 // operation is one IEEE operation in `real` (the library is built with
 // -ffp-contract=off), so a reimplementation that follows the same definitions
-// reproduces each integer decision.
+// reproduces each integer decision. Two pieces reach the same result in FP32: the
+// square root (correctly rounded) and the BTRS final test's decision (FP32 with an
+// error bound, FP64 near the boundary).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -150,8 +152,9 @@ __device__ __forceinline__ double lfact(double x)
 
 // BTRS transformed rejection (W. Hoermann, J. Stat. Comput. Simul. 46, 1993) for
 // p <= 1/2, n p >= 10. Constants, proposal index and squeeze in `real`; the centre
-// n p + 1/2 split in FP64 into integer and fraction; the final acceptance test in
-// FP64 on log-factorials. Attempt e uses words 2(e&1), 2(e&1)+1 of call e>>1.
+// n p + 1/2 split in FP64 into integer and fraction; the final acceptance test is
+// defined in FP64 on log-factorials (btrs_final) and decided FP32-first with an error
+// bound (btrs_final_fast, btrs_decide). Attempt e uses words 2(e&1), 2(e&1)+1 of call e>>1.
 // The three pieces below are shared by the per-draw sampler (binom_btrs) and the
 // particle filter's pooled schedule, which defers final tests; both take identical
 // decisions because each piece is a pure function of (n, p, k, words).

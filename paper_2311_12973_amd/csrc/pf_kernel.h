@@ -40,7 +40,7 @@ struct PFArgs {
 };
 
 // How a workgroup schedules the binomial draws of a day: every lane finishes its own
-// draws in turn, or (SIR, SEIR) the wave pools the draws and batches the FP64 final
+// draws in turn, or (SIR, SEIR) the wave pools the draws and batches the final
 // acceptance tests of the BTRS sampler. Both give identical flows.
 enum : int { PF_SCHED_AUTO = 0, PF_SCHED_PER_DRAW = 1, PF_SCHED_POOLED = 2 };
 // dynamic LDS budget of one workgroup (the kernel adds a few bytes of static LDS)

@@ -184,10 +184,10 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
 // Every round each free lane takes the next item (inversion draws and trivial
 // cases finish at once), and every lane with a BTRS item makes one attempt. An
 // attempt that passes neither the squeeze nor the range check is retried next
-// round; one that needs the FP64 final test is appended to the wave's queue in LDS
-// and the lane moves on. When 64 tests are queued (or nothing else is left) the
-// wave runs them with all lanes busy; a rejected candidate continues with its next
-// attempt in that lane. A 64-wide wave otherwise pays for the final test whenever
+// round; one that needs the final acceptance test is appended to the wave's queue in
+// LDS and the lane moves on. When 64 tests are queued (or nothing else is left) the
+// wave runs them with all lanes busy (FP32 first, FP64 only near the boundary); a
+// rejected candidate continues with its next attempt in that lane. A 64-wide wave otherwise pays for the final test whenever
 // any one lane needs it, which is nearly every round. Every attempt is a pure
 // function of its Philox coordinates, so the flows equal the per-draw schedule's.
 // Flows go to flows[b * cap + j] (the quantised-weight and gather buffers, free
