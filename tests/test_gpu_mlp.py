@@ -195,3 +195,26 @@ def test_learned_proposal_gains_over_random_walk():
     assert np.allclose(mlp["sd"], rw["sd"], rtol=0.25)
     assert mlp["ess_rep"] >= rw["ess_rep"]
     assert mlp["rate"] >= 3 * rw["rate"]
+
+
+def test_learned_proposal_graph_replay_matches_direct_launches():
+    """One iteration (begin, network outputs, proposal, filters, outer step, training)
+    captured as a HIP graph and replayed K times, with the sampler's own reads and
+    synchronisations between the replays, equals the direct launches after every
+    iteration; the filters resample multinomially here."""
+    w, y = _learned_case()
+    w = dict(w, pf_resampling=G.PF_RS_MULTINOMIAL)
+    out = []
+    for graph in (0, 1):
+        s = G.Sampler(w, [dict(T=y.shape[0], nx=64, seed=5, y=y)], N=256, K=5, use_graph=graph)
+        it = []
+        for _ in range(5):
+            s.step()
+            it.append({key: s.dump(key) for key in ("phi_new", "ll_new", "logw_pre", "anc", "mlp_params", "logq")})
+        it.append({"rec": s.records()})
+        s.close()
+        out.append(it)
+    assert out[0][-1]["rec"][1:, -2].any()  # the network proposed at some iteration
+    for k, (a, b) in enumerate(zip(out[0], out[1])):
+        for key in a:
+            assert np.array_equal(a[key], b[key]), (k, key)
