@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--graph", type=int, default=0)
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0, help="particle-filter draw schedule (0 auto, 1 per draw, 2 pooled)")
+    ap.add_argument("--tune", type=int, default=0, help="1: time the launch configurations at init and keep the fastest")
+    ap.add_argument("--persistent", type=int, default=0, help="1: persistent grid pulling filters from the work list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ess", action="store_true", help="skip the learned-proposal vs random-walk ESS/s comparison")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
@@ -106,7 +108,8 @@ def main():
         runs = [dict(T=w["T"], nx=w["nx"], seed=w["seed"], y=W.observations(w))]
     N = w["N"]
     K = args.warmup + args.steps
-    s = G.Sampler(w, runs, N=N, K=K, use_graph=args.graph, block=args.block, schedule=args.schedule)
+    s = G.Sampler(w, runs, N=N, K=K, use_graph=args.graph, block=args.block, schedule=args.schedule, tune=args.tune,
+                  persistent=args.persistent)
     for _ in range(args.warmup):
         s.step()
     torch.cuda.synchronize()
@@ -162,6 +165,7 @@ def main():
         "data": "synthetic (observations simulated from the model at fixed seeds)",
         "config": {"workload": desc, "runs": len(runs), "N": N, "global_batch": N * len(runs),
                    "particle_steps_per_iteration": psteps, "parallelism": "single GPU", "graph": bool(args.graph),
+                   "tune": bool(args.tune), "persistent": bool(args.persistent),
                    "dead_samples_per_step": dead, "device_ms_per_step": ms_step_dev},
         "roofline": roofline, "cpu_baseline": cpu, "ess_per_s": ess,
     }
