@@ -91,9 +91,15 @@ def _learned_case():
     return w, W.observations(w)
 
 
-def test_learned_proposal_replayed_by_reference():
-    w, y = _learned_case()
-    N, K, nx = 256, 4, 128
+@pytest.mark.parametrize("case", ["seir_d5", "age_seir_d8"])
+def test_learned_proposal_replayed_by_reference(case):
+    if case == "seir_d5":
+        w, y = _learned_case()
+        N, K, nx = 256, 4, 128
+    else:  # the age-structured model, D = 8 (the largest network)
+        w = dict(W.preset("age_seir"), T=30, mlp_epochs=3, mlp_batch=64, mlp_lr=3e-3)
+        y = W.observations(w)
+        N, K, nx = 128, 4, 64
     D = w["D"]
     s = G.Sampler(w, [dict(T=y.shape[0], nx=nx, seed=w["seed"], y=y)], N=N, K=K)
     cfg = O.config_from_workload(w)
