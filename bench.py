@@ -173,21 +173,22 @@ def main():
 
 
 def ess_per_second(G, W, np):
-    """ESS per second at the same posterior, learned proposal vs random walk: SEIR with
-    the dispersion estimated (D = 5), T = 40, N_x = 256, K = 6; 16 independent runs of
-    each form (one batched sampler per form), the learned proposal with N = 512, the
-    random walk with N = 4096. Replicate ESS = posterior variance / variance of the
-    recycled posterior mean across runs (averaged over coordinates); per second of the
-    whole batch's iterations, per run."""
+    """ESS per second at the same posterior, learned proposal vs random walk, on the
+    learned-proposal configuration: SEIR with the dispersion estimated (D = 5), T = 150,
+    N = 4096, N_x = 1024, K = 20; 8 independent runs of each form (one batched sampler
+    per form). Replicate ESS = posterior variance / variance of the recycled posterior
+    mean across runs (averaged over coordinates); per second of the whole batch's
+    iterations, per run."""
     import torch
 
-    w = dict(W.preset("seir_learned"), T=40, mlp_epochs=4, mlp_batch=128, mlp_lr=3e-3)
+    w = W.preset("seir_learned")
     y = W.observations(w)
-    seeds = list(range(1, 17))
+    seeds = list(range(1, 9))
+    K = w["K"]
     out = {}
-    for name, prop, N in (("learned", G.PROP_MLP, 512), ("random_walk", G.PROP_RW, 4096)):
-        K = 6
-        s = G.Sampler(dict(w, proposal=prop), [dict(T=y.shape[0], nx=256, seed=sd, y=y) for sd in seeds], N=N, K=K)
+    for name, prop in (("learned", G.PROP_MLP), ("random_walk", G.PROP_RW)):
+        s = G.Sampler(dict(w, proposal=prop), [dict(T=y.shape[0], nx=w["nx"], seed=sd, y=y) for sd in seeds],
+                      N=w["N"], K=K)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(K):
@@ -195,17 +196,19 @@ def ess_per_second(G, W, np):
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         est = [s.estimate(r, recycled=True) for r in range(len(seeds))]
+        wess = float(np.mean([s.records(r)[1:, 1].mean() for r in range(len(seeds))]))
         s.close()
         means = np.array([m for m, _ in est])
         post_var = np.mean([np.diag(c) for _, c in est], 0)
         ess = 1.0 / float(np.mean(means.var(0, ddof=1) / post_var))
-        out[name] = {"N": N, "replicate_ess": ess, "seconds": sec, "ess_per_s_per_run": ess / (sec / len(seeds)),
-                     "posterior_mean": means.mean(0).tolist(), "posterior_sd": np.sqrt(post_var).tolist()}
+        out[name] = {"N": w["N"], "replicate_ess": ess, "weight_ess_per_iteration": wess, "seconds": sec,
+                     "ess_per_s_per_run": ess / (sec / len(seeds)), "posterior_mean": means.mean(0).tolist(),
+                     "posterior_sd": np.sqrt(post_var).tolist()}
     sd = 0.5 * (np.array(out["learned"]["posterior_sd"]) + np.array(out["random_walk"]["posterior_sd"]))
     out["mean_difference_in_sd"] = ((np.array(out["learned"]["posterior_mean"]) -
                                      np.array(out["random_walk"]["posterior_mean"])) / sd).tolist()
     out["speedup"] = out["learned"]["ess_per_s_per_run"] / out["random_walk"]["ess_per_s_per_run"]
-    out["workload"] = "seir_learned at T=40, N_x=256, K=6, 16 runs per form"
+    out["workload"] = "seir_learned: D=5, T=150, N=4096, N_x=1024, K=20, 8 runs per form"
     return out
 
 
