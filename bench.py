@@ -178,7 +178,7 @@ def ess_per_second(G, W, np):
     N = 4096, N_x = 1024, K = 20; 8 independent runs of each form (one batched sampler
     per form). Replicate ESS = posterior variance / variance of the recycled posterior
     mean across runs (averaged over coordinates); per second of the whole batch's
-    iterations, per run."""
+    iterations, per run. Also the recycled ESS sum_k l_k of each run per second."""
     import torch
 
     w = W.preset("seir_learned")
@@ -197,17 +197,21 @@ def ess_per_second(G, W, np):
         sec = time.perf_counter() - t0
         est = [s.estimate(r, recycled=True) for r in range(len(seeds))]
         wess = float(np.mean([s.records(r)[1:, 1].mean() for r in range(len(seeds))]))
+        ress = float(np.mean([s.records(r)[:, 1].sum() for r in range(len(seeds))]))  # recycled ESS, sum_k l_k
         s.close()
         means = np.array([m for m, _ in est])
         post_var = np.mean([np.diag(c) for _, c in est], 0)
         ess = 1.0 / float(np.mean(means.var(0, ddof=1) / post_var))
         out[name] = {"N": w["N"], "replicate_ess": ess, "weight_ess_per_iteration": wess, "seconds": sec,
+                     "recycled_ess": ress, "recycled_ess_per_s_per_run": ress / (sec / len(seeds)),
                      "ess_per_s_per_run": ess / (sec / len(seeds)), "posterior_mean": means.mean(0).tolist(),
                      "posterior_sd": np.sqrt(post_var).tolist()}
     sd = 0.5 * (np.array(out["learned"]["posterior_sd"]) + np.array(out["random_walk"]["posterior_sd"]))
     out["mean_difference_in_sd"] = ((np.array(out["learned"]["posterior_mean"]) -
                                      np.array(out["random_walk"]["posterior_mean"])) / sd).tolist()
     out["speedup"] = out["learned"]["ess_per_s_per_run"] / out["random_walk"]["ess_per_s_per_run"]
+    out["recycled_ess_speedup"] = (out["learned"]["recycled_ess_per_s_per_run"] /
+                                   out["random_walk"]["recycled_ess_per_s_per_run"])
     out["workload"] = "seir_learned: D=5, T=150, N=4096, N_x=1024, K=20, 8 runs per form"
     return out
 
