@@ -42,10 +42,10 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_amd/csrc/pf_kernel.h",
                   "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h",
                   "paper_2311_12973_amd/build.py"]
-KERNEL_SHA = "40961ce125e84f7c"
+KERNEL_SHA = "2aa212109eb66ada"
 PROFILED_WORKLOAD = "seir"
-VALU_LANE_INSTR_PER_PSTEP = 1574.9
-HBM_BYTES_PER_LAUNCH = 1.0086e6
+VALU_LANE_INSTR_PER_PSTEP = 1525.1
+HBM_BYTES_PER_LAUNCH = 0.9891e6
 
 
 def kernel_sha():

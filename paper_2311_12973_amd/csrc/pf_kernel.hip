@@ -260,30 +260,37 @@ __device__ __forceinline__ bool item_begin(const MConst<real>& mc, const int32_t
 
 template <typename real, int MODEL>
 __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t* flows, int cap, int nx,
-                             WavePool<real>* q, uint32_t filt, uint32_t kt, uint32_t k0, uint32_t k1)
+                             WavePool<real>* q, uint32_t filt, uint32_t kt, uint32_t k0, uint32_t k1, int* wg_next)
 {
     constexpr int ND = ModelShape<MODEL>::NC;
-    const int nthr = (int)blockDim.x;
     const int lane = lane_id();
-    const int wbase = wave_id() * 64;
-    const int P = 64 * (cap / nthr);  // particle slots of this wave
-    const int F = ND * P;             // items of this wave (b-major: one draw type at a time)
+    const int F = ND * cap;           // items of the workgroup, b-major: item f is (b, j) = (f / cap, f % cap)
     const uint64_t below = lanes_below();
-    int next = 0, fq = 0;             // wave-uniform: next fresh item, queued final tests
+    int fq = 0;                       // wave-uniform: queued final tests
+    bool exhausted = false;           // wave-uniform: the workgroup's item list is used up
     bool busy = false;
     int32_t j = 0, b = 0, n = 0, e = 0;
     bool flip = false;
     real pp = (real)0;
     BtrsConst<real> c{};
     for (;;) {
-        // 1. free lanes take the next items
+        // 1. free lanes take the next items of the workgroup's list (the waves share it,
+        //    so a wave whose draws needed fewer attempts takes more items)
         const uint64_t freem = __ballot(!busy);
+        const int nfree = __popcll(freem);
+        int base = 0;
+        if (!exhausted && nfree > 0) {
+            if (lane == 0) base = atomicAdd(wg_next, nfree);
+            base = uniform_i32(base);  // lane 0's value: every lane is active here
+            if (base + nfree >= F) exhausted = true;
+        } else {
+            base = F;
+        }
         if (!busy) {
-            const int f = next + __popcll(freem & below);
+            const int f = base + __popcll(freem & below);
             if (f < F) {
-                b = f / P;
-                const int jl = f - b * P;
-                j = wbase + (jl & 63) + (jl >> 6) * nthr;
+                b = (f >= cap ? 1 : 0) + (ND > 2 && f >= 2 * cap ? 1 : 0);
+                j = f - b * cap;
                 if (j < nx) {
                     int32_t res;
                     const DrawStream ds{(uint32_t)j, filt, kt, (uint32_t)b, k0, k1};
@@ -296,7 +303,6 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
                 }
             }
         }
-        next += __popcll(freem);
         // 2. one BTRS attempt per busy lane
         bool push = false;
         int64_t kk = 0;
@@ -328,7 +334,7 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
                              (uint32_t)j | ((uint32_t)b << 12) | ((uint32_t)flip << 15) | ((uint32_t)e << 16), n,
                              (int32_t)kk, wu, wv, pp);
         fq += __popcll(pushm);
-        const bool more = next < F || __ballot(busy) != 0ull;
+        const bool more = !exhausted || __ballot(busy) != 0ull;
         // flush while a full batch is queued (so the queue holds < 64 entries before the
         // next round adds at most 64), and everything once no new attempts remain
         while (fq >= 64 || (!more && fq > 0)) {
@@ -462,6 +468,7 @@ __device__ void pf_filter(const PFArgs& a, int item)
     const int cap = ((nx + nthr - 1) / nthr) * nthr;
 
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ int wg_next;  // next draw item of the day (pooled schedule)
     uint64_t* C = reinterpret_cast<uint64_t*>(smem);
     int32_t* tmp = reinterpret_cast<int32_t*>(C + cap);
     int32_t* anc = tmp + cap;
@@ -488,6 +495,7 @@ __device__ void pf_filter(const PFArgs& a, int item)
         for (int c = 0; c < NC; ++c) st[c * cap + j] = mc.x0[c];
         lw[j] = (real)0;
     }
+    if (tid == 0) wg_next = 0;
     __syncthreads();
 
     double ll = 0.0;
@@ -498,7 +506,9 @@ __device__ void pf_filter(const PFArgs& a, int item)
         // 1. propagate and weight: lw[j] <- a_j = lw_j + log g(y_t | x_t^j)
         real amax = (real)-INFINITY;
         if constexpr (SCHED == PF_SCHED_POOLED && MODEL != MODEL_AGE) {
-            draws_pooled<real, MODEL>(mc, st, flows, cap, nx, pool, filt, kt, run.k0, run.k1);
+            draws_pooled<real, MODEL>(mc, st, flows, cap, nx, pool, filt, kt, run.k0, run.k1, &wg_next);
+            __syncthreads();  // any wave may have drawn any particle's flows
+            if (tid == 0) wg_next = 0;  // for the next day (read again only after further barriers)
             for (int j = tid; j < nx; j += nthr) {
                 const double lg = particle_update<real, MODEL, OBS>(mc, st, flows, cap, j, yt);
                 const real av = lw[j] + (real)lg;
