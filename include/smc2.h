@@ -172,7 +172,9 @@ typedef struct {
 /* learned proposal (SMC2_PROP_MLP only) */
 #define SMC2_DUMP_MLP_OUT 9     /* N x P  float: network outputs at the population the
                                    last step proposed from (P = D + D(D+1)/2)            */
-#define SMC2_DUMP_LOGQ 10       /* N      doubles: log q(phi_new | phi) of the last step   */
+#define SMC2_DUMP_LOGQ 10       /* N      doubles: log q(phi_new | phi) of the learned
+                                   proposal at the last step; 0 where that step drew from
+                                   the prior (k = 1) or the random walk                   */
 #define SMC2_DUMP_MLP_PARAMS 11 /* NP     float: FP32 master weights W1[64][D] b1[64]
                                    W2[64][64] b2[64] W3[P][64] b3[P] (after training)    */
 #define SMC2_DUMP_MLP_FRAME 12  /* D+D*D  doubles: input frame of the current network: the

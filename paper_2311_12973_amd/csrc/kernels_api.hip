@@ -201,6 +201,13 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     const size_t lds = pf_lds_bytes(cfg->model, cfg->precision, block, run->n_x, run->T, sched);
     if (lds > PF_LDS_MAX) return kfail(SMC2_E_ARG, "particle filter does not fit in LDS");
     if (e == hipSuccess) e = pf_prepare(cfg->precision, cfg->model, cfg->obs, sched, lds);
+    // wave priorities when every filter is resident at once (they even out its tail)
+    int per_cu = 0, n_cu = 0, dev = 0;
+    if (e == hipSuccess) e = pf_occupancy(cfg->precision, cfg->model, cfg->obs, sched, block, lds, &per_cu);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess && (long)n_theta <= (long)per_cu * n_cu)
+        a.prio_scale = (float)(1.0 / ((double)run->T * (double)run->n_x));
     if (e == hipSuccess) e = launch_pf(cfg->precision, cfg->model, cfg->obs, sched, block, lds, a, s);
     // the host copies of rd and y must stay valid until the copies have run
     if (e == hipSuccess) e = hipStreamSynchronize(s);

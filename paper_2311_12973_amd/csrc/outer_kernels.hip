@@ -108,6 +108,8 @@ __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, c
             }
         }
     }
+    // the learned proposal's density is stored where it proposed; 0 marks the other draws
+    if (p.mlp && (k == 1 || !o.mlp_use[r])) o.logq[g] = 0.0;
     double lpn = 0.0;
 #pragma unroll
     for (int d = 0; d < D; ++d) {

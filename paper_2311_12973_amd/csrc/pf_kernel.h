@@ -35,6 +35,8 @@ struct PFArgs {
     int32_t D;
     int32_t pf_always;
     int32_t multinomial;    // 1: multinomial resampling, 0: systematic
+    float prio_scale;       // 1 / largest T_r * N_x,r of the launch: wave priority from the
+                            // filter's remaining work (0: leave the priority alone)
     double n_pop;
     double fx[32];          // model constants
 };

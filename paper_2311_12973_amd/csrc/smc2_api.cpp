@@ -126,8 +126,18 @@ struct PFGroup {
     int persistent;  // 1: resident workgroups pull filters from the work list
     int grid;        // workgroups launched when persistent
     int max_nx, max_T;
-    float tuned_ms;  // time of the chosen configuration on the tuning sample (0: not tuned)
+    float tuned_ms;   // time of the chosen configuration on the tuning sample (0: not tuned)
+    double max_cost;  // largest T_r * N_x,r of the group's runs
+    long resident;    // workgroups of this configuration resident at once on the device
+    float prio;       // PFArgs::prio_scale of the group's launches
 };
+
+// Wave-priority scale of a launch of n filters of this group: only when every filter
+// is resident at once (the priorities even out the tail of a single round).
+float prio_scale(const PFGroup& gr, long n)
+{
+    return gr.max_cost > 0.0 && n <= gr.resident ? (float)(1.0 / gr.max_cost) : 0.f;
+}
 
 }  // namespace
 
@@ -247,15 +257,16 @@ extern "C" size_t smc2_workspace_bytes(const smc2_config* cfg, int32_t n_runs, c
     return make_layout(cfg, n_runs, runs).total;
 }
 
-// Persistent grid of a group: every workgroup that can be resident at once, at most one
-// per filter.
-static hipError_t set_grid(smc2_ctx* c, PFGroup& gr)
+// Launch shape of a group: the workgroups resident at once, the persistent grid (all of
+// them, at most one per filter) and the wave-priority scale.
+static hipError_t set_launch(smc2_ctx* c, PFGroup& gr)
 {
     int per_cu = 0;
     const hipError_t e = pf_occupancy(c->cfg.precision, c->cfg.model, c->cfg.obs, gr.sched, gr.block, gr.lds, &per_cu);
     if (e != hipSuccess) return e;
-    const long cap = (long)(per_cu > 0 ? per_cu : 1) * (c->n_cu > 0 ? c->n_cu : 1);
-    gr.grid = (int)std::min<long>(cap, gr.n_items);
+    gr.resident = (long)(per_cu > 0 ? per_cu : 1) * (c->n_cu > 0 ? c->n_cu : 1);
+    if (gr.persistent) gr.grid = (int)std::min<long>(gr.resident, gr.n_items);
+    gr.prio = prio_scale(gr, gr.n_items);
     return hipSuccess;
 }
 
@@ -306,7 +317,7 @@ static hipError_t autotune(smc2_ctx* c)
                     cand.sched = sc;
                     cand.lds = lds;
                     cand.persistent = pers;
-                    if (pers) e = set_grid(c, cand);
+                    e = set_launch(c, cand);
                     if (e != hipSuccess) break;
                     PFArgs a = c->pa;
                     a.items = d_tune;
@@ -314,6 +325,7 @@ static hipError_t autotune(smc2_ctx* c)
                     a.k_dev = nullptr;
                     a.k_const = 1;
                     a.queue = pers ? d_queue : nullptr;
+                    a.prio_scale = prio_scale(cand, S);
                     int grid = pers ? std::min(cand.grid, S) : 0;
                     float ms = -1.f;
                     for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {  // rep 0 warms up
@@ -420,7 +432,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     });
     for (size_t idx = 0; idx < run_order.size();) {
         const int b = blk[run_order[idx]];
-        PFGroup gr{b, 0, (int)items.size(), 0, PF_SCHED_POOLED, cfg->persistent, 0, 0, 0, 0.f};
+        PFGroup gr{b, 0, (int)items.size(), 0, PF_SCHED_POOLED, cfg->persistent, 0, 0, 0, 0.f, 0.0, 0, 0.f};
         const size_t g0 = idx;
         // the pooled schedule when every run of the group fits in LDS with it
         for (size_t x = g0; x < run_order.size() && blk[run_order[x]] == b; ++x) {
@@ -438,6 +450,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
             gr.lds = std::max(gr.lds, pf_lds_bytes(cfg->model, cfg->precision, b, runs[r].n_x, runs[r].T, gr.sched));
             gr.max_nx = std::max(gr.max_nx, runs[r].n_x);
             gr.max_T = std::max(gr.max_T, runs[r].T);
+            gr.max_cost = std::max(gr.max_cost, (double)runs[r].T * (double)runs[r].n_x);
         }
         gr.n_items = (int)items.size() - gr.first_item;
         c->groups.push_back(gr);
@@ -569,7 +582,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     if (e == hipSuccess && cfg->tune) e = autotune(c);
     for (PFGroup& gr : c->groups) {
         if (e != hipSuccess) break;
-        if (gr.persistent) e = set_grid(c, gr);
+        e = set_launch(c, gr);
     }
     if (e == hipSuccess) {
         c->ev.resize(4 * (size_t)cfg->K, nullptr);
@@ -600,6 +613,7 @@ static hipError_t enqueue_iteration(smc2_ctx* c, hipStream_t s, hipEvent_t pf0, 
         a.items = c->pa.items + gr.first_item;
         a.n_items = gr.n_items;
         a.queue = gr.persistent ? queues + gi : nullptr;
+        a.prio_scale = gr.prio;
         e = launch_pf(c->cfg.precision, c->cfg.model, c->cfg.obs, gr.sched, gr.block, gr.lds, a, s, gr.grid);
     }
     if (e == hipSuccess && pf1) e = hipEventRecord(pf1, s);

@@ -117,6 +117,8 @@ def test_learned_proposal_replayed_by_reference(case):
         used = bool(rec[RL - 2])
         _log("k=%d learned=%d ESS %.1f score %.4g" % (k, used, rec[1], rec[RL - 1]))
         lq = None
+        if not used:
+            assert not s.dump("logq").any(), k  # no learned density at prior or random-walk steps
         if used:
             used_any = True
             out = s.dump("mlp_out")
