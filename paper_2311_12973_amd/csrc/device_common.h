@@ -163,20 +163,27 @@ template <typename real> struct BtrsConst {
     int64_t ci;
 };
 
-template <typename real> __device__ __forceinline__ BtrsConst<real> btrs_setup(int32_t n, real p)
+// The set-up given its two costly values, spq = sqrt(n p q) and vr = 0.92 - 4.2 / bb.
+template <typename real>
+__device__ __forceinline__ BtrsConst<real> btrs_setup_from(int32_t n, real p, real spq, real vr)
 {
     BtrsConst<real> c;
-    const real nr = (real)n;
-    const real q = (real)1 - p;
-    c.spq = rsqrt_rn<real>((nr * p) * q);
+    c.spq = spq;
     c.bb = (real)1.15 + (real)2.53 * c.spq;
     c.aa = ((real)-0.0873 + (real)0.0248 * c.bb) + (real)0.01 * p;
-    c.vr = (real)0.92 - rdiv<real>((real)4.2, c.bb);
+    c.vr = vr;
     const double cc = (double)n * (double)p + 0.5;
     const double cfl = floor(cc);
     c.ci = (int64_t)cfl;
     c.cf = (real)(cc - cfl);
     return c;
+}
+
+template <typename real> __device__ __forceinline__ BtrsConst<real> btrs_setup(int32_t n, real p)
+{
+    const real spq = rsqrt_rn<real>(((real)n * p) * ((real)1 - p));
+    const real bb = (real)1.15 + (real)2.53 * spq;
+    return btrs_setup_from<real>(n, p, spq, (real)0.92 - rdiv<real>((real)4.2, bb));
 }
 
 enum : int { BTRS_OUT = 0, BTRS_ACCEPT = 1, BTRS_FINAL = 2 };

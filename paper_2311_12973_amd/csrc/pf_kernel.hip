@@ -201,11 +201,13 @@ template <typename real> struct WavePool {
     uint32_t wu[POOL_CAP];
     uint32_t wv[POOL_CAP];
     real p[POOL_CAP];
+    real spq[POOL_CAP];  // the draw's BTRS set-up values sqrt(n p q) and v_r, so that the
+    real vr[POOL_CAP];   // test does not redo the root and the division
 };
 
 template <typename real> __device__ __forceinline__ void pool_store(WavePool<real>* q, int s, uint32_t id,
                                                                      int32_t n, int32_t k, uint32_t wu,
-                                                                     uint32_t wv, real p)
+                                                                     uint32_t wv, real p, const BtrsConst<real>& c)
 {
     q->id[s] = id;
     q->n[s] = n;
@@ -213,6 +215,8 @@ template <typename real> __device__ __forceinline__ void pool_store(WavePool<rea
     q->wu[s] = wu;
     q->wv[s] = wv;
     q->p[s] = p;
+    q->spq[s] = c.spq;
+    q->vr[s] = c.vr;
 }
 
 __device__ __forceinline__ uint64_t lanes_below() { return __lanemask_lt(); }
@@ -332,7 +336,7 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
         if (push)
             pool_store<real>(q, fq + __popcll(pushm & below),
                              (uint32_t)j | ((uint32_t)b << 12) | ((uint32_t)flip << 15) | ((uint32_t)e << 16), n,
-                             (int32_t)kk, wu, wv, pp);
+                             (int32_t)kk, wu, wv, pp, c);
         fq += __popcll(pushm);
         const bool more = !exhausted || __ballot(busy) != 0ull;
         // flush while a full batch is queued (so the queue holds < 64 entries before the
@@ -344,7 +348,7 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
             const bool mine = lane < m;
             uint32_t id2 = 0, wu2 = 0, wv2 = 0;
             int32_t n2 = 0, k2 = 0;
-            real p2 = (real)0;
+            real p2 = (real)0, spq2 = (real)1, vr2 = (real)0;
             if (mine) {
                 const int s = base + lane;
                 id2 = q->id[s];
@@ -353,6 +357,8 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
                 wu2 = q->wu[s];
                 wv2 = q->wv[s];
                 p2 = q->p[s];
+                spq2 = q->spq[s];
+                vr2 = q->vr[s];
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             fq = base;
@@ -362,7 +368,7 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
             if (mine) {
                 const int j2 = (int)(id2 & 0xFFFu), b2 = (int)((id2 >> 12) & 7u);
                 const bool flip2 = ((id2 >> 15) & 1u) != 0u;
-                const BtrsConst<real> c2 = btrs_setup<real>(n2, p2);
+                const BtrsConst<real> c2 = btrs_setup_from<real>(n2, p2, spq2, vr2);
                 int32_t res = -1;
                 if (btrs_decide<real>(c2, n2, p2, kk2, wu2, wv2)) {
                     res = k2;
@@ -387,7 +393,9 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
                 id2 = (id2 & 0xFFFFu) | ((uint32_t)e2 << 16);
             }
             const uint64_t pm = __ballot(push2);
-            if (push2) pool_store<real>(q, fq + __popcll(pm & below), id2, n2, (int32_t)kk2, wu2, wv2, p2);
+            if (push2)
+                pool_store<real>(q, fq + __popcll(pm & below), id2, n2, (int32_t)kk2, wu2, wv2, p2,
+                                 BtrsConst<real>{spq2, (real)0, (real)0, vr2, (real)0, 0});
             fq += __popcll(pm);
         }
         if (!more && fq == 0) break;
@@ -516,7 +524,8 @@ __device__ void pf_filter(const PFArgs& a, int item)
     __syncthreads();
 
     double ll = 0.0;
-    double s_prev = (double)nx;
+    const double log_nx = log((double)nx);
+    double log_prev = log_nx;  // log of the previous day's weight sum (N_x after a resampling)
     for (int t = 1; t <= T; ++t) {
         const uint32_t kt = (kit << 16) | (uint32_t)t;
         if (a.prio_scale > 0.f) wave_priority((float)(T - t + 1) * (float)nx * a.prio_scale);
@@ -584,9 +593,10 @@ __device__ void pf_filter(const PFArgs& a, int item)
         block_sum3(sl, q1, q2, red);
         sl = 0.0;
         for (int c = 0; c < (cap >> 6); ++c) sl += red->chunk[c];
-        const double inc = (((double)m + log(sl)) - log(s_prev)) + cst[t - 1];
+        const double lsl = log(sl);
+        const double inc = (((double)m + lsl) - log_prev) + cst[t - 1];
         ll = ll + inc;
-        s_prev = sl;
+        log_prev = lsl;
         // 3. resample when ESS < N_x / 2 (never after the last observation)
         const bool rs = uniform_bool(t < T && (a.pf_always || ess_below_half(q1, q2, nx)));
         if (a.trace_inc && first_wave()) {
@@ -610,7 +620,7 @@ __device__ void pf_filter(const PFArgs& a, int item)
                 for (int j = tid; j < nx; j += nthr) sc[j] = tmp[j];
             }
             for (int j = tid; j < nx; j += nthr) lw[j] = (real)0;
-            s_prev = (double)nx;
+            log_prev = log_nx;
         }
     }
     if (first_wave()) a.ll[g] = ll;

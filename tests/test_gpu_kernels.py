@@ -233,6 +233,19 @@ def test_pf_schedules_identical(name, prec, nx, T):
         assert np.array_equal(xa, xb)
 
 
+def test_pf_results_do_not_depend_on_the_launch_round():
+    """A launch whose filters are all resident at once sets the waves' issue priority
+    from each filter's remaining work; a larger launch (several rounds of workgroups)
+    leaves it alone. Priorities only order instruction issue, so the same filters give
+    the same log-likelihoods to the last bit in both launches."""
+    w, y, theta = _pf_case("seir", G.PREC_FP32, 512, 3000, T=40)
+    small = G.pf_loglik(w, theta[:200], y, 512, seed=5, k=2, block=256)
+    large = G.pf_loglik(w, theta, y, 512, seed=5, k=2, block=256)
+    _log("single round %d filters, several rounds %d filters" % (200, len(theta)))
+    assert np.isfinite(small).all()
+    assert np.array_equal(small, large[:200])
+
+
 def test_pooled_schedule_rejected_for_age_model():
     w = W.preset("age_seir")
     w["T"] = 5
