@@ -27,7 +27,8 @@ int smc2_philox_batch(int32_t n, const uint32_t* d_ctr, uint64_t seed, uint32_t*
 /* Binomial(d_n[j], d_p[j]) draws of the particle-filter sampler (the flows of the
  * chain-binomial model, Sec. V-A) at coordinates (particle j, filter i, iteration k,
  * day t, draw b), j < count, in precision SMC2_PREC_FP32 (d_p rounded to FP32) or
- * SMC2_PREC_FP64. d_n: int32[count]; d_p: double[count]; d_out: int32[count]. */
+ * SMC2_PREC_FP64. d_n: int32[count], each below 2^30 (n <= 0 draws 0); d_p:
+ * double[count]; d_out: int32[count]. */
 int smc2_binomial_batch(int32_t precision, int32_t count, const int32_t* d_n, const double* d_p, uint64_t seed,
                         uint32_t i, uint32_t k, uint32_t t, uint32_t b, int32_t* d_out, void* hip_stream);
 

@@ -160,7 +160,7 @@ __device__ __forceinline__ double lfact(double x)
 // decisions because each piece is a pure function of (n, p, k, words).
 template <typename real> struct BtrsConst {
     real spq, bb, aa, vr, cf;
-    int64_t ci;
+    int32_t ci;
 };
 
 // The set-up given its two costly values, spq = sqrt(n p q) and vr = 0.92 - 4.2 / bb.
@@ -174,7 +174,7 @@ __device__ __forceinline__ BtrsConst<real> btrs_setup_from(int32_t n, real p, re
     c.vr = vr;
     const double cc = (double)n * (double)p + 0.5;
     const double cfl = floor(cc);
-    c.ci = (int64_t)cfl;
+    c.ci = (int32_t)cfl;
     c.cf = (real)(cc - cfl);
     return c;
 }
@@ -191,7 +191,7 @@ enum : int { BTRS_OUT = 0, BTRS_ACCEPT = 1, BTRS_FINAL = 2 };
 // One attempt from the uniform words (wu, wv): the candidate k, and whether it lies
 // outside [0, n], is accepted by the squeeze, or needs the final test.
 template <typename real>
-__device__ __forceinline__ int btrs_try(const BtrsConst<real>& c, int32_t n, uint32_t wu, uint32_t wv, int64_t& k)
+__device__ __forceinline__ int btrs_try(const BtrsConst<real>& c, int32_t n, uint32_t wu, uint32_t wv, int32_t& k)
 {
     const real u = (real)u24(wu) - (real)0.5;
     const real v = (real)u24(wv);
@@ -201,7 +201,9 @@ __device__ __forceinline__ int btrs_try(const BtrsConst<real>& c, int32_t n, uin
     t = t + c.bb;
     t = t * u;
     t = t + c.cf;
-    k = c.ci + (int64_t)floor((double)t);
+    // beyond 2^30 in magnitude the candidate lies outside [0, n] either way (n < 2^30):
+    // clamped there, the sum stays within int32 and the range check decides the same
+    k = c.ci + (int32_t)fmin(fmax(floor(t), (real)-0x1p30), (real)0x1p30);
     if (k < 0 || k > n) return BTRS_OUT;
     if (us >= (real)0.07 && v <= c.vr) return BTRS_ACCEPT;
     return BTRS_FINAL;
@@ -209,7 +211,7 @@ __device__ __forceinline__ int btrs_try(const BtrsConst<real>& c, int32_t n, uin
 
 // The final acceptance test of candidate k (FP64).
 template <typename real>
-__device__ __forceinline__ bool btrs_final(const BtrsConst<real>& c, int32_t n, real p, int64_t k, uint32_t wu,
+__device__ __forceinline__ bool btrs_final(const BtrsConst<real>& c, int32_t n, real p, int32_t k, uint32_t wu,
                                            uint32_t wv)
 {
     const real u = (real)u24(wu) - (real)0.5;
@@ -280,7 +282,7 @@ __device__ __forceinline__ float log1p_minus_x(float x)
 }
 
 template <typename real>
-__device__ __forceinline__ int btrs_final_fast(const BtrsConst<real>& c, int32_t n, real p, int64_t k, uint32_t wu,
+__device__ __forceinline__ int btrs_final_fast(const BtrsConst<real>& c, int32_t n, real p, int32_t k, uint32_t wu,
                                                uint32_t wv)
 {
     if constexpr (sizeof(real) != 4) {
@@ -294,7 +296,7 @@ __device__ __forceinline__ int btrs_final_fast(const BtrsConst<real>& c, int32_t
         const double mp = (double)(n + 1) * (double)p;  // exact: 24-bit times 24-bit
         const double mfl = floor(mp);
         const int32_t m = (int32_t)mfl;
-        const int32_t ki = (int32_t)k;
+        const int32_t ki = k;
         const int32_t d = ki - m;
         const float df = (float)d;
         const float A = (float)(ki + 1), B = (float)(n - ki + 1);
@@ -331,7 +333,7 @@ __device__ __forceinline__ int btrs_final_fast(const BtrsConst<real>& c, int32_t
 // The acceptance decision of a candidate that needs the final test: FP32 first, the
 // FP64 test only when the FP32 value cannot decide.
 template <typename real>
-__device__ __forceinline__ bool btrs_decide(const BtrsConst<real>& c, int32_t n, real p, int64_t k, uint32_t wu,
+__device__ __forceinline__ bool btrs_decide(const BtrsConst<real>& c, int32_t n, real p, int32_t k, uint32_t wu,
                                             uint32_t wv)
 {
     const int f = btrs_final_fast<real>(c, n, p, k, wu, wv);
@@ -355,7 +357,7 @@ __device__ __forceinline__ int32_t binom_btrs(int32_t n, real p, const DrawStrea
         if ((e & 1) == 0) w = s.call((uint32_t)(e >> 1));
         const uint32_t wu = (e & 1) ? w.z : w.x;
         const uint32_t wv = (e & 1) ? w.w : w.y;
-        int64_t k = 0;
+        int32_t k = 0;
         const int r = btrs_try<real>(c, n, wu, wv, k);
         // The acceptance is merged as a flag and k is returned after the branch: the
         // form "if (quick || final(...)) return k" was miscompiled for gfx950 (the

@@ -309,7 +309,7 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
         }
         // 2. one BTRS attempt per busy lane
         bool push = false;
-        int64_t kk = 0;
+        int32_t kk = 0;
         uint32_t wu = 0, wv = 0;
         if (busy) {
             if (e >= 256) {
@@ -364,7 +364,7 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
             fq = base;
             bool push2 = false;
             int e2 = (int)(id2 >> 16);
-            int64_t kk2 = k2;
+            int32_t kk2 = k2;
             if (mine) {
                 const int j2 = (int)(id2 & 0xFFFu), b2 = (int)((id2 >> 12) & 7u);
                 const bool flip2 = ((id2 >> 15) & 1u) != 0u;
