@@ -342,15 +342,24 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
         // flush while a full batch is queued (so the queue holds < 64 entries before the
         // next round adds at most 64), and everything once no new attempts remain
         while (fq >= 64 || (!more && fq > 0)) {
-            // 3. final tests of the newest min(64, fq) entries, one per lane
+            // 3. final tests of the newest m = min(64, fq) entries. A partial batch (the
+            //    day's last tests) spreads each entry over r = 2^lr lanes, r m <= 64: lane jj
+            //    of the entry's group takes attempt e + jj of the draw (lane 0 the queued
+            //    attempt's final test, the others the next attempts from their own Philox
+            //    words), and the first accepted attempt in that order is the draw, exactly
+            //    as when they run one after another. Only when all r attempts fail does the
+            //    group's last lane go on, from attempt e + r.
             const int m = fq < 64 ? fq : 64;
             const int base = fq - m;
-            const bool mine = lane < m;
+            const int lr = m > 32 ? 0 : (m > 16 ? 1 : (m > 8 ? 2 : (m > 4 ? 3 : (m > 2 ? 4 : (m > 1 ? 5 : 6)))));
+            const int r = 1 << lr;
+            const int g = lane >> lr, jj = lane & (r - 1);
+            const bool mine = g < m;
             uint32_t id2 = 0, wu2 = 0, wv2 = 0;
             int32_t n2 = 0, k2 = 0;
             real p2 = (real)0, spq2 = (real)1, vr2 = (real)0;
             if (mine) {
-                const int s = base + lane;
+                const int s = base + g;
                 id2 = q->id[s];
                 n2 = q->n[s];
                 k2 = q->k[s];
@@ -362,18 +371,42 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
             }
             __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
             fq = base;
-            bool push2 = false;
-            int e2 = (int)(id2 >> 16);
+            const int j2 = (int)(id2 & 0xFFFu), b2 = (int)((id2 >> 12) & 7u);
+            const bool flip2 = ((id2 >> 15) & 1u) != 0u;
+            const DrawStream ds2{(uint32_t)j2, filt, kt, (uint32_t)b2, k0, k1};
+            int e2 = (int)(id2 >> 16) + jj;  // this lane's attempt
             int32_t kk2 = k2;
+            bool acc = false;
             if (mine) {
-                const int j2 = (int)(id2 & 0xFFFu), b2 = (int)((id2 >> 12) & 7u);
-                const bool flip2 = ((id2 >> 15) & 1u) != 0u;
                 const BtrsConst<real> c2 = btrs_setup_from<real>(n2, p2, spq2, vr2);
-                int32_t res = -1;
-                if (btrs_decide<real>(c2, n2, p2, kk2, wu2, wv2)) {
-                    res = k2;
-                } else {
-                    const DrawStream ds2{(uint32_t)j2, filt, kt, (uint32_t)b2, k0, k1};
+                bool need = jj == 0;
+                if (jj > 0) {
+                    if (e2 >= 256) {
+                        acc = true;  // all 256 attempts failed: the mode
+                        kk2 = btrs_mode<real>(n2, p2);
+                    } else {
+                        const W4 w = ds2.call((uint32_t)(e2 >> 1));
+                        wu2 = (e2 & 1) ? w.z : w.x;
+                        wv2 = (e2 & 1) ? w.w : w.y;
+                        const int t = btrs_try<real>(c2, n2, wu2, wv2, kk2);
+                        acc = t == BTRS_ACCEPT;
+                        need = t == BTRS_FINAL;
+                    }
+                }
+                if (need) acc = btrs_decide<real>(c2, n2, p2, kk2, wu2, wv2);
+            }
+            // the first accepting lane of each group (g << lr <= lane, so the shift is valid)
+            const uint64_t am = __ballot(acc);
+            const uint64_t gm = lr == 6 ? am : (am >> (g << lr)) & ((1ull << r) - 1ull);
+            const int win = gm ? (g << lr) + (int)__builtin_ctzll(gm) : lane;
+            const int32_t kw = __shfl(kk2, win);
+            bool push2 = false;
+            if (mine) {
+                if (gm) {
+                    if (jj == 0) flows[b2 * cap + j2] = flip2 ? n2 - kw : kw;
+                } else if (jj == r - 1) {
+                    const BtrsConst<real> c2 = btrs_setup_from<real>(n2, p2, spq2, vr2);
+                    int32_t res = -1;
                     for (++e2;; ++e2) {
                         if (e2 >= 256) {
                             res = btrs_mode<real>(n2, p2);
@@ -382,19 +415,19 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
                         const W4 w = ds2.call((uint32_t)(e2 >> 1));
                         wu2 = (e2 & 1) ? w.z : w.x;
                         wv2 = (e2 & 1) ? w.w : w.y;
-                        const int r = btrs_try<real>(c2, n2, wu2, wv2, kk2);
-                        if (r == BTRS_OUT) continue;
-                        if (r == BTRS_ACCEPT) res = (int32_t)kk2;
+                        const int t = btrs_try<real>(c2, n2, wu2, wv2, kk2);
+                        if (t == BTRS_OUT) continue;
+                        if (t == BTRS_ACCEPT) res = kk2;
                         else push2 = true;
                         break;
                     }
+                    if (res >= 0) flows[b2 * cap + j2] = flip2 ? n2 - res : res;
+                    id2 = (id2 & 0xFFFFu) | ((uint32_t)e2 << 16);
                 }
-                if (res >= 0) flows[b2 * cap + j2] = flip2 ? n2 - res : res;
-                id2 = (id2 & 0xFFFFu) | ((uint32_t)e2 << 16);
             }
             const uint64_t pm = __ballot(push2);
             if (push2)
-                pool_store<real>(q, fq + __popcll(pm & below), id2, n2, (int32_t)kk2, wu2, wv2, p2,
+                pool_store<real>(q, fq + __popcll(pm & below), id2, n2, kk2, wu2, wv2, p2,
                                  BtrsConst<real>{spq2, (real)0, (real)0, vr2, (real)0, 0});
             fq += __popcll(pm);
         }
@@ -502,8 +535,10 @@ __device__ void pf_filter(const PFArgs& a, int item)
     double* cst = reinterpret_cast<double*>(red + 1);
     real* lw = reinterpret_cast<real*>(cst + T);
     int32_t* st = reinterpret_cast<int32_t*>(lw + cap);
-    WavePool<real>* pool = reinterpret_cast<WavePool<real>*>(
-        (reinterpret_cast<uintptr_t>(st + NC * cap) + 15) & ~(uintptr_t)15) + wave_id();
+    // offset from the LDS base (not an integer round trip, which would lose the address
+    // space and turn every queue access into a generic FLAT access)
+    const size_t pool_off = ((size_t)(reinterpret_cast<unsigned char*>(st + NC * cap) - smem) + 15) & ~(size_t)15;
+    WavePool<real>* pool = reinterpret_cast<WavePool<real>*>(smem + pool_off) + wave_id();
 
     const double* th = a.theta + (size_t)g * a.D;
     MConst<real> mc;
@@ -621,6 +656,9 @@ __device__ void pf_filter(const PFArgs& a, int item)
             }
             for (int j = tid; j < nx; j += nthr) lw[j] = (real)0;
             log_prev = log_nx;
+            // the next day's draws read any particle's counts (the pooled schedule hands
+            // out items workgroup-wide): every gathered count must be in place first
+            __syncthreads();
         }
     }
     if (first_wave()) a.ll[g] = ll;
