@@ -614,11 +614,13 @@ __device__ void pf_filter(const PFArgs& a, int item)
             if (j < nx) {
                 const real av = lw[j];
                 w = exp((double)av - (double)m);
-                const uint64_t q = (uint64_t)floor(w * 4294967296.0);
+                // w <= 1 (av <= m): q = floor(w 2^32) is 2^32 at w = 1 and fits 32 bits
+                // otherwise, where the truncating conversion is the floor; h < 2^25
+                const uint64_t q = w >= 1.0 ? (1ull << 32) : (uint64_t)(uint32_t)(w * 4294967296.0);
                 C[j] = q;
-                const uint64_t h = q >> 8;
+                const uint32_t h = (uint32_t)(q >> 8);
                 q1 += h;
-                q2 += h * h;
+                q2 += (uint64_t)h * h;
                 lw[j] = av - m;
             }
             const double cs = wave_sum(w);
