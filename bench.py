@@ -84,7 +84,7 @@ def main():
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the sampler is not sharded across GPUs); "
+        print("bench.py: the sampler runs on one GPU (it is not sharded across GPUs); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

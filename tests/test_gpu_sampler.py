@@ -88,6 +88,29 @@ def test_paper_sir_end_to_end(lkernel):
     _compare(gpu, ref, 2, 1e-10, 1e-9)
 
 
+def test_paper_sir_recovers_the_papers_estimates():
+    """The paper's SIR experiment at its sizes (N = 1024, K = 10, N_x = 500; Sec. V-A/V-B)
+    on the GPU, four synthetic datasets: the recycled posterior means recover the truth
+    to the accuracy of the paper's SMC^2 row of Table II (tests/golden)."""
+    from tests import paper_sir_golden as PG
+    g = PG.load()
+    w = W.preset("paper_sir")
+    means, sds = [], []
+    for ds in PG.DATA_SEEDS:
+        y = W.observations(dict(w, data_seed=ds))
+        s = G.Sampler(w, [dict(T=y.shape[0], nx=w["nx"], seed=w["seed"], y=y)], N=w["N"], K=w["K"])
+        for _ in range(w["K"]):
+            s.step()
+        m, c = s.estimate(recycled=True)
+        s.close()
+        _log("data seed %d: mean %s sd %s" % (ds, m, np.sqrt(np.diag(c))))
+        means.append(m)
+        sds.append(np.sqrt(np.diag(c)))
+    avg, mse = PG.check(means, sds, g)
+    _log("mean over datasets %s, mse %.3g (the paper: %.4g %.4g, %.3g)"
+         % (avg, mse, g["smc2_mean_beta"], g["smc2_mean_gamma"], g["smc2_mse"]))
+
+
 def test_seir_fp32_end_to_end():
     """SEIR, FP32 propagation: N=96, N_x=256, T=60, K=4."""
     w = W.preset("seir")
