@@ -42,10 +42,10 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_amd/csrc/pf_kernel.h",
                   "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h",
                   "paper_2311_12973_amd/build.py"]
-KERNEL_SHA = "2f8653c7d2df6710"
+KERNEL_SHA = "c226b7af12da1863"
 PROFILED_WORKLOAD = "seir"
-VALU_LANE_INSTR_PER_PSTEP = 1511.0
-HBM_BYTES_PER_LAUNCH = 1.0291e6
+VALU_LANE_INSTR_PER_PSTEP = 1506.1
+HBM_BYTES_PER_LAUNCH = 1.028e6
 
 
 def kernel_sha():
