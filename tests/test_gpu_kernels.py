@@ -246,14 +246,16 @@ def test_pf_results_do_not_depend_on_the_launch_round():
     assert np.array_equal(small, large[:200])
 
 
-@pytest.mark.parametrize("pf_always", [1, 0])
-def test_pf_repeated_launches_are_identical(pf_always):
+@pytest.mark.parametrize("pf_always,resampling", [(1, G.PF_RS_SYSTEMATIC), (0, G.PF_RS_SYSTEMATIC),
+                                                 (1, G.PF_RS_MULTINOMIAL)])
+def test_pf_repeated_launches_are_identical(pf_always, resampling):
     """Every draw is a function of its coordinates, whichever wave takes it, so repeated
     launches at the benchmark's filter shape give identical log-likelihoods. Resampling
     every day puts a resampling gather before each day's draws: a missing barrier
     between the two let a wave read counts that another wave had not yet written back,
     and about one filter in a thousand then differed from launch to launch."""
     w, y, theta = _pf_case("seir", G.PREC_FP32, 512, 1024, T=100)
+    w = dict(w, pf_resampling=resampling)
     ref = G.pf_loglik(w, theta, y, 512, seed=3, k=2, pf_always=pf_always)
     assert np.isfinite(ref).all()
     for rep in range(8):
