@@ -178,20 +178,23 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
 }
 
 // ---------------------------------------------------------------- pooled schedule
-// SIR and SEIR draw a day's flows as a per-wave work pool instead of one particle
-// after another. The flows of a day depend only on the previous day's counts, so
-// the draws of the wave's particles are independent items (particle j, draw b).
-// Every round each free lane takes the next item (inversion draws and trivial
-// cases finish at once), and every lane with a BTRS item makes one attempt. An
-// attempt that passes neither the squeeze nor the range check is retried next
-// round; one that needs the final acceptance test is appended to the wave's queue in
-// LDS and the lane moves on. When 64 tests are queued (or nothing else is left) the
-// wave runs them with all lanes busy (FP32 first, FP64 only near the boundary); a
-// rejected candidate continues with its next attempt in that lane. A 64-wide wave otherwise pays for the final test whenever
-// any one lane needs it, which is nearly every round. Every attempt is a pure
-// function of its Philox coordinates, so the flows equal the per-draw schedule's.
-// Flows go to flows[b * cap + j] (the quantised-weight and gather buffers, free
-// during propagation); the counts are updated once all draws of the day are done.
+// SIR and SEIR draw a day's flows as a pool of work items instead of one particle
+// after another. The flows of a day depend only on the previous day's counts, so the
+// draws of all the filter's particles are independent items (particle j, draw b),
+// handed out from one workgroup-wide list through an LDS counter. Every round each
+// free lane of a wave takes the next item (trivial draws finish at once, inversion
+// draws within the round), and every lane with a BTRS item makes one attempt. An
+// attempt outside [0, n] is retried next round; one that needs the final acceptance
+// test goes to the wave's queue in LDS and the lane moves on. When 64 tests are
+// queued the wave runs them with all lanes busy (FP32 first, FP64 only near the
+// boundary), and a candidate that fails continues with its next attempts in its lane.
+// The last tests of the day, fewer than 64, each take several lanes that evaluate the
+// draw's following attempts at once. A wave would otherwise pay for the final test
+// whenever any one of its lanes needs it, which is nearly every round. Every attempt
+// is a function of its Philox coordinates alone, so the flows equal the per-draw
+// schedule's whichever lane or wave draws them. Flows go to flows[b * cap + j] (the
+// quantised-weight and gather buffers, free during propagation); the counts are
+// updated once every wave has finished the day's draws.
 constexpr int POOL_CAP = 128;  // < 64 entries remain after the flushes; one round adds at most 64
 
 template <typename real> struct WavePool {
