@@ -79,6 +79,9 @@ def main():
     ap.add_argument("--persistent", type=int, default=0, help="1: persistent grid pulling filters from the work list")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ess", action="store_true", help="skip the learned-proposal vs random-walk ESS/s comparison")
+    ap.add_argument("--ess-protocol", type=int, default=0,
+                    help="1: ESS/s at a fixed posterior error against a long reference run (about a minute more)")
+    ap.add_argument("--ess-protocol-n", type=int, default=0, help="samples per run of that protocol (0: the workload's)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="run one plain device copy of this many MiB before the timed region (calibrates "
                          "the FETCH_SIZE / WRITE_SIZE counters of a profiling run)")
@@ -146,6 +149,8 @@ def main():
     ess = None
     if not args.no_ess:
         ess = ess_per_second(G, W, np)
+        if args.ess_protocol:
+            ess["at_fixed_error"] = ess_at_fixed_error(G, W, np, n_runs=args.ess_protocol_n or None)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -213,6 +218,84 @@ def ess_per_second(G, W, np):
     out["recycled_ess_speedup"] = (out["learned"]["recycled_ess_per_s_per_run"] /
                                    out["random_walk"]["recycled_ess_per_s_per_run"])
     out["workload"] = "seir_learned: D=5, T=150, N=4096, N_x=1024, K=20, 8 runs per form"
+    return out
+
+
+def ess_at_fixed_error(G, W, np, n_ref=32768, k_ref=100, ref_seeds=3, seeds=10, k_max=(20, 80), n_runs=None,
+                       thresholds=(0.1, 0.25)):
+    """ESS per second at a fixed posterior error, learned proposal against the random
+    walk, on the learned-proposal configuration (SEIR with the dispersion estimated,
+    D = 5, T = 150, N = 4096, N_x = 1024):
+    * reference posterior: `ref_seeds` long random-walk runs (N = n_ref, K = k_ref, one
+      batched sampler), f_ref the average of their recycled means and s_ref the root of
+      their average variance; the reference's own standard error, the spread of the
+      runs' means over sqrt(ref_seeds), is reported in s_ref units;
+    * each form runs `seeds` independent runs (one batched sampler) for up to k_max
+      iterations (learned, random walk). After iteration k a run's error is
+      eps(k) = max_d |f_d(k) - f_ref,d| / s_ref,d, f(k) its recycled mean over
+      iterations 1..k; at the first k with eps(k) <= threshold the run's ESS per second
+      is its recycled ESS sum_{k' <= k} l_k' over its share of the wall time of
+      iterations 1..k (the batch's time divided by the number of runs);
+    * reported per form and threshold: the median and quartiles over the runs that
+      reach it, the iterations taken and the runs that do not within k_max; the mean
+      error of the final means per coordinate (in s_ref units); and the ratio of medians."""
+    import torch
+
+    w = W.preset("seir_learned")
+    y = W.observations(w)
+    N = n_runs or w["N"]
+    run = lambda sd: dict(T=y.shape[0], nx=w["nx"], seed=sd, y=y)
+    s = G.Sampler(dict(w, proposal=G.PROP_RW), [run(1000 + i) for i in range(ref_seeds)], N=n_ref, K=k_ref)
+    t0 = time.perf_counter()
+    for _ in range(k_ref):
+        s.step()
+    ref = [s.estimate(r, recycled=True) for r in range(ref_seeds)]
+    t_ref = time.perf_counter() - t0
+    s.close()
+    m_each = np.array([m for m, _ in ref])
+    m_ref = m_each.mean(0)
+    s_ref = np.sqrt(np.mean([np.diag(c) for _, c in ref], 0))
+    se_ref = m_each.std(0, ddof=1) / np.sqrt(ref_seeds) / s_ref if ref_seeds > 1 else np.full(len(m_ref), np.nan)
+    out = {"reference": {"proposal": "random walk", "runs": ref_seeds, "N": n_ref, "K": k_ref, "seconds": t_ref,
+                         "posterior_mean": m_ref.tolist(), "posterior_sd": s_ref.tolist(),
+                         "standard_error_in_sd": se_ref.tolist(),
+                         "run_means_in_sd": ((m_each - m_ref) / s_ref).tolist()}}
+    for (name, prop), kmax in zip((("learned", G.PROP_MLP), ("random_walk", G.PROP_RW)), k_max):
+        s = G.Sampler(dict(w, proposal=prop), [run(sd) for sd in range(1, seeds + 1)], N=N, K=kmax)
+        t_cum = 0.0
+        first = {th: [None] * seeds for th in thresholds}
+        rate = {th: [None] * seeds for th in thresholds}
+        for k in range(1, kmax + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step()
+            torch.cuda.synchronize()
+            t_cum += time.perf_counter() - t0
+            means = [s.estimate(r, recycled=True)[0] for r in range(seeds)]
+            for r in range(seeds):
+                eps = float(np.max(np.abs(means[r] - m_ref) / s_ref))
+                for th in thresholds:
+                    if first[th][r] is None and eps <= th:
+                        first[th][r] = k
+                        rate[th][r] = float(s.records(r)[:k, 1].sum()) / (t_cum / seeds)
+            if all(x is not None for x in first[min(thresholds)]):
+                break
+        s.close()
+        res = {"runs": seeds, "N": N, "k_max": kmax, "iterations_run": k,
+               "final_mean_error_in_sd": (np.mean([(m - m_ref) / s_ref for m in means], 0)).tolist()}
+        for th in thresholds:
+            ok = np.array([x for x in rate[th] if x is not None])
+            q = np.percentile(ok, [25, 50, 75]).tolist() if len(ok) else [None] * 3
+            res["eps_%g" % th] = {"iterations_to_error": first[th], "not_reached": int(sum(x is None for x in first[th])),
+                                  "ess_per_s_quartiles": q}
+        out[name] = res
+    for th in thresholds:
+        a = out["learned"]["eps_%g" % th]["ess_per_s_quartiles"][1]
+        b = out["random_walk"]["eps_%g" % th]["ess_per_s_quartiles"][1]
+        out["ratio_of_medians_eps_%g" % th] = a / b if a and b else None
+    out["protocol"] = ("recycled ESS per second at the first iteration with max_d |mean - ref| / sd_ref <= eps; "
+                       "reference: %d random-walk runs, N=%d, K=%d; %d runs per form at N=%d"
+                       % (ref_seeds, n_ref, k_ref, seeds, N))
     return out
 
 
