@@ -180,15 +180,17 @@ def main():
 def ess_per_second(G, W, np):
     """ESS per second at the same posterior, learned proposal vs random walk, on the
     learned-proposal configuration: SEIR with the dispersion estimated (D = 5), T = 150,
-    N = 4096, N_x = 1024, K = 20; 8 independent runs of each form (one batched sampler
+    N = 4096, N_x = 1024, K = 20; 16 independent runs of each form (one batched sampler
     per form). Replicate ESS = posterior variance / variance of the recycled posterior
     mean across runs (averaged over coordinates); per second of the whole batch's
-    iterations, per run. Also the recycled ESS sum_k l_k of each run per second."""
+    iterations, per run. The variance across R runs has a relative standard error of
+    about sqrt(2 / (R - 1)), reported with it. Also the recycled ESS sum_k l_k of each
+    run per second."""
     import torch
 
     w = W.preset("seir_learned")
     y = W.observations(w)
-    seeds = list(range(1, 9))
+    seeds = list(range(1, 17))
     K = w["K"]
     out = {}
     for name, prop in (("learned", G.PROP_MLP), ("random_walk", G.PROP_RW)):
@@ -217,7 +219,8 @@ def ess_per_second(G, W, np):
     out["speedup"] = out["learned"]["ess_per_s_per_run"] / out["random_walk"]["ess_per_s_per_run"]
     out["recycled_ess_speedup"] = (out["learned"]["recycled_ess_per_s_per_run"] /
                                    out["random_walk"]["recycled_ess_per_s_per_run"])
-    out["workload"] = "seir_learned: D=5, T=150, N=4096, N_x=1024, K=20, 8 runs per form"
+    out["replicate_ess_rel_se"] = float(np.sqrt(2.0 / (len(seeds) - 1)))
+    out["workload"] = "seir_learned: D=5, T=150, N=4096, N_x=1024, K=20, %d runs per form" % len(seeds)
     return out
 
 

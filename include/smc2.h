@@ -104,6 +104,15 @@ extern "C" {
 #define SMC2_PF_RS_SYSTEMATIC 0
 #define SMC2_PF_RS_MULTINOMIAL 1
 
+/* Training layout of the learned proposal (smc2_config.mlp_train). Per run: one
+ * workgroup per run takes every minibatch step. Split: each minibatch's 64-row
+ * sub-batches take a workgroup each and a second launch sums their gradients in order
+ * and takes the Adam step (for few runs, which would leave most of the device idle).
+ * The two group the minibatch's rows differently, so they agree to FP32 rounding. */
+#define SMC2_MLP_TRAIN_AUTO 0    /* split for up to 32 runs, per run above               */
+#define SMC2_MLP_TRAIN_PER_RUN 1
+#define SMC2_MLP_TRAIN_SPLIT 2
+
 #define SMC2_DMAX 8
 #define SMC2_NFIXED 32
 
@@ -138,7 +147,8 @@ typedef struct {
     int32_t mlp_batch;  /* learned proposal: minibatch rows (0: the whole population)      */
     double mlp_lr;      /* learned proposal: Adam learning rate (> 0)                      */
     int32_t pf_resampling; /* SMC2_PF_RS_*: the particle filters' resampling scheme       */
-    int32_t reserved;      /* 0                                                           */
+    int32_t mlp_train;     /* SMC2_MLP_TRAIN_*: how the learned proposal's training is laid
+                              out on the device (same mathematics, FP32 rounding aside)   */
 } smc2_config;
 
 typedef struct {
@@ -182,6 +192,8 @@ typedef struct {
                                    weighted covariance (row-major); inputs are F^-1(phi-c) */
 #define SMC2_DUMP_MLP_STATE 13  /* 4      doubles: {use next iteration (0/1), Adam steps,
                                    held-out NLL of the network, of the random walk}      */
+#define SMC2_DUMP_MLP_GRAD 14   /* NP     float: gradient of the last minibatch, before
+                                   clipping, in the layout of SMC2_DUMP_MLP_PARAMS       */
 
 /* Bytes of device workspace needed for this config and these runs (0 on bad input). */
 size_t smc2_workspace_bytes(const smc2_config* cfg, int32_t n_runs, const smc2_run* runs);

@@ -22,9 +22,10 @@ PRIOR_UNIFORM, PRIOR_LOGNORMAL, PRIOR_LOGITNORMAL, PRIOR_NORMAL = 0, 1, 2, 3
 L_FORWARD, L_GAUSS_OPT = 0, 1
 PROP_RW, PROP_MLP = 0, 1
 PF_RS_SYSTEMATIC, PF_RS_MULTINOMIAL = 0, 1
+MLP_TRAIN_AUTO, MLP_TRAIN_PER_RUN, MLP_TRAIN_SPLIT = 0, 1, 2
 SCHED_AUTO, SCHED_PER_DRAW, SCHED_POOLED = 0, 1, 2
 DUMP = dict(phi=0, lp=1, ll=2, logw=3, phi_new=4, lp_new=5, ll_new=6, logw_pre=7, anc=8, mlp_out=9, logq=10,
-            mlp_params=11, mlp_frame=12, mlp_state=13)
+            mlp_params=11, mlp_frame=12, mlp_state=13, mlp_grad=14)
 MLP_H = 64
 
 
@@ -57,7 +58,7 @@ class Config(ctypes.Structure):
                 ("fixed", ctypes.POINTER(ctypes.c_double)), ("n_fixed", ctypes.c_int32),
                 ("tune", ctypes.c_int32), ("persistent", ctypes.c_int32), ("mlp_epochs", ctypes.c_int32),
                 ("mlp_batch", ctypes.c_int32), ("mlp_lr", ctypes.c_double), ("pf_resampling", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("mlp_train", ctypes.c_int32)]
 
 
 class Run(ctypes.Structure):
@@ -192,6 +193,7 @@ def make_config(w, N=None, K=None, precision=None, use_graph=0, block=0, lkernel
     c.use_graph, c.block, c.schedule = int(use_graph), int(block), int(schedule)
     c.tune, c.persistent = int(tune), int(persistent)
     c.pf_resampling = int(w.get("pf_resampling", PF_RS_SYSTEMATIC))
+    c.mlp_train = int(w.get("mlp_train", MLP_TRAIN_AUTO))
     c.n_pop = float(w["n_pop"])
     dp = ctypes.POINTER(ctypes.c_double)
     c.prior = keep.prior.ctypes.data_as(dp)
@@ -265,7 +267,7 @@ class Sampler:
             out = np.zeros(self.N, dtype=np.int32)
         elif what == "mlp_out":
             out = np.zeros((self.N, mlp_nout(self.D)), dtype=np.float32)
-        elif what == "mlp_params":
+        elif what in ("mlp_params", "mlp_grad"):
             out = np.zeros(mlp_nparams(self.D), dtype=np.float32)
         elif what == "mlp_frame":
             out = np.zeros(self.D + self.D * self.D)

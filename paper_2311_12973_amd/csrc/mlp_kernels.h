@@ -42,6 +42,7 @@ struct MlpArrays {
     double* score;    // [R][2] held-out mean weighted NLL (network, random walk)
     float* rows;      // [R][N][MLP_ROW] the population whitened in the current frame (training scratch)
     double* wfull;    // [R][N] N w_i, the normalised weights times N (training scratch)
+    float* gpart;     // [R][nsub][NP] gradients of the sub-batches of a minibatch (split training)
 };
 
 struct MlpParams {
@@ -49,8 +50,20 @@ struct MlpParams {
     int32_t epochs, batch;
     float lr;
     int32_t rec_len;
+    int32_t nsub;       // sub-batches of MLP_SUB rows per minibatch: ceil(min(batch, N) / MLP_SUB)
+    int32_t split;      // 1: train with a workgroup per sub-batch (few runs), 0: one workgroup per run
     const double* lrw;  // [D][D] lower Cholesky factor of the random-walk covariance (device)
 };
+
+// Sub-batches of MLP_SUB rows in a training minibatch of `batch` rows (0 or > N: N).
+inline int mlp_nsub(int batch, int N)
+{
+    const int B = (batch < 1 || batch > N) ? N : batch;
+    return (B + MLP_SUB - 1) / MLP_SUB;
+}
+// Whether training spreads a minibatch's sub-batches over workgroups: layout mode
+// SMC2_MLP_TRAIN_* (0 auto: when the runs alone would leave most of the device idle).
+inline bool mlp_split(int mode, int n_runs) { return mode == 2 || (mode == 0 && n_runs <= 32); }
 
 // Network outputs at the current population, for runs that propose with it at this
 // iteration (k >= 2 and use = 1); other runs are skipped on the device.

@@ -107,13 +107,45 @@ __device__ void mlp_load_weights(int D, const float* w, MlpW* L)
     const float* b2 = W2 + MLP_H * MLP_H;
     const float* W3 = b2 + MLP_H;
     const float* b3 = W3 + P * MLP_H;
-    for (int i = tid; i < MLP_H * 16; i += nthr) {
-        const int h = i >> 4, d = i & 15;
-        L->W1[h * LW1 + d] = d < D ? f2bf(W1[h * D + d]) : (short)0;
+    if (nthr == 256) {
+        // every load of the thread issued before the first conversion and store
+        float v1[4], v2[16], v3[12];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = tid + 256 * e, h = i >> 4, d = i & 15;
+            v1[e] = d < D ? W1[h * D + d] : 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) v2[e] = W2[tid + 256 * e];
+#pragma unroll
+        for (int e = 0; e < 12; ++e) {
+            const int i = tid + 256 * e;
+            v3[e] = (i / MLP_H) < P ? W3[i] : 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int i = tid + 256 * e;
+            L->W1[(i >> 4) * LW1 + (i & 15)] = f2bf(v1[e]);
+        }
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            const int i = tid + 256 * e;
+            L->W2[(i / MLP_H) * LWH + (i % MLP_H)] = f2bf(v2[e]);
+        }
+#pragma unroll
+        for (int e = 0; e < 12; ++e) {
+            const int i = tid + 256 * e;
+            L->W3[(i / MLP_H) * LWH + (i % MLP_H)] = f2bf(v3[e]);
+        }
+    } else {
+        for (int i = tid; i < MLP_H * 16; i += nthr) {
+            const int h = i >> 4, d = i & 15;
+            L->W1[h * LW1 + d] = d < D ? f2bf(W1[h * D + d]) : (short)0;
+        }
+        for (int i = tid; i < MLP_H * MLP_H; i += nthr) L->W2[(i / MLP_H) * LWH + (i % MLP_H)] = f2bf(W2[i]);
+        for (int i = tid; i < MLP_PPAD * MLP_H; i += nthr)
+            L->W3[(i / MLP_H) * LWH + (i % MLP_H)] = (i / MLP_H) < P ? f2bf(W3[i]) : (short)0;
     }
-    for (int i = tid; i < MLP_H * MLP_H; i += nthr) L->W2[(i / MLP_H) * LWH + (i % MLP_H)] = f2bf(W2[i]);
-    for (int i = tid; i < MLP_PPAD * MLP_H; i += nthr)
-        L->W3[(i / MLP_H) * LWH + (i % MLP_H)] = (i / MLP_H) < P ? f2bf(W3[i]) : (short)0;
     for (int i = tid; i < MLP_H; i += nthr) {
         L->b1[i] = b1[i];
         L->b2[i] = b2[i];
@@ -548,29 +580,20 @@ __global__ void __launch_bounds__(256) k_mlp_forward(MlpArrays m, MlpParams p, O
 }
 
 // ------------------------------------------------------------------ training
+// Training prologue of run r (every thread of the block): the population's weights
+// W = log sum exp (log w), the frame (weighted mean c and the Cholesky factor F of the
+// weighted covariance; the diagonal of the standard deviations when a pivot is not above
+// 1e-12 of its coordinate's raw second moment) into frs (LDS) and m.frame, and the
+// population whitened in that frame with N w_i, read by the sub-batches in their random
+// pairing order. A is free LDS scratch here.
 template <int D>
-__global__ void __launch_bounds__(256) k_mlp_train(MlpArrays m, MlpParams p, OuterArrays o, const uint64_t* seeds)
+__device__ void mlp_train_prologue(const MlpArrays& m, const MlpParams& p, const OuterArrays& o, int r, MlpAct* A,
+                                   double* red, double* frs)
 {
-    constexpr int P = D + D * (D + 1) / 2;
-    const int r = (int)blockIdx.x;
     const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
     const int N = p.N;
-    const int k = *o.k_dev;
-    if (o.status[r] != 0) return;  // every weight vanished: nothing to learn from
-    extern __shared__ __align__(16) unsigned char smem[];
-    MlpW* W = reinterpret_cast<MlpW*>(smem);
-    MlpAct* A = reinterpret_cast<MlpAct*>(smem + sizeof(MlpW));
-    __shared__ double red[16 * (2 * DMAX + 1)];
-    __shared__ double frs[DMAX + DMAX * DMAX];
-    const int NP = mlp_nparams(D);
-    float* prm = m.params + (size_t)r * NP;
-    float* am = m.adam_m + (size_t)r * NP;
-    float* av = m.adam_v + (size_t)r * NP;
-    float* grad = m.grad + (size_t)r * NP;
     const double* phi = o.phi + (size_t)r * N * D;
     const double* logw = o.logw + (size_t)r * N;
-    const uint64_t seed = seeds[r];
-
     // weights of the population: W = log sum exp (log w)
     double mx = -INFINITY;
     for (int i = tid; i < N; i += nthr) mx = logw[i] > mx ? logw[i] : mx;
@@ -665,6 +688,114 @@ __global__ void __launch_bounds__(256) k_mlp_train(MlpArrays m, MlpParams p, Out
         wfull[i] = (double)N * exp(logw[i] - LW);
     }
     __syncthreads();
+
+}
+
+// Held-out check of run r after training: the mean weighted NLL of the network W (LDS)
+// on the pairing of "epoch" E against the random walk's; the next iteration proposes
+// with the network only if it is finite and lower. mlp_heldout_rows adds the weighted
+// NLLs of the pairs of sub-batches s_lo, s_lo + 64, ... below s_hi to the thread's sums
+// (threads < 64 hold a row each; every thread of the block calls it); frs holds the
+// frame (LDS), A is LDS scratch.
+template <int D>
+__device__ void mlp_heldout_rows(const MlpArrays& m, const MlpParams& p, const OuterArrays& o, int r, int k,
+                                 uint64_t seed, const MlpW* W, MlpAct* A, const double* frs, int s_lo, int s_hi,
+                                 double (&sums)[2])
+{
+    const int tid = (int)threadIdx.x;
+    const int N = p.N;
+    const double* phi = o.phi + (size_t)r * N * D;
+    const float* rows = m.rows + (size_t)r * N * MLP_ROW;
+    const double* wfull = m.wfull + (size_t)r * N;
+    uint64_t ta, tb, ia, ib;
+    mlp_perm_dev(seed, (uint32_t)k, (uint32_t)p.epochs, 0u, N, ta, tb);
+    mlp_perm_dev(seed, (uint32_t)k, (uint32_t)p.epochs, 1u, N, ia, ib);
+    double sls = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) sls += log(frs[D + d * D + d]);
+    for (int s0 = s_lo; s0 < s_hi; s0 += MLP_SUB) {
+        int jt = 0, ii = 0;
+        double wt = 0.0;
+        if (tid < MLP_SUB) {
+            const int rr = s0 + tid;
+            const bool valid = rr < N;
+            jt = valid ? (int)((ta * (uint64_t)rr + tb) % (uint64_t)N) : 0;
+            ii = valid ? (int)((ia * (uint64_t)rr + ib) % (uint64_t)N) : 0;
+            wt = valid ? wfull[jt] : 0.0;
+#pragma unroll
+            for (int d = 0; d < 16; ++d)
+                A->U[tid * LD16 + d] = (valid && d < MLP_ROW) ? rows[(size_t)ii * MLP_ROW + d] : 0.f;
+#pragma unroll
+            for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = valid ? rows[(size_t)jt * MLP_ROW + d] : 0.f;
+        }
+        __syncthreads();
+        mlp_fwd16<false>(W, A, wave_id() * 16);
+        __syncthreads();
+        if (tid < MLP_SUB && wt > 0.0) {
+            const float nll = mlp_row_nll<D>(A, tid, 0.f, false);
+            sums[0] += wt * ((double)nll + sls);
+            // random walk: -log N(phi_j; phi_i, L L^T)
+            double v[D], quad = 0.0, ld = 0.0;
+#pragma unroll
+            for (int a2 = 0; a2 < D; ++a2) {
+                double sa = phi[(size_t)jt * D + a2] - phi[(size_t)ii * D + a2];
+#pragma unroll
+                for (int b2 = 0; b2 < a2; ++b2) sa -= p.lrw[a2 * D + b2] * v[b2];
+                v[a2] = sa / p.lrw[a2 * D + a2];
+                quad += v[a2] * v[a2];
+                ld += log(p.lrw[a2 * D + a2]);
+            }
+            sums[1] += wt * (0.5 * quad + ld + 0.5 * D * MLP_LOG_2PI);
+        }
+        __syncthreads();
+    }
+}
+
+// the decision from the summed weighted NLLs (one thread)
+__device__ __forceinline__ void mlp_heldout_decide(const MlpArrays& m, const MlpParams& p, const OuterArrays& o,
+                                                   int r, int k, double sm, double sr)
+{
+    const double nm = sm / p.N, nr = sr / p.N;
+    m.score[2 * r] = nm;
+    m.score[2 * r + 1] = nr;
+    m.use[r] = (isfinite(nm) && nm < nr) ? 1 : 0;
+    o.records[((size_t)r * p.K + (k - 1)) * p.rec_len + p.rec_len - 1] = nm - nr;
+}
+
+template <int D>
+__device__ void mlp_heldout(const MlpArrays& m, const MlpParams& p, const OuterArrays& o, int r, int k,
+                            uint64_t seed, const MlpW* W, MlpAct* A, double* red, const double* frs)
+{
+    double sums[2] = {0.0, 0.0};
+    mlp_heldout_rows<D>(m, p, o, r, k, seed, W, A, frs, 0, p.N, sums);
+    mlp_block_sum<2>(sums, red);
+    if (threadIdx.x == 0) mlp_heldout_decide(m, p, o, r, k, sums[0], sums[1]);
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) k_mlp_train(MlpArrays m, MlpParams p, OuterArrays o, const uint64_t* seeds)
+{
+    constexpr int P = D + D * (D + 1) / 2;
+    const int r = (int)blockIdx.x;
+    const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
+    const int N = p.N;
+    const int k = *o.k_dev;
+    if (o.status[r] != 0) return;  // every weight vanished: nothing to learn from
+    extern __shared__ __align__(16) unsigned char smem[];
+    MlpW* W = reinterpret_cast<MlpW*>(smem);
+    MlpAct* A = reinterpret_cast<MlpAct*>(smem + sizeof(MlpW));
+    __shared__ double red[16 * (2 * DMAX + 1)];
+    __shared__ double frs[DMAX + DMAX * DMAX];
+    const int NP = mlp_nparams(D);
+    float* prm = m.params + (size_t)r * NP;
+    float* am = m.adam_m + (size_t)r * NP;
+    float* av = m.adam_v + (size_t)r * NP;
+    float* grad = m.grad + (size_t)r * NP;
+    const uint64_t seed = seeds[r];
+
+    mlp_train_prologue<D>(m, p, o, r, A, red, frs);
+    const float* rows = m.rows + (size_t)r * N * MLP_ROW;
+    const double* wfull = m.wfull + (size_t)r * N;
 
     const int B = (p.batch < 1 || p.batch > N) ? N : p.batch;
     int t_adam = m.adam_t[r];
@@ -773,63 +904,217 @@ __global__ void __launch_bounds__(256) k_mlp_train(MlpArrays m, MlpParams p, Out
     }
     if (tid == 0) m.adam_t[r] = t_adam;
 
-    // held-out comparison on the pairing of "epoch" E
-    {
-        uint64_t ta, tb, ia, ib;
-        mlp_perm_dev(seed, (uint32_t)k, (uint32_t)p.epochs, 0u, N, ta, tb);
-        mlp_perm_dev(seed, (uint32_t)k, (uint32_t)p.epochs, 1u, N, ia, ib);
-        double sls = 0.0;
-#pragma unroll
-        for (int d = 0; d < D; ++d) sls += log(frs[D + d * D + d]);
-        double sums[2] = {0.0, 0.0};
-        for (int s0 = 0; s0 < N; s0 += MLP_SUB) {
-            int jt = 0, ii = 0;
-            double wt = 0.0;
-            if (tid < MLP_SUB) {
-                const int rr = s0 + tid;
-                const bool valid = rr < N;
-                jt = valid ? (int)((ta * (uint64_t)rr + tb) % (uint64_t)N) : 0;
-                ii = valid ? (int)((ia * (uint64_t)rr + ib) % (uint64_t)N) : 0;
-                wt = valid ? wfull[jt] : 0.0;
-#pragma unroll
-                for (int d = 0; d < 16; ++d)
-                    A->U[tid * LD16 + d] = (valid && d < MLP_ROW) ? rows[(size_t)ii * MLP_ROW + d] : 0.f;
-#pragma unroll
-                for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = valid ? rows[(size_t)jt * MLP_ROW + d] : 0.f;
-            }
-            __syncthreads();
-            mlp_fwd16<false>(W, A, wave_id() * 16);
-            __syncthreads();
-            if (tid < MLP_SUB && wt > 0.0) {
-                const float nll = mlp_row_nll<D>(A, tid, 0.f, false);
-                sums[0] += wt * ((double)nll + sls);
-                // random walk: -log N(phi_j; phi_i, L L^T)
-                double v[D], quad = 0.0, ld = 0.0;
-#pragma unroll
-                for (int a2 = 0; a2 < D; ++a2) {
-                    double sa = phi[(size_t)jt * D + a2] - phi[(size_t)ii * D + a2];
-#pragma unroll
-                    for (int b2 = 0; b2 < a2; ++b2) sa -= p.lrw[a2 * D + b2] * v[b2];
-                    v[a2] = sa / p.lrw[a2 * D + a2];
-                    quad += v[a2] * v[a2];
-                    ld += log(p.lrw[a2 * D + a2]);
-                }
-                sums[1] += wt * (0.5 * quad + ld + 0.5 * D * MLP_LOG_2PI);
-            }
-            __syncthreads();
-        }
-        mlp_block_sum<2>(sums, red);
-        const double nm = sums[0] / N, nr = sums[1] / N;
-        if (tid == 0) {
-            m.score[2 * r] = nm;
-            m.score[2 * r + 1] = nr;
-            m.use[r] = (isfinite(nm) && nm < nr) ? 1 : 0;
-            o.records[((size_t)r * p.K + (k - 1)) * p.rec_len + p.rec_len - 1] = nm - nr;
-        }
-    }
+    mlp_heldout<D>(m, p, o, r, k, seed, W, A, red, frs);
 }
 
 // ------------------------------------------------------------------ kernel-level entry points
+// ------------------------------------------------------------------ split training
+// The same training with a minibatch's sub-batches spread over workgroups, for few
+// runs (one workgroup per run would leave most CUs idle): per minibatch one launch
+// computes each sub-batch's gradient in its own workgroup (the network loaded from the
+// master weights), and a second sums them in sub-batch order and takes the clipped
+// Adam step. The sums group the rows differently from one workgroup's running
+// accumulation, so the two forms agree to FP32 rounding, not bit for bit.
+
+template <int D>
+__global__ void __launch_bounds__(256) k_mlp_prep(MlpArrays m, MlpParams p, OuterArrays o)
+{
+    const int r = (int)blockIdx.x;
+    if (o.status[r] != 0) return;  // every weight vanished: nothing to learn from
+    extern __shared__ __align__(16) unsigned char smem[];
+    MlpAct* A = reinterpret_cast<MlpAct*>(smem + sizeof(MlpW));
+    __shared__ double red[16 * (2 * DMAX + 1)];
+    __shared__ double frs[DMAX + DMAX * DMAX];
+    mlp_train_prologue<D>(m, p, o, r, A, red, frs);
+}
+
+// gradient of sub-batch blockIdx.x (rows b0 + 64 s .. of the minibatch of nb rows at b0)
+// of epoch ep, run blockIdx.y, into m.gpart[r][s]
+template <int D>
+__global__ void __launch_bounds__(256) k_mlp_sub(MlpArrays m, MlpParams p, OuterArrays o, const uint64_t* seeds,
+                                                 int ep, int b0, int nb)
+{
+    const int s = (int)blockIdx.x, r = (int)blockIdx.y;
+    const int s0 = s * MLP_SUB;
+    if (o.status[r] != 0 || s0 >= nb) return;
+    const int tid = (int)threadIdx.x;
+    const int N = p.N, NP = mlp_nparams(D);
+    const int k = *o.k_dev;
+    extern __shared__ __align__(16) unsigned char smem[];
+    MlpW* W = reinterpret_cast<MlpW*>(smem);
+    MlpAct* A = reinterpret_cast<MlpAct*>(smem + sizeof(MlpW));
+    mlp_load_weights(D, m.params + (size_t)r * NP, W);
+    const float* rows = m.rows + (size_t)r * N * MLP_ROW;
+    const double* wfull = m.wfull + (size_t)r * N;
+    if (tid < MLP_SUB) {
+        uint64_t ta, tb, ia, ib;
+        mlp_perm_dev(seeds[r], (uint32_t)k, (uint32_t)ep, 0u, N, ta, tb);
+        mlp_perm_dev(seeds[r], (uint32_t)k, (uint32_t)ep, 1u, N, ia, ib);
+        float u[MLP_ROW], t[MLP_ROW], wr = 0.f;
+#pragma unroll
+        for (int d = 0; d < MLP_ROW; ++d) u[d] = t[d] = 0.f;
+        if (s0 + tid < nb) {
+            const int rr = b0 + s0 + tid;
+            const int jt = (int)((ta * (uint64_t)rr + tb) % (uint64_t)N);
+            const int ii = (int)((ia * (uint64_t)rr + ib) % (uint64_t)N);
+#pragma unroll
+            for (int d = 0; d < MLP_ROW; ++d) {
+                u[d] = rows[(size_t)ii * MLP_ROW + d];
+                t[d] = rows[(size_t)jt * MLP_ROW + d];
+            }
+            wr = (float)(wfull[jt] / (double)nb);
+        }
+#pragma unroll
+        for (int d = 0; d < 16; ++d) {
+            const float ud = d < MLP_ROW ? u[d] : 0.f;
+            A->U[tid * LD16 + d] = ud;
+            A->TU[d * LDT + tid] = f2bf(ud);
+        }
+#pragma unroll
+        for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = t[d];
+        A->wr[tid] = wr;
+    }
+    __syncthreads();
+    f32x4 acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bb3 = 0.f, bb2 = 0.f, bb1 = 0.f;
+    mlp_fwd16<true>(W, A, wave_id() * 16);
+    if (lane_id() < 16) mlp_row_nll<D>(A, wave_id() * 16 + lane_id(), A->wr[wave_id() * 16 + lane_id()], true);
+    wave_sync();
+    mlp_copy_ograd(A, wave_id() * 16);
+    mlp_bwd16(W, A, wave_id() * 16);
+    mlp_bias16(A, wave_id() * 16, bb3, bb2, bb1);
+    __syncthreads();
+    mlp_wgrad(A, acc);
+    __syncthreads();  // the bias sums below reuse the activations' LDS
+    float* gp = m.gpart + ((size_t)r * p.nsub + s) * NP;
+    mlp_scatter_wgrad<D>(acc, gp);
+    mlp_bias_write<D>(A->H1, bb3, bb2, bb1, gp);
+}
+
+// the minibatch gradient (the nsub_b sub-batch gradients summed in order), its global
+// norm clipped to MLP_CLIP, and one Adam step on the master weights of run blockIdx.x
+template <int D>
+__global__ void __launch_bounds__(256) k_mlp_adam(MlpArrays m, MlpParams p, OuterArrays o, int nsub_b)
+{
+    const int r = (int)blockIdx.x;
+    if (o.status[r] != 0) return;
+    const int tid = (int)threadIdx.x;
+    const int NP = mlp_nparams(D);
+    __shared__ double red[16 * (2 * DMAX + 1)];
+    const float* gp = m.gpart + (size_t)r * p.nsub * NP;
+    float* grad = m.grad + (size_t)r * NP;
+    float* prm = m.params + (size_t)r * NP;
+    float* am = m.adam_m + (size_t)r * NP;
+    float* av = m.adam_v + (size_t)r * NP;
+    // parameters i = tid + 256 e in chunks of CH, every load of a chunk issued first
+    constexpr int PER = (mlp_np_const(D) + 255) / 256, CH = 8;
+    double nn[1] = {0.0};
+#pragma nounroll
+    for (int e0 = 0; e0 < PER; e0 += CH) {
+        float g[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int i = tid + 256 * (e0 + e);
+            g[e] = (e0 + e < PER && i < NP) ? gp[i] : 0.f;
+        }
+        for (int b = 1; b < nsub_b; ++b) {
+            float h[CH];
+#pragma unroll
+            for (int e = 0; e < CH; ++e) {
+                const int i = tid + 256 * (e0 + e);
+                h[e] = (e0 + e < PER && i < NP) ? gp[(size_t)b * NP + i] : 0.f;
+            }
+#pragma unroll
+            for (int e = 0; e < CH; ++e) g[e] += h[e];
+        }
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int i = tid + 256 * (e0 + e);
+            if (e0 + e < PER && i < NP) {
+                grad[i] = g[e];
+                nn[0] += (double)g[e] * (double)g[e];
+            }
+        }
+    }
+    mlp_block_sum<1>(nn, red);
+    const double nrm = sqrt(nn[0]);
+    const double clip = nrm > MLP_CLIP ? MLP_CLIP / nrm : 1.0;
+    const int t_adam = m.adam_t[r] + 1;
+    const float c1 = 1.f - powf(0.9f, (float)t_adam), c2 = 1.f - powf(0.999f, (float)t_adam);
+#pragma nounroll
+    for (int e0 = 0; e0 < PER; e0 += CH) {
+        float g[CH], mo[CH], vo[CH], po[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int i = tid + 256 * (e0 + e);
+            if (e0 + e < PER && i < NP) {
+                g[e] = grad[i];
+                mo[e] = am[i];
+                vo[e] = av[i];
+                po[e] = prm[i];
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int i = tid + 256 * (e0 + e);
+            if (e0 + e < PER && i < NP) {
+                const float gi = (float)((double)g[e] * clip);
+                const float mi = 0.9f * mo[e] + 0.1f * gi;
+                const float vi = 0.999f * vo[e] + 0.001f * gi * gi;
+                am[i] = mi;
+                av[i] = vi;
+                prm[i] = po[e] - p.lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
+            }
+        }
+    }
+    __syncthreads();  // every thread has read the step count
+    if (tid == 0) m.adam_t[r] = t_adam;
+}
+
+// held-out sums of sub-batch blockIdx.x of run blockIdx.y, into the run's scratch as
+// doubles hp[s][2] (at most 512 sub-batches: far inside the run's share of gpart)
+template <int D>
+__global__ void __launch_bounds__(256) k_mlp_heldout(MlpArrays m, MlpParams p, OuterArrays o, const uint64_t* seeds)
+{
+    const int s = (int)blockIdx.x, r = (int)blockIdx.y;
+    if (o.status[r] != 0) return;
+    const int tid = (int)threadIdx.x;
+    extern __shared__ __align__(16) unsigned char smem[];
+    MlpW* W = reinterpret_cast<MlpW*>(smem);
+    MlpAct* A = reinterpret_cast<MlpAct*>(smem + sizeof(MlpW));
+    __shared__ double red[16 * (2 * DMAX + 1)];
+    __shared__ double frs[DMAX + DMAX * DMAX];
+    const double* fr = m.frame + (size_t)r * (D + D * D);
+    for (int d = tid; d < D + D * D; d += 256) frs[d] = fr[d];
+    mlp_load_weights(D, m.params + (size_t)r * mlp_nparams(D), W);
+    __syncthreads();
+    double sums[2] = {0.0, 0.0};
+    mlp_heldout_rows<D>(m, p, o, r, *o.k_dev, seeds[r], W, A, frs, s * MLP_SUB, (s + 1) * MLP_SUB, sums);
+    mlp_block_sum<2>(sums, red);
+    if (tid == 0) {
+        double* hp = reinterpret_cast<double*>(m.gpart + (size_t)r * p.nsub * mlp_nparams(D)) + 2 * (size_t)s;
+        hp[0] = sums[0];
+        hp[1] = sums[1];
+    }
+}
+
+// the sub-batches' held-out sums added in order, and the decision (run blockIdx.x)
+template <int D>
+__global__ void __launch_bounds__(64) k_mlp_heldout_sum(MlpArrays m, MlpParams p, OuterArrays o, int nblk)
+{
+    const int r = (int)blockIdx.x;
+    if (o.status[r] != 0 || threadIdx.x != 0) return;
+    const double* hp = reinterpret_cast<const double*>(m.gpart + (size_t)r * p.nsub * mlp_nparams(D));
+    double sm = 0.0, sr = 0.0;
+    for (int b = 0; b < nblk; ++b) {
+        sm += hp[2 * b];
+        sr += hp[2 * b + 1];
+    }
+    mlp_heldout_decide(m, p, o, r, *o.k_dev, sm, sr);
+}
+
 template <int D>
 __global__ void __launch_bounds__(256) k_mlp_rows_forward(int n, const float* params, const double* frame,
                                                           const double* phi, float* out)
@@ -955,10 +1240,41 @@ hipError_t launch_mlp_train(const MlpArrays& m, const MlpParams& p, const OuterA
                             hipStream_t s)
 {
     hipError_t e = hipSuccess;
+    if (!p.split) {
 #define CALL_TRAIN(DD)                                                                                          \
     hipLaunchKernelGGL(k_mlp_train<DD>, dim3((unsigned)p.R), dim3(256), MLP_LDS_TRAIN, s, m, p, o, seeds);
-    MLP_DISPATCH(p.D, CALL_TRAIN)
+        MLP_DISPATCH(p.D, CALL_TRAIN)
 #undef CALL_TRAIN
+        return e != hipSuccess ? e : hipGetLastError();
+    }
+    const int N = p.N, B = (p.batch < 1 || p.batch > N) ? N : p.batch;
+    const dim3 runs((unsigned)p.R);
+#define CALL_PREP(DD) hipLaunchKernelGGL(k_mlp_prep<DD>, runs, dim3(256), MLP_LDS_TRAIN, s, m, p, o);
+    MLP_DISPATCH(p.D, CALL_PREP)
+#undef CALL_PREP
+    e = hipGetLastError();
+    for (int ep = 0; ep < p.epochs && e == hipSuccess; ++ep) {
+        for (int b0 = 0; b0 < N && e == hipSuccess; b0 += B) {
+            const int nb = (N - b0) < B ? (N - b0) : B;
+            const int nsub_b = (nb + MLP_SUB - 1) / MLP_SUB;
+            const dim3 grid((unsigned)nsub_b, (unsigned)p.R);
+#define CALL_STEP(DD)                                                                                           \
+    hipLaunchKernelGGL(k_mlp_sub<DD>, grid, dim3(256), MLP_LDS_TRAIN, s, m, p, o, seeds, ep, b0, nb);            \
+    hipLaunchKernelGGL(k_mlp_adam<DD>, runs, dim3(256), 0, s, m, p, o, nsub_b);
+            MLP_DISPATCH(p.D, CALL_STEP)
+#undef CALL_STEP
+            e = hipGetLastError();
+        }
+    }
+    const int nblk = (N + MLP_SUB - 1) / MLP_SUB;
+#define CALL_HELD(DD)                                                                                           \
+    hipLaunchKernelGGL(k_mlp_heldout<DD>, dim3((unsigned)nblk, (unsigned)p.R), dim3(256), MLP_LDS_TRAIN, s, m, p, o, \
+                       seeds);                                                                                  \
+    hipLaunchKernelGGL(k_mlp_heldout_sum<DD>, runs, dim3(64), 0, s, m, p, o, nblk);
+    if (e == hipSuccess) {
+        MLP_DISPATCH(p.D, CALL_HELD)
+    }
+#undef CALL_HELD
     return e != hipSuccess ? e : hipGetLastError();
 }
 
@@ -992,6 +1308,9 @@ hipError_t mlp_prepare(int D)
 #define CALL_PREP(DD)                                                                                           \
     e = raise_lds(k_mlp_forward<DD>, MLP_LDS_FWD);                                                              \
     if (e == hipSuccess) e = raise_lds(k_mlp_train<DD>, MLP_LDS_TRAIN);                                         \
+    if (e == hipSuccess) e = raise_lds(k_mlp_prep<DD>, MLP_LDS_TRAIN);                                          \
+    if (e == hipSuccess) e = raise_lds(k_mlp_sub<DD>, MLP_LDS_TRAIN);                                           \
+    if (e == hipSuccess) e = raise_lds(k_mlp_heldout<DD>, MLP_LDS_TRAIN);                                       \
     if (e == hipSuccess) e = raise_lds(k_mlp_rows_forward<DD>, MLP_LDS_FWD);                                    \
     if (e == hipSuccess) e = raise_lds(k_mlp_rows_grad<DD>, MLP_LDS_TRAIN);
     MLP_DISPATCH(D, CALL_PREP)

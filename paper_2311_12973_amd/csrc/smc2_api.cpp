@@ -60,7 +60,7 @@ struct Layout {
     size_t off_k, off_status, off_seeds, off_runs, off_y, off_prior, off_lrw, off_phi, off_phin, off_thn, off_lp,
         off_ll, off_logw, off_lpn, off_lln, off_lwp, off_scr, off_qc, off_anc, off_active, off_rec, off_items,
         off_queues, off_tune_items, off_mlp_params, off_mlp_m, off_mlp_v, off_mlp_grad, off_mlp_t, off_mlp_frame,
-        off_mlp_use, off_mlp_out, off_mlp_logq, off_mlp_score, off_mlp_rows, off_mlp_wfull;
+        off_mlp_use, off_mlp_out, off_mlp_logq, off_mlp_score, off_mlp_rows, off_mlp_wfull, off_mlp_gpart;
     size_t take(size_t bytes)
     {
         const size_t o = total;
@@ -114,6 +114,7 @@ Layout make_layout(const smc2_config* c, int R, const smc2_run* runs)
     L.off_mlp_score = L.take(sizeof(double) * Rm * 2);
     L.off_mlp_rows = L.take(sizeof(float) * Rm * N * MLP_ROW);
     L.off_mlp_wfull = L.take(sizeof(double) * Rm * N);
+    L.off_mlp_gpart = L.take(sizeof(float) * (mlp_split(c->mlp_train, (int)R) ? Rm * (size_t)mlp_nsub(c->mlp_batch, (int)N) * NP : 0));
     return L;
 }
 
@@ -213,6 +214,8 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
     if (c->persistent < 0 || c->persistent > 1) return m = "persistent must be 0 or 1", SMC2_E_ARG;
     if (c->pf_resampling != SMC2_PF_RS_SYSTEMATIC && c->pf_resampling != SMC2_PF_RS_MULTINOMIAL)
         return m = "pf_resampling must be SMC2_PF_RS_SYSTEMATIC or SMC2_PF_RS_MULTINOMIAL", SMC2_E_ARG;
+    if (c->mlp_train < SMC2_MLP_TRAIN_AUTO || c->mlp_train > SMC2_MLP_TRAIN_SPLIT)
+        return m = "mlp_train must be SMC2_MLP_TRAIN_AUTO, _PER_RUN or _SPLIT", SMC2_E_ARG;
     if (c->schedule == 2 && c->model == SMC2_AGE_SEIR)
         return m = "the pooled schedule supports SIR and SEIR only", SMC2_E_UNSUPPORTED;
     if (!c->prior || !c->rw_cov) return m = "prior and rw_cov are required", SMC2_E_ARG;
@@ -506,6 +509,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
         ma.score = (double*)(w + lay.off_mlp_score);
         ma.rows = (float*)(w + lay.off_mlp_rows);
         ma.wfull = (double*)(w + lay.off_mlp_wfull);
+        ma.gpart = (float*)(w + lay.off_mlp_gpart);
         o.mlp_use = ma.use;
         o.mlp_out = ma.out;
         o.mlp_frame = ma.frame;
@@ -531,6 +535,8 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
         q.batch = cfg->mlp_batch;
         q.lr = (float)cfg->mlp_lr;
         q.rec_len = SMC2_RECORD_LEN(cfg->D);
+        q.nsub = mlp_nsub(cfg->mlp_batch, cfg->N);
+        q.split = mlp_split(cfg->mlp_train, n_runs) ? 1 : 0;
         q.lrw = p.lrw;
     }
     c->d_seeds = (const uint64_t*)(w + lay.off_seeds);
@@ -737,6 +743,7 @@ extern "C" int smc2_dump(smc2_ctx* c, int32_t what, int32_t run, void* host_dst,
     case SMC2_DUMP_LOGQ:
     case SMC2_DUMP_MLP_PARAMS:
     case SMC2_DUMP_MLP_FRAME:
+    case SMC2_DUMP_MLP_GRAD:
     case SMC2_DUMP_MLP_STATE: {
         if (!c->op.mlp) return c->fail(SMC2_E_ARG, "the context has no learned proposal");
         const size_t NP = (size_t)mlp_nparams((int)D), P = (size_t)mlp_nout((int)D);
@@ -744,6 +751,7 @@ extern "C" int smc2_dump(smc2_ctx* c, int32_t what, int32_t run, void* host_dst,
         if (what == SMC2_DUMP_LOGQ) src = c->oa.logq + base, need = N * 8;
         if (what == SMC2_DUMP_MLP_PARAMS) src = c->ma.params + (size_t)run * NP, need = NP * 4;
         if (what == SMC2_DUMP_MLP_FRAME) src = c->ma.frame + (size_t)run * (D + D * D), need = (D + D * D) * 8;
+        if (what == SMC2_DUMP_MLP_GRAD) src = c->ma.grad + (size_t)run * NP, need = NP * 4;
         if (what == SMC2_DUMP_MLP_STATE) {
             if (bytes < 4 * 8) return c->fail(SMC2_E_ARG, "destination too small");
             if (c->poisoned) return c->fail(SMC2_E_DEVICE, "context poisoned by an earlier device error");

@@ -73,6 +73,10 @@ def test_workspace_bytes_and_validation():
         assert b"pf_resampling" in L.smc2_last_error(None)
     c = G.make_config(dict(w, pf_resampling=G.PF_RS_MULTINOMIAL))
     assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == nb
+    for v in (3, -1):
+        c = G.make_config(dict(w, mlp_train=v))
+        assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == 0
+        assert b"mlp_train" in L.smc2_last_error(None)
     yneg = y.copy()
     yneg[3] = -1
     assert L.smc2_workspace_bytes(ctypes.byref(cfg), 1, G.make_runs([dict(T=100, nx=512, seed=1, y=yneg)])) == 0

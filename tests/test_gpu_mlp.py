@@ -91,6 +91,35 @@ def _learned_case():
     return w, W.observations(w)
 
 
+@pytest.mark.parametrize("batch", [0, 100])
+def test_training_layouts_agree(batch):
+    """The two training layouts (one workgroup per run; a workgroup per 64-row sub-batch
+    with a second launch for the sum and the Adam step) compute the same minibatch
+    gradient from the same network and rows, up to FP32 summation order. One epoch: with
+    batch 0 a single full-population minibatch (four sub-batches at N = 256), with 100
+    rows three minibatches whose last one is ragged (56 rows). Trained networks then
+    agree to that rounding, amplified by the Adam steps, and give the same held-out
+    decision."""
+    w, y = _learned_case()
+    w = dict(w, mlp_epochs=1, mlp_batch=batch)
+    res = {}
+    for layout in (G.MLP_TRAIN_PER_RUN, G.MLP_TRAIN_SPLIT):
+        s = G.Sampler(dict(w, mlp_train=layout), [dict(T=y.shape[0], nx=128, seed=3, y=y)], N=256, K=2)
+        s.step()
+        res[layout] = {key: s.dump(key) for key in ("mlp_grad", "mlp_params", "mlp_state", "mlp_frame")}
+        s.close()
+    a, b = res[G.MLP_TRAIN_PER_RUN], res[G.MLP_TRAIN_SPLIT]
+    assert np.array_equal(a["mlp_frame"], b["mlp_frame"])
+    g1, g2 = a["mlp_grad"].astype(np.float64), b["mlp_grad"].astype(np.float64)
+    scale = np.abs(g1).max()
+    _log("batch %d: gradient max |diff| %.3g of max |g| %.3g" % (batch, np.abs(g1 - g2).max(), scale))
+    assert scale > 0 and np.abs(g1 - g2).max() <= 1e-4 * scale
+    assert a["mlp_state"][1] == b["mlp_state"][1]  # Adam steps taken
+    assert a["mlp_state"][0] == b["mlp_state"][0]  # the held-out decision
+    assert np.allclose(a["mlp_state"][2:], b["mlp_state"][2:], rtol=1e-3)
+    assert np.abs(a["mlp_params"] - b["mlp_params"]).max() <= 0.05
+
+
 @pytest.mark.parametrize("case", ["seir_d5", "age_seir_d8"])
 def test_learned_proposal_replayed_by_reference(case):
     if case == "seir_d5":
