@@ -138,15 +138,17 @@ def _pf_case(name, prec, nx, n_theta, T=None, pf_always=0, seed=11, k=2):
     return w, y, theta
 
 
-@pytest.mark.parametrize("name,prec,nx,T", [("sir_fp64", G.PREC_FP64, 64, None), ("sir_fp64", G.PREC_FP32, 100, None),
-                                            ("paper_sir", G.PREC_FP64, 500, None), ("seir", G.PREC_FP32, 512, 60),
-                                            ("seir", G.PREC_FP64, 300, 40), ("age_seir", G.PREC_FP32, 300, 60),
-                                            ("age_seir", G.PREC_FP64, 130, 40)])
+_PF_CASES = [("sir_fp64", G.PREC_FP64, 64, None), ("sir_fp64", G.PREC_FP32, 100, None),
+             ("paper_sir", G.PREC_FP64, 500, None), ("seir", G.PREC_FP32, 512, 60), ("seir", G.PREC_FP64, 300, 40),
+             ("age_seir", G.PREC_FP32, 300, 60), ("age_seir", G.PREC_FP64, 130, 40)]
+
+
+# the pooled schedule covers SIR and SEIR; the age-structured model always runs per draw
+@pytest.mark.parametrize("name,prec,nx,T,schedule",
+                         [c + (G.SCHED_PER_DRAW,) for c in _PF_CASES] +
+                         [c + (G.SCHED_POOLED,) for c in _PF_CASES if c[0] != "age_seir"])
 @pytest.mark.parametrize("block", [0, 64, 128, 512])
-@pytest.mark.parametrize("schedule", [G.SCHED_PER_DRAW, G.SCHED_POOLED])
 def test_pf_loglik_matches_oracle(name, prec, nx, T, block, schedule):
-    if name == "age_seir" and schedule == G.SCHED_POOLED:
-        pytest.skip("the pooled schedule covers SIR and SEIR")
     _log("pf %s prec=%d nx=%d block=%d schedule=%d" % (name, prec, nx, block, schedule))
     w, y, theta = _pf_case(name, prec, nx, 24, T)
     got = G.pf_loglik(w, theta, y, nx, seed=9, k=2, precision=prec, block=block, schedule=schedule)
