@@ -208,6 +208,26 @@ def test_pf_multinomial_resampling_matches_oracle(name, prec, nx, T, pf_always):
             assert np.array_equal(st[i], st_ref)
 
 
+@pytest.mark.parametrize("name,prec,nx,T", [("seir", G.PREC_FP32, 4096, 20), ("sir_fp64", G.PREC_FP64, 4096, 30),
+                                            ("age_seir", G.PREC_FP32, 2048, 12)])
+@pytest.mark.parametrize("block", [0, 1024])
+@pytest.mark.parametrize("schedule", [G.SCHED_AUTO, G.SCHED_PER_DRAW])
+def test_pf_maximum_particles_matches_oracle(name, prec, nx, T, block, schedule):
+    """The largest particle count the interface accepts per model (4096; 2048 for the
+    age model), with the automatic and the per-draw schedule, against the reference."""
+    _log("pf max %s prec=%d nx=%d block=%d schedule=%d" % (name, prec, nx, block, schedule))
+    w, y, theta = _pf_case(name, prec, nx, 8, T)
+    got = G.pf_loglik(w, theta, y, nx, seed=5, k=3, precision=prec, block=block, schedule=schedule)
+    cfg = O.config_from_workload(w, prec=prec)
+    want = np.array([O.pf_loglik(cfg, theta[i], y, nx, 5, i, 3) for i in range(len(theta))])
+    fin = np.isfinite(want)
+    assert fin.sum() >= 4
+    assert np.array_equal(np.isfinite(got), fin)
+    rel = np.abs(got[fin] - want[fin]) / np.abs(want[fin])
+    _log("  max rel err %.3g" % rel.max())
+    assert rel.max() <= (1e-12 if prec == G.PREC_FP64 else 1e-4)
+
+
 def test_pf_dead_filter_is_minus_inf():
     w = W.preset("paper_sir")
     y = np.zeros((5, 1), dtype=np.int32)

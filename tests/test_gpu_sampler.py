@@ -318,3 +318,46 @@ def test_batched_matches_reference_per_run():
         ref = O.smc2_run(cfg, run["y"], run["nx"], run["seed"], 32, 2)
         assert np.array_equal(recs[r][:, [0, 2, 3, 4]], ref["rec"][:, [0, 2, 3, 4]])
         assert np.allclose(recs[r][:, 6:], ref["rec"][:, 6:], rtol=1e-4, atol=1e-10)
+
+
+@pytest.mark.parametrize("N", [2, 32768])
+def test_sample_count_limits_sampled_parity(N):
+    """The smallest and largest sample counts the interface accepts (N = 2 and 32768),
+    SEIR FP32 with small filters: proposals, sampled log-likelihoods and the outer step
+    of every iteration against the reference. With two samples the joint Gaussian fit
+    of the L-kernel is singular, and every iteration after the first takes the forward
+    kernel's weights (the record's fallback column)."""
+    w = dict(W.preset("seir"), T=15)
+    y = W.observations(w)
+    nx, K = 32, 3
+    _log("N=%d nx=%d T=%d K=%d" % (N, nx, w["T"], K))
+    s = G.Sampler(w, [dict(T=w["T"], nx=nx, seed=w["seed"], y=y)], N=N, K=K)
+    cfg = O.config_from_workload(w)
+    rng = np.random.default_rng(1)
+    for k in range(1, K + 1):
+        before = {key: s.dump(key) for key in ("phi", "lp", "ll", "logw")} if k > 1 else None
+        s.step()
+        phin, lpn, lln = s.dump("phi_new"), s.dump("lp_new"), s.dump("ll_new")
+        lwp, anc = s.dump("logw_pre"), s.dump("anc")
+        if k == 1:
+            ph_ref, lp_ref = O.prior_draw(cfg, N, w["seed"])
+        else:
+            ph_ref, lp_ref = O.propose_rw(cfg, w["seed"], k, before["phi"])
+        assert np.allclose(phin, ph_ref, rtol=1e-12, atol=1e-12)
+        assert np.allclose(lpn, lp_ref, rtol=1e-12, atol=1e-12)
+        idx = np.arange(N) if N <= 8 else np.concatenate([[0, N - 1], rng.choice(N, size=6, replace=False)])
+        for i in idx:
+            ref = O.pf_loglik(cfg, O.theta_of_phi(cfg, phin[i]), y, nx, w["seed"], int(i), k)
+            if np.isfinite(ref):
+                assert abs(lln[i] - ref) <= 1e-4 * abs(ref), (k, i)
+            else:
+                assert lln[i] == ref, (k, i)
+        st = dict(phi=np.zeros((N, w["D"])), lp=np.zeros(N), ll=np.zeros(N), logw=np.zeros(N)) if k == 1 else before
+        status, lwp_ref, anc_ref, rec_ref = O.outer_update(cfg, k, w["seed"], st, phin, lpn, lln)
+        assert status == 0
+        assert np.allclose(lwp, lwp_ref, rtol=1e-9, atol=1e-9)
+        assert np.array_equal(anc, anc_ref)
+        assert np.allclose(s.records()[k - 1], rec_ref, rtol=1e-8, atol=1e-12)
+        if N == 2 and k > 1:
+            assert s.records()[k - 1][4] == 1
+    s.close()
