@@ -42,7 +42,7 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_amd/csrc/pf_kernel.h",
                   "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h",
                   "paper_2311_12973_amd/build.py"]
-KERNEL_SHA = "c226b7af12da1863"
+KERNEL_SHA = "2d9e2dae3ea4b73b"
 PROFILED_WORKLOAD = "seir"
 VALU_LANE_INSTR_PER_PSTEP = 1506.1
 HBM_BYTES_PER_LAUNCH = 1.028e6

@@ -17,6 +17,7 @@
 //      through LDS, log-weights reset (every particle gets the mean weight).
 #include <map>
 #include <mutex>
+#include <utility>
 
 #include "block_ops.h"
 #include "pf_kernel.h"
@@ -805,12 +806,15 @@ hipError_t pf_prepare(int prec, int model, int obs, int sched, size_t lds)
     const void* f = kernel_for(prec, model, obs, sched);
     if (!f) return hipErrorInvalidValue;
     if (lds <= 65536) return hipSuccess;
-    // the attribute belongs to the kernel, shared by every launch group and context of
-    // the process: only ever raise it to the largest size asked for
+    // the attribute belongs to the kernel on the current device, shared by every launch
+    // group and context there: only ever raise it to the largest size asked for
+    int dev = 0;
+    const hipError_t ed = hipGetDevice(&dev);
+    if (ed != hipSuccess) return ed;
     static std::mutex mu;
-    static std::map<const void*, size_t> raised;
+    static std::map<std::pair<int, const void*>, size_t> raised;
     std::lock_guard<std::mutex> lock(mu);
-    size_t& cur = raised[f];
+    size_t& cur = raised[{dev, f}];
     if (lds <= cur) return hipSuccess;
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess) cur = lds;

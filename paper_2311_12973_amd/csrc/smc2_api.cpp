@@ -584,7 +584,9 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     if (e == hipSuccess)
         e = hipMemsetAsync(w + lay.off_rec, 0, sizeof(double) * n_runs * cfg->K * SMC2_RECORD_LEN(cfg->D), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, 0);
+    int dev = 0;
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess && cfg->tune) e = autotune(c);
     for (PFGroup& gr : c->groups) {
         if (e != hipSuccess) break;
