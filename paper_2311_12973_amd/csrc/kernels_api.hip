@@ -165,9 +165,20 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     const int no = n_obs_of(cfg->model);
     for (int e = 0; e < run->T * no; ++e)
         if (run->y[e] < 0) return kfail(SMC2_E_ARG, "negative observation");
+    if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64 != 0))
+        return kfail(SMC2_E_ARG, "block must be 0 or a multiple of 64 up to 1024");
+    if (cfg->schedule < 0 || cfg->schedule > 2) return kfail(SMC2_E_ARG, "schedule must be 0, 1 or 2");
+    const int block = cfg->block ? cfg->block
+                                 : pf_default_block(cfg->model, cfg->precision, run->n_x, run->T, cfg->schedule);
+    const int sched = pf_pick_schedule(cfg->model, cfg->precision, block, run->n_x, run->T, cfg->schedule);
+    if (sched < 0) return kfail(SMC2_E_ARG, "the pooled schedule cannot run this model, n_x and T");
+    const size_t lds = pf_lds_bytes(cfg->model, cfg->precision, block, run->n_x, run->T, sched);
+    if (lds > PF_LDS_MAX) return kfail(SMC2_E_ARG, "particle filter does not fit in LDS");
     if (n_theta == 0) return SMC2_OK;
     hipStream_t s = (hipStream_t)stream;
     unsigned char* w = (unsigned char*)d_ws;
+    // every argument is checked before the first copy: from here on the host copies of rd
+    // and y must stay valid until the stream has run the copies, also on a device error
     RunDev rd{run->T, run->n_x, 0, 0, (uint32_t)run->seed, (uint32_t)(run->seed >> 32)};
     hipError_t e = hipMemcpyAsync(w, &rd, sizeof(rd), hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -191,15 +202,6 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     a.multinomial = cfg->pf_resampling;
     a.n_pop = cfg->n_pop;
     for (int i = 0; i < SMC2_NFIXED; ++i) a.fx[i] = i < cfg->n_fixed ? cfg->fixed[i] : 0.0;
-    if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64 != 0))
-        return kfail(SMC2_E_ARG, "block must be 0 or a multiple of 64 up to 1024");
-    const int block = cfg->block ? cfg->block
-                                 : pf_default_block(cfg->model, cfg->precision, run->n_x, run->T, cfg->schedule);
-    if (cfg->schedule < 0 || cfg->schedule > 2) return kfail(SMC2_E_ARG, "schedule must be 0, 1 or 2");
-    const int sched = pf_pick_schedule(cfg->model, cfg->precision, block, run->n_x, run->T, cfg->schedule);
-    if (sched < 0) return kfail(SMC2_E_ARG, "the pooled schedule cannot run this model, n_x and T");
-    const size_t lds = pf_lds_bytes(cfg->model, cfg->precision, block, run->n_x, run->T, sched);
-    if (lds > PF_LDS_MAX) return kfail(SMC2_E_ARG, "particle filter does not fit in LDS");
     if (e == hipSuccess) e = pf_prepare(cfg->precision, cfg->model, cfg->obs, sched, lds);
     // wave priorities when every filter is resident at once (they even out its tail)
     int per_cu = 0, n_cu = 0, dev = 0;
@@ -209,8 +211,8 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     if (e == hipSuccess && (long)n_theta <= (long)per_cu * n_cu)
         a.prio_scale = (float)(1.0 / ((double)run->T * (double)run->n_x));
     if (e == hipSuccess) e = launch_pf(cfg->precision, cfg->model, cfg->obs, sched, block, lds, a, s);
-    // the host copies of rd and y must stay valid until the copies have run
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    const hipError_t es = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = es;
     return e == hipSuccess ? SMC2_OK : kfail(SMC2_E_DEVICE, hipGetErrorString(e));
 }
 

@@ -111,3 +111,18 @@ def test_kernel_entry_points_reject_bad_arguments():
     assert L.smc2_mlp_forward(9, 4, None, None, None, None, None) == G.E_ARG
     assert L.smc2_mlp_forward(4, 4, None, None, None, None, None) == G.E_ARG
     assert L.smc2_mlp_grad(4, 0, None, None, None, None, None, None, None, None) == G.E_ARG
+    # the filter entry point checks every argument before its first copy or launch: these
+    # stand-in addresses are never dereferenced
+    w = _w()
+    y = W.observations(w)
+    runs = G.make_runs([dict(T=100, nx=512, seed=1, y=y)])
+    fake = ctypes.c_void_p(1 << 20)
+    ws = L.smc2_pf_workspace_bytes(ctypes.byref(G.make_config(w)), runs)
+    for over, msg in [(dict(block=96), b"block"), (dict(schedule=3), b"schedule")]:
+        c = G.make_config(w, **over)
+        assert L.smc2_pf_loglik(ctypes.byref(c), 4, fake, runs, 1, fake, fake, ws, None) == G.E_ARG, over
+        assert msg in L.smc2_last_error(None)
+    ra = G.make_runs([dict(T=10, nx=256, seed=1, y=W.observations(dict(W.preset("age_seir"), T=10)))])
+    ca = G.make_config(W.preset("age_seir"), schedule=G.SCHED_POOLED)
+    assert L.smc2_pf_loglik(ctypes.byref(ca), 4, fake, ra, 1, fake, fake, ws, None) == G.E_ARG
+    assert b"pooled" in L.smc2_last_error(None)
