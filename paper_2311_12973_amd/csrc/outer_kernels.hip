@@ -181,7 +181,7 @@ template <int D> __device__ __forceinline__ double mvn_logpdf(const double* x, c
 }
 
 constexpr int OUTER_WAVES = OUTER_BLOCK / 64;
-constexpr int VSUM_MAX = 17;  // widest block_sum_vec: 2 D + 1 for D = 8
+constexpr int VSUM_MAX = 18;  // widest block_sum_vec (2 D + 1 = 17 for D = 8; covariance passes up to 18)
 
 // Sum of E per-thread values over the block, in a fixed order (butterfly inside each
 // wave, then the waves in index order); every thread then reads the E sums from out[]
@@ -205,29 +205,47 @@ __device__ __forceinline__ void block_sum_vec(double (&v)[E], double* lds, doubl
 }
 
 // out (NV x NV, symmetric) = sum_i w_i (z_i - m)(z_i - m)^T, z_i loaded by load(i, z).
-// The NV (NV + 1) / 2 upper-triangle entries are accumulated eight at a time so a
-// thread never holds more than eight partial sums.
+// The NV (NV + 1) / 2 upper-triangle entries are accumulated in as few passes as the
+// reduction width allows (at most VSUM_MAX partial sums per thread), each pass ending
+// in one block reduction. Every entry is summed in the same order however the entries
+// are grouped into passes.
+// row and column of each upper-triangle entry of an NV x NV matrix, row by row
+template <int NV> struct TriIndex {
+    int row[NV * (NV + 1) / 2], col[NV * (NV + 1) / 2];
+    constexpr TriIndex() : row(), col()
+    {
+        int e = 0;
+        for (int a = 0; a < NV; ++a)
+            for (int c = a; c < NV; ++c) {
+                row[e] = a;
+                col[e] = c;
+                ++e;
+            }
+    }
+};
+
 template <int NV, class Load>
 __device__ __forceinline__ void block_weighted_cov(int N, const double* w, const double* m, Load load, double* out,
                                                    double* vlds, double* tmp)
 {
     constexpr int NE = NV * (NV + 1) / 2;
+    constexpr int NPASS = (NE + VSUM_MAX - 1) / VSUM_MAX;
+    constexpr int CH = (NE + NPASS - 1) / NPASS;
+    constexpr TriIndex<NV> tri{};
     const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
-    for (int c0 = 0; c0 < NE; c0 += 8) {
-        int ea[8], ec[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            int t = c0 + e < NE ? c0 + e : NE - 1, r0 = 0;
-            while (t >= NV - r0) {
-                t -= NV - r0;
-                ++r0;
-            }
-            ea[e] = r0;
-            ec[e] = r0 + t;
+    for (int pass = 0; pass < NPASS; ++pass) {
+        const int c0 = pass * CH;
+        int ea[CH], ec[CH];
+#pragma unroll
+        for (int e = 0; e < CH; ++e) {
+            const int t = c0 + e < NE ? c0 + e : NE - 1;
+            ea[e] = tri.row[t];
+            ec[e] = tri.col[t];
         }
-        double acc[8];
+        double acc[CH];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) acc[e] = 0.0;
+        for (int e = 0; e < CH; ++e) acc[e] = 0.0;
         for (int i = tid; i < N; i += nthr) {
             double z[NV];
             load(i, z);
@@ -235,10 +253,10 @@ __device__ __forceinline__ void block_weighted_cov(int N, const double* w, const
             for (int v = 0; v < NV; ++v) z[v] -= m[v];
             const double wi = w[i];
 #pragma unroll
-            for (int e = 0; e < 8; ++e) acc[e] += wi * z[ea[e]] * z[ec[e]];
+            for (int e = 0; e < CH; ++e) acc[e] += wi * z[ea[e]] * z[ec[e]];
         }
-        block_sum_vec<8>(acc, vlds, tmp);
-        if (tid < 8 && c0 + tid < NE) {
+        block_sum_vec<CH>(acc, vlds, tmp);
+        if (tid < CH && c0 + tid < NE) {
             out[ea[tid] * NV + ec[tid]] = tmp[tid];
             out[ec[tid] * NV + ea[tid]] = tmp[tid];
         }
