@@ -33,16 +33,19 @@ struct W4 {
     uint32_t x, y, z, w;
 };
 
-// a ^ b ^ c; on the device one three-input bitwise instruction (truth table 0x96)
-__host__ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+// a ^ b ^ c. With V3 on the device, one three-input bitwise vector instruction (truth
+// table 0x96) instead of two XORs; it is a vector instruction even for uniform inputs, so
+// it is meant for counters that differ per lane, where the XORs are vector work anyway.
+template <bool V3> __host__ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 {
 #if defined(__HIP_DEVICE_COMPILE__)
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
-#else
-    return a ^ b ^ c;
+    if constexpr (V3) return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
 #endif
+    return a ^ b ^ c;
 }
 
+// V3: the round XORs as three-input vector instructions (per-lane counters)
+template <bool V3 = false>
 __host__ __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
                                                 uint32_t k1)
 {
@@ -50,8 +53,8 @@ __host__ __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
-        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+        const uint32_t n0 = xor3<V3>((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3<V3>((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -97,7 +100,7 @@ struct DrawStream {
     uint32_t k0, k1;
     __device__ __forceinline__ W4 call(uint32_t a) const
     {
-        return philox10(j, i, kt, (S_PF_PROP << 24) | (b << 16) | a, k0, k1);
+        return philox10<true>(j, i, kt, (S_PF_PROP << 24) | (b << 16) | a, k0, k1);
     }
 };
 
