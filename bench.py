@@ -42,9 +42,9 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_amd/csrc/pf_kernel.h",
                   "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h",
                   "paper_2311_12973_amd/build.py"]
-KERNEL_SHA = "e65035f1a6d2a5b0"
+KERNEL_SHA = "1f81db080fc0dc9e"
 PROFILED_WORKLOAD = "seir"
-VALU_LANE_INSTR_PER_PSTEP = 1455.9
+VALU_LANE_INSTR_PER_PSTEP = 1437.6
 HBM_BYTES_PER_LAUNCH = 1.0383e6
 
 

@@ -65,7 +65,13 @@ __host__ __device__ __forceinline__ W4 philox10(uint32_t c0, uint32_t c1, uint32
     return W4{c0, c1, c2, c3};
 }
 
-__device__ __forceinline__ float u24(uint32_t x) { return (float)(2u * (x >> 9) + 1u) * 0x1p-24f; }
+// (2 (x >> 9) + 1) 2^-24. One funnel shift puts k = x >> 9 under the exponent of 1.0,
+// giving 1 + k 2^-23; subtracting 1 - 2^-24 leaves (2k + 1) 2^-24 exactly (the operands
+// lie within a factor of two of each other, so the difference is exact).
+__device__ __forceinline__ float u24(uint32_t x)
+{
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, x, 9u)) - 0x1.fffffep-1f;
+}
 
 __host__ __device__ __forceinline__ double u53(uint32_t lo, uint32_t hi)
 {
