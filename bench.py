@@ -42,10 +42,10 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_amd/csrc/pf_kernel.h",
                   "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h",
                   "paper_2311_12973_amd/build.py"]
-KERNEL_SHA = "1f81db080fc0dc9e"
+KERNEL_SHA = "35952fdc1a70dab8"
 PROFILED_WORKLOAD = "seir"
-VALU_LANE_INSTR_PER_PSTEP = 1437.6
-HBM_BYTES_PER_LAUNCH = 1.0383e6
+VALU_LANE_INSTR_PER_PSTEP = 1427.3
+HBM_BYTES_PER_LAUNCH = 1.0342e6
 
 
 def kernel_sha():

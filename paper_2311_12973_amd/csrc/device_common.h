@@ -209,6 +209,25 @@ enum : int { BTRS_OUT = 0, BTRS_ACCEPT = 1, BTRS_FINAL = 2 };
 
 // One attempt from the uniform words (wu, wv): the candidate k, and whether it lies
 // outside [0, n], is accepted by the squeeze, or needs the final test.
+// a / b correctly rounded, for positive normal operands whose quotient needs no range
+// scaling: a >= 2^-100, b in [2^-100, 2^100], a / b below 2^100. Then the scale steps of
+// the general division sequence leave the operands unchanged and its fix-up step passes
+// the value through, so the core below (reciprocal, one Newton step, quotient, two
+// residual corrections, all FMAs) gives the same bits as the general division.
+__device__ __forceinline__ float fdiv_rn_inrange(float a, float b)
+{
+    const float y0 = __builtin_amdgcn_rcpf(b);
+    const float e = fmaf(-b, y0, 1.0f);
+    const float y1 = fmaf(e, y0, y0);
+    const float q0 = a * y1;
+    const float r0 = fmaf(-b, q0, a);
+    const float q1 = fmaf(r0, y1, q0);
+    const float r1 = fmaf(-b, q1, a);
+    return fmaf(r1, y1, q1);
+}
+template <typename real> __device__ __forceinline__ real rdiv_btrs(real a, real b) { return rdiv<real>(a, b); }
+template <> __device__ __forceinline__ float rdiv_btrs<float>(float a, float b) { return fdiv_rn_inrange(a, b); }
+
 template <typename real>
 __device__ __forceinline__ int btrs_try(const BtrsConst<real>& c, int32_t n, uint32_t wu, uint32_t wv, int32_t& k)
 {
@@ -216,7 +235,9 @@ __device__ __forceinline__ int btrs_try(const BtrsConst<real>& c, int32_t n, uin
     const real v = (real)u24(wv);
     const real us = (real)0.5 - (real)fabs((double)u);
     real t = (real)2 * c.aa;
-    t = rdiv<real>(t, us);
+    // in range: 2a with a = -0.0873 + 0.0248 b + 0.01 p in [0.12, 1100] (b = 1.15 + 2.53 sqrt(npq),
+    // npq > 9, n < 2^30), over us in [2^-24, 1/2]
+    t = rdiv_btrs<real>(t, us);
     t = t + c.bb;
     t = t * u;
     t = t + c.cf;
