@@ -79,16 +79,21 @@ extern "C" {
 #define SMC2_PRIOR_LOGITNORMAL 2 /* theta_d = logistic(phi_d), phi_d ~ N(a, b^2) */
 #define SMC2_PRIOR_NORMAL 3      /* theta_d = phi_d ~ N(a, b^2)                 */
 
-#define SMC2_L_FORWARD 0   /* L = forward proposal (Sec. IV-D, Eq. aimplified_l_weights) */
-#define SMC2_L_GAUSS_OPT 1 /* approximately optimal Gaussian L-kernel (Sec. IV-D)        */
+/* L-kernel of Eq. l_weights. Whenever the Gaussian fit is not used (SMC2_L_FORWARD, or
+ * a rejected fit, reported in the record) L(phi_{k-1} | phi_k) = N(phi_{k-1}; phi_k,
+ * Sigma_RW): for the random walk this is the forward proposal of Sec. IV-D and the
+ * weight is the target ratio (Eq. aimplified_l_weights); for the learned proposal it is
+ * still a normalised density in phi_{k-1}, and the network's log q stays in the weight. */
+#define SMC2_L_FORWARD 0   /* L = the random walk's forward kernel (Sec. IV-D)          */
+#define SMC2_L_GAUSS_OPT 1 /* approximately optimal Gaussian L-kernel (Sec. IV-D)       */
 
 #define SMC2_PROP_RW 0  /* Gaussian random walk on phi (Eq. proposal) */
 #define SMC2_PROP_MLP 1 /* learned Gaussian proposal: a D -> 64 -> 64 -> (mean, Cholesky)
                            network, BF16 matrix-core products, trained after every
                            iteration on the weighted population; its exact density
-                           enters the weights (Eq. l_weights, approximately optimal
-                           L-kernel only); the random walk whenever the network does not
-                           beat it on held-out pairs                                     */
+                           enters the weights (Eq. l_weights, with either L-kernel);
+                           the random walk whenever the network does not beat it on
+                           held-out pairs                                                */
 
 /* particle-filter draw schedule (smc2_config.schedule); both give identical results */
 #define SMC2_SCHED_AUTO 0     /* pooled where supported and it fits in LDS, else per draw */

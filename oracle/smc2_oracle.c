@@ -29,7 +29,11 @@
  *  L-kernel (Sec. IV-D): Gaussian fitted to the pairs (phi_{k-1}^i, phi_k^i) with the
  *  normalised weights of iteration k-1, then conditioned (textbook Gaussian
  *  conditioning): L = N(phi_{k-1}; mu_1 + A (phi_k - mu_2), S), A = S12 S22^-1,
- *  S = S11 - A S21. A failed Cholesky falls back to the forward kernel.
+ *  S = S11 - A S21. The forward-kernel setting, and a rejected fit, use the random
+ *  walk's Gaussian read backwards, L = N(phi_{k-1}; phi_k, Sigma_RW): for the random
+ *  walk this is the paper's forward kernel (the weight becomes the target ratio), and
+ *  for a learned proposal it is still a normalised density in phi_{k-1}, so the
+ *  proposal's own density stays in the weight.
  *
  *  Parameters live on sampler coordinates phi (identity for a uniform prior, log for
  *  a log-normal prior, logit for a logit-normal prior); the proposal, the L-kernel
@@ -529,8 +533,10 @@ static double logsumexp(int n, const double* v)
  * ess_smc2), and, if ESS < N/2, systematic resampling with redistribution and reset
  * (Sec. IV-B). The state arrays (phi, lp, ll, logw) are replaced by the new
  * population. logq (may be NULL: the random walk, whose density the function
- * evaluates) holds log q(phi_new | phi) of a learned proposal; with the forward
- * L-kernel the proposal must be symmetric (the random walk). Records carry, after
+ * evaluates) holds log q(phi_new | phi) of a learned proposal. L is the fitted
+ * Gaussian kernel, or the random walk's Gaussian read backwards when the forward
+ * kernel is configured or the fit is rejected (a normalised density in phi_{k-1}
+ * for any proposal; for the random walk it cancels q exactly). Records carry, after
  * the estimates, the proposal used (0 random walk, 1 learned) and a slot for the
  * caller (the learned proposal's held-out score). Returns 0, or -4 when every
  * weight is zero.
@@ -545,34 +551,46 @@ int or_outer_update(const or_config* cfg, int N, uint32_t k, uint64_t seed,
     if (k == 1) {
         for (int i = 0; i < N; ++i) logw_pre[i] = ll_new[i];
     } else {
+        /* log L - log q per sample. L is the approximately optimal Gaussian kernel when
+           it is configured and its fit succeeds; otherwise (the forward-kernel setting,
+           or a rejected fit) it is the random walk's Gaussian read backwards,
+           L(phi_{k-1} | phi_k) = N(phi_{k-1}; phi_k, Sigma_RW), a normalised density in
+           phi_{k-1} whatever proposal drew phi_k. For the random walk that is its own
+           forward kernel (Sec. IV-D), log L - log q is exactly 0, and the weight is the
+           target ratio of Eq. aimplified_l_weights; for the learned proposal the
+           network's density stays in the weight. */
         double* logL = (double*)calloc((size_t)N, sizeof(double));
-        int use_ratio_only = (cfg->lkernel == OR_L_FORWARD);
+        double C[OR_DMAX * OR_DMAX], Lq[OR_DMAX * OR_DMAX];
+        for (int a = 0; a < D; ++a)
+            for (int c = 0; c < D; ++c) C[a * D + c] = cfg->rw_cov[a][c];
+        or_cholesky(D, C, Lq);
+        int fit = 0;
+        double mu[2 * OR_DMAX], A[OR_DMAX * OR_DMAX], LS[OR_DMAX * OR_DMAX];
         if (cfg->lkernel == OR_L_GAUSS_OPT) {
             double* omega = (double*)malloc(sizeof(double) * (size_t)N);
             double W0 = logsumexp(N, logw);
             for (int i = 0; i < N; ++i) omega[i] = exp(logw[i] - W0);
-            double mu[2 * OR_DMAX], A[OR_DMAX * OR_DMAX], LS[OR_DMAX * OR_DMAX];
-            if (or_lkernel_fit(N, D, phi, phi_new, omega, mu, A, LS) == 0) {
-                double C[OR_DMAX * OR_DMAX], Lq[OR_DMAX * OR_DMAX];
-                for (int a = 0; a < D; ++a)
-                    for (int c = 0; c < D; ++c) C[a * D + c] = cfg->rw_cov[a][c];
-                or_cholesky(D, C, Lq);
-                for (int i = 0; i < N; ++i) {
-                    double m[OR_DMAX];
-                    for (int a = 0; a < D; ++a) {
-                        double s = mu[a];
-                        for (int c = 0; c < D; ++c) s += A[a * D + c] * (phi_new[i * D + c] - mu[D + c]);
-                        m[a] = s;
-                    }
-                    double lL = or_mvn_logpdf_chol(D, phi + (size_t)i * D, m, LS);
-                    double lq = logq ? logq[i] : or_mvn_logpdf_chol(D, phi_new + (size_t)i * D, phi + (size_t)i * D, Lq);
-                    logL[i] = lL - lq;
-                }
-            } else {
-                fallback = 1;
-                use_ratio_only = 1;
-            }
+            fit = or_lkernel_fit(N, D, phi, phi_new, omega, mu, A, LS) == 0;
+            fallback = !fit;
             free(omega);
+        }
+        for (int i = 0; i < N; ++i) {
+            const double* xo = phi + (size_t)i * D;
+            const double* xn = phi_new + (size_t)i * D;
+            double lL;
+            if (fit) {
+                double m[OR_DMAX];
+                for (int a = 0; a < D; ++a) {
+                    double s = mu[a];
+                    for (int c = 0; c < D; ++c) s += A[a * D + c] * (xn[c] - mu[D + c]);
+                    m[a] = s;
+                }
+                lL = or_mvn_logpdf_chol(D, xo, m, LS);
+            } else {
+                lL = or_mvn_logpdf_chol(D, xo, xn, Lq);
+            }
+            double lq = logq ? logq[i] : or_mvn_logpdf_chol(D, xn, xo, Lq);
+            logL[i] = lL - lq;
         }
         for (int i = 0; i < N; ++i) {
             double pin = lp_new[i] + ll_new[i];
@@ -580,8 +598,7 @@ int or_outer_update(const or_config* cfg, int N, uint32_t k, uint64_t seed,
                 logw_pre[i] = -INFINITY;
             } else {
                 double v = (logw[i] + pin) - (lp[i] + ll[i]);
-                if (!use_ratio_only) v = v + logL[i];
-                logw_pre[i] = v;
+                logw_pre[i] = v + logL[i];
             }
         }
         free(logL);

@@ -6,7 +6,8 @@
 //             filter has to run (a zero-weight sample or an out-of-support proposal
 //             keeps weight zero and skips its filter).
 // k_outer     one workgroup per run: approximately optimal Gaussian L-kernel fit and
-//             conditioning (Sec. IV-D), weight update (Eq. l_weights), normalisation,
+//             conditioning (Sec. IV-D; without a usable fit, the random walk's Gaussian
+//             read backwards), weight update (Eq. l_weights), normalisation,
 //             ESS = l_k (Eq. ess_smc2, recycling_I), estimates (Eq. realised_estimates),
 //             integer systematic resampling (Eq. cdf, ncopies) as a prefix-sum search and
 //             redistribution (Alg. 1) as a gather, reset (log w = 0), and the record.
@@ -299,7 +300,12 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
     const bool learned = p.mlp && k >= 2 && uniform_bool(o.mlp_use[r] != 0);
 
     // ---------------- approximately optimal L-kernel (k > 1)
-    bool ratio_only = (p.lkernel == L_FORWARD);
+    // Without a usable fit (forward-kernel setting, or the fit rejected) the backward
+    // kernel is the random walk's Gaussian read backwards, N(phi_{k-1}; phi_k, Sigma_RW):
+    // normalised in phi_{k-1} for any proposal, the forward kernel of the random walk
+    // (whose log q it cancels exactly), and it keeps a learned proposal's density in
+    // the weight.
+    bool use_fit = false;
     int fallback = 0;
     if (k >= 2 && p.lkernel == L_GAUSS_OPT) {
         double m0 = -INFINITY;
@@ -364,10 +370,8 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
             fit_ok = ok;
         }
         __syncthreads();
-        if (!uniform_bool(fit_ok != 0)) {
-            ratio_only = true;
-            fallback = 1;
-        }
+        use_fit = uniform_bool(fit_ok != 0);
+        fallback = use_fit ? 0 : 1;
     }
 
     // ---------------- weight update (Eq. l_weights)
@@ -383,13 +387,15 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
                 v = -INFINITY;
             } else {
                 v = (logw[i] + pin) - (lp[i] + ll[i]);
-                if (!ratio_only) {
-                    double xo[D], xn[D], m[D];
+                double xo[D], xn[D];
 #pragma unroll
-                    for (int a2 = 0; a2 < D; ++a2) {
-                        xo[a2] = phi[(size_t)i * D + a2];
-                        xn[a2] = phin[(size_t)i * D + a2];
-                    }
+                for (int a2 = 0; a2 < D; ++a2) {
+                    xo[a2] = phi[(size_t)i * D + a2];
+                    xn[a2] = phin[(size_t)i * D + a2];
+                }
+                double lL;
+                if (use_fit) {
+                    double m[D];
 #pragma unroll
                     for (int a2 = 0; a2 < D; ++a2) {
                         double s = mu[a2];
@@ -397,10 +403,12 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
                         for (int c = 0; c < D; ++c) s += A[a2 * D + c] * (xn[c] - mu[D + c]);
                         m[a2] = s;
                     }
-                    const double lL = mvn_logpdf<D>(xo, m, LS);
-                    const double lq = learned ? o.logq[base + i] : mvn_logpdf<D>(xn, xo, Lq);
-                    v = v + (lL - lq);
+                    lL = mvn_logpdf<D>(xo, m, LS);
+                } else {
+                    lL = mvn_logpdf<D>(xo, xn, Lq);
                 }
+                const double lq = learned ? o.logq[base + i] : mvn_logpdf<D>(xn, xo, Lq);
+                v = v + (lL - lq);
             }
         }
         lwp[i] = v;

@@ -198,8 +198,6 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
     if (c->precision != SMC2_PREC_FP32 && c->precision != SMC2_PREC_FP64) return m = "bad precision", SMC2_E_ARG;
     if (c->proposal != SMC2_PROP_RW && c->proposal != SMC2_PROP_MLP) return m = "unknown proposal", SMC2_E_UNSUPPORTED;
     if (c->proposal == SMC2_PROP_MLP) {
-        if (c->lkernel != SMC2_L_GAUSS_OPT)
-            return m = "the learned proposal needs the approximately optimal L-kernel", SMC2_E_UNSUPPORTED;
         if (c->mlp_epochs < 0 || c->mlp_epochs > 1000) return m = "mlp_epochs must be in [0, 1000]", SMC2_E_ARG;
         if (c->mlp_batch < 0) return m = "mlp_batch must be >= 0", SMC2_E_ARG;
         if (!(c->mlp_lr > 0.0 && c->mlp_lr < 1.0)) return m = "mlp_lr must be in (0, 1)", SMC2_E_ARG;

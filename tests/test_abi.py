@@ -54,13 +54,14 @@ def test_workspace_bytes_and_validation():
     assert b"positive definite" in L.smc2_last_error(None)
     for r in [dict(T=100, nx=0, seed=1, y=y), dict(T=0, nx=512, seed=1, y=y[:0]), dict(T=100, nx=5000, seed=1, y=y)]:
         assert L.smc2_workspace_bytes(ctypes.byref(cfg), 1, G.make_runs([r])) == 0, r
-    # the learned proposal needs the approximately optimal L-kernel and sane settings
-    for over in [dict(lkernel=G.L_FORWARD), dict(mlp_lr=0.0), dict(mlp_epochs=-1)]:
-        cm = G.make_config(dict(w, proposal=G.PROP_MLP, **{k: v for k, v in over.items() if k != "lkernel"}),
-                           lkernel=over.get("lkernel"))
+    # the learned proposal needs sane settings; it runs with either L-kernel
+    for over in [dict(mlp_lr=0.0), dict(mlp_epochs=-1)]:
+        cm = G.make_config(dict(w, proposal=G.PROP_MLP, **over))
         assert L.smc2_workspace_bytes(ctypes.byref(cm), 1, runs) == 0, over
     cm = G.make_config(dict(w, proposal=G.PROP_MLP))
     assert L.smc2_workspace_bytes(ctypes.byref(cm), 1, runs) > nb  # network state and outputs
+    cf = G.make_config(dict(w, proposal=G.PROP_MLP), lkernel=G.L_FORWARD)
+    assert L.smc2_workspace_bytes(ctypes.byref(cf), 1, runs) == L.smc2_workspace_bytes(ctypes.byref(cm), 1, runs)
     wa = W.preset("age_seir")
     ya = W.observations(dict(wa, T=10))
     ca = G.make_config(wa, schedule=G.SCHED_POOLED)

@@ -120,16 +120,31 @@ def test_training_layouts_agree(batch):
     assert np.abs(a["mlp_params"] - b["mlp_params"]).max() <= 0.05
 
 
-@pytest.mark.parametrize("case", ["seir_d5", "age_seir_d8"])
+@pytest.mark.parametrize("case", ["seir_d5", "age_seir_d8", "seir_d5_n4_fallback", "seir_d5_forward_kernel"])
 def test_learned_proposal_replayed_by_reference(case):
+    """Cases: the learned-proposal workload; the age-structured model (D = 8, the
+    largest network); N = 4, where the 10-dimensional L-kernel fit is always rejected,
+    so every learned step is weighted through the fallback kernel N(phi_{k-1}; phi_k,
+    Sigma_RW) with the network's density; and the forward-kernel setting, which weights
+    every learned step that way."""
+    check_training = True
     if case == "seir_d5":
         w, y = _learned_case()
         N, K, nx = 256, 4, 128
-    else:  # the age-structured model, D = 8 (the largest network)
+    elif case == "age_seir_d8":
         w = dict(W.preset("age_seir"), T=30, mlp_epochs=3, mlp_batch=64, mlp_lr=3e-3)
         y = W.observations(w)
         N, K, nx = 128, 4, 64
+    elif case == "seir_d5_n4_fallback":
+        w, y = _learned_case()
+        N, K, nx = 4, 5, 128
+        check_training = False
+    else:
+        w, y = _learned_case()
+        w = dict(w, lkernel=G.L_FORWARD)
+        N, K, nx = 256, 4, 128
     D = w["D"]
+    fallback_learned = 0
     s = G.Sampler(w, [dict(T=y.shape[0], nx=nx, seed=w["seed"], y=y)], N=N, K=K)
     cfg = O.config_from_workload(w)
     RL = G.record_len(D)
@@ -144,7 +159,8 @@ def test_learned_proposal_replayed_by_reference(case):
         rec = s.records()[k - 1]
         phin, lpn, lln, lwp, anc = (s.dump(x) for x in ("phi_new", "lp_new", "ll_new", "logw_pre", "anc"))
         used = bool(rec[RL - 2])
-        _log("k=%d learned=%d ESS %.1f score %.4g" % (k, used, rec[1], rec[RL - 1]))
+        _log("k=%d learned=%d fallback=%d ESS %.1f score %.4g" % (k, used, int(rec[4]), rec[1], rec[RL - 1]))
+        fallback_learned += int(used and (rec[4] == 1 or w["lkernel"] == G.L_FORWARD))
         lq = None
         if not used:
             assert not s.dump("logq").any(), k  # no learned density at prior or random-walk steps
@@ -168,7 +184,7 @@ def test_learned_proposal_replayed_by_reference(case):
         assert np.array_equal(np.isfinite(lwp), fin)
         assert np.allclose(lwp[fin], lwp_ref[fin], rtol=1e-9, atol=1e-9)
         assert np.array_equal(anc, anc_ref)
-        if k == 1:
+        if k == 1 and check_training:
             # first training, from the common initial weights, on the common population
             pr, m, v = init.copy(), np.zeros_like(init), np.zeros_like(init)
             use_ref, t, fr_ref, nm, nr = O.mlp_train(cfg, st["phi"], st["logw"], w["seed"], 1, pr, m, v, 0)
@@ -185,6 +201,8 @@ def test_learned_proposal_replayed_by_reference(case):
             assert int(state[0]) == use_ref or abs(nm - nr) < 0.05 * abs(nr)
     s.close()
     assert used_any
+    if case in ("seir_d5_n4_fallback", "seir_d5_forward_kernel"):
+        assert fallback_learned >= 1, "no learned step went through the fallback kernel"
 
 
 def _replicates(w, y, prop, N, K, nx, seeds):

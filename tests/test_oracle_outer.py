@@ -131,6 +131,41 @@ def test_forward_kernel_is_target_ratio():
     assert np.array_equal(logw_pre, want)
 
 
+@pytest.mark.parametrize("lkernel,N", [(O.L_GAUSS_OPT, 2), (O.L_GAUSS_OPT, 40), (O.L_FORWARD, 40)])
+def test_fallback_kernel_keeps_the_learned_density(lkernel, N):
+    """Eq. l_weights needs a backward kernel that is a normalised density in
+    theta_{k-1}. When the Gaussian fit is not used (forward-kernel setting, or a fit
+    rejected: at N = 2 the 2D-dimensional covariance has rank one; at N = 40 with one
+    ancestor the previous population is a single point) the kernel is the random
+    walk's Gaussian read backwards, N(phi_{k-1}; phi_k, Sigma_RW), and a learned
+    proposal's log q stays in the weight. Dropping both (the target ratio alone, right
+    only for a symmetric q) fails this."""
+    rng = np.random.default_rng(40 + N + lkernel)
+    D = 2
+    rw = np.array([[0.05, 0.01], [0.01, 0.03]])
+    cfg = _cfg(D, lkernel, rw=rw)
+    st0 = _state(rng, N, D)
+    if N > 2:
+        st0["phi"][:] = st0["phi"][0]
+    st = {k: v.copy() for k, v in st0.items()}
+    phi_new = st0["phi"] + rng.normal(size=(N, D)) * 0.7 + 0.4   # not a random-walk draw
+    lp_new = rng.normal(size=N) - 3
+    ll_new = rng.normal(size=N) * 5 - 100
+    logq = rng.normal(size=N) - 2.0
+    status, logw_pre, anc, rec = O.outer_update(cfg, 3, 5, st, phi_new, lp_new, ll_new, logq=logq)
+    assert status == 0
+    assert rec[4] == (1 if lkernel == O.L_GAUSS_OPT else 0)
+    for i in range(N):
+        logL = stats.multivariate_normal(phi_new[i], rw).logpdf(st0["phi"][i])
+        want = st0["logw"][i] + (lp_new[i] + ll_new[i]) - (st0["lp"][i] + st0["ll"][i]) + logL - logq[i]
+        assert logw_pre[i] == pytest.approx(want, rel=1e-12, abs=1e-10)
+    # the random walk's own density cancels the backward kernel exactly
+    st = {k: v.copy() for k, v in st0.items()}
+    phi_rw, lp_rw = O.propose_rw(cfg, 5, 3, st0["phi"])
+    _, lw_rw, _, rec = O.outer_update(cfg, 3, 5, st, phi_rw, lp_rw, ll_new)
+    assert np.array_equal(lw_rw, (st0["logw"] + (lp_rw + ll_new)) - (st0["lp"] + st0["ll"]))
+
+
 def test_gauss_opt_weights_against_scipy_conditional():
     rng = np.random.default_rng(4)
     N, D = 500, 4
