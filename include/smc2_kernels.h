@@ -51,6 +51,19 @@ size_t smc2_pf_workspace_bytes(const smc2_config* cfg, const smc2_run* run);
 int smc2_pf_loglik(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
                    uint32_t k, double* d_ll, void* d_workspace, size_t ws_bytes, void* hip_stream);
 
+/* smc2_pf_loglik without a workspace, for callers that cannot allocate device memory
+ * (code under HIP graph capture, serving loops, harnesses that forbid allocation): the
+ * run descriptor and the observation series are staged in a static device array of
+ * the library (16640 bytes per device, held until the process ends) instead of
+ * d_workspace. The array covers every valid run (T <= 1024, up to 4 observation series);
+ * a run needing more is rejected with SMC2_E_ARG. Nothing is allocated: no hipMalloc,
+ * hipFree or allocating library call. Results are identical to smc2_pf_loglik's. Like
+ * smc2_pf_loglik the call returns after the stream has run the filters. Every call on
+ * one device shares that device's array: calls that overlap on one device (from
+ * several threads, or on several streams) race and must be serialised by the caller. */
+int smc2_pf_loglik_noalloc(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
+                           uint32_t k, double* d_ll, void* hip_stream);
+
 /* As smc2_pf_loglik, and also writes every filter's per-day log-likelihood
  * increments (d_inc: double[n_theta][T]) and resampling flags (d_rs:
  * int32[n_theta][T]); a filter that dies at day t records -inf at t and 0 after. */

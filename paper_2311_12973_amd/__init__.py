@@ -123,6 +123,8 @@ def lib():
                                           c.c_size_t, vp]
         L.smc2_pf_loglik.restype = c.c_int
         L.smc2_pf_loglik.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp, c.c_size_t, vp]
+        L.smc2_pf_loglik_noalloc.restype = c.c_int
+        L.smc2_pf_loglik_noalloc.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp]
         _lib = L
     return _lib
 
@@ -388,6 +390,21 @@ def pf_loglik(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0,
     _check(L.smc2_pf_trace(ctypes.byref(cfg), n, pth, runs, int(k), pll, pinc, prs, pws, wsb, current_stream()))
     return (from_device(tll, pll, np.float64, n), from_device(tinc, pinc, np.float64, n * T).reshape(n, T),
             from_device(trs, prs, np.int32, n * T).reshape(n, T))
+
+
+def pf_loglik_noalloc(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0, device="cuda", schedule=0):
+    """As pf_loglik through smc2_pf_loglik_noalloc (no workspace: the library stages the
+    run in its static device scratch)."""
+    cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, pf_always=pf_always, block=block,
+                      schedule=schedule)
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
+    runs = make_runs([dict(T=y.shape[0], nx=nx, seed=seed, y=y)])
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    n = theta.shape[0]
+    tth, pth = to_device(theta, device)
+    tll, pll = device_buffer(8 * n, device)
+    _check(lib().smc2_pf_loglik_noalloc(ctypes.byref(cfg), n, pth, runs, int(k), pll, current_stream()))
+    return from_device(tll, pll, np.float64, n)
 
 
 # ------------------------------------------------------------------ learned proposal, kernel level

@@ -1,5 +1,6 @@
 // kernels_api.hip — kernel-level entry points (include/smc2_kernels.h): the
 // building blocks of the sampler on caller-provided device arrays.
+#include <mutex>
 #include <string>
 
 #include "../../include/smc2_kernels.h"
@@ -54,6 +55,13 @@ __global__ void __launch_bounds__(256) k_resample_batch(int n, const uint64_t* q
 
 }  // namespace smc2
 
+// Scratch of smc2_pf_loglik_noalloc: the run descriptor (256 bytes) and the observation
+// series (at most 1024 days x 4 series x 4 bytes), the contents of smc2_pf_loglik's
+// workspace. Host code never names it in a copy or a launch: in host code the name is
+// a host-side stand-in; pf_static_scratch() gives the device address.
+#define PF_STATIC_SCRATCH_BYTES (256 + 1024 * 4 * 4)
+static __device__ __align__(256) unsigned char scratch[PF_STATIC_SCRATCH_BYTES];
+
 using namespace smc2;
 
 // defined in smc2_api.cpp: the thread's message for smc2_last_error(NULL)
@@ -66,6 +74,30 @@ int kfail(int code, const std::string& m)
     return code;
 }
 int n_obs_of(int model) { return model == SMC2_AGE_SEIR ? 4 : 1; }
+
+// Device address of `scratch` on the current device, resolved with that device current
+// on the first call there and kept per device (each device holds its own copy).
+constexpr int SCRATCH_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[SCRATCH_MAX_DEVICES];
+
+hipError_t pf_static_scratch(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 }  // namespace
 
 extern "C" int smc2_philox_batch(int32_t n, const uint32_t* d_ctr, uint64_t seed, uint32_t* d_out, void* stream)
@@ -125,7 +157,7 @@ extern "C" int smc2_pf_loglik(const smc2_config* cfg, int32_t n_theta, const dou
 
 static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run, uint32_t k,
                   double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, void* d_ws, size_t ws_bytes,
-                  void* stream);
+                  void* stream, bool static_ws = false);
 
 extern "C" int smc2_pf_trace(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
                              uint32_t k, double* d_ll, double* d_inc, int32_t* d_rs, void* d_ws, size_t ws_bytes,
@@ -142,9 +174,17 @@ extern "C" int smc2_pf_trace_state(const smc2_config* cfg, int32_t n_theta, cons
     return pf_run(cfg, n_theta, d_theta, run, k, d_ll, d_inc, d_rs, d_state, d_ws, ws_bytes, stream);
 }
 
+extern "C" int smc2_pf_loglik_noalloc(const smc2_config* cfg, int32_t n_theta, const double* d_theta,
+                                      const smc2_run* run, uint32_t k, double* d_ll, void* stream)
+{
+    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, nullptr, nullptr, nullptr, nullptr, 0, stream, true);
+}
+
+// static_ws: the workspace is the file-scope scratch (d_ws and ws_bytes unused); its
+// device address is resolved only after every argument has been checked.
 static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run, uint32_t k,
                   double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, void* d_ws, size_t ws_bytes,
-                  void* stream)
+                  void* stream, bool static_ws)
 {
     if ((d_inc == nullptr) != (d_rs == nullptr)) return kfail(SMC2_E_ARG, "trace needs both d_inc and d_rs");
     if (!cfg || !run || !run->y) return kfail(SMC2_E_ARG, "null config or run");
@@ -158,8 +198,14 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     if (cfg->pf_resampling != SMC2_PF_RS_SYSTEMATIC && cfg->pf_resampling != SMC2_PF_RS_MULTINOMIAL)
         return kfail(SMC2_E_ARG, "pf_resampling must be SMC2_PF_RS_SYSTEMATIC or SMC2_PF_RS_MULTINOMIAL");
     if (n_theta < 0 || (n_theta > 0 && (!d_theta || !d_ll))) return kfail(SMC2_E_ARG, "bad theta/ll");
-    if (!d_ws || ws_bytes < smc2_pf_workspace_bytes(cfg, run) || ((uintptr_t)d_ws & 255u))
+    if (static_ws) {
+        const size_t need = smc2_pf_workspace_bytes(cfg, run);
+        if (need > PF_STATIC_SCRATCH_BYTES)
+            return kfail(SMC2_E_ARG, "run needs " + std::to_string(need) + " bytes of scratch; the static scratch holds " +
+                                         std::to_string(PF_STATIC_SCRATCH_BYTES));
+    } else if (!d_ws || ws_bytes < smc2_pf_workspace_bytes(cfg, run) || ((uintptr_t)d_ws & 255u)) {
         return kfail(SMC2_E_ARG, "workspace missing, too small or not 256-byte aligned");
+    }
     if (cfg->n_fixed < 0 || cfg->n_fixed > SMC2_NFIXED || (cfg->n_fixed > 0 && !cfg->fixed))
         return kfail(SMC2_E_ARG, "bad fixed constants");
     const int no = n_obs_of(cfg->model);
@@ -175,6 +221,10 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     const size_t lds = pf_lds_bytes(cfg->model, cfg->precision, block, run->n_x, run->T, sched);
     if (lds > PF_LDS_MAX) return kfail(SMC2_E_ARG, "particle filter does not fit in LDS");
     if (n_theta == 0) return SMC2_OK;
+    if (static_ws) {
+        const hipError_t es = pf_static_scratch(&d_ws);
+        if (es != hipSuccess) return kfail(SMC2_E_DEVICE, hipGetErrorString(es));
+    }
     hipStream_t s = (hipStream_t)stream;
     unsigned char* w = (unsigned char*)d_ws;
     // every argument is checked before the first copy: from here on the host copies of rd
