@@ -128,3 +128,77 @@ def sir_grid_loglik(betas, gammas, n_pop, i0, y, obs=POIS_PREV):
             logZ += np.log(z)
             alpha = np.where(z[:, None, None] > 0, new / np.where(z > 0, z, 1.0)[:, None, None], 0.0)
     return logZ.reshape(len(betas), len(gammas))
+
+
+def _group_states(n):
+    """Every (S, E, I) with S + E + I <= n (R implied), and their index."""
+    st = [(S, E, I) for S in range(n + 1) for E in range(n + 1 - S) for I in range(n + 1 - S - E)]
+    return st, {s: a for a, s in enumerate(st)}
+
+
+def age_seir_loglik_coef(A, group_sizes, i0, sigma, gamma, y, r):
+    """log p(y | theta) for the four-group chain-binomial SEIR whose per-susceptible
+    daily infection probability in group g is 1 - exp(-lambda_g) with
+    lambda_g = sum_h A[g, h] I_h (previous day's infected), E->I and I->R as in the
+    one-group SEIR, and y[t, g] ~ NB(mean = new cases E->I of group g, dispersion r).
+    Groups are independent given the previous day's joint state, so one day's
+    transition of the joint distribution is sum_x alpha(x) prod_g K_g(x, x'_g), with
+    K_g the group's flow probabilities times its observation pmf."""
+    A = np.asarray(A, dtype=np.float64)
+    G = len(group_sizes)
+    sts, idx = zip(*[_group_states(int(n)) for n in group_sizes])
+    dims = [len(s) for s in sts]
+    X = int(np.prod(dims))
+    # own-state index of every joint state, per group, and that state's counts
+    own = np.indices(dims).reshape(G, X)
+    Icnt = [np.array([s[2] for s in sts[g]])[own[g]] for g in range(G)]
+    p_ei = -math.expm1(-sigma)
+    p_ir = -math.expm1(-gamma)
+    alpha = np.zeros(X)
+    start = [idx[g][(int(group_sizes[g]) - int(i0[g]), 0, int(i0[g]))] for g in range(G)]
+    alpha[np.ravel_multi_index(start, dims)] = 1.0
+    logZ = 0.0
+    for yt in np.asarray(y).reshape(-1, G):
+        lam = [sum(A[g, h] * Icnt[h] for h in range(G)) for g in range(G)]
+        K = []
+        for g in range(G):
+            Kg = np.zeros((X, dims[g]))
+            p_se = -np.expm1(-lam[g])
+            for a, (S, E, I) in enumerate(sts[g]):
+                rows = np.flatnonzero(own[g] == a)
+                f1 = stats.binom.pmf(np.arange(S + 1)[None, :], S, p_se[rows][:, None])
+                f2 = stats.binom.pmf(np.arange(E + 1), E, p_ei)
+                f3 = stats.binom.pmf(np.arange(I + 1), I, p_ir)
+                obs = _obs_pmf(NB_INC, int(yt[g]), np.arange(E + 1), r)
+                for nse in range(S + 1):
+                    for nei in range(E + 1):
+                        for nir in range(I + 1):
+                            c = f2[nei] * f3[nir] * obs[nei]
+                            if c == 0.0:
+                                continue
+                            b = idx[g][(S - nse, E + nse - nei, I + nei - nir)]
+                            Kg[rows, b] += f1[:, nse] * c
+            K.append(Kg)
+        new = np.zeros((dims[0] * dims[1], dims[2] * dims[3]))
+        live = np.flatnonzero(alpha)
+        for c0 in range(0, live.size, 4096):
+            x = live[c0:c0 + 4096]
+            m12 = (alpha[x, None, None] * K[0][x, :, None] * K[1][x, None, :]).reshape(x.size, -1)
+            m34 = (K[2][x, :, None] * K[3][x, None, :]).reshape(x.size, -1)
+            new += m12.T @ m34
+        z = new.sum()
+        if z == 0.0:
+            return -np.inf
+        logZ += math.log(z)
+        alpha = new.reshape(-1) / z
+    return logZ
+
+
+def age_seir_loglik(beta, s, C, group_sizes, i0, sigma, gamma, y, r):
+    """The age-structured SEIR's exact log-likelihood with the force of infection
+    lambda_g = beta s_g sum_h C[g, h] I_h / N_h (susceptibility of the receiving group,
+    contacts of g with h, prevalence in h)."""
+    s = np.asarray(s, dtype=np.float64)
+    N = np.asarray(group_sizes, dtype=np.float64)
+    A = beta * s[:, None] * np.asarray(C, dtype=np.float64) / N[None, :]
+    return age_seir_loglik_coef(A, group_sizes, i0, sigma, gamma, y, r)

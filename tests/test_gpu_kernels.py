@@ -292,3 +292,34 @@ def test_pooled_schedule_rejected_for_age_model():
     y = W.observations(w)
     with pytest.raises(RuntimeError):
         G.pf_loglik(w, np.array([w["truth"]] * 2), y, 64, seed=1, k=1, schedule=G.SCHED_POOLED)
+
+
+@pytest.mark.parametrize("prec", [G.PREC_FP64, G.PREC_FP32])
+def test_pf_age_seir_unequal_groups_matches_oracle(prec):
+    """The age model's force of infection with unequal groups and a non-symmetric contact
+    matrix: the enumerable four-group population of the reference's exact pin (sizes 3,
+    3, 2, 2), and a large population with group fractions 0.4, 0.3, 0.2, 0.1 (the
+    workloads use equal groups, where N_g and N_h coincide)."""
+    from tests.test_oracle_pf_exact import AGE_THETA, age_pin_case
+    cfg_small, y_small, _ = age_pin_case(prec)
+    wa = W.preset("age_seir")
+    fixed = list(np.asarray(wa["fixed"][:16])) + [0.4, 0.3, 0.2, 0.1]
+    cases = [(dict(wa, n_pop=float(sum([3, 3, 2, 2])), fixed=[cfg_small.fixed[i] for i in range(20)]), y_small,
+              np.tile(AGE_THETA, (64, 1)) * np.exp(np.random.default_rng(1).normal(0, 0.1, (64, 8))), 32),
+             (dict(wa, fixed=fixed, T=60), None, None, 256)]
+    for w, y, theta, nx in cases:
+        if y is None:
+            y = W.observations(w)
+            rng = np.random.default_rng(2)
+            theta = np.array(w["truth"]) * np.exp(rng.normal(0, 0.15, size=(24, 8)))
+            theta[:, 3] = np.clip(theta[:, 3], 1e-7, 1e-3)
+        _log("age unequal groups n_pop=%g nx=%d prec=%d" % (w["n_pop"], nx, prec))
+        got = G.pf_loglik(w, theta, y, nx, seed=13, k=2, precision=prec)
+        cfg = O.config_from_workload(w, prec=prec)
+        want = np.array([O.pf_loglik(cfg, theta[i], y, nx, 13, i, 2) for i in range(len(theta))])
+        fin = np.isfinite(want)
+        assert fin.sum() >= len(theta) // 2
+        assert np.array_equal(np.isfinite(got), fin)
+        rel = np.abs(got[fin] - want[fin]) / np.abs(want[fin])
+        _log("  max rel err %.3g" % rel.max())
+        assert rel.max() <= (1e-12 if prec == G.PREC_FP64 else 1e-4)

@@ -44,16 +44,20 @@ def test_kalman_reference_on_a_hand_case():
     assert ll == pytest.approx(-0.5 * (np.log(2 * np.pi * var) + (0.7 - 0.5) ** 2 / var), rel=1e-14)
 
 
+def kalman_pin_statistic(pf_always=0, resampling=O.RS_SYSTEMATIC, M=2000):
+    """Mean and standard error of exp(ll - ll_Kalman) over M independent filters."""
+    y = simulate(25, 11)
+    ref = kalman_loglik(PHI, SQ, SR, M0, S0, y)
+    r = np.array([np.exp(O.pf_lg(PHI, SQ, SR, M0, S0, y, 64, 7, filt=f, pf_always=pf_always,
+                                 resampling=resampling) - ref) for f in range(M)])
+    return r.mean(), r.std(ddof=1) / np.sqrt(M)
+
+
 @pytest.mark.parametrize("resampling", [O.RS_SYSTEMATIC, O.RS_MULTINOMIAL])
 @pytest.mark.parametrize("pf_always", [0, 1])
 def test_likelihood_estimate_is_unbiased(pf_always, resampling):
-    y = simulate(25, 11)
-    ref = kalman_loglik(PHI, SQ, SR, M0, S0, y)
-    M = 2000
-    r = np.array([np.exp(O.pf_lg(PHI, SQ, SR, M0, S0, y, 64, 7, filt=f, pf_always=pf_always,
-                                 resampling=resampling) - ref) for f in range(M)])
-    se = r.std(ddof=1) / np.sqrt(M)
-    assert abs(r.mean() - 1.0) < 4 * se + 1e-3, (r.mean(), se)
+    mean, se = kalman_pin_statistic(pf_always, resampling)
+    assert abs(mean - 1.0) < 4 * se + 1e-3, (mean, se)
 
 
 def test_large_filter_converges_to_the_exact_likelihood():

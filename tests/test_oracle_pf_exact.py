@@ -110,6 +110,57 @@ def test_age_seir_reduces_to_independent_seir():
     assert abs(mean - 1.0) < 4 * se, (mean, se)
 
 
+# A four-group population small enough to enumerate (group sizes 3, 3, 2, 2: 40000 joint
+# states), a contact matrix far from symmetric, unequal groups and distinct
+# susceptibilities, so that a transposed C, N_g in place of N_h or s_h in place of s_g
+# changes log Z by 0.25 to 0.72 on this data series (checked in the test).
+AGE_C = np.array([[0.2, 1.8, 0.1, 0.4], [0.3, 0.2, 1.2, 0.1], [1.5, 0.1, 0.3, 0.2], [0.1, 0.9, 2.2, 0.2]])
+AGE_GROUPS = [3, 3, 2, 2]
+AGE_S = [1.0, 0.4, 2.2, 0.7]
+AGE_THETA = np.array([1.3, 0.7, 0.3, 0.01, 3.0] + AGE_S[1:])  # beta sigma gamma iota r s2 s3 s4
+
+
+def age_pin_case(prec=O.PREC_FP64):
+    """Config, theta, data and exact log Z of the age-structured pin; I_0 = 1 per group
+    (iota N_g rounds to 0 and is raised to one infected)."""
+    n_pop = sum(AGE_GROUPS)
+    fixed = list(AGE_C.ravel()) + [g / n_pop for g in AGE_GROUPS]
+    y = W.simulate(W.AGE_SEIR, W.OBS_NB_INC, n_pop, AGE_THETA, 5, seed=5, fixed=fixed, min_frac=0)
+    beta, sigma, gamma, _, r = AGE_THETA[:5]
+    logZ = X.age_seir_loglik(beta, AGE_S, AGE_C, AGE_GROUPS, [1] * 4, sigma, gamma, y, r)
+    cfg = O.make_config(O.AGE_SEIR, O.OBS_NB_INC, 8, prec, n_pop, [[1, 0, 1]] * 8, np.eye(8), fixed)
+    return cfg, y, logZ
+
+
+def age_pin_statistic(prec=O.PREC_FP64, M=4000):
+    """Mean and standard error of exp(ll - log Z) over M independent filters."""
+    cfg, y, logZ = age_pin_case(prec)
+    mean, se, _ = _unbiased(cfg, AGE_THETA, y, logZ, nx=32, M=M)
+    return mean, se
+
+
+def test_age_seir_exact_likelihood_is_sensitive_to_the_coupling():
+    """The exact likelihood itself tells the force of infection
+    lambda_g = beta s_g sum_h C_gh I_h / N_h apart from its plausible misreadings."""
+    _, y, logZ = age_pin_case()
+    assert np.isfinite(logZ) and y.sum() >= 3
+    beta, sigma, gamma, _, r = AGE_THETA[:5]
+    s, N = np.array(AGE_S), np.array(AGE_GROUPS, dtype=float)
+    for A in (beta * s[:, None] * AGE_C.T / N[None, :],   # transposed contact matrix
+              beta * s[:, None] * AGE_C / N[:, None],     # size of the receiving group
+              beta * s[None, :] * AGE_C / N[None, :]):    # susceptibility of the source
+        assert abs(X.age_seir_loglik_coef(A, AGE_GROUPS, [1] * 4, sigma, gamma, y, r) - logZ) > 0.2
+
+
+@pytest.mark.parametrize("prec", [O.PREC_FP64, O.PREC_FP32])
+def test_age_seir_pf_unbiased_with_a_nonsymmetric_contact_matrix(prec):
+    """The age-structured filter (Sec. V-A chain binomial, four coupled groups) is
+    unbiased for the exact likelihood of the enumerated model."""
+    mean, se = age_pin_statistic(prec)
+    assert se < 0.03
+    assert abs(mean - 1.0) < 4 * se, (mean, se)
+
+
 def test_dead_filter_returns_minus_inf():
     # Poisson on new cases with an observation that no trajectory can produce
     y = np.array([[0], [0], [500]], dtype=np.int32)

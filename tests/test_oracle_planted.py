@@ -1,0 +1,66 @@
+"""Each pin catches the mistakes it is there for: copies of the CPU reference with one
+plausible mistake planted (tests/planted.py) fail the pin that the reference passes.
+
+* The age-structured force of infection lambda_g = beta s_g sum_h C_gh I_h / N_h
+  (exact enumeration of a four-group population with a non-symmetric contact matrix,
+  unequal groups and distinct susceptibilities): a transposed C, N_g in place of N_h,
+  and s_h in place of s_g.
+* The filter's weight recursion and likelihood increment (Sec. II, with the mean-weight
+  reset after resampling) against the Kalman filter: a dropped log S_prev, S_prev not
+  updated, no weight reset after resampling, log-weights not re-based on the maximum,
+  and ancestors shifted by one slot.
+"""
+import concurrent.futures as cf
+
+import pytest
+
+from tests import planted as PL
+from tests.test_oracle_kalman import kalman_pin_statistic
+from tests.test_oracle_pf_exact import age_pin_statistic
+
+COEF = "mc.cs[g][h] = (REAL)(((beta * s[g]) * cfg->fixed[4 * g + h]) / ngs[h]);"
+AGE_PLANTS = {
+    "transposed_contact_matrix": [("pf_real.inc", COEF, COEF.replace("fixed[4 * g + h]", "fixed[4 * h + g]"))],
+    "receiving_group_size": [("pf_real.inc", COEF, COEF.replace("/ ngs[h]", "/ ngs[g]"))],
+    "source_susceptibility": [("pf_real.inc", COEF, COEF.replace("s[g])", "s[h])"))],
+}
+KALMAN_PLANTS = {
+    "dropped_log_s_prev": [("pf_real.inc", "*inc = (((double)m + log(S)) - log(*s_prev)) + cst;",
+                            "*inc = ((double)m + log(S)) + cst;")],
+    "s_prev_not_updated": [("pf_real.inc", "    *s_prev = S;\n", "")],
+    "no_weight_reset": [("pf_real.inc", "    for (int jj = 0; jj < nx; ++jj) lw[jj] = (REAL)0;\n", "")],
+    "not_rebased_on_max": [("pf_real.inc", "lw[jj] = a[jj] - m;", "lw[jj] = a[jj];")],
+    "ancestors_shifted": [("smc2_oracle.c", "        anc[m] = j;", "        anc[m] = j + 1 < n ? j + 1 : j;")],
+}
+
+
+@pytest.fixture(scope="module")
+def planted_libs(tmp_path_factory):
+    d = str(tmp_path_factory.mktemp("planted"))
+    plants = dict(AGE_PLANTS, **KALMAN_PLANTS)
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        futs = {name: ex.submit(PL.build_planted, name, edits, d) for name, edits in plants.items()}
+        return {name: f.result() for name, f in futs.items()}
+
+
+def test_the_reference_passes_both_pins():
+    mean, se = age_pin_statistic()
+    assert abs(mean - 1.0) < 4 * se, (mean, se)
+    mean, se = kalman_pin_statistic()
+    assert abs(mean - 1.0) < 4 * se + 1e-3, (mean, se)
+
+
+@pytest.mark.parametrize("name", sorted(AGE_PLANTS))
+def test_age_pin_catches_a_misread_force_of_infection(planted_libs, name):
+    with PL.installed(planted_libs[name]):
+        mean, se = age_pin_statistic()
+    print(name, mean, se)
+    assert abs(mean - 1.0) > 4 * se, (name, mean, se)
+
+
+@pytest.mark.parametrize("name", sorted(KALMAN_PLANTS))
+def test_kalman_pin_catches_a_broken_weight_recursion(planted_libs, name):
+    with PL.installed(planted_libs[name]):
+        mean, se = kalman_pin_statistic()
+    print(name, mean, se)
+    assert abs(mean - 1.0) > 4 * se + 1e-3, (name, mean, se)
