@@ -184,6 +184,14 @@ typedef struct {
 #define SMC2_DUMP_LL_NEW 6   /* N      doubles: their particle-filter log-likelihoods      */
 #define SMC2_DUMP_LOGW_PRE 7 /* N      doubles: log-weights before resampling              */
 #define SMC2_DUMP_ANC 8      /* N      int32:   ancestors chosen (identity if no resampling) */
+#define SMC2_DUMP_PSTEPS 15  /* 1      uint64:  particle-steps the run's filters executed since
+                                smc2_init: N_x x the days each active filter ran (a filter
+                                whose weights all vanish stops that day; inactive samples,
+                                with zero weight or outside the prior's support, run none) */
+#define SMC2_DUMP_LKFIT 16   /* 2D + 4D^2 doubles: moments of the last approximately optimal
+                                L-kernel fit (Sec. IV-D), the weighted mean of the pairs
+                                (phi_{k-1}, phi_k) then their weighted covariance (row-major,
+                                2D x 2D); zero before the first fit */
 /* learned proposal (SMC2_PROP_MLP only) */
 #define SMC2_DUMP_MLP_OUT 9     /* N x P  float: network outputs at the population the
                                    last step proposed from (P = D + D(D+1)/2)            */

@@ -72,10 +72,14 @@ int smc2_pf_trace(const smc2_config* cfg, int32_t n_theta, const double* d_theta
 
 /* As smc2_pf_trace, and also writes every filter's particle counts of each day
  * before resampling (d_state: int32[n_theta][T][n_counts][n_x], n_counts = 2 / 3 / 12
- * for SIR / SEIR / age-structured SEIR). */
+ * for SIR / SEIR / age-structured SEIR) and, when d_anc is not NULL, the ancestors
+ * chosen after each day (d_anc: int32[n_theta][T][n_x]; the identity on days without
+ * resampling; rows after a filter's death day are left unwritten). Together with d_rs
+ * these are the filter's integer decisions, from which an FP64 replay of Sec. II's
+ * weights recomputes its likelihood estimate. */
 int smc2_pf_trace_state(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
-                        uint32_t k, double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, void* d_workspace,
-                        size_t ws_bytes, void* hip_stream);
+                        uint32_t k, double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, int32_t* d_anc,
+                        void* d_workspace, size_t ws_bytes, void* hip_stream);
 
 /* Learned proposal, network outputs (SMC2_PROP_MLP). d_params: FP32 weights in the
  * layout of SMC2_DUMP_MLP_PARAMS for dimension D (1..8); d_frame: D + D*D doubles

@@ -85,6 +85,8 @@ def _declare(L):
     L.or_mvn_logpdf_chol.argtypes = [c.c_int, P(c.c_double), P(c.c_double), P(c.c_double)]
     L.or_lkernel_fit.restype = c.c_int
     L.or_lkernel_fit.argtypes = [c.c_int, c.c_int] + [P(c.c_double)] * 6
+    L.or_lkernel_fit_cov.restype = c.c_int
+    L.or_lkernel_fit_cov.argtypes = [c.c_int, c.c_int] + [P(c.c_double)] * 7
     L.or_prior_logpdf.restype = c.c_double
     L.or_prior_logpdf.argtypes = [P(Config), P(c.c_double)]
     L.or_theta_of_phi.argtypes = [P(Config), P(c.c_double), P(c.c_double)]
@@ -95,6 +97,13 @@ def _declare(L):
     L.or_pf_trace_state.restype = c.c_double
     L.or_pf_trace_state.argtypes = [P(Config), P(c.c_double), P(c.c_int32), c.c_int, c.c_int, c.c_uint64,
                                     c.c_uint32, c.c_uint32, P(c.c_double), P(c.c_int32), P(c.c_int32)]
+    L.or_pf_trace_full.restype = c.c_double
+    L.or_pf_trace_full.argtypes = [P(Config), P(c.c_double), P(c.c_int32), c.c_int, c.c_int, c.c_uint64,
+                                   c.c_uint32, c.c_uint32, P(c.c_double), P(c.c_int32), P(c.c_int32),
+                                   P(c.c_int32)]
+    L.or_pf_replay.restype = c.c_double
+    L.or_pf_replay.argtypes = [P(Config), P(c.c_double), P(c.c_int32), c.c_int, c.c_int, P(c.c_int32),
+                               P(c.c_int32), P(c.c_int32), P(c.c_double)]
     L.or_prior_draw.argtypes = [P(Config), c.c_int, c.c_uint64, P(c.c_double), P(c.c_double)]
     L.or_propose_rw.argtypes = [P(Config), c.c_int, c.c_uint64, c.c_uint32, P(c.c_double),
                                 P(c.c_double), P(c.c_double)]
@@ -252,6 +261,22 @@ def lkernel_fit(phi, phi_new, omega):
     return st, mu, A, LS
 
 
+def lkernel_fit_cov(phi, phi_new, omega):
+    """(status, mu[2D], cov[2D][2D]) of the L-kernel fit's weighted moments."""
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    phi_new = np.ascontiguousarray(phi_new, dtype=np.float64)
+    omega = np.ascontiguousarray(omega, dtype=np.float64)
+    N, D = phi.shape
+    mu = np.zeros(2 * D)
+    A = np.zeros((D, D))
+    LS = np.zeros((D, D))
+    cov = np.zeros((2 * D, 2 * D))
+    st = lib().or_lkernel_fit_cov(N, D, _p(phi, ctypes.c_double), _p(phi_new, ctypes.c_double),
+                                  _p(omega, ctypes.c_double), _p(mu, ctypes.c_double), _p(A, ctypes.c_double),
+                                  _p(LS, ctypes.c_double), _p(cov, ctypes.c_double))
+    return st, mu, cov
+
+
 def prior_logpdf(cfg, phi):
     phi = np.ascontiguousarray(phi, dtype=np.float64)
     return lib().or_prior_logpdf(ctypes.byref(cfg), _p(phi, ctypes.c_double))
@@ -305,6 +330,38 @@ def pf_trace_state(cfg, theta, y, nx, seed, filt, k):
                                  int(seed), int(filt), int(k), _p(inc, ctypes.c_double), _p(rs, ctypes.c_int32),
                                  _p(st, ctypes.c_int32))
     return ll, inc, rs, st
+
+
+def pf_trace_full(cfg, theta, y, nx, seed, filt, k):
+    """(ll, inc[T], rs[T], state[T][n_counts][nx], anc[T][nx]) of one filter."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    T = y.shape[0]
+    nc = {SIR: 2, SEIR: 3, AGE_SEIR: 12}[cfg.model]
+    inc = np.zeros(T)
+    rs = np.zeros(T, dtype=np.int32)
+    st = np.zeros((T, nc, nx), dtype=np.int32)
+    anc = np.zeros((T, nx), dtype=np.int32)
+    ll = lib().or_pf_trace_full(ctypes.byref(cfg), _p(theta, ctypes.c_double), _p(y, ctypes.c_int32), T, nx,
+                                int(seed), int(filt), int(k), _p(inc, ctypes.c_double), _p(rs, ctypes.c_int32),
+                                _p(st, ctypes.c_int32), _p(anc, ctypes.c_int32))
+    return ll, inc, rs, st, anc
+
+
+def pf_replay(cfg, theta, y, state, anc, rs):
+    """FP64 log-likelihood (and per-day increments) of a filter replayed from another
+    implementation's integer decisions: state [T][n_counts][nx], anc [T][nx], rs [T]."""
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    state = np.ascontiguousarray(state, dtype=np.int32)
+    anc = np.ascontiguousarray(anc, dtype=np.int32)
+    rs = np.ascontiguousarray(rs, dtype=np.int32)
+    T, nc, nx = state.shape
+    inc = np.zeros(T)
+    ll = lib().or_pf_replay(ctypes.byref(cfg), _p(theta, ctypes.c_double), _p(y, ctypes.c_int32), T, nx,
+                            _p(state, ctypes.c_int32), _p(anc, ctypes.c_int32), _p(rs, ctypes.c_int32),
+                            _p(inc, ctypes.c_double))
+    return ll, inc
 
 
 def prior_draw(cfg, N, seed):

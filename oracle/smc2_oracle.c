@@ -222,6 +222,12 @@ static void chol_solve(int n, const double* L, double* b)
 int or_lkernel_fit(int N, int D, const double* phi, const double* phi_new, const double* omega,
                    double* mu, double* A, double* LS)
 {
+    return or_lkernel_fit_cov(N, D, phi, phi_new, omega, mu, A, LS, NULL);
+}
+
+int or_lkernel_fit_cov(int N, int D, const double* phi, const double* phi_new, const double* omega,
+                       double* mu, double* A, double* LS, double* cov_out)
+{
     const int D2 = 2 * D;
     double cov[4 * OR_DMAX * OR_DMAX];
     for (int a = 0; a < D2; ++a) mu[a] = 0.0;
@@ -237,6 +243,8 @@ int or_lkernel_fit(int N, int D, const double* phi, const double* phi_new, const
         for (int a = 0; a < D2; ++a)
             for (int c = 0; c < D2; ++c) cov[a * D2 + c] += omega[i] * z[a] * z[c];
     }
+    if (cov_out)
+        for (int a = 0; a < D2 * D2; ++a) cov_out[a] = cov[a];
     /* Numerical-rank floor: a Cholesky pivot of coordinate a must exceed
        OR_LK_REL_FLOOR times that coordinate's raw second moment cov_aa + mu_a^2 (the
        scale of the rounding error of a variance computed from the samples); a fit
@@ -406,6 +414,39 @@ void or_events_reset(void)
 
 /* ------------------------------------------------------------------ particle filters */
 
+/* The deterministic initial state x_0 of every particle (Sec. V-A: the initially
+ * infected, the rest susceptible; SEIR models start with I_0 = round(iota N), at least
+ * one and at most N, per group for the age-structured model, whose group sizes are
+ * round(fraction N_pop)) and the negative-binomial dispersion r (0 where unused). */
+static double or_model_start(const or_config* cfg, const double* th, int32_t* x0)
+{
+    if (cfg->model == OR_SIR) {
+        int32_t i0 = (int32_t)cfg->fixed[0];
+        x0[0] = (int32_t)cfg->n_pop - i0;
+        x0[1] = i0;
+        return 0.0;
+    }
+    if (cfg->model == OR_SEIR) {
+        double i0 = floor(th[3] * cfg->n_pop + 0.5);
+        if (i0 < 1.0) i0 = 1.0;
+        if (i0 > cfg->n_pop) i0 = cfg->n_pop;
+        x0[0] = (int32_t)(cfg->n_pop - i0);
+        x0[1] = 0;
+        x0[2] = (int32_t)i0;
+        return (cfg->D >= 5) ? th[4] : cfg->fixed[0];
+    }
+    for (int g = 0; g < 4; ++g) {
+        double ng = floor(cfg->fixed[16 + g] * cfg->n_pop + 0.5);
+        double i0 = floor(th[3] * ng + 0.5);
+        if (i0 < 1.0) i0 = 1.0;
+        if (i0 > ng) i0 = ng;
+        x0[3 * g] = (int32_t)(ng - i0);
+        x0[3 * g + 1] = 0;
+        x0[3 * g + 2] = (int32_t)i0;
+    }
+    return th[4];
+}
+
 #define REAL float
 #define FN(x) x##_f32
 #include "pf_real.inc"
@@ -502,8 +543,81 @@ double or_pf_trace_state(const or_config* cfg, const double* theta, const int32_
                          uint64_t seed, uint32_t filt, uint32_t k, double* inc_out, int32_t* rs_out,
                          int32_t* state_out)
 {
-    if (cfg->prec == OR_PREC_FP32) return pf_f32(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out, state_out);
-    return pf_f64(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out, state_out);
+    return or_pf_trace_full(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out, state_out, NULL);
+}
+
+double or_pf_trace_full(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx,
+                        uint64_t seed, uint32_t filt, uint32_t k, double* inc_out, int32_t* rs_out,
+                        int32_t* state_out, int32_t* anc_out)
+{
+    if (cfg->prec == OR_PREC_FP32)
+        return pf_f32(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out, state_out, anc_out);
+    return pf_f64(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out, state_out, anc_out);
+}
+
+/*
+ * The log-likelihood estimate of one filter recomputed in FP64 from another
+ * implementation's integer decisions (Sec. II, injected trajectory):
+ *   state[t][c][j]  counts of particle j after day t+1's transitions, before resampling
+ *   anc[t][j]       ancestor of slot j after day t+1 (read only where rs[t] = 1)
+ *   rs[t]           1 where the filter resampled after day t+1
+ * The count each observation looks at follows from a particle's counts and those it
+ * started the day from (x_0, or the previous day's counts of its ancestor): the new
+ * cases leave S (SIR) or S + E (SEIR models) and nothing else does. Weights,
+ * increments and the mean-weight reset after resampling are those of the filter, in
+ * FP64. inc_out (may be NULL) receives the per-day increments. Returns the
+ * log-likelihood, -inf when every weight vanishes.
+ */
+double or_pf_replay(const or_config* cfg, const double* th, const int32_t* y, int T, int nx,
+                    const int32_t* state, const int32_t* anc, const int32_t* rs, double* inc_out)
+{
+    const int nc = (cfg->model == OR_SIR) ? 2 : (cfg->model == OR_SEIR ? 3 : 12);
+    const int ng = or_n_obs(cfg->model);
+    int32_t x0[12];
+    const double r = or_model_start(cfg, th, x0);
+    double* lw = (double*)malloc(sizeof(double) * (size_t)nx);
+    double* a = (double*)malloc(sizeof(double) * (size_t)nx);
+    double* w = (double*)malloc(sizeof(double) * (size_t)nx);
+    uint64_t* qq = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)nx);
+    int32_t* unused = (int32_t*)malloc(sizeof(int32_t) * (size_t)nx);
+    for (int j = 0; j < nx; ++j) lw[j] = 0.0;
+    double s_prev = (double)nx, ll = 0.0;
+    for (int t = 0; t < T; ++t) {
+        const int32_t* cur = state + (size_t)t * nc * nx;
+        double cst = 0.0;
+        for (int g = 0; g < ng; ++g) cst = cst + or_obs_const(cfg->obs, y[t * ng + g], r);
+        for (int j = 0; j < nx; ++j) {
+            int32_t prev[12];
+            const int from = (t > 0 && rs[t - 1]) ? anc[(size_t)(t - 1) * nx + j] : j;
+            for (int c = 0; c < nc; ++c) prev[c] = t == 0 ? x0[c] : state[((size_t)(t - 1) * nc + c) * nx + from];
+            double lg = 0.0;
+            for (int g = 0; g < ng; ++g) {
+                int32_t cnt;
+                if (cfg->model == OR_SIR)
+                    cnt = cfg->obs == OR_OBS_POIS_PREV ? cur[1 * nx + j] : prev[0] - cur[0 * nx + j];
+                else if (cfg->obs == OR_OBS_POIS_PREV)
+                    cnt = cur[(3 * g + 2) * nx + j];
+                else
+                    cnt = (prev[3 * g] + prev[3 * g + 1]) - (cur[(3 * g) * nx + j] + cur[(3 * g + 1) * nx + j]);
+                lg = lg + or_obs_part(cfg->obs, y[t * ng + g], cnt, r);
+            }
+            a[j] = lw[j] + lg;
+        }
+        double inc;
+        const int st = weigh_f64(nx, a, lw, w, qq, unused, &s_prev, cst, 0, 0, OR_RS_SYSTEMATIC, 0, 0, 0, &inc);
+        if (inc_out) inc_out[t] = inc;
+        if (st < 0) {
+            ll = -INFINITY;
+            break;
+        }
+        ll = ll + inc;
+        if (rs[t]) {
+            for (int j = 0; j < nx; ++j) lw[j] = 0.0;
+            s_prev = (double)nx;
+        }
+    }
+    free(lw); free(a); free(w); free(qq); free(unused);
+    return ll;
 }
 
 /* ------------------------------------------------------------------ outer sampler */

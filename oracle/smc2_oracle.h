@@ -89,6 +89,10 @@ int or_cholesky(int n, const double* A, double* L);
 double or_mvn_logpdf_chol(int n, const double* x, const double* mu, const double* L);
 int or_lkernel_fit(int N, int D, const double* phi, const double* phi_new, const double* omega,
                    double* mu /*2D*/, double* A /*DxD*/, double* LS /*DxD*/);
+/* As or_lkernel_fit, also writing the fitted 2D x 2D weighted covariance (cov_out, may
+ * be NULL); the moments are written even when the conditioning is rejected. */
+int or_lkernel_fit_cov(int N, int D, const double* phi, const double* phi_new, const double* omega,
+                       double* mu, double* A, double* LS, double* cov_out);
 double or_prior_logpdf(const or_config* cfg, const double* phi);
 void or_theta_of_phi(const or_config* cfg, const double* phi, double* theta);
 void or_recycle(int K, int D, const double* rec, double* mean, double* cov, double* c_out);
@@ -102,6 +106,16 @@ double or_pf_loglik(const or_config* cfg, const double* theta, const int32_t* y,
 double or_pf_trace_state(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx,
                          uint64_t seed, uint32_t filt, uint32_t k, double* inc_out, int32_t* rs_out,
                          int32_t* state_out);
+/* As or_pf_trace_state, also writing the ancestors chosen after every day (anc_out:
+ * int32[T][nx], the identity on days without resampling; may be NULL). */
+double or_pf_trace_full(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx,
+                        uint64_t seed, uint32_t filt, uint32_t k, double* inc_out, int32_t* rs_out,
+                        int32_t* state_out, int32_t* anc_out);
+/* The FP64 log-likelihood estimate of a filter replayed from injected integer decisions:
+ * state int32[T][n_counts][nx] and anc int32[T][nx] as or_pf_trace_full writes them,
+ * rs int32[T] resampling flags; inc_out (T, optional) the per-day increments. */
+double or_pf_replay(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx,
+                    const int32_t* state, const int32_t* anc, const int32_t* rs, double* inc_out);
 
 /* ---- the outer sampler (Sec. IV) ---- */
 void or_prior_draw(const or_config* cfg, int N, uint64_t seed, double* phi, double* lp);

@@ -25,7 +25,7 @@ PF_RS_SYSTEMATIC, PF_RS_MULTINOMIAL = 0, 1
 MLP_TRAIN_AUTO, MLP_TRAIN_PER_RUN, MLP_TRAIN_SPLIT = 0, 1, 2
 SCHED_AUTO, SCHED_PER_DRAW, SCHED_POOLED = 0, 1, 2
 DUMP = dict(phi=0, lp=1, ll=2, logw=3, phi_new=4, lp_new=5, ll_new=6, logw_pre=7, anc=8, mlp_out=9, logq=10,
-            mlp_params=11, mlp_frame=12, mlp_state=13, mlp_grad=14)
+            mlp_params=11, mlp_frame=12, mlp_state=13, mlp_grad=14, psteps=15, lkfit=16)
 MLP_H = 64
 
 
@@ -119,7 +119,7 @@ def lib():
         L.smc2_pf_trace.restype = c.c_int
         L.smc2_pf_trace.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp, vp, vp, c.c_size_t, vp]
         L.smc2_pf_trace_state.restype = c.c_int
-        L.smc2_pf_trace_state.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp, vp, vp, vp,
+        L.smc2_pf_trace_state.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp, vp, vp, vp, vp,
                                           c.c_size_t, vp]
         L.smc2_pf_loglik.restype = c.c_int
         L.smc2_pf_loglik.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp, c.c_size_t, vp]
@@ -275,6 +275,10 @@ class Sampler:
             out = np.zeros(self.D + self.D * self.D)
         elif what == "mlp_state":
             out = np.zeros(4)
+        elif what == "psteps":
+            out = np.zeros(1, dtype=np.uint64)
+        elif what == "lkfit":
+            out = np.zeros(2 * self.D + 4 * self.D * self.D)
         else:
             out = np.zeros(self.N)
         _check(lib().smc2_dump(self.h, code, run, out.ctypes.data_as(ctypes.c_void_p), out.nbytes), self.h)
@@ -343,8 +347,9 @@ def resample_batch(q, x64, device="cuda"):
     return from_device(ta, pa, np.int32, S * n).reshape(S, n), from_device(tt, pt, np.int32, S)
 
 
-def pf_trace_state(w, theta, y, nx, seed, k, precision=None, block=0, device="cuda", schedule=0):
-    """(ll, inc[n][T], rs[n][T], state[n][T][n_counts][nx]) for the rows of theta."""
+def pf_trace_state(w, theta, y, nx, seed, k, precision=None, block=0, device="cuda", schedule=0, with_anc=False):
+    """(ll, inc[n][T], rs[n][T], state[n][T][n_counts][nx]) for the rows of theta, and
+    with_anc=True also anc[n][T][nx], the ancestors chosen after each day."""
     cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, block=block, schedule=schedule)
     y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
     runs = make_runs([dict(T=y.shape[0], nx=nx, seed=seed, y=y)])
@@ -359,11 +364,15 @@ def pf_trace_state(w, theta, y, nx, seed, k, precision=None, block=0, device="cu
     tinc, pinc = device_buffer(8 * n * T, device)
     trs, prs = device_buffer(4 * n * T, device)
     tst, pst = device_buffer(4 * n * T * nc * nx, device)
-    _check(L.smc2_pf_trace_state(ctypes.byref(cfg), n, pth, runs, int(k), pll, pinc, prs, pst, pws, wsb,
+    tanc, panc = device_buffer(4 * n * T * nx, device) if with_anc else (None, None)
+    _check(L.smc2_pf_trace_state(ctypes.byref(cfg), n, pth, runs, int(k), pll, pinc, prs, pst, panc, pws, wsb,
                                  current_stream()))
-    return (from_device(tll, pll, np.float64, n), from_device(tinc, pinc, np.float64, n * T).reshape(n, T),
-            from_device(trs, prs, np.int32, n * T).reshape(n, T),
-            from_device(tst, pst, np.int32, n * T * nc * nx).reshape(n, T, nc, nx))
+    out = (from_device(tll, pll, np.float64, n), from_device(tinc, pinc, np.float64, n * T).reshape(n, T),
+           from_device(trs, prs, np.int32, n * T).reshape(n, T),
+           from_device(tst, pst, np.int32, n * T * nc * nx).reshape(n, T, nc, nx))
+    if with_anc:
+        out = out + (from_device(tanc, panc, np.int32, n * T * nx).reshape(n, T, nx),)
+    return out
 
 
 def pf_loglik(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0, device="cuda", trace=False,

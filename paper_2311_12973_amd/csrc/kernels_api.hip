@@ -156,35 +156,35 @@ extern "C" int smc2_pf_loglik(const smc2_config* cfg, int32_t n_theta, const dou
 }
 
 static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run, uint32_t k,
-                  double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, void* d_ws, size_t ws_bytes,
-                  void* stream, bool static_ws = false);
+                  double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, int32_t* d_anc, void* d_ws,
+                  size_t ws_bytes, void* stream, bool static_ws = false);
 
 extern "C" int smc2_pf_trace(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
                              uint32_t k, double* d_ll, double* d_inc, int32_t* d_rs, void* d_ws, size_t ws_bytes,
                              void* stream)
 {
-    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, d_inc, d_rs, nullptr, d_ws, ws_bytes, stream);
+    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, d_inc, d_rs, nullptr, nullptr, d_ws, ws_bytes, stream);
 }
 
 extern "C" int smc2_pf_trace_state(const smc2_config* cfg, int32_t n_theta, const double* d_theta,
                                    const smc2_run* run, uint32_t k, double* d_ll, double* d_inc, int32_t* d_rs,
-                                   int32_t* d_state, void* d_ws, size_t ws_bytes, void* stream)
+                                   int32_t* d_state, int32_t* d_anc, void* d_ws, size_t ws_bytes, void* stream)
 {
     if (!d_state) return kfail(SMC2_E_ARG, "d_state is NULL");
-    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, d_inc, d_rs, d_state, d_ws, ws_bytes, stream);
+    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, d_inc, d_rs, d_state, d_anc, d_ws, ws_bytes, stream);
 }
 
 extern "C" int smc2_pf_loglik_noalloc(const smc2_config* cfg, int32_t n_theta, const double* d_theta,
                                       const smc2_run* run, uint32_t k, double* d_ll, void* stream)
 {
-    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, nullptr, nullptr, nullptr, nullptr, 0, stream, true);
+    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, nullptr, nullptr, nullptr, nullptr, nullptr, 0, stream, true);
 }
 
 // static_ws: the workspace is the file-scope scratch (d_ws and ws_bytes unused); its
 // device address is resolved only after every argument has been checked.
 static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run, uint32_t k,
-                  double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, void* d_ws, size_t ws_bytes,
-                  void* stream, bool static_ws)
+                  double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, int32_t* d_anc, void* d_ws,
+                  size_t ws_bytes, void* stream, bool static_ws)
 {
     if ((d_inc == nullptr) != (d_rs == nullptr)) return kfail(SMC2_E_ARG, "trace needs both d_inc and d_rs");
     if (!cfg || !run || !run->y) return kfail(SMC2_E_ARG, "null config or run");
@@ -244,6 +244,7 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     a.trace_inc = d_inc;
     a.trace_rs = d_rs;
     a.trace_state = d_state;
+    a.trace_anc = d_anc;
     a.k_const = k;
     a.n_items = n_theta;
     a.N = n_theta;

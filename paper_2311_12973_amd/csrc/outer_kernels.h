@@ -27,6 +27,8 @@ struct OuterArrays {
     uint8_t* active;   // [R][N]    run the particle filter for this proposal
     double* records;   // [R][K][record_len]
     int32_t* status;   // [R]       0, or -4 when every weight of the run vanished
+    double* lkfit;     // [R][2D + 4D^2] moments of the last L-kernel fit: mean of (phi_{k-1},
+                       //               phi_k), then its weighted covariance (row-major)
     int32_t* k_dev;    // iteration counter
     // learned proposal (NULL unless the configuration uses it)
     const int32_t* mlp_use;   // [R]        1: this iteration proposes with the network

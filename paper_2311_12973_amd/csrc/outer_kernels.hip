@@ -343,6 +343,8 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
                 }
             },
             cov, vlds, est);
+        for (int e = tid; e < D2 + D2 * D2; e += nthr)
+            o.lkfit[(size_t)r * (D2 + D2 * D2) + e] = e < D2 ? mu[e] : cov[e - D2];
         if (tid == 0) {
             // numerical-rank floor: every Cholesky pivot must exceed LK_REL_FLOOR times
             // its coordinate's raw second moment, else the population is degenerate

@@ -28,6 +28,10 @@ struct PFArgs {
     double* trace_inc;      // [G][T] per-day likelihood increments, or NULL (diagnostics)
     int32_t* trace_rs;      // [G][T] per-day resampling flags, or NULL
     int32_t* trace_state;   // [G][T][NC][nx] per-day counts before resampling, or NULL
+    int32_t* trace_anc;     // [G][T][nx] ancestors chosen after each day (identity without
+                            // resampling; unwritten after a filter's death day), or NULL
+    unsigned long long* psteps;  // [n_runs] executed particle-steps: each filter adds N_x x
+                                 // the days it ran (to its death day), or NULL
     int32_t* queue;         // work-list counter (zero at launch) for a persistent grid, or NULL
     uint32_t k_const;
     int32_t n_items;

@@ -563,6 +563,7 @@ __device__ void pf_filter(const PFArgs& a, int item)
     __syncthreads();
 
     double ll = 0.0;
+    int days = T;  // days run: T, or the day every weight vanished
     const double log_nx = log((double)nx);
     double log_prev = log_nx;  // log of the previous day's weight sum (N_x after a resampling)
     for (int t = 1; t <= T; ++t) {
@@ -599,6 +600,7 @@ __device__ void pf_filter(const PFArgs& a, int item)
         const real m = uniform_real<real>(block_max<real>(amax, red));
         if (m == (real)-INFINITY) {
             ll = -INFINITY;
+            days = t;
             if (a.trace_inc && first_wave()) {
                 for (int tt = t; tt <= T; ++tt) {
                     a.trace_inc[(size_t)g * T + tt - 1] = tt == t ? -INFINITY : 0.0;
@@ -653,6 +655,8 @@ __device__ void pf_filter(const PFArgs& a, int item)
                 block_ancestors(C, nx, Q, (uint64_t)wd.x | ((uint64_t)wd.y << 32), anc);
             }
             __syncthreads();
+            if (a.trace_anc)
+                for (int j = tid; j < nx; j += nthr) a.trace_anc[((size_t)g * T + (t - 1)) * nx + j] = anc[j];
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
                 int32_t* sc = st + c * cap;
@@ -665,9 +669,12 @@ __device__ void pf_filter(const PFArgs& a, int item)
             // the next day's draws read any particle's counts (the pooled schedule hands
             // out items workgroup-wide): every gathered count must be in place first
             __syncthreads();
+        } else if (a.trace_anc) {
+            for (int j = tid; j < nx; j += nthr) a.trace_anc[((size_t)g * T + (t - 1)) * nx + j] = j;
         }
     }
     if (first_wave()) a.ll[g] = ll;
+    if (a.psteps && tid == 0) atomicAdd(a.psteps + run_i, (unsigned long long)nx * (unsigned long long)days);
 }
 
 // One filter per workgroup (a.queue == NULL: filter blockIdx.x), or a persistent grid

@@ -60,7 +60,8 @@ struct Layout {
     size_t off_k, off_status, off_seeds, off_runs, off_y, off_prior, off_lrw, off_phi, off_phin, off_thn, off_lp,
         off_ll, off_logw, off_lpn, off_lln, off_lwp, off_scr, off_qc, off_anc, off_active, off_rec, off_items,
         off_queues, off_tune_items, off_mlp_params, off_mlp_m, off_mlp_v, off_mlp_grad, off_mlp_t, off_mlp_frame,
-        off_mlp_use, off_mlp_out, off_mlp_logq, off_mlp_score, off_mlp_rows, off_mlp_wfull, off_mlp_gpart;
+        off_mlp_use, off_mlp_out, off_mlp_logq, off_mlp_score, off_mlp_rows, off_mlp_wfull, off_mlp_gpart,
+        off_psteps, off_lkfit;
     size_t take(size_t bytes)
     {
         const size_t o = total;
@@ -77,6 +78,8 @@ Layout make_layout(const smc2_config* c, int R, const smc2_run* runs)
     for (int r = 0; r < R; ++r) ytot += (size_t)runs[r].T * n_obs_of(c->model);
     L.off_k = L.take(sizeof(int32_t));
     L.off_status = L.take(sizeof(int32_t) * R);
+    L.off_psteps = L.take(sizeof(unsigned long long) * R);
+    L.off_lkfit = L.take(sizeof(double) * R * (2 * D + 4 * D * D));
     L.off_seeds = L.take(sizeof(uint64_t) * R);
     L.off_runs = L.take(sizeof(RunDev) * R);
     L.off_y = L.take(sizeof(int32_t) * ytot);
@@ -492,6 +495,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     o.active = (uint8_t*)(w + lay.off_active);
     o.records = (double*)(w + lay.off_rec);
     o.status = (int32_t*)(w + lay.off_status);
+    o.lkfit = (double*)(w + lay.off_lkfit);
     o.k_dev = (int32_t*)(w + lay.off_k);
     const bool mlp = cfg->proposal == SMC2_PROP_MLP;
     if (mlp) {
@@ -578,6 +582,9 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     }
     if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_k, 0, sizeof(int32_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_status, 0, sizeof(int32_t) * n_runs, s);
+    if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_psteps, 0, sizeof(unsigned long long) * n_runs, s);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(w + lay.off_lkfit, 0, sizeof(double) * n_runs * (2 * cfg->D + 4 * cfg->D * cfg->D), s);
     if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_logw, 0, sizeof(double) * n_runs * N, s);
     if (e == hipSuccess)
         e = hipMemsetAsync(w + lay.off_rec, 0, sizeof(double) * n_runs * cfg->K * SMC2_RECORD_LEN(cfg->D), s);
@@ -620,6 +627,7 @@ static hipError_t enqueue_iteration(smc2_ctx* c, hipStream_t s, hipEvent_t pf0, 
         a.n_items = gr.n_items;
         a.queue = gr.persistent ? queues + gi : nullptr;
         a.prio_scale = gr.prio;
+        a.psteps = (unsigned long long*)(c->ws + c->lay.off_psteps);
         e = launch_pf(c->cfg.precision, c->cfg.model, c->cfg.obs, gr.sched, gr.block, gr.lds, a, s, gr.grid);
     }
     if (e == hipSuccess && pf1) e = hipEventRecord(pf1, s);
@@ -739,6 +747,11 @@ extern "C" int smc2_dump(smc2_ctx* c, int32_t what, int32_t run, void* host_dst,
     case SMC2_DUMP_LL_NEW: src = c->oa.ll_new + base; need = N * 8; break;
     case SMC2_DUMP_LOGW_PRE: src = c->oa.logw_pre + base; need = N * 8; break;
     case SMC2_DUMP_ANC: src = c->oa.anc + base; need = N * 4; break;
+    case SMC2_DUMP_PSTEPS: src = c->ws + c->lay.off_psteps + sizeof(unsigned long long) * run; need = 8; break;
+    case SMC2_DUMP_LKFIT:
+        src = c->oa.lkfit + (size_t)run * (2 * D + 4 * D * D);
+        need = (2 * D + 4 * D * D) * 8;
+        break;
     case SMC2_DUMP_MLP_OUT:
     case SMC2_DUMP_LOGQ:
     case SMC2_DUMP_MLP_PARAMS:
