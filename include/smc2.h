@@ -188,6 +188,8 @@ typedef struct {
                                 smc2_init: N_x x the days each active filter ran (a filter
                                 whose weights all vanish stops that day; inactive samples,
                                 with zero weight or outside the prior's support, run none) */
+#define SMC2_DUMP_THETA_NEW 17 /* N x D doubles: model parameters theta(phi_new) of the samples
+                                  proposed in the last step (what their filters ran with)  */
 #define SMC2_DUMP_LKFIT 16   /* 2D + 4D^2 doubles: moments of the last approximately optimal
                                 L-kernel fit (Sec. IV-D), the weighted mean of the pairs
                                 (phi_{k-1}, phi_k) then their weighted covariance (row-major,

@@ -10,6 +10,12 @@ range reduction plus a degree-12 polynomial. The result is the mean number of
 operations one particle-step needs, independent of how a kernel schedules them.
 
     python -m oracle.opcount [--workload seir] [--N 128] [--K 12]
+    python -m oracle.opcount --workload age_seir --filters 16 --spread 0.05
+
+The second form counts single filters at parameters drawn around the workload's
+truth (theta_d x exp(spread z), z standard normal) instead of a whole run: a
+population near the posterior, which is where the timed iterations of a long run
+spend their filters (prior draws of the age-structured model die within days).
 """
 import argparse
 import json
@@ -34,8 +40,9 @@ COST = {
     # classification: n <= 0, p in (0, 1), flip to p <= 1/2, n p < 10 (cvt, mul, cmp),
     # flip of the result
     "draw": 8,
-    # 10 rounds x (two 32x32->64 products = 4 multiplies, two 3-input XORs = 4)
-    "philox": 80,
+    # 10 rounds x (two 32x32->64 products, each one multiply giving both halves; four
+    # two-input XORs); the key schedule's additions are the same for every lane
+    "philox": 60,
     # inversion set-up: uniform (3), q, r = p/q, n * log1p(-p) (2), rounding (1)
     "inv": 8,
     # inversion step: (n-k) and its conversion, two products and the reciprocal
@@ -73,16 +80,40 @@ def count(w, N, K, nx=None, T=None, seed=None):
                 status=int(out["status"]))
 
 
+def count_filters(w, n_filters, spread, seed=1, k=1):
+    """Events of n_filters single filters (the workload's N_x, T and precision) at
+    theta = truth x exp(spread z), on the streams of filters 0..n_filters-1 at
+    iteration k."""
+    cfg = O.config_from_workload(w)
+    y = W.observations(w)
+    rng = np.random.default_rng(seed)
+    theta = np.array(w["truth"]) * np.exp(spread * rng.standard_normal((n_filters, w["D"])))
+    O.events_reset()
+    t0 = time.time()
+    ll = [O.pf_loglik(cfg, th, y, w["nx"], w["seed"], i, k) for i, th in enumerate(theta)]
+    ev = O.events_get()
+    per = {key: v / ev["pstep"] for key, v in ev.items()}
+    ops = sum(COST[key] * per[key] for key in COST)
+    return dict(per_pstep=per, ops_per_pstep=ops, psteps=ev["pstep"], seconds=time.time() - t0,
+                finite=int(np.isfinite(ll).sum()))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="seir")
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--K", type=int, default=12)
+    ap.add_argument("--filters", type=int, default=0, help="count single filters near the truth instead of a run")
+    ap.add_argument("--spread", type=float, default=0.05)
     a = ap.parse_args()
     w = W.preset(a.workload)
-    r = count(w, a.N, a.K)
-    print(json.dumps(dict(workload=a.workload, N=a.N, nx=w["nx"], T=w["T"], K=a.K, cost=COST,
-                          per_pstep={k: round(v, 5) for k, v in r["per_pstep"].items()},
+    if a.filters:
+        r = count_filters(w, a.filters, a.spread)
+        head = dict(workload=a.workload, filters=a.filters, spread=a.spread, nx=w["nx"], T=w["T"])
+    else:
+        r = count(w, a.N, a.K)
+        head = dict(workload=a.workload, N=a.N, nx=w["nx"], T=w["T"], K=a.K)
+    print(json.dumps(dict(head, cost=COST, per_pstep={k: round(v, 5) for k, v in r["per_pstep"].items()},
                           ops_per_pstep=round(r["ops_per_pstep"], 1), psteps=r["psteps"],
                           seconds=round(r["seconds"], 1)), indent=1))
 

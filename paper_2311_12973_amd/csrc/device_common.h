@@ -370,6 +370,16 @@ __device__ __forceinline__ int btrs_final_fast(const BtrsConst<real>& c, int32_t
     }
 }
 
+// btrs_final as a call, for the per-draw sampler: the FP64 test is taken only near the
+// boundary of the FP32 one, and kept out of line its registers do not weigh on the
+// draw loop around it.
+template <typename real>
+__device__ __attribute__((noinline)) bool btrs_final_call(const BtrsConst<real> c, int32_t n, real p, int32_t k,
+                                                          uint32_t wu, uint32_t wv)
+{
+    return btrs_final<real>(c, n, p, k, wu, wv);
+}
+
 // The acceptance decision of a candidate that needs the final test: FP32 first, the
 // FP64 test only when the FP32 value cannot decide.
 template <typename real>
@@ -378,7 +388,7 @@ __device__ __forceinline__ bool btrs_decide(const BtrsConst<real>& c, int32_t n,
 {
     const int f = btrs_final_fast<real>(c, n, p, k, wu, wv);
     bool acc = f > 0;
-    if (f == 0) acc = btrs_final<real>(c, n, p, k, wu, wv);
+    if (f == 0) acc = btrs_final_call<real>(c, n, p, k, wu, wv);
     return acc;
 }
 
@@ -403,7 +413,11 @@ __device__ __forceinline__ int32_t binom_btrs(int32_t n, real p, const DrawStrea
         // form "if (quick || final(...)) return k" was miscompiled for gfx950 (the
         // register holding k was reused inside the final test on the accepting path).
         bool acc = r == BTRS_ACCEPT;
-        if (r == BTRS_FINAL) acc = btrs_decide<real>(c, n, p, k, wu, wv);
+        if (r == BTRS_FINAL) {
+            const int f = btrs_final_fast<real>(c, n, p, k, wu, wv);
+            acc = f > 0;
+            if (f == 0) acc = btrs_final_call<real>(c, n, p, k, wu, wv);
+        }
         if (acc) return (int32_t)k;
     }
     return btrs_mode<real>(n, p);

@@ -88,6 +88,19 @@ __device__ __forceinline__ void model_setup(const PFArgs& a, const double* th, M
     }
     mc.l1p_ei = l1p_of<real>(mc.p_ei);
     mc.l1p_ir = l1p_of<real>(mc.p_ir);
+    if (MODEL == MODEL_AGE) {
+        // every thread computed the same values: held in scalar registers, they leave
+        // the vector registers to the draws
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+            for (int h = 0; h < 4; ++h) mc.cs[g][h] = uniform_real<real>(mc.cs[g][h]);
+        mc.p_ei = uniform_real<real>(mc.p_ei);
+        mc.p_ir = uniform_real<real>(mc.p_ir);
+        mc.l1p_ei = uniform_f64(mc.l1p_ei);
+        mc.l1p_ir = uniform_f64(mc.l1p_ir);
+        mc.r = uniform_f64(mc.r);
+    }
 }
 
 // One day of the chain-binomial model for particle j, whose counts live in LDS
@@ -511,7 +524,7 @@ __device__ __forceinline__ void wave_priority(float r)
 }
 
 template <typename real, int MODEL, int OBS, int SCHED>
-__device__ void pf_filter(const PFArgs& a, int item)
+__device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a, int item)
 {
     constexpr int NC = ModelShape<MODEL>::NC;
     constexpr int NG = ModelShape<MODEL>::NG;

@@ -743,6 +743,7 @@ extern "C" int smc2_dump(smc2_ctx* c, int32_t what, int32_t run, void* host_dst,
     case SMC2_DUMP_LL: src = c->oa.ll + base; need = N * 8; break;
     case SMC2_DUMP_LOGW: src = c->oa.logw + base; need = N * 8; break;
     case SMC2_DUMP_PHI_NEW: src = c->oa.phi_new + base * D; need = N * D * 8; break;
+    case SMC2_DUMP_THETA_NEW: src = c->oa.theta_new + base * D; need = N * D * 8; break;
     case SMC2_DUMP_LP_NEW: src = c->oa.lp_new + base; need = N * 8; break;
     case SMC2_DUMP_LL_NEW: src = c->oa.ll_new + base; need = N * 8; break;
     case SMC2_DUMP_LOGW_PRE: src = c->oa.logw_pre + base; need = N * 8; break;
