@@ -115,11 +115,14 @@ def run_timed(G, W, np, name, steps, warmup, extra=0, **launch):
     ms_pf, ms_step_dev, _ = s.timing()
     ps1 = sum(int(s.dump("psteps", r)[0]) for r in range(len(runs)))
     dead = float(np.mean([s.records(r)[warmup:warmup + steps, 3].mean() for r in range(len(runs))]))
+    infos = [s.info(k) for k in range(warmup + 1, warmup + steps + 1)]
+    phases = {key: float(np.mean([inf[key] for inf in infos])) for key in ("ms_filters", "ms_outer", "ms_mlp",
+                                                                           "ms_step")}
     ms = (t1 - t0) * 1e3 / steps
     executed = float(ps1 - ps0)
     nominal = float(N) * sum(r["nx"] * r["T"] for r in runs) * steps
     m = dict(w=w, runs=runs, N=N, ms=ms, ms_pf=ms_pf, ms_step_dev=ms_step_dev, executed=executed, nominal=nominal,
-             value=executed / ((t1 - t0)), dead=dead, steps=steps, warmup=warmup)
+             value=executed / ((t1 - t0)), dead=dead, steps=steps, warmup=warmup, phases=phases)
     if not extra:
         s.close()
         s = None
@@ -226,7 +229,7 @@ def main():
                    "nominal_particle_steps_per_s": m["nominal"] / (m["ms"] * 1e-3 * m["steps"]),
                    "parallelism": "single GPU", "graph": bool(args.graph), "tune": bool(args.tune),
                    "persistent": bool(args.persistent), "dead_samples_per_step": m["dead"],
-                   "device_ms_per_step": m["ms_step_dev"]},
+                   "device_ms_per_step": m["ms_step_dev"], "device_ms_per_phase": m["phases"]},
         "roofline": roofline, "cpu_baseline": cpu, "precision": precision, "ess_per_s": ess, "secondary": secondary,
     }
     print(json.dumps(out))

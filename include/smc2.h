@@ -210,6 +210,29 @@ typedef struct {
 #define SMC2_DUMP_MLP_GRAD 14   /* NP     float: gradient of the last minibatch, before
                                    clipping, in the layout of SMC2_DUMP_MLP_PARAMS       */
 
+/* One completed iteration of one run, as smc2_info reports it. The record's scalars
+ * (Sec. IV: ESS = l_k before resampling, Eq. ess_smc2 and recycling_I; whether the
+ * population was resampled, Eq. cdf and ncopies), the work the run's filters executed,
+ * and the device time of the iteration's phases (all runs of the context together;
+ * -1 where the iteration was replayed as one graph, whose phases are not timed). */
+typedef struct {
+    int32_t k;                /* iteration, 1-based                                          */
+    int32_t resampled;        /* 1 when the population was resampled after the weights      */
+    int32_t dead;             /* samples with zero weight                                    */
+    int32_t lkernel_fallback; /* 1 when the Gaussian L-kernel fit was rejected              */
+    int32_t learned;          /* 1 when the learned proposal drew the samples               */
+    int32_t pad;
+    double ess;               /* effective sample size of the weights, = l_k                 */
+    double log_weight_sum;    /* log sum_i w_k^i                                             */
+    uint64_t particle_steps;  /* executed particle-steps of the run's filters (N_x x days
+                                 each active filter ran)                                     */
+    double ms_filters;        /* particle-filter launches                                    */
+    double ms_outer;          /* proposal (prior draw / random walk / learned) and the outer
+                                 update (L-kernel, weights, estimates, resampling)           */
+    double ms_mlp;            /* learned proposal's network outputs and training (0 without) */
+    double ms_step;           /* the whole iteration                                         */
+} smc2_step_info;
+
 /* Bytes of device workspace needed for this config and these runs (0 on bad input). */
 size_t smc2_workspace_bytes(const smc2_config* cfg, int32_t n_runs, const smc2_run* runs);
 
@@ -226,6 +249,11 @@ int smc2_step(smc2_ctx* ctx);
 /* Copy run `run`'s records of the completed iterations (k_done x SMC2_RECORD_LEN(D)
  * doubles) to host_dst; *k_done receives the number of completed iterations. */
 int smc2_records(smc2_ctx* ctx, int32_t run, double* host_dst, size_t n_doubles, int32_t* k_done);
+
+/* Information on completed iteration k (1 <= k <= iterations run) of run `run`.
+ * Synchronises the stream. SMC2_E_ARG for a k that has not run. smc2_step itself returns
+ * at once (the iteration runs asynchronously), so its information is read here. */
+int smc2_info(smc2_ctx* ctx, int32_t run, int32_t k, smc2_step_info* info);
 
 /* Posterior estimate of theta for run `run`: recycled over all completed iterations
  * with c_k = l_k / sum_j l_j (Sec. IV-C) when recycled != 0, else the last

@@ -66,6 +66,14 @@ class Run(ctypes.Structure):
                 ("y", ctypes.POINTER(ctypes.c_int32))]
 
 
+class StepInfo(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("resampled", ctypes.c_int32), ("dead", ctypes.c_int32),
+                ("lkernel_fallback", ctypes.c_int32), ("learned", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("ess", ctypes.c_double), ("log_weight_sum", ctypes.c_double), ("particle_steps", ctypes.c_uint64),
+                ("ms_filters", ctypes.c_double), ("ms_outer", ctypes.c_double), ("ms_mlp", ctypes.c_double),
+                ("ms_step", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -95,6 +103,8 @@ def lib():
         L.smc2_estimate.argtypes = [vp, c.c_int32, c.c_int32, P(c.c_double), P(c.c_double)]
         L.smc2_dump.restype = c.c_int
         L.smc2_dump.argtypes = [vp, c.c_int32, c.c_int32, vp, c.c_size_t]
+        L.smc2_info.restype = c.c_int
+        L.smc2_info.argtypes = [vp, c.c_int32, c.c_int32, P(StepInfo)]
         L.smc2_timing.restype = c.c_int
         L.smc2_timing.argtypes = [vp, P(c.c_double), P(c.c_double), P(c.c_int32)]
         L.smc2_destroy.restype = c.c_int
@@ -283,6 +293,12 @@ class Sampler:
             out = np.zeros(self.N)
         _check(lib().smc2_dump(self.h, code, run, out.ctypes.data_as(ctypes.c_void_p), out.nbytes), self.h)
         return out
+
+    def info(self, k, run=0):
+        """smc2_info of completed iteration k (1-based) as a dict."""
+        out = StepInfo()
+        _check(lib().smc2_info(self.h, run, int(k), ctypes.byref(out)), self.h)
+        return {name: getattr(out, name) for name, _ in StepInfo._fields_ if name != "pad"}
 
     def timing(self):
         a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()

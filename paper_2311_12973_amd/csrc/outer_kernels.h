@@ -30,6 +30,8 @@ struct OuterArrays {
     double* lkfit;     // [R][2D + 4D^2] moments of the last L-kernel fit: mean of (phi_{k-1},
                        //               phi_k), then its weighted covariance (row-major)
     int32_t* k_dev;    // iteration counter
+    const unsigned long long* psteps;  // [R]    executed particle-steps so far (filter kernel)
+    unsigned long long* psteps_at;     // [R][K] its value after each iteration's filters
     // learned proposal (NULL unless the configuration uses it)
     const int32_t* mlp_use;   // [R]        1: this iteration proposes with the network
     const float* mlp_out;     // [R][N][P]  network outputs at the current population

@@ -294,6 +294,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
     __shared__ double est[VSUM_MAX];
     __shared__ int fit_ok;
     for (int e = tid; e < D * D; e += nthr) Lq[e] = p.lrw[e];
+    if (tid == 0 && o.psteps_at) o.psteps_at[(size_t)r * p.K + (k - 1)] = o.psteps[r];
     __syncthreads();
 
     // proposal of this iteration: the learned one (then its density is in o.logq)

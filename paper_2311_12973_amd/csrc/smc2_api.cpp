@@ -54,6 +54,9 @@ bool host_cholesky(int n, const double* A, double* L)
 
 // work-list counters in the workspace: one per launch group, plus one for tuning
 constexpr int MAX_GROUPS = 64;
+// timing events per iteration: start, after the learned proposal's forward pass, filters
+// start and end, after the outer update, end
+constexpr int EV_PER_STEP = 6;
 
 struct Layout {
     size_t total = 0;
@@ -61,7 +64,7 @@ struct Layout {
         off_ll, off_logw, off_lpn, off_lln, off_lwp, off_scr, off_qc, off_anc, off_active, off_rec, off_items,
         off_queues, off_tune_items, off_mlp_params, off_mlp_m, off_mlp_v, off_mlp_grad, off_mlp_t, off_mlp_frame,
         off_mlp_use, off_mlp_out, off_mlp_logq, off_mlp_score, off_mlp_rows, off_mlp_wfull, off_mlp_gpart,
-        off_psteps, off_lkfit;
+        off_psteps, off_lkfit, off_psteps_at;
     size_t take(size_t bytes)
     {
         const size_t o = total;
@@ -80,6 +83,7 @@ Layout make_layout(const smc2_config* c, int R, const smc2_run* runs)
     L.off_status = L.take(sizeof(int32_t) * R);
     L.off_psteps = L.take(sizeof(unsigned long long) * R);
     L.off_lkfit = L.take(sizeof(double) * R * (2 * D + 4 * D * D));
+    L.off_psteps_at = L.take(sizeof(unsigned long long) * R * (size_t)c->K);
     L.off_seeds = L.take(sizeof(uint64_t) * R);
     L.off_runs = L.take(sizeof(RunDev) * R);
     L.off_y = L.take(sizeof(int32_t) * ytot);
@@ -496,6 +500,8 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     o.records = (double*)(w + lay.off_rec);
     o.status = (int32_t*)(w + lay.off_status);
     o.lkfit = (double*)(w + lay.off_lkfit);
+    o.psteps = (const unsigned long long*)(w + lay.off_psteps);
+    o.psteps_at = (unsigned long long*)(w + lay.off_psteps_at);
     o.k_dev = (int32_t*)(w + lay.off_k);
     const bool mlp = cfg->proposal == SMC2_PROP_MLP;
     if (mlp) {
@@ -584,6 +590,8 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_status, 0, sizeof(int32_t) * n_runs, s);
     if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_psteps, 0, sizeof(unsigned long long) * n_runs, s);
     if (e == hipSuccess)
+        e = hipMemsetAsync(w + lay.off_psteps_at, 0, sizeof(unsigned long long) * n_runs * cfg->K, s);
+    if (e == hipSuccess)
         e = hipMemsetAsync(w + lay.off_lkfit, 0, sizeof(double) * n_runs * (2 * cfg->D + 4 * cfg->D * cfg->D), s);
     if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_logw, 0, sizeof(double) * n_runs * N, s);
     if (e == hipSuccess)
@@ -598,7 +606,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
         e = set_launch(c, gr);
     }
     if (e == hipSuccess) {
-        c->ev.resize(4 * (size_t)cfg->K, nullptr);
+        c->ev.resize(EV_PER_STEP * (size_t)cfg->K, nullptr);
         for (auto& ev : c->ev)
             if (e == hipSuccess) e = hipEventCreate(&ev);
     }
@@ -612,13 +620,16 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     return SMC2_OK;
 }
 
-static hipError_t enqueue_iteration(smc2_ctx* c, hipStream_t s, hipEvent_t pf0, hipEvent_t pf1)
+// ev (NULL inside a graph capture): events [1] after the learned proposal's forward
+// pass, [2] before and [3] after the filter launches, [4] after the outer update.
+static hipError_t enqueue_iteration(smc2_ctx* c, hipStream_t s, const hipEvent_t* ev)
 {
     int32_t* queues = (int32_t*)(c->ws + c->lay.off_queues);
     hipError_t e = launch_begin_iteration(c->oa, queues, (int)c->groups.size(), s);
     if (e == hipSuccess && c->op.mlp) e = launch_mlp_forward(c->ma, c->mp, c->oa, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
     if (e == hipSuccess) e = launch_propose(c->oa, c->op, c->d_seeds, s);
-    if (e == hipSuccess && pf0) e = hipEventRecord(pf0, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
     for (size_t gi = 0; gi < c->groups.size(); ++gi) {
         if (e != hipSuccess) break;
         const PFGroup& gr = c->groups[gi];
@@ -630,8 +641,9 @@ static hipError_t enqueue_iteration(smc2_ctx* c, hipStream_t s, hipEvent_t pf0, 
         a.psteps = (unsigned long long*)(c->ws + c->lay.off_psteps);
         e = launch_pf(c->cfg.precision, c->cfg.model, c->cfg.obs, gr.sched, gr.block, gr.lds, a, s, gr.grid);
     }
-    if (e == hipSuccess && pf1) e = hipEventRecord(pf1, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[3], s);
     if (e == hipSuccess) e = launch_outer_update(c->oa, c->op, c->d_seeds, s);
+    if (e == hipSuccess && ev) e = hipEventRecord(ev[4], s);
     if (e == hipSuccess && c->op.mlp) e = launch_mlp_train(c->ma, c->mp, c->oa, c->d_seeds, s);
     return e;
 }
@@ -642,7 +654,7 @@ extern "C" int smc2_step(smc2_ctx* c)
     if (c->poisoned) return c->fail(SMC2_E_DEVICE, "context poisoned by an earlier device error");
     if (c->k_host >= c->cfg.K) return c->fail(SMC2_E_STATE, "all K iterations have run");
     const int k = c->k_host + 1;
-    hipEvent_t* ev = &c->ev[4 * (size_t)(k - 1)];
+    hipEvent_t* ev = &c->ev[EV_PER_STEP * (size_t)(k - 1)];
     hipError_t e = hipEventRecord(ev[0], c->stream);
     if (e == hipSuccess) {
         if (c->cfg.use_graph) {
@@ -652,21 +664,22 @@ extern "C" int smc2_step(smc2_ctx* c)
                 if (!c->cap_stream) e = hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking);
                 if (e == hipSuccess) e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
                 if (e == hipSuccess) {
-                    const hipError_t e1 = enqueue_iteration(c, c->cap_stream, nullptr, nullptr);
+                    const hipError_t e1 = enqueue_iteration(c, c->cap_stream, nullptr);
                     e = hipStreamEndCapture(c->cap_stream, &c->graph);
                     if (e1 != hipSuccess) e = e1;
                 }
                 if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0);
                 if (e == hipSuccess) c->graph_ready = true;
             }
-            if (e == hipSuccess) e = hipEventRecord(ev[1], c->stream);
-            if (e == hipSuccess) e = hipGraphLaunch(c->graph_exec, c->stream);
+            // the graph's phases are not timed; [2] and [3] bracket the whole graph
             if (e == hipSuccess) e = hipEventRecord(ev[2], c->stream);
+            if (e == hipSuccess) e = hipGraphLaunch(c->graph_exec, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
         } else {
-            e = enqueue_iteration(c, c->stream, ev[1], ev[2]);
+            e = enqueue_iteration(c, c->stream, ev);
         }
     }
-    if (e == hipSuccess) e = hipEventRecord(ev[3], c->stream);
+    if (e == hipSuccess) e = hipEventRecord(ev[5], c->stream);
     if (e != hipSuccess) return c->device_fail(e, "smc2_step");
     c->k_host = k;
     return SMC2_OK;
@@ -805,8 +818,8 @@ extern "C" int smc2_timing(smc2_ctx* c, double* ms_pf, double* ms_step, int32_t*
     const int n = c->k_host - c->timed_from;
     for (int k = c->timed_from; k < c->k_host; ++k) {
         float a = 0.f, b = 0.f;
-        e = hipEventElapsedTime(&a, c->ev[4 * k + 1], c->ev[4 * k + 2]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&b, c->ev[4 * k + 0], c->ev[4 * k + 3]);
+        e = hipEventElapsedTime(&a, c->ev[EV_PER_STEP * k + 2], c->ev[EV_PER_STEP * k + 3]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, c->ev[EV_PER_STEP * k + 0], c->ev[EV_PER_STEP * k + 5]);
         if (e != hipSuccess) return c->device_fail(e, "event timing");
         pf += a;
         st += b;
@@ -815,6 +828,57 @@ extern "C" int smc2_timing(smc2_ctx* c, double* ms_pf, double* ms_step, int32_t*
     if (ms_pf) *ms_pf = n > 0 ? pf / n : 0.0;
     if (ms_step) *ms_step = n > 0 ? st / n : 0.0;
     if (n_steps) *n_steps = n;
+    return SMC2_OK;
+}
+
+extern "C" int smc2_info(smc2_ctx* c, int32_t run, int32_t k, smc2_step_info* info)
+{
+    if (!c) return g_thread_error = "ctx is NULL", SMC2_E_ARG;
+    if (run < 0 || run >= c->R || !info) return c->fail(SMC2_E_ARG, "bad run or info");
+    if (k < 1 || k > c->k_host) return c->fail(SMC2_E_ARG, "iteration k has not run");
+    if (c->poisoned) return c->fail(SMC2_E_DEVICE, "context poisoned by an earlier device error");
+    hipError_t e = hipStreamSynchronize(c->stream);
+    const size_t RL = SMC2_RECORD_LEN(c->cfg.D);
+    std::vector<double> rec(RL);
+    unsigned long long at[2] = {0ull, 0ull};
+    const unsigned long long* hist = c->oa.psteps_at + (size_t)run * c->cfg.K;
+    if (e == hipSuccess)
+        e = hipMemcpy(rec.data(), c->oa.records + ((size_t)run * c->cfg.K + (k - 1)) * RL, sizeof(double) * RL,
+                      hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipMemcpy(&at[1], hist + (k - 1), sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && k > 1) e = hipMemcpy(&at[0], hist + (k - 2), sizeof(unsigned long long), hipMemcpyDeviceToHost);
+    float t[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+    const hipEvent_t* ev = &c->ev[EV_PER_STEP * (size_t)(k - 1)];
+    if (e == hipSuccess) e = hipEventElapsedTime(&t[0], ev[0], ev[5]);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t[1], ev[2], ev[3]);
+    if (e == hipSuccess && !c->cfg.use_graph) {
+        e = hipEventElapsedTime(&t[2], ev[0], ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t[3], ev[1], ev[2]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&t[4], ev[3], ev[4]);
+    }
+    float t_train = 0.f;
+    if (e == hipSuccess && !c->cfg.use_graph) e = hipEventElapsedTime(&t_train, ev[4], ev[5]);
+    if (e != hipSuccess) return c->device_fail(e, "smc2_info");
+    info->k = (int32_t)rec[0];
+    info->ess = rec[1];
+    info->resampled = (int32_t)rec[2];
+    info->dead = (int32_t)rec[3];
+    info->lkernel_fallback = (int32_t)rec[4];
+    info->log_weight_sum = rec[5];
+    info->learned = (int32_t)rec[RL - 2];
+    info->pad = 0;
+    info->particle_steps = at[1] - at[0];
+    info->ms_step = t[0];
+    info->ms_filters = t[1];
+    if (c->cfg.use_graph) {
+        info->ms_outer = -1.0;
+        info->ms_mlp = -1.0;
+    } else {
+        // [0, 1): the learned proposal's forward pass (with the iteration's begin kernel),
+        // [1, 2): the proposal, [3, 4): the outer update, [4, 5): training
+        info->ms_outer = (double)t[3] + (double)t[4];
+        info->ms_mlp = c->op.mlp ? (double)t[2] + (double)t_train : 0.0;
+    }
     return SMC2_OK;
 }
 

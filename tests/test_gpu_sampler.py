@@ -361,3 +361,37 @@ def test_sample_count_limits_sampled_parity(N):
         if N == 2 and k > 1:
             assert s.records()[k - 1][4] == 1
     s.close()
+
+
+@pytest.mark.parametrize("proposal,graph", [(G.PROP_RW, 0), (G.PROP_MLP, 0), (G.PROP_RW, 1)])
+def test_step_info_matches_records_counter_and_timing(proposal, graph):
+    """smc2_info per iteration: the record's scalars, the executed particle-steps of the
+    iteration (summing to the run's counter), and phase times that add up within the
+    step's (the phases are not timed inside a replayed graph)."""
+    w = dict(W.preset("seir_learned"), T=40, proposal=proposal, mlp_epochs=2, mlp_batch=256, mlp_lr=3e-3)
+    y = W.observations(w)
+    runs = [dict(T=y.shape[0], nx=128, seed=sd, y=y) for sd in (3, 4)]
+    s = G.Sampler(w, runs, N=512, K=3, use_graph=graph)
+    for _ in range(3):
+        s.step()
+    RL = G.record_len(w["D"])
+    for r in range(2):
+        rec = s.records(r)
+        tot = 0
+        for k in range(1, 4):
+            inf = s.info(k, run=r)
+            assert inf["k"] == k and inf["ess"] == rec[k - 1, 1] and inf["resampled"] == rec[k - 1, 2]
+            assert inf["dead"] == rec[k - 1, 3] and inf["lkernel_fallback"] == rec[k - 1, 4]
+            assert inf["log_weight_sum"] == rec[k - 1, 5] and inf["learned"] == rec[k - 1, RL - 2]
+            assert 0 < inf["particle_steps"] <= 512 * 128 * 40
+            tot += inf["particle_steps"]
+            assert 0 < inf["ms_filters"] < inf["ms_step"]
+            if graph:
+                assert inf["ms_outer"] == -1 and inf["ms_mlp"] == -1
+            else:
+                assert inf["ms_outer"] > 0 and inf["ms_filters"] + inf["ms_outer"] + inf["ms_mlp"] <= inf["ms_step"] * 1.001
+                assert (inf["ms_mlp"] > 0) == (proposal == G.PROP_MLP)
+        assert tot == int(s.dump("psteps", r)[0])
+    with pytest.raises(G.Smc2Error):
+        s.info(4)
+    s.close()
