@@ -43,6 +43,8 @@ struct MlpArrays {
     float* rows;      // [R][N][MLP_ROW] the population whitened in the current frame (training scratch)
     double* wfull;    // [R][N] N w_i, the normalised weights times N (training scratch)
     float* gpart;     // [R][nsub][NP] gradients of the sub-batches of a minibatch (split training)
+    int32_t* done;    // [R] sub-batch workgroups of the current minibatch that have written their
+                      //     gradient (split training; the last one takes the Adam step and resets it)
 };
 
 struct MlpParams {

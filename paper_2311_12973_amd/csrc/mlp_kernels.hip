@@ -153,15 +153,42 @@ __device__ void mlp_load_weights(int D, const float* w, MlpW* L)
     for (int i = tid; i < MLP_PPAD; i += nthr) L->b3[i] = i < P ? b3[i] : 0.f;
 }
 
+// gfx950's 16 x 16 x 32 BF16 product: lane l holds row (A) / column (B) l % 16 at
+// k = 8 (l / 16) .. + 7; the accumulator layout is that of the 16 x 16 x 16 form. The
+// helpers below take k in steps of 32, and a K that leaves 16 over in one 16 x 16 x 16
+// step (lane l: k = 4 (l / 16) .. + 3).
+typedef short bf16x8s __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f32x4 mfma_k32(bf16x8s a, bf16x8s b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+}
+
 // acc[t] += A[16 x K] W_t^T for NT output tiles: A rows FP32 (stride lda), rounded to
 // BF16 once per k-step and shared by the tiles; W[n][k] BF16 (stride ldw), tile t from
 // row 16 t. The tiles' independent chains interleave; each accumulates over k in order.
 template <int K, int NT>
 __device__ __forceinline__ void mm_a_wt(const float* A, int lda, const short* W, int ldw, f32x4 (&acc)[NT])
 {
-    const int l = lane_id(), i = l & 15, kq = (l >> 4) << 2;
+    const int l = lane_id(), i = l & 15;
 #pragma unroll
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int k0 = 0; k0 + 32 <= K; k0 += 32) {
+        const int kq = (l >> 4) << 3;
+        bf16x8s a;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) a[c] = f2bf(A[i * lda + k0 + kq + c]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            bf16x8s b;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) b[c] = W[(t * 16 + i) * ldw + k0 + kq + c];
+            acc[t] = mfma_k32(a, b, acc[t]);
+        }
+    }
+    const int kq = (l >> 4) << 2;
+#pragma unroll
+    for (int k0 = K - K % 32; k0 < K; k0 += 16) {
         bf16x4 a;
 #pragma unroll
         for (int c = 0; c < 4; ++c) a[c] = f2bf(A[i * lda + k0 + kq + c]);
@@ -179,9 +206,24 @@ __device__ __forceinline__ void mm_a_wt(const float* A, int lda, const short* W,
 template <int K, int NT>
 __device__ __forceinline__ void mm_a_w(const float* A, int lda, const short* W, int ldw, f32x4 (&acc)[NT])
 {
-    const int l = lane_id(), i = l & 15, kq = (l >> 4) << 2;
+    const int l = lane_id(), i = l & 15;
 #pragma unroll
-    for (int k0 = 0; k0 < K; k0 += 16) {
+    for (int k0 = 0; k0 + 32 <= K; k0 += 32) {
+        const int kq = (l >> 4) << 3;
+        bf16x8s a;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) a[c] = f2bf(A[i * lda + k0 + kq + c]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            bf16x8s b;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) b[c] = W[(k0 + kq + c) * ldw + t * 16 + i];
+            acc[t] = mfma_k32(a, b, acc[t]);
+        }
+    }
+    const int kq = (l >> 4) << 2;
+#pragma unroll
+    for (int k0 = K - K % 32; k0 < K; k0 += 16) {
         bf16x4 a;
 #pragma unroll
         for (int c = 0; c < 4; ++c) a[c] = f2bf(A[i * lda + k0 + kq + c]);
@@ -199,16 +241,17 @@ __device__ __forceinline__ void mm_a_w(const float* A, int lda, const short* W, 
 // YT[n][row] (stride LDT) of the tile's first output row / column
 __device__ __forceinline__ f32x4 mm_t(const short* XT, const short* YT, f32x4 acc)
 {
-    const int l = lane_id(), i = l & 15, kq = (l >> 4) << 2;
+    static_assert(MLP_SUB % 32 == 0, "sub-batch rows in steps of 32");
+    const int l = lane_id(), i = l & 15, kq = (l >> 4) << 3;
 #pragma unroll
-    for (int k0 = 0; k0 < MLP_SUB; k0 += 16) {
-        bf16x4 a, b;
+    for (int k0 = 0; k0 < MLP_SUB; k0 += 32) {
+        bf16x8s a, b;
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < 8; ++c) {
             a[c] = XT[i * LDT + k0 + kq + c];
             b[c] = YT[i * LDT + k0 + kq + c];
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        acc = mfma_k32(a, b, acc);
     }
     return acc;
 }
@@ -928,81 +971,14 @@ __global__ void __launch_bounds__(256) k_mlp_prep(MlpArrays m, MlpParams p, Oute
     mlp_train_prologue<D>(m, p, o, r, A, red, frs);
 }
 
-// gradient of sub-batch blockIdx.x (rows b0 + 64 s .. of the minibatch of nb rows at b0)
-// of epoch ep, run blockIdx.y, into m.gpart[r][s]
-template <int D>
-__global__ void __launch_bounds__(256) k_mlp_sub(MlpArrays m, MlpParams p, OuterArrays o, const uint64_t* seeds,
-                                                 int ep, int b0, int nb)
-{
-    const int s = (int)blockIdx.x, r = (int)blockIdx.y;
-    const int s0 = s * MLP_SUB;
-    if (o.status[r] != 0 || s0 >= nb) return;
-    const int tid = (int)threadIdx.x;
-    const int N = p.N, NP = mlp_nparams(D);
-    const int k = *o.k_dev;
-    extern __shared__ __align__(16) unsigned char smem[];
-    MlpW* W = reinterpret_cast<MlpW*>(smem);
-    MlpAct* A = reinterpret_cast<MlpAct*>(smem + sizeof(MlpW));
-    mlp_load_weights(D, m.params + (size_t)r * NP, W);
-    const float* rows = m.rows + (size_t)r * N * MLP_ROW;
-    const double* wfull = m.wfull + (size_t)r * N;
-    if (tid < MLP_SUB) {
-        uint64_t ta, tb, ia, ib;
-        mlp_perm_dev(seeds[r], (uint32_t)k, (uint32_t)ep, 0u, N, ta, tb);
-        mlp_perm_dev(seeds[r], (uint32_t)k, (uint32_t)ep, 1u, N, ia, ib);
-        float u[MLP_ROW], t[MLP_ROW], wr = 0.f;
-#pragma unroll
-        for (int d = 0; d < MLP_ROW; ++d) u[d] = t[d] = 0.f;
-        if (s0 + tid < nb) {
-            const int rr = b0 + s0 + tid;
-            const int jt = (int)((ta * (uint64_t)rr + tb) % (uint64_t)N);
-            const int ii = (int)((ia * (uint64_t)rr + ib) % (uint64_t)N);
-#pragma unroll
-            for (int d = 0; d < MLP_ROW; ++d) {
-                u[d] = rows[(size_t)ii * MLP_ROW + d];
-                t[d] = rows[(size_t)jt * MLP_ROW + d];
-            }
-            wr = (float)(wfull[jt] / (double)nb);
-        }
-#pragma unroll
-        for (int d = 0; d < 16; ++d) {
-            const float ud = d < MLP_ROW ? u[d] : 0.f;
-            A->U[tid * LD16 + d] = ud;
-            A->TU[d * LDT + tid] = f2bf(ud);
-        }
-#pragma unroll
-        for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = t[d];
-        A->wr[tid] = wr;
-    }
-    __syncthreads();
-    f32x4 acc[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float bb3 = 0.f, bb2 = 0.f, bb1 = 0.f;
-    mlp_fwd16<true>(W, A, wave_id() * 16);
-    if (lane_id() < 16) mlp_row_nll<D>(A, wave_id() * 16 + lane_id(), A->wr[wave_id() * 16 + lane_id()], true);
-    wave_sync();
-    mlp_copy_ograd(A, wave_id() * 16);
-    mlp_bwd16(W, A, wave_id() * 16);
-    mlp_bias16(A, wave_id() * 16, bb3, bb2, bb1);
-    __syncthreads();
-    mlp_wgrad(A, acc);
-    __syncthreads();  // the bias sums below reuse the activations' LDS
-    float* gp = m.gpart + ((size_t)r * p.nsub + s) * NP;
-    mlp_scatter_wgrad<D>(acc, gp);
-    mlp_bias_write<D>(A->H1, bb3, bb2, bb1, gp);
-}
-
 // the minibatch gradient (the nsub_b sub-batch gradients summed in order), its global
-// norm clipped to MLP_CLIP, and one Adam step on the master weights of run blockIdx.x
+// norm clipped to MLP_CLIP, and one Adam step on the master weights of run r, by one
+// 256-thread workgroup (red: block-reduction LDS)
 template <int D>
-__global__ void __launch_bounds__(256) k_mlp_adam(MlpArrays m, MlpParams p, OuterArrays o, int nsub_b)
+__device__ __forceinline__ void mlp_adam_step(const MlpArrays& m, const MlpParams& p, int r, int nsub_b, double* red)
 {
-    const int r = (int)blockIdx.x;
-    if (o.status[r] != 0) return;
     const int tid = (int)threadIdx.x;
     const int NP = mlp_nparams(D);
-    __shared__ double red[16 * (2 * DMAX + 1)];
     const float* gp = m.gpart + (size_t)r * p.nsub * NP;
     float* grad = m.grad + (size_t)r * NP;
     float* prm = m.params + (size_t)r * NP;
@@ -1071,6 +1047,84 @@ __global__ void __launch_bounds__(256) k_mlp_adam(MlpArrays m, MlpParams p, Oute
     }
     __syncthreads();  // every thread has read the step count
     if (tid == 0) m.adam_t[r] = t_adam;
+}
+
+// gradient of sub-batch blockIdx.x (rows b0 + 64 s .. of the minibatch of nb rows at b0)
+// of epoch ep, run blockIdx.y, into m.gpart[r][s]; the last of the minibatch's nsub_b
+// workgroups to finish then takes the Adam step (a count per run, no waiting: each
+// workgroup releases its gradient device-wide before counting itself, the last one
+// acquires before reading them all, and resets the count for the next minibatch)
+template <int D>
+__global__ void __launch_bounds__(256) k_mlp_sub(MlpArrays m, MlpParams p, OuterArrays o, const uint64_t* seeds,
+                                                 int ep, int b0, int nb, int nsub_b)
+{
+    const int s = (int)blockIdx.x, r = (int)blockIdx.y;
+    const int s0 = s * MLP_SUB;
+    if (o.status[r] != 0 || s0 >= nb) return;
+    const int tid = (int)threadIdx.x;
+    const int N = p.N, NP = mlp_nparams(D);
+    const int k = *o.k_dev;
+    extern __shared__ __align__(16) unsigned char smem[];
+    MlpW* W = reinterpret_cast<MlpW*>(smem);
+    MlpAct* A = reinterpret_cast<MlpAct*>(smem + sizeof(MlpW));
+    mlp_load_weights(D, m.params + (size_t)r * NP, W);
+    const float* rows = m.rows + (size_t)r * N * MLP_ROW;
+    const double* wfull = m.wfull + (size_t)r * N;
+    if (tid < MLP_SUB) {
+        uint64_t ta, tb, ia, ib;
+        mlp_perm_dev(seeds[r], (uint32_t)k, (uint32_t)ep, 0u, N, ta, tb);
+        mlp_perm_dev(seeds[r], (uint32_t)k, (uint32_t)ep, 1u, N, ia, ib);
+        float u[MLP_ROW], t[MLP_ROW], wr = 0.f;
+#pragma unroll
+        for (int d = 0; d < MLP_ROW; ++d) u[d] = t[d] = 0.f;
+        if (s0 + tid < nb) {
+            const int rr = b0 + s0 + tid;
+            const int jt = (int)((ta * (uint64_t)rr + tb) % (uint64_t)N);
+            const int ii = (int)((ia * (uint64_t)rr + ib) % (uint64_t)N);
+#pragma unroll
+            for (int d = 0; d < MLP_ROW; ++d) {
+                u[d] = rows[(size_t)ii * MLP_ROW + d];
+                t[d] = rows[(size_t)jt * MLP_ROW + d];
+            }
+            wr = (float)(wfull[jt] / (double)nb);
+        }
+#pragma unroll
+        for (int d = 0; d < 16; ++d) {
+            const float ud = d < MLP_ROW ? u[d] : 0.f;
+            A->U[tid * LD16 + d] = ud;
+            A->TU[d * LDT + tid] = f2bf(ud);
+        }
+#pragma unroll
+        for (int d = 0; d < 8; ++d) A->UT[tid * 8 + d] = t[d];
+        A->wr[tid] = wr;
+    }
+    __syncthreads();
+    f32x4 acc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bb3 = 0.f, bb2 = 0.f, bb1 = 0.f;
+    mlp_fwd16<true>(W, A, wave_id() * 16);
+    if (lane_id() < 16) mlp_row_nll<D>(A, wave_id() * 16 + lane_id(), A->wr[wave_id() * 16 + lane_id()], true);
+    wave_sync();
+    mlp_copy_ograd(A, wave_id() * 16);
+    mlp_bwd16(W, A, wave_id() * 16);
+    mlp_bias16(A, wave_id() * 16, bb3, bb2, bb1);
+    __syncthreads();
+    mlp_wgrad(A, acc);
+    __syncthreads();  // the bias sums below reuse the activations' LDS
+    float* gp = m.gpart + ((size_t)r * p.nsub + s) * NP;
+    mlp_scatter_wgrad<D>(acc, gp);
+    mlp_bias_write<D>(A->H1, bb3, bb2, bb1, gp);
+    __shared__ int last;
+    __shared__ double red[16 * (2 * DMAX + 1)];
+    __threadfence();
+    __syncthreads();
+    if (tid == 0) last = atomicAdd(m.done + r, 1) == nsub_b - 1 ? 1 : 0;
+    __syncthreads();
+    if (!uniform_bool(last != 0)) return;
+    __threadfence();
+    mlp_adam_step<D>(m, p, r, nsub_b, red);
+    if (tid == 0) m.done[r] = 0;
 }
 
 // held-out sums of sub-batch blockIdx.x of run blockIdx.y, into the run's scratch as
@@ -1259,8 +1313,7 @@ hipError_t launch_mlp_train(const MlpArrays& m, const MlpParams& p, const OuterA
             const int nsub_b = (nb + MLP_SUB - 1) / MLP_SUB;
             const dim3 grid((unsigned)nsub_b, (unsigned)p.R);
 #define CALL_STEP(DD)                                                                                           \
-    hipLaunchKernelGGL(k_mlp_sub<DD>, grid, dim3(256), MLP_LDS_TRAIN, s, m, p, o, seeds, ep, b0, nb);            \
-    hipLaunchKernelGGL(k_mlp_adam<DD>, runs, dim3(256), 0, s, m, p, o, nsub_b);
+    hipLaunchKernelGGL(k_mlp_sub<DD>, grid, dim3(256), MLP_LDS_TRAIN, s, m, p, o, seeds, ep, b0, nb, nsub_b);
             MLP_DISPATCH(p.D, CALL_STEP)
 #undef CALL_STEP
             e = hipGetLastError();

@@ -63,7 +63,7 @@ struct Layout {
     size_t off_k, off_status, off_seeds, off_runs, off_y, off_prior, off_lrw, off_phi, off_phin, off_thn, off_lp,
         off_ll, off_logw, off_lpn, off_lln, off_lwp, off_scr, off_qc, off_anc, off_active, off_rec, off_items,
         off_queues, off_tune_items, off_mlp_params, off_mlp_m, off_mlp_v, off_mlp_grad, off_mlp_t, off_mlp_frame,
-        off_mlp_use, off_mlp_out, off_mlp_logq, off_mlp_score, off_mlp_rows, off_mlp_wfull, off_mlp_gpart,
+        off_mlp_use, off_mlp_done, off_mlp_out, off_mlp_logq, off_mlp_score, off_mlp_rows, off_mlp_wfull, off_mlp_gpart,
         off_psteps, off_lkfit, off_psteps_at;
     size_t take(size_t bytes)
     {
@@ -116,6 +116,7 @@ Layout make_layout(const smc2_config* c, int R, const smc2_run* runs)
     L.off_mlp_t = L.take(sizeof(int32_t) * Rm);
     L.off_mlp_frame = L.take(sizeof(double) * Rm * (D + D * D));
     L.off_mlp_use = L.take(sizeof(int32_t) * Rm);
+    L.off_mlp_done = L.take(sizeof(int32_t) * Rm);
     L.off_mlp_out = L.take(sizeof(float) * Rm * N * P);
     L.off_mlp_logq = L.take(sizeof(double) * Rm * N);
     L.off_mlp_score = L.take(sizeof(double) * Rm * 2);
@@ -518,6 +519,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
         ma.rows = (float*)(w + lay.off_mlp_rows);
         ma.wfull = (double*)(w + lay.off_mlp_wfull);
         ma.gpart = (float*)(w + lay.off_mlp_gpart);
+        ma.done = (int32_t*)(w + lay.off_mlp_done);
         o.mlp_use = ma.use;
         o.mlp_out = ma.out;
         o.mlp_frame = ma.frame;
@@ -582,7 +584,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
         init_params.resize(NP * n_runs);
         for (int r = 0; r < n_runs; ++r) mlp_init_host(cfg->D, runs[r].seed, init_params.data() + NP * r);
         H2D(lay.off_mlp_params, init_params.data(), sizeof(float) * init_params.size());
-        const size_t zero_from = lay.off_mlp_m, zero_to = lay.off_mlp_out;  // moments, grad, steps, frame, use
+        const size_t zero_from = lay.off_mlp_m, zero_to = lay.off_mlp_out;  // moments, grad, steps, frame, use, count
         if (e == hipSuccess) e = hipMemsetAsync(w + zero_from, 0, zero_to - zero_from, s);
         if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_mlp_score, 0, sizeof(double) * 2 * n_runs, s);
     }
