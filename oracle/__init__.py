@@ -104,6 +104,11 @@ def _declare(L):
     L.or_pf_replay.restype = c.c_double
     L.or_pf_replay.argtypes = [P(Config), P(c.c_double), P(c.c_int32), c.c_int, c.c_int, P(c.c_int32),
                                P(c.c_int32), P(c.c_int32), P(c.c_double)]
+    L.or_pmcmc_run.restype = c.c_int
+    L.or_pmcmc_run.argtypes = [P(Config), P(c.c_int32), c.c_int, c.c_int, c.c_uint64, c.c_int, c.c_int, c.c_int,
+                               P(c.c_double), P(c.c_double), P(c.c_int32)]
+    L.or_mh_accept.restype = c.c_int
+    L.or_mh_accept.argtypes = [c.c_double] * 5
     L.or_prior_draw.argtypes = [P(Config), c.c_int, c.c_uint64, P(c.c_double), P(c.c_double)]
     L.or_propose_rw.argtypes = [P(Config), c.c_int, c.c_uint64, c.c_uint32, P(c.c_double),
                                 P(c.c_double), P(c.c_double)]
@@ -362,6 +367,24 @@ def pf_replay(cfg, theta, y, state, anc, rs):
                             _p(state, ctypes.c_int32), _p(anc, ctypes.c_int32), _p(rs, ctypes.c_int32),
                             _p(inc, ctypes.c_double))
     return ll, inc
+
+
+def pmcmc_run(cfg, y, nx, seed, chains, iters, n_threads=0):
+    """Particle marginal Metropolis-Hastings: (theta [chains][iters+1][D], ll [chains][iters+1],
+    accepted [chains][iters])."""
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    T = y.shape[0]
+    th = np.zeros((chains, iters + 1, cfg.D))
+    ll = np.zeros((chains, iters + 1))
+    acc = np.zeros((chains, iters), dtype=np.int32)
+    st = lib().or_pmcmc_run(ctypes.byref(cfg), _p(y, ctypes.c_int32), T, nx, int(seed), chains, iters, n_threads,
+                            _p(th, ctypes.c_double), _p(ll, ctypes.c_double), _p(acc, ctypes.c_int32))
+    assert st == 0
+    return th, ll, acc
+
+
+def mh_accept(lp, ll, lp_new, ll_new, u):
+    return bool(lib().or_mh_accept(lp, ll, lp_new, ll_new, u))
 
 
 def prior_draw(cfg, N, seed):

@@ -784,6 +784,104 @@ int or_outer_update(const or_config* cfg, int N, uint32_t k, uint64_t seed,
     return 0;
 }
 
+/* ------------------------------------------------------------------ p-MCMC
+ * Particle marginal Metropolis-Hastings (Sec. III, after Andrieu, Doucet and Holenstein):
+ * a random-walk Metropolis-Hastings chain on the sampler coordinates whose target density
+ * uses the particle filter's likelihood estimate. The estimate of the current state is
+ * kept until a proposal is accepted (the estimate travels with its state), which makes the
+ * chain target the exact posterior for any number of particles. With the symmetric random
+ * walk the proposal densities of Eq. MHalgorithm_ cancel. A proposal outside the prior's
+ * support is rejected without running its filter.
+ * Random numbers (Philox, key = the seed): the chain's starting point, coordinate d,
+ * from (c, 0, 0, 11<<24 | d) as the SMC^2 prior draw; at iteration m >= 1 the random-walk
+ * normal of coordinate d from (c, 0, m<<16, 9<<24 | d) and the uniform u53 of the words
+ * (0, 1) of (c, 0, m<<16, 10<<24); the filter of chain c at iteration m runs on the
+ * particle-filter streams of filter c and iteration index m (m = 0: the starting point). */
+int or_mh_accept(double lp, double ll, double lp_new, double ll_new, double u)
+{
+    const double cur = lp + ll, nw = lp_new + ll_new;
+    if (nw == -INFINITY) return 0;
+    if (cur == -INFINITY) return 1;
+    return log(u) < nw - cur;
+}
+
+static void or_mcmc_start(const or_config* cfg, uint64_t seed, uint32_t c, double* phi)
+{
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int d = 0; d < cfg->D; ++d) {
+        const uint32_t ctr[4] = {c, 0u, 0u, ((uint32_t)OR_S_MCMC_INIT << 24) | (uint32_t)d};
+        uint32_t w[4];
+        or_philox(ctr, key, w);
+        const double u1 = or_u53(w[0], w[1]), u2 = or_u53(w[2], w[3]);
+        const int fam = (int)cfg->prior[d][0];
+        const double a = cfg->prior[d][1], b = cfg->prior[d][2];
+        if (fam == OR_PRIOR_UNIFORM) phi[d] = a + (b - a) * u1;
+        else phi[d] = a + b * (sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2));
+    }
+}
+
+int or_pmcmc_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t seed, int chains, int iters,
+                 int n_threads, double* theta_trace, double* ll_trace, int32_t* acc_trace)
+{
+    const int D = cfg->D;
+    double C[OR_DMAX * OR_DMAX], L[OR_DMAX * OR_DMAX];
+    for (int a = 0; a < D; ++a)
+        for (int b = 0; b < D; ++b) C[a * D + b] = cfg->rw_cov[a][b];
+    if (or_cholesky(D, C, L) != 0) return -1;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#else
+    (void)n_threads;
+#endif
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int c = 0; c < chains; ++c) {
+        double phi[OR_DMAX], phn[OR_DMAX], th[OR_DMAX];
+        or_mcmc_start(cfg, seed, (uint32_t)c, phi);
+        double lp = or_prior_logpdf(cfg, phi), ll = -INFINITY;
+        if (lp != -INFINITY) {
+            or_theta_of_phi(cfg, phi, th);
+            ll = or_pf_loglik(cfg, th, y, T, nx, seed, (uint32_t)c, 0u, NULL, NULL);
+        }
+        for (int m = 0; m <= iters; ++m) {
+            if (m > 0) {
+                double z[OR_DMAX];
+                for (int d = 0; d < D; ++d) {
+                    const uint32_t ctr[4] = {(uint32_t)c, 0u, (uint32_t)m << 16, ((uint32_t)OR_S_MCMC_RW << 24) | (uint32_t)d};
+                    z[d] = or_normal_call(seed, ctr);
+                }
+                for (int d = 0; d < D; ++d) {
+                    double acc = 0.0;
+                    for (int e = 0; e <= d; ++e) acc += L[d * D + e] * z[e];
+                    phn[d] = phi[d] + acc;
+                }
+                const double lpn = or_prior_logpdf(cfg, phn);
+                double lln = -INFINITY;
+                if (lpn != -INFINITY) {
+                    or_theta_of_phi(cfg, phn, th);
+                    lln = or_pf_loglik(cfg, th, y, T, nx, seed, (uint32_t)c, (uint32_t)m, NULL, NULL);
+                }
+                const uint32_t ctr[4] = {(uint32_t)c, 0u, (uint32_t)m << 16, (uint32_t)OR_S_MCMC_U << 24};
+                uint32_t w[4];
+                or_philox(ctr, key, w);
+                const int acc = or_mh_accept(lp, ll, lpn, lln, or_u53(w[0], w[1]));
+                if (acc) {
+                    for (int d = 0; d < D; ++d) phi[d] = phn[d];
+                    lp = lpn;
+                    ll = lln;
+                }
+                if (acc_trace) acc_trace[(size_t)c * iters + (m - 1)] = acc;
+            }
+            if (theta_trace) {
+                or_theta_of_phi(cfg, phi, th);
+                for (int d = 0; d < D; ++d) theta_trace[((size_t)c * (iters + 1) + m) * D + d] = th[d];
+            }
+            if (ll_trace) ll_trace[(size_t)c * (iters + 1) + m] = ll;
+        }
+    }
+    return 0;
+}
+
 /* Recycled estimate (Sec. IV-C): c_k = l_k / sum l, mean = sum c_k f_k; the covariance
  * combines the per-iteration second moments with the same constants. */
 void or_recycle(int K, int D, const double* rec, double* mean, double* cov, double* c_out)

@@ -35,7 +35,7 @@ enum { OR_PROP_RW = 0, OR_PROP_MLP = 1 };
 
 /* Philox stream identifiers (bits 24..31 of the fourth counter word). */
 enum { OR_S_PF_PROP = 1, OR_S_PF_RS = 2, OR_S_PRIOR = 3, OR_S_RW = 4, OR_S_OUTER_RS = 5,
-       OR_S_MLP_INIT = 6, OR_S_MLP_PERM = 7 };
+       OR_S_MLP_INIT = 6, OR_S_MLP_PERM = 7, OR_S_MCMC_RW = 9, OR_S_MCMC_U = 10, OR_S_MCMC_INIT = 11 };
 
 #define OR_DMAX 8
 
@@ -116,6 +116,18 @@ double or_pf_trace_full(const or_config* cfg, const double* theta, const int32_t
  * rs int32[T] resampling flags; inc_out (T, optional) the per-day increments. */
 double or_pf_replay(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx,
                     const int32_t* state, const int32_t* anc, const int32_t* rs, double* inc_out);
+
+/* ---- particle marginal Metropolis-Hastings (Sec. III), the paper's comparison ----
+ * `chains` independent chains of `iters` random-walk Metropolis-Hastings iterations each;
+ * theta_trace [chains][iters+1][D] (state 0: the prior draw the chain starts from),
+ * ll_trace [chains][iters+1], acc_trace [chains][iters] (may each be NULL). */
+int or_pmcmc_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t seed, int chains, int iters,
+                 int n_threads, double* theta_trace, double* ll_trace, int32_t* acc_trace);
+/* The Metropolis-Hastings decision of Eq. MHalgorithm_ for a symmetric proposal, from
+ * the log prior and log-likelihood estimate of the current and proposed states and the
+ * uniform u in (0, 1): accept when the proposal has positive target and either the
+ * current state has none or log u < (lp_new + ll_new) - (lp + ll). */
+int or_mh_accept(double lp, double ll, double lp_new, double ll_new, double u);
 
 /* ---- the outer sampler (Sec. IV) ---- */
 void or_prior_draw(const or_config* cfg, int N, uint64_t seed, double* phi, double* lp);

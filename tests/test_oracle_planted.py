@@ -9,14 +9,19 @@ plausible mistake planted (tests/planted.py) fail the pin that the reference pas
   reset after resampling) against the Kalman filter: a dropped log S_prev, S_prev not
   updated, no weight reset after resampling, log-weights not re-based on the maximum,
   and ancestors shifted by one slot.
+* The p-MCMC acceptance (Sec. III, Eq. MHalgorithm_) against the exact grid posterior:
+  the prior dropped from the ratio, and the current state's likelihood estimate drawn
+  afresh every iteration instead of travelling with the state.
 """
 import concurrent.futures as cf
 
+import numpy as np
 import pytest
 
 from tests import planted as PL
 from tests.test_oracle_kalman import kalman_pin_statistic
 from tests.test_oracle_pf_exact import age_pin_statistic
+from tests.test_oracle_pmcmc import pmcmc_pin_statistic
 
 COEF = "mc.cs[g][h] = (REAL)(((beta * s[g]) * cfg->fixed[4 * g + h]) / ngs[h]);"
 AGE_PLANTS = {
@@ -34,10 +39,21 @@ KALMAN_PLANTS = {
 }
 
 
+PMCMC_PLANTS = {
+    "prior_dropped_from_the_ratio": [("smc2_oracle.c", "    const double cur = lp + ll, nw = lp_new + ll_new;",
+                                      "    const double cur = ll, nw = ll_new;")],
+    # the current state's estimate refreshed every iteration (Monte Carlo within Metropolis)
+    "estimate_not_kept": [("smc2_oracle.c", "                const int acc = or_mh_accept(lp, ll, lpn, lln, or_u53(w[0], w[1]));",
+                           "                if (lp != -INFINITY) { or_theta_of_phi(cfg, phi, th); ll = or_pf_loglik(cfg, th, y, T, nx, "
+                           "seed, (uint32_t)c, (uint32_t)(m + 40000), NULL, NULL); }\n"
+                           "                const int acc = or_mh_accept(lp, ll, lpn, lln, or_u53(w[0], w[1]));")],
+}
+
+
 @pytest.fixture(scope="module")
 def planted_libs(tmp_path_factory):
     d = str(tmp_path_factory.mktemp("planted"))
-    plants = dict(AGE_PLANTS, **KALMAN_PLANTS)
+    plants = dict(AGE_PLANTS, **KALMAN_PLANTS, **PMCMC_PLANTS)
     with cf.ThreadPoolExecutor(max_workers=4) as ex:
         futs = {name: ex.submit(PL.build_planted, name, edits, d) for name, edits in plants.items()}
         return {name: f.result() for name, f in futs.items()}
@@ -64,3 +80,11 @@ def test_kalman_pin_catches_a_broken_weight_recursion(planted_libs, name):
         mean, se = kalman_pin_statistic()
     print(name, mean, se)
     assert abs(mean - 1.0) > 4 * se + 1e-3, (name, mean, se)
+
+
+@pytest.mark.parametrize("name", sorted(PMCMC_PLANTS))
+def test_pmcmc_pin_catches_a_wrong_acceptance(planted_libs, name):
+    with PL.installed(planted_libs[name]):
+        mean, se, sd, gm, gsd, rate = pmcmc_pin_statistic()
+    print(name, mean, gm, se, sd, gsd)
+    assert np.any(np.abs(mean - gm) > 4 * se + 2e-3) or np.any(np.abs(sd / gsd - 1) > 0.15), (name, mean, sd)
