@@ -29,7 +29,8 @@ Prints one JSON line.
 * ess_per_s: the metric's second part on the learned-proposal configuration (SEIR,
   D = 5, T = 150, N = 4096, N_x = 1024): recycled ESS per second at a fixed posterior
   error, learned proposal against the random walk (ess_at_fixed_error).
-* secondary: the SEIR configuration (N = 1024, N_x = 512, T = 100, D = 4, RW).
+* secondary: the SEIR configuration (N = 1024, N_x = 512, T = 100, D = 4, RW), and the
+  paper's SIR experiment, SMC^2 against p-MCMC (paper_experiment).
 """
 import argparse
 import concurrent.futures as cf
@@ -211,6 +212,9 @@ def main():
                               "kernel_ms": m2["ms_pf"]}}
         log("secondary seir: %.3g particle-steps/s" % m2["value"])
 
+    if not args.no_secondary:
+        secondary = dict(secondary or {}, paper_sir=paper_experiment(G, W, np))
+
     ess = None
     if not args.no_ess:
         ess = ess_at_fixed_error(G, W, np)
@@ -361,6 +365,49 @@ def cpu_baseline_leg(G, np, m, s, n_filters, n_single=6, n_trace=16):
         precision["filters_fp32_vs_fp64_reference"]["replayed_rel_err_max"],
         precision["outer_fp64_vs_reference"]["logw_rel_err_max"]))
     return cpu, precision
+
+
+def paper_experiment(G, W, np, seed=1):
+    """The paper's SIR experiment (Sec. V, Table II: beta = 0.85, gamma = 0.2, T = 30,
+    N_pop = 1e4, N_x = 500, FP64) on one MI355X, on synthetic data of that model: SMC^2
+    with N = 1024 and K = 10 against p-MCMC with M = K N = 10240 samples, half burned in,
+    as one chain (the paper's sequential form) and as 64 chains of 160 iterations (80
+    burned in), each chain's filter in one launch per iteration. Wall time of the
+    iterations (synchronised), the estimates and their squared error against the truth;
+    the paper's figures (128 CPU cores for SMC^2, one for p-MCMC) beside them as context."""
+    import torch
+    w = W.preset("paper_sir")
+    y = W.observations(w)
+    truth = np.array(w["truth"])
+    run = dict(T=y.shape[0], nx=w["nx"], seed=seed, y=y)
+    out = {"workload": "paper_sir: SIR, T=30, N_pop=1e4, N_x=500, FP64; SMC^2 N=1024 K=10; p-MCMC M=10240"}
+    s = G.Sampler(w, [run], N=w["N"], K=w["K"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(w["K"]):
+        s.step()
+    mean, _ = s.estimate(recycled=True)
+    sec = time.perf_counter() - t0
+    s.close()
+    out["smc2"] = {"seconds": sec, "posterior_mean": mean.tolist(), "squared_error": float(np.mean((mean - truth) ** 2))}
+    for name, chains, iters in (("pmcmc_64_chains", 64, 160), ("pmcmc_1_chain", 1, 10240)):
+        mc = G.PMCMC(w, run, chains, iters)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mc.step(iters)
+        m2, _, rate = mc.estimate(iters // 2)
+        sec2 = time.perf_counter() - t0
+        mc.close()
+        out[name] = {"chains": chains, "iterations": iters, "seconds": sec2, "posterior_mean": m2.tolist(),
+                     "squared_error": float(np.mean((m2 - truth) ** 2)), "acceptance": rate}
+        log("paper_sir: %s %.3f s" % (name, sec2))
+    out["smc2_speedup_vs_pmcmc_1_chain"] = out["pmcmc_1_chain"]["seconds"] / out["smc2"]["seconds"]
+    out["smc2_speedup_vs_pmcmc_64_chains"] = out["pmcmc_64_chains"]["seconds"] / out["smc2"]["seconds"]
+    out["paper_context"] = {"smc2_seconds": 2.39, "smc2_mean": [0.8526, 0.2003], "smc2_mse": 7.75e-5,
+                            "pmcmc_seconds": 130.01, "pmcmc_mean": [0.8628, 0.2038], "pmcmc_mse": 2.42e-4,
+                            "hardware": "SMC^2 on 128 Xeon Gold 6138 cores, p-MCMC on one (Table II)"}
+    log("paper_sir: SMC^2 %.4f s, %.1fx faster than one p-MCMC chain" % (sec, out["smc2_speedup_vs_pmcmc_1_chain"]))
+    return out
 
 
 def ess_at_fixed_error(G, W, np, n_ref=32768, k_ref=(30, 60), ref_seeds=3, seeds=10, k_max=(20, 60),

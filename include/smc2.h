@@ -281,6 +281,56 @@ const char* smc2_last_error(const smc2_ctx* ctx);
  * Host-only; does not touch the device. */
 int smc2_groups(const smc2_ctx* ctx, int32_t max_groups, int32_t* n_groups, int32_t* desc, float* tuned_ms);
 
+/* ------------------------------------------------------------------ p-MCMC
+ * Particle marginal Metropolis-Hastings (Sec. III, Eq. MHalgorithm_), the paper's
+ * comparison method, on the same particle-filter kernels: `chains` independent chains,
+ * each a Gaussian random walk on the sampler coordinates (covariance cfg->rw_cov) whose
+ * target is the prior times the particle filter's likelihood estimate. The estimate of
+ * the current state is kept until a proposal is accepted, so every chain targets the
+ * exact posterior for any N_x (Andrieu, Doucet and Holenstein). The random walk is
+ * symmetric, so the proposal densities of Eq. MHalgorithm_ cancel; a proposal outside
+ * the prior's support is rejected without running its filter. Each chain starts from a
+ * prior draw. Estimates are means over the chains' states after a burn-in.
+ * Uses cfg's model, obs, D, precision, n_pop, prior, rw_cov, fixed, pf_always,
+ * pf_resampling, block and schedule (N, K, proposal, lkernel, tune and the learned
+ * proposal's settings are ignored). Random numbers (Philox, key = run->seed): chain c's
+ * start from counter (c, 0, 0, 11<<24 | d), at iteration m its normals from
+ * (c, 0, m<<16, 9<<24 | d) and its uniform from words 0 and 1 of (c, 0, m<<16, 10<<24);
+ * its filter at iteration m runs as filter c of iteration m (0: the start).
+ * Ownership, errors and synchronisation as for the sampler (smc2_last_error(NULL) gives
+ * the message); smc2_pmcmc_step is asynchronous, the other calls synchronise. */
+typedef struct smc2_pmcmc smc2_pmcmc;
+
+#define SMC2_PMCMC_PHI 0         /* chains x (iterations+1) x D doubles: states (sampler coordinates),
+                                    row 0 the start                                               */
+#define SMC2_PMCMC_LL 1          /* chains x (iterations+1) doubles: their likelihood estimates    */
+#define SMC2_PMCMC_LL_PROPOSED 2 /* chains x iterations doubles: the proposals' estimates (-inf
+                                    outside the prior's support)                                  */
+#define SMC2_PMCMC_ACCEPTED 3    /* chains x iterations int32: 1 where the proposal was accepted  */
+
+/* Workspace bytes for `chains` chains (1..32768) of up to `iters` iterations (0..65535). */
+size_t smc2_pmcmc_workspace_bytes(const smc2_config* cfg, int32_t chains, int32_t iters, const smc2_run* run);
+
+/* Validate, copy the inputs and enqueue the chains' starts and their filters. */
+int smc2_pmcmc_init(const smc2_config* cfg, int32_t chains, int32_t iters, const smc2_run* run, void* d_workspace,
+                    size_t ws_bytes, void* hip_stream, smc2_pmcmc** out);
+
+/* Enqueue n_iter further iterations of every chain; SMC2_E_STATE beyond `iters`. */
+int smc2_pmcmc_step(smc2_pmcmc* ctx, int32_t n_iter);
+
+/* Mean (D) and covariance (D x D, may be NULL) of theta over every chain's states after
+ * the first burn_in iterations, and the acceptance rate over those iterations. */
+int smc2_pmcmc_estimate(smc2_pmcmc* ctx, int32_t burn_in, double* mean, double* cov, double* accept_rate);
+
+/* Copy one of the SMC2_PMCMC_* traces to host memory. */
+int smc2_pmcmc_dump(smc2_pmcmc* ctx, int32_t what, void* host_dst, size_t bytes);
+
+/* Device time of the iterations run by smc2_pmcmc_step (from the first step's start to
+ * the last one's end) and the number of iterations run. */
+int smc2_pmcmc_timing(smc2_pmcmc* ctx, double* ms, int32_t* iterations);
+
+int smc2_pmcmc_destroy(smc2_pmcmc* ctx);
+
 #ifdef __cplusplus
 }
 #endif

@@ -27,6 +27,7 @@ SCHED_AUTO, SCHED_PER_DRAW, SCHED_POOLED = 0, 1, 2
 DUMP = dict(phi=0, lp=1, ll=2, logw=3, phi_new=4, lp_new=5, ll_new=6, logw_pre=7, anc=8, mlp_out=9, logq=10,
             mlp_params=11, mlp_frame=12, mlp_state=13, mlp_grad=14, psteps=15, lkfit=16, theta_new=17)
 MLP_H = 64
+PMCMC_PHI, PMCMC_LL, PMCMC_LL_PROPOSED, PMCMC_ACCEPTED = 0, 1, 2, 3
 
 
 def mlp_nout(D):
@@ -135,6 +136,20 @@ def lib():
         L.smc2_pf_loglik.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp, c.c_size_t, vp]
         L.smc2_pf_loglik_noalloc.restype = c.c_int
         L.smc2_pf_loglik_noalloc.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp]
+        L.smc2_pmcmc_workspace_bytes.restype = c.c_size_t
+        L.smc2_pmcmc_workspace_bytes.argtypes = [P(Config), c.c_int32, c.c_int32, P(Run)]
+        L.smc2_pmcmc_init.restype = c.c_int
+        L.smc2_pmcmc_init.argtypes = [P(Config), c.c_int32, c.c_int32, P(Run), vp, c.c_size_t, vp, P(vp)]
+        L.smc2_pmcmc_step.restype = c.c_int
+        L.smc2_pmcmc_step.argtypes = [vp, c.c_int32]
+        L.smc2_pmcmc_estimate.restype = c.c_int
+        L.smc2_pmcmc_estimate.argtypes = [vp, c.c_int32, P(c.c_double), P(c.c_double), P(c.c_double)]
+        L.smc2_pmcmc_dump.restype = c.c_int
+        L.smc2_pmcmc_dump.argtypes = [vp, c.c_int32, vp, c.c_size_t]
+        L.smc2_pmcmc_timing.restype = c.c_int
+        L.smc2_pmcmc_timing.argtypes = [vp, P(c.c_double), P(c.c_int32)]
+        L.smc2_pmcmc_destroy.restype = c.c_int
+        L.smc2_pmcmc_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -456,3 +471,62 @@ def mlp_grad(D, params, frame, phi_in, phi_t, w, device="cuda"):
     tl, pl = device_buffer(8, device)
     _check(lib().smc2_mlp_grad(D, n, *[b[1] for b in bufs], pg, pl, current_stream()))
     return from_device(tg, pg, np.float32, mlp_nparams(D)), float(from_device(tl, pl, np.float64, 1)[0])
+
+
+# ------------------------------------------------------------------ p-MCMC
+class PMCMC:
+    """Particle marginal Metropolis-Hastings (smc2_pmcmc_*): `chains` independent chains of
+    up to `iters` iterations on the current HIP stream, every chain's filter in one launch
+    per iteration. Uses the workload's model, observations, prior and random-walk
+    covariance; run = dict(T, nx, seed, y)."""
+
+    def __init__(self, w, run, chains, iters, device="cuda", **cfg_over):
+        self.cfg = make_config(w, N=2, K=1, **cfg_over)
+        self.runs = make_runs([run])
+        self.C, self.iters, self.D = int(chains), int(iters), self.cfg.D
+        L = lib()
+        nbytes = L.smc2_pmcmc_workspace_bytes(ctypes.byref(self.cfg), self.C, self.iters, self.runs)
+        if nbytes == 0:
+            _check(E_ARG)
+        self.ws, self.ws_ptr = device_buffer(nbytes, device)
+        h = ctypes.c_void_p()
+        _check(L.smc2_pmcmc_init(ctypes.byref(self.cfg), self.C, self.iters, self.runs, ctypes.c_void_p(self.ws_ptr),
+                                 nbytes, ctypes.c_void_p(current_stream()), ctypes.byref(h)))
+        self.h = h
+
+    def step(self, n=1):
+        _check(lib().smc2_pmcmc_step(self.h, int(n)))
+
+    def estimate(self, burn_in):
+        """(mean, covariance, acceptance rate) over the states after burn_in iterations."""
+        mean = np.zeros(self.D)
+        cov = np.zeros((self.D, self.D))
+        rate = ctypes.c_double()
+        dp = ctypes.POINTER(ctypes.c_double)
+        _check(lib().smc2_pmcmc_estimate(self.h, int(burn_in), mean.ctypes.data_as(dp), cov.ctypes.data_as(dp),
+                                         ctypes.byref(rate)))
+        return mean, cov, rate.value
+
+    def dump(self, what):
+        code = dict(phi=PMCMC_PHI, ll=PMCMC_LL, ll_proposed=PMCMC_LL_PROPOSED, accepted=PMCMC_ACCEPTED)[what]
+        C, I, D = self.C, self.iters, self.D
+        out = {"phi": lambda: np.zeros((C, I + 1, D)), "ll": lambda: np.zeros((C, I + 1)),
+               "ll_proposed": lambda: np.zeros((C, I)), "accepted": lambda: np.zeros((C, I), dtype=np.int32)}[what]()
+        _check(lib().smc2_pmcmc_dump(self.h, code, out.ctypes.data_as(ctypes.c_void_p), out.nbytes))
+        return out
+
+    def timing(self):
+        ms, n = ctypes.c_double(), ctypes.c_int32()
+        _check(lib().smc2_pmcmc_timing(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().smc2_pmcmc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsmc2.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["pf_kernel.hip", "outer_kernels.hip", "mlp_kernels.hip", "kernels_api.hip", "smc2_api.cpp"]
+SOURCES = ["pf_kernel.hip", "outer_kernels.hip", "mlp_kernels.hip", "pmcmc_kernels.hip", "kernels_api.hip", "smc2_api.cpp"]
 
 # -ffp-contract=off: every floating-point operation of the sampler is rounded on its
 # own (the precision conventions are stated per operation); packed FP32 VALU forms

@@ -48,6 +48,33 @@ struct OuterParams {
     int32_t mlp;         // 1: the learned proposal is configured
 };
 
+// model parameter theta_d from the sampler coordinate phi_d of a prior family
+__device__ __forceinline__ double theta_of(int fam, double v)
+{
+    if (fam == PRIOR_LOGNORMAL) return exp(v);
+    if (fam == PRIOR_LOGITNORMAL) return 1.0 / (1.0 + exp(-v));
+    return v;
+}
+
+// log prior density on the sampler coordinates (prior: D x {family, a, b}); -inf outside
+// a uniform prior's support
+template <int D> __device__ __forceinline__ double prior_logpdf(const double* prior, const double* phi)
+{
+    double lp = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; ++d) {
+        const int fam = (int)prior[3 * d];
+        const double a = prior[3 * d + 1], b = prior[3 * d + 2];
+        if (fam == PRIOR_UNIFORM) {
+            lp = (phi[d] >= a && phi[d] <= b && lp != -INFINITY) ? lp + -log(b - a) : -INFINITY;
+        } else {
+            const double zz = (phi[d] - a) / b;
+            lp = lp + ((-0.5 * zz * zz - log(b)) - 0.5 * 1.8378770664093453);
+        }
+    }
+    return lp;
+}
+
 hipError_t launch_begin_iteration(const OuterArrays& o, int32_t* queues, int n_queues, hipStream_t s);
 hipError_t launch_propose(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds, hipStream_t s);
 hipError_t launch_outer_update(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds,

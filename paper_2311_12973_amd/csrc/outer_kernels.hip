@@ -24,13 +24,6 @@ namespace smc2 {
 // relative numerical-rank floor of the L-kernel fit
 #define LK_REL_FLOOR 1e-12
 
-__device__ __forceinline__ double theta_of(int fam, double v)
-{
-    if (fam == PRIOR_LOGNORMAL) return exp(v);
-    if (fam == PRIOR_LOGITNORMAL) return 1.0 / (1.0 + exp(-v));
-    return v;
-}
-
 // Advances the device iteration counter and zeroes the particle filter's work-list
 // counters (a kernel, so that a captured iteration holds no memset node).
 __global__ void k_begin(int32_t* k_dev, int32_t* queues, int n_queues)
@@ -111,18 +104,7 @@ __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, c
     }
     // the learned proposal's density is stored where it proposed; 0 marks the other draws
     if (p.mlp && (k == 1 || !o.mlp_use[r])) o.logq[g] = 0.0;
-    double lpn = 0.0;
-#pragma unroll
-    for (int d = 0; d < D; ++d) {
-        const int fam = (int)p.prior[3 * d];
-        const double a = p.prior[3 * d + 1], b = p.prior[3 * d + 2];
-        if (fam == PRIOR_UNIFORM) {
-            lpn = (phin[d] >= a && phin[d] <= b && lpn != -INFINITY) ? lpn + -log(b - a) : -INFINITY;
-        } else {
-            const double zz = (phin[d] - a) / b;
-            lpn = lpn + ((-0.5 * zz * zz - log(b)) - 0.5 * LOG_2PI);
-        }
-    }
+    const double lpn = prior_logpdf<D>(p.prior, phin);
 #pragma unroll
     for (int d = 0; d < D; ++d) {
         o.phi_new[(size_t)g * D + d] = phin[d];

@@ -17,6 +17,7 @@
 #include "mlp_kernels.h"
 #include "outer_kernels.h"
 #include "pf_kernel.h"
+#include "pmcmc_kernels.h"
 
 using namespace smc2;
 
@@ -919,5 +920,318 @@ extern "C" int smc2_groups(const smc2_ctx* c, int32_t max_groups, int32_t* n_gro
         d[5] = (int32_t)gr.lds;
         if (tuned_ms) tuned_ms[g] = gr.tuned_ms;
     }
+    return SMC2_OK;
+}
+
+// ------------------------------------------------------------------ p-MCMC (Sec. III)
+
+struct smc2_pmcmc {
+    smc2_config cfg{};
+    std::vector<double> prior, rw_cov, fixed;
+    std::vector<int32_t> y;
+    smc2_run run{};
+    int C = 0, iters = 0, m_host = 0;
+    unsigned char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    McArrays ma{};
+    McParams mp{};
+    PFArgs pa{};
+    int block = 0, sched = 0;
+    size_t lds = 0;
+    hipEvent_t ev_first = nullptr, ev_last = nullptr;
+    bool timed = false, poisoned = false;
+};
+
+namespace {
+struct McLayout {
+    size_t total = 0;
+    size_t off_run, off_y, off_prior, off_lrw, off_phi, off_lp, off_ll, off_phin, off_thn, off_lpn, off_lln, off_act,
+        off_m, off_phit, off_llt, off_llnt, off_acct;
+    size_t take(size_t bytes)
+    {
+        const size_t o = total;
+        total += (bytes + 255) & ~(size_t)255;
+        return o;
+    }
+};
+
+McLayout mc_layout(const smc2_config* c, int C, int iters, const smc2_run* run)
+{
+    McLayout L;
+    const size_t D = (size_t)c->D;
+    L.off_run = L.take(sizeof(RunDev));
+    L.off_y = L.take(sizeof(int32_t) * (size_t)run->T * n_obs_of(c->model));
+    L.off_prior = L.take(sizeof(double) * D * 3);
+    L.off_lrw = L.take(sizeof(double) * D * D);
+    L.off_phi = L.take(sizeof(double) * C * D);
+    L.off_lp = L.take(sizeof(double) * C);
+    L.off_ll = L.take(sizeof(double) * C);
+    L.off_phin = L.take(sizeof(double) * C * D);
+    L.off_thn = L.take(sizeof(double) * C * D);
+    L.off_lpn = L.take(sizeof(double) * C);
+    L.off_lln = L.take(sizeof(double) * C);
+    L.off_act = L.take((size_t)C);
+    L.off_m = L.take(sizeof(int32_t));
+    L.off_phit = L.take(sizeof(double) * C * (size_t)(iters + 1) * D);
+    L.off_llt = L.take(sizeof(double) * C * (size_t)(iters + 1));
+    L.off_llnt = L.take(sizeof(double) * C * (size_t)iters);
+    L.off_acct = L.take(sizeof(int32_t) * C * (size_t)iters);
+    return L;
+}
+
+int mc_validate(const smc2_config* cfg, int32_t chains, int32_t iters, const smc2_run* run, std::string& m)
+{
+    if (!cfg || !run) return m = "null config or run", SMC2_E_ARG;
+    if (chains < 1 || chains > 32768) return m = "chains must be in [1, 32768]", SMC2_E_ARG;
+    if (iters < 0 || iters > 65535) return m = "iterations must be in [0, 65535]", SMC2_E_ARG;
+    // the sampler's checks, with the population fields (unused here) set to valid values
+    smc2_config c = *cfg;
+    c.N = 2;
+    c.K = 1;
+    c.proposal = SMC2_PROP_RW;
+    c.lkernel = SMC2_L_GAUSS_OPT;
+    c.tune = 0;
+    c.persistent = 0;
+    c.mlp_train = SMC2_MLP_TRAIN_AUTO;
+    return validate(&c, 1, run, m);
+}
+
+double host_theta_of(int fam, double v)
+{
+    if (fam == SMC2_PRIOR_LOGNORMAL) return std::exp(v);
+    if (fam == SMC2_PRIOR_LOGITNORMAL) return 1.0 / (1.0 + std::exp(-v));
+    return v;
+}
+
+hipError_t mc_filters(smc2_pmcmc* c)
+{
+    return launch_pf(c->cfg.precision, c->cfg.model, c->cfg.obs, c->sched, c->block, c->lds, c->pa, c->stream);
+}
+}  // namespace
+
+extern "C" size_t smc2_pmcmc_workspace_bytes(const smc2_config* cfg, int32_t chains, int32_t iters, const smc2_run* run)
+{
+    std::string m;
+    if (mc_validate(cfg, chains, iters, run, m) != SMC2_OK) {
+        g_thread_error = m;
+        return 0;
+    }
+    return mc_layout(cfg, chains, iters, run).total;
+}
+
+extern "C" int smc2_pmcmc_init(const smc2_config* cfg, int32_t chains, int32_t iters, const smc2_run* run,
+                               void* d_workspace, size_t ws_bytes, void* hip_stream, smc2_pmcmc** out)
+{
+    if (!out) return g_thread_error = "out is NULL", SMC2_E_ARG;
+    *out = nullptr;
+    std::string m;
+    int rc = mc_validate(cfg, chains, iters, run, m);
+    if (rc != SMC2_OK) return g_thread_error = m, rc;
+    const McLayout L = mc_layout(cfg, chains, iters, run);
+    if (!d_workspace || ws_bytes < L.total || ((uintptr_t)d_workspace & 255u))
+        return g_thread_error = "workspace missing, too small or not 256-byte aligned", SMC2_E_ARG;
+    const int block = cfg->block ? cfg->block : pf_default_block(cfg->model, cfg->precision, run->n_x, run->T, cfg->schedule);
+    const int sched = pf_pick_schedule(cfg->model, cfg->precision, block, run->n_x, run->T, cfg->schedule);
+    if (sched < 0) return g_thread_error = "the pooled schedule cannot run this model, n_x and T", SMC2_E_ARG;
+    const size_t lds = pf_lds_bytes(cfg->model, cfg->precision, block, run->n_x, run->T, sched);
+    if (lds > PF_LDS_MAX) return g_thread_error = "particle filter does not fit in LDS", SMC2_E_ARG;
+
+    smc2_pmcmc* c = new smc2_pmcmc();
+    c->cfg = *cfg;
+    c->prior.assign(cfg->prior, cfg->prior + cfg->D * 3);
+    c->rw_cov.assign(cfg->rw_cov, cfg->rw_cov + cfg->D * cfg->D);
+    c->fixed.assign(SMC2_NFIXED, 0.0);
+    for (int i = 0; i < cfg->n_fixed; ++i) c->fixed[i] = cfg->fixed[i];
+    c->cfg.prior = c->prior.data();
+    c->cfg.rw_cov = c->rw_cov.data();
+    c->cfg.fixed = c->fixed.data();
+    c->y.assign(run->y, run->y + (size_t)run->T * n_obs_of(cfg->model));
+    c->run = *run;
+    c->run.y = c->y.data();
+    c->C = chains;
+    c->iters = iters;
+    c->ws = (unsigned char*)d_workspace;
+    c->stream = (hipStream_t)hip_stream;
+    c->block = block;
+    c->sched = sched;
+    c->lds = lds;
+    unsigned char* w = c->ws;
+    McArrays& a = c->ma;
+    a.phi = (double*)(w + L.off_phi);
+    a.lp = (double*)(w + L.off_lp);
+    a.ll = (double*)(w + L.off_ll);
+    a.phi_new = (double*)(w + L.off_phin);
+    a.theta_new = (double*)(w + L.off_thn);
+    a.lp_new = (double*)(w + L.off_lpn);
+    a.ll_new = (double*)(w + L.off_lln);
+    a.active = (uint8_t*)(w + L.off_act);
+    a.phi_trace = (double*)(w + L.off_phit);
+    a.ll_trace = (double*)(w + L.off_llt);
+    a.lln_trace = (double*)(w + L.off_llnt);
+    a.acc_trace = (int32_t*)(w + L.off_acct);
+    a.m_dev = (int32_t*)(w + L.off_m);
+    McParams& p = c->mp;
+    p.C = chains;
+    p.D = cfg->D;
+    p.iters = iters;
+    p.prior = (const double*)(w + L.off_prior);
+    p.lrw = (const double*)(w + L.off_lrw);
+    PFArgs& f = c->pa;
+    f.theta = a.theta_new;
+    f.active = a.active;
+    f.ll = a.ll_new;
+    f.y = (const int32_t*)(w + L.off_y);
+    f.runs = (const RunDev*)(w + L.off_run);
+    f.items = nullptr;
+    f.k_dev = a.m_dev;
+    f.n_items = chains;
+    f.N = chains;
+    f.D = cfg->D;
+    f.pf_always = cfg->pf_always;
+    f.multinomial = cfg->pf_resampling;
+    f.n_pop = cfg->n_pop;
+    for (int i = 0; i < SMC2_NFIXED; ++i) f.fx[i] = c->fixed[i];
+
+    std::vector<double> lrw((size_t)cfg->D * cfg->D);
+    host_cholesky(cfg->D, cfg->rw_cov, lrw.data());
+    const RunDev rd{run->T, run->n_x, 0, 0, (uint32_t)run->seed, (uint32_t)(run->seed >> 32)};
+    hipStream_t s = c->stream;
+    hipError_t e = hipMemcpyAsync(w + L.off_run, &rd, sizeof(rd), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w + L.off_y, c->y.data(), sizeof(int32_t) * c->y.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w + L.off_prior, c->prior.data(), sizeof(double) * c->prior.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w + L.off_lrw, lrw.data(), sizeof(double) * lrw.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(w + L.off_m, 0, sizeof(int32_t), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host copies above are released below
+    // wave priorities when every chain's filter is resident at once
+    int per_cu = 0, n_cu = 0, dev = 0;
+    if (e == hipSuccess) e = pf_prepare(cfg->precision, cfg->model, cfg->obs, sched, lds);
+    if (e == hipSuccess) e = pf_occupancy(cfg->precision, cfg->model, cfg->obs, sched, block, lds, &per_cu);
+    if (e == hipSuccess) e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess && (long)chains <= (long)per_cu * n_cu)
+        f.prio_scale = (float)(1.0 / ((double)run->T * (double)run->n_x));
+    if (e == hipSuccess) e = hipEventCreate(&c->ev_first);
+    if (e == hipSuccess) e = hipEventCreate(&c->ev_last);
+    // iteration 0: the chains' starting points and their filters
+    if (e == hipSuccess) e = launch_mc_start(a, p, run->seed, s);
+    if (e == hipSuccess) e = mc_filters(c);
+    if (e == hipSuccess) e = launch_mc_accept(a, p, run->seed, s);
+    if (e != hipSuccess) {
+        g_thread_error = std::string("smc2_pmcmc_init: ") + hipGetErrorString(e);
+        smc2_pmcmc_destroy(c);
+        return SMC2_E_DEVICE;
+    }
+    *out = c;
+    return SMC2_OK;
+}
+
+extern "C" int smc2_pmcmc_step(smc2_pmcmc* c, int32_t n_iter)
+{
+    if (!c) return g_thread_error = "ctx is NULL", SMC2_E_ARG;
+    if (c->poisoned) return g_thread_error = "context poisoned by an earlier device error", SMC2_E_DEVICE;
+    if (n_iter < 0) return g_thread_error = "n_iter < 0", SMC2_E_ARG;
+    if (c->m_host + n_iter > c->iters) return g_thread_error = "more iterations than configured", SMC2_E_STATE;
+    if (n_iter == 0) return SMC2_OK;
+    hipError_t e = hipSuccess;
+    if (!c->timed) e = hipEventRecord(c->ev_first, c->stream);
+    for (int i = 0; i < n_iter && e == hipSuccess; ++i) {
+        e = launch_mc_propose(c->ma, c->mp, c->run.seed, c->stream);
+        if (e == hipSuccess) e = mc_filters(c);
+        if (e == hipSuccess) e = launch_mc_accept(c->ma, c->mp, c->run.seed, c->stream);
+    }
+    if (e == hipSuccess) e = hipEventRecord(c->ev_last, c->stream);
+    if (e != hipSuccess) {
+        c->poisoned = true;
+        return g_thread_error = std::string("smc2_pmcmc_step: ") + hipGetErrorString(e), SMC2_E_DEVICE;
+    }
+    c->timed = true;
+    c->m_host += n_iter;
+    return SMC2_OK;
+}
+
+extern "C" int smc2_pmcmc_estimate(smc2_pmcmc* c, int32_t burn_in, double* mean, double* cov, double* accept_rate)
+{
+    if (!c || !mean) return g_thread_error = "ctx or mean is NULL", SMC2_E_ARG;
+    if (burn_in < 0 || burn_in >= c->m_host) return g_thread_error = "burn_in must be in [0, iterations run)", SMC2_E_ARG;
+    if (c->poisoned) return g_thread_error = "context poisoned by an earlier device error", SMC2_E_DEVICE;
+    const int D = c->cfg.D, C = c->C, I = c->iters;
+    std::vector<double> tr((size_t)C * (I + 1) * D);
+    std::vector<int32_t> acc((size_t)C * (I > 0 ? I : 1));
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = hipMemcpy(tr.data(), c->ma.phi_trace, sizeof(double) * tr.size(), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && I > 0) e = hipMemcpy(acc.data(), c->ma.acc_trace, sizeof(int32_t) * C * I, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        c->poisoned = true;
+        return g_thread_error = std::string("smc2_pmcmc_estimate: ") + hipGetErrorString(e), SMC2_E_DEVICE;
+    }
+    // mean and covariance of theta over the states after burn_in iterations, all chains
+    std::vector<double> m(D, 0.0), S((size_t)D * D, 0.0);
+    double n = 0.0, na = 0.0;
+    for (int ch = 0; ch < C; ++ch)
+        for (int it = burn_in + 1; it <= c->m_host; ++it) {
+            double th[SMC2_DMAX];
+            for (int d = 0; d < D; ++d)
+                th[d] = host_theta_of((int)c->prior[3 * d], tr[((size_t)ch * (I + 1) + it) * D + d]);
+            n += 1.0;
+            for (int d = 0; d < D; ++d) m[d] += th[d];
+            for (int d = 0; d < D; ++d)
+                for (int f = 0; f < D; ++f) S[(size_t)d * D + f] += th[d] * th[f];
+            na += acc[(size_t)ch * I + (it - 1)];
+        }
+    for (int d = 0; d < D; ++d) mean[d] = m[d] / n;
+    if (cov)
+        for (int d = 0; d < D; ++d)
+            for (int f = 0; f < D; ++f) cov[(size_t)d * D + f] = S[(size_t)d * D + f] / n - mean[d] * mean[f];
+    if (accept_rate) *accept_rate = na / n;
+    return SMC2_OK;
+}
+
+extern "C" int smc2_pmcmc_dump(smc2_pmcmc* c, int32_t what, void* host_dst, size_t bytes)
+{
+    if (!c || !host_dst) return g_thread_error = "ctx or destination is NULL", SMC2_E_ARG;
+    const size_t C = (size_t)c->C, I = (size_t)c->iters, D = (size_t)c->cfg.D;
+    const void* src = nullptr;
+    size_t need = 0;
+    switch (what) {
+    case SMC2_PMCMC_PHI: src = c->ma.phi_trace; need = C * (I + 1) * D * 8; break;
+    case SMC2_PMCMC_LL: src = c->ma.ll_trace; need = C * (I + 1) * 8; break;
+    case SMC2_PMCMC_LL_PROPOSED: src = c->ma.lln_trace; need = C * I * 8; break;
+    case SMC2_PMCMC_ACCEPTED: src = c->ma.acc_trace; need = C * I * 4; break;
+    default: return g_thread_error = "unknown dump", SMC2_E_ARG;
+    }
+    if (bytes < need) return g_thread_error = "destination too small", SMC2_E_ARG;
+    if (c->poisoned) return g_thread_error = "context poisoned by an earlier device error", SMC2_E_DEVICE;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && need) e = hipMemcpy(host_dst, src, need, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+        c->poisoned = true;
+        return g_thread_error = std::string("smc2_pmcmc_dump: ") + hipGetErrorString(e), SMC2_E_DEVICE;
+    }
+    return SMC2_OK;
+}
+
+extern "C" int smc2_pmcmc_timing(smc2_pmcmc* c, double* ms, int32_t* iterations)
+{
+    if (!c) return g_thread_error = "ctx is NULL", SMC2_E_ARG;
+    if (c->poisoned) return g_thread_error = "context poisoned by an earlier device error", SMC2_E_DEVICE;
+    float t = 0.f;
+    hipError_t e = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess && c->timed) e = hipEventElapsedTime(&t, c->ev_first, c->ev_last);
+    if (e != hipSuccess) {
+        c->poisoned = true;
+        return g_thread_error = std::string("smc2_pmcmc_timing: ") + hipGetErrorString(e), SMC2_E_DEVICE;
+    }
+    if (ms) *ms = t;
+    if (iterations) *iterations = c->m_host;
+    return SMC2_OK;
+}
+
+extern "C" int smc2_pmcmc_destroy(smc2_pmcmc* c)
+{
+    if (!c) return SMC2_OK;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->ev_first) (void)hipEventDestroy(c->ev_first);
+    if (c->ev_last) (void)hipEventDestroy(c->ev_last);
+    delete c;
     return SMC2_OK;
 }

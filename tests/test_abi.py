@@ -127,3 +127,26 @@ def test_kernel_entry_points_reject_bad_arguments():
     ca = G.make_config(W.preset("age_seir"), schedule=G.SCHED_POOLED)
     assert L.smc2_pf_loglik(ctypes.byref(ca), 4, fake, ra, 1, fake, fake, ws, None) == G.E_ARG
     assert b"pooled" in L.smc2_last_error(None)
+
+
+def test_pmcmc_entry_points_reject_bad_arguments():
+    L = G.lib()
+    w = W.preset("paper_sir")
+    y = W.observations(w)
+    cfg = G.make_config(w, N=2, K=1)
+    runs = G.make_runs([dict(T=30, nx=500, seed=1, y=y)])
+    nb = L.smc2_pmcmc_workspace_bytes(ctypes.byref(cfg), 64, 160, runs)
+    assert nb > 64 * 161 * 2 * 8  # the chains' traces
+    for chains, iters in [(0, 10), (40000, 10), (4, -1), (4, 70000)]:
+        assert L.smc2_pmcmc_workspace_bytes(ctypes.byref(cfg), chains, iters, runs) == 0
+    h = ctypes.c_void_p()
+    assert L.smc2_pmcmc_init(ctypes.byref(cfg), 64, 160, runs, None, 0, None, ctypes.byref(h)) == G.E_ARG
+    assert L.smc2_pmcmc_init(ctypes.byref(cfg), 64, 160, runs, ctypes.c_void_p(4097), nb, None,
+                             ctypes.byref(h)) == G.E_ARG
+    bad = G.make_config(dict(w, rw_cov=(-np.eye(2)).tolist()), N=2, K=1)
+    assert L.smc2_pmcmc_init(ctypes.byref(bad), 4, 10, runs, ctypes.c_void_p(4096), nb, None,
+                             ctypes.byref(h)) == G.E_ARG
+    assert b"positive definite" in L.smc2_last_error(None)
+    assert h.value is None
+    assert L.smc2_pmcmc_step(None, 1) == G.E_ARG
+    assert L.smc2_pmcmc_destroy(None) == G.OK
