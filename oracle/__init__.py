@@ -69,8 +69,8 @@ def _declare(L):
     L.or_binomial_many.argtypes = [c.c_int, c.c_int, P(c.c_int32), P(c.c_double), c.c_uint64] + [
         c.c_uint32] * 4 + [P(c.c_int32)]
     L.or_pf_lg.restype = c.c_double
-    L.or_pf_lg.argtypes = [c.c_double] * 5 + [P(c.c_double), c.c_int, c.c_int, c.c_uint64, c.c_uint32, c.c_int,
-                                              c.c_int, P(c.c_double), P(c.c_int32)]
+    L.or_pf_lg.argtypes = [c.c_double] * 5 + [P(c.c_double), c.c_int, c.c_int, c.c_uint64, c.c_uint32, c.c_uint32,
+                                              c.c_int, c.c_int, P(c.c_double), P(c.c_int32), P(c.c_double)]
     L.or_resample_multinomial.argtypes = [P(c.c_uint64), c.c_int, c.c_uint64, c.c_uint32, c.c_uint32, P(c.c_int32)]
     L.or_events_get.argtypes = [P(c.c_double)]
     L.or_events_reset.argtypes = []
@@ -433,17 +433,22 @@ def resample_multinomial(q, seed, filt, kt):
     return anc
 
 
-def pf_lg(phi, sq, sr, m0, s0, y, nx, seed, filt=0, pf_always=0, trace=False, resampling=RS_SYSTEMATIC):
+def pf_lg(phi, sq, sr, m0, s0, y, nx, seed, filt=0, pf_always=0, trace=False, resampling=RS_SYSTEMATIC, k=0,
+          states=False):
     """Log of the particle filter's likelihood estimate on the scalar linear-Gaussian
-    model x_t = phi x_{t-1} + sq e_t, y_t = x_t + sr d_t, x_0 ~ N(m0, s0^2)."""
+    model x_t = phi x_{t-1} + sq e_t, y_t = x_t + sr d_t, x_0 ~ N(m0, s0^2), on the
+    streams of iteration k. trace: also the per-day increments and resampling flags;
+    states: also the states of each day before resampling (T x nx)."""
     y = np.ascontiguousarray(y, dtype=np.float64)
     T = y.shape[0]
     inc = np.zeros(T) if trace else None
     rs = np.zeros(T, dtype=np.int32) if trace else None
-    ll = lib().or_pf_lg(phi, sq, sr, m0, s0, _p(y, ctypes.c_double), T, nx, int(seed), int(filt), int(pf_always),
-                        int(resampling), _p(inc, ctypes.c_double) if trace else None,
-                        _p(rs, ctypes.c_int32) if trace else None)
-    return (ll, inc, rs) if trace else ll
+    xs = np.zeros((T, nx)) if states else None
+    ll = lib().or_pf_lg(phi, sq, sr, m0, s0, _p(y, ctypes.c_double), T, nx, int(seed), int(filt), int(k),
+                        int(pf_always), int(resampling), _p(inc, ctypes.c_double) if trace else None,
+                        _p(rs, ctypes.c_int32) if trace else None, _p(xs, ctypes.c_double) if states else None)
+    out = (ll,) + ((inc, rs) if trace else ()) + ((xs,) if states else ())
+    return out if len(out) > 1 else ll
 
 
 # event counters of the particle filter (order of the OR_EV_* enumeration)

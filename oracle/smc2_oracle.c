@@ -488,10 +488,13 @@ void or_binomial_many(int prec, int count, const int32_t* n, const double* p, ui
  * this model shares with the epidemic models through weigh_f64):
  *   x_0 ~ N(m0, s0^2),  x_t = phi x_{t-1} + sq e_t,  y_t = x_t + sr d_t,  e, d ~ N(0, 1).
  * Bootstrap proposal; normals from Box-Muller on the Philox counter
- * (particle j, filter, t, 8<<24) -- t = 0 draws x_0. FP64 throughout.
+ * (particle j, filter, k<<16 | t, 8<<24) -- t = 0 draws x_0, k selects the iteration's
+ * streams as for the epidemic filters. FP64 throughout. x_out (T x nx, optional): the
+ * states of each day before resampling.
  */
 double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const double* y, int T, int nx,
-                uint64_t seed, uint32_t filt, int pf_always, int resampling, double* inc_out, int32_t* rs_out)
+                uint64_t seed, uint32_t filt, uint32_t k, int pf_always, int resampling, double* inc_out,
+                int32_t* rs_out, double* x_out)
 {
     double* x = (double*)malloc(sizeof(double) * (size_t)nx);
     double* xs = (double*)malloc(sizeof(double) * (size_t)nx);
@@ -501,7 +504,7 @@ double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const do
     uint64_t* qq = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)nx);
     int32_t* anc = (int32_t*)malloc(sizeof(int32_t) * (size_t)nx);
     for (int j = 0; j < nx; ++j) {
-        uint32_t ctr[4] = {(uint32_t)j, filt, 0u, 8u << 24};
+        uint32_t ctr[4] = {(uint32_t)j, filt, k << 16, 8u << 24};
         x[j] = m0 + s0 * or_normal_call(seed, ctr);
         lw[j] = 0.0;
     }
@@ -509,11 +512,12 @@ double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const do
     const double cst = -log(sr) - 0.5 * log(2.0 * M_PI);
     for (int t = 1; t <= T; ++t) {
         for (int j = 0; j < nx; ++j) {
-            uint32_t ctr[4] = {(uint32_t)j, filt, (uint32_t)t, 8u << 24};
+            uint32_t ctr[4] = {(uint32_t)j, filt, (k << 16) | (uint32_t)t, 8u << 24};
             x[j] = phi * x[j] + sq * or_normal_call(seed, ctr);
             const double z = (y[t - 1] - x[j]) / sr;
             a[j] = lw[j] + -0.5 * z * z;
         }
+        if (x_out) memcpy(x_out + (size_t)(t - 1) * nx, x, sizeof(double) * (size_t)nx);
         double inc;
         const int rs = weigh_f64(nx, a, lw, w, qq, anc, &s_prev, cst, t < T, pf_always, resampling, seed, filt,
                                  (uint32_t)t, &inc);

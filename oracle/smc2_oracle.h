@@ -166,9 +166,12 @@ void or_events_reset(void);
 
 /* Particle filter on a scalar linear-Gaussian model (a pin against the Kalman filter):
  * x_0 ~ N(m0, s0^2), x_t = phi x_{t-1} + sq e_t, y_t = x_t + sr d_t; returns the log of
- * the likelihood estimate; inc_out / rs_out (T entries, optional) as or_pf_loglik. */
+ * the likelihood estimate; k is the iteration index of the streams; inc_out / rs_out
+ * (T entries, optional) as or_pf_loglik; x_out (T x nx, optional) the states of each
+ * day before resampling. */
 double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const double* y, int T, int nx,
-                uint64_t seed, uint32_t filt, int pf_always, int resampling, double* inc_out, int32_t* rs_out);
+                uint64_t seed, uint32_t filt, uint32_t k, int pf_always, int resampling, double* inc_out,
+                int32_t* rs_out, double* x_out);
 /* Multinomial ancestors from quantised weights: slot m draws U_m = floor(x64_m Q / 2^64)
  * (x64_m: 64-bit word m&1 of the Philox call (m>>1, filt, kt, 2<<24 | 1<<16)) and takes
  * the first j whose inclusive scan C_j exceeds U_m. */

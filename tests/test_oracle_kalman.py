@@ -75,3 +75,31 @@ def test_increments_sum_to_the_estimate_and_resampling_is_adaptive():
     assert rs[-1] == 0 and 0 < rs.sum() < len(y) - 1
     _, _, rs1 = O.pf_lg(PHI, SQ, SR, M0, S0, y, 256, 5, pf_always=1, trace=True)
     assert rs1[:-1].all() and rs1[-1] == 0
+
+
+def test_deterministic_special_case_gives_the_exact_likelihood_and_states():
+    # sq = s0 = 0: every particle follows x_t = phi^t m0 exactly, every weight is equal,
+    # so the estimate is the exact likelihood and no day resamples
+    phi, sr, m0 = 0.8, 0.7, 2.5
+    y = simulate(12, 14)
+    ll, inc, rs, xs = O.pf_lg(phi, 0.0, sr, m0, 0.0, y, 96, 9, trace=True, states=True, k=3)
+    x, ref = m0, 0.0
+    for t in range(len(y)):
+        x = phi * x
+        assert np.all(xs[t] == x), t
+        ref += -0.5 * np.log(2 * np.pi * sr * sr) - 0.5 * ((y[t] - x) / sr) ** 2
+    assert ll == pytest.approx(ref, rel=1e-13)
+    assert not rs.any()
+
+
+def test_iteration_index_selects_independent_streams():
+    y = simulate(20, 15)
+    a = O.pf_lg(PHI, SQ, SR, M0, S0, y, 64, 7, filt=3, k=0)
+    b = O.pf_lg(PHI, SQ, SR, M0, S0, y, 64, 7, filt=3, k=1)
+    c = O.pf_lg(PHI, SQ, SR, M0, S0, y, 64, 7, filt=3, k=1)
+    assert a != b and b == c
+    # the estimate stays unbiased on the streams of a later iteration
+    ref = kalman_loglik(PHI, SQ, SR, M0, S0, simulate(25, 11))
+    r = np.array([np.exp(O.pf_lg(PHI, SQ, SR, M0, S0, simulate(25, 11), 64, 7, filt=f, k=5) - ref)
+                  for f in range(2000)])
+    assert abs(r.mean() - 1.0) < 4 * r.std(ddof=1) / np.sqrt(len(r)) + 1e-3
