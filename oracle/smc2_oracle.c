@@ -488,8 +488,9 @@ void or_binomial_many(int prec, int count, const int32_t* n, const double* p, ui
  * this model shares with the epidemic models through weigh_f64):
  *   x_0 ~ N(m0, s0^2),  x_t = phi x_{t-1} + sq e_t,  y_t = x_t + sr d_t,  e, d ~ N(0, 1).
  * Bootstrap proposal; normals from Box-Muller on the Philox counter
- * (particle j, filter, k<<16 | t, 8<<24) -- t = 0 draws x_0, k selects the iteration's
- * streams as for the epidemic filters. FP64 throughout. x_out (T x nx, optional): the
+ * (particle j, filter, k<<16 | t, 8<<24) -- t = 0 draws x_0; the resampling uniforms
+ * come from the epidemic filters' streams with the same k<<16 | t, so k selects the
+ * iteration's streams throughout. FP64 throughout. x_out (T x nx, optional): the
  * states of each day before resampling.
  */
 double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const double* y, int T, int nx,
@@ -520,7 +521,7 @@ double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const do
         if (x_out) memcpy(x_out + (size_t)(t - 1) * nx, x, sizeof(double) * (size_t)nx);
         double inc;
         const int rs = weigh_f64(nx, a, lw, w, qq, anc, &s_prev, cst, t < T, pf_always, resampling, seed, filt,
-                                 (uint32_t)t, &inc);
+                                 (k << 16) | (uint32_t)t, &inc);
         if (inc_out) inc_out[t - 1] = inc;
         if (rs_out) rs_out[t - 1] = rs > 0;
         if (rs < 0) {

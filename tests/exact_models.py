@@ -202,3 +202,42 @@ def age_seir_loglik(beta, s, C, group_sizes, i0, sigma, gamma, y, r):
     N = np.asarray(group_sizes, dtype=np.float64)
     A = beta * s[:, None] * np.asarray(C, dtype=np.float64) / N[None, :]
     return age_seir_loglik_coef(A, group_sizes, i0, sigma, gamma, y, r)
+
+
+def kalman_loglik_grid(a, sx, sy, m0, s0, y):
+    """Exact log p(y_{1:T}) of the scalar linear-Gaussian model x_0 ~ N(m0, s0^2),
+    x_t = a x_{t-1} + sx e_t, y_t = x_t + sy d_t (Kalman filter, prediction-error
+    decomposition), vectorised over broadcastable parameter arrays a, sx, sy."""
+    a, sx, sy = np.broadcast_arrays(*(np.asarray(v, dtype=np.float64) for v in (a, sx, sy)))
+    m = np.full(a.shape, float(m0))
+    P = np.full(a.shape, float(s0) ** 2)
+    ll = np.zeros(a.shape)
+    for yt in np.asarray(y, dtype=np.float64):
+        m = a * m
+        P = a * a * P + sx * sx
+        S = P + sy * sy
+        v = yt - m
+        ll += -0.5 * (np.log(2.0 * np.pi * S) + v * v / S)
+        K = P / S
+        m = m + K * v
+        P = (1.0 - K) * P
+    return ll
+
+
+def lingauss_loglik_joint(a, sx, sy, m0, s0, y):
+    """The same likelihood from the joint Gaussian of y_{1:T}: mean a^t m0 and covariance
+    a^(s+t) s0^2 + sx^2 sum_{u <= min(s,t)} a^(s-u) a^(t-u) + sy^2 [s = t]."""
+    from scipy import stats as st
+    y = np.asarray(y, dtype=np.float64)
+    T = y.shape[0]
+    t = np.arange(1, T + 1)
+    mean = a ** t * m0
+    cov = np.empty((T, T))
+    for i in range(T):
+        for j in range(T):
+            s_, t_ = i + 1, j + 1
+            acc = a ** (s_ + t_) * s0 * s0
+            for u in range(1, min(s_, t_) + 1):
+                acc += sx * sx * a ** (s_ - u) * a ** (t_ - u)
+            cov[i, j] = acc + (sy * sy if i == j else 0.0)
+    return st.multivariate_normal(mean, cov).logpdf(y)

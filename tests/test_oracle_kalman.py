@@ -103,3 +103,28 @@ def test_iteration_index_selects_independent_streams():
     r = np.array([np.exp(O.pf_lg(PHI, SQ, SR, M0, S0, simulate(25, 11), 64, 7, filt=f, k=5) - ref)
                   for f in range(2000)])
     assert abs(r.mean() - 1.0) < 4 * r.std(ddof=1) / np.sqrt(len(r)) + 1e-3
+
+
+def test_kalman_recursion_equals_the_joint_gaussian():
+    # the prediction-error decomposition against the joint density of y_1:T written out
+    from tests.exact_models import kalman_loglik_grid, lingauss_loglik_joint
+    y = simulate(7, 16)
+    for (a, sx, sy, m0, s0) in [(0.9, 1.0, 1.0, 0.0, 1.0), (-0.6, 0.4, 1.7, 1.5, 0.3), (1.1, 2.0, 0.5, -1.0, 0.0)]:
+        ref = lingauss_loglik_joint(a, sx, sy, m0, s0, y)
+        assert kalman_loglik(a, sx, sy, m0, s0, y) == pytest.approx(ref, rel=1e-12)
+        assert kalman_loglik_grid(np.array([a, a]), sx, sy, m0, s0, y) == pytest.approx([ref, ref], rel=1e-12)
+
+
+def test_iteration_index_reaches_the_resampling_stream():
+    # no state noise: the states of day 2 are PHI times the day-1 states picked by the
+    # day-1 ancestors, which must come from the uniforms of counter word k<<16 | 1
+    y = simulate(3, 17)
+    for k in (0, 1, 5):
+        _, _, rs, xs = O.pf_lg(PHI, 0.0, SR, M0, S0, y, 64, 7, filt=2, pf_always=1, trace=True, k=k, states=True,
+                               resampling=O.RS_MULTINOMIAL)
+        assert rs[0] == 1
+        a = -0.5 * ((y[0] - xs[0]) / SR) ** 2
+        w = np.exp(a - a.max())
+        q = np.where(w >= 1.0, 2 ** 32, np.floor(w * 2.0 ** 32)).astype(np.uint64)
+        anc = O.resample_multinomial(q, 7, 2, (k << 16) | 1)
+        assert np.array_equal(xs[1], PHI * xs[0][anc]), k
