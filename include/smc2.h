@@ -62,11 +62,18 @@ extern "C" {
                            fixed[0] = negative-binomial dispersion r when D == 4 */
 #define SMC2_AGE_SEIR 2 /* theta = (beta, sigma, gamma, iota, r, s_2, s_3, s_4), four groups;
                            fixed[0..15] contact matrix (row-major), fixed[16..19] group fractions */
+#define SMC2_LINGAUSS 3 /* scalar linear-Gaussian model, a test model whose likelihood the
+                           Kalman filter gives in closed form (Sec. II's filter on it is
+                           otherwise the epidemic models'): theta = (a, sigma_x, sigma_y),
+                           x_t = a x_{t-1} + sigma_x e_t, y_t = x_t + sigma_y d_t, e, d ~ N(0, 1),
+                           x_0 = fixed[0] + fixed[1] e_0; real observations (smc2_run.y_real);
+                           SMC2_OBS_GAUSS; SMC2_PREC_FP64 only; n_pop is not used             */
 
 /* observation model of y_t */
 #define SMC2_OBS_POIS_PREV 0 /* Poisson(I_t)            (Sec. V-A)                      */
 #define SMC2_OBS_POIS_INC 1  /* Poisson(new infections) (S->I for SIR, E->I for SEIR)   */
 #define SMC2_OBS_NB_INC 2    /* negative binomial(mean = new infections, dispersion r)  */
+#define SMC2_OBS_GAUSS 3     /* N(x_t, sigma_y^2) (SMC2_LINGAUSS)                       */
 
 /* precision of the particle-filter propagation and per-step weights. The
  * log-likelihood accumulation and everything in the outer sampler are FP64. */
@@ -124,7 +131,7 @@ extern "C" {
 typedef struct smc2_ctx smc2_ctx;
 
 typedef struct {
-    int32_t model;     /* SMC2_SIR / SMC2_SEIR / SMC2_AGE_SEIR                          */
+    int32_t model;     /* SMC2_SIR / SMC2_SEIR / SMC2_AGE_SEIR / SMC2_LINGAUSS          */
     int32_t obs;       /* SMC2_OBS_*                                                    */
     int32_t D;         /* number of parameters, 1..SMC2_DMAX (fixed by the model)       */
     int32_t N;         /* parameter samples per run, 2..32768                           */
@@ -137,7 +144,7 @@ typedef struct {
     int32_t block;     /* particle-filter workgroup size, a multiple of 64 up to 1024
                           (0: chosen from the filter's LDS footprint)                   */
     int32_t schedule;  /* SMC2_SCHED_*: particle-filter draw schedule (same results)     */
-    double n_pop;      /* population size, integer, 1 .. 2^24                           */
+    double n_pop;      /* population size, integer, 1 .. 2^24 (not used by SMC2_LINGAUSS) */
     const double* prior;  /* host, D x 3 row-major: {family, a, b} per coordinate        */
     const double* rw_cov; /* host, D x D row-major, symmetric positive definite          */
     const double* fixed;  /* host, n_fixed model constants (see the model codes)         */
@@ -160,7 +167,10 @@ typedef struct {
     int32_t T;          /* number of observations, 1..1024                             */
     int32_t n_x;        /* particles per filter, 1..4096 (1..2048 for SMC2_AGE_SEIR)   */
     uint64_t seed;      /* Philox key of this run                                      */
-    const int32_t* y;   /* host, T x n_obs row-major, non-negative (n_obs = 4 for AGE) */
+    const int32_t* y;   /* host, T x n_obs row-major, non-negative (n_obs = 4 for AGE);
+                           not read for SMC2_LINGAUSS                                   */
+    const double* y_real; /* host, T finite reals: the observations of SMC2_LINGAUSS (not
+                             read for the other models, may be NULL there)               */
 } smc2_run;
 
 /* Per-iteration record, SMC2_RECORD_LEN(D) doubles:

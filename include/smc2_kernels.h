@@ -72,7 +72,8 @@ int smc2_pf_trace(const smc2_config* cfg, int32_t n_theta, const double* d_theta
 
 /* As smc2_pf_trace, and also writes every filter's particle counts of each day
  * before resampling (d_state: int32[n_theta][T][n_counts][n_x], n_counts = 2 / 3 / 12
- * for SIR / SEIR / age-structured SEIR) and, when d_anc is not NULL, the ancestors
+ * for SIR / SEIR / age-structured SEIR; for SMC2_LINGAUSS n_counts = 2, the low and
+ * high 32-bit words of each particle's FP64 state) and, when d_anc is not NULL, the ancestors
  * chosen after each day (d_anc: int32[n_theta][T][n_x]; the identity on days without
  * resampling; rows after a filter's death day are left unwritten). Together with d_rs
  * these are the filter's integer decisions, from which an FP64 replay of Sec. II's

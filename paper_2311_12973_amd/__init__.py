@@ -15,8 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libsmc2.so")
 
 OK, E_ARG, E_DEVICE, E_STATE, E_NUMERIC, E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
-SIR, SEIR, AGE_SEIR = 0, 1, 2
-OBS_POIS_PREV, OBS_POIS_INC, OBS_NB_INC = 0, 1, 2
+SIR, SEIR, AGE_SEIR, LINGAUSS = 0, 1, 2, 3
+OBS_POIS_PREV, OBS_POIS_INC, OBS_NB_INC, OBS_GAUSS = 0, 1, 2, 3
 PREC_FP32, PREC_FP64 = 0, 1
 PRIOR_UNIFORM, PRIOR_LOGNORMAL, PRIOR_LOGITNORMAL, PRIOR_NORMAL = 0, 1, 2, 3
 L_FORWARD, L_GAUSS_OPT = 0, 1
@@ -64,7 +64,7 @@ class Config(ctypes.Structure):
 
 class Run(ctypes.Structure):
     _fields_ = [("T", ctypes.c_int32), ("n_x", ctypes.c_int32), ("seed", ctypes.c_uint64),
-                ("y", ctypes.POINTER(ctypes.c_int32))]
+                ("y", ctypes.POINTER(ctypes.c_int32)), ("y_real", ctypes.POINTER(ctypes.c_double))]
 
 
 class StepInfo(ctypes.Structure):
@@ -231,17 +231,28 @@ def make_config(w, N=None, K=None, precision=None, use_graph=0, block=0, lkernel
     return c
 
 
+def obs_array(y):
+    """Observations as the ABI takes them: float64 reals (the linear-Gaussian model) stay
+    float64, counts become int32."""
+    a = np.asarray(y)
+    return np.ascontiguousarray(a, dtype=np.float64 if np.issubdtype(a.dtype, np.floating) else np.int32)
+
+
 def make_runs(runs):
-    """runs: list of dict(T, nx, seed, y)."""
+    """runs: list of dict(T, nx, seed, y); a floating-point y (the linear-Gaussian model)
+    goes to y_real, counts to y."""
     arr = (Run * len(runs))()
     keep = []
     for r, d in enumerate(runs):
-        y = np.ascontiguousarray(np.asarray(d["y"], dtype=np.int32))
+        y = obs_array(d["y"])
         keep.append(y)
         arr[r].T = int(d.get("T", y.shape[0]))
         arr[r].n_x = int(d["nx"])
         arr[r].seed = int(d["seed"])
-        arr[r].y = y.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        if y.dtype == np.float64:
+            arr[r].y_real = y.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            arr[r].y = y.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
     arr._keep = keep
     return arr
 
@@ -382,11 +393,11 @@ def pf_trace_state(w, theta, y, nx, seed, k, precision=None, block=0, device="cu
     """(ll, inc[n][T], rs[n][T], state[n][T][n_counts][nx]) for the rows of theta, and
     with_anc=True also anc[n][T][nx], the ancestors chosen after each day."""
     cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, block=block, schedule=schedule)
-    y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
+    y = obs_array(y)
     runs = make_runs([dict(T=y.shape[0], nx=nx, seed=seed, y=y)])
     theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
     n, T = theta.shape[0], y.shape[0]
-    nc = {SIR: 2, SEIR: 3, AGE_SEIR: 12}[cfg.model]
+    nc = {SIR: 2, SEIR: 3, AGE_SEIR: 12, LINGAUSS: 2}[cfg.model]
     L = lib()
     wsb = L.smc2_pf_workspace_bytes(ctypes.byref(cfg), runs)
     tws, pws = device_buffer(wsb, device)
@@ -412,7 +423,7 @@ def pf_loglik(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0,
     with trace=True also the per-day increments and resampling flags."""
     cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, pf_always=pf_always, block=block,
                       schedule=schedule)
-    y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
+    y = obs_array(y)
     runs = make_runs([dict(T=y.shape[0], nx=nx, seed=seed, y=y)])
     theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
     n = theta.shape[0]
@@ -437,7 +448,7 @@ def pf_loglik_noalloc(w, theta, y, nx, seed, k, precision=None, pf_always=None, 
     run in its static device scratch)."""
     cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, pf_always=pf_always, block=block,
                       schedule=schedule)
-    y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
+    y = obs_array(y)
     runs = make_runs([dict(T=y.shape[0], nx=nx, seed=seed, y=y)])
     theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
     n = theta.shape[0]

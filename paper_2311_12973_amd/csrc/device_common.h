@@ -11,6 +11,8 @@
 //   outer resample (0, 0, k<<16, 5<<24)
 //   learned proposal: initial parameter p (p, 0, 0, 6<<24); training permutation
 //   (k, epoch, which, 7<<24)
+//   linear-Gaussian state noise (particle j, filter i, k<<16 | t, 8<<24); t = 0 draws
+//   the initial state
 // Uniforms: u24(x) = (2(x>>9)+1) 2^-24 (exact in FP32); u53 = (2(x64>>12)+1) 2^-53.
 //
 // Precision: the particle filter works in `real` (float or double). Every
@@ -27,7 +29,7 @@
 namespace smc2 {
 
 enum : uint32_t { S_PF_PROP = 1u, S_PF_RS = 2u, S_PRIOR = 3u, S_RW = 4u, S_OUTER_RS = 5u, S_MLP_INIT = 6u,
-                  S_MLP_PERM = 7u };
+                  S_MLP_PERM = 7u, S_LG = 8u };
 
 struct W4 {
     uint32_t x, y, z, w;
@@ -80,12 +82,18 @@ __host__ __device__ __forceinline__ double u53(uint32_t lo, uint32_t hi)
 }
 
 // Box-Muller on one Philox call, first output.
+__device__ __forceinline__ double normal_key(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                             uint32_t k1)
+{
+    const W4 w = philox10(c0, c1, c2, c3, k0, k1);
+    const double r = sqrt(-2.0 * log(u53(w.x, w.y)));
+    return r * cos(6.283185307179586 * u53(w.z, w.w));
+}
+
 __device__ __forceinline__ double normal_call(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint64_t seed)
 {
-    const W4 w = philox10(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
-    const double r = sqrt(-2.0 * log(u53(w.x, w.y)));
-    return r * cos(6.283185307179586 * u53(w.z, w.w));
+    return normal_key(c0, c1, c2, c3, (uint32_t)seed, (uint32_t)(seed >> 32));
 }
 
 // ----------------------------------------------------------- precision helpers
@@ -448,7 +456,7 @@ template <typename real> __device__ __forceinline__ real leave_prob(real x)
 }
 
 // ----------------------------------------------------------- observations (FP64)
-enum : int { OBS_POIS_PREV = 0, OBS_POIS_INC = 1, OBS_NB_INC = 2 };
+enum : int { OBS_POIS_PREV = 0, OBS_POIS_INC = 1, OBS_NB_INC = 2, OBS_GAUSS = 3 };
 
 // The observation log-pmf split into a per-day constant (no particle dependence)
 // and a per-particle part, both FP64:

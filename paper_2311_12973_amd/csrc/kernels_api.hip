@@ -2,10 +2,12 @@
 // building blocks of the sampler on caller-provided device arrays.
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/smc2_kernels.h"
 #include "block_ops.h"
 #include "mlp_kernels.h"
+#include "obs_words.h"
 #include "pf_kernel.h"
 
 namespace smc2 {
@@ -73,7 +75,6 @@ int kfail(int code, const std::string& m)
     smc2_set_thread_error(m);
     return code;
 }
-int n_obs_of(int model) { return model == SMC2_AGE_SEIR ? 4 : 1; }
 
 // Device address of `scratch` on the current device, resolved with that device current
 // on the first call there and kept per device (each device holds its own copy).
@@ -145,7 +146,7 @@ extern "C" int smc2_resample_batch(int32_t n_sets, int32_t n, const uint64_t* d_
 extern "C" size_t smc2_pf_workspace_bytes(const smc2_config* cfg, const smc2_run* run)
 {
     if (!cfg || !run || run->T < 1) return 0;
-    const size_t y = ((size_t)run->T * n_obs_of(cfg->model) * 4 + 255) & ~(size_t)255;
+    const size_t y = ((size_t)run->T * obs_words(cfg->model) * 4 + 255) & ~(size_t)255;
     return 256 + y;
 }
 
@@ -187,13 +188,16 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
                   size_t ws_bytes, void* stream, bool static_ws)
 {
     if ((d_inc == nullptr) != (d_rs == nullptr)) return kfail(SMC2_E_ARG, "trace needs both d_inc and d_rs");
-    if (!cfg || !run || !run->y) return kfail(SMC2_E_ARG, "null config or run");
+    if (!cfg || !run) return kfail(SMC2_E_ARG, "null config or run");
     if (!pf_supported(cfg->model, cfg->obs)) return kfail(SMC2_E_UNSUPPORTED, "model/observation not supported");
     if (cfg->precision != SMC2_PREC_FP32 && cfg->precision != SMC2_PREC_FP64) return kfail(SMC2_E_ARG, "precision");
-    if (cfg->D < 1 || cfg->D > SMC2_DMAX) return kfail(SMC2_E_ARG, "bad D");
+    const bool lg = cfg->model == SMC2_LINGAUSS;
+    if (lg && cfg->precision != SMC2_PREC_FP64)
+        return kfail(SMC2_E_UNSUPPORTED, "the linear-Gaussian model runs in FP64 only");
+    if (cfg->D < 1 || cfg->D > SMC2_DMAX || (lg && cfg->D != 3)) return kfail(SMC2_E_ARG, "bad D");
     if (run->T < 1 || run->T > 1024 || run->n_x < 1 || run->n_x > (cfg->model == SMC2_AGE_SEIR ? 2048 : 4096))
         return kfail(SMC2_E_ARG, "T or n_x out of range");
-    if (!(cfg->n_pop >= 1.0 && cfg->n_pop <= 16777216.0)) return kfail(SMC2_E_ARG, "n_pop out of range");
+    if (!lg && !(cfg->n_pop >= 1.0 && cfg->n_pop <= 16777216.0)) return kfail(SMC2_E_ARG, "n_pop out of range");
     if (k > 65535) return kfail(SMC2_E_ARG, "k out of range");
     if (cfg->pf_resampling != SMC2_PF_RS_SYSTEMATIC && cfg->pf_resampling != SMC2_PF_RS_MULTINOMIAL)
         return kfail(SMC2_E_ARG, "pf_resampling must be SMC2_PF_RS_SYSTEMATIC or SMC2_PF_RS_MULTINOMIAL");
@@ -208,9 +212,7 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     }
     if (cfg->n_fixed < 0 || cfg->n_fixed > SMC2_NFIXED || (cfg->n_fixed > 0 && !cfg->fixed))
         return kfail(SMC2_E_ARG, "bad fixed constants");
-    const int no = n_obs_of(cfg->model);
-    for (int e = 0; e < run->T * no; ++e)
-        if (run->y[e] < 0) return kfail(SMC2_E_ARG, "negative observation");
+    if (const char* why = obs_check(cfg->model, *run)) return kfail(SMC2_E_ARG, why);
     if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64 != 0))
         return kfail(SMC2_E_ARG, "block must be 0 or a multiple of 64 up to 1024");
     if (cfg->schedule < 0 || cfg->schedule > 2) return kfail(SMC2_E_ARG, "schedule must be 0, 1 or 2");
@@ -228,11 +230,13 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     hipStream_t s = (hipStream_t)stream;
     unsigned char* w = (unsigned char*)d_ws;
     // every argument is checked before the first copy: from here on the host copies of rd
-    // and y must stay valid until the stream has run the copies, also on a device error
+    // and the observation words must stay valid until the stream has run the copies, also
+    // on a device error (the stream is synchronised before returning)
+    std::vector<int32_t> yw;
+    obs_pack(cfg->model, *run, yw);
     RunDev rd{run->T, run->n_x, 0, 0, (uint32_t)run->seed, (uint32_t)(run->seed >> 32)};
     hipError_t e = hipMemcpyAsync(w, &rd, sizeof(rd), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(w + 256, run->y, (size_t)run->T * no * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w + 256, yw.data(), yw.size() * 4, hipMemcpyHostToDevice, s);
     PFArgs a{};
     a.theta = d_theta;
     a.active = nullptr;

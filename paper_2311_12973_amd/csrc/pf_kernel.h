@@ -6,9 +6,11 @@
 
 namespace smc2 {
 
-enum : int { MODEL_SIR = 0, MODEL_SEIR = 1, MODEL_AGE = 2 };
+enum : int { MODEL_SIR = 0, MODEL_SEIR = 1, MODEL_AGE = 2, MODEL_LG = 3 };
 
-// One run of the batch: its observation series starts at y_off (T x n_obs int32).
+// One run of the batch: its observations start at word y_off of the concatenated
+// 32-bit words (T x n_obs counts; for the linear-Gaussian model T FP64 values, low
+// word first).
 struct RunDev {
     int32_t T;
     int32_t nx;

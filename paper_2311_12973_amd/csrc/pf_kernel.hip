@@ -15,8 +15,13 @@
 //   4. if ESS < N_x/2 (exact integer test on the quantised weights) and t < T:
 //      integer systematic resampling (LDS scan + search), gather of the counts
 //      through LDS, log-weights reset (every particle gets the mean weight).
+// The scalar linear-Gaussian model, whose likelihood the Kalman filter gives in
+// closed form, runs through the same steps (FP64 only): its state is one FP64 value
+// per particle, held in LDS as two 32-bit words, and its noise comes from Box-Muller
+// on the counter (particle j, filter i, k<<16 | t, 8<<24).
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <utility>
 
 #include "block_ops.h"
@@ -28,6 +33,8 @@ template <int MODEL> struct ModelShape;
 template <> struct ModelShape<MODEL_SIR> { static constexpr int NC = 2, NG = 1; };
 template <> struct ModelShape<MODEL_SEIR> { static constexpr int NC = 3, NG = 1; };
 template <> struct ModelShape<MODEL_AGE> { static constexpr int NC = 12, NG = 4; };
+// linear-Gaussian: the FP64 state and the FP64 observation each take two 32-bit words
+template <> struct ModelShape<MODEL_LG> { static constexpr int NC = 2, NG = 2; };
 
 // Per-filter constants of the transition kernel, rounded once to `real`.
 template <typename real> struct MConst {
@@ -39,6 +46,8 @@ template <typename real> struct MConst {
     double l1p_ir;
     double r;       // negative-binomial dispersion
     int32_t x0[12]; // initial compartment counts
+    double ar, sq, sr, m0, s0;  // linear-Gaussian: x_t = ar x_{t-1} + sq e_t, y_t = x_t + sr d_t,
+                                // x_0 = m0 + s0 e_0
 };
 
 template <typename real> __device__ __forceinline__ double l1p_of(real p)
@@ -50,6 +59,14 @@ template <typename real> __device__ __forceinline__ double l1p_of(real p)
 template <typename real, int MODEL>
 __device__ __forceinline__ void model_setup(const PFArgs& a, const double* th, MConst<real>& mc)
 {
+    if constexpr (MODEL == MODEL_LG) {
+        mc.ar = uniform_f64(th[0]);
+        mc.sq = uniform_f64(th[1]);
+        mc.sr = uniform_f64(th[2]);
+        mc.m0 = a.fx[0];
+        mc.s0 = a.fx[1];
+        return;
+    }
     if (MODEL == MODEL_SIR) {
         const int32_t i0 = (int32_t)a.fx[0];
         mc.cinf = (real)(th[0] / a.n_pop);
@@ -113,6 +130,17 @@ template <typename real, int MODEL, int OBS>
 __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* st, int cap, int j,
                                                DrawStream ds, const int32_t* yt)
 {
+    if constexpr (MODEL == MODEL_LG) {
+        // x_t = ar x_{t-1} + sq e_t; log g = -z^2 / 2 with z = (y_t - x_t) / sr (the
+        // constant -log sr - log(2 pi) / 2 goes with the day's constant)
+        const double x = __hiloint2double(st[cap + j], st[j]);
+        const double e = normal_key(ds.j, ds.i, ds.kt, S_LG << 24, ds.k0, ds.k1);
+        const double x1 = mc.ar * x + mc.sq * e;
+        st[j] = __double2loint(x1);
+        st[cap + j] = __double2hiint(x1);
+        const double z = (__hiloint2double(yt[1], yt[0]) - x1) / mc.sr;
+        return -0.5 * z * z;
+    }
     if (MODEL == MODEL_SIR) {
         const int32_t S = st[j], I = st[cap + j];
         const real p_si = leave_prob<real>(mc.cinf * (real)I);
@@ -563,13 +591,23 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
     const int32_t* y = a.y + run.y_off;
     for (int t = tid; t < T; t += nthr) {
         double c = 0.0;
+        if constexpr (MODEL == MODEL_LG) {
+            c = -log(mc.sr) - 0.5 * log(6.283185307179586);
+        } else {
 #pragma unroll
-        for (int gi = 0; gi < NG; ++gi) c = c + obs_const(OBS, y[t * NG + gi], mc.r);
+            for (int gi = 0; gi < NG; ++gi) c = c + obs_const(OBS, y[t * NG + gi], mc.r);
+        }
         cst[t] = c;
     }
     for (int j = tid; j < nx; j += nthr) {
+        if constexpr (MODEL == MODEL_LG) {
+            const double x0 = mc.m0 + mc.s0 * normal_key((uint32_t)j, filt, kit << 16, S_LG << 24, run.k0, run.k1);
+            st[j] = __double2loint(x0);
+            st[cap + j] = __double2hiint(x0);
+        } else {
 #pragma unroll
-        for (int c = 0; c < NC; ++c) st[c * cap + j] = mc.x0[c];
+            for (int c = 0; c < NC; ++c) st[c * cap + j] = mc.x0[c];
+        }
         lw[j] = (real)0;
     }
     if (tid == 0) wg_next = 0;
@@ -585,7 +623,7 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
         const int32_t* yt = y + (size_t)(t - 1) * NG;
         // 1. propagate and weight: lw[j] <- a_j = lw_j + log g(y_t | x_t^j)
         real amax = (real)-INFINITY;
-        if constexpr (SCHED == PF_SCHED_POOLED && MODEL != MODEL_AGE) {
+        if constexpr (SCHED == PF_SCHED_POOLED && (MODEL == MODEL_SIR || MODEL == MODEL_SEIR)) {
             draws_pooled<real, MODEL>(mc, st, flows, cap, nx, pool, filt, kt, run.k0, run.k1, &wg_next);
             __syncthreads();  // any wave may have drawn any particle's flows
             if (tid == 0) wg_next = 0;  // for the next day (read again only after further barriers)
@@ -727,7 +765,7 @@ __global__ void __launch_bounds__(1024) k_pf(PFArgs a)
 
 size_t pf_lds_bytes(int model, int prec, int block, int nx, int T, int sched)
 {
-    const int nc = model == MODEL_SIR ? 2 : (model == MODEL_SEIR ? 3 : 12);
+    const int nc = model == MODEL_SIR ? 2 : (model == MODEL_SEIR ? 3 : (model == MODEL_LG ? 2 : 12));
     const size_t cap = (size_t)((nx + block - 1) / block) * block;
     const size_t rb = prec == 0 ? 4 : 8;
     size_t bytes = cap * 8 + 2 * cap * 4 + sizeof(RedLds) + (size_t)T * 8 + cap * rb + (size_t)nc * cap * 4;
@@ -765,7 +803,8 @@ int pf_default_block(int model, int prec, int nx, int T, int requested_sched)
 
 int pf_pick_schedule(int model, int prec, int block, int nx, int T, int requested)
 {
-    const bool pooled_ok = model != MODEL_AGE && pf_lds_bytes(model, prec, block, nx, T, PF_SCHED_POOLED) <= PF_LDS_MAX;
+    const bool pooled_ok = (model == MODEL_SIR || model == MODEL_SEIR) &&
+                           pf_lds_bytes(model, prec, block, nx, T, PF_SCHED_POOLED) <= PF_LDS_MAX;
     if (requested == PF_SCHED_PER_DRAW) return PF_SCHED_PER_DRAW;
     if (requested == PF_SCHED_POOLED) return pooled_ok ? PF_SCHED_POOLED : -1;
     return pooled_ok ? PF_SCHED_POOLED : PF_SCHED_PER_DRAW;
@@ -795,6 +834,9 @@ static hipError_t launch_model(int model, int obs, int block, size_t lds, const 
         return launch_one<real, MODEL_SEIR, OBS_NB_INC, SCHED>(block, lds, a, s, grid);
     if (model == MODEL_AGE && obs == OBS_NB_INC && SCHED == PF_SCHED_PER_DRAW)
         return launch_one<real, MODEL_AGE, OBS_NB_INC, PF_SCHED_PER_DRAW>(block, lds, a, s, grid);
+    if constexpr (std::is_same<real, double>::value && SCHED == PF_SCHED_PER_DRAW)
+        if (model == MODEL_LG && obs == OBS_GAUSS)
+            return launch_one<double, MODEL_LG, OBS_GAUSS, PF_SCHED_PER_DRAW>(block, lds, a, s, grid);
     return hipErrorInvalidValue;
 }
 
@@ -805,13 +847,16 @@ template <typename real, int SCHED> static const void* kernel_of(int model, int 
     if (model == MODEL_SEIR && obs == OBS_NB_INC) return kernel_ptr<real, MODEL_SEIR, OBS_NB_INC, SCHED>();
     if (model == MODEL_AGE && obs == OBS_NB_INC && SCHED == PF_SCHED_PER_DRAW)
         return kernel_ptr<real, MODEL_AGE, OBS_NB_INC, PF_SCHED_PER_DRAW>();
+    if constexpr (std::is_same<real, double>::value && SCHED == PF_SCHED_PER_DRAW)
+        if (model == MODEL_LG && obs == OBS_GAUSS) return kernel_ptr<double, MODEL_LG, OBS_GAUSS, PF_SCHED_PER_DRAW>();
     return nullptr;
 }
 
 bool pf_supported(int model, int obs)
 {
     return (model == MODEL_SIR && (obs == OBS_POIS_PREV || obs == OBS_POIS_INC)) ||
-           (model == MODEL_SEIR && obs == OBS_NB_INC) || (model == MODEL_AGE && obs == OBS_NB_INC);
+           (model == MODEL_SEIR && obs == OBS_NB_INC) || (model == MODEL_AGE && obs == OBS_NB_INC) ||
+           (model == MODEL_LG && obs == OBS_GAUSS);
 }
 
 static const void* kernel_for(int prec, int model, int obs, int sched)

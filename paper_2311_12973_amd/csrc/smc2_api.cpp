@@ -15,6 +15,7 @@
 
 #include "../../include/smc2.h"
 #include "mlp_kernels.h"
+#include "obs_words.h"
 #include "outer_kernels.h"
 #include "pf_kernel.h"
 #include "pmcmc_kernels.h"
@@ -25,13 +26,12 @@ namespace {
 
 thread_local std::string g_thread_error;
 
-int n_obs_of(int model) { return model == SMC2_AGE_SEIR ? 4 : 1; }
-
 int expected_D(int model, int D)
 {
     if (model == SMC2_SIR) return 2;
     if (model == SMC2_SEIR) return (D == 5) ? 5 : 4;
     if (model == SMC2_AGE_SEIR) return 8;
+    if (model == SMC2_LINGAUSS) return 3;
     return -1;
 }
 
@@ -79,7 +79,7 @@ Layout make_layout(const smc2_config* c, int R, const smc2_run* runs)
     Layout L;
     const size_t N = (size_t)c->N, D = (size_t)c->D, RN = (size_t)R * N;
     size_t ytot = 0;
-    for (int r = 0; r < R; ++r) ytot += (size_t)runs[r].T * n_obs_of(c->model);
+    for (int r = 0; r < R; ++r) ytot += (size_t)runs[r].T * obs_words(c->model);
     L.off_k = L.take(sizeof(int32_t));
     L.off_status = L.take(sizeof(int32_t) * R);
     L.off_psteps = L.take(sizeof(unsigned long long) * R);
@@ -197,14 +197,17 @@ struct smc2_ctx {
 static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::string& m)
 {
     if (!c || !runs || R < 1) return m = "null config/runs or n_runs < 1", SMC2_E_ARG;
-    if (c->model < SMC2_SIR || c->model > SMC2_AGE_SEIR) return m = "unknown model", SMC2_E_ARG;
-    if (c->obs < SMC2_OBS_POIS_PREV || c->obs > SMC2_OBS_NB_INC) return m = "unknown observation model", SMC2_E_ARG;
+    if (c->model < SMC2_SIR || c->model > SMC2_LINGAUSS) return m = "unknown model", SMC2_E_ARG;
+    if (c->obs < SMC2_OBS_POIS_PREV || c->obs > SMC2_OBS_GAUSS) return m = "unknown observation model", SMC2_E_ARG;
     if (!pf_supported(c->model, c->obs)) return m = "model/observation combination not supported", SMC2_E_UNSUPPORTED;
     if (c->D < 1 || c->D > SMC2_DMAX || expected_D(c->model, c->D) != c->D)
         return m = "D does not match the model", SMC2_E_ARG;
     if (c->N < 2 || c->N > 32768) return m = "N must be in [2, 32768]", SMC2_E_ARG;
     if (c->K < 1 || c->K > 65535) return m = "K must be in [1, 65535]", SMC2_E_ARG;
     if (c->precision != SMC2_PREC_FP32 && c->precision != SMC2_PREC_FP64) return m = "bad precision", SMC2_E_ARG;
+    const bool lg = c->model == SMC2_LINGAUSS;
+    if (lg && c->precision != SMC2_PREC_FP64)
+        return m = "the linear-Gaussian model runs in FP64 only", SMC2_E_UNSUPPORTED;
     if (c->proposal != SMC2_PROP_RW && c->proposal != SMC2_PROP_MLP) return m = "unknown proposal", SMC2_E_UNSUPPORTED;
     if (c->proposal == SMC2_PROP_MLP) {
         if (c->mlp_epochs < 0 || c->mlp_epochs > 1000) return m = "mlp_epochs must be in [0, 1000]", SMC2_E_ARG;
@@ -212,7 +215,7 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
         if (!(c->mlp_lr > 0.0 && c->mlp_lr < 1.0)) return m = "mlp_lr must be in (0, 1)", SMC2_E_ARG;
     }
     if (c->lkernel != SMC2_L_FORWARD && c->lkernel != SMC2_L_GAUSS_OPT) return m = "unknown L-kernel", SMC2_E_ARG;
-    if (!(c->n_pop >= 1.0 && c->n_pop <= 16777216.0 && c->n_pop == std::floor(c->n_pop)))
+    if (!lg && !(c->n_pop >= 1.0 && c->n_pop <= 16777216.0 && c->n_pop == std::floor(c->n_pop)))
         return m = "n_pop must be an integer in [1, 2^24]", SMC2_E_ARG;
     if (c->block != 0 && (c->block < 64 || c->block > 1024 || c->block % 64 != 0))
         return m = "block must be 0 or a multiple of 64 up to 1024", SMC2_E_ARG;
@@ -223,7 +226,7 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
         return m = "pf_resampling must be SMC2_PF_RS_SYSTEMATIC or SMC2_PF_RS_MULTINOMIAL", SMC2_E_ARG;
     if (c->mlp_train < SMC2_MLP_TRAIN_AUTO || c->mlp_train > SMC2_MLP_TRAIN_SPLIT)
         return m = "mlp_train must be SMC2_MLP_TRAIN_AUTO, _PER_RUN or _SPLIT", SMC2_E_ARG;
-    if (c->schedule == 2 && c->model == SMC2_AGE_SEIR)
+    if (c->schedule == 2 && c->model != SMC2_SIR && c->model != SMC2_SEIR)
         return m = "the pooled schedule supports SIR and SEIR only", SMC2_E_UNSUPPORTED;
     if (!c->prior || !c->rw_cov) return m = "prior and rw_cov are required", SMC2_E_ARG;
     if (c->n_fixed < 0 || c->n_fixed > SMC2_NFIXED || (c->n_fixed > 0 && !c->fixed))
@@ -239,19 +242,20 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
     }
     double L[SMC2_DMAX * SMC2_DMAX];
     if (!host_cholesky(c->D, c->rw_cov, L)) return m = "rw_cov is not positive definite", SMC2_E_ARG;
-    const int need_fixed = c->model == SMC2_SIR ? 1 : (c->model == SMC2_SEIR ? (c->D == 4 ? 1 : 0) : 20);
+    const int need_fixed = c->model == SMC2_SIR ? 1
+                         : c->model == SMC2_SEIR ? (c->D == 4 ? 1 : 0)
+                         : c->model == SMC2_LINGAUSS ? 2 : 20;
     if (c->n_fixed < need_fixed) return m = "missing model constants in fixed", SMC2_E_ARG;
     if (c->model == SMC2_SIR && !(c->fixed[0] >= 0 && c->fixed[0] <= c->n_pop))
         return m = "I_0 out of range", SMC2_E_ARG;
     if (c->model == SMC2_SEIR && c->D == 4 && !(c->fixed[0] > 0)) return m = "dispersion r must be > 0", SMC2_E_ARG;
+    if (lg && !(std::isfinite(c->fixed[0]) && c->fixed[1] >= 0 && std::isfinite(c->fixed[1])))
+        return m = "the initial state needs a finite mean and a finite standard deviation >= 0", SMC2_E_ARG;
     const int nxmax = c->model == SMC2_AGE_SEIR ? 2048 : 4096;
     for (int r = 0; r < R; ++r) {
         if (runs[r].T < 1 || runs[r].T > 1024) return m = "T must be in [1, 1024]", SMC2_E_ARG;
         if (runs[r].n_x < 1 || runs[r].n_x > nxmax) return m = "n_x out of range", SMC2_E_ARG;
-        if (!runs[r].y) return m = "null observations", SMC2_E_ARG;
-        const int no = n_obs_of(c->model);
-        for (int e = 0; e < runs[r].T * no; ++e)
-            if (runs[r].y[e] < 0) return m = "negative observation", SMC2_E_ARG;
+        if (const char* why = obs_check(c->model, runs[r])) return m = why, SMC2_E_ARG;
     }
     return SMC2_OK;
 }
@@ -317,7 +321,7 @@ static hipError_t autotune(smc2_ctx* c)
             if (b > std::max(64, full)) break;
             for (int sc = PF_SCHED_PER_DRAW; sc <= PF_SCHED_POOLED && e == hipSuccess; ++sc) {
                 if (cfg.schedule != SMC2_SCHED_AUTO && sc != cfg.schedule) continue;
-                if (sc == PF_SCHED_POOLED && cfg.model == SMC2_AGE_SEIR) continue;
+                if (sc == PF_SCHED_POOLED && cfg.model != SMC2_SIR && cfg.model != SMC2_SEIR) continue;
                 const size_t lds = pf_lds_bytes(cfg.model, cfg.precision, b, gr.max_nx, gr.max_T, sc);
                 if (lds > PF_LDS_MAX) continue;
                 e = pf_prepare(cfg.precision, cfg.model, cfg.obs, sc, lds);
@@ -407,14 +411,15 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     c->stream = (hipStream_t)hip_stream;
     c->ws = (unsigned char*)d_workspace;
     c->lay = lay;
-    const int no = n_obs_of(cfg->model);
     c->runs.assign(runs, runs + n_runs);
     std::vector<int32_t> yall;
     std::vector<RunDev> rd(n_runs);
     std::vector<uint64_t> seeds(n_runs);
     for (int r = 0; r < n_runs; ++r) {
-        c->ys.emplace_back(runs[r].y, runs[r].y + (size_t)runs[r].T * no);
-        c->runs[r].y = c->ys.back().data();
+        c->ys.emplace_back();
+        obs_pack(cfg->model, runs[r], c->ys.back());
+        c->runs[r].y = c->ys.back().data();  // the staged words (also for the linear-Gaussian model)
+        c->runs[r].y_real = nullptr;
         rd[r].T = runs[r].T;
         rd[r].nx = runs[r].n_x;
         rd[r].y_off = (int32_t)yall.size();
@@ -960,7 +965,7 @@ McLayout mc_layout(const smc2_config* c, int C, int iters, const smc2_run* run)
     McLayout L;
     const size_t D = (size_t)c->D;
     L.off_run = L.take(sizeof(RunDev));
-    L.off_y = L.take(sizeof(int32_t) * (size_t)run->T * n_obs_of(c->model));
+    L.off_y = L.take(sizeof(int32_t) * (size_t)run->T * obs_words(c->model));
     L.off_prior = L.take(sizeof(double) * D * 3);
     L.off_lrw = L.take(sizeof(double) * D * D);
     L.off_phi = L.take(sizeof(double) * C * D);
@@ -1045,9 +1050,10 @@ extern "C" int smc2_pmcmc_init(const smc2_config* cfg, int32_t chains, int32_t i
     c->cfg.prior = c->prior.data();
     c->cfg.rw_cov = c->rw_cov.data();
     c->cfg.fixed = c->fixed.data();
-    c->y.assign(run->y, run->y + (size_t)run->T * n_obs_of(cfg->model));
+    obs_pack(cfg->model, *run, c->y);
     c->run = *run;
     c->run.y = c->y.data();
+    c->run.y_real = nullptr;
     c->C = chains;
     c->iters = iters;
     c->ws = (unsigned char*)d_workspace;

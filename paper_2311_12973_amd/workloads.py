@@ -14,8 +14,8 @@ import math
 
 import numpy as np
 
-SIR, SEIR, AGE_SEIR = 0, 1, 2
-OBS_POIS_PREV, OBS_POIS_INC, OBS_NB_INC = 0, 1, 2
+SIR, SEIR, AGE_SEIR, LINGAUSS = 0, 1, 2, 3
+OBS_POIS_PREV, OBS_POIS_INC, OBS_NB_INC, OBS_GAUSS = 0, 1, 2, 3
 PREC_FP32, PREC_FP64 = 0, 1
 PRIOR_UNIFORM, PRIOR_LOGNORMAL, PRIOR_LOGITNORMAL, PRIOR_NORMAL = 0, 1, 2, 3
 L_FORWARD, L_GAUSS_OPT = 0, 1
@@ -34,8 +34,11 @@ def simulate(model, obs, n_pop, theta, T, seed, fixed=(), min_frac=0.01, max_tri
     """Simulate y_{1:T} (int32, shape (T, n_obs)) from the chain-binomial model.
 
     Redraws with seed+1, seed+2, ... until the total observed count reaches
-    ``min_frac`` of the population (an epidemic that took off).
+    ``min_frac`` of the population (an epidemic that took off). The linear-Gaussian
+    model gives float64 observations of shape (T,).
     """
+    if model == LINGAUSS:
+        return _simulate_lg(np.random.Generator(np.random.PCG64(seed)), theta, T, fixed)
     for attempt in range(max_tries):
         rng = np.random.Generator(np.random.PCG64(seed + attempt))
         y = _simulate_once(rng, model, obs, n_pop, theta, T, fixed)
@@ -93,6 +96,16 @@ def _simulate_once(rng, model, obs, n_pop, th, T, fixed):
     return y
 
 
+def _simulate_lg(rng, th, T, fixed):
+    a, sx, sy = th[0], th[1], th[2]
+    x = fixed[0] + fixed[1] * rng.standard_normal()
+    y = np.empty(T)
+    for t in range(T):
+        x = a * x + sx * rng.standard_normal()
+        y[t] = x + sy * rng.standard_normal()
+    return y
+
+
 def contact_matrix(seed=5):
     """4x4 contact matrix: Dirichlet(1,1,1,1) rows from a fixed seed, scaled to spectral radius 1."""
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -113,6 +126,8 @@ def preset(name, **over):
     seir_batched  256 SEIR runs, uneven T in [30,200] and Nx in {128,...,1024}, N=256
     seir_learned  SEIR with r estimated (D=5), T=150, N=4096, Nx=1024, K=20, MLP proposal
     age_seir    4-group SEIR, T=365, D=8, N=16384, Nx=2048, K=30
+    lingauss    scalar linear-Gaussian model (closed-form likelihood), T=100, D=3,
+                N=1024, Nx=256, K=10, FP64
     """
     if name == "paper_sir":
         w = dict(model=SIR, obs=OBS_POIS_PREV, D=2, prec=PREC_FP64, n_pop=1e4, fixed=[3],
@@ -145,6 +160,11 @@ def preset(name, **over):
                  + _lognormal_prior([10.0], 0.5) + [[PRIOR_LOGNORMAL, 0.0, 0.5]] * 3,
                  rw_cov=(0.01 * np.eye(8)).tolist(), T=365, N=16384, nx=2048, K=30, data_seed=5, seed=1,
                  proposal=PROP_MLP)
+    elif name == "lingauss":
+        w = dict(model=LINGAUSS, obs=OBS_GAUSS, D=3, prec=PREC_FP64, n_pop=1.0, fixed=[0.0, 1.0],
+                 truth=[0.8, 0.6, 1.0],
+                 prior=[[PRIOR_NORMAL, 0.5, 0.4]] + _lognormal_prior([0.5, 0.8], 0.5),
+                 rw_cov=(0.01 * np.eye(3)).tolist(), T=100, N=1024, nx=256, K=10, data_seed=8, seed=1)
     else:
         raise KeyError(name)
     w.setdefault("lkernel", L_GAUSS_OPT)

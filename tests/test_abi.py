@@ -150,3 +150,40 @@ def test_pmcmc_entry_points_reject_bad_arguments():
     assert h.value is None
     assert L.smc2_pmcmc_step(None, 1) == G.E_ARG
     assert L.smc2_pmcmc_destroy(None) == G.OK
+
+
+def test_linear_gaussian_model_validation():
+    # real observations through y_real; FP64 only; D = 3; per-draw schedule only
+    L = G.lib()
+    w = W.preset("lingauss")
+    y = W.observations(w)
+    runs = G.make_runs([dict(T=w["T"], nx=w["nx"], seed=1, y=y)])
+    assert runs[0].y_real and not runs[0].y
+    cfg = G.make_config(w)
+    nb = L.smc2_workspace_bytes(ctypes.byref(cfg), 1, runs)
+    assert nb > 0, L.smc2_last_error(None)
+    c32 = G.make_config(w, precision=G.PREC_FP32)
+    assert L.smc2_workspace_bytes(ctypes.byref(c32), 1, runs) == 0
+    assert b"FP64 only" in L.smc2_last_error(None)
+    h = ctypes.c_void_p()
+    assert L.smc2_init(ctypes.byref(c32), 1, runs, ctypes.c_void_p(4096), 1 << 30, None,
+                       ctypes.byref(h)) == G.E_UNSUPPORTED
+    for over in [dict(D=2, prior=w["prior"][:2], rw_cov=np.eye(2).tolist()), dict(obs=W.OBS_NB_INC),
+                 dict(fixed=[0.0]), dict(fixed=[0.0, -1.0])]:
+        c = G.make_config(dict(w, **over))
+        assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == 0, over
+    cp = G.make_config(w, schedule=G.SCHED_POOLED)
+    assert L.smc2_workspace_bytes(ctypes.byref(cp), 1, runs) == 0
+    assert b"pooled" in L.smc2_last_error(None)
+    bad = y.copy()
+    bad[3] = np.nan
+    assert L.smc2_workspace_bytes(ctypes.byref(cfg), 1, G.make_runs([dict(T=w["T"], nx=64, seed=1, y=bad)])) == 0
+    assert b"non-finite" in L.smc2_last_error(None)
+    # counts where reals are expected: no y_real
+    rc = G.make_runs([dict(T=w["T"], nx=64, seed=1, y=np.zeros(w["T"], dtype=np.int32))])
+    assert L.smc2_workspace_bytes(ctypes.byref(cfg), 1, rc) == 0
+    assert b"y_real" in L.smc2_last_error(None)
+    fake = ctypes.c_void_p(1 << 20)
+    ws = L.smc2_pf_workspace_bytes(ctypes.byref(cfg), runs)
+    assert ws >= 256 + 8 * w["T"]
+    assert L.smc2_pf_loglik(ctypes.byref(c32), 4, fake, runs, 1, fake, fake, ws, None) == G.E_UNSUPPORTED
