@@ -58,7 +58,12 @@ VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_amd/csrc/pf_kernel.h",
                   "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h",
                   "paper_2311_12973_amd/build.py"]
-MEASURED = {}
+MEASURED = {
+    "age_seir": dict(sha="af212835b43c92fb", valu_lane_instr_per_pstep=2416.9, hbm_bytes_per_launch=13927920363,
+                     profile="profiles/pf_kernel_age_seir_n16384_nx2048_t365.txt"),
+    "seir": dict(sha="af212835b43c92fb", valu_lane_instr_per_pstep=1419.2, hbm_bytes_per_launch=1102715,
+                 profile="profiles/pf_kernel_seir_n1024_nx512_t100.txt"),
+}
 
 
 def kernel_sha():
