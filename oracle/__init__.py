@@ -70,7 +70,10 @@ def _declare(L):
         c.c_uint32] * 4 + [P(c.c_int32)]
     L.or_pf_lg.restype = c.c_double
     L.or_pf_lg.argtypes = [c.c_double] * 5 + [P(c.c_double), c.c_int, c.c_int, c.c_uint64, c.c_uint32, c.c_uint32,
-                                              c.c_int, c.c_int, P(c.c_double), P(c.c_int32), P(c.c_double)]
+                                              c.c_int, c.c_int, P(c.c_double), P(c.c_int32), P(c.c_double),
+                                              P(c.c_double)]
+    L.or_digamma.restype = c.c_double
+    L.or_digamma.argtypes = [c.c_double]
     L.or_resample_multinomial.argtypes = [P(c.c_uint64), c.c_int, c.c_uint64, c.c_uint32, c.c_uint32, P(c.c_int32)]
     L.or_events_get.argtypes = [P(c.c_double)]
     L.or_events_reset.argtypes = []
@@ -91,6 +94,9 @@ def _declare(L):
     L.or_prior_logpdf.argtypes = [P(Config), P(c.c_double)]
     L.or_theta_of_phi.argtypes = [P(Config), P(c.c_double), P(c.c_double)]
     L.or_recycle.argtypes = [c.c_int, c.c_int, P(c.c_double), P(c.c_double), P(c.c_double), P(c.c_double)]
+    L.or_pf_score.restype = c.c_double
+    L.or_pf_score.argtypes = [P(Config), P(c.c_double), P(c.c_int32), c.c_int, c.c_int, c.c_uint64, c.c_uint32,
+                              c.c_uint32, P(c.c_double)]
     L.or_pf_loglik.restype = c.c_double
     L.or_pf_loglik.argtypes = [P(Config), P(c.c_double), P(c.c_int32), c.c_int, c.c_int, c.c_uint64,
                                c.c_uint32, c.c_uint32, P(c.c_double), P(c.c_int32)]
@@ -434,21 +440,39 @@ def resample_multinomial(q, seed, filt, kt):
 
 
 def pf_lg(phi, sq, sr, m0, s0, y, nx, seed, filt=0, pf_always=0, trace=False, resampling=RS_SYSTEMATIC, k=0,
-          states=False):
+          states=False, score=False):
     """Log of the particle filter's likelihood estimate on the scalar linear-Gaussian
     model x_t = phi x_{t-1} + sq e_t, y_t = x_t + sr d_t, x_0 ~ N(m0, s0^2), on the
     streams of iteration k. trace: also the per-day increments and resampling flags;
-    states: also the states of each day before resampling (T x nx)."""
+    states: also the states of each day before resampling (T x nx); score: also the
+    estimate of d log p(y) / d(phi, sq, sr)."""
     y = np.ascontiguousarray(y, dtype=np.float64)
     T = y.shape[0]
     inc = np.zeros(T) if trace else None
     rs = np.zeros(T, dtype=np.int32) if trace else None
     xs = np.zeros((T, nx)) if states else None
+    sc = np.zeros(3) if score else None
     ll = lib().or_pf_lg(phi, sq, sr, m0, s0, _p(y, ctypes.c_double), T, nx, int(seed), int(filt), int(k),
                         int(pf_always), int(resampling), _p(inc, ctypes.c_double) if trace else None,
-                        _p(rs, ctypes.c_int32) if trace else None, _p(xs, ctypes.c_double) if states else None)
-    out = (ll,) + ((inc, rs) if trace else ()) + ((xs,) if states else ())
+                        _p(rs, ctypes.c_int32) if trace else None, _p(xs, ctypes.c_double) if states else None,
+                        _p(sc, ctypes.c_double) if score else None)
+    out = (ll,) + ((inc, rs) if trace else ()) + ((xs,) if states else ()) + ((sc,) if score else ())
     return out if len(out) > 1 else ll
+
+
+def pf_score(cfg, theta, y, nx, seed, filt, k):
+    """(log-likelihood estimate, score estimate on the natural parameters) of one
+    filter (SIR and SEIR)."""
+    y = np.ascontiguousarray(y, dtype=np.int32)
+    th = np.ascontiguousarray(theta, dtype=np.float64)
+    sc = np.zeros(cfg.D)
+    ll = lib().or_pf_score(ctypes.byref(cfg), _p(th, ctypes.c_double), _p(y, ctypes.c_int32), y.shape[0], nx,
+                           int(seed), int(filt), int(k), _p(sc, ctypes.c_double))
+    return ll, sc
+
+
+def digamma(x):
+    return lib().or_digamma(float(x))
 
 
 # event counters of the particle filter (order of the OR_EV_* enumeration)

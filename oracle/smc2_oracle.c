@@ -447,6 +447,22 @@ static double or_model_start(const or_config* cfg, const double* th, int32_t* x0
     return th[4];
 }
 
+/* Digamma psi(x) for x > 0 (FP64): the recurrence psi(x) = psi(x + 1) - 1/x up to
+ * x >= 10, then the asymptotic series ln x - 1/(2x) - sum_k B_2k / (2k x^2k) with the
+ * Bernoulli numbers B_2 .. B_14 (remainder below 1e-17 at x = 10). */
+double or_digamma(double x)
+{
+    double acc = 0.0;
+    while (x < 10.0) {
+        acc = acc - 1.0 / x;
+        x = x + 1.0;
+    }
+    const double r = 1.0 / x, r2 = r * r;
+    const double series =
+        r2 * (1.0 / 12 - r2 * (1.0 / 120 - r2 * (1.0 / 252 - r2 * (1.0 / 240 - r2 * (1.0 / 132 - r2 * (691.0 / 32760 - r2 * (1.0 / 12)))))));
+    return acc + ((log(x) - 0.5 * r) - series);
+}
+
 #define REAL float
 #define FN(x) x##_f32
 #include "pf_real.inc"
@@ -495,7 +511,7 @@ void or_binomial_many(int prec, int count, const int32_t* n, const double* p, ui
  */
 double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const double* y, int T, int nx,
                 uint64_t seed, uint32_t filt, uint32_t k, int pf_always, int resampling, double* inc_out,
-                int32_t* rs_out, double* x_out)
+                int32_t* rs_out, double* x_out, double* score_out)
 {
     double* x = (double*)malloc(sizeof(double) * (size_t)nx);
     double* xs = (double*)malloc(sizeof(double) * (size_t)nx);
@@ -504,6 +520,11 @@ double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const do
     double* w = (double*)malloc(sizeof(double) * (size_t)nx);
     uint64_t* qq = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)nx);
     int32_t* anc = (int32_t*)malloc(sizeof(int32_t) * (size_t)nx);
+    /* score: running complete-data score of (phi, sq, sr) per particle; with the drawn
+     * noise e = (x_t - phi x_{t-1}) / sq: d/dphi = e x_{t-1} / sq, d/dsq = (e^2 - 1) / sq,
+     * and from the observation d/dsr = (z^2 - 1) / sr */
+    double* sj = score_out ? (double*)calloc((size_t)nx * 3, sizeof(double)) : NULL;
+    double* sjs = score_out ? (double*)malloc(sizeof(double) * (size_t)nx * 3) : NULL;
     for (int j = 0; j < nx; ++j) {
         uint32_t ctr[4] = {(uint32_t)j, filt, k << 16, 8u << 24};
         x[j] = m0 + s0 * or_normal_call(seed, ctr);
@@ -514,9 +535,17 @@ double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const do
     for (int t = 1; t <= T; ++t) {
         for (int j = 0; j < nx; ++j) {
             uint32_t ctr[4] = {(uint32_t)j, filt, (k << 16) | (uint32_t)t, 8u << 24};
-            x[j] = phi * x[j] + sq * or_normal_call(seed, ctr);
+            const double e = or_normal_call(seed, ctr);
+            const double xp = x[j];
+            x[j] = phi * xp + sq * e;
             const double z = (y[t - 1] - x[j]) / sr;
             a[j] = lw[j] + -0.5 * z * z;
+            if (sj) {
+                double* sc = sj + (size_t)j * 3;
+                sc[0] = sc[0] + (e * xp) / sq;
+                sc[1] = sc[1] + (e * e - 1.0) / sq;
+                sc[2] = sc[2] + (z * z - 1.0) / sr;
+            }
         }
         if (x_out) memcpy(x_out + (size_t)(t - 1) * nx, x, sizeof(double) * (size_t)nx);
         double inc;
@@ -532,8 +561,26 @@ double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const do
         if (rs) {
             for (int j = 0; j < nx; ++j) xs[j] = x[anc[j]];
             memcpy(x, xs, sizeof(double) * (size_t)nx);
+            if (sj) {
+                for (int j = 0; j < nx; ++j)
+                    for (int d = 0; d < 3; ++d) sjs[(size_t)j * 3 + d] = sj[(size_t)anc[j] * 3 + d];
+                memcpy(sj, sjs, sizeof(double) * (size_t)nx * 3);
+            }
         }
     }
+    if (score_out) { /* the final weights average the particles' scores */
+        for (int d = 0; d < 3; ++d) score_out[d] = 0.0;
+        if (ll != -INFINITY) {
+            double S = 0.0;
+            for (int j = 0; j < nx; ++j) S = S + w[j];
+            for (int d = 0; d < 3; ++d) {
+                double num = 0.0;
+                for (int j = 0; j < nx; ++j) num = num + w[j] * sj[(size_t)j * 3 + d];
+                score_out[d] = num / S;
+            }
+        }
+    }
+    free(sj); free(sjs);
     free(x); free(xs); free(lw); free(a); free(w); free(qq); free(anc);
     return ll;
 }
@@ -556,8 +603,20 @@ double or_pf_trace_full(const or_config* cfg, const double* theta, const int32_t
                         int32_t* state_out, int32_t* anc_out)
 {
     if (cfg->prec == OR_PREC_FP32)
-        return pf_f32(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out, state_out, anc_out);
-    return pf_f64(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out, state_out, anc_out);
+        return pf_f32(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out, state_out, anc_out, NULL);
+    return pf_f64(cfg, theta, y, T, nx, seed, filt, k, inc_out, rs_out, state_out, anc_out, NULL);
+}
+
+double or_pf_score(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx, uint64_t seed,
+                   uint32_t filt, uint32_t k, double* score_out)
+{
+    if (cfg->model != OR_SIR && cfg->model != OR_SEIR) {
+        for (int d = 0; d < cfg->D; ++d) score_out[d] = NAN;
+        return NAN;
+    }
+    if (cfg->prec == OR_PREC_FP32)
+        return pf_f32(cfg, theta, y, T, nx, seed, filt, k, NULL, NULL, NULL, NULL, score_out);
+    return pf_f64(cfg, theta, y, T, nx, seed, filt, k, NULL, NULL, NULL, NULL, score_out);
 }
 
 /*

@@ -168,10 +168,24 @@ void or_events_reset(void);
  * x_0 ~ N(m0, s0^2), x_t = phi x_{t-1} + sq e_t, y_t = x_t + sr d_t; returns the log of
  * the likelihood estimate; k is the iteration index of the streams; inc_out / rs_out
  * (T entries, optional) as or_pf_loglik; x_out (T x nx, optional) the states of each
- * day before resampling. */
+ * day before resampling; score_out (3, optional, needs sq > 0) the estimate of the score
+ * d log p(y) / d(phi, sq, sr) as or_pf_score forms it. */
 double or_pf_lg(double phi, double sq, double sr, double m0, double s0, const double* y, int T, int nx,
                 uint64_t seed, uint32_t filt, uint32_t k, int pf_always, int resampling, double* inc_out,
-                int32_t* rs_out, double* x_out);
+                int32_t* rs_out, double* x_out, double* score_out);
+
+/* Score of the log-likelihood estimate (Fisher's identity: grad log p(y | theta) =
+ * E[grad log p(x_{0:T}, y | theta) | y]), estimated by the same filter: each particle
+ * carries the running complete-data score of its trajectory on the natural parameters
+ * theta (the flows' d log Bin / d theta, and d log NB / d r when r is estimated),
+ * resampling moves it with the particle, and the last day's weights average it. SIR and
+ * SEIR; the SEIR initial fraction iota enters only through a rounding and gets 0.
+ * score_out: D doubles (0 when every weight vanished; NaN for other models). Returns
+ * the log-likelihood estimate, equal to or_pf_loglik's. */
+double or_pf_score(const or_config* cfg, const double* theta, const int32_t* y, int T, int nx, uint64_t seed,
+                   uint32_t filt, uint32_t k, double* score_out);
+/* Digamma function psi(x), x > 0. */
+double or_digamma(double x);
 /* Multinomial ancestors from quantised weights: slot m draws U_m = floor(x64_m Q / 2^64)
  * (x64_m: 64-bit word m&1 of the Philox call (m>>1, filt, kt, 2<<24 | 1<<16)) and takes
  * the first j whose inclusive scan C_j exceeds U_m. */

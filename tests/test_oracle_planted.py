@@ -39,6 +39,21 @@ KALMAN_PLANTS = {
 }
 
 
+SCORE_PLANTS = {
+    # a particle keeps its own score when resampling hands it another trajectory's state
+    "score_not_resampled": [("pf_real.inc", "                memcpy(sj, sjs, sizeof(double) * (size_t)nx * D);\n", ""),
+                            ("smc2_oracle.c", "                memcpy(sj, sjs, sizeof(double) * (size_t)nx * 3);\n", "")],
+    # the final average without the last day's weights
+    "score_unweighted": [("pf_real.inc", "num = num + w[jj] * sj[(size_t)jj * D + d];",
+                          "num = num + (S / (double)nx) * sj[(size_t)jj * D + d];"),
+                         ("smc2_oracle.c", "num = num + w[j] * sj[(size_t)j * 3 + d];",
+                          "num = num + (S / (double)nx) * sj[(size_t)j * 3 + d];")],
+    # the infection flow's d h / d beta = I / N_pop dropped
+    "hazard_derivative_dropped": [("pf_real.inc", "sc[0] = FN(flow_score)(S, p_si, nsi) * ((double)I / cfg->n_pop);",
+                                   "sc[0] = FN(flow_score)(S, p_si, nsi);")],
+}
+
+
 PMCMC_PLANTS = {
     "prior_dropped_from_the_ratio": [("smc2_oracle.c", "    const double cur = lp + ll, nw = lp_new + ll_new;",
                                       "    const double cur = ll, nw = ll_new;")],
@@ -53,7 +68,7 @@ PMCMC_PLANTS = {
 @pytest.fixture(scope="module")
 def planted_libs(tmp_path_factory):
     d = str(tmp_path_factory.mktemp("planted"))
-    plants = dict(AGE_PLANTS, **KALMAN_PLANTS, **PMCMC_PLANTS)
+    plants = dict(AGE_PLANTS, **KALMAN_PLANTS, **PMCMC_PLANTS, **SCORE_PLANTS)
     with cf.ThreadPoolExecutor(max_workers=4) as ex:
         futs = {name: ex.submit(PL.build_planted, name, edits, d) for name, edits in plants.items()}
         return {name: f.result() for name, f in futs.items()}
@@ -80,6 +95,16 @@ def test_kalman_pin_catches_a_broken_weight_recursion(planted_libs, name):
         mean, se = kalman_pin_statistic()
     print(name, mean, se)
     assert abs(mean - 1.0) > 4 * se + 1e-3, (name, mean, se)
+
+
+@pytest.mark.parametrize("name", sorted(SCORE_PLANTS))
+def test_score_pins_catch_a_broken_score(planted_libs, name):
+    from tests.test_oracle_score import _close, lg_score_statistic, sir_score_statistic
+    with PL.installed(planted_libs[name]):
+        ok_sir = _close(*sir_score_statistic(M=100))[0]
+        ok_lg = _close(*lg_score_statistic(M=100))[0]
+    print(name, ok_sir, ok_lg)
+    assert not (ok_sir and ok_lg), name
 
 
 @pytest.mark.parametrize("name", sorted(PMCMC_PLANTS))
