@@ -82,6 +82,23 @@ int smc2_pf_trace_state(const smc2_config* cfg, int32_t n_theta, const double* d
                         uint32_t k, double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, int32_t* d_anc,
                         void* d_workspace, size_t ws_bytes, void* hip_stream);
 
+/* Score of the log-likelihood estimate (the gradient of log p(y | theta) on the natural
+ * parameters; by Fisher's identity the posterior mean of the complete-data score, Sec. II
+ * filter): each particle carries its trajectory's running score (per flow
+ * d log Bin / d theta through the hazard, d log NB / d r when r is a parameter; for
+ * SMC2_LINGAUSS the derivatives of the two Gaussian densities), resampling moves it with
+ * the particle, and the last day's weights average it. The estimate is consistent in
+ * n_x, not unbiased. d_ll: double[n_theta], the same estimates as smc2_pf_loglik's;
+ * d_score: double[n_theta][D]. SIR (D = 2), SEIR (D = 4 or 5; the initial fraction iota
+ * enters only through a rounding and gets 0) and SMC2_LINGAUSS (D = 3, needs
+ * sigma_x > 0); other models return SMC2_E_UNSUPPORTED. A filter whose weights all
+ * vanish gets -inf and a zero score. Runs the per-draw schedule whatever cfg->schedule
+ * says, with the scores in LDS beside the counts: n_x up to 2048 (for SEIR in FP64 with
+ * T <= 365); beyond the LDS budget SMC2_E_ARG. The workspace is smc2_pf_workspace_bytes'.
+ * Returns after the stream has run the filters. */
+int smc2_pf_score(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run, uint32_t k,
+                  double* d_ll, double* d_score, void* d_workspace, size_t ws_bytes, void* hip_stream);
+
 /* Learned proposal, network outputs (SMC2_PROP_MLP). d_params: FP32 weights in the
  * layout of SMC2_DUMP_MLP_PARAMS for dimension D (1..8); d_frame: D + D*D doubles
  * (mean c, lower Cholesky factor F row-major; the inputs are F^-1 (phi - c)); d_phi:

@@ -134,6 +134,8 @@ def lib():
                                           c.c_size_t, vp]
         L.smc2_pf_loglik.restype = c.c_int
         L.smc2_pf_loglik.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp, c.c_size_t, vp]
+        L.smc2_pf_score.restype = c.c_int
+        L.smc2_pf_score.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp, vp, c.c_size_t, vp]
         L.smc2_pf_loglik_noalloc.restype = c.c_int
         L.smc2_pf_loglik_noalloc.argtypes = [P(Config), c.c_int32, vp, P(Run), c.c_uint32, vp, vp]
         L.smc2_pmcmc_workspace_bytes.restype = c.c_size_t
@@ -441,6 +443,24 @@ def pf_loglik(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0,
     _check(L.smc2_pf_trace(ctypes.byref(cfg), n, pth, runs, int(k), pll, pinc, prs, pws, wsb, current_stream()))
     return (from_device(tll, pll, np.float64, n), from_device(tinc, pinc, np.float64, n * T).reshape(n, T),
             from_device(trs, prs, np.int32, n * T).reshape(n, T))
+
+
+def pf_score(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0, device="cuda"):
+    """(log-likelihood estimates [n], score estimates [n][D] on the natural parameters)
+    for the rows of theta (smc2_pf_score)."""
+    cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, pf_always=pf_always, block=block)
+    y = obs_array(y)
+    runs = make_runs([dict(T=y.shape[0], nx=nx, seed=seed, y=y)])
+    theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))
+    n, D = theta.shape
+    L = lib()
+    wsb = L.smc2_pf_workspace_bytes(ctypes.byref(cfg), runs)
+    tws, pws = device_buffer(wsb, device)
+    tth, pth = to_device(theta, device)
+    tll, pll = device_buffer(8 * n, device)
+    tsc, psc = device_buffer(8 * n * D, device)
+    _check(L.smc2_pf_score(ctypes.byref(cfg), n, pth, runs, int(k), pll, psc, pws, wsb, current_stream()))
+    return from_device(tll, pll, np.float64, n), from_device(tsc, psc, np.float64, n * D).reshape(n, D)
 
 
 def pf_loglik_noalloc(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0, device="cuda", schedule=0):

@@ -157,14 +157,14 @@ extern "C" int smc2_pf_loglik(const smc2_config* cfg, int32_t n_theta, const dou
 }
 
 static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run, uint32_t k,
-                  double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, int32_t* d_anc, void* d_ws,
-                  size_t ws_bytes, void* stream, bool static_ws = false);
+                  double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, int32_t* d_anc, double* d_score,
+                  void* d_ws, size_t ws_bytes, void* stream, bool static_ws = false, bool score = false);
 
 extern "C" int smc2_pf_trace(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
                              uint32_t k, double* d_ll, double* d_inc, int32_t* d_rs, void* d_ws, size_t ws_bytes,
                              void* stream)
 {
-    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, d_inc, d_rs, nullptr, nullptr, d_ws, ws_bytes, stream);
+    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, d_inc, d_rs, nullptr, nullptr, nullptr, d_ws, ws_bytes, stream);
 }
 
 extern "C" int smc2_pf_trace_state(const smc2_config* cfg, int32_t n_theta, const double* d_theta,
@@ -172,20 +172,34 @@ extern "C" int smc2_pf_trace_state(const smc2_config* cfg, int32_t n_theta, cons
                                    int32_t* d_state, int32_t* d_anc, void* d_ws, size_t ws_bytes, void* stream)
 {
     if (!d_state) return kfail(SMC2_E_ARG, "d_state is NULL");
-    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, d_inc, d_rs, d_state, d_anc, d_ws, ws_bytes, stream);
+    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, d_inc, d_rs, d_state, d_anc, nullptr, d_ws, ws_bytes, stream);
+}
+
+extern "C" int smc2_pf_score(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run,
+                             uint32_t k, double* d_ll, double* d_score, void* d_ws, size_t ws_bytes, void* stream)
+{
+    if (n_theta > 0 && !d_score) return kfail(SMC2_E_ARG, "d_score is NULL");
+    if (!cfg) return kfail(SMC2_E_ARG, "null config or run");
+    if (pf_score_dims(cfg->model) == 0) return kfail(SMC2_E_UNSUPPORTED, "no score for this model");
+    if (cfg->model == SMC2_SEIR && cfg->D != 4 && cfg->D != 5) return kfail(SMC2_E_ARG, "SEIR needs D = 4 or 5");
+    if (cfg->model != SMC2_SEIR && cfg->D != pf_score_dims(cfg->model)) return kfail(SMC2_E_ARG, "bad D");
+    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, nullptr, nullptr, nullptr, nullptr, d_score, d_ws, ws_bytes,
+                  stream, false, true);
 }
 
 extern "C" int smc2_pf_loglik_noalloc(const smc2_config* cfg, int32_t n_theta, const double* d_theta,
                                       const smc2_run* run, uint32_t k, double* d_ll, void* stream)
 {
-    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, nullptr, nullptr, nullptr, nullptr, nullptr, 0, stream, true);
+    return pf_run(cfg, n_theta, d_theta, run, k, d_ll, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, stream,
+                  true);
 }
 
 // static_ws: the workspace is the file-scope scratch (d_ws and ws_bytes unused); its
 // device address is resolved only after every argument has been checked.
+// score: the score launch into d_score (the per-draw schedule carrying each particle's score)
 static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run, uint32_t k,
-                  double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, int32_t* d_anc, void* d_ws,
-                  size_t ws_bytes, void* stream, bool static_ws)
+                  double* d_ll, double* d_inc, int32_t* d_rs, int32_t* d_state, int32_t* d_anc, double* d_score,
+                  void* d_ws, size_t ws_bytes, void* stream, bool static_ws, bool score)
 {
     if ((d_inc == nullptr) != (d_rs == nullptr)) return kfail(SMC2_E_ARG, "trace needs both d_inc and d_rs");
     if (!cfg || !run) return kfail(SMC2_E_ARG, "null config or run");
@@ -216,9 +230,9 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64 != 0))
         return kfail(SMC2_E_ARG, "block must be 0 or a multiple of 64 up to 1024");
     if (cfg->schedule < 0 || cfg->schedule > 2) return kfail(SMC2_E_ARG, "schedule must be 0, 1 or 2");
-    const int block = cfg->block ? cfg->block
-                                 : pf_default_block(cfg->model, cfg->precision, run->n_x, run->T, cfg->schedule);
-    const int sched = pf_pick_schedule(cfg->model, cfg->precision, block, run->n_x, run->T, cfg->schedule);
+    const int want = score ? PF_SCHED_SCORE : cfg->schedule;
+    const int block = cfg->block ? cfg->block : pf_default_block(cfg->model, cfg->precision, run->n_x, run->T, want);
+    const int sched = pf_pick_schedule(cfg->model, cfg->precision, block, run->n_x, run->T, want);
     if (sched < 0) return kfail(SMC2_E_ARG, "the pooled schedule cannot run this model, n_x and T");
     const size_t lds = pf_lds_bytes(cfg->model, cfg->precision, block, run->n_x, run->T, sched);
     if (lds > PF_LDS_MAX) return kfail(SMC2_E_ARG, "particle filter does not fit in LDS");
@@ -249,6 +263,7 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     a.trace_rs = d_rs;
     a.trace_state = d_state;
     a.trace_anc = d_anc;
+    a.score = d_score;
     a.k_const = k;
     a.n_items = n_theta;
     a.N = n_theta;

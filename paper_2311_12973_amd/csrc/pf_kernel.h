@@ -34,6 +34,7 @@ struct PFArgs {
                             // resampling; unwritten after a filter's death day), or NULL
     unsigned long long* psteps;  // [n_runs] executed particle-steps: each filter adds N_x x
                                  // the days it ran (to its death day), or NULL
+    double* score;          // [G][D] score estimates (PF_SCHED_SCORE launches only)
     int32_t* queue;         // work-list counter (zero at launch) for a persistent grid, or NULL
     uint32_t k_const;
     int32_t n_items;
@@ -51,6 +52,13 @@ struct PFArgs {
 // draws in turn, or (SIR, SEIR) the wave pools the draws and batches the final
 // acceptance tests of the BTRS sampler. Both give identical flows.
 enum : int { PF_SCHED_AUTO = 0, PF_SCHED_PER_DRAW = 1, PF_SCHED_POOLED = 2 };
+// Internal launch variant: the per-draw schedule that also carries each particle's
+// running score of its trajectory and writes the filter's score estimate (SIR, SEIR and
+// the linear-Gaussian model). Not a value of smc2_config.schedule.
+constexpr int PF_SCHED_SCORE = 3;
+// score coordinates kept per particle: SIR 2, SEIR 5 (iota's stays 0, r's is used when
+// r is estimated), linear-Gaussian 3; 0 where the score is not supported
+int pf_score_dims(int model);
 // dynamic LDS budget of one workgroup (the kernel adds a few bytes of static LDS)
 constexpr size_t PF_LDS_MAX = 160 * 1024 - 256;
 

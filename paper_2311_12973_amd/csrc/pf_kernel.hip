@@ -120,15 +120,65 @@ __device__ __forceinline__ void model_setup(const PFArgs& a, const double* th, M
     }
 }
 
+// ------------------------------------------------------------ score (Fisher's identity)
+// Score coordinates kept per particle (on the natural parameters), as FP64 values in
+// pairs of 32-bit LDS words after the counts: column d at sw[2d cap + j] (low word) and
+// sw[(2d + 1) cap + j] (high word), so the resampling gather moves them with the counts.
+template <int MODEL> struct ScoreDims { static constexpr int NS = 0; };
+template <> struct ScoreDims<MODEL_SIR> { static constexpr int NS = 2; };   // beta, gamma
+template <> struct ScoreDims<MODEL_SEIR> { static constexpr int NS = 5; };  // beta, sigma, gamma, iota (0), r
+template <> struct ScoreDims<MODEL_LG> { static constexpr int NS = 3; };    // a, sigma_x, sigma_y
+
+__device__ __forceinline__ double lds_f64(const int32_t* w, int cap, int j) { return __hiloint2double(w[cap + j], w[j]); }
+__device__ __forceinline__ void lds_add_f64(int32_t* w, int cap, int j, double v)
+{
+    const double x = __hiloint2double(w[cap + j], w[j]) + v;
+    w[j] = __double2loint(x);
+    w[cap + j] = __double2hiint(x);
+}
+
+// d log Bin(k; n, p) / d h for p = 1 - exp(-h): (k - n p) / p, and -n at p = 0 (k = 0 then)
+template <typename real> __device__ __forceinline__ double flow_score(int32_t n, real p, int32_t k)
+{
+    return p > (real)0 ? ((double)k - (double)n * (double)p) / (double)p : -(double)n;
+}
+
+// psi(x), x > 0, in FP64: the recurrence psi(x) = psi(x + 1) - 1/x up to x >= 10, then the
+// asymptotic expansion ln x - 1/(2x) - sum_{k=1..7} B_2k / (2k x^2k) (Bernoulli numbers)
+__device__ __noinline__ double digamma_f64(double x)
+{
+    double acc = 0.0;
+    while (x < 10.0) {
+        acc = acc - 1.0 / x;
+        x = x + 1.0;
+    }
+    const double r = 1.0 / x, r2 = r * r;
+    const double tail =
+        r2 * (1.0 / 12 - r2 * (1.0 / 120 - r2 * (1.0 / 252 - r2 * (1.0 / 240 - r2 * (1.0 / 132 - r2 * (691.0 / 32760 - r2 * (1.0 / 12)))))));
+    return acc + ((log(x) - 0.5 * r) - tail);
+}
+
+// what particle_day needs for the score: the score words, N_pop, the day's
+// psi(y_t + r) - psi(r), and whether r is a parameter
+struct ScoreDay {
+    int32_t* sw;
+    double n_pop;
+    double dpsi;
+    bool nr;
+};
+
 // One day of the chain-binomial model for particle j, whose counts live in LDS
 // (st[c * cap + j]); flows drawn from the previous day's state. Draw index b:
 // SIR (S->I, I->R) = (0, 1); SEIR (S->E, E->I, I->R) = (0, 1, 2); age-structured
 // group g: 3g, 3g+1, 3g+2 (the draw index equals the index of the compartment the
 // flow leaves). One copy of the sampler per model: the draws of a day run in a
-// loop. Returns the per-particle part of log g(y_t | x_t) in FP64.
-template <typename real, int MODEL, int OBS>
+// loop. Returns the per-particle part of log g(y_t | x_t) in FP64. With SCORE it adds
+// the day's complete-data score to the particle's: per flow d log Bin / d h times
+// d h / d theta (I / N_pop for beta, 1 for sigma and gamma), d log g / d r, and for the
+// linear-Gaussian model the derivatives of its two Gaussian densities.
+template <typename real, int MODEL, int OBS, bool SCORE = false>
 __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* st, int cap, int j,
-                                               DrawStream ds, const int32_t* yt)
+                                               DrawStream ds, const int32_t* yt, const ScoreDay& sd = ScoreDay{})
 {
     if constexpr (MODEL == MODEL_LG) {
         // x_t = ar x_{t-1} + sq e_t; log g = -z^2 / 2 with z = (y_t - x_t) / sr (the
@@ -139,6 +189,11 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
         st[j] = __double2loint(x1);
         st[cap + j] = __double2hiint(x1);
         const double z = (__hiloint2double(yt[1], yt[0]) - x1) / mc.sr;
+        if constexpr (SCORE) {
+            lds_add_f64(sd.sw, cap, j, (e * x) / mc.sq);
+            lds_add_f64(sd.sw + 2 * cap, cap, j, (e * e - 1.0) / mc.sq);
+            lds_add_f64(sd.sw + 4 * cap, cap, j, (z * z - 1.0) / mc.sr);
+        }
         return -0.5 * z * z;
     }
     if (MODEL == MODEL_SIR) {
@@ -155,6 +210,10 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
         const int32_t I1 = I + nsi - nir;
         st[j] = S - nsi;
         st[cap + j] = I1;
+        if constexpr (SCORE) {
+            lds_add_f64(sd.sw, cap, j, flow_score<real>(S, p_si, nsi) * ((double)I / sd.n_pop));
+            lds_add_f64(sd.sw + 2 * cap, cap, j, flow_score<real>(I, mc.p_ir, nir));
+        }
         return obs_part<OBS>(yt[0], OBS == OBS_POIS_PREV ? I1 : nsi, mc.r);
     } else if (MODEL == MODEL_SEIR) {
         const int32_t S = st[j], E = st[cap + j], I = st[2 * cap + j];
@@ -175,6 +234,16 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
         st[j] = S - nse;
         st[cap + j] = E + nse - nei;
         st[2 * cap + j] = I1;
+        if constexpr (SCORE) {
+            lds_add_f64(sd.sw, cap, j, flow_score<real>(S, p_se, nse) * ((double)I / sd.n_pop));
+            lds_add_f64(sd.sw + 2 * cap, cap, j, flow_score<real>(E, mc.p_ei, nei));
+            lds_add_f64(sd.sw + 4 * cap, cap, j, flow_score<real>(I, mc.p_ir, nir));
+            // d/dr log NB(y; mu, r) = psi(y + r) - psi(r) - log1p(mu / r) + (mu - y) / (r + mu)
+            if (sd.nr && nei > 0) {
+                const double mu = (double)nei, r = mc.r;
+                lds_add_f64(sd.sw + 8 * cap, cap, j, (sd.dpsi - log1p(mu / r)) + (mu - (double)yt[0]) / (r + mu));
+            }
+        }
         return obs_part<OBS>(yt[0], OBS == OBS_POIS_PREV ? I1 : nei, mc.r);
     } else {
         // forces of infection from the previous day's infected counts
@@ -556,11 +625,17 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
 {
     constexpr int NC = ModelShape<MODEL>::NC;
     constexpr int NG = ModelShape<MODEL>::NG;
+    constexpr bool SCORE = SCHED == PF_SCHED_SCORE;
+    constexpr int NS = SCORE ? ScoreDims<MODEL>::NS : 0;  // score columns (FP64, two words each)
     const int g = a.items ? a.items[item] : item;
     const int tid = (int)threadIdx.x;
     const int nthr = (int)blockDim.x;
     if (a.active && !a.active[g]) {
-        if (first_wave()) a.ll[g] = -INFINITY;
+        if (first_wave()) {
+            a.ll[g] = -INFINITY;
+            if constexpr (SCORE)
+                for (int d = lane_id(); d < a.D; d += 64) a.score[(size_t)g * a.D + d] = 0.0;
+        }
         return;
     }
     const int run_i = g / a.N;
@@ -578,8 +653,12 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
     int32_t* flows = reinterpret_cast<int32_t*>(C);
     RedLds* red = reinterpret_cast<RedLds*>(anc + cap);
     double* cst = reinterpret_cast<double*>(red + 1);
-    real* lw = reinterpret_cast<real*>(cst + T);
+    // score launches of SEIR: each day's psi(y_t + r) - psi(r) after the day constants
+    constexpr bool DPSI = SCORE && MODEL == MODEL_SEIR;
+    double* dps = cst + T;
+    real* lw = reinterpret_cast<real*>(cst + (DPSI ? 2 * T : T));
     int32_t* st = reinterpret_cast<int32_t*>(lw + cap);
+    int32_t* sw = st + NC * cap;  // score words (NS columns of two words)
     // offset from the LDS base (not an integer round trip, which would lose the address
     // space and turn every queue access into a generic FLAT access)
     const size_t pool_off = ((size_t)(reinterpret_cast<unsigned char*>(st + NC * cap) - smem) + 15) & ~(size_t)15;
@@ -598,6 +677,8 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
             for (int gi = 0; gi < NG; ++gi) c = c + obs_const(OBS, y[t * NG + gi], mc.r);
         }
         cst[t] = c;
+        if constexpr (DPSI)
+            dps[t] = a.D >= 5 ? digamma_f64((double)y[t] + mc.r) - digamma_f64(mc.r) : 0.0;
     }
     for (int j = tid; j < nx; j += nthr) {
         if constexpr (MODEL == MODEL_LG) {
@@ -608,12 +689,15 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
 #pragma unroll
             for (int c = 0; c < NC; ++c) st[c * cap + j] = mc.x0[c];
         }
+#pragma unroll
+        for (int c = 0; c < 2 * NS; ++c) sw[c * cap + j] = 0;
         lw[j] = (real)0;
     }
     if (tid == 0) wg_next = 0;
     __syncthreads();
 
     double ll = 0.0;
+    double sl_last = 0.0;  // the last day's FP64 weight sum (the score's normaliser)
     int days = T;  // days run: T, or the day every weight vanished
     const double log_nx = log((double)nx);
     double log_prev = log_nx;  // log of the previous day's weight sum (N_x after a resampling)
@@ -634,9 +718,11 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
                 amax = av > amax ? av : amax;
             }
         } else {
+            ScoreDay sd{};
+            if constexpr (SCORE) sd = ScoreDay{sw, a.n_pop, DPSI ? dps[t - 1] : 0.0, MODEL == MODEL_SEIR && a.D >= 5};
             for (int j = tid; j < nx; j += nthr) {
-                const double lg = particle_day<real, MODEL, OBS>(
-                    mc, st, cap, j, DrawStream{(uint32_t)j, filt, kt, 0u, run.k0, run.k1}, yt);
+                const double lg = particle_day<real, MODEL, OBS, SCORE>(
+                    mc, st, cap, j, DrawStream{(uint32_t)j, filt, kt, 0u, run.k0, run.k1}, yt, sd);
                 const real av = lw[j] + (real)lg;
                 lw[j] = av;
                 amax = av > amax ? av : amax;
@@ -674,7 +760,9 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
                 // w <= 1 (av <= m): q = floor(w 2^32) is 2^32 at w = 1 and fits 32 bits
                 // otherwise, where the truncating conversion is the floor; h < 2^25
                 const uint64_t q = w >= 1.0 ? (1ull << 32) : (uint64_t)(uint32_t)(w * 4294967296.0);
-                C[j] = q;
+                // the last day never resamples: score launches keep its FP64 weights instead
+                if (SCORE && t == T) reinterpret_cast<double*>(C)[j] = w;
+                else C[j] = q;
                 const uint32_t h = (uint32_t)(q >> 8);
                 q1 += h;
                 q2 += (uint64_t)h * h;
@@ -687,6 +775,7 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
         block_sum3(sl, q1, q2, red);
         sl = 0.0;
         for (int c = 0; c < (cap >> 6); ++c) sl += red->chunk[c];
+        sl_last = sl;
         const double lsl = log(sl);
         const double inc = (((double)m + lsl) - log_prev) + cst[t - 1];
         ll = ll + inc;
@@ -709,7 +798,7 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
             if (a.trace_anc)
                 for (int j = tid; j < nx; j += nthr) a.trace_anc[((size_t)g * T + (t - 1)) * nx + j] = anc[j];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
+            for (int c = 0; c < NC + 2 * NS; ++c) {  // counts, then the score words
                 int32_t* sc = st + c * cap;
                 for (int j = tid; j < nx; j += nthr) tmp[j] = sc[anc[j]];
                 __syncthreads();
@@ -722,6 +811,27 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
             __syncthreads();
         } else if (a.trace_anc) {
             for (int j = tid; j < nx; j += nthr) a.trace_anc[((size_t)g * T + (t - 1)) * nx + j] = j;
+        }
+    }
+    if constexpr (SCORE) {
+        // the estimate sum_j w_j s_j / sum_j w_j with the last day's FP64 weights (kept in C),
+        // summed per 64-particle chunk and the chunks in order, like the weight sum
+        const double* wT = reinterpret_cast<const double*>(C);
+        const int nwv = nthr >> 6;
+        const bool alive = uniform_bool(ll != -INFINITY);
+        for (int d = 0; d < a.D; ++d) {
+            double num = 0.0;
+            if (alive && d < NS) {
+                for (int j = tid, step = 0; j < cap; j += nthr, ++step) {
+                    const double v = j < nx ? wT[j] * lds_f64(sw + 2 * d * cap, cap, j) : 0.0;
+                    const double cs = wave_sum(v);
+                    if (lane_id() == 0) red->chunk[step * nwv + wave_id()] = cs;
+                }
+                __syncthreads();
+                for (int c = 0; c < (cap >> 6); ++c) num += red->chunk[c];
+                __syncthreads();  // the chunk slots are reused by the next coordinate
+            }
+            if (tid == 0) a.score[(size_t)g * a.D + d] = alive ? num / sl_last : 0.0;
         }
     }
     if (first_wave()) a.ll[g] = ll;
@@ -763,12 +873,25 @@ __global__ void __launch_bounds__(1024) k_pf(PFArgs a)
 
 // ---------------------------------------------------------------- host side
 
+int pf_score_dims(int model)
+{
+    if (model == MODEL_SIR) return ScoreDims<MODEL_SIR>::NS;
+    if (model == MODEL_SEIR) return ScoreDims<MODEL_SEIR>::NS;
+    if (model == MODEL_LG) return ScoreDims<MODEL_LG>::NS;
+    return 0;
+}
+
 size_t pf_lds_bytes(int model, int prec, int block, int nx, int T, int sched)
 {
-    const int nc = model == MODEL_SIR ? 2 : (model == MODEL_SEIR ? 3 : (model == MODEL_LG ? 2 : 12));
+    int nc = model == MODEL_SIR ? 2 : (model == MODEL_SEIR ? 3 : (model == MODEL_LG ? 2 : 12));
     const size_t cap = (size_t)((nx + block - 1) / block) * block;
     const size_t rb = prec == 0 ? 4 : 8;
-    size_t bytes = cap * 8 + 2 * cap * 4 + sizeof(RedLds) + (size_t)T * 8 + cap * rb + (size_t)nc * cap * 4;
+    size_t days = (size_t)T;
+    if (sched == PF_SCHED_SCORE) {
+        nc += 2 * pf_score_dims(model);            // the score words
+        if (model == MODEL_SEIR) days += (size_t)T;  // psi(y_t + r) - psi(r) per day
+    }
+    size_t bytes = cap * 8 + 2 * cap * 4 + sizeof(RedLds) + days * 8 + cap * rb + (size_t)nc * cap * 4;
     if (sched == PF_SCHED_POOLED) {
         const size_t pool = prec == 0 ? sizeof(WavePool<float>) : sizeof(WavePool<double>);
         bytes = ((bytes + 15) & ~(size_t)15) + (size_t)(block / 64) * pool;
@@ -805,6 +928,7 @@ int pf_pick_schedule(int model, int prec, int block, int nx, int T, int requeste
 {
     const bool pooled_ok = (model == MODEL_SIR || model == MODEL_SEIR) &&
                            pf_lds_bytes(model, prec, block, nx, T, PF_SCHED_POOLED) <= PF_LDS_MAX;
+    if (requested == PF_SCHED_SCORE) return pf_score_dims(model) > 0 ? PF_SCHED_SCORE : -1;
     if (requested == PF_SCHED_PER_DRAW) return PF_SCHED_PER_DRAW;
     if (requested == PF_SCHED_POOLED) return pooled_ok ? PF_SCHED_POOLED : -1;
     return pooled_ok ? PF_SCHED_POOLED : PF_SCHED_PER_DRAW;
@@ -834,9 +958,9 @@ static hipError_t launch_model(int model, int obs, int block, size_t lds, const 
         return launch_one<real, MODEL_SEIR, OBS_NB_INC, SCHED>(block, lds, a, s, grid);
     if (model == MODEL_AGE && obs == OBS_NB_INC && SCHED == PF_SCHED_PER_DRAW)
         return launch_one<real, MODEL_AGE, OBS_NB_INC, PF_SCHED_PER_DRAW>(block, lds, a, s, grid);
-    if constexpr (std::is_same<real, double>::value && SCHED == PF_SCHED_PER_DRAW)
+    if constexpr (std::is_same<real, double>::value && (SCHED == PF_SCHED_PER_DRAW || SCHED == PF_SCHED_SCORE))
         if (model == MODEL_LG && obs == OBS_GAUSS)
-            return launch_one<double, MODEL_LG, OBS_GAUSS, PF_SCHED_PER_DRAW>(block, lds, a, s, grid);
+            return launch_one<double, MODEL_LG, OBS_GAUSS, SCHED>(block, lds, a, s, grid);
     return hipErrorInvalidValue;
 }
 
@@ -847,8 +971,8 @@ template <typename real, int SCHED> static const void* kernel_of(int model, int 
     if (model == MODEL_SEIR && obs == OBS_NB_INC) return kernel_ptr<real, MODEL_SEIR, OBS_NB_INC, SCHED>();
     if (model == MODEL_AGE && obs == OBS_NB_INC && SCHED == PF_SCHED_PER_DRAW)
         return kernel_ptr<real, MODEL_AGE, OBS_NB_INC, PF_SCHED_PER_DRAW>();
-    if constexpr (std::is_same<real, double>::value && SCHED == PF_SCHED_PER_DRAW)
-        if (model == MODEL_LG && obs == OBS_GAUSS) return kernel_ptr<double, MODEL_LG, OBS_GAUSS, PF_SCHED_PER_DRAW>();
+    if constexpr (std::is_same<real, double>::value && (SCHED == PF_SCHED_PER_DRAW || SCHED == PF_SCHED_SCORE))
+        if (model == MODEL_LG && obs == OBS_GAUSS) return kernel_ptr<double, MODEL_LG, OBS_GAUSS, SCHED>();
     return nullptr;
 }
 
@@ -863,6 +987,8 @@ static const void* kernel_for(int prec, int model, int obs, int sched)
 {
     if (sched == PF_SCHED_POOLED)
         return prec == 0 ? kernel_of<float, PF_SCHED_POOLED>(model, obs) : kernel_of<double, PF_SCHED_POOLED>(model, obs);
+    if (sched == PF_SCHED_SCORE)
+        return prec == 0 ? kernel_of<float, PF_SCHED_SCORE>(model, obs) : kernel_of<double, PF_SCHED_SCORE>(model, obs);
     return prec == 0 ? kernel_of<float, PF_SCHED_PER_DRAW>(model, obs) : kernel_of<double, PF_SCHED_PER_DRAW>(model, obs);
 }
 
@@ -894,6 +1020,11 @@ hipError_t launch_pf(int prec, int model, int obs, int sched, int block, size_t 
     if (sched == PF_SCHED_POOLED) {
         if (prec == 0) return launch_model<float, PF_SCHED_POOLED>(model, obs, block, lds, a, s, grid);
         return launch_model<double, PF_SCHED_POOLED>(model, obs, block, lds, a, s, grid);
+    }
+    if (sched == PF_SCHED_SCORE) {
+        if (!a.score) return hipErrorInvalidValue;
+        if (prec == 0) return launch_model<float, PF_SCHED_SCORE>(model, obs, block, lds, a, s, grid);
+        return launch_model<double, PF_SCHED_SCORE>(model, obs, block, lds, a, s, grid);
     }
     if (prec == 0) return launch_model<float, PF_SCHED_PER_DRAW>(model, obs, block, lds, a, s, grid);
     return launch_model<double, PF_SCHED_PER_DRAW>(model, obs, block, lds, a, s, grid);

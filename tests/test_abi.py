@@ -187,3 +187,23 @@ def test_linear_gaussian_model_validation():
     ws = L.smc2_pf_workspace_bytes(ctypes.byref(cfg), runs)
     assert ws >= 256 + 8 * w["T"]
     assert L.smc2_pf_loglik(ctypes.byref(c32), 4, fake, runs, 1, fake, fake, ws, None) == G.E_UNSUPPORTED
+
+
+def test_score_entry_point_rejects_before_device_use():
+    L = G.lib()
+    fake = ctypes.c_void_p(1 << 20)
+    wa = W.preset("age_seir")
+    ra = G.make_runs([dict(T=10, nx=256, seed=1, y=W.observations(dict(wa, T=10)))])
+    ca = G.make_config(wa)
+    ws = L.smc2_pf_workspace_bytes(ctypes.byref(ca), ra)
+    assert L.smc2_pf_score(ctypes.byref(ca), 4, fake, ra, 1, fake, fake, fake, ws, None) == G.E_UNSUPPORTED
+    w = _w()
+    runs = G.make_runs([dict(T=100, nx=512, seed=1, y=W.observations(w))])
+    c = G.make_config(w)
+    ws = L.smc2_pf_workspace_bytes(ctypes.byref(c), runs)
+    assert L.smc2_pf_score(ctypes.byref(c), 4, fake, runs, 1, fake, None, fake, ws, None) == G.E_ARG
+    c3 = G.make_config(dict(w, D=3, prior=w["prior"][:3], rw_cov=np.eye(3).tolist()))
+    assert L.smc2_pf_score(ctypes.byref(c3), 4, fake, runs, 1, fake, fake, fake, ws, None) == G.E_ARG
+    # the score launch's LDS: SEIR at N_x = 4096 does not fit with five FP64 score columns
+    r4 = G.make_runs([dict(T=100, nx=4096, seed=1, y=W.observations(w))])
+    assert L.smc2_pf_score(ctypes.byref(c), 4, fake, r4, 1, fake, fake, fake, ws, None) == G.E_ARG
