@@ -20,7 +20,7 @@ OBS_POIS_PREV, OBS_POIS_INC, OBS_NB_INC = 0, 1, 2
 PREC_FP32, PREC_FP64 = 0, 1
 PRIOR_UNIFORM, PRIOR_LOGNORMAL, PRIOR_LOGITNORMAL, PRIOR_NORMAL = 0, 1, 2, 3
 L_FORWARD, L_GAUSS_OPT = 0, 1
-PROP_RW, PROP_MLP = 0, 1
+PROP_RW, PROP_MLP, PROP_LANGEVIN = 0, 1, 2
 RS_SYSTEMATIC, RS_MULTINOMIAL = 0, 1
 
 
@@ -72,6 +72,9 @@ def _declare(L):
     L.or_pf_lg.argtypes = [c.c_double] * 5 + [P(c.c_double), c.c_int, c.c_int, c.c_uint64, c.c_uint32, c.c_uint32,
                                               c.c_int, c.c_int, P(c.c_double), P(c.c_int32), P(c.c_double),
                                               P(c.c_double)]
+    L.or_propose_langevin_one.restype = c.c_double
+    L.or_propose_langevin_one.argtypes = [P(Config), P(c.c_double), P(c.c_double), P(c.c_double), c.c_uint64,
+                                          c.c_uint32, c.c_int, P(c.c_double)]
     L.or_digamma.restype = c.c_double
     L.or_digamma.argtypes = [c.c_double]
     L.or_resample_multinomial.argtypes = [P(c.c_uint64), c.c_int, c.c_uint64, c.c_uint32, c.c_uint32, P(c.c_int32)]
@@ -469,6 +472,19 @@ def pf_score(cfg, theta, y, nx, seed, filt, k):
     ll = lib().or_pf_score(ctypes.byref(cfg), _p(th, ctypes.c_double), _p(y, ctypes.c_int32), y.shape[0], nx,
                            int(seed), int(filt), int(k), _p(sc, ctypes.c_double))
     return ll, sc
+
+
+def propose_langevin(cfg, phi, s_theta, seed, k, i):
+    """(phi_new, log q(phi_new | phi)) of the truncated Langevin proposal of sample i."""
+    D = cfg.D
+    C = np.array([[cfg.rw_cov[a][c] for c in range(D)] for a in range(D)])
+    L = np.ascontiguousarray(np.linalg.cholesky(C))
+    phi = np.ascontiguousarray(phi, dtype=np.float64)
+    st = np.ascontiguousarray(s_theta, dtype=np.float64)
+    out = np.zeros(D)
+    lq = lib().or_propose_langevin_one(ctypes.byref(cfg), _p(L, ctypes.c_double), _p(phi, ctypes.c_double),
+                                       _p(st, ctypes.c_double), int(seed), int(k), int(i), _p(out, ctypes.c_double))
+    return out, lq
 
 
 def digamma(x):

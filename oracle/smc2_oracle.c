@@ -353,6 +353,52 @@ void or_propose_rw(const or_config* cfg, int N, uint64_t seed, uint32_t k, const
     }
 }
 
+/* Truncated Langevin proposal (a gradient-informed random walk; the drift shrunk to a
+ * bounded length as in Roberts and Tweedie's truncated form). The gradient is the
+ * particle filter's score estimate of the sample, which travelled with it like its
+ * likelihood estimate, mapped to the sampler coordinates, plus the prior's gradient; the
+ * proposal is then an exactly computable density given the sample's stored state. */
+double or_propose_langevin_one(const or_config* cfg, const double* L, const double* phi, const double* s_theta,
+                               uint64_t seed, uint32_t k, int i, double* phi_new)
+{
+    const int D = cfg->D;
+    double th[OR_DMAX], g[OR_DMAX], v[OR_DMAX], delta[OR_DMAX], z[OR_DMAX], m[OR_DMAX];
+    or_theta_of_phi(cfg, phi, th);
+    for (int d = 0; d < D; ++d) {
+        const int fam = (int)cfg->prior[d][0];
+        const double a = cfg->prior[d][1], b = cfg->prior[d][2];
+        const double J = fam == OR_PRIOR_LOGNORMAL ? th[d] : (fam == OR_PRIOR_LOGITNORMAL ? th[d] * (1.0 - th[d]) : 1.0);
+        const double gp = fam == OR_PRIOR_UNIFORM ? 0.0 : -(phi[d] - a) / (b * b);
+        g[d] = J * s_theta[d] + gp;
+    }
+    /* delta = 1/2 Sigma g = 1/2 L v with v = L' g; its Mahalanobis length |L^-1 delta| is |v| / 2 */
+    double n2 = 0.0;
+    for (int a = 0; a < D; ++a) {
+        double acc = 0.0;
+        for (int c = a; c < D; ++c) acc += L[c * D + a] * g[c];
+        v[a] = acc;
+        n2 += acc * acc;
+    }
+    const double len = 0.5 * sqrt(n2);
+    const double shrink = len > 1.0 ? 1.0 / len : 1.0;
+    for (int a = 0; a < D; ++a) {
+        double acc = 0.0;
+        for (int c = 0; c <= a; ++c) acc += L[a * D + c] * v[c];
+        delta[a] = (0.5 * acc) * shrink;
+    }
+    for (int d = 0; d < D; ++d) {
+        uint32_t ctr[4] = {(uint32_t)i, 0u, k << 16, ((uint32_t)OR_S_RW << 24) | (uint32_t)d};
+        z[d] = or_normal_call(seed, ctr);
+    }
+    for (int a = 0; a < D; ++a) {
+        m[a] = phi[a] + delta[a];
+        double acc = 0.0;
+        for (int c = 0; c <= a; ++c) acc += L[a * D + c] * z[c];
+        phi_new[a] = m[a] + acc;
+    }
+    return or_mvn_logpdf_chol(D, phi_new, m, L);
+}
+
 /* Multinomial resampling, the particle filter's scheme in Sec. II: every slot draws its
  * ancestor independently with probability q_j / Q, from its own 64-bit uniform
  * U_m = floor(x64_m Q / 2^64) and the first j with C_j > U_m (exact integers). */
@@ -992,6 +1038,17 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
     int32_t* anc = (int32_t*)calloc((size_t)N, sizeof(int32_t));
     double* lq = (double*)calloc((size_t)N, sizeof(double));
     const int mlp = cfg->proposal == OR_PROP_MLP;
+    const int lgv = cfg->proposal == OR_PROP_LANGEVIN;
+    /* Langevin: the score estimates of the population and of the proposals */
+    double* sc = lgv ? (double*)calloc((size_t)N * D, sizeof(double)) : NULL;
+    double* scn = lgv ? (double*)calloc((size_t)N * D, sizeof(double)) : NULL;
+    double Lrw[OR_DMAX * OR_DMAX];
+    if (lgv) {
+        double C[OR_DMAX * OR_DMAX];
+        for (int a = 0; a < D; ++a)
+            for (int c = 0; c < D; ++c) C[a * D + c] = cfg->rw_cov[a][c];
+        or_cholesky(D, C, Lrw);
+    }
     const int np = or_mlp_nparams(D);
     float* params = mlp ? (float*)calloc((size_t)np, sizeof(float)) : NULL;
     float* am = mlp ? (float*)calloc((size_t)np, sizeof(float)) : NULL;
@@ -1018,6 +1075,12 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
                 lq[i] = or_mlp_propose_one(D, frame, o, seed, (uint32_t)k, i, phin + (size_t)i * D);
                 lpn[i] = or_prior_logpdf(cfg, phin + (size_t)i * D);
             }
+        } else if (lgv) {
+            for (int i = 0; i < N; ++i) {
+                lq[i] = or_propose_langevin_one(cfg, Lrw, phi + (size_t)i * D, sc + (size_t)i * D, seed, (uint32_t)k, i,
+                                                phin + (size_t)i * D);
+                lpn[i] = or_prior_logpdf(cfg, phin + (size_t)i * D);
+            }
         } else {
             or_propose_rw(cfg, N, seed, (uint32_t)k, phi, phin, lpn);
         }
@@ -1027,15 +1090,24 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
             if (run) {
                 double th[OR_DMAX];
                 or_theta_of_phi(cfg, phin + (size_t)i * D, th);
-                lln[i] = or_pf_loglik(cfg, th, y, T, nx, seed, (uint32_t)i, (uint32_t)k, NULL, NULL);
+                if (lgv)
+                    lln[i] = or_pf_score(cfg, th, y, T, nx, seed, (uint32_t)i, (uint32_t)k, scn + (size_t)i * D);
+                else
+                    lln[i] = or_pf_loglik(cfg, th, y, T, nx, seed, (uint32_t)i, (uint32_t)k, NULL, NULL);
             } else {
                 lln[i] = -INFINITY;
+                if (lgv)
+                    for (int d = 0; d < D; ++d) scn[(size_t)i * D + d] = 0.0;
             }
         }
         double* rk = rec + (size_t)(k - 1) * RL;
+        const int drift = lgv && k > 1;
         int st = or_outer_update(cfg, N, (uint32_t)k, seed, phi, lp, ll, logw, phin, lpn, lln,
-                                 learned ? lq : NULL, lwp, anc, rk);
-        rk[RL - 2] = learned ? 1.0 : 0.0;
+                                 (learned || drift) ? lq : NULL, lwp, anc, rk);
+        rk[RL - 2] = learned ? 1.0 : (drift ? 2.0 : 0.0);
+        if (lgv && st == 0) /* the scores travel with their samples through resampling */
+            for (int i = 0; i < N; ++i)
+                for (int d = 0; d < D; ++d) sc[(size_t)i * D + d] = scn[(size_t)anc[i] * D + d];
         if (mlp && st == 0) {
             double nm, nr;
             use_mlp = or_mlp_train(cfg, N, phi, logw, seed, (uint32_t)k, cfg->mlp_epochs, cfg->mlp_batch, cfg->mlp_lr,
@@ -1053,6 +1125,6 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
         }
     }
     free(phi); free(lp); free(ll); free(logw); free(phin); free(lpn); free(lln); free(lwp); free(anc);
-    free(lq); free(params); free(am); free(av);
+    free(lq); free(params); free(am); free(av); free(sc); free(scn);
     return status;
 }

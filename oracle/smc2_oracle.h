@@ -31,7 +31,7 @@ enum { OR_OBS_POIS_PREV = 0, OR_OBS_POIS_INC = 1, OR_OBS_NB_INC = 2 };
 enum { OR_PREC_FP32 = 0, OR_PREC_FP64 = 1 };
 enum { OR_PRIOR_UNIFORM = 0, OR_PRIOR_LOGNORMAL = 1, OR_PRIOR_LOGITNORMAL = 2, OR_PRIOR_NORMAL = 3 };
 enum { OR_L_FORWARD = 0, OR_L_GAUSS_OPT = 1 };
-enum { OR_PROP_RW = 0, OR_PROP_MLP = 1 };
+enum { OR_PROP_RW = 0, OR_PROP_MLP = 1, OR_PROP_LANGEVIN = 2 };
 
 /* Philox stream identifiers (bits 24..31 of the fourth counter word). */
 enum { OR_S_PF_PROP = 1, OR_S_PF_RS = 2, OR_S_PRIOR = 3, OR_S_RW = 4, OR_S_OUTER_RS = 5,
@@ -53,7 +53,7 @@ typedef struct {
     int32_t model, obs, D, prec;
     int32_t pf_always;  /* 1: resample the particle filter at every step; 0: when ESS < Nx/2 */
     int32_t lkernel;    /* OR_L_FORWARD or OR_L_GAUSS_OPT */
-    int32_t proposal;   /* OR_PROP_RW or OR_PROP_MLP */
+    int32_t proposal;   /* OR_PROP_RW, OR_PROP_MLP or OR_PROP_LANGEVIN */
     int32_t n_fixed;
     double n_pop;
     double prior[OR_DMAX][3];      /* {family, a, b} per sampler coordinate */
@@ -186,6 +186,15 @@ double or_pf_score(const or_config* cfg, const double* theta, const int32_t* y, 
                    uint32_t filt, uint32_t k, double* score_out);
 /* Digamma function psi(x), x > 0. */
 double or_digamma(double x);
+
+/* The truncated Langevin proposal of sample phi given the score estimate s_theta (on the
+ * natural parameters) that travelled with it: the drift delta = 1/2 Sigma g with
+ * g = J s_theta + grad log prior(phi) (J = d theta / d phi per coordinate), shrunk to a
+ * Mahalanobis length of at most 1 (|L^-1 delta| <= 1, L L' = Sigma), and
+ * phi_new = phi + delta + L z with z the random walk's normals of sample i at iteration k.
+ * Returns log q(phi_new | phi) = log N(phi_new; phi + delta, Sigma). */
+double or_propose_langevin_one(const or_config* cfg, const double* L, const double* phi, const double* s_theta,
+                               uint64_t seed, uint32_t k, int i, double* phi_new);
 /* Multinomial ancestors from quantised weights: slot m draws U_m = floor(x64_m Q / 2^64)
  * (x64_m: 64-bit word m&1 of the Philox call (m>>1, filt, kt, 2<<24 | 1<<16)) and takes
  * the first j whose inclusive scan C_j exceeds U_m. */

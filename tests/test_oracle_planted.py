@@ -54,6 +54,15 @@ SCORE_PLANTS = {
 }
 
 
+LANGEVIN_PLANTS = {
+    # the drifted proposal weighted as if it were the symmetric random walk
+    "langevin_density_dropped": [("smc2_oracle.c", "(learned || drift) ? lq : NULL", "learned ? lq : NULL")],
+    # log q evaluated around phi instead of the drifted mean phi + delta
+    "langevin_density_undrifted": [("smc2_oracle.c", "    return or_mvn_logpdf_chol(D, phi_new, m, L);",
+                                    "    return or_mvn_logpdf_chol(D, phi_new, phi, L);")],
+}
+
+
 PMCMC_PLANTS = {
     "prior_dropped_from_the_ratio": [("smc2_oracle.c", "    const double cur = lp + ll, nw = lp_new + ll_new;",
                                       "    const double cur = ll, nw = ll_new;")],
@@ -68,7 +77,7 @@ PMCMC_PLANTS = {
 @pytest.fixture(scope="module")
 def planted_libs(tmp_path_factory):
     d = str(tmp_path_factory.mktemp("planted"))
-    plants = dict(AGE_PLANTS, **KALMAN_PLANTS, **PMCMC_PLANTS, **SCORE_PLANTS)
+    plants = dict(AGE_PLANTS, **KALMAN_PLANTS, **PMCMC_PLANTS, **SCORE_PLANTS, **LANGEVIN_PLANTS)
     with cf.ThreadPoolExecutor(max_workers=4) as ex:
         futs = {name: ex.submit(PL.build_planted, name, edits, d) for name, edits in plants.items()}
         return {name: f.result() for name, f in futs.items()}
@@ -105,6 +114,17 @@ def test_score_pins_catch_a_broken_score(planted_libs, name):
         ok_lg = _close(*lg_score_statistic(M=100))[0]
     print(name, ok_sir, ok_lg)
     assert not (ok_sir and ok_lg), name
+
+
+@pytest.mark.parametrize("name", sorted(LANGEVIN_PLANTS))
+def test_langevin_pin_catches_an_inexact_weight(planted_libs, name):
+    from tests.test_oracle_langevin import langevin_grid_statistic
+    with PL.installed(planted_libs[name]):
+        ests, second, grid_mean, grid_sd, _ = langevin_grid_statistic()
+    se = ests.std(0, ddof=1) / np.sqrt(len(ests))
+    pooled_sd = np.sqrt(second.mean(0) - ests.mean(0) ** 2)
+    print(name, ests.mean(0), grid_mean, se, pooled_sd / grid_sd)
+    assert np.any(np.abs(ests.mean(0) - grid_mean) > 4 * se + 2e-3) or np.any(np.abs(pooled_sd / grid_sd - 1) > 0.2)
 
 
 @pytest.mark.parametrize("name", sorted(PMCMC_PLANTS))
