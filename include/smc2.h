@@ -95,6 +95,12 @@ extern "C" {
 #define SMC2_L_GAUSS_OPT 1 /* approximately optimal Gaussian L-kernel (Sec. IV-D)       */
 
 #define SMC2_PROP_RW 0  /* Gaussian random walk on phi (Eq. proposal) */
+#define SMC2_PROP_LANGEVIN 2 /* truncated Langevin proposal (SIR, SEIR, SMC2_LINGAUSS):
+                                phi' = phi + delta + L z, delta = 1/2 Sigma_RW g shrunk to
+                                Mahalanobis length <= 1, g the gradient of log(prior x
+                                likelihood) on the sampler coordinates from the filter's
+                                score estimate (smc2_pf_score's), which travels with its
+                                sample; its exact log q enters the weights (Eq. l_weights) */
 #define SMC2_PROP_MLP 1 /* learned Gaussian proposal: a D -> 64 -> 64 -> (mean, Cholesky)
                            network, BF16 matrix-core products, trained after every
                            iteration on the weighted population; its exact density
@@ -179,7 +185,8 @@ typedef struct {
  *   [6 .. 6+D)            posterior mean of theta at iteration k (Eq. realised_estimates)
  *   [6+D .. 6+D+D*D)      weighted covariance of theta
  *   [6+D+D*D .. 6+2D+D*D) weighted mean of the sampler coordinates phi
- *   [6+2D+D*D]            proposal used at iteration k (0 random walk, 1 learned)
+ *   [6+2D+D*D]            proposal used at iteration k (0 random walk, 1 learned,
+ *                         2 Langevin)
  *   [7+2D+D*D]            learned proposal trained after iteration k: held-out mean
  *                         weighted NLL minus the random walk's (0 without training)    */
 #define SMC2_RECORD_LEN(D) (8 + 2 * (D) + (D) * (D))
@@ -200,6 +207,9 @@ typedef struct {
                                 with zero weight or outside the prior's support, run none) */
 #define SMC2_DUMP_THETA_NEW 17 /* N x D doubles: model parameters theta(phi_new) of the samples
                                   proposed in the last step (what their filters ran with)  */
+#define SMC2_DUMP_SCORE 18     /* N x D doubles: the population's score estimates (natural
+                                  parameters; SMC2_PROP_LANGEVIN only)                     */
+#define SMC2_DUMP_SCORE_NEW 19 /* N x D doubles: the last step's proposals' score estimates */
 #define SMC2_DUMP_LKFIT 16   /* 2D + 4D^2 doubles: moments of the last approximately optimal
                                 L-kernel fit (Sec. IV-D), the weighted mean of the pairs
                                 (phi_{k-1}, phi_k) then their weighted covariance (row-major,
@@ -209,7 +219,8 @@ typedef struct {
                                    last step proposed from (P = D + D(D+1)/2)            */
 #define SMC2_DUMP_LOGQ 10       /* N      doubles: log q(phi_new | phi) of the learned
                                    proposal at the last step; 0 where that step drew from
-                                   the prior (k = 1) or the random walk                   */
+                                   the prior (k = 1) or the random walk (also for the
+                                   Langevin proposal: its log q at the last step)          */
 #define SMC2_DUMP_MLP_PARAMS 11 /* NP     float: FP32 master weights W1[64][D] b1[64]
                                    W2[64][64] b2[64] W3[P][64] b3[P] (after training)    */
 #define SMC2_DUMP_MLP_FRAME 12  /* D+D*D  doubles: input frame of the current network: the

@@ -20,12 +20,13 @@ OBS_POIS_PREV, OBS_POIS_INC, OBS_NB_INC, OBS_GAUSS = 0, 1, 2, 3
 PREC_FP32, PREC_FP64 = 0, 1
 PRIOR_UNIFORM, PRIOR_LOGNORMAL, PRIOR_LOGITNORMAL, PRIOR_NORMAL = 0, 1, 2, 3
 L_FORWARD, L_GAUSS_OPT = 0, 1
-PROP_RW, PROP_MLP = 0, 1
+PROP_RW, PROP_MLP, PROP_LANGEVIN = 0, 1, 2
 PF_RS_SYSTEMATIC, PF_RS_MULTINOMIAL = 0, 1
 MLP_TRAIN_AUTO, MLP_TRAIN_PER_RUN, MLP_TRAIN_SPLIT = 0, 1, 2
 SCHED_AUTO, SCHED_PER_DRAW, SCHED_POOLED = 0, 1, 2
 DUMP = dict(phi=0, lp=1, ll=2, logw=3, phi_new=4, lp_new=5, ll_new=6, logw_pre=7, anc=8, mlp_out=9, logq=10,
-            mlp_params=11, mlp_frame=12, mlp_state=13, mlp_grad=14, psteps=15, lkfit=16, theta_new=17)
+            mlp_params=11, mlp_frame=12, mlp_state=13, mlp_grad=14, psteps=15, lkfit=16, theta_new=17, score=18,
+            score_new=19)
 MLP_H = 64
 PMCMC_PHI, PMCMC_LL, PMCMC_LL_PROPOSED, PMCMC_ACCEPTED = 0, 1, 2, 3
 
@@ -301,7 +302,7 @@ class Sampler:
 
     def dump(self, what, run=0):
         code = DUMP[what]
-        if what in ("phi", "phi_new", "theta_new"):
+        if what in ("phi", "phi_new", "theta_new", "score", "score_new"):
             out = np.zeros((self.N, self.D))
         elif what == "anc":
             out = np.zeros(self.N, dtype=np.int32)

@@ -36,7 +36,10 @@ struct OuterArrays {
     const int32_t* mlp_use;   // [R]        1: this iteration proposes with the network
     const float* mlp_out;     // [R][N][P]  network outputs at the current population
     const double* mlp_frame;  // [R][D+D*D] input frame of the network: mean c, Cholesky factor F
-    double* logq;             // [R][N]     log q(phi_new | phi) of the learned proposal
+    double* logq;             // [R][N]     log q(phi_new | phi) of the learned or Langevin proposal
+    // Langevin proposal (NULL unless configured): score estimates on the natural parameters
+    double* score;            // [R][N][D]  of the population (they travel with their samples)
+    double* score_new;        // [R][N][D]  of the proposals (the filters' output)
 };
 
 struct OuterParams {
@@ -46,6 +49,7 @@ struct OuterParams {
     const double* prior; // [D][3] {family, a, b} (device)
     const double* lrw;   // [D][D] lower Cholesky factor of the RW covariance (device)
     int32_t mlp;         // 1: the learned proposal is configured
+    int32_t langevin;    // 1: the truncated Langevin proposal is configured
 };
 
 // model parameter theta_d from the sampler coordinate phi_d of a prior family

@@ -32,6 +32,8 @@ __global__ void k_begin(int32_t* k_dev, int32_t* queues, int n_queues)
     for (int i = (int)threadIdx.x; i < n_queues; i += (int)blockDim.x) queues[i] = 0;
 }
 
+template <int D> __device__ __forceinline__ double mvn_logpdf(const double* x, const double* mu, const double* L);
+
 template <int D>
 __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, const uint64_t* seeds)
 {
@@ -91,6 +93,45 @@ __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, c
                 phin[a] = sa;
             }
             o.logq[g] = lq;
+        } else if (p.langevin) {
+            // truncated Langevin proposal: drift delta = 1/2 Sigma_RW g with g the gradient of
+            // log(prior x likelihood) on the sampler coordinates, from the score estimate that
+            // travelled with the sample; shrunk to Mahalanobis length 1; phi' = phi + delta + L z
+            const double* ph = o.phi + (size_t)g * D;
+            const double* sth = o.score + (size_t)g * D;
+            double gr[D], v[D], m[D];
+#pragma unroll
+            for (int d = 0; d < D; ++d) {
+                const int fam = (int)p.prior[3 * d];
+                const double a = p.prior[3 * d + 1], b = p.prior[3 * d + 2];
+                const double th = theta_of(fam, ph[d]);
+                const double J = fam == PRIOR_LOGNORMAL ? th : (fam == PRIOR_LOGITNORMAL ? th * (1.0 - th) : 1.0);
+                const double gp = fam == PRIOR_UNIFORM ? 0.0 : -(ph[d] - a) / (b * b);
+                gr[d] = J * sth[d] + gp;
+            }
+            double n2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                double acc = 0.0;
+#pragma unroll
+                for (int c = a; c < D; ++c) acc += p.lrw[c * D + a] * gr[c];
+                v[a] = acc;
+                n2 += acc * acc;
+            }
+            const double len = 0.5 * sqrt(n2);
+            const double shrink = len > 1.0 ? 1.0 / len : 1.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                double acc = 0.0;
+#pragma unroll
+                for (int c = 0; c <= a; ++c) acc += p.lrw[a * D + c] * v[c];
+                m[a] = ph[a] + (0.5 * acc) * shrink;
+                double lz = 0.0;
+#pragma unroll
+                for (int c = 0; c <= a; ++c) lz += p.lrw[a * D + c] * z[c];
+                phin[a] = m[a] + lz;
+            }
+            o.logq[g] = mvn_logpdf<D>(phin, m, p.lrw);
         } else {
             const double* ph = o.phi + (size_t)g * D;
 #pragma unroll
@@ -279,8 +320,10 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
     if (tid == 0 && o.psteps_at) o.psteps_at[(size_t)r * p.K + (k - 1)] = o.psteps[r];
     __syncthreads();
 
-    // proposal of this iteration: the learned one (then its density is in o.logq)
+    // proposal of this iteration: the learned one or the Langevin one (then its density is
+    // in o.logq)
     const bool learned = p.mlp && k >= 2 && uniform_bool(o.mlp_use[r] != 0);
+    const bool drift = p.langevin && k >= 2;
 
     // ---------------- approximately optimal L-kernel (k > 1)
     // Without a usable fit (forward-kernel setting, or the fit rejected) the backward
@@ -392,7 +435,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
                 } else {
                     lL = mvn_logpdf<D>(xo, xn, Lq);
                 }
-                const double lq = learned ? o.logq[base + i] : mvn_logpdf<D>(xn, xo, Lq);
+                const double lq = (learned || drift) ? o.logq[base + i] : mvn_logpdf<D>(xn, xo, Lq);
                 v = v + (lL - lq);
             }
         }
@@ -476,7 +519,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
         rec[3] = (double)dead;
         rec[4] = (double)fallback;
         rec[5] = W;
-        rec[p.rec_len - 2] = learned ? 1.0 : 0.0;
+        rec[p.rec_len - 2] = learned ? 1.0 : (drift ? 2.0 : 0.0);
         for (int a2 = 0; a2 < D; ++a2) {
             rec[6 + a2] = mth[a2];
             rec[6 + D + D * D + a2] = mph[a2];
@@ -502,6 +545,9 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
         lp[m] = lpn[s];
         ll[m] = lln[s];
         logw[m] = rs ? 0.0 : lwp[m];
+        if (p.langevin)  // the score estimates travel with their samples
+#pragma unroll
+            for (int d = 0; d < D; ++d) o.score[((size_t)base + m) * D + d] = o.score_new[((size_t)base + s) * D + d];
     }
 }
 

@@ -65,7 +65,7 @@ struct Layout {
         off_ll, off_logw, off_lpn, off_lln, off_lwp, off_scr, off_qc, off_anc, off_active, off_rec, off_items,
         off_queues, off_tune_items, off_mlp_params, off_mlp_m, off_mlp_v, off_mlp_grad, off_mlp_t, off_mlp_frame,
         off_mlp_use, off_mlp_done, off_mlp_out, off_mlp_logq, off_mlp_score, off_mlp_rows, off_mlp_wfull, off_mlp_gpart,
-        off_psteps, off_lkfit, off_psteps_at;
+        off_psteps, off_lkfit, off_psteps_at, off_score, off_score_new;
     size_t take(size_t bytes)
     {
         const size_t o = total;
@@ -119,7 +119,10 @@ Layout make_layout(const smc2_config* c, int R, const smc2_run* runs)
     L.off_mlp_use = L.take(sizeof(int32_t) * Rm);
     L.off_mlp_done = L.take(sizeof(int32_t) * Rm);
     L.off_mlp_out = L.take(sizeof(float) * Rm * N * P);
-    L.off_mlp_logq = L.take(sizeof(double) * Rm * N);
+    const bool lgv = c->proposal == SMC2_PROP_LANGEVIN;
+    L.off_mlp_logq = L.take(sizeof(double) * (mlp || lgv ? (size_t)R : 0) * N);
+    L.off_score = L.take(sizeof(double) * (lgv ? RN * D : 0));
+    L.off_score_new = L.take(sizeof(double) * (lgv ? RN * D : 0));
     L.off_mlp_score = L.take(sizeof(double) * Rm * 2);
     L.off_mlp_rows = L.take(sizeof(float) * Rm * N * MLP_ROW);
     L.off_mlp_wfull = L.take(sizeof(double) * Rm * N);
@@ -208,7 +211,10 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
     const bool lg = c->model == SMC2_LINGAUSS;
     if (lg && c->precision != SMC2_PREC_FP64)
         return m = "the linear-Gaussian model runs in FP64 only", SMC2_E_UNSUPPORTED;
-    if (c->proposal != SMC2_PROP_RW && c->proposal != SMC2_PROP_MLP) return m = "unknown proposal", SMC2_E_UNSUPPORTED;
+    if (c->proposal != SMC2_PROP_RW && c->proposal != SMC2_PROP_MLP && c->proposal != SMC2_PROP_LANGEVIN)
+        return m = "unknown proposal", SMC2_E_UNSUPPORTED;
+    if (c->proposal == SMC2_PROP_LANGEVIN && pf_score_dims(c->model) == 0)
+        return m = "the Langevin proposal needs the filter's score (SIR, SEIR, linear-Gaussian)", SMC2_E_UNSUPPORTED;
     if (c->proposal == SMC2_PROP_MLP) {
         if (c->mlp_epochs < 0 || c->mlp_epochs > 1000) return m = "mlp_epochs must be in [0, 1000]", SMC2_E_ARG;
         if (c->mlp_batch < 0) return m = "mlp_batch must be >= 0", SMC2_E_ARG;
@@ -319,8 +325,10 @@ static hipError_t autotune(smc2_ctx* c)
         const int full = ((gr.max_nx + 63) / 64) * 64;
         for (int b = 64; b <= 1024 && e == hipSuccess; b *= 2) {
             if (b > std::max(64, full)) break;
-            for (int sc = PF_SCHED_PER_DRAW; sc <= PF_SCHED_POOLED && e == hipSuccess; ++sc) {
-                if (cfg.schedule != SMC2_SCHED_AUTO && sc != cfg.schedule) continue;
+            for (int sc = PF_SCHED_PER_DRAW; sc <= PF_SCHED_SCORE && e == hipSuccess; ++sc) {
+                // the Langevin proposal's launches carry the scores: only that variant
+                if ((cfg.proposal == SMC2_PROP_LANGEVIN) != (sc == PF_SCHED_SCORE)) continue;
+                if (sc != PF_SCHED_SCORE && cfg.schedule != SMC2_SCHED_AUTO && sc != cfg.schedule) continue;
                 if (sc == PF_SCHED_POOLED && cfg.model != SMC2_SIR && cfg.model != SMC2_SEIR) continue;
                 const size_t lds = pf_lds_bytes(cfg.model, cfg.precision, b, gr.max_nx, gr.max_T, sc);
                 if (lds > PF_LDS_MAX) continue;
@@ -436,9 +444,11 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     const size_t N = (size_t)cfg->N;
     std::vector<int32_t> items;
     std::vector<int> blk(n_runs);
+    // the Langevin proposal needs the filters' scores: their launches carry them
+    const bool lgv = cfg->proposal == SMC2_PROP_LANGEVIN;
+    const int want = lgv ? PF_SCHED_SCORE : cfg->schedule;
     for (int r = 0; r < n_runs; ++r)
-        blk[r] = cfg->block ? cfg->block
-                            : pf_default_block(cfg->model, cfg->precision, runs[r].n_x, runs[r].T, cfg->schedule);
+        blk[r] = cfg->block ? cfg->block : pf_default_block(cfg->model, cfg->precision, runs[r].n_x, runs[r].T, want);
     std::vector<int> run_order(n_runs);
     for (int r = 0; r < n_runs; ++r) run_order[r] = r;
     std::stable_sort(run_order.begin(), run_order.end(), [&](int a, int b) {
@@ -447,12 +457,13 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     });
     for (size_t idx = 0; idx < run_order.size();) {
         const int b = blk[run_order[idx]];
-        PFGroup gr{b, 0, (int)items.size(), 0, PF_SCHED_POOLED, cfg->persistent, 0, 0, 0, 0.f, 0.0, 0, 0.f};
+        PFGroup gr{b, 0, (int)items.size(), 0, lgv ? PF_SCHED_SCORE : PF_SCHED_POOLED, cfg->persistent, 0, 0, 0, 0.f,
+                   0.0, 0, 0.f};
         const size_t g0 = idx;
         // the pooled schedule when every run of the group fits in LDS with it
         for (size_t x = g0; x < run_order.size() && blk[run_order[x]] == b; ++x) {
             const int r = run_order[x];
-            const int sc = pf_pick_schedule(cfg->model, cfg->precision, b, runs[r].n_x, runs[r].T, cfg->schedule);
+            const int sc = pf_pick_schedule(cfg->model, cfg->precision, b, runs[r].n_x, runs[r].T, want);
             if (sc < 0) {
                 delete c;
                 return g_thread_error = "the pooled schedule does not fit in LDS for this n_x and T", SMC2_E_ARG;
@@ -531,6 +542,11 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
         o.mlp_frame = ma.frame;
         o.logq = (double*)(w + lay.off_mlp_logq);
     }
+    if (lgv) {
+        o.logq = (double*)(w + lay.off_mlp_logq);
+        o.score = (double*)(w + lay.off_score);
+        o.score_new = (double*)(w + lay.off_score_new);
+    }
     OuterParams& p = c->op;
     p.N = cfg->N;
     p.D = cfg->D;
@@ -541,6 +557,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     p.prior = (const double*)(w + lay.off_prior);
     p.lrw = (const double*)(w + lay.off_lrw);
     p.mlp = mlp ? 1 : 0;
+    p.langevin = lgv ? 1 : 0;
     {
         MlpParams& q = c->mp;
         q.D = cfg->D;
@@ -570,6 +587,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     a.pf_always = cfg->pf_always;
     a.multinomial = cfg->pf_resampling;
     a.n_pop = cfg->n_pop;
+    a.score = lgv ? o.score_new : nullptr;
     for (int i = 0; i < SMC2_NFIXED; ++i) a.fx[i] = c->fixed[i];
 
     hipStream_t s = c->stream;
@@ -594,6 +612,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
         if (e == hipSuccess) e = hipMemsetAsync(w + zero_from, 0, zero_to - zero_from, s);
         if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_mlp_score, 0, sizeof(double) * 2 * n_runs, s);
     }
+    if (lgv && e == hipSuccess) e = hipMemsetAsync(w + lay.off_score, 0, sizeof(double) * n_runs * N * cfg->D, s);
     if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_k, 0, sizeof(int32_t), s);
     if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_status, 0, sizeof(int32_t) * n_runs, s);
     if (e == hipSuccess) e = hipMemsetAsync(w + lay.off_psteps, 0, sizeof(unsigned long long) * n_runs, s);
@@ -774,12 +793,23 @@ extern "C" int smc2_dump(smc2_ctx* c, int32_t what, int32_t run, void* host_dst,
         src = c->oa.lkfit + (size_t)run * (2 * D + 4 * D * D);
         need = (2 * D + 4 * D * D) * 8;
         break;
+    case SMC2_DUMP_SCORE:
+    case SMC2_DUMP_SCORE_NEW:
+        if (!c->op.langevin) return c->fail(SMC2_E_ARG, "the context has no Langevin proposal");
+        src = (what == SMC2_DUMP_SCORE ? c->oa.score : c->oa.score_new) + base * D;
+        need = N * D * 8;
+        break;
     case SMC2_DUMP_MLP_OUT:
     case SMC2_DUMP_LOGQ:
     case SMC2_DUMP_MLP_PARAMS:
     case SMC2_DUMP_MLP_FRAME:
     case SMC2_DUMP_MLP_GRAD:
     case SMC2_DUMP_MLP_STATE: {
+        if (what == SMC2_DUMP_LOGQ && c->op.langevin) {
+            src = c->oa.logq + base;
+            need = N * 8;
+            break;
+        }
         if (!c->op.mlp) return c->fail(SMC2_E_ARG, "the context has no learned proposal");
         const size_t NP = (size_t)mlp_nparams((int)D), P = (size_t)mlp_nout((int)D);
         if (what == SMC2_DUMP_MLP_OUT) src = c->ma.out + base * P, need = N * P * 4;

@@ -207,3 +207,17 @@ def test_score_entry_point_rejects_before_device_use():
     # the score launch's LDS: SEIR at N_x = 4096 does not fit with five FP64 score columns
     r4 = G.make_runs([dict(T=100, nx=4096, seed=1, y=W.observations(w))])
     assert L.smc2_pf_score(ctypes.byref(c), 4, fake, r4, 1, fake, fake, fake, ws, None) == G.E_ARG
+
+
+def test_langevin_proposal_validation():
+    L = G.lib()
+    w = _w()
+    runs = G.make_runs([dict(T=100, nx=512, seed=1, y=W.observations(w))])
+    c = G.make_config(w, proposal=G.PROP_LANGEVIN)
+    nb = L.smc2_workspace_bytes(ctypes.byref(c), 1, runs)
+    assert nb > L.smc2_workspace_bytes(ctypes.byref(G.make_config(w)), 1, runs)  # scores and log q
+    wa = dict(W.preset("age_seir"), proposal=G.PROP_LANGEVIN)
+    ra = G.make_runs([dict(T=10, nx=256, seed=1, y=W.observations(dict(wa, T=10)))])
+    assert L.smc2_workspace_bytes(ctypes.byref(G.make_config(wa)), 1, ra) == 0
+    assert b"score" in L.smc2_last_error(None)
+    assert L.smc2_workspace_bytes(ctypes.byref(G.make_config(w, proposal=3)), 1, runs) == 0
