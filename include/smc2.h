@@ -96,7 +96,8 @@ extern "C" {
 
 #define SMC2_PROP_RW 0  /* Gaussian random walk on phi (Eq. proposal) */
 #define SMC2_PROP_LANGEVIN 2 /* truncated Langevin proposal (SIR, SEIR, SMC2_LINGAUSS):
-                                phi' = phi + delta + L z, delta = 1/2 Sigma_RW g shrunk to
+                                phi' = phi + delta + L z, Sigma = L L' the weighted covariance
+                                of the proposing population, delta = 1/2 Sigma g shrunk to
                                 Mahalanobis length <= 1, g the gradient of log(prior x
                                 likelihood) on the sampler coordinates from the filter's
                                 score estimate (smc2_pf_score's), which travels with its

@@ -1042,13 +1042,6 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
     /* Langevin: the score estimates of the population and of the proposals */
     double* sc = lgv ? (double*)calloc((size_t)N * D, sizeof(double)) : NULL;
     double* scn = lgv ? (double*)calloc((size_t)N * D, sizeof(double)) : NULL;
-    double Lrw[OR_DMAX * OR_DMAX];
-    if (lgv) {
-        double C[OR_DMAX * OR_DMAX];
-        for (int a = 0; a < D; ++a)
-            for (int c = 0; c < D; ++c) C[a * D + c] = cfg->rw_cov[a][c];
-        or_cholesky(D, C, Lrw);
-    }
     const int np = or_mlp_nparams(D);
     float* params = mlp ? (float*)calloc((size_t)np, sizeof(float)) : NULL;
     float* am = mlp ? (float*)calloc((size_t)np, sizeof(float)) : NULL;
@@ -1076,9 +1069,17 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
                 lpn[i] = or_prior_logpdf(cfg, phin + (size_t)i * D);
             }
         } else if (lgv) {
+            /* the proposal covariance: the weighted covariance of the proposing population
+               (its Cholesky factor as the learned proposal's frame forms it) */
+            const double Wl = logsumexp(N, logw);
+            double* wn = (double*)malloc(sizeof(double) * (size_t)N);
+            for (int i = 0; i < N; ++i) wn[i] = exp(logw[i] - Wl);
+            double fr[OR_DMAX + OR_DMAX * OR_DMAX];
+            or_mlp_frame(N, D, phi, wn, fr);
+            free(wn);
             for (int i = 0; i < N; ++i) {
-                lq[i] = or_propose_langevin_one(cfg, Lrw, phi + (size_t)i * D, sc + (size_t)i * D, seed, (uint32_t)k, i,
-                                                phin + (size_t)i * D);
+                lq[i] = or_propose_langevin_one(cfg, fr + D, phi + (size_t)i * D, sc + (size_t)i * D, seed, (uint32_t)k,
+                                                i, phin + (size_t)i * D);
                 lpn[i] = or_prior_logpdf(cfg, phin + (size_t)i * D);
             }
         } else {

@@ -192,7 +192,9 @@ double or_digamma(double x);
  * g = J s_theta + grad log prior(phi) (J = d theta / d phi per coordinate), shrunk to a
  * Mahalanobis length of at most 1 (|L^-1 delta| <= 1, L L' = Sigma), and
  * phi_new = phi + delta + L z with z the random walk's normals of sample i at iteration k.
- * Returns log q(phi_new | phi) = log N(phi_new; phi + delta, Sigma). */
+ * Returns log q(phi_new | phi) = log N(phi_new; phi + delta, Sigma). The sampler takes
+ * Sigma as the weighted covariance of the proposing population (L its frame's factor,
+ * or_mlp_frame). */
 double or_propose_langevin_one(const or_config* cfg, const double* L, const double* phi, const double* s_theta,
                                uint64_t seed, uint32_t k, int i, double* phi_new);
 /* Multinomial ancestors from quantised weights: slot m draws U_m = floor(x64_m Q / 2^64)

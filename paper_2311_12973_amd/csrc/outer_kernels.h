@@ -40,6 +40,8 @@ struct OuterArrays {
     // Langevin proposal (NULL unless configured): score estimates on the natural parameters
     double* score;            // [R][N][D]  of the population (they travel with their samples)
     double* score_new;        // [R][N][D]  of the proposals (the filters' output)
+    double* lgv_chol;         // [R][D][D]  Cholesky factor of the proposing population's
+                              //            weighted covariance (the proposal covariance)
 };
 
 struct OuterParams {
@@ -81,6 +83,8 @@ template <int D> __device__ __forceinline__ double prior_logpdf(const double* pr
 
 hipError_t launch_begin_iteration(const OuterArrays& o, int32_t* queues, int n_queues, hipStream_t s);
 hipError_t launch_propose(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds, hipStream_t s);
+// Langevin proposal: the proposing population's weighted covariance factor (k > 1)
+hipError_t launch_langevin_frame(const OuterArrays& o, const OuterParams& p, hipStream_t s);
 hipError_t launch_outer_update(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds,
                                hipStream_t s);
 

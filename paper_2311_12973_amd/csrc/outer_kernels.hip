@@ -94,11 +94,13 @@ __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, c
             }
             o.logq[g] = lq;
         } else if (p.langevin) {
-            // truncated Langevin proposal: drift delta = 1/2 Sigma_RW g with g the gradient of
+            // truncated Langevin proposal: drift delta = 1/2 Sigma g with g the gradient of
             // log(prior x likelihood) on the sampler coordinates, from the score estimate that
-            // travelled with the sample; shrunk to Mahalanobis length 1; phi' = phi + delta + L z
+            // travelled with the sample; shrunk to Mahalanobis length 1; phi' = phi + delta + L z,
+            // Sigma = L L' the weighted covariance of the proposing population
             const double* ph = o.phi + (size_t)g * D;
             const double* sth = o.score + (size_t)g * D;
+            const double* Lq = o.lgv_chol + (size_t)r * D * D;
             double gr[D], v[D], m[D];
 #pragma unroll
             for (int d = 0; d < D; ++d) {
@@ -114,7 +116,7 @@ __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, c
             for (int a = 0; a < D; ++a) {
                 double acc = 0.0;
 #pragma unroll
-                for (int c = a; c < D; ++c) acc += p.lrw[c * D + a] * gr[c];
+                for (int c = a; c < D; ++c) acc += Lq[c * D + a] * gr[c];
                 v[a] = acc;
                 n2 += acc * acc;
             }
@@ -124,14 +126,14 @@ __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, c
             for (int a = 0; a < D; ++a) {
                 double acc = 0.0;
 #pragma unroll
-                for (int c = 0; c <= a; ++c) acc += p.lrw[a * D + c] * v[c];
+                for (int c = 0; c <= a; ++c) acc += Lq[a * D + c] * v[c];
                 m[a] = ph[a] + (0.5 * acc) * shrink;
                 double lz = 0.0;
 #pragma unroll
-                for (int c = 0; c <= a; ++c) lz += p.lrw[a * D + c] * z[c];
+                for (int c = 0; c <= a; ++c) lz += Lq[a * D + c] * z[c];
                 phin[a] = m[a] + lz;
             }
-            o.logq[g] = mvn_logpdf<D>(phin, m, p.lrw);
+            o.logq[g] = mvn_logpdf<D>(phin, m, Lq);
         } else {
             const double* ph = o.phi + (size_t)g * D;
 #pragma unroll
@@ -551,6 +553,84 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
     }
 }
 
+// The Langevin proposal's covariance at iteration k > 1: the weighted covariance of the
+// proposing population (normalised weights exp(log w - W), W = log sum exp log w) and its
+// lower Cholesky factor, the diagonal of the standard deviations (floored at 1e-6) when a
+// pivot is not above 1e-12 of its coordinate's raw second moment. One workgroup per run;
+// the normalised weights go to o.scratch (free between outer updates).
+template <int D>
+__global__ void __launch_bounds__(OUTER_BLOCK) k_lgv_frame(OuterArrays o, OuterParams p)
+{
+    if (*o.k_dev < 2) return;
+    const int r = (int)blockIdx.x;
+    const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
+    const int N = p.N;
+    const size_t base = (size_t)r * N;
+    const double* phi = o.phi + base * D;
+    const double* logw = o.logw + base;
+    double* wn = o.scratch + base;
+    __shared__ RedLds red;
+    __shared__ double vlds[OUTER_WAVES * VSUM_MAX];
+    __shared__ double tmp[VSUM_MAX];
+    __shared__ double c[D], C[D * D];
+    double mx = -INFINITY;
+    for (int i = tid; i < N; i += nthr) mx = logw[i] > mx ? logw[i] : mx;
+    const double M = uniform_f64(block_max<double>(mx, &red));
+    double sw[1] = {0.0};
+    for (int i = tid; i < N; i += nthr) sw[0] += exp(logw[i] - M);
+    block_sum_vec<1>(sw, vlds, tmp);
+    const double W = M + log(tmp[0]);
+    double acc[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc[d] = 0.0;
+    for (int i = tid; i < N; i += nthr) {
+        const double w = exp(logw[i] - W);
+        wn[i] = w;
+#pragma unroll
+        for (int d = 0; d < D; ++d) acc[d] += w * phi[(size_t)i * D + d];
+    }
+    block_sum_vec<D>(acc, vlds, tmp);
+    if (tid < D) c[tid] = tmp[tid];
+    __syncthreads();
+    block_weighted_cov<D>(
+        N, wn, c,
+        [&](int i, double* z) {
+#pragma unroll
+            for (int d = 0; d < D; ++d) z[d] = phi[(size_t)i * D + d];
+        },
+        C, vlds, tmp);
+    if (tid == 0) {
+        double F[D * D];
+#pragma unroll
+        for (int e = 0; e < D * D; ++e) F[e] = 0.0;
+        bool ok = true;
+        for (int j = 0; j < D && ok; ++j) {
+            double sj = C[j * D + j];
+            for (int q = 0; q < j; ++q) sj -= F[j * D + q] * F[j * D + q];
+            ok = sj > 1e-12 * (C[j * D + j] + c[j] * c[j]);
+            if (!ok) break;
+            F[j * D + j] = sqrt(sj);
+            for (int i2 = j + 1; i2 < D; ++i2) {
+                double v = C[i2 * D + j];
+                for (int q = 0; q < j; ++q) v -= F[i2 * D + q] * F[j * D + q];
+                F[i2 * D + j] = v / F[j * D + j];
+            }
+        }
+        if (!ok) {
+#pragma unroll
+            for (int e = 0; e < D * D; ++e) F[e] = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const double sd = sqrt(C[a * D + a]);
+                F[a * D + a] = sd > 1e-6 ? sd : 1e-6;
+            }
+        }
+        double* out = o.lgv_chol + (size_t)r * D * D;
+#pragma unroll
+        for (int e = 0; e < D * D; ++e) out[e] = F[e];
+    }
+}
+
 hipError_t launch_begin_iteration(const OuterArrays& o, int32_t* queues, int n_queues, hipStream_t s)
 {
     hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, s, o.k_dev, queues, n_queues);
@@ -594,6 +674,27 @@ hipError_t launch_outer_update(const OuterArrays& o, const OuterParams& p, const
                                hipStream_t s)
 {
     return dispatch(o, p, d_seeds, s, true);
+}
+
+template <int D> static hipError_t launch_frame_d(const OuterArrays& o, const OuterParams& p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lgv_frame<D>, dim3((unsigned)p.R), dim3(OUTER_BLOCK), 0, s, o, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_langevin_frame(const OuterArrays& o, const OuterParams& p, hipStream_t s)
+{
+    switch (p.D) {
+    case 1: return launch_frame_d<1>(o, p, s);
+    case 2: return launch_frame_d<2>(o, p, s);
+    case 3: return launch_frame_d<3>(o, p, s);
+    case 4: return launch_frame_d<4>(o, p, s);
+    case 5: return launch_frame_d<5>(o, p, s);
+    case 6: return launch_frame_d<6>(o, p, s);
+    case 7: return launch_frame_d<7>(o, p, s);
+    case 8: return launch_frame_d<8>(o, p, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace smc2

@@ -65,7 +65,7 @@ struct Layout {
         off_ll, off_logw, off_lpn, off_lln, off_lwp, off_scr, off_qc, off_anc, off_active, off_rec, off_items,
         off_queues, off_tune_items, off_mlp_params, off_mlp_m, off_mlp_v, off_mlp_grad, off_mlp_t, off_mlp_frame,
         off_mlp_use, off_mlp_done, off_mlp_out, off_mlp_logq, off_mlp_score, off_mlp_rows, off_mlp_wfull, off_mlp_gpart,
-        off_psteps, off_lkfit, off_psteps_at, off_score, off_score_new;
+        off_psteps, off_lkfit, off_psteps_at, off_score, off_score_new, off_lgv_chol;
     size_t take(size_t bytes)
     {
         const size_t o = total;
@@ -123,6 +123,7 @@ Layout make_layout(const smc2_config* c, int R, const smc2_run* runs)
     L.off_mlp_logq = L.take(sizeof(double) * (mlp || lgv ? (size_t)R : 0) * N);
     L.off_score = L.take(sizeof(double) * (lgv ? RN * D : 0));
     L.off_score_new = L.take(sizeof(double) * (lgv ? RN * D : 0));
+    L.off_lgv_chol = L.take(sizeof(double) * (lgv ? (size_t)R * D * D : 0));
     L.off_mlp_score = L.take(sizeof(double) * Rm * 2);
     L.off_mlp_rows = L.take(sizeof(float) * Rm * N * MLP_ROW);
     L.off_mlp_wfull = L.take(sizeof(double) * Rm * N);
@@ -546,6 +547,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
         o.logq = (double*)(w + lay.off_mlp_logq);
         o.score = (double*)(w + lay.off_score);
         o.score_new = (double*)(w + lay.off_score_new);
+        o.lgv_chol = (double*)(w + lay.off_lgv_chol);
     }
     OuterParams& p = c->op;
     p.N = cfg->N;
@@ -655,6 +657,7 @@ static hipError_t enqueue_iteration(smc2_ctx* c, hipStream_t s, const hipEvent_t
     hipError_t e = launch_begin_iteration(c->oa, queues, (int)c->groups.size(), s);
     if (e == hipSuccess && c->op.mlp) e = launch_mlp_forward(c->ma, c->mp, c->oa, s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess && c->op.langevin) e = launch_langevin_frame(c->oa, c->op, s);
     if (e == hipSuccess) e = launch_propose(c->oa, c->op, c->d_seeds, s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
     for (size_t gi = 0; gi < c->groups.size(); ++gi) {

@@ -4,8 +4,11 @@ iteration's drift, and the proposal's exact log q enters the weights.
 
 * Free-running parity with the reference sampler on the same streams: every iteration's
   proposals, log-likelihoods, pre-resampling log-weights, ancestors and records, the
-  proposals' scores and log q (FP64: 1e-10; the FP32 filter: 1e-4 on the estimates,
-  identical ancestors).
+  proposals' scores. The proposal covariance is the Cholesky factor of the proposing
+  population's weighted covariance, summed in a different order on each side; the factor
+  of a poorly conditioned covariance (few distinct samples after a resampling, a logit
+  coordinate with a tiny spread) amplifies that rounding, so the proposals agree to 1e-9
+  rather than the random walk's 1e-12; ancestors are identical.
 * The scores travel with their samples: after a step the population's scores are the
   proposals' scores gathered by the ancestors.
 * The GPU sampler with it reaches the exact grid posterior of the tiny SIR problem.
@@ -16,7 +19,6 @@ import pytest
 import oracle as O
 import paper_2311_12973_amd as G
 from paper_2311_12973_amd import workloads as W
-from tests.test_gpu_sampler import _compare
 
 pytestmark = pytest.mark.gpu
 
@@ -51,16 +53,46 @@ def _run_pair(w, N, K, nx, T=None, seed=1, lkernel=None, prec=None):
     return gpu, ref, cfg, y
 
 
-@pytest.mark.parametrize("name,N,K,nx,T,lkernel,prec,tol_ll,tol_outer", [
-    ("sir_fp64", 64, 5, 64, None, None, None, 1e-10, 1e-9),
-    ("seir", 256, 4, 128, 40, G.L_FORWARD, None, 1e-4, 1e-8),
-    ("seir_learned", 128, 4, 96, 30, None, G.PREC_FP64, 1e-10, 1e-9),
+def _compare(gpu, ref, D, tol_ll):
+    assert ref["status"] == 0
+    K = gpu["ll"].shape[0]
+    worst = dict(phi=0.0, ll=0.0, logw=0.0)
+    for k in range(K):
+        dphi = np.abs(gpu["phi"][k] - ref["phi"][k]) / np.maximum(1.0, np.abs(ref["phi"][k]))
+        worst["phi"] = max(worst["phi"], float(dphi.max()))
+        assert dphi.max() <= 1e-9, k
+        assert np.allclose(gpu["lp"][k], ref["lp"][k], rtol=1e-9, atol=1e-9), k
+        fin = np.isfinite(ref["ll"][k])
+        assert np.array_equal(np.isfinite(gpu["ll"][k]), fin), k
+        rel = np.abs(gpu["ll"][k][fin] - ref["ll"][k][fin]) / np.abs(ref["ll"][k][fin])
+        worst["ll"] = max(worst["ll"], float(rel.max()) if rel.size else 0.0)
+        assert rel.max() <= tol_ll, k
+        fin = np.isfinite(ref["logw"][k])
+        assert np.array_equal(np.isfinite(gpu["logw"][k]), fin), k
+        dl = np.abs(gpu["logw"][k][fin] - ref["logw"][k][fin]) / np.maximum(1.0, np.abs(ref["logw"][k][fin]))
+        worst["logw"] = max(worst["logw"], float(dl.max()))
+        assert dl.max() <= 1e-7, k
+        assert np.array_equal(gpu["anc"][k], ref["anc"][k]), k
+    for col in [0, 2, 3, 4]:
+        assert np.array_equal(gpu["rec"][:, col], ref["rec"][:, col]), col
+    assert np.allclose(gpu["rec"][:, 1], ref["rec"][:, 1], rtol=1e-7)
+    assert np.allclose(gpu["rec"][:, 6:], ref["rec"][:, 6:], rtol=1e-7, atol=1e-12)
+    m_ref, _, _ = O.recycle(ref["rec"], D)
+    assert np.allclose(gpu["est"][0], m_ref, rtol=1e-7)
+    _log("  largest differences: proposals %.3g, estimates %.3g, log-weights %.3g" % (worst["phi"], worst["ll"],
+                                                                                     worst["logw"]))
+
+
+@pytest.mark.parametrize("name,N,K,nx,T,lkernel,prec,tol_ll", [
+    ("sir_fp64", 64, 5, 64, None, None, None, 1e-9),
+    ("seir", 256, 4, 128, 40, G.L_FORWARD, None, 1e-4),
+    ("seir_learned", 128, 4, 96, 30, None, G.PREC_FP64, 1e-9),
 ])
-def test_langevin_sampler_matches_reference(name, N, K, nx, T, lkernel, prec, tol_ll, tol_outer):
+def test_langevin_sampler_matches_reference(name, N, K, nx, T, lkernel, prec, tol_ll):
     w = W.preset(name)
     _log("Langevin %s N=%d K=%d nx=%d" % (name, N, K, nx))
     gpu, ref, cfg, y = _run_pair(w, N, K, nx, T=T, lkernel=lkernel, prec=prec)
-    _compare(gpu, ref, w["D"], tol_ll, tol_outer)
+    _compare(gpu, ref, w["D"], tol_ll)
     assert np.all(gpu["rec"][1:, -2] == 2) and gpu["rec"][0, -2] == 0
     # the proposals' scores: the reference's score estimates of the same filters
     for k in range(K):
