@@ -415,12 +415,13 @@ def paper_experiment(G, W, np, seed=1):
     return out
 
 
-def ess_at_fixed_error(G, W, np, n_ref=32768, k_ref=(30, 60), ref_seeds=3, seeds=10, k_max=(20, 60, 60),
+def ess_at_fixed_error(G, W, np, n_ref=32768, k_ref=(30, 60), ref_seeds=3, seeds=10, k_max=(20, 60, 60, 60),
                        thresholds=(0.05, 0.1, 0.15, 0.2, 0.25, 0.3)):
     """ESS per second at a fixed posterior error, learned proposal against the random
-    walk (and the truncated Langevin proposal, driven by the filters' score estimates,
-    against the random walk), on the learned-proposal configuration (SEIR with the
-    dispersion estimated, D = 5, T = 150, N = 4096, N_x = 1024):
+    walk (and, against the same random walk, the truncated Langevin proposal driven by
+    the filters' score estimates and the random walk with the population's covariance),
+    on the learned-proposal configuration (SEIR with the dispersion estimated, D = 5,
+    T = 150, N = 4096, N_x = 1024):
     * reference posterior: `ref_seeds` long runs of each form (N = n_ref, K = k_ref;
       one batched sampler per form). Per form, f the average of its runs' recycled
       means, s the root of their average variance, and its standard error the spread
@@ -430,7 +431,8 @@ def ess_at_fixed_error(G, W, np, n_ref=32768, k_ref=(30, 60), ref_seeds=3, seeds
       spread of all of them; a threshold counts as resolved when it is at least twice
       the reference's largest standard error;
     * each form runs `seeds` independent runs (one batched sampler) for up to k_max
-      iterations (learned, random walk). After iteration k a run's error is
+      iterations (learned, random walk, Langevin, population random walk). After
+      iteration k a run's error is
       eps(k) = max_d |f_d(k) - f_ref,d| / s_ref,d, f(k) its recycled mean over
       iterations 1..k; at the first k with eps(k) <= threshold the run's ESS per second
       is its recycled ESS sum_{k' <= k} l_k' over its share of the wall time of
@@ -440,8 +442,9 @@ def ess_at_fixed_error(G, W, np, n_ref=32768, k_ref=(30, 60), ref_seeds=3, seeds
     * the headline: the ratio of the medians at the smallest resolved threshold that
       at least 80% of each form's runs reach; also the replicate ESS (posterior variance
       over the variance of the final recycled means across runs) per second. The
-      Langevin form is reported beside it, against the random walk at the same
-      threshold."""
+      Langevin and population random-walk forms are reported beside it, against the
+      random walk at the same threshold, and the learned proposal against the population
+      random walk."""
     import torch
 
     w = W.preset("seir_learned")
@@ -479,7 +482,8 @@ def ess_at_fixed_error(G, W, np, n_ref=32768, k_ref=(30, 60), ref_seeds=3, seeds
                                       "seconds": v["seconds"], "posterior_mean": v["mean"].tolist(),
                                       "standard_error_in_sd": v["se"].tolist()} for k, v in refs.items()},
                          "difference_in_sd": ((a["mean"] - b["mean"]) / s_ref).tolist()}}
-    forms = (("learned", G.PROP_MLP), ("random_walk", G.PROP_RW), ("langevin", G.PROP_LANGEVIN))
+    forms = (("learned", G.PROP_MLP), ("random_walk", G.PROP_RW), ("langevin", G.PROP_LANGEVIN),
+             ("rw_pop", G.PROP_RW_POP))
     for (name, prop), kmax in zip(forms, k_max):
         log("ess: %s, %d runs at N=%d, up to K=%d" % (name, seeds, N, kmax))
         s = G.Sampler(dict(w, proposal=prop), [run(sd) for sd in range(1, seeds + 1)], N=N, K=kmax)
@@ -529,25 +533,32 @@ def ess_at_fixed_error(G, W, np, n_ref=32768, k_ref=(30, 60), ref_seeds=3, seeds
     out["speedup"] = out["ratio_of_medians_eps_%g" % head] if head is not None else None
     out["replicate_ess_speedup"] = (out["learned"]["replicate_ess_per_s_per_run"] /
                                     out["random_walk"]["replicate_ess_per_s_per_run"])
-    if "langevin" in out:
+    for form, against in (("langevin", "random_walk"), ("rw_pop", "random_walk"), ("learned", "rw_pop")):
+        if form not in out or against not in out:
+            continue
+        tag = form if against == "random_walk" else "%s_vs_%s" % (form, against)
         for th in thresholds:
-            a = out["langevin"]["eps_%g" % th]
-            b = out["random_walk"]["eps_%g" % th]
-            out["langevin_ratio_of_medians_eps_%g" % th] = (
+            a = out[form]["eps_%g" % th]
+            b = out[against]["eps_%g" % th]
+            out["%s_ratio_of_medians_eps_%g" % (tag, th)] = (
                 a["ess_per_s_quartiles"][1] / b["ess_per_s_quartiles"][1]
                 if a["ess_per_s_quartiles"][1] and b["ess_per_s_quartiles"][1] else None)
-        ok = head is not None and out["langevin"]["eps_%g" % head]["not_reached"] <= 0.2 * seeds
-        out["langevin_speedup"] = out["langevin_ratio_of_medians_eps_%g" % head] if ok else None
-        out["langevin_replicate_ess_speedup"] = (out["langevin"]["replicate_ess_per_s_per_run"] /
-                                                 out["random_walk"]["replicate_ess_per_s_per_run"])
+        ok = (head is not None and out[form]["eps_%g" % head]["not_reached"] <= 0.2 * seeds
+              and out[against]["eps_%g" % head]["not_reached"] <= 0.2 * seeds)
+        out["%s_speedup" % tag] = out["%s_ratio_of_medians_eps_%g" % (tag, head)] if ok else None
+        out["%s_replicate_ess_speedup" % tag] = (out[form]["replicate_ess_per_s_per_run"] /
+                                                 out[against]["replicate_ess_per_s_per_run"])
     out["protocol"] = ("recycled ESS per second at the first iteration with max_d |mean - ref| / sd_ref <= eps; "
                        "reference: %d runs of each form at N=%d (K=%d learned, %d random walk), the more precise "
                        "when they agree; %d runs per form at N=%d; speedup at the smallest resolved eps that 80%% "
                        "of each form's runs reach" % (ref_seeds, n_ref, k_ref[0], k_ref[1], seeds, N))
     out["workload"] = "seir_learned: D=5, T=150, N=4096, N_x=1024"
-    log("ess: speedup %s at eps %s (replicate ESS %.3g); Langevin %s (replicate ESS %.3g)"
+    log("ess: speedup %s at eps %s (replicate ESS %.3g); Langevin %s (replicate ESS %.3g); population random "
+        "walk %s (replicate ESS %.3g); learned against it %s (replicate ESS %.3g)"
         % (out["speedup"], head, out["replicate_ess_speedup"], out.get("langevin_speedup"),
-           out.get("langevin_replicate_ess_speedup", float("nan"))))
+           out.get("langevin_replicate_ess_speedup", float("nan")), out.get("rw_pop_speedup"),
+           out.get("rw_pop_replicate_ess_speedup", float("nan")), out.get("learned_vs_rw_pop_speedup"),
+           out.get("learned_vs_rw_pop_replicate_ess_speedup", float("nan"))))
     return out
 
 

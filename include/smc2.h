@@ -102,6 +102,11 @@ extern "C" {
                                 likelihood) on the sampler coordinates from the filter's
                                 score estimate (smc2_pf_score's), which travels with its
                                 sample; its exact log q enters the weights (Eq. l_weights) */
+#define SMC2_PROP_RW_POP 3 /* random walk with the population's covariance (every model):
+                               phi' = phi + L z, Sigma = L L' the weighted covariance of
+                               the proposing population (SMC2_PROP_LANGEVIN's covariance,
+                               without its drift); its log q enters the weights
+                               (Eq. l_weights). Iteration 1 draws from the prior. */
 #define SMC2_PROP_MLP 1 /* learned Gaussian proposal: a D -> 64 -> 64 -> (mean, Cholesky)
                            network, BF16 matrix-core products, trained after every
                            iteration on the weighted population; its exact density
@@ -187,7 +192,7 @@ typedef struct {
  *   [6+D .. 6+D+D*D)      weighted covariance of theta
  *   [6+D+D*D .. 6+2D+D*D) weighted mean of the sampler coordinates phi
  *   [6+2D+D*D]            proposal used at iteration k (0 random walk, 1 learned,
- *                         2 Langevin)
+ *                         2 Langevin, 3 population random walk)
  *   [7+2D+D*D]            learned proposal trained after iteration k: held-out mean
  *                         weighted NLL minus the random walk's (0 without training)    */
 #define SMC2_RECORD_LEN(D) (8 + 2 * (D) + (D) * (D))
@@ -221,7 +226,8 @@ typedef struct {
 #define SMC2_DUMP_LOGQ 10       /* N      doubles: log q(phi_new | phi) of the learned
                                    proposal at the last step; 0 where that step drew from
                                    the prior (k = 1) or the random walk (also for the
-                                   Langevin proposal: its log q at the last step)          */
+                                   Langevin and population random-walk proposals: their
+                                   log q at the last step)                                 */
 #define SMC2_DUMP_MLP_PARAMS 11 /* NP     float: FP32 master weights W1[64][D] b1[64]
                                    W2[64][64] b2[64] W3[P][64] b3[P] (after training)    */
 #define SMC2_DUMP_MLP_FRAME 12  /* D+D*D  doubles: input frame of the current network: the

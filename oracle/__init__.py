@@ -20,7 +20,7 @@ OBS_POIS_PREV, OBS_POIS_INC, OBS_NB_INC = 0, 1, 2
 PREC_FP32, PREC_FP64 = 0, 1
 PRIOR_UNIFORM, PRIOR_LOGNORMAL, PRIOR_LOGITNORMAL, PRIOR_NORMAL = 0, 1, 2, 3
 L_FORWARD, L_GAUSS_OPT = 0, 1
-PROP_RW, PROP_MLP, PROP_LANGEVIN = 0, 1, 2
+PROP_RW, PROP_MLP, PROP_LANGEVIN, PROP_RW_POP = 0, 1, 2, 3
 RS_SYSTEMATIC, RS_MULTINOMIAL = 0, 1
 
 

@@ -1019,12 +1019,15 @@ void or_recycle(int K, int D, const double* rec, double* mean, double* cov, doub
  * likelihood estimated by a particle filter with nx particles. Per-iteration dumps
  * (pre-resampling proposals, their log-likelihoods, log-priors, log-weights and the
  * ancestors chosen) are written when the pointers are not NULL; each holds K
- * consecutive blocks. Returns 0, or the first non-zero status of an update.
+ * consecutive blocks. Returns 0, or the first non-zero status of an update; -5 for a
+ * model the reference sampler does not run (only the epidemic models: the
+ * linear-Gaussian filter is or_pf_lg, on real observations).
  */
 int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t seed, int N, int K,
                 int n_threads, double* rec, double* phi_dump, double* ll_dump, double* lp_dump,
                 double* logw_dump, int32_t* anc_dump)
 {
+    if (cfg->model != OR_SIR && cfg->model != OR_SEIR && cfg->model != OR_AGE_SEIR) return -5;
     const int D = cfg->D;
     const int RL = or_record_len(D);
     double* phi = (double*)calloc((size_t)N * D, sizeof(double));
@@ -1039,6 +1042,7 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
     double* lq = (double*)calloc((size_t)N, sizeof(double));
     const int mlp = cfg->proposal == OR_PROP_MLP;
     const int lgv = cfg->proposal == OR_PROP_LANGEVIN;
+    const int rwp = cfg->proposal == OR_PROP_RW_POP;
     /* Langevin: the score estimates of the population and of the proposals */
     double* sc = lgv ? (double*)calloc((size_t)N * D, sizeof(double)) : NULL;
     double* scn = lgv ? (double*)calloc((size_t)N * D, sizeof(double)) : NULL;
@@ -1068,7 +1072,7 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
                 lq[i] = or_mlp_propose_one(D, frame, o, seed, (uint32_t)k, i, phin + (size_t)i * D);
                 lpn[i] = or_prior_logpdf(cfg, phin + (size_t)i * D);
             }
-        } else if (lgv) {
+        } else if (lgv || rwp) {
             /* the proposal covariance: the weighted covariance of the proposing population
                (its Cholesky factor as the learned proposal's frame forms it) */
             const double Wl = logsumexp(N, logw);
@@ -1078,8 +1082,24 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
             or_mlp_frame(N, D, phi, wn, fr);
             free(wn);
             for (int i = 0; i < N; ++i) {
-                lq[i] = or_propose_langevin_one(cfg, fr + D, phi + (size_t)i * D, sc + (size_t)i * D, seed, (uint32_t)k,
-                                                i, phin + (size_t)i * D);
+                if (lgv) {
+                    lq[i] = or_propose_langevin_one(cfg, fr + D, phi + (size_t)i * D, sc + (size_t)i * D, seed,
+                                                    (uint32_t)k, i, phin + (size_t)i * D);
+                } else { /* the random walk with the population's covariance: phi' = phi + F z */
+                    const double* ph = phi + (size_t)i * D;
+                    const double* F = fr + D;
+                    double z[OR_DMAX];
+                    for (int d = 0; d < D; ++d) {
+                        uint32_t ctr[4] = {(uint32_t)i, 0u, (uint32_t)k << 16, ((uint32_t)OR_S_RW << 24) | (uint32_t)d};
+                        z[d] = or_normal_call(seed, ctr);
+                    }
+                    for (int a = 0; a < D; ++a) {
+                        double acc = 0.0;
+                        for (int c = 0; c <= a; ++c) acc += F[a * D + c] * z[c];
+                        phin[(size_t)i * D + a] = ph[a] + acc;
+                    }
+                    lq[i] = or_mvn_logpdf_chol(D, phin + (size_t)i * D, ph, F);
+                }
                 lpn[i] = or_prior_logpdf(cfg, phin + (size_t)i * D);
             }
         } else {
@@ -1102,10 +1122,10 @@ int or_smc2_run(const or_config* cfg, const int32_t* y, int T, int nx, uint64_t 
             }
         }
         double* rk = rec + (size_t)(k - 1) * RL;
-        const int drift = lgv && k > 1;
+        const int drift = (lgv || rwp) && k > 1; /* proposals with their own density in lq */
         int st = or_outer_update(cfg, N, (uint32_t)k, seed, phi, lp, ll, logw, phin, lpn, lln,
                                  (learned || drift) ? lq : NULL, lwp, anc, rk);
-        rk[RL - 2] = learned ? 1.0 : (drift ? 2.0 : 0.0);
+        rk[RL - 2] = learned ? 1.0 : (drift ? (lgv ? 2.0 : 3.0) : 0.0);
         if (lgv && st == 0) /* the scores travel with their samples through resampling */
             for (int i = 0; i < N; ++i)
                 for (int d = 0; d < D; ++d) sc[(size_t)i * D + d] = scn[(size_t)anc[i] * D + d];

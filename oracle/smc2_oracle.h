@@ -31,7 +31,7 @@ enum { OR_OBS_POIS_PREV = 0, OR_OBS_POIS_INC = 1, OR_OBS_NB_INC = 2 };
 enum { OR_PREC_FP32 = 0, OR_PREC_FP64 = 1 };
 enum { OR_PRIOR_UNIFORM = 0, OR_PRIOR_LOGNORMAL = 1, OR_PRIOR_LOGITNORMAL = 2, OR_PRIOR_NORMAL = 3 };
 enum { OR_L_FORWARD = 0, OR_L_GAUSS_OPT = 1 };
-enum { OR_PROP_RW = 0, OR_PROP_MLP = 1, OR_PROP_LANGEVIN = 2 };
+enum { OR_PROP_RW = 0, OR_PROP_MLP = 1, OR_PROP_LANGEVIN = 2, OR_PROP_RW_POP = 3 };
 
 /* Philox stream identifiers (bits 24..31 of the fourth counter word). */
 enum { OR_S_PF_PROP = 1, OR_S_PF_RS = 2, OR_S_PRIOR = 3, OR_S_RW = 4, OR_S_OUTER_RS = 5,
@@ -53,7 +53,7 @@ typedef struct {
     int32_t model, obs, D, prec;
     int32_t pf_always;  /* 1: resample the particle filter at every step; 0: when ESS < Nx/2 */
     int32_t lkernel;    /* OR_L_FORWARD or OR_L_GAUSS_OPT */
-    int32_t proposal;   /* OR_PROP_RW, OR_PROP_MLP or OR_PROP_LANGEVIN */
+    int32_t proposal;   /* OR_PROP_RW, OR_PROP_MLP, OR_PROP_LANGEVIN or OR_PROP_RW_POP */
     int32_t n_fixed;
     double n_pop;
     double prior[OR_DMAX][3];      /* {family, a, b} per sampler coordinate */

@@ -36,12 +36,14 @@ struct OuterArrays {
     const int32_t* mlp_use;   // [R]        1: this iteration proposes with the network
     const float* mlp_out;     // [R][N][P]  network outputs at the current population
     const double* mlp_frame;  // [R][D+D*D] input frame of the network: mean c, Cholesky factor F
-    double* logq;             // [R][N]     log q(phi_new | phi) of the learned or Langevin proposal
+    double* logq;             // [R][N]     log q(phi_new | phi) of the learned proposal or of a
+                              //            proposal with the population's covariance
     // Langevin proposal (NULL unless configured): score estimates on the natural parameters
     double* score;            // [R][N][D]  of the population (they travel with their samples)
     double* score_new;        // [R][N][D]  of the proposals (the filters' output)
-    double* lgv_chol;         // [R][D][D]  Cholesky factor of the proposing population's
-                              //            weighted covariance (the proposal covariance)
+    double* pop_chol;         // [R][D][D]  Cholesky factor of the proposing population's
+                              //            weighted covariance (the proposal covariance of the
+                              //            Langevin and population random-walk proposals)
 };
 
 struct OuterParams {
@@ -51,7 +53,9 @@ struct OuterParams {
     const double* prior; // [D][3] {family, a, b} (device)
     const double* lrw;   // [D][D] lower Cholesky factor of the RW covariance (device)
     int32_t mlp;         // 1: the learned proposal is configured
-    int32_t langevin;    // 1: the truncated Langevin proposal is configured
+    int32_t langevin;    // 1: the truncated Langevin proposal is configured (drift + scores)
+    int32_t popcov;      // 1: the proposal covariance is the proposing population's (the
+                         //    Langevin proposal and the population random walk)
 };
 
 // model parameter theta_d from the sampler coordinate phi_d of a prior family
@@ -84,7 +88,7 @@ template <int D> __device__ __forceinline__ double prior_logpdf(const double* pr
 hipError_t launch_begin_iteration(const OuterArrays& o, int32_t* queues, int n_queues, hipStream_t s);
 hipError_t launch_propose(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds, hipStream_t s);
 // Langevin proposal: the proposing population's weighted covariance factor (k > 1)
-hipError_t launch_langevin_frame(const OuterArrays& o, const OuterParams& p, hipStream_t s);
+hipError_t launch_pop_frame(const OuterArrays& o, const OuterParams& p, hipStream_t s);
 hipError_t launch_outer_update(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds,
                                hipStream_t s);
 

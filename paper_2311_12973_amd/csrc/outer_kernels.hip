@@ -93,41 +93,51 @@ __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, c
                 phin[a] = sa;
             }
             o.logq[g] = lq;
-        } else if (p.langevin) {
-            // truncated Langevin proposal: drift delta = 1/2 Sigma g with g the gradient of
-            // log(prior x likelihood) on the sampler coordinates, from the score estimate that
-            // travelled with the sample; shrunk to Mahalanobis length 1; phi' = phi + delta + L z,
-            // Sigma = L L' the weighted covariance of the proposing population
+        } else if (p.popcov) {
+            // Sigma = L L' the weighted covariance of the proposing population; phi' = m + L z.
+            // The population random walk: m = phi. The truncated Langevin proposal:
+            // m = phi + delta, delta = 1/2 Sigma g with g the gradient of log(prior x
+            // likelihood) on the sampler coordinates, from the score estimate that travelled
+            // with the sample, shrunk to Mahalanobis length 1.
             const double* ph = o.phi + (size_t)g * D;
-            const double* sth = o.score + (size_t)g * D;
-            const double* Lq = o.lgv_chol + (size_t)r * D * D;
-            double gr[D], v[D], m[D];
+            const double* Lq = o.pop_chol + (size_t)r * D * D;
+            double m[D];
 #pragma unroll
-            for (int d = 0; d < D; ++d) {
-                const int fam = (int)p.prior[3 * d];
-                const double a = p.prior[3 * d + 1], b = p.prior[3 * d + 2];
-                const double th = theta_of(fam, ph[d]);
-                const double J = fam == PRIOR_LOGNORMAL ? th : (fam == PRIOR_LOGITNORMAL ? th * (1.0 - th) : 1.0);
-                const double gp = fam == PRIOR_UNIFORM ? 0.0 : -(ph[d] - a) / (b * b);
-                gr[d] = J * sth[d] + gp;
+            for (int d = 0; d < D; ++d) m[d] = ph[d];
+            if (p.langevin) {
+                const double* sth = o.score + (size_t)g * D;
+                double gr[D], v[D];
+#pragma unroll
+                for (int d = 0; d < D; ++d) {
+                    const int fam = (int)p.prior[3 * d];
+                    const double a = p.prior[3 * d + 1], b = p.prior[3 * d + 2];
+                    const double th = theta_of(fam, ph[d]);
+                    const double J =
+                        fam == PRIOR_LOGNORMAL ? th : (fam == PRIOR_LOGITNORMAL ? th * (1.0 - th) : 1.0);
+                    const double gp = fam == PRIOR_UNIFORM ? 0.0 : -(ph[d] - a) / (b * b);
+                    gr[d] = J * sth[d] + gp;
+                }
+                double n2 = 0.0;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int c = a; c < D; ++c) acc += Lq[c * D + a] * gr[c];
+                    v[a] = acc;
+                    n2 += acc * acc;
+                }
+                const double len = 0.5 * sqrt(n2);
+                const double shrink = len > 1.0 ? 1.0 / len : 1.0;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int c = 0; c <= a; ++c) acc += Lq[a * D + c] * v[c];
+                    m[a] = ph[a] + (0.5 * acc) * shrink;
+                }
             }
-            double n2 = 0.0;
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                double acc = 0.0;
-#pragma unroll
-                for (int c = a; c < D; ++c) acc += Lq[c * D + a] * gr[c];
-                v[a] = acc;
-                n2 += acc * acc;
-            }
-            const double len = 0.5 * sqrt(n2);
-            const double shrink = len > 1.0 ? 1.0 / len : 1.0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                double acc = 0.0;
-#pragma unroll
-                for (int c = 0; c <= a; ++c) acc += Lq[a * D + c] * v[c];
-                m[a] = ph[a] + (0.5 * acc) * shrink;
                 double lz = 0.0;
 #pragma unroll
                 for (int c = 0; c <= a; ++c) lz += Lq[a * D + c] * z[c];
@@ -322,10 +332,10 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
     if (tid == 0 && o.psteps_at) o.psteps_at[(size_t)r * p.K + (k - 1)] = o.psteps[r];
     __syncthreads();
 
-    // proposal of this iteration: the learned one or the Langevin one (then its density is
-    // in o.logq)
+    // proposal of this iteration: the learned one or one with the population's covariance
+    // (then its density is in o.logq)
     const bool learned = p.mlp && k >= 2 && uniform_bool(o.mlp_use[r] != 0);
-    const bool drift = p.langevin && k >= 2;
+    const bool drift = p.popcov && k >= 2;
 
     // ---------------- approximately optimal L-kernel (k > 1)
     // Without a usable fit (forward-kernel setting, or the fit rejected) the backward
@@ -521,7 +531,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
         rec[3] = (double)dead;
         rec[4] = (double)fallback;
         rec[5] = W;
-        rec[p.rec_len - 2] = learned ? 1.0 : (drift ? 2.0 : 0.0);
+        rec[p.rec_len - 2] = learned ? 1.0 : (drift ? (p.langevin ? 2.0 : 3.0) : 0.0);
         for (int a2 = 0; a2 < D; ++a2) {
             rec[6 + a2] = mth[a2];
             rec[6 + D + D * D + a2] = mph[a2];
@@ -553,13 +563,14 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_outer(OuterArrays o, OuterParam
     }
 }
 
-// The Langevin proposal's covariance at iteration k > 1: the weighted covariance of the
-// proposing population (normalised weights exp(log w - W), W = log sum exp log w) and its
+// The proposal covariance of the Langevin and population random-walk proposals at iteration
+// k > 1: the weighted covariance of the proposing population (normalised weights
+// exp(log w - W), W = log sum exp log w) and its
 // lower Cholesky factor, the diagonal of the standard deviations (floored at 1e-6) when a
 // pivot is not above 1e-12 of its coordinate's raw second moment. One workgroup per run;
 // the normalised weights go to o.scratch (free between outer updates).
 template <int D>
-__global__ void __launch_bounds__(OUTER_BLOCK) k_lgv_frame(OuterArrays o, OuterParams p)
+__global__ void __launch_bounds__(OUTER_BLOCK) k_pop_frame(OuterArrays o, OuterParams p)
 {
     if (*o.k_dev < 2) return;
     const int r = (int)blockIdx.x;
@@ -625,7 +636,7 @@ __global__ void __launch_bounds__(OUTER_BLOCK) k_lgv_frame(OuterArrays o, OuterP
                 F[a * D + a] = sd > 1e-6 ? sd : 1e-6;
             }
         }
-        double* out = o.lgv_chol + (size_t)r * D * D;
+        double* out = o.pop_chol + (size_t)r * D * D;
 #pragma unroll
         for (int e = 0; e < D * D; ++e) out[e] = F[e];
     }
@@ -678,11 +689,11 @@ hipError_t launch_outer_update(const OuterArrays& o, const OuterParams& p, const
 
 template <int D> static hipError_t launch_frame_d(const OuterArrays& o, const OuterParams& p, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_lgv_frame<D>, dim3((unsigned)p.R), dim3(OUTER_BLOCK), 0, s, o, p);
+    hipLaunchKernelGGL(k_pop_frame<D>, dim3((unsigned)p.R), dim3(OUTER_BLOCK), 0, s, o, p);
     return hipGetLastError();
 }
 
-hipError_t launch_langevin_frame(const OuterArrays& o, const OuterParams& p, hipStream_t s)
+hipError_t launch_pop_frame(const OuterArrays& o, const OuterParams& p, hipStream_t s)
 {
     switch (p.D) {
     case 1: return launch_frame_d<1>(o, p, s);

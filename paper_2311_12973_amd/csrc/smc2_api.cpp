@@ -65,7 +65,7 @@ struct Layout {
         off_ll, off_logw, off_lpn, off_lln, off_lwp, off_scr, off_qc, off_anc, off_active, off_rec, off_items,
         off_queues, off_tune_items, off_mlp_params, off_mlp_m, off_mlp_v, off_mlp_grad, off_mlp_t, off_mlp_frame,
         off_mlp_use, off_mlp_done, off_mlp_out, off_mlp_logq, off_mlp_score, off_mlp_rows, off_mlp_wfull, off_mlp_gpart,
-        off_psteps, off_lkfit, off_psteps_at, off_score, off_score_new, off_lgv_chol;
+        off_psteps, off_lkfit, off_psteps_at, off_score, off_score_new, off_pop_chol;
     size_t take(size_t bytes)
     {
         const size_t o = total;
@@ -120,10 +120,11 @@ Layout make_layout(const smc2_config* c, int R, const smc2_run* runs)
     L.off_mlp_done = L.take(sizeof(int32_t) * Rm);
     L.off_mlp_out = L.take(sizeof(float) * Rm * N * P);
     const bool lgv = c->proposal == SMC2_PROP_LANGEVIN;
-    L.off_mlp_logq = L.take(sizeof(double) * (mlp || lgv ? (size_t)R : 0) * N);
+    const bool popcov = lgv || c->proposal == SMC2_PROP_RW_POP;
+    L.off_mlp_logq = L.take(sizeof(double) * (mlp || popcov ? (size_t)R : 0) * N);
     L.off_score = L.take(sizeof(double) * (lgv ? RN * D : 0));
     L.off_score_new = L.take(sizeof(double) * (lgv ? RN * D : 0));
-    L.off_lgv_chol = L.take(sizeof(double) * (lgv ? (size_t)R * D * D : 0));
+    L.off_pop_chol = L.take(sizeof(double) * (popcov ? (size_t)R * D * D : 0));
     L.off_mlp_score = L.take(sizeof(double) * Rm * 2);
     L.off_mlp_rows = L.take(sizeof(float) * Rm * N * MLP_ROW);
     L.off_mlp_wfull = L.take(sizeof(double) * Rm * N);
@@ -212,7 +213,8 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
     const bool lg = c->model == SMC2_LINGAUSS;
     if (lg && c->precision != SMC2_PREC_FP64)
         return m = "the linear-Gaussian model runs in FP64 only", SMC2_E_UNSUPPORTED;
-    if (c->proposal != SMC2_PROP_RW && c->proposal != SMC2_PROP_MLP && c->proposal != SMC2_PROP_LANGEVIN)
+    if (c->proposal != SMC2_PROP_RW && c->proposal != SMC2_PROP_MLP && c->proposal != SMC2_PROP_LANGEVIN &&
+        c->proposal != SMC2_PROP_RW_POP)
         return m = "unknown proposal", SMC2_E_UNSUPPORTED;
     if (c->proposal == SMC2_PROP_LANGEVIN && pf_score_dims(c->model) == 0)
         return m = "the Langevin proposal needs the filter's score (SIR, SEIR, linear-Gaussian)", SMC2_E_UNSUPPORTED;
@@ -543,11 +545,14 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
         o.mlp_frame = ma.frame;
         o.logq = (double*)(w + lay.off_mlp_logq);
     }
-    if (lgv) {
+    const bool popcov = lgv || cfg->proposal == SMC2_PROP_RW_POP;
+    if (popcov) {
         o.logq = (double*)(w + lay.off_mlp_logq);
+        o.pop_chol = (double*)(w + lay.off_pop_chol);
+    }
+    if (lgv) {
         o.score = (double*)(w + lay.off_score);
         o.score_new = (double*)(w + lay.off_score_new);
-        o.lgv_chol = (double*)(w + lay.off_lgv_chol);
     }
     OuterParams& p = c->op;
     p.N = cfg->N;
@@ -560,6 +565,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     p.lrw = (const double*)(w + lay.off_lrw);
     p.mlp = mlp ? 1 : 0;
     p.langevin = lgv ? 1 : 0;
+    p.popcov = popcov ? 1 : 0;
     {
         MlpParams& q = c->mp;
         q.D = cfg->D;
@@ -657,7 +663,7 @@ static hipError_t enqueue_iteration(smc2_ctx* c, hipStream_t s, const hipEvent_t
     hipError_t e = launch_begin_iteration(c->oa, queues, (int)c->groups.size(), s);
     if (e == hipSuccess && c->op.mlp) e = launch_mlp_forward(c->ma, c->mp, c->oa, s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[1], s);
-    if (e == hipSuccess && c->op.langevin) e = launch_langevin_frame(c->oa, c->op, s);
+    if (e == hipSuccess && c->op.popcov) e = launch_pop_frame(c->oa, c->op, s);
     if (e == hipSuccess) e = launch_propose(c->oa, c->op, c->d_seeds, s);
     if (e == hipSuccess && ev) e = hipEventRecord(ev[2], s);
     for (size_t gi = 0; gi < c->groups.size(); ++gi) {
@@ -808,7 +814,7 @@ extern "C" int smc2_dump(smc2_ctx* c, int32_t what, int32_t run, void* host_dst,
     case SMC2_DUMP_MLP_FRAME:
     case SMC2_DUMP_MLP_GRAD:
     case SMC2_DUMP_MLP_STATE: {
-        if (what == SMC2_DUMP_LOGQ && c->op.langevin) {
+        if (what == SMC2_DUMP_LOGQ && c->op.popcov) {
             src = c->oa.logq + base;
             need = N * 8;
             break;

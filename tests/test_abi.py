@@ -220,4 +220,19 @@ def test_langevin_proposal_validation():
     ra = G.make_runs([dict(T=10, nx=256, seed=1, y=W.observations(dict(wa, T=10)))])
     assert L.smc2_workspace_bytes(ctypes.byref(G.make_config(wa)), 1, ra) == 0
     assert b"score" in L.smc2_last_error(None)
-    assert L.smc2_workspace_bytes(ctypes.byref(G.make_config(w, proposal=3)), 1, runs) == 0
+    assert L.smc2_workspace_bytes(ctypes.byref(G.make_config(w, proposal=4)), 1, runs) == 0
+
+
+def test_population_random_walk_validation():
+    """every model takes it (no score needed); it holds the log q and the covariance
+    factors, not the scores"""
+    L = G.lib()
+    w = _w()
+    runs = G.make_runs([dict(T=100, nx=512, seed=1, y=W.observations(w))])
+    base = L.smc2_workspace_bytes(ctypes.byref(G.make_config(w)), 1, runs)
+    pop = L.smc2_workspace_bytes(ctypes.byref(G.make_config(w, proposal=G.PROP_RW_POP)), 1, runs)
+    lgv = L.smc2_workspace_bytes(ctypes.byref(G.make_config(w, proposal=G.PROP_LANGEVIN)), 1, runs)
+    assert base < pop < lgv
+    wa = dict(W.preset("age_seir"), proposal=G.PROP_RW_POP)
+    ra = G.make_runs([dict(T=10, nx=256, seed=1, y=W.observations(dict(wa, T=10)))])
+    assert L.smc2_workspace_bytes(ctypes.byref(G.make_config(wa)), 1, ra) > 0

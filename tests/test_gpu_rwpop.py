@@ -1,0 +1,103 @@
+"""The random walk with the population's covariance on the GPU sampler
+(SMC2_PROP_RW_POP), through the C ABI. Its proposal covariance is the Cholesky factor of
+the proposing population's weighted covariance (one workgroup per run before the
+proposals); it needs no score, so the filters keep their configured schedule (the
+pooled one included) and every model runs it.
+
+* Free-running parity with the reference sampler on the same streams: every iteration's
+  proposals, log-likelihoods, pre-resampling log-weights, ancestors, records and the
+  recycled estimate. The two sides sum the covariance in different orders and its factor
+  amplifies that rounding for a poorly conditioned population, so proposals agree to
+  1e-9; ancestors are identical.
+* The proposals' log q dumped by the GPU equals log N(phi_new; phi, Sigma_pop), Sigma_pop
+  the weighted covariance of the dumped population (numpy, with the degenerate
+  population's diagonal fallback).
+* The GPU sampler with it reaches the exact grid posterior of the tiny SIR problem.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle as O
+import paper_2311_12973_amd as G
+from paper_2311_12973_amd import workloads as W
+from tests.test_gpu_langevin import _compare
+from tests.test_oracle_rwpop import _factor
+
+pytestmark = pytest.mark.gpu
+
+
+def _log(msg):
+    print(msg, flush=True)
+
+
+def _run_pair(w, N, K, nx, sched, seed=1):
+    y = W.observations(w)
+    s = G.Sampler(w, [dict(T=y.shape[0], nx=nx, seed=seed, y=y)], N=N, K=K, schedule=sched)
+    gpu = dict(phi=[], ll=[], lp=[], logw=[], anc=[], logq=[], pop=[], pop_logw=[])
+    for k in range(K):
+        gpu["pop"].append(s.dump("phi"))
+        gpu["pop_logw"].append(s.dump("logw"))
+        s.step()
+        for key, what in (("phi", "phi_new"), ("ll", "ll_new"), ("lp", "lp_new"), ("logw", "logw_pre"),
+                          ("anc", "anc"), ("logq", "logq")):
+            gpu[key].append(s.dump(what))
+    gpu = {k: np.array(v) for k, v in gpu.items()}
+    gpu["rec"] = s.records()
+    gpu["est"] = s.estimate(recycled=True)
+    s.close()
+    cfg = O.config_from_workload(w)
+    ref = O.smc2_run(cfg, y, nx, seed, N, K, dumps=True)
+    return gpu, ref
+
+
+CASES = [  # workload, overrides, N, K, nx, filter schedule
+    ("sir_fp64", dict(T=30), 64, 5, 64, G.SCHED_AUTO),
+    ("seir", dict(T=40, lkernel=G.L_FORWARD), 256, 4, 128, G.SCHED_AUTO),
+    ("seir", dict(T=40), 256, 4, 96, G.SCHED_POOLED),
+    ("seir_learned", dict(T=30, prec=G.PREC_FP64), 128, 4, 96, G.SCHED_PER_DRAW),
+    ("age_seir", dict(T=12), 48, 3, 64, G.SCHED_AUTO),
+]
+
+
+@pytest.mark.parametrize("name,over,N,K,nx,sched", CASES)
+def test_population_walk_matches_reference(name, over, N, K, nx, sched):
+    w = dict(W.preset(name), proposal=G.PROP_RW_POP, **over)
+    _log("population random walk %s %s N=%d K=%d nx=%d schedule=%d" % (name, over, N, K, nx, sched))
+    gpu, ref = _run_pair(w, N, K, nx, sched)
+    tol_ll = 1e-9 if w["prec"] == G.PREC_FP64 else 1e-4
+    _compare(gpu, ref, w["D"], tol_ll)
+    assert np.all(gpu["rec"][1:, -2] == 3) and gpu["rec"][0, -2] == 0
+    # log q of each proposal from its definition, at the population it was proposed from
+    for k in range(1, K):
+        pop, lw = gpu["pop"][k], gpu["pop_logw"][k]
+        fin = np.isfinite(lw)
+        wn = np.where(fin, np.exp(lw - lw[fin].max()), 0.0)
+        wn /= wn.sum()
+        mu = wn @ pop
+        L = _factor((pop - mu).T @ ((pop - mu) * wn[:, None]), mu)
+        for i in range(0, N, max(1, N // 16)):
+            want = stats.multivariate_normal(pop[i], L @ L.T).logpdf(gpu["phi"][k][i])
+            assert gpu["logq"][k][i] == pytest.approx(want, rel=1e-8, abs=1e-8), (k, i)
+
+
+def test_gpu_population_walk_targets_the_grid_posterior():
+    from tests.test_oracle_mlp import I0, MED, N_POP, SD, _grid_posterior
+    y, grid_mean, grid_sd = _grid_posterior()
+    prior = [[W.PRIOR_LOGNORMAL, np.log(MED[0]), SD], [W.PRIOR_LOGNORMAL, np.log(MED[1]), SD]]
+    w = dict(model=W.SIR, obs=W.OBS_POIS_PREV, D=2, prec=W.PREC_FP64, n_pop=N_POP, fixed=[I0], prior=prior,
+             rw_cov=(0.05 * np.eye(2)).tolist(), lkernel=G.L_GAUSS_OPT, proposal=G.PROP_RW_POP)
+    R = 24
+    runs = [dict(T=y.shape[0], nx=48, seed=s, y=y) for s in range(1, R + 1)]
+    smp = G.Sampler(w, runs, N=1024, K=8)
+    for _ in range(8):
+        smp.step()
+    ests = np.array([smp.estimate(r)[0] for r in range(R)])
+    second = np.array([np.diag(smp.estimate(r)[1]) + smp.estimate(r)[0] ** 2 for r in range(R)])
+    smp.close()
+    se = ests.std(0, ddof=1) / np.sqrt(R)
+    pooled_sd = np.sqrt(second.mean(0) - ests.mean(0) ** 2)
+    _log("GPU population random walk: posterior mean %s (grid %s, s.e. %s), sd %s (grid %s)"
+         % (ests.mean(0), grid_mean, se, pooled_sd, grid_sd))
+    assert np.all(np.abs(ests.mean(0) - grid_mean) < 4 * se + 2e-3)
+    assert np.all(np.abs(pooled_sd / grid_sd - 1) < 0.2)

@@ -9,6 +9,9 @@ plausible mistake planted (tests/planted.py) fail the pin that the reference pas
   reset after resampling) against the Kalman filter: a dropped log S_prev, S_prev not
   updated, no weight reset after resampling, log-weights not re-based on the maximum,
   and ancestors shifted by one slot.
+* The population random walk's proposals and weights against their definitions: the
+  proposal's density dropped from the weight, and the covariance taken without the
+  population's weights.
 * The p-MCMC acceptance (Sec. III, Eq. MHalgorithm_) against the exact grid posterior:
   the prior dropped from the ratio, and the current state's likelihood estimate drawn
   afresh every iteration instead of travelling with the state.
@@ -62,6 +65,15 @@ LANGEVIN_PLANTS = {
                                     "    return or_mvn_logpdf_chol(D, phi_new, phi, L);")],
 }
 
+RW_POP_PLANTS = {
+    # the population random walk weighted with the fixed random walk's density
+    "rw_pop_density_dropped": [("smc2_oracle.c", "(learned || drift) ? lq : NULL",
+                                "(learned || (drift && lgv)) ? lq : NULL")],
+    # the proposal covariance of the population with its weights ignored
+    "rw_pop_unweighted_covariance": [("smc2_oracle.c", "for (int i = 0; i < N; ++i) wn[i] = exp(logw[i] - Wl);",
+                                      "for (int i = 0; i < N; ++i) wn[i] = 1.0 / N;")],
+}
+
 
 PMCMC_PLANTS = {
     "prior_dropped_from_the_ratio": [("smc2_oracle.c", "    const double cur = lp + ll, nw = lp_new + ll_new;",
@@ -77,7 +89,7 @@ PMCMC_PLANTS = {
 @pytest.fixture(scope="module")
 def planted_libs(tmp_path_factory):
     d = str(tmp_path_factory.mktemp("planted"))
-    plants = dict(AGE_PLANTS, **KALMAN_PLANTS, **PMCMC_PLANTS, **SCORE_PLANTS, **LANGEVIN_PLANTS)
+    plants = dict(AGE_PLANTS, **KALMAN_PLANTS, **PMCMC_PLANTS, **SCORE_PLANTS, **LANGEVIN_PLANTS, **RW_POP_PLANTS)
     with cf.ThreadPoolExecutor(max_workers=4) as ex:
         futs = {name: ex.submit(PL.build_planted, name, edits, d) for name, edits in plants.items()}
         return {name: f.result() for name, f in futs.items()}
@@ -125,6 +137,15 @@ def test_langevin_pin_catches_an_inexact_weight(planted_libs, name):
     pooled_sd = np.sqrt(second.mean(0) - ests.mean(0) ** 2)
     print(name, ests.mean(0), grid_mean, se, pooled_sd / grid_sd)
     assert np.any(np.abs(ests.mean(0) - grid_mean) > 4 * se + 2e-3) or np.any(np.abs(pooled_sd / grid_sd - 1) > 0.2)
+
+
+@pytest.mark.parametrize("name", sorted(RW_POP_PLANTS))
+def test_rw_pop_pin_catches_a_wrong_covariance_or_density(planted_libs, name):
+    from tests.test_oracle_rwpop import rw_pop_discrepancies
+    with PL.installed(planted_libs[name]):
+        dphi, dlw, _, _ = rw_pop_discrepancies()
+    print(name, dphi, dlw)
+    assert dphi > 1e-6 or dlw > 1e-6, (name, dphi, dlw)
 
 
 @pytest.mark.parametrize("name", sorted(PMCMC_PLANTS))
