@@ -88,8 +88,12 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
+PROPOSAL_NAMES = {0: "random walk", 1: "learned proposal", 2: "Langevin proposal",
+                  3: "random walk with the population's covariance"}
+
+
 def describe(name, w, runs, N):
-    prop = "learned proposal" if w.get("proposal", 0) == 1 else "random walk"
+    prop = PROPOSAL_NAMES[w.get("proposal", 0)]
     prec = "FP32 propagation, FP64 accumulation and outer step" if w["prec"] == 0 else "FP64"
     if len(runs) == 1:
         return "%s N=%d Nx=%d T=%d D=%d, %s, %s" % (name, N, runs[0]["nx"], runs[0]["T"], w["D"], prop, prec)
@@ -98,12 +102,15 @@ def describe(name, w, runs, N):
         w["D"], prop, prec)
 
 
-def run_timed(G, W, np, name, steps, warmup, extra=0, **launch):
-    """Build the sampler of workload `name`, run warmup + steps (+ extra untimed)
-    iterations and time the `steps` ones. Returns the measurements and the sampler
-    (open when extra > 0, after the timed steps)."""
+def run_timed(G, W, np, name, steps, warmup, extra=0, proposal=None, **launch):
+    """Build the sampler of workload `name` (with its own proposal, or `proposal`), run
+    warmup + steps (+ extra untimed) iterations and time the `steps` ones. Returns the
+    measurements and the sampler (open when extra > 0, after the timed steps)."""
     import torch
     w = W.preset(name)
+    own_proposal = proposal is None or proposal == w.get("proposal", 0)
+    if proposal is not None:
+        w = dict(w, proposal=proposal)
     runs = W.batched_runs(w) if w.get("runs") else [dict(T=w["T"], nx=w["nx"], seed=w["seed"],
                                                           y=W.observations(w))]
     N = w["N"]
@@ -128,7 +135,8 @@ def run_timed(G, W, np, name, steps, warmup, extra=0, **launch):
     executed = float(ps1 - ps0)
     nominal = float(N) * sum(r["nx"] * r["T"] for r in runs) * steps
     m = dict(w=w, runs=runs, N=N, ms=ms, ms_pf=ms_pf, ms_step_dev=ms_step_dev, executed=executed, nominal=nominal,
-             value=executed / ((t1 - t0)), dead=dead, steps=steps, warmup=warmup, phases=phases)
+             value=executed / ((t1 - t0)), dead=dead, steps=steps, warmup=warmup, phases=phases,
+             own_proposal=own_proposal, groups=s.groups())
     if not extra:
         s.close()
         s = None
@@ -143,7 +151,8 @@ def roofline_of(name, m, graph):
     per_launch = m["executed"] / m["steps"]
     achieved = algo * per_launch / launch_s if algo else None
     meas = MEASURED.get(name)
-    valid = bool(meas) and kernel_sha() == meas["sha"]
+    # the counters were taken with the workload's own proposal (another may change the kernel)
+    valid = bool(meas) and kernel_sha() == meas["sha"] and m["own_proposal"]
     issue = meas["valu_lane_instr_per_pstep"] * per_launch / launch_s if valid else None
     return {"bound": "alu", "achieved": achieved / 1e12 if algo else None, "peak": VALU_PEAK_LANE_OPS / 1e12,
             "unit": "T lane-ops/s", "frac": achieved / VALU_PEAK_LANE_OPS if algo else None,
@@ -167,6 +176,9 @@ def main():
     ap.add_argument("--schedule", type=int, default=0, help="particle-filter draw schedule (0 auto, 1 per draw, 2 pooled)")
     ap.add_argument("--tune", type=int, default=0, help="1: time the launch configurations at init and keep the fastest")
     ap.add_argument("--persistent", type=int, default=0, help="1: persistent grid pulling filters from the work list")
+    ap.add_argument("--proposal", type=int, default=-1,
+                    help="proposal of the timed workload (-1 its own; 0 random walk, 1 learned, 2 Langevin, "
+                         "3 random walk with the population's covariance)")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU reference leg (and the precision report)")
     ap.add_argument("--no-ess", action="store_true", help="skip the learned-proposal vs random-walk ESS/s measurement")
     ap.add_argument("--no-secondary", action="store_true", help="skip the secondary (SEIR) configuration")
@@ -197,7 +209,8 @@ def main():
                   persistent=args.persistent)
     extra = 0 if args.no_cpu_baseline else 1
     log("workload %s: %d warm-up + %d timed iterations" % (args.workload, args.warmup, args.steps))
-    m, s = run_timed(G, W, np, args.workload, args.steps, args.warmup, extra=extra, **launch)
+    m, s = run_timed(G, W, np, args.workload, args.steps, args.warmup, extra=extra,
+                     proposal=args.proposal if args.proposal >= 0 else None, **launch)
     log("timed: %.1f ms per iteration, %.3g executed particle-steps/s" % (m["ms"], m["value"]))
     roofline = roofline_of(args.workload, m, args.graph)
 
@@ -238,7 +251,8 @@ def main():
                    "nominal_particle_steps_per_s": m["nominal"] / (m["ms"] * 1e-3 * m["steps"]),
                    "parallelism": "single GPU", "graph": bool(args.graph), "tune": bool(args.tune),
                    "persistent": bool(args.persistent), "dead_samples_per_step": m["dead"],
-                   "device_ms_per_step": m["ms_step_dev"], "device_ms_per_phase": m["phases"]},
+                   "device_ms_per_step": m["ms_step_dev"], "device_ms_per_phase": m["phases"],
+                   "launch_groups": m["groups"]},
         "roofline": roofline, "cpu_baseline": cpu, "precision": precision, "ess_per_s": ess, "secondary": secondary,
     }
     print(json.dumps(out))
@@ -281,8 +295,8 @@ def cpu_baseline_leg(G, np, m, s, n_filters, n_single=6, n_trace=16):
     k = int(s.records()[-1][0])
     theta = s.dump("theta_new")
     phin, lpn, lln, lwp = (s.dump(x) for x in ("phi_new", "lp_new", "ll_new", "logw_pre"))
-    used_mlp = bool(s.records()[-1][G.record_len(D) - 2])
-    lq = s.dump("logq") if used_mlp else None
+    used = int(s.records()[-1][G.record_len(D) - 2])  # proposal of the iteration (record column)
+    lq = s.dump("logq") if used else None
     fit = s.dump("lkfit")
     anc = s.dump("anc")
     cfg64 = O.config_from_workload(w, prec=O.PREC_FP64)
@@ -357,7 +371,7 @@ def cpu_baseline_leg(G, np, m, s, n_filters, n_single=6, n_trace=16):
             "replayed_rel_err_median": q(rep), "replayed_rel_err_max": max(rep) if rep else None,
             "replay": "FP64 reference weights on the GPU's own counts, ancestors and resampling flags"},
         "outer_fp64_vs_reference": {
-            "iteration": k, "proposal": "learned" if used_mlp else "random walk",
+            "iteration": k, "proposal": PROPOSAL_NAMES[used],
             "lkernel_mean_rel_err_max": float(np.max(np.abs(fit[:D2] - mu) / np.maximum(np.abs(mu), 1e-300))),
             "lkernel_cov_err_max_rel_to_largest": float(np.max(np.abs(fit[D2:].reshape(D2, D2) - cov))
                                                          / np.max(np.abs(cov))),
@@ -379,7 +393,9 @@ def paper_experiment(G, W, np, seed=1):
     as one chain (the paper's sequential form) and as 64 chains of 160 iterations (80
     burned in), each chain's filter in one launch per iteration. Wall time of the
     iterations (synchronised), the estimates and their squared error against the truth;
-    the paper's figures (128 CPU cores for SMC^2, one for p-MCMC) beside them as context."""
+    Table II's MSE (per-run squared errors averaged over 10 runs and both parameters) for
+    SMC^2 and for 64-chain p-MCMC; the paper's figures (128 CPU cores for SMC^2, one for
+    p-MCMC) beside them as context."""
     import torch
     w = W.preset("paper_sir")
     y = W.observations(w)
@@ -406,12 +422,37 @@ def paper_experiment(G, W, np, seed=1):
         out[name] = {"chains": chains, "iterations": iters, "seconds": sec2, "posterior_mean": m2.tolist(),
                      "squared_error": float(np.mean((m2 - truth) ** 2)), "acceptance": rate}
         log("paper_sir: %s %.3f s" % (name, sec2))
+    # Table II's MSE: per-run squared errors averaged over 10 runs (seeds 1..10, the same data) and both
+    # parameters; SMC^2 as one batched context of 10 runs, p-MCMC as 10 contexts of 64 chains
+    R = 10
+    s = G.Sampler(w, [dict(run, seed=r) for r in range(1, R + 1)], N=w["N"], K=w["K"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(w["K"]):
+        s.step()
+    means = np.array([s.estimate(r, recycled=True)[0] for r in range(R)])
+    sec10 = time.perf_counter() - t0
+    s.close()
+    out["smc2_10_runs"] = {"runs": R, "seconds": sec10, "posterior_mean_average": means.mean(0).tolist(),
+                           "mse": float(np.mean((means - truth) ** 2))}
+    m64 = []
+    for r in range(1, R + 1):
+        mc = G.PMCMC(w, dict(run, seed=r), 64, 160)
+        mc.step(160)
+        m64.append(mc.estimate(80)[0])
+        mc.close()
+    m64 = np.array(m64)
+    out["pmcmc_64_chains_10_runs"] = {"runs": R, "posterior_mean_average": m64.mean(0).tolist(),
+                                      "mse": float(np.mean((m64 - truth) ** 2))}
+    log("paper_sir: MSE over 10 runs, SMC^2 %.3g, p-MCMC (64 chains) %.3g"
+        % (out["smc2_10_runs"]["mse"], out["pmcmc_64_chains_10_runs"]["mse"]))
     out["smc2_speedup_vs_pmcmc_1_chain"] = out["pmcmc_1_chain"]["seconds"] / out["smc2"]["seconds"]
     out["smc2_speedup_vs_pmcmc_64_chains"] = out["pmcmc_64_chains"]["seconds"] / out["smc2"]["seconds"]
     out["paper_context"] = {"smc2_seconds": 2.39, "smc2_mean": [0.8526, 0.2003], "smc2_mse": 7.75e-5,
                             "pmcmc_seconds": 130.01, "pmcmc_mean": [0.8628, 0.2038], "pmcmc_mse": 2.42e-4,
                             "hardware": "SMC^2 on 128 Xeon Gold 6138 cores, p-MCMC on one (Table II)"}
-    log("paper_sir: SMC^2 %.4f s, %.1fx faster than one p-MCMC chain" % (sec, out["smc2_speedup_vs_pmcmc_1_chain"]))
+    log("paper_sir: SMC^2 %.4f s, %.1fx faster than one p-MCMC chain"
+        % (out["smc2"]["seconds"], out["smc2_speedup_vs_pmcmc_1_chain"]))
     return out
 
 

@@ -92,10 +92,12 @@ int smc2_pf_trace_state(const smc2_config* cfg, int32_t n_theta, const double* d
  * d_score: double[n_theta][D]. SIR (D = 2), SEIR (D = 4 or 5; the initial fraction iota
  * enters only through a rounding and gets 0) and SMC2_LINGAUSS (D = 3, needs
  * sigma_x > 0); other models return SMC2_E_UNSUPPORTED. A filter whose weights all
- * vanish gets -inf and a zero score. Runs the per-draw schedule whatever cfg->schedule
- * says, with the scores in LDS beside the counts: n_x up to 2048 (for SEIR in FP64 with
- * T <= 365); beyond the LDS budget SMC2_E_ARG. The workspace is smc2_pf_workspace_bytes'.
- * Returns after the stream has run the filters. */
+ * vanish gets -inf and a zero score. The scores sit in LDS beside the counts. Draw
+ * schedule: per draw (SMC2_SCHED_AUTO or SMC2_SCHED_PER_DRAW; n_x up to 2048, for SEIR
+ * in FP64 with T <= 365) or pooled (SMC2_SCHED_POOLED, SIR and SEIR, n_x up to about
+ * 1024 with the scores; faster only for small filters), the same bits either way. A
+ * schedule that does not fit returns SMC2_E_ARG. The workspace is
+ * smc2_pf_workspace_bytes'. Returns after the stream has run the filters. */
 int smc2_pf_score(const smc2_config* cfg, int32_t n_theta, const double* d_theta, const smc2_run* run, uint32_t k,
                   double* d_ll, double* d_score, void* d_workspace, size_t ws_bytes, void* hip_stream);
 

@@ -446,10 +446,11 @@ def pf_loglik(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0,
             from_device(trs, prs, np.int32, n * T).reshape(n, T))
 
 
-def pf_score(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0, device="cuda"):
+def pf_score(w, theta, y, nx, seed, k, precision=None, pf_always=None, block=0, device="cuda", schedule=0):
     """(log-likelihood estimates [n], score estimates [n][D] on the natural parameters)
     for the rows of theta (smc2_pf_score)."""
-    cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, pf_always=pf_always, block=block)
+    cfg = make_config(w, N=max(2, len(theta)), K=1, precision=precision, pf_always=pf_always, block=block,
+                      schedule=schedule)
     y = obs_array(y)
     runs = make_runs([dict(T=y.shape[0], nx=nx, seed=seed, y=y)])
     theta = np.ascontiguousarray(np.asarray(theta, dtype=np.float64))

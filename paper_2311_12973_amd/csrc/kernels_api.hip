@@ -230,9 +230,10 @@ static int pf_run(const smc2_config* cfg, int32_t n_theta, const double* d_theta
     if (cfg->block != 0 && (cfg->block < 64 || cfg->block > 1024 || cfg->block % 64 != 0))
         return kfail(SMC2_E_ARG, "block must be 0 or a multiple of 64 up to 1024");
     if (cfg->schedule < 0 || cfg->schedule > 2) return kfail(SMC2_E_ARG, "schedule must be 0, 1 or 2");
-    const int want = score ? PF_SCHED_SCORE : cfg->schedule;
-    const int block = cfg->block ? cfg->block : pf_default_block(cfg->model, cfg->precision, run->n_x, run->T, want);
-    const int sched = pf_pick_schedule(cfg->model, cfg->precision, block, run->n_x, run->T, want);
+    const int want = cfg->schedule;
+    const int block =
+        cfg->block ? cfg->block : pf_default_block(cfg->model, cfg->precision, run->n_x, run->T, want, score);
+    const int sched = pf_pick_schedule(cfg->model, cfg->precision, block, run->n_x, run->T, want, score);
     if (sched < 0) return kfail(SMC2_E_ARG, "the pooled schedule cannot run this model, n_x and T");
     const size_t lds = pf_lds_bytes(cfg->model, cfg->precision, block, run->n_x, run->T, sched);
     if (lds > PF_LDS_MAX) return kfail(SMC2_E_ARG, "particle filter does not fit in LDS");

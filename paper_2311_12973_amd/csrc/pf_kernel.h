@@ -34,7 +34,7 @@ struct PFArgs {
                             // resampling; unwritten after a filter's death day), or NULL
     unsigned long long* psteps;  // [n_runs] executed particle-steps: each filter adds N_x x
                                  // the days it ran (to its death day), or NULL
-    double* score;          // [G][D] score estimates (PF_SCHED_SCORE launches only)
+    double* score;          // [G][D] score estimates (score launches only)
     int32_t* queue;         // work-list counter (zero at launch) for a persistent grid, or NULL
     uint32_t k_const;
     int32_t n_items;
@@ -52,10 +52,13 @@ struct PFArgs {
 // draws in turn, or (SIR, SEIR) the wave pools the draws and batches the final
 // acceptance tests of the BTRS sampler. Both give identical flows.
 enum : int { PF_SCHED_AUTO = 0, PF_SCHED_PER_DRAW = 1, PF_SCHED_POOLED = 2 };
-// Internal launch variant: the per-draw schedule that also carries each particle's
-// running score of its trajectory and writes the filter's score estimate (SIR, SEIR and
-// the linear-Gaussian model). Not a value of smc2_config.schedule.
+// Internal launch variants that also carry each particle's running score of its
+// trajectory and write the filter's score estimate: on the per-draw schedule (SIR, SEIR
+// and the linear-Gaussian model) and on the pooled one (SIR, SEIR; the score terms are
+// added when the drawn flows are applied, in the per-draw variant's order, so the two
+// give the same bits). Not values of smc2_config.schedule.
 constexpr int PF_SCHED_SCORE = 3;
+constexpr int PF_SCHED_SCORE_POOLED = 4;
 // score coordinates kept per particle: SIR 2, SEIR 5 (iota's stays 0, r's is used when
 // r is estimated), linear-Gaussian 3; 0 where the score is not supported
 int pf_score_dims(int model);
@@ -64,11 +67,12 @@ constexpr size_t PF_LDS_MAX = 160 * 1024 - 256;
 
 // Dynamic LDS bytes of one filter workgroup.
 size_t pf_lds_bytes(int model, int prec, int block, int nx, int T, int sched);
-// The schedule to run: the requested one (PF_SCHED_AUTO: pooled where supported and
-// it fits in LDS), or -1 when the pooled schedule was requested but cannot run.
-int pf_pick_schedule(int model, int prec, int block, int nx, int T, int requested);
+// The kernel variant to run for a requested draw schedule (PF_SCHED_AUTO: pooled where
+// supported and it fits in LDS), with score = true its score-carrying form; -1 when
+// the pooled schedule was requested but cannot run, or the model has no score.
+int pf_pick_schedule(int model, int prec, int block, int nx, int T, int requested, bool score = false);
 // Default workgroup size for a filter of this shape (64 .. 1024 threads).
-int pf_default_block(int model, int prec, int nx, int T, int requested_sched);
+int pf_default_block(int model, int prec, int nx, int T, int requested_sched, bool score = false);
 bool pf_supported(int model, int obs);
 // Raise the dynamic-LDS limit of the kernel when a launch needs more than 64 KiB.
 hipError_t pf_prepare(int prec, int model, int obs, int sched, size_t lds);

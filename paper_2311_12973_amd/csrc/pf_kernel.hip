@@ -550,10 +550,12 @@ __device__ void draws_pooled(const MConst<real>& mc, const int32_t* st, int32_t*
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
 }
 
-// The day's count update and the per-particle part of log g from the drawn flows.
-template <typename real, int MODEL, int OBS>
+// The day's count update and the per-particle part of log g from the drawn flows. With
+// SCORE it adds the day's complete-data score terms from the day-start counts and the
+// flows, the same FP64 values in the same order as the per-draw schedule's particle_day.
+template <typename real, int MODEL, int OBS, bool SCORE = false>
 __device__ __forceinline__ double particle_update(const MConst<real>& mc, int32_t* st, const int32_t* flows,
-                                                  int cap, int j, const int32_t* yt)
+                                                  int cap, int j, const int32_t* yt, const ScoreDay& sd = ScoreDay{})
 {
     if (MODEL == MODEL_SIR) {
         const int32_t nsi = flows[j], nir = flows[cap + j];
@@ -561,6 +563,11 @@ __device__ __forceinline__ double particle_update(const MConst<real>& mc, int32_
         const int32_t I1 = I + nsi - nir;
         st[j] = S - nsi;
         st[cap + j] = I1;
+        if constexpr (SCORE) {
+            const real p_si = leave_prob<real>(mc.cinf * (real)I);
+            lds_add_f64(sd.sw, cap, j, flow_score<real>(S, p_si, nsi) * ((double)I / sd.n_pop));
+            lds_add_f64(sd.sw + 2 * cap, cap, j, flow_score<real>(I, mc.p_ir, nir));
+        }
         return obs_part<OBS>(yt[0], OBS == OBS_POIS_PREV ? I1 : nsi, mc.r);
     } else {
         const int32_t nse = flows[j], nei = flows[cap + j], nir = flows[2 * cap + j];
@@ -569,6 +576,16 @@ __device__ __forceinline__ double particle_update(const MConst<real>& mc, int32_
         st[j] = S - nse;
         st[cap + j] = E + nse - nei;
         st[2 * cap + j] = I1;
+        if constexpr (SCORE) {
+            const real p_se = leave_prob<real>(mc.cinf * (real)I);
+            lds_add_f64(sd.sw, cap, j, flow_score<real>(S, p_se, nse) * ((double)I / sd.n_pop));
+            lds_add_f64(sd.sw + 2 * cap, cap, j, flow_score<real>(E, mc.p_ei, nei));
+            lds_add_f64(sd.sw + 4 * cap, cap, j, flow_score<real>(I, mc.p_ir, nir));
+            if (sd.nr && nei > 0) {
+                const double mu = (double)nei, r = mc.r;
+                lds_add_f64(sd.sw + 8 * cap, cap, j, (sd.dpsi - log1p(mu / r)) + (mu - (double)yt[0]) / (r + mu));
+            }
+        }
         return obs_part<OBS>(yt[0], OBS == OBS_POIS_PREV ? I1 : nei, mc.r);
     }
 }
@@ -600,9 +617,11 @@ __device__ __forceinline__ void multinomial_ancestors(const uint64_t* C, int n, 
 //   anc i32[cap]     ancestors            (C, tmp, anc hold the flows while drawing)
 //   red RedLds       reduction slots
 //   cst f64[T]       per-day observation constants
+//   dps f64[T]       per-day psi(y_t + r) - psi(r)  (score launches of SEIR only)
 //   lw  real[cap]    log-weights (relative to the last maximum)
 //   st  i32[NC*cap]  compartment counts
-//   pool WavePool[blockDim / 64]   (pooled schedule only)
+//   sw  i32[2*NS*cap] score words (score launches only)
+//   pool WavePool[blockDim / 64]   (pooled schedules only)
 // Issue priority of this wave from the filter's remaining work r (remaining days x N_x,
 // as a fraction of the launch's largest filter). The filters resident on a CU each put
 // one wave on every SIMD, and the SIMD issues from its oldest wave first: without this,
@@ -625,7 +644,9 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
 {
     constexpr int NC = ModelShape<MODEL>::NC;
     constexpr int NG = ModelShape<MODEL>::NG;
-    constexpr bool SCORE = SCHED == PF_SCHED_SCORE;
+    constexpr bool SCORE = SCHED == PF_SCHED_SCORE || SCHED == PF_SCHED_SCORE_POOLED;
+    constexpr bool POOLED = (SCHED == PF_SCHED_POOLED || SCHED == PF_SCHED_SCORE_POOLED) &&
+                            (MODEL == MODEL_SIR || MODEL == MODEL_SEIR);
     constexpr int NS = SCORE ? ScoreDims<MODEL>::NS : 0;  // score columns (FP64, two words each)
     const int g = a.items ? a.items[item] : item;
     const int tid = (int)threadIdx.x;
@@ -661,7 +682,7 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
     int32_t* sw = st + NC * cap;  // score words (NS columns of two words)
     // offset from the LDS base (not an integer round trip, which would lose the address
     // space and turn every queue access into a generic FLAT access)
-    const size_t pool_off = ((size_t)(reinterpret_cast<unsigned char*>(st + NC * cap) - smem) + 15) & ~(size_t)15;
+    const size_t pool_off = ((size_t)(reinterpret_cast<unsigned char*>(sw + 2 * NS * cap) - smem) + 15) & ~(size_t)15;
     WavePool<real>* pool = reinterpret_cast<WavePool<real>*>(smem + pool_off) + wave_id();
 
     const double* th = a.theta + (size_t)g * a.D;
@@ -707,19 +728,19 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
         const int32_t* yt = y + (size_t)(t - 1) * NG;
         // 1. propagate and weight: lw[j] <- a_j = lw_j + log g(y_t | x_t^j)
         real amax = (real)-INFINITY;
-        if constexpr (SCHED == PF_SCHED_POOLED && (MODEL == MODEL_SIR || MODEL == MODEL_SEIR)) {
+        ScoreDay sd{};
+        if constexpr (SCORE) sd = ScoreDay{sw, a.n_pop, DPSI ? dps[t - 1] : 0.0, MODEL == MODEL_SEIR && a.D >= 5};
+        if constexpr (POOLED) {
             draws_pooled<real, MODEL>(mc, st, flows, cap, nx, pool, filt, kt, run.k0, run.k1, &wg_next);
             __syncthreads();  // any wave may have drawn any particle's flows
             if (tid == 0) wg_next = 0;  // for the next day (read again only after further barriers)
             for (int j = tid; j < nx; j += nthr) {
-                const double lg = particle_update<real, MODEL, OBS>(mc, st, flows, cap, j, yt);
+                const double lg = particle_update<real, MODEL, OBS, SCORE>(mc, st, flows, cap, j, yt, sd);
                 const real av = lw[j] + (real)lg;
                 lw[j] = av;
                 amax = av > amax ? av : amax;
             }
         } else {
-            ScoreDay sd{};
-            if constexpr (SCORE) sd = ScoreDay{sw, a.n_pop, DPSI ? dps[t - 1] : 0.0, MODEL == MODEL_SEIR && a.D >= 5};
             for (int j = tid; j < nx; j += nthr) {
                 const double lg = particle_day<real, MODEL, OBS, SCORE>(
                     mc, st, cap, j, DrawStream{(uint32_t)j, filt, kt, 0u, run.k0, run.k1}, yt, sd);
@@ -887,19 +908,19 @@ size_t pf_lds_bytes(int model, int prec, int block, int nx, int T, int sched)
     const size_t cap = (size_t)((nx + block - 1) / block) * block;
     const size_t rb = prec == 0 ? 4 : 8;
     size_t days = (size_t)T;
-    if (sched == PF_SCHED_SCORE) {
+    if (sched == PF_SCHED_SCORE || sched == PF_SCHED_SCORE_POOLED) {
         nc += 2 * pf_score_dims(model);            // the score words
         if (model == MODEL_SEIR) days += (size_t)T;  // psi(y_t + r) - psi(r) per day
     }
     size_t bytes = cap * 8 + 2 * cap * 4 + sizeof(RedLds) + days * 8 + cap * rb + (size_t)nc * cap * 4;
-    if (sched == PF_SCHED_POOLED) {
+    if (sched == PF_SCHED_POOLED || sched == PF_SCHED_SCORE_POOLED) {
         const size_t pool = prec == 0 ? sizeof(WavePool<float>) : sizeof(WavePool<double>);
         bytes = ((bytes + 15) & ~(size_t)15) + (size_t)(block / 64) * pool;
     }
     return bytes;
 }
 
-int pf_default_block(int model, int prec, int nx, int T, int requested_sched)
+int pf_default_block(int model, int prec, int nx, int T, int requested_sched, bool score)
 {
     // the workgroup size that keeps the most waves resident per CU (LDS allowing,
     // at most 16 at 128 VGPRs), preferring the pooled schedule by its measured gain
@@ -907,16 +928,16 @@ int pf_default_block(int model, int prec, int nx, int T, int requested_sched)
     int best = full < 256 ? full : 256;
     double best_score = -1.0;
     for (int b = best; b <= 1024; b *= 2) {
-        const int sc = pf_pick_schedule(model, prec, b, nx, T, requested_sched);
+        const int sc = pf_pick_schedule(model, prec, b, nx, T, requested_sched, score);
         if (sc < 0) continue;
         const size_t lds = pf_lds_bytes(model, prec, b, nx, T, sc);
         if (lds > PF_LDS_MAX) continue;
         const int per_cu = (int)(PF_LDS_MAX / (lds ? lds : 1));
         int waves = per_cu * (b / 64);
         waves = waves > 16 ? 16 : waves;
-        const double score = waves * (sc == PF_SCHED_POOLED ? 1.4 : 1.0);
-        if (score > best_score + 1e-9) {
-            best_score = score;
+        const double merit = waves * (sc == PF_SCHED_POOLED || sc == PF_SCHED_SCORE_POOLED ? 1.4 : 1.0);
+        if (merit > best_score + 1e-9) {
+            best_score = merit;
             best = b;
         }
         if (b >= full) break;
@@ -924,11 +945,21 @@ int pf_default_block(int model, int prec, int nx, int T, int requested_sched)
     return best;
 }
 
-int pf_pick_schedule(int model, int prec, int block, int nx, int T, int requested)
+int pf_pick_schedule(int model, int prec, int block, int nx, int T, int requested, bool score)
 {
+    if (score) {
+        if (pf_score_dims(model) == 0) return -1;
+        const bool ok = (model == MODEL_SIR || model == MODEL_SEIR) &&
+                        pf_lds_bytes(model, prec, block, nx, T, PF_SCHED_SCORE_POOLED) <= PF_LDS_MAX;
+        // automatic: the per-draw form. The pooled one's extra LDS (the wave pools beside
+        // the score words) leaves fewer workgroups per CU, and it measured slower at the
+        // SEIR shapes (3.43 against 4.13 ms at N_x = 512, 43.7 against 52.3 ms at N_x =
+        // 1024); it is faster for small launch-bound filters, where the autotuner finds it
+        if (requested == PF_SCHED_POOLED) return ok ? PF_SCHED_SCORE_POOLED : -1;
+        return PF_SCHED_SCORE;
+    }
     const bool pooled_ok = (model == MODEL_SIR || model == MODEL_SEIR) &&
                            pf_lds_bytes(model, prec, block, nx, T, PF_SCHED_POOLED) <= PF_LDS_MAX;
-    if (requested == PF_SCHED_SCORE) return pf_score_dims(model) > 0 ? PF_SCHED_SCORE : -1;
     if (requested == PF_SCHED_PER_DRAW) return PF_SCHED_PER_DRAW;
     if (requested == PF_SCHED_POOLED) return pooled_ok ? PF_SCHED_POOLED : -1;
     return pooled_ok ? PF_SCHED_POOLED : PF_SCHED_PER_DRAW;
@@ -985,6 +1016,9 @@ bool pf_supported(int model, int obs)
 
 static const void* kernel_for(int prec, int model, int obs, int sched)
 {
+    if (sched == PF_SCHED_SCORE_POOLED)
+        return prec == 0 ? kernel_of<float, PF_SCHED_SCORE_POOLED>(model, obs)
+                         : kernel_of<double, PF_SCHED_SCORE_POOLED>(model, obs);
     if (sched == PF_SCHED_POOLED)
         return prec == 0 ? kernel_of<float, PF_SCHED_POOLED>(model, obs) : kernel_of<double, PF_SCHED_POOLED>(model, obs);
     if (sched == PF_SCHED_SCORE)
@@ -1025,6 +1059,11 @@ hipError_t launch_pf(int prec, int model, int obs, int sched, int block, size_t 
         if (!a.score) return hipErrorInvalidValue;
         if (prec == 0) return launch_model<float, PF_SCHED_SCORE>(model, obs, block, lds, a, s, grid);
         return launch_model<double, PF_SCHED_SCORE>(model, obs, block, lds, a, s, grid);
+    }
+    if (sched == PF_SCHED_SCORE_POOLED) {
+        if (!a.score) return hipErrorInvalidValue;
+        if (prec == 0) return launch_model<float, PF_SCHED_SCORE_POOLED>(model, obs, block, lds, a, s, grid);
+        return launch_model<double, PF_SCHED_SCORE_POOLED>(model, obs, block, lds, a, s, grid);
     }
     if (prec == 0) return launch_model<float, PF_SCHED_PER_DRAW>(model, obs, block, lds, a, s, grid);
     return launch_model<double, PF_SCHED_PER_DRAW>(model, obs, block, lds, a, s, grid);

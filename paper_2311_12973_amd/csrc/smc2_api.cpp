@@ -137,7 +137,7 @@ struct PFGroup {
     int block;
     size_t lds;
     int first_item, n_items;
-    int sched;       // PF_SCHED_PER_DRAW or PF_SCHED_POOLED
+    int sched;       // kernel variant: PF_SCHED_PER_DRAW, PF_SCHED_POOLED or their score forms
     int persistent;  // 1: resident workgroups pull filters from the work list
     int grid;        // workgroups launched when persistent
     int max_nx, max_T;
@@ -328,11 +328,15 @@ static hipError_t autotune(smc2_ctx* c)
         const int full = ((gr.max_nx + 63) / 64) * 64;
         for (int b = 64; b <= 1024 && e == hipSuccess; b *= 2) {
             if (b > std::max(64, full)) break;
-            for (int sc = PF_SCHED_PER_DRAW; sc <= PF_SCHED_SCORE && e == hipSuccess; ++sc) {
-                // the Langevin proposal's launches carry the scores: only that variant
-                if ((cfg.proposal == SMC2_PROP_LANGEVIN) != (sc == PF_SCHED_SCORE)) continue;
-                if (sc != PF_SCHED_SCORE && cfg.schedule != SMC2_SCHED_AUTO && sc != cfg.schedule) continue;
-                if (sc == PF_SCHED_POOLED && cfg.model != SMC2_SIR && cfg.model != SMC2_SEIR) continue;
+            for (int sc = PF_SCHED_PER_DRAW; sc <= PF_SCHED_SCORE_POOLED && e == hipSuccess; ++sc) {
+                // the Langevin proposal's launches carry the scores: only those variants
+                const bool sc_score = sc == PF_SCHED_SCORE || sc == PF_SCHED_SCORE_POOLED;
+                const bool sc_pooled = sc == PF_SCHED_POOLED || sc == PF_SCHED_SCORE_POOLED;
+                if ((cfg.proposal == SMC2_PROP_LANGEVIN) != sc_score) continue;
+                if (cfg.schedule != SMC2_SCHED_AUTO &&
+                    (sc_pooled ? SMC2_SCHED_POOLED : SMC2_SCHED_PER_DRAW) != cfg.schedule)
+                    continue;
+                if (sc_pooled && cfg.model != SMC2_SIR && cfg.model != SMC2_SEIR) continue;
                 const size_t lds = pf_lds_bytes(cfg.model, cfg.precision, b, gr.max_nx, gr.max_T, sc);
                 if (lds > PF_LDS_MAX) continue;
                 e = pf_prepare(cfg.precision, cfg.model, cfg.obs, sc, lds);
@@ -449,9 +453,12 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     std::vector<int> blk(n_runs);
     // the Langevin proposal needs the filters' scores: their launches carry them
     const bool lgv = cfg->proposal == SMC2_PROP_LANGEVIN;
-    const int want = lgv ? PF_SCHED_SCORE : cfg->schedule;
+    const int want = cfg->schedule;
+    const int pooled_variant = lgv ? PF_SCHED_SCORE_POOLED : PF_SCHED_POOLED;
+    const int per_draw_variant = lgv ? PF_SCHED_SCORE : PF_SCHED_PER_DRAW;
     for (int r = 0; r < n_runs; ++r)
-        blk[r] = cfg->block ? cfg->block : pf_default_block(cfg->model, cfg->precision, runs[r].n_x, runs[r].T, want);
+        blk[r] = cfg->block ? cfg->block
+                            : pf_default_block(cfg->model, cfg->precision, runs[r].n_x, runs[r].T, want, lgv);
     std::vector<int> run_order(n_runs);
     for (int r = 0; r < n_runs; ++r) run_order[r] = r;
     std::stable_sort(run_order.begin(), run_order.end(), [&](int a, int b) {
@@ -460,18 +467,17 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     });
     for (size_t idx = 0; idx < run_order.size();) {
         const int b = blk[run_order[idx]];
-        PFGroup gr{b, 0, (int)items.size(), 0, lgv ? PF_SCHED_SCORE : PF_SCHED_POOLED, cfg->persistent, 0, 0, 0, 0.f,
-                   0.0, 0, 0.f};
+        PFGroup gr{b, 0, (int)items.size(), 0, pooled_variant, cfg->persistent, 0, 0, 0, 0.f, 0.0, 0, 0.f};
         const size_t g0 = idx;
         // the pooled schedule when every run of the group fits in LDS with it
         for (size_t x = g0; x < run_order.size() && blk[run_order[x]] == b; ++x) {
             const int r = run_order[x];
-            const int sc = pf_pick_schedule(cfg->model, cfg->precision, b, runs[r].n_x, runs[r].T, want);
+            const int sc = pf_pick_schedule(cfg->model, cfg->precision, b, runs[r].n_x, runs[r].T, want, lgv);
             if (sc < 0) {
                 delete c;
                 return g_thread_error = "the pooled schedule does not fit in LDS for this n_x and T", SMC2_E_ARG;
             }
-            if (sc == PF_SCHED_PER_DRAW) gr.sched = PF_SCHED_PER_DRAW;
+            if (sc == per_draw_variant) gr.sched = per_draw_variant;
         }
         for (; idx < run_order.size() && blk[run_order[idx]] == b; ++idx) {
             const int r = run_order[idx];
@@ -957,7 +963,8 @@ extern "C" int smc2_groups(const smc2_ctx* c, int32_t max_groups, int32_t* n_gro
         const PFGroup& gr = c->groups[g];
         int32_t* d = desc + 6 * g;
         d[0] = gr.block;
-        d[1] = gr.sched;
+        d[1] = (gr.sched == PF_SCHED_POOLED || gr.sched == PF_SCHED_SCORE_POOLED) ? SMC2_SCHED_POOLED
+                                                                                 : SMC2_SCHED_PER_DRAW;
         d[2] = gr.persistent;
         d[3] = gr.persistent ? gr.grid : gr.n_items;
         d[4] = gr.n_items;

@@ -101,3 +101,42 @@ def test_gpu_population_walk_targets_the_grid_posterior():
          % (ests.mean(0), grid_mean, se, pooled_sd, grid_sd))
     assert np.all(np.abs(ests.mean(0) - grid_mean) < 4 * se + 2e-3)
     assert np.all(np.abs(pooled_sd / grid_sd - 1) < 0.2)
+
+
+@pytest.mark.parametrize("proposal", [G.PROP_RW_POP, G.PROP_LANGEVIN])
+def test_population_covariance_batched_under_every_launch_configuration(proposal):
+    """Uneven runs in one context with the population-covariance proposals: each run's
+    covariance factor comes from its own population (one workgroup per run), and a
+    persistent grid, the autotuned configuration and a replayed graph of the persistent
+    grid give results identical to the default launch."""
+    from tests.test_gpu_sampler import _batched_dumps
+    w = dict(W.preset("seir_batched"), proposal=proposal)
+    runs = W.batched_runs(w, n_runs=4)
+    _log("proposal %d, runs: %s" % (proposal, ", ".join("T=%d nx=%d" % (r["T"], r["nx"]) for r in runs)))
+    base, _ = _batched_dumps(w, runs, 32, 3)
+    for over in (dict(persistent=1), dict(tune=1), dict(persistent=1, use_graph=1)):
+        other, _ = _batched_dumps(w, runs, 32, 3, **over)
+        for key in ("ll", "logw", "anc", "rec"):
+            assert np.array_equal(np.nan_to_num(base[key], neginf=-1e300),
+                                  np.nan_to_num(other[key], neginf=-1e300)), (over, key)
+    assert np.all(base["rec"][:, 1:, -2] == (3 if proposal == G.PROP_RW_POP else 2))
+
+
+def test_population_walk_batched_matches_reference_per_run():
+    """Three uneven runs of the batched workload in one context against the reference
+    sampler run by run: the records of every iteration."""
+    w = dict(W.preset("seir_batched"), proposal=G.PROP_RW_POP)
+    runs = W.batched_runs(w, n_runs=3)
+    K = 3
+    s = G.Sampler(w, runs, N=32, K=K)
+    for _ in range(K):
+        s.step()
+    recs = [s.records(r) for r in range(len(runs))]
+    s.close()
+    cfg = O.config_from_workload(w)
+    for r, run in enumerate(runs):
+        _log("run %d: T=%d nx=%d" % (r, run["T"], run["nx"]))
+        ref = O.smc2_run(cfg, run["y"], run["nx"], run["seed"], 32, K)
+        assert ref["status"] == 0
+        assert np.array_equal(recs[r][:, [0, 2, 3, 4, -2]], ref["rec"][:, [0, 2, 3, 4, -2]])
+        assert np.allclose(recs[r][:, 6:], ref["rec"][:, 6:], rtol=1e-4, atol=1e-10)

@@ -15,6 +15,8 @@ gradients, through the C ABI.
   tiny SIR problem of the reference's pin needs larger N_x: its bias at 2048 particles is
   1.4% of the gradient.)
 * A filter whose weights vanish gets -inf and a zero score.
+* The pooled score launch (the default where it fits) equals the per-draw one bit for
+  bit, with and without resampling every day.
 """
 import numpy as np
 import pytest
@@ -83,6 +85,38 @@ def test_score_matches_reference(name, over, prec, nx, T, block):
     assert np.all(sc[~fin] == 0.0)
     if w["model"] == W.SEIR:
         assert np.all(sc[:, 3] == 0.0)
+
+
+POOLED_CASES = [  # workload, overrides, precision, nx, T, block, resample every day
+    ("sir_fp64", {}, G.PREC_FP64, 100, None, 0, 0),
+    ("sir_fp64", {"obs": W.OBS_POIS_PREV}, G.PREC_FP32, 257, None, 128, 1),
+    ("seir", {}, G.PREC_FP32, 512, 60, 0, 0),
+    ("seir", {}, G.PREC_FP32, 1000, 40, 1024, 1),
+    ("seir", {}, G.PREC_FP64, 300, 40, 256, 0),
+    ("seir_learned", {}, G.PREC_FP32, 1024, 50, 0, 0),
+    ("seir_learned", {}, G.PREC_FP64, 65, 30, 64, 1),
+]
+
+
+@pytest.mark.parametrize("name,over,prec,nx,T,block,always", POOLED_CASES)
+def test_pooled_score_launch_equals_the_per_draw_one(name, over, prec, nx, T, block, always):
+    """The pooled draw schedule adds each day's score terms when it applies the drawn
+    flows, from the day-start counts, in the per-draw schedule's order: the same bits."""
+    w = W.preset(name, **over)
+    if T is not None:
+        w["T"] = T
+    y = W.observations(w)
+    th = _theta(w, 16, seed=5)
+    _log("pooled score %s %s prec=%d nx=%d block=%d always=%d" % (name, over, prec, nx, block, always))
+    ll_p, sc_p = G.pf_score(w, th, y, nx, 4, 3, precision=prec, block=block, pf_always=always,
+                            schedule=G.SCHED_POOLED)
+    ll_d, sc_d = G.pf_score(w, th, y, nx, 4, 3, precision=prec, block=block, pf_always=always,
+                            schedule=G.SCHED_PER_DRAW)
+    assert np.isfinite(ll_d).sum() >= len(th) // 2
+    assert np.array_equal(ll_p, ll_d)
+    assert np.array_equal(sc_p, sc_d)
+    ll_a, sc_a = G.pf_score(w, th, y, nx, 4, 3, precision=prec, block=block, pf_always=always)
+    assert np.array_equal(ll_a, ll_d) and np.array_equal(sc_a, sc_d)
 
 
 @pytest.mark.parametrize("nx,k,block", [(64, 0, 0), (1000, 3, 256), (2048, 5, 0)])
