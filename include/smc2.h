@@ -10,7 +10,8 @@
  *     likelihood estimate as the mean unnormalised weight, ESS-triggered resampling
  *     with the mean-weight reset).
  *   - The outer SMC sampler (Sec. IV) draws theta_1 from the prior (Eq. init_sample),
- *     moves theta with a Gaussian random walk (Eq. proposal), weights with an
+ *     moves theta with a Gaussian random walk (Eq. proposal) or one of the other
+ *     proposals below (Sec. IV-A leaves q free), weights with an
  *     L-kernel (Eq. l_weights; forward kernel, Eq. aimplified_l_weights, or the
  *     approximately optimal Gaussian kernel, Eq. Gauss_joint and the conditional that
  *     follows), normalises (Eq. normalise_smc2), estimates (Eq. realised_estimates),
@@ -89,12 +90,18 @@ extern "C" {
 /* L-kernel of Eq. l_weights. Whenever the Gaussian fit is not used (SMC2_L_FORWARD, or
  * a rejected fit, reported in the record) L(phi_{k-1} | phi_k) = N(phi_{k-1}; phi_k,
  * Sigma_RW): for the random walk this is the forward proposal of Sec. IV-D and the
- * weight is the target ratio (Eq. aimplified_l_weights); for the learned proposal it is
- * still a normalised density in phi_{k-1}, and the network's log q stays in the weight. */
+ * weight is the target ratio (Eq. aimplified_l_weights); for the other proposals it is
+ * still a normalised density in phi_{k-1}, and their log q stays in the weight. */
 #define SMC2_L_FORWARD 0   /* L = the random walk's forward kernel (Sec. IV-D)          */
 #define SMC2_L_GAUSS_OPT 1 /* approximately optimal Gaussian L-kernel (Sec. IV-D)       */
 
 #define SMC2_PROP_RW 0  /* Gaussian random walk on phi (Eq. proposal) */
+#define SMC2_PROP_MLP 1 /* learned Gaussian proposal: a D -> 64 -> 64 -> (mean, Cholesky)
+                           network, BF16 matrix-core products, trained after every
+                           iteration on the weighted population; its exact density
+                           enters the weights (Eq. l_weights, with either L-kernel);
+                           the random walk whenever the network does not beat it on
+                           held-out pairs                                                */
 #define SMC2_PROP_LANGEVIN 2 /* truncated Langevin proposal (SIR, SEIR, SMC2_LINGAUSS):
                                 phi' = phi + delta + L z, Sigma = L L' the weighted covariance
                                 of the proposing population, delta = 1/2 Sigma g shrunk to
@@ -107,15 +114,10 @@ extern "C" {
                                the proposing population (SMC2_PROP_LANGEVIN's covariance,
                                without its drift); its log q enters the weights
                                (Eq. l_weights). Iteration 1 draws from the prior. */
-#define SMC2_PROP_MLP 1 /* learned Gaussian proposal: a D -> 64 -> 64 -> (mean, Cholesky)
-                           network, BF16 matrix-core products, trained after every
-                           iteration on the weighted population; its exact density
-                           enters the weights (Eq. l_weights, with either L-kernel);
-                           the random walk whenever the network does not beat it on
-                           held-out pairs                                                */
 
 /* particle-filter draw schedule (smc2_config.schedule); both give identical results */
-#define SMC2_SCHED_AUTO 0     /* pooled where supported and it fits in LDS, else per draw */
+#define SMC2_SCHED_AUTO 0     /* pooled where supported and it fits in LDS, else per draw
+                                 (the score launches of SMC2_PROP_LANGEVIN: per draw)     */
 #define SMC2_SCHED_PER_DRAW 1 /* each lane finishes its draws one after another          */
 #define SMC2_SCHED_POOLED 2   /* SIR/SEIR: a wave pools its draws and runs the final
                                  acceptance tests of the BTRS sampler 64 at a time        */
@@ -149,7 +151,7 @@ typedef struct {
     int32_t N;         /* parameter samples per run, 2..32768                           */
     int32_t K;         /* iterations, >= 1 (k = 1 is the prior importance-sampling step) */
     int32_t precision; /* SMC2_PREC_FP32 or SMC2_PREC_FP64                              */
-    int32_t proposal;  /* SMC2_PROP_RW or SMC2_PROP_MLP                                 */
+    int32_t proposal;  /* SMC2_PROP_RW, _MLP, _LANGEVIN or _RW_POP                       */
     int32_t lkernel;   /* SMC2_L_FORWARD or SMC2_L_GAUSS_OPT                            */
     int32_t pf_always; /* 1: resample the particle filter at every step                 */
     int32_t use_graph; /* 1: replay each iteration as one captured HIP graph            */
@@ -249,7 +251,9 @@ typedef struct {
     int32_t dead;             /* samples with zero weight                                    */
     int32_t lkernel_fallback; /* 1 when the Gaussian L-kernel fit was rejected              */
     int32_t learned;          /* 1 when the learned proposal drew the samples               */
-    int32_t pad;
+    int32_t proposal;         /* the proposal that drew them: the record's column (0 random
+                                 walk or prior draw, 1 learned, 2 Langevin, 3 population
+                                 random walk)                                                */
     double ess;               /* effective sample size of the weights, = l_k                 */
     double log_weight_sum;    /* log sum_i w_k^i                                             */
     uint64_t particle_steps;  /* executed particle-steps of the run's filters (N_x x days

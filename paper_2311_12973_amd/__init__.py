@@ -70,7 +70,7 @@ class Run(ctypes.Structure):
 
 class StepInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("resampled", ctypes.c_int32), ("dead", ctypes.c_int32),
-                ("lkernel_fallback", ctypes.c_int32), ("learned", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("lkernel_fallback", ctypes.c_int32), ("learned", ctypes.c_int32), ("proposal", ctypes.c_int32),
                 ("ess", ctypes.c_double), ("log_weight_sum", ctypes.c_double), ("particle_steps", ctypes.c_uint64),
                 ("ms_filters", ctypes.c_double), ("ms_outer", ctypes.c_double), ("ms_mlp", ctypes.c_double),
                 ("ms_step", ctypes.c_double)]
@@ -327,7 +327,7 @@ class Sampler:
         """smc2_info of completed iteration k (1-based) as a dict."""
         out = StepInfo()
         _check(lib().smc2_info(self.h, run, int(k), ctypes.byref(out)), self.h)
-        return {name: getattr(out, name) for name, _ in StepInfo._fields_ if name != "pad"}
+        return {name: getattr(out, name) for name, _ in StepInfo._fields_}
 
     def timing(self):
         a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()

@@ -87,7 +87,8 @@ template <int D> __device__ __forceinline__ double prior_logpdf(const double* pr
 
 hipError_t launch_begin_iteration(const OuterArrays& o, int32_t* queues, int n_queues, hipStream_t s);
 hipError_t launch_propose(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds, hipStream_t s);
-// Langevin proposal: the proposing population's weighted covariance factor (k > 1)
+// Langevin and population random-walk proposals: the proposing population's weighted
+// covariance factor (k > 1)
 hipError_t launch_pop_frame(const OuterArrays& o, const OuterParams& p, hipStream_t s);
 hipError_t launch_outer_update(const OuterArrays& o, const OuterParams& p, const uint64_t* d_seeds,
                                hipStream_t s);

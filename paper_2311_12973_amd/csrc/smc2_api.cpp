@@ -918,8 +918,8 @@ extern "C" int smc2_info(smc2_ctx* c, int32_t run, int32_t k, smc2_step_info* in
     info->dead = (int32_t)rec[3];
     info->lkernel_fallback = (int32_t)rec[4];
     info->log_weight_sum = rec[5];
-    info->learned = (int32_t)rec[RL - 2];
-    info->pad = 0;
+    info->proposal = (int32_t)rec[RL - 2];
+    info->learned = info->proposal == 1 ? 1 : 0;
     info->particle_steps = at[1] - at[0];
     info->ms_step = t[0];
     info->ms_filters = t[1];

@@ -140,3 +140,16 @@ def test_population_walk_batched_matches_reference_per_run():
         assert ref["status"] == 0
         assert np.array_equal(recs[r][:, [0, 2, 3, 4, -2]], ref["rec"][:, [0, 2, 3, 4, -2]])
         assert np.allclose(recs[r][:, 6:], ref["rec"][:, 6:], rtol=1e-4, atol=1e-10)
+
+
+@pytest.mark.parametrize("N", [2, 32768])
+def test_population_walk_sample_count_limits(N):
+    """The smallest and largest sample counts the interface accepts, against the reference
+    sampler: with two samples the population's covariance is singular after every
+    resampling (the diagonal fallback), with 32768 one workgroup per run sums it over the
+    whole population."""
+    w = dict(W.preset("seir"), T=10, proposal=G.PROP_RW_POP, prec=G.PREC_FP64)
+    _log("population random walk N=%d" % N)
+    gpu, ref = _run_pair(w, N, 3, 16, G.SCHED_AUTO)
+    _compare(gpu, ref, w["D"], 1e-9)
+    assert np.all(gpu["rec"][1:, -2] == 3)

@@ -363,7 +363,8 @@ def test_sample_count_limits_sampled_parity(N):
     s.close()
 
 
-@pytest.mark.parametrize("proposal,graph", [(G.PROP_RW, 0), (G.PROP_MLP, 0), (G.PROP_RW, 1)])
+@pytest.mark.parametrize("proposal,graph", [(G.PROP_RW, 0), (G.PROP_MLP, 0), (G.PROP_RW, 1), (G.PROP_RW_POP, 0),
+                                            (G.PROP_LANGEVIN, 1)])
 def test_step_info_matches_records_counter_and_timing(proposal, graph):
     """smc2_info per iteration: the record's scalars, the executed particle-steps of the
     iteration (summing to the run's counter), and phase times that add up within the
@@ -382,7 +383,8 @@ def test_step_info_matches_records_counter_and_timing(proposal, graph):
             inf = s.info(k, run=r)
             assert inf["k"] == k and inf["ess"] == rec[k - 1, 1] and inf["resampled"] == rec[k - 1, 2]
             assert inf["dead"] == rec[k - 1, 3] and inf["lkernel_fallback"] == rec[k - 1, 4]
-            assert inf["log_weight_sum"] == rec[k - 1, 5] and inf["learned"] == rec[k - 1, RL - 2]
+            assert inf["log_weight_sum"] == rec[k - 1, 5] and inf["proposal"] == rec[k - 1, RL - 2]
+            assert inf["learned"] == (rec[k - 1, RL - 2] == 1)
             assert 0 < inf["particle_steps"] <= 512 * 128 * 40
             tot += inf["particle_steps"]
             assert 0 < inf["ms_filters"] < inf["ms_step"]
