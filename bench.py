@@ -394,8 +394,9 @@ def paper_experiment(G, W, np, seed=1):
     burned in), each chain's filter in one launch per iteration. Wall time of the
     iterations (synchronised), the estimates and their squared error against the truth;
     Table II's MSE (per-run squared errors averaged over 10 runs and both parameters) for
-    SMC^2 and for 64-chain p-MCMC; the paper's figures (128 CPU cores for SMC^2, one for
-    p-MCMC) beside them as context."""
+    SMC^2 and for 64-chain p-MCMC; the analogues of Fig. 3 (the estimates per iteration)
+    and Fig. 1 (the run time of K = 10 iterations for N = 256 .. 16384); the paper's
+    figures (128 CPU cores for SMC^2, one for p-MCMC) beside them as context."""
     import torch
     w = W.preset("paper_sir")
     y = W.observations(w)
@@ -409,8 +410,23 @@ def paper_experiment(G, W, np, seed=1):
         s.step()
     mean, _ = s.estimate(recycled=True)
     sec = time.perf_counter() - t0
+    rec_k = s.records()
     s.close()
     out["smc2"] = {"seconds": sec, "posterior_mean": mean.tolist(), "squared_error": float(np.mean((mean - truth) ** 2))}
+    # Fig. 3's analogue: the per-iteration estimates of (beta, gamma) and the recycled one
+    out["smc2"]["estimates_per_iteration"] = rec_k[:, 6:8].tolist()
+    # Fig. 1's analogue: the run time of K = 10 iterations against the problem size K N
+    sizes = []
+    for n in (256, 512, 1024, 2048, 4096, 8192, 16384):
+        s = G.Sampler(w, [run], N=n, K=w["K"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(w["K"]):
+            s.step()
+        s.estimate(recycled=True)
+        sizes.append({"N": n, "KN": n * w["K"], "seconds": time.perf_counter() - t0})
+        s.close()
+    out["runtime_vs_problem_size"] = sizes
     for name, chains, iters in (("pmcmc_64_chains", 64, 160), ("pmcmc_1_chain", 1, 10240)):
         mc = G.PMCMC(w, run, chains, iters)
         torch.cuda.synchronize()
