@@ -40,7 +40,9 @@ int smc2_binomial_batch(int32_t precision, int32_t count, const int32_t* d_n, co
 int smc2_resample_batch(int32_t n_sets, int32_t n, const uint64_t* d_q, const uint64_t* d_x64, int32_t* d_anc,
                         int32_t* d_trigger, void* hip_stream);
 
-/* Device workspace bytes for smc2_pf_loglik. */
+/* Device workspace bytes for smc2_pf_loglik (and the other filter entry points): the
+ * staged run and observations. A size only: the entry points validate the rest of cfg
+ * and run when called. 0 (with a message) when cfg or run is NULL or run->T < 1. */
 size_t smc2_pf_workspace_bytes(const smc2_config* cfg, const smc2_run* run);
 
 /* Particle-filter log-likelihood estimates (Sec. II) for n_theta model parameter

@@ -145,7 +145,10 @@ extern "C" int smc2_resample_batch(int32_t n_sets, int32_t n, const uint64_t* d_
 
 extern "C" size_t smc2_pf_workspace_bytes(const smc2_config* cfg, const smc2_run* run)
 {
-    if (!cfg || !run || run->T < 1) return 0;
+    if (!cfg || !run || run->T < 1) {
+        kfail(SMC2_E_ARG, "cfg or run is NULL, or run->T < 1");
+        return 0;
+    }
     const size_t y = ((size_t)run->T * obs_words(cfg->model) * 4 + 255) & ~(size_t)255;
     return 256 + y;
 }
