@@ -818,9 +818,8 @@ __device__ void mlp_heldout(const MlpArrays& m, const MlpParams& p, const OuterA
 template <int D>
 __global__ void __launch_bounds__(256) k_mlp_train(MlpArrays m, MlpParams p, OuterArrays o, const uint64_t* seeds)
 {
-    constexpr int P = D + D * (D + 1) / 2;
     const int r = (int)blockIdx.x;
-    const int tid = (int)threadIdx.x, nthr = (int)blockDim.x;
+    const int tid = (int)threadIdx.x;
     const int N = p.N;
     const int k = *o.k_dev;
     if (o.status[r] != 0) return;  // every weight vanished: nothing to learn from
@@ -1202,12 +1201,10 @@ __global__ void __launch_bounds__(256) k_mlp_rows_grad(int n, const float* param
                                                        const double* phi_in, const double* phi_t, const double* wrow,
                                                        float* grad, double* loss)
 {
-    constexpr int P = D + D * (D + 1) / 2;
     extern __shared__ __align__(16) unsigned char smem[];
     MlpW* W = reinterpret_cast<MlpW*>(smem);
     MlpAct* A = reinterpret_cast<MlpAct*>(smem + sizeof(MlpW));
     __shared__ double red[16 * 2];
-    const int NP = mlp_nparams(D);
     const int tid = (int)threadIdx.x;
     mlp_load_weights(D, params, W);
     f32x4 acc[8];

@@ -394,8 +394,8 @@ static hipError_t autotune(smc2_ctx* c)
             e = pf_prepare(cfg.precision, cfg.model, cfg.obs, gr.sched, gr.lds);
         }
     }
-    if (t0) hipEventDestroy(t0);
-    if (t1) hipEventDestroy(t1);
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
     if (e == hipSuccess) e = hipMemsetAsync(w + c->lay.off_k, 0, sizeof(int32_t), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return e;
