@@ -175,7 +175,9 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--schedule", type=int, default=0, help="particle-filter draw schedule (0 auto, 1 per draw, 2 pooled)")
     ap.add_argument("--tune", type=int, default=0, help="1: time the launch configurations at init and keep the fastest")
-    ap.add_argument("--persistent", type=int, default=0, help="1: persistent grid pulling filters from the work list")
+    ap.add_argument("--persistent", type=int, default=0,
+                    help="particle-filter launch: 0 automatic (a persistent grid pulling filters from the work list "
+                         "when they do not fit at once), 1 persistent, 2 a workgroup per filter")
     ap.add_argument("--proposal", type=int, default=-1,
                     help="proposal of the timed workload (-1 its own; 0 random walk, 1 learned, 2 Langevin, "
                          "3 random walk with the population's covariance)")
@@ -250,7 +252,7 @@ def main():
                    "nominal_particle_steps_per_iteration": m["nominal"] / m["steps"],
                    "nominal_particle_steps_per_s": m["nominal"] / (m["ms"] * 1e-3 * m["steps"]),
                    "parallelism": "single GPU", "graph": bool(args.graph), "tune": bool(args.tune),
-                   "persistent": bool(args.persistent), "dead_samples_per_step": m["dead"],
+                   "persistent": any(g["persistent"] for g in m["groups"]), "dead_samples_per_step": m["dead"],
                    "device_ms_per_step": m["ms_step_dev"], "device_ms_per_phase": m["phases"],
                    "launch_groups": m["groups"]},
         "roofline": roofline, "cpu_baseline": cpu, "precision": precision, "ess_per_s": ess, "secondary": secondary,

@@ -139,6 +139,14 @@ extern "C" {
 #define SMC2_MLP_TRAIN_PER_RUN 1
 #define SMC2_MLP_TRAIN_SPLIT 2
 
+/* Particle-filter launch (smc2_config.persistent, with tune = 0; the autotuner chooses
+ * for itself). Persistent: the resident workgroups pull filters from the cost-sorted work
+ * list (an atomic counter) until it is exhausted. */
+#define SMC2_LAUNCH_AUTO 0       /* persistent when a launch group has more filters than
+                                    fit on the device at once, else a workgroup per filter */
+#define SMC2_LAUNCH_PERSISTENT 1
+#define SMC2_LAUNCH_PER_FILTER 2 /* one workgroup per filter                               */
+
 #define SMC2_DMAX 8
 #define SMC2_NFIXED 32
 
@@ -167,8 +175,8 @@ typedef struct {
                            configurations (workgroup size, draw schedule, persistent grid)
                            of every launch group on a sample of its filters and keeps the
                            fastest; 0: defaults from the LDS footprint. Same results.     */
-    int32_t persistent; /* with tune = 0: 1 launches a persistent grid whose workgroups
-                           pull filters from the cost-sorted work list (atomic counter)   */
+    int32_t persistent; /* with tune = 0, SMC2_LAUNCH_*: how the filters are launched
+                           (same results)                                                 */
     int32_t mlp_epochs; /* learned proposal: training epochs per iteration (0 .. 1000)     */
     int32_t mlp_batch;  /* learned proposal: minibatch rows (0: the whole population)      */
     double mlp_lr;      /* learned proposal: Adam learning rate (> 0)                      */

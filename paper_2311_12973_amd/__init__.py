@@ -24,6 +24,7 @@ PROP_RW, PROP_MLP, PROP_LANGEVIN, PROP_RW_POP = 0, 1, 2, 3
 PF_RS_SYSTEMATIC, PF_RS_MULTINOMIAL = 0, 1
 MLP_TRAIN_AUTO, MLP_TRAIN_PER_RUN, MLP_TRAIN_SPLIT = 0, 1, 2
 SCHED_AUTO, SCHED_PER_DRAW, SCHED_POOLED = 0, 1, 2
+LAUNCH_AUTO, LAUNCH_PERSISTENT, LAUNCH_PER_FILTER = 0, 1, 2
 DUMP = dict(phi=0, lp=1, ll=2, logw=3, phi_new=4, lp_new=5, ll_new=6, logw_pre=7, anc=8, mlp_out=9, logq=10,
             mlp_params=11, mlp_frame=12, mlp_state=13, mlp_grad=14, psteps=15, lkfit=16, theta_new=17, score=18,
             score_new=19)

@@ -230,7 +230,8 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
         return m = "block must be 0 or a multiple of 64 up to 1024", SMC2_E_ARG;
     if (c->schedule < 0 || c->schedule > 2) return m = "schedule must be 0, 1 or 2", SMC2_E_ARG;
     if (c->tune < 0 || c->tune > 1) return m = "tune must be 0 or 1", SMC2_E_ARG;
-    if (c->persistent < 0 || c->persistent > 1) return m = "persistent must be 0 or 1", SMC2_E_ARG;
+    if (c->persistent < SMC2_LAUNCH_AUTO || c->persistent > SMC2_LAUNCH_PER_FILTER)
+        return m = "persistent must be SMC2_LAUNCH_AUTO, _PERSISTENT or _PER_FILTER", SMC2_E_ARG;
     if (c->pf_resampling != SMC2_PF_RS_SYSTEMATIC && c->pf_resampling != SMC2_PF_RS_MULTINOMIAL)
         return m = "pf_resampling must be SMC2_PF_RS_SYSTEMATIC or SMC2_PF_RS_MULTINOMIAL", SMC2_E_ARG;
     if (c->mlp_train < SMC2_MLP_TRAIN_AUTO || c->mlp_train > SMC2_MLP_TRAIN_SPLIT)
@@ -280,14 +281,19 @@ extern "C" size_t smc2_workspace_bytes(const smc2_config* cfg, int32_t n_runs, c
     return make_layout(cfg, n_runs, runs).total;
 }
 
-// Launch shape of a group: the workgroups resident at once, the persistent grid (all of
-// them, at most one per filter) and the wave-priority scale.
+// Launch shape of a group: the workgroups resident at once; without the autotuner and with
+// SMC2_LAUNCH_AUTO, a persistent grid when the group has more filters than fit at once (at
+// the age-structured shape, 16384 filters of one workgroup per CU, 1419 against 1501 ms
+// per launch with a workgroup per filter; the same within noise for a single round); the
+// persistent grid (all resident workgroups, at most one per filter) and the wave-priority
+// scale.
 static hipError_t set_launch(smc2_ctx* c, PFGroup& gr)
 {
     int per_cu = 0;
     const hipError_t e = pf_occupancy(c->cfg.precision, c->cfg.model, c->cfg.obs, gr.sched, gr.block, gr.lds, &per_cu);
     if (e != hipSuccess) return e;
     gr.resident = (long)(per_cu > 0 ? per_cu : 1) * (c->n_cu > 0 ? c->n_cu : 1);
+    if (!c->cfg.tune && c->cfg.persistent == SMC2_LAUNCH_AUTO) gr.persistent = gr.n_items > gr.resident ? 1 : 0;
     if (gr.persistent) gr.grid = (int)std::min<long>(gr.resident, gr.n_items);
     gr.prio = prio_scale(gr, gr.n_items);
     return hipSuccess;
@@ -467,7 +473,8 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     });
     for (size_t idx = 0; idx < run_order.size();) {
         const int b = blk[run_order[idx]];
-        PFGroup gr{b, 0, (int)items.size(), 0, pooled_variant, cfg->persistent, 0, 0, 0, 0.f, 0.0, 0, 0.f};
+        PFGroup gr{b, 0, (int)items.size(), 0, pooled_variant, cfg->persistent == SMC2_LAUNCH_PERSISTENT ? 1 : 0,
+                   0, 0, 0, 0.f, 0.0, 0, 0.f};
         const size_t g0 = idx;
         // the pooled schedule when every run of the group fits in LDS with it
         for (size_t x = g0; x < run_order.size() && blk[run_order[x]] == b; ++x) {

@@ -43,7 +43,7 @@ def test_workspace_bytes_and_validation():
     nb = L.smc2_workspace_bytes(ctypes.byref(cfg), 1, runs)
     assert 3 * 1024 * 4 * 8 < nb < 1 << 20  # O(N D) doubles: particles never leave the chip
     bad = [dict(N=1), dict(N=40000), dict(K=0), dict(precision=3), dict(block=96), dict(block=2048),
-           dict(schedule=3), dict(schedule=-1)]
+           dict(schedule=3), dict(schedule=-1), dict(persistent=3), dict(persistent=-1)]
     for over in bad:
         c = G.make_config(w, **over)
         assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == 0, over

@@ -290,7 +290,7 @@ def test_batched_runs_identical_under_every_launch_configuration():
     w = W.preset("seir_batched")
     runs = W.batched_runs(w, n_runs=6)
     _log("runs: " + ", ".join("T=%d nx=%d" % (r["T"], r["nx"]) for r in runs))
-    base, g0 = _batched_dumps(w, runs, 32, 3)
+    base, g0 = _batched_dumps(w, runs, 32, 3, persistent=G.LAUNCH_PER_FILTER)
     pers, g1 = _batched_dumps(w, runs, 32, 3, persistent=1)
     tuned, g2 = _batched_dumps(w, runs, 32, 3, tune=1)
     graph, g3 = _batched_dumps(w, runs, 32, 3, persistent=1, use_graph=1)
@@ -302,6 +302,31 @@ def test_batched_runs_identical_under_every_launch_configuration():
     for other in (pers, tuned, graph):
         for key in ("ll", "logw", "anc", "rec"):
             assert np.array_equal(np.nan_to_num(base[key], neginf=-1e300), np.nan_to_num(other[key], neginf=-1e300)), key
+
+
+def test_automatic_launch_is_persistent_beyond_one_round():
+    """SMC2_LAUNCH_AUTO: a launch group with more filters than fit on the device at once
+    runs as a persistent grid, one that fits as a workgroup per filter; the results equal
+    the explicit per-filter launch's."""
+    w = dict(W.preset("seir"), T=12)
+    y = W.observations(w)
+    run = [dict(T=12, nx=48, seed=3, y=y)]
+    for N in (64, 32768):
+        out = {}
+        for launch in (G.LAUNCH_AUTO, G.LAUNCH_PER_FILTER):
+            s = G.Sampler(w, run, N=N, K=2, persistent=launch)
+            for _ in range(2):
+                s.step()
+            out[launch] = (s.groups(), s.records(), s.dump("ll_new"), s.dump("anc"))
+            s.close()
+        groups = out[G.LAUNCH_AUTO][0]
+        _log("N=%d automatic launch groups %s" % (N, groups))
+        for g in groups:
+            assert g["persistent"] == (1 if N == 32768 else 0)
+            assert g["grid"] < g["filters"] if N == 32768 else g["grid"] == g["filters"]
+        assert all(g["persistent"] == 0 for g in out[G.LAUNCH_PER_FILTER][0])
+        for a, b in zip(out[G.LAUNCH_AUTO][1:], out[G.LAUNCH_PER_FILTER][1:]):
+            assert np.array_equal(np.nan_to_num(a, neginf=-1e300), np.nan_to_num(b, neginf=-1e300))
 
 
 def test_batched_matches_reference_per_run():
