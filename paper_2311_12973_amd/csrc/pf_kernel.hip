@@ -836,7 +836,10 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
     }
     if constexpr (SCORE) {
         // the estimate sum_j w_j s_j / sum_j w_j with the last day's FP64 weights (kept in C),
-        // summed per 64-particle chunk and the chunks in order, like the weight sum
+        // summed per 64-particle chunk and the chunks in order, like the weight sum. The
+        // chunk slots still hold the last day's weight sums, which every thread has read
+        // only once all have passed this barrier.
+        __syncthreads();
         const double* wT = reinterpret_cast<const double*>(C);
         const int nwv = nthr >> 6;
         const bool alive = uniform_bool(ll != -INFINITY);

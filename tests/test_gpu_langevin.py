@@ -125,3 +125,35 @@ def test_gpu_langevin_sampler_targets_the_grid_posterior():
          % (ests.mean(0), grid_mean, se, pooled_sd, grid_sd))
     assert np.all(np.abs(ests.mean(0) - grid_mean) < 4 * se + 2e-3)
     assert np.all(np.abs(pooled_sd / grid_sd - 1) < 0.2)
+
+
+@pytest.mark.parametrize("schedule", [G.SCHED_AUTO, G.SCHED_POOLED])
+def test_langevin_score_launches_identical_under_every_launch(schedule):
+    """Score launches with several filters per workgroup: a persistent grid (automatic for
+    2048 filters of 1024 particles, four rounds of resident workgroups) and a workgroup per
+    filter give the same records, likelihoods and scores, under either draw schedule. (The
+    score's chunk sums once started without waiting for every wave to finish reading the
+    last day's weight sums from the same slots; a lagging wave could then take a wrong sum,
+    which showed as a diverging run under the persistent grid.)"""
+    w = dict(W.preset("seir_learned"), T=30, proposal=G.PROP_LANGEVIN)
+    y = W.observations(w)
+    run = [dict(T=30, nx=1024, seed=7, y=y)]
+    out = {}
+    for launch in (G.LAUNCH_PER_FILTER, G.LAUNCH_AUTO, G.LAUNCH_PERSISTENT):
+        s = G.Sampler(w, run, N=2048, K=4, persistent=launch, schedule=schedule)
+        dumps = []
+        for _ in range(4):
+            s.step()
+            dumps.append((s.dump("ll_new"), s.dump("score_new"), s.dump("anc"), s.dump("phi_new")))
+        out[launch] = (s.records(), dumps, s.groups())
+        s.close()
+    _log("schedule %d groups: per filter %s, automatic %s" % (schedule, out[G.LAUNCH_PER_FILTER][2],
+                                                               out[G.LAUNCH_AUTO][2]))
+    assert all(g["persistent"] == 1 for g in out[G.LAUNCH_AUTO][2])
+    ref = out[G.LAUNCH_PER_FILTER]
+    for launch in (G.LAUNCH_AUTO, G.LAUNCH_PERSISTENT):
+        got = out[launch]
+        assert np.array_equal(got[0], ref[0]), launch
+        for a, b in zip(got[1], ref[1]):
+            for x, z in zip(a, b):
+                assert np.array_equal(np.nan_to_num(x, neginf=-1e300), np.nan_to_num(z, neginf=-1e300)), launch
