@@ -271,7 +271,7 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline_leg(G, np, m, s, n_filters, n_single=6, n_trace=16):
+def cpu_baseline_leg(G, np, m, s, n_filters, n_single=6, n_trace=16, n_replay=256):
     """The CPU reference on a bounded sample of the workload, and what its runs say
     about the GPU's precision.
 
@@ -284,9 +284,10 @@ def cpu_baseline_leg(G, np, m, s, n_filters, n_single=6, n_trace=16):
     ancestors and resampling flags of every day) against the reference's free-running
     FP64 filters (relative error of the log-likelihood; filters whose decisions differ
     anywhere, and the median day they first do) and against its FP64 replay of the
-    GPU's decisions (the FP32 weight arithmetic alone); and that iteration's outer
-    step recomputed by the reference from the GPU's inputs (L-kernel fit moments and
-    log-weights)."""
+    GPU's decisions (the FP32 weight arithmetic alone); the replay alone on the first
+    n_replay samples, traced in chunks of 32 (the whole-day traces are ~36 MB a filter at
+    the age-structured shape); and that iteration's outer step recomputed by the
+    reference from the GPU's inputs (L-kernel fit moments and log-weights)."""
     import oracle as O
 
     w, N, run = m["w"], m["N"], m["runs"][0]
@@ -356,6 +357,23 @@ def cpu_baseline_leg(G, np, m, s, n_filters, n_single=6, n_trace=16):
             differ += 1
     del st, anc_t
 
+    # the replay on a larger sample, chunk by chunk (each replay needs only the GPU's trace)
+    n_replay = min(n_replay, N)
+    rep_all = []
+    for c0 in range(0, n_replay, 32):
+        c1 = min(c0 + 32, n_replay)
+        llc, _, rsc, stc, ancc = G.pf_trace_state(w, theta[c0:c1], y, nx, seed, k, precision=G.PREC_FP32,
+                                                  with_anc=True)
+
+        def replay(i, llc=llc, rsc=rsc, stc=stc, ancc=ancc, c0=c0):
+            r64, _ = O.pf_replay(cfg64, theta[c0 + i], y, stc[i], ancc[i], rsc[i])
+            return abs(llc[i] - r64) / abs(r64) if np.isfinite(llc[i]) and np.isfinite(r64) else None
+
+        with cf.ThreadPoolExecutor(threads) as ex:
+            rep_all += [v for v in ex.map(replay, range(c1 - c0)) if v is not None]
+        del stc, ancc
+    log("precision: %d filters replayed, largest relative error %s" % (len(rep_all), max(rep_all) if rep_all else None))
+
     # the outer step of this iteration from the GPU's inputs
     om = np.exp(before["logw"] - np.max(before["logw"]))
     om /= om.sum()
@@ -372,6 +390,12 @@ def cpu_baseline_leg(G, np, m, s, n_filters, n_single=6, n_trace=16):
             "first_differing_day_median": q(first), "days": T,
             "replayed_rel_err_median": q(rep), "replayed_rel_err_max": max(rep) if rep else None,
             "replay": "FP64 reference weights on the GPU's own counts, ancestors and resampling flags"},
+        "replay_sample": {
+            "filters": n_replay, "compared": len(rep_all), "replayed_rel_err_median": q(rep_all),
+            "replayed_rel_err_max": float(max(rep_all)) if rep_all else None,
+            "within_1e-4": bool(rep_all) and bool(max(rep_all) <= 1e-4),
+            "replay": "the first filters of the same iteration, each traced on the GPU (FP32) and its weights "
+                      "recomputed in FP64 by the reference on the GPU's decisions"},
         "outer_fp64_vs_reference": {
             "iteration": k, "proposal": PROPOSAL_NAMES[used],
             "lkernel_mean_rel_err_max": float(np.max(np.abs(fit[:D2] - mu) / np.maximum(np.abs(mu), 1e-300))),
