@@ -10,6 +10,9 @@
     decisions agree reproduce the free-running FP64 estimate exactly in the replay.
 * The FP64 outer step against the reference recomputing it from the GPU's inputs: the
   L-kernel fit's weighted moments and the log-weights.
+* End to end: every filter of a sampler iteration replayed in FP64 on the GPU's
+  decisions, and the reference's outer step on the replayed estimates: posterior means
+  and ESS within 1e-4 of the GPU's.
 * The executed particle-steps of a run (N_x x days each active filter ran, stopping at
   a filter's death day) against the reference's filters.
 """
@@ -118,6 +121,49 @@ def test_outer_step_fp64_against_the_reference(proposal):
     _log("outer step (proposal %d): L-kernel mean rel err %.3g, covariance %.3g (of its largest entry), "
          "log-weights %.3g" % (proposal, errs["mu"], errs["cov"], errs["logw"]))
     assert errs["mu"] <= 1e-12 and errs["cov"] <= 1e-12 and errs["logw"] <= 1e-9
+
+
+def test_end_to_end_replay_posterior_means():
+    """The end-to-end level of the replay: every filter of each iteration (FP32 on the
+    GPU) is traced on the same streams through the kernel-level entry point (which
+    reproduces the sampler's estimate bit for bit), its weights are recomputed in FP64 by
+    the reference on the GPU's decisions, and the reference's outer step on those
+    estimates gives the iteration's posterior mean and ESS: within 1e-4 of the GPU's."""
+    w = dict(W.preset("seir"), T=40)
+    y = W.observations(w)
+    N, K, nx, seed = 256, 3, 256, 5
+    s = G.Sampler(w, [dict(T=y.shape[0], nx=nx, seed=seed, y=y)], N=N, K=K)
+    cfg = O.config_from_workload(w)
+    cfg64 = O.config_from_workload(w, prec=O.PREC_FP64)
+    D = w["D"]
+    worst = dict(ll=0.0, mean=0.0, ess=0.0)
+    for k in range(1, K + 1):
+        before = {key: s.dump(key) for key in ("phi", "lp", "ll", "logw")}
+        s.step()
+        rec = s.records()[k - 1]
+        theta, phin, lpn, lln = (s.dump(x) for x in ("theta_new", "phi_new", "lp_new", "ll_new"))
+        ll32, _, rs, st, anc = G.pf_trace_state(w, theta, y, nx, seed, k, precision=G.PREC_FP32, with_anc=True)
+        act = np.isfinite(lln)
+        assert np.array_equal(ll32[act], lln[act])
+
+        def replay(i):
+            return O.pf_replay(cfg64, theta[i], y, st[i], anc[i], rs[i])[0] if act[i] else -np.inf
+
+        with cf.ThreadPoolExecutor(8) as ex:
+            ll_rep = np.array(list(ex.map(replay, range(N))))
+        fin = np.isfinite(ll_rep)
+        assert np.array_equal(fin, act)
+        worst["ll"] = max(worst["ll"], float(np.max(np.abs(lln[fin] - ll_rep[fin]) / np.abs(ll_rep[fin]))))
+        st_ref = dict(phi=np.zeros((N, D)), lp=np.zeros(N), ll=np.zeros(N), logw=np.zeros(N)) if k == 1 else before
+        status, _, _, rec_ref = O.outer_update(cfg, k, seed, dict(st_ref), phin, lpn, ll_rep)
+        assert status == 0
+        worst["mean"] = max(worst["mean"], float(np.max(np.abs(rec[6:6 + D] - rec_ref[6:6 + D])
+                                                       / np.abs(rec_ref[6:6 + D]))))
+        worst["ess"] = max(worst["ess"], abs(rec[1] - rec_ref[1]) / rec_ref[1])
+    s.close()
+    _log("end-to-end replay: log-likelihoods %.3g, posterior means %.3g, ESS %.3g (largest relative differences)"
+         % (worst["ll"], worst["mean"], worst["ess"]))
+    assert worst["ll"] <= 1e-4 and worst["mean"] <= 1e-4 and worst["ess"] <= 1e-4
 
 
 def test_executed_particle_steps_counter():
