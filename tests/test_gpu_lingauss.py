@@ -12,8 +12,9 @@ pinned on the GPU itself, besides the parity with the reference:
   states a^t m0, bit for bit;
 * unbiasedness: the mean of exp(ll - ll_Kalman) over thousands of GPU filters is 1;
 * the whole GPU sampler (outer step, L-kernel, recycling) on this model reaches the
-  exact posterior computed from the Kalman likelihood on a grid, with the random walk
-  and with the learned proposal.
+  exact posterior computed from the Kalman likelihood on a grid, with the random walk,
+  the learned proposal, the population random walk and the Langevin proposal (its
+  score launches on this model).
 """
 import numpy as np
 import pytest
@@ -145,7 +146,7 @@ def grid_posterior(w, y, G_=48):
     return mt, stt
 
 
-@pytest.mark.parametrize("proposal", [G.PROP_RW, G.PROP_MLP])
+@pytest.mark.parametrize("proposal", [G.PROP_RW, G.PROP_MLP, G.PROP_RW_POP, G.PROP_LANGEVIN])
 def test_sampler_reaches_the_exact_posterior(proposal):
     w = W.preset("lingauss", proposal=proposal)
     y = W.observations(w)
@@ -161,7 +162,9 @@ def test_sampler_reaches_the_exact_posterior(proposal):
     rec = smp.records(0)
     smp.close()
     se = est.std(0, ddof=1) / np.sqrt(R)
-    _log("  posterior mean %s (exact %s, s.e. %s); sd %s (exact %s); learned iterations %d"
-         % (est.mean(0), gm, se, sds.mean(0), gsd, int(rec[:, -2].sum()) if proposal == G.PROP_MLP else 0))
+    _log("  posterior mean %s (exact %s, s.e. %s); sd %s (exact %s); iterations by proposal code %s"
+         % (est.mean(0), gm, se, sds.mean(0), gsd, np.bincount(rec[:, -2].astype(int), minlength=4).tolist()))
+    if proposal in (G.PROP_RW_POP, G.PROP_LANGEVIN):
+        assert np.all(rec[1:, -2] == (3 if proposal == G.PROP_RW_POP else 2))
     assert np.all(np.abs(est.mean(0) - gm) < 4 * se + 0.05 * gsd)
     assert np.all(np.abs(sds.mean(0) / gsd - 1) < 0.2)
