@@ -252,7 +252,7 @@ int or_lkernel_fit_cov(int N, int D, const double* phi, const double* phi_new, c
        conditioned on rounding noise. */
     double floor_[2 * OR_DMAX];
     for (int a = 0; a < D2; ++a) floor_[a] = OR_LK_REL_FLOOR * (cov[a * D2 + a] + mu[a] * mu[a]);
-    double S22[OR_DMAX * OR_DMAX] = {0}, L22[OR_DMAX * OR_DMAX], S[OR_DMAX * OR_DMAX];
+    double S22[OR_DMAX * OR_DMAX] = {0}, L22[OR_DMAX * OR_DMAX], S[OR_DMAX * OR_DMAX] = {0};
     for (int a = 0; a < D; ++a)
         for (int c = 0; c < D; ++c) S22[a * D + c] = cov[(D + a) * D2 + D + c];
     if (or_cholesky(D, S22, L22) != 0) return -1;
