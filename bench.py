@@ -216,28 +216,40 @@ def main():
     log("timed: %.1f ms per iteration, %.3g executed particle-steps/s" % (m["ms"], m["value"]))
     roofline = roofline_of(args.workload, m, args.graph)
 
+    def section(name, fn):
+        """a part of the line beside the headline: a failure is reported in the line (and on
+        stderr) instead of taking the headline measurement with it"""
+        try:
+            return fn()
+        except Exception as e:  # noqa: BLE001 - reported, not hidden
+            log("%s failed: %r" % (name, e))
+            return {"error": "%s: %r" % (name, e)}
+
     cpu = precision = None
     if s is not None:
-        cpu, precision = cpu_baseline_leg(G, np, m, s, args.cpu_filters)
+        both = section("cpu_baseline", lambda: cpu_baseline_leg(G, np, m, s, args.cpu_filters))
+        cpu, precision = (both, both) if isinstance(both, dict) else both
         s.close()
+
+    def seir_secondary():
+        m2, _ = run_timed(G, W, np, "seir", 10, 2, **launch)
+        r2 = roofline_of("seir", m2, args.graph)
+        log("secondary seir: %.3g particle-steps/s" % m2["value"])
+        return {"workload": describe("seir", m2["w"], m2["runs"], m2["N"]), "value": m2["value"],
+                "unit": "particle-steps/s", "ms_per_step": m2["ms"],
+                "nominal_particle_steps_per_s": m2["nominal"] / (m2["ms"] * 1e-3 * m2["steps"]),
+                "roofline_frac": r2["frac"] if r2 else None, "kernel_ms": m2["ms_pf"]}
 
     secondary = None
     if not args.no_secondary and args.workload != "seir":
-        m2, _ = run_timed(G, W, np, "seir", 10, 2, **launch)
-        r2 = roofline_of("seir", m2, args.graph)
-        secondary = {"seir": {"workload": describe("seir", m2["w"], m2["runs"], m2["N"]), "value": m2["value"],
-                              "unit": "particle-steps/s", "ms_per_step": m2["ms"],
-                              "nominal_particle_steps_per_s": m2["nominal"] / (m2["ms"] * 1e-3 * m2["steps"]),
-                              "roofline_frac": r2["frac"] if r2 else None,
-                              "kernel_ms": m2["ms_pf"]}}
-        log("secondary seir: %.3g particle-steps/s" % m2["value"])
+        secondary = {"seir": section("secondary seir", seir_secondary)}
 
     if not args.no_secondary:
-        secondary = dict(secondary or {}, paper_sir=paper_experiment(G, W, np))
+        secondary = dict(secondary or {}, paper_sir=section("paper_sir", lambda: paper_experiment(G, W, np)))
 
     ess = None
     if not args.no_ess:
-        ess = ess_at_fixed_error(G, W, np)
+        ess = section("ess_per_s", lambda: ess_at_fixed_error(G, W, np))
 
     out = {
         "metric": "PF particle-steps/s (theta x x x t), whole SMC^2 iterations; ESS/s at fixed posterior error, "
