@@ -7,8 +7,8 @@ contains none of the sampler's arithmetic.
 
 The paper measures on simulated SIR data it does not print (Sec. V-A/V-B); every
 preset below therefore simulates its own data from a stated seed, at the paper's
-shape (``paper_sir``) or at larger epidemic shapes. Model constants and
-observation models: see DESIGN.md "Workloads".
+shape (``paper_sir``) or at larger epidemic shapes. The model constants and
+observation models of each preset are in ``preset``'s table below.
 """
 import math
 
