@@ -52,16 +52,19 @@ ALGO_OPS_PER_PSTEP = {"seir": 647.8, "seir_learned": 647.8, "seir_batched": 647.
 VALU_PEAK_LANE_OPS = 256 * 64 * 2.4e9
 # rocprofv3 figures of the particle-filter kernel, per workload, measured on the kernel
 # sources and build flags with hash `sha` (profiles/<file>): VALU instructions executed by
-# active lanes per executed particle-step (SQ_INSTS_VALU x 64 x lane utilisation) and HBM
-# bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a 256 MiB device copy). A
-# changed kernel reports them as null.
+# active lanes per executed particle-step (SQ_INSTS_VALU x 64 x lane utilisation), HBM
+# bytes per launch (FETCH_SIZE + WRITE_SIZE, calibrated on a 256 MiB device copy) and the
+# VALU-busy fraction (SQ_ACTIVE_INST_VALU / 256 CUs / (GRBM_GUI_ACTIVE / 8 XCDs): cycles
+# in which the VALU issued, whatever the lanes). A changed kernel reports them as null.
 KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_amd/csrc/pf_kernel.h",
                   "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h",
                   "paper_2311_12973_amd/build.py"]
 MEASURED = {
     "age_seir": dict(sha="a461133986f9969c", valu_lane_instr_per_pstep=2408.1, hbm_bytes_per_launch=11163301497,
+                     valu_busy=0.9141,
                      profile="profiles/pf_kernel_age_seir_n16384_nx2048_t365.txt"),
     "seir": dict(sha="a461133986f9969c", valu_lane_instr_per_pstep=1419.2, hbm_bytes_per_launch=1072000,
+                 valu_busy=0.9867,
                  profile="profiles/pf_kernel_seir_n1024_nx512_t100.txt"),
 }
 
@@ -161,6 +164,7 @@ def roofline_of(name, m, graph):
             "algorithmic_ops_per_particle_step": algo,
             "valu_lane_instr_per_particle_step": meas["valu_lane_instr_per_pstep"] if valid else None,
             "valu_issue_frac": issue / VALU_PEAK_LANE_OPS if valid else None,
+            "valu_busy": meas["valu_busy"] if valid else None,
             "profile": meas["profile"] if valid else None,
             "pf_particle_steps_per_s": per_launch / launch_s}
 
