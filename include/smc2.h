@@ -104,8 +104,9 @@ extern "C" {
                            held-out pairs                                                */
 #define SMC2_PROP_LANGEVIN 2 /* truncated Langevin proposal (SIR, SEIR, SMC2_LINGAUSS):
                                 phi' = phi + delta + L z, Sigma = L L' the weighted covariance
-                                of the proposing population, delta = 1/2 Sigma g shrunk to
-                                Mahalanobis length <= 1, g the gradient of log(prior x
+                                of the proposing population, delta = s times 1/2 Sigma g
+                                shrunk to Mahalanobis length <= 1 (s = lgv_step, 1/4 by
+                                default), g the gradient of log(prior x
                                 likelihood) on the sampler coordinates from the filter's
                                 score estimate (smc2_pf_score's), which travels with its
                                 sample; its exact log q enters the weights (Eq. l_weights) */
@@ -183,6 +184,8 @@ typedef struct {
     int32_t pf_resampling; /* SMC2_PF_RS_*: the particle filters' resampling scheme       */
     int32_t mlp_train;     /* SMC2_MLP_TRAIN_*: how the learned proposal's training is laid
                               out on the device (same mathematics, FP32 rounding aside)   */
+    double lgv_step;       /* SMC2_PROP_LANGEVIN: the fraction of the truncated drift
+                              applied, in (0, 1]; 0 selects 1/4                           */
 } smc2_config;
 
 typedef struct {

@@ -32,6 +32,7 @@ class Config(ctypes.Structure):
         ("prior", (ctypes.c_double * 3) * DMAX), ("rw_cov", (ctypes.c_double * DMAX) * DMAX),
         ("fixed", ctypes.c_double * NFIXED), ("mlp_epochs", ctypes.c_int32), ("mlp_batch", ctypes.c_int32),
         ("mlp_lr", ctypes.c_double), ("pf_resampling", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("lgv_step", ctypes.c_double),
     ]
 
 
@@ -159,12 +160,13 @@ def _declare(L):
 
 def make_config(model, obs, D, prec, n_pop, prior, rw_cov, fixed=(), lkernel=L_GAUSS_OPT,
                 proposal=PROP_RW, pf_always=0, mlp_epochs=4, mlp_batch=256, mlp_lr=1e-3,
-                pf_resampling=RS_SYSTEMATIC):
+                pf_resampling=RS_SYSTEMATIC, lgv_step=0.0):
     cfg = Config()
     cfg.mlp_epochs, cfg.mlp_batch, cfg.mlp_lr = int(mlp_epochs), int(mlp_batch), float(mlp_lr)
     cfg.model, cfg.obs, cfg.D, cfg.prec = model, obs, D, prec
     cfg.pf_always, cfg.lkernel, cfg.proposal = pf_always, lkernel, proposal
     cfg.pf_resampling = int(pf_resampling)
+    cfg.lgv_step = float(lgv_step)
     cfg.n_pop = float(n_pop)
     prior = np.asarray(prior, dtype=np.float64).reshape(D, 3)
     rw = np.asarray(rw_cov, dtype=np.float64).reshape(D, D)
@@ -185,7 +187,8 @@ def config_from_workload(w, prec=None):
     return make_config(w["model"], w["obs"], w["D"], w["prec"] if prec is None else prec, w["n_pop"],
                        w["prior"], w["rw_cov"], w.get("fixed", ()), w.get("lkernel", L_GAUSS_OPT),
                        w.get("proposal", PROP_RW), w.get("pf_always", 0), w.get("mlp_epochs", 4),
-                       w.get("mlp_batch", 256), w.get("mlp_lr", 1e-3), w.get("pf_resampling", RS_SYSTEMATIC))
+                       w.get("mlp_batch", 256), w.get("mlp_lr", 1e-3), w.get("pf_resampling", RS_SYSTEMATIC),
+                       w.get("lgv_step", 0.0))
 
 
 def philox(ctr, key):

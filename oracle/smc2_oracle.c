@@ -381,10 +381,11 @@ double or_propose_langevin_one(const or_config* cfg, const double* L, const doub
     }
     const double len = 0.5 * sqrt(n2);
     const double shrink = len > 1.0 ? 1.0 / len : 1.0;
+    const double step = cfg->lgv_step > 0.0 ? cfg->lgv_step : 0.25;
     for (int a = 0; a < D; ++a) {
         double acc = 0.0;
         for (int c = 0; c <= a; ++c) acc += L[a * D + c] * v[c];
-        delta[a] = (0.5 * acc) * shrink;
+        delta[a] = step * ((0.5 * acc) * shrink);
     }
     for (int d = 0; d < D; ++d) {
         uint32_t ctr[4] = {(uint32_t)i, 0u, k << 16, ((uint32_t)OR_S_RW << 24) | (uint32_t)d};

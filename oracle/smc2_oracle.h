@@ -63,6 +63,8 @@ typedef struct {
     double mlp_lr;                 /* learned proposal: Adam learning rate */
     int32_t pf_resampling;         /* OR_RS_SYSTEMATIC or OR_RS_MULTINOMIAL (the particle filter's) */
     int32_t pad;
+    double lgv_step;               /* Langevin proposal: the fraction of the truncated drift
+                                      applied, in (0, 1]; 0 selects 1/4 */
 } or_config;
 
 /* Number of doubles in one per-iteration record. */
@@ -188,10 +190,11 @@ double or_pf_score(const or_config* cfg, const double* theta, const int32_t* y, 
 double or_digamma(double x);
 
 /* The truncated Langevin proposal of sample phi given the score estimate s_theta (on the
- * natural parameters) that travelled with it: the drift delta = 1/2 Sigma g with
+ * natural parameters) that travelled with it: the drift 1/2 Sigma g with
  * g = J s_theta + grad log prior(phi) (J = d theta / d phi per coordinate), shrunk to a
- * Mahalanobis length of at most 1 (|L^-1 delta| <= 1, L L' = Sigma), and
- * phi_new = phi + delta + L z with z the random walk's normals of sample i at iteration k.
+ * Mahalanobis length of at most 1 (|L^-1 . | <= 1, L L' = Sigma), times the step fraction
+ * s = cfg->lgv_step (1/4 when 0): delta; phi_new = phi + delta + L z with z the random
+ * walk's normals of sample i at iteration k.
  * Returns log q(phi_new | phi) = log N(phi_new; phi + delta, Sigma). The sampler takes
  * Sigma as the weighted covariance of the proposing population (L its frame's factor,
  * or_mlp_frame). */

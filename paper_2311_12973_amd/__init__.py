@@ -61,7 +61,7 @@ class Config(ctypes.Structure):
                 ("fixed", ctypes.POINTER(ctypes.c_double)), ("n_fixed", ctypes.c_int32),
                 ("tune", ctypes.c_int32), ("persistent", ctypes.c_int32), ("mlp_epochs", ctypes.c_int32),
                 ("mlp_batch", ctypes.c_int32), ("mlp_lr", ctypes.c_double), ("pf_resampling", ctypes.c_int32),
-                ("mlp_train", ctypes.c_int32)]
+                ("mlp_train", ctypes.c_int32), ("lgv_step", ctypes.c_double)]
 
 
 class Run(ctypes.Structure):
@@ -225,6 +225,7 @@ def make_config(w, N=None, K=None, precision=None, use_graph=0, block=0, lkernel
     c.tune, c.persistent = int(tune), int(persistent)
     c.pf_resampling = int(w.get("pf_resampling", PF_RS_SYSTEMATIC))
     c.mlp_train = int(w.get("mlp_train", MLP_TRAIN_AUTO))
+    c.lgv_step = float(w.get("lgv_step", 0.0))
     c.n_pop = float(w["n_pop"])
     dp = ctypes.POINTER(ctypes.c_double)
     c.prior = keep.prior.ctypes.data_as(dp)

@@ -56,6 +56,7 @@ struct OuterParams {
     int32_t langevin;    // 1: the truncated Langevin proposal is configured (drift + scores)
     int32_t popcov;      // 1: the proposal covariance is the proposing population's (the
                          //    Langevin proposal and the population random walk)
+    double lgv_step;     // Langevin proposal: the fraction of the truncated drift applied
 };
 
 // model parameter theta_d from the sampler coordinate phi_d of a prior family

@@ -96,9 +96,9 @@ __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, c
         } else if (p.popcov) {
             // Sigma = L L' the weighted covariance of the proposing population; phi' = m + L z.
             // The population random walk: m = phi. The truncated Langevin proposal:
-            // m = phi + delta, delta = 1/2 Sigma g with g the gradient of log(prior x
-            // likelihood) on the sampler coordinates, from the score estimate that travelled
-            // with the sample, shrunk to Mahalanobis length 1.
+            // m = phi + delta, delta = s times 1/2 Sigma g shrunk to Mahalanobis length 1, g
+            // the gradient of log(prior x likelihood) on the sampler coordinates from the
+            // score estimate that travelled with the sample, s the step fraction.
             const double* ph = o.phi + (size_t)g * D;
             const double* Lq = o.pop_chol + (size_t)r * D * D;
             double m[D];
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(256) k_propose(OuterArrays o, OuterParams p, c
                     double acc = 0.0;
 #pragma unroll
                     for (int c = 0; c <= a; ++c) acc += Lq[a * D + c] * v[c];
-                    m[a] = ph[a] + (0.5 * acc) * shrink;
+                    m[a] = ph[a] + p.lgv_step * ((0.5 * acc) * shrink);
                 }
             }
 #pragma unroll

@@ -216,6 +216,7 @@ static int validate(const smc2_config* c, int32_t R, const smc2_run* runs, std::
     if (c->proposal != SMC2_PROP_RW && c->proposal != SMC2_PROP_MLP && c->proposal != SMC2_PROP_LANGEVIN &&
         c->proposal != SMC2_PROP_RW_POP)
         return m = "unknown proposal", SMC2_E_UNSUPPORTED;
+    if (!(c->lgv_step >= 0.0 && c->lgv_step <= 1.0)) return m = "lgv_step must be in [0, 1]", SMC2_E_ARG;
     if (c->proposal == SMC2_PROP_LANGEVIN && pf_score_dims(c->model) == 0)
         return m = "the Langevin proposal needs the filter's score (SIR, SEIR, linear-Gaussian)", SMC2_E_UNSUPPORTED;
     if (c->proposal == SMC2_PROP_MLP) {
@@ -579,6 +580,7 @@ extern "C" int smc2_init(const smc2_config* cfg, int32_t n_runs, const smc2_run*
     p.mlp = mlp ? 1 : 0;
     p.langevin = lgv ? 1 : 0;
     p.popcov = popcov ? 1 : 0;
+    p.lgv_step = cfg->lgv_step > 0.0 ? cfg->lgv_step : 0.25;
     {
         MlpParams& q = c->mp;
         q.D = cfg->D;

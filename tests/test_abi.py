@@ -44,8 +44,12 @@ def test_workspace_bytes_and_validation():
     assert 3 * 1024 * 4 * 8 < nb < 1 << 20  # O(N D) doubles: particles never leave the chip
     bad = [dict(N=1), dict(N=40000), dict(K=0), dict(precision=3), dict(block=96), dict(block=2048),
            dict(schedule=3), dict(schedule=-1), dict(persistent=3), dict(persistent=-1)]
+    bad_w = [dict(lgv_step=-0.1), dict(lgv_step=1.5), dict(lgv_step=float("nan"))]
     for over in bad:
         c = G.make_config(w, **over)
+        assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == 0, over
+    for over in bad_w:
+        c = G.make_config(dict(w, **over))
         assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == 0, over
     c = G.make_config(dict(w, D=3, prior=w["prior"][:3], rw_cov=np.eye(3).tolist()))
     assert L.smc2_workspace_bytes(ctypes.byref(c), 1, runs) == 0

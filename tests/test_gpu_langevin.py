@@ -27,8 +27,8 @@ def _log(msg):
     print(msg, flush=True)
 
 
-def _run_pair(w, N, K, nx, T=None, seed=1, lkernel=None, prec=None):
-    w = dict(w, proposal=G.PROP_LANGEVIN)
+def _run_pair(w, N, K, nx, T=None, seed=1, lkernel=None, prec=None, step=0.0):
+    w = dict(w, proposal=G.PROP_LANGEVIN, lgv_step=step)
     if T is not None:
         w["T"] = T
     if lkernel is not None:
@@ -83,15 +83,16 @@ def _compare(gpu, ref, D, tol_ll):
                                                                                      worst["logw"]))
 
 
-@pytest.mark.parametrize("name,N,K,nx,T,lkernel,prec,tol_ll", [
-    ("sir_fp64", 64, 5, 64, None, None, None, 1e-9),
-    ("seir", 256, 4, 128, 40, G.L_FORWARD, None, 1e-4),
-    ("seir_learned", 128, 4, 96, 30, None, G.PREC_FP64, 1e-9),
+@pytest.mark.parametrize("name,N,K,nx,T,lkernel,prec,tol_ll,step", [
+    ("sir_fp64", 64, 5, 64, None, None, None, 1e-9, 0.0),
+    ("seir", 256, 4, 128, 40, G.L_FORWARD, None, 1e-4, 0.0),
+    ("seir_learned", 128, 4, 96, 30, None, G.PREC_FP64, 1e-9, 0.0),
+    ("seir_learned", 128, 4, 96, 30, None, G.PREC_FP64, 1e-9, 1.0),
 ])
-def test_langevin_sampler_matches_reference(name, N, K, nx, T, lkernel, prec, tol_ll):
+def test_langevin_sampler_matches_reference(name, N, K, nx, T, lkernel, prec, tol_ll, step):
     w = W.preset(name)
-    _log("Langevin %s N=%d K=%d nx=%d" % (name, N, K, nx))
-    gpu, ref, cfg, y = _run_pair(w, N, K, nx, T=T, lkernel=lkernel, prec=prec)
+    _log("Langevin %s N=%d K=%d nx=%d step=%g" % (name, N, K, nx, step))
+    gpu, ref, cfg, y = _run_pair(w, N, K, nx, T=T, lkernel=lkernel, prec=prec, step=step)
     _compare(gpu, ref, w["D"], tol_ll)
     assert np.all(gpu["rec"][1:, -2] == 2) and gpu["rec"][0, -2] == 0
     # the proposals' scores: the reference's score estimates of the same filters

@@ -132,7 +132,9 @@ def test_score_pins_catch_a_broken_score(planted_libs, name):
 def test_langevin_pin_catches_an_inexact_weight(planted_libs, name):
     from tests.test_oracle_langevin import langevin_grid_statistic
     with PL.installed(planted_libs[name]):
-        ests, second, grid_mean, grid_sd, _ = langevin_grid_statistic()
+        # at the full step the weight's error is large enough for the grid test to see; at
+        # the default quarter step the proposal is nearly symmetric and the error small
+        ests, second, grid_mean, grid_sd, _ = langevin_grid_statistic(step=1.0)
     se = ests.std(0, ddof=1) / np.sqrt(len(ests))
     pooled_sd = np.sqrt(second.mean(0) - ests.mean(0) ** 2)
     print(name, ests.mean(0), grid_mean, se, pooled_sd / grid_sd)
