@@ -57,6 +57,7 @@ CASES = [  # workload, overrides, N, K, nx, filter schedule
     ("seir", dict(T=40), 256, 4, 96, G.SCHED_POOLED),
     ("seir_learned", dict(T=30, prec=G.PREC_FP64), 128, 4, 96, G.SCHED_PER_DRAW),
     ("age_seir", dict(T=12), 48, 3, 64, G.SCHED_AUTO),
+    ("sir_fp64", dict(T=30, pf_resampling=G.PF_RS_MULTINOMIAL, pf_always=1), 64, 4, 64, G.SCHED_AUTO),
 ]
 
 

@@ -57,6 +57,8 @@ CASES = [  # workload, overrides, precision, nx, T, block
     ("seir", {}, G.PREC_FP64, 300, 40, 1024),
     ("seir_learned", {}, G.PREC_FP32, 1000, 50, 256),
     ("seir_learned", {}, G.PREC_FP64, 1, 30, 0),
+    ("sir_fp64", {"pf_resampling": G.PF_RS_MULTINOMIAL}, G.PREC_FP64, 100, None, 0),
+    ("seir", {"pf_resampling": G.PF_RS_MULTINOMIAL, "pf_always": 1}, G.PREC_FP32, 300, 40, 256),
 ]
 
 
