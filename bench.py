@@ -515,7 +515,7 @@ def paper_experiment(G, W, np, seed=1):
 
 
 def ess_at_fixed_error(G, W, np, n_ref=32768, k_ref=(30, 60), ref_seeds=3, seeds=10, k_max=(20, 60, 60, 60),
-                       thresholds=(0.05, 0.1, 0.15, 0.2, 0.25, 0.3)):
+                       thresholds=(0.05, 0.1, 0.15, 0.2, 0.25, 0.3), seed0=1):
     """ESS per second at a fixed posterior error, learned proposal against the random
     walk (and, against the same random walk, the truncated Langevin proposal driven by
     the filters' score estimates and the random walk with the population's covariance),
@@ -585,7 +585,7 @@ def ess_at_fixed_error(G, W, np, n_ref=32768, k_ref=(30, 60), ref_seeds=3, seeds
              ("rw_pop", G.PROP_RW_POP))
     for (name, prop), kmax in zip(forms, k_max):
         log("ess: %s, %d runs at N=%d, up to K=%d" % (name, seeds, N, kmax))
-        s = G.Sampler(dict(w, proposal=prop), [run(sd) for sd in range(1, seeds + 1)], N=N, K=kmax)
+        s = G.Sampler(dict(w, proposal=prop), [run(sd) for sd in range(seed0, seed0 + seeds)], N=N, K=kmax)
         t_cum = 0.0
         first = {th: [None] * seeds for th in thresholds}
         rate = {th: [None] * seeds for th in thresholds}
