@@ -167,6 +167,26 @@ struct ScoreDay {
     bool nr;
 };
 
+// Issue priority of a wave from its progress through the day's draws, step of total (a
+// particle pass times the model's draw groups): 3 in the first quarter of its work, down
+// to 0 in the last. The waves of a filter meet at a barrier after the draws, and their
+// draws take different times (attempts, final tests, inversion lengths differ): a wave
+// that has done less of its day outranks one near its end, so the laggards catch up and
+// the barrier waits shrink (age-structured SEIR, one filter per CU: 1418 -> 1282 ms per
+// launch). Results do not depend on it: it only orders instruction issue.
+__device__ __forceinline__ void progress_priority(int step, int total)
+{
+    const int q = uniform_i32((4 * step) / total);
+    if (q <= 0) __builtin_amdgcn_s_setprio(3);
+    else if (q == 1) __builtin_amdgcn_s_setprio(2);
+    else if (q == 2) __builtin_amdgcn_s_setprio(1);
+    else __builtin_amdgcn_s_setprio(0);
+}
+
+// Draw groups of a particle-day, the steps of progress_priority: SIR's two draws, SEIR's
+// three, the age-structured model's four groups, the linear-Gaussian model's one normal.
+template <int MODEL> struct DrawGroups { static constexpr int G = MODEL == MODEL_SIR ? 2 : (MODEL == MODEL_SEIR ? 3 : (MODEL == MODEL_AGE ? 4 : 1)); };
+
 // One day of the chain-binomial model for particle j, whose counts live in LDS
 // (st[c * cap + j]); flows drawn from the previous day's state. Draw index b:
 // SIR (S->I, I->R) = (0, 1); SEIR (S->E, E->I, I->R) = (0, 1, 2); age-structured
@@ -175,14 +195,18 @@ struct ScoreDay {
 // loop. Returns the per-particle part of log g(y_t | x_t) in FP64. With SCORE it adds
 // the day's complete-data score to the particle's: per flow d log Bin / d h times
 // d h / d theta (I / N_pop for beta, 1 for sigma and gamma), d log g / d r, and for the
-// linear-Gaussian model the derivatives of its two Gaussian densities.
+// linear-Gaussian model the derivatives of its two Gaussian densities. With ptotal > 0
+// each draw group first sets the wave's issue priority (progress_priority, step pbase +
+// group of ptotal).
 template <typename real, int MODEL, int OBS, bool SCORE = false>
 __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* st, int cap, int j,
-                                               DrawStream ds, const int32_t* yt, const ScoreDay& sd = ScoreDay{})
+                                               DrawStream ds, const int32_t* yt, const ScoreDay& sd = ScoreDay{},
+                                               int pbase = 0, int ptotal = 0)
 {
     if constexpr (MODEL == MODEL_LG) {
         // x_t = ar x_{t-1} + sq e_t; log g = -z^2 / 2 with z = (y_t - x_t) / sr (the
         // constant -log sr - log(2 pi) / 2 goes with the day's constant)
+        if (ptotal > 0) progress_priority(pbase, ptotal);
         const double x = __hiloint2double(st[cap + j], st[j]);
         const double e = normal_key(ds.j, ds.i, ds.kt, S_LG << 24, ds.k0, ds.k1);
         const double x1 = mc.ar * x + mc.sq * e;
@@ -202,6 +226,7 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
         int32_t nsi = 0, nir = 0;
 #pragma nounroll
         for (int b = 0; b < 2; ++b) {
+            if (ptotal > 0) progress_priority(pbase + b, ptotal);
             ds.b = (uint32_t)b;
             const int32_t v = binomial<real>(b == 0 ? S : I, b == 0 ? p_si : mc.p_ir, ds, b == 0 ? NAN : mc.l1p_ir);
             nsi = b == 0 ? v : nsi;
@@ -221,6 +246,7 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
         int32_t nse = 0, nei = 0, nir = 0;
 #pragma nounroll
         for (int b = 0; b < 3; ++b) {
+            if (ptotal > 0) progress_priority(pbase + b, ptotal);
             ds.b = (uint32_t)b;
             const int32_t n = b == 0 ? S : (b == 1 ? E : I);
             const real p = b == 0 ? p_se : (b == 1 ? mc.p_ei : mc.p_ir);
@@ -264,6 +290,7 @@ __device__ __forceinline__ double particle_day(const MConst<real>& mc, int32_t* 
         double lg = 0.0;
 #pragma nounroll
         for (int g = 0; g < 4; ++g) {
+            if (ptotal > 0) progress_priority(pbase + g, ptotal);
             const int32_t S = st[(3 * g) * cap + j], E = st[(3 * g + 1) * cap + j], I = st[(3 * g + 2) * cap + j];
             const real p_se = g == 0 ? pse0 : (g == 1 ? pse1 : (g == 2 ? pse2 : pse3));
             int32_t nse = 0, nei = 0, nir = 0;
@@ -741,9 +768,13 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
                 amax = av > amax ? av : amax;
             }
         } else {
-            for (int j = tid; j < nx; j += nthr) {
+            // without the filter-level priority, each wave's from its progress through the day
+            constexpr int G = DrawGroups<MODEL>::G;
+            const int ptotal = a.prio_scale > 0.f ? 0 : (cap / nthr) * G;
+            for (int j = tid, pass = 0; j < nx; j += nthr, ++pass) {
                 const double lg = particle_day<real, MODEL, OBS, SCORE>(
-                    mc, st, cap, j, DrawStream{(uint32_t)j, filt, kt, 0u, run.k0, run.k1}, yt, sd);
+                    mc, st, cap, j, DrawStream{(uint32_t)j, filt, kt, 0u, run.k0, run.k1}, yt, sd, pass * G,
+                    ptotal);
                 const real av = lw[j] + (real)lg;
                 lw[j] = av;
                 amax = av > amax ? av : amax;
