@@ -850,12 +850,26 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
             __syncthreads();
             if (a.trace_anc)
                 for (int j = tid; j < nx; j += nthr) a.trace_anc[((size_t)g * T + (t - 1)) * nx + j] = anc[j];
+            // the ancestors' words (counts, then the score words), three at a time through the
+            // staging rows: tmp and the weights' row C, free once the ancestors are drawn. A
+            // barrier separates each group's reads from its writes; each thread touches only
+            // its own staging slots, so the next group needs none before it
+            constexpr int NW = NC + 2 * NS;
+            int32_t* stage = reinterpret_cast<int32_t*>(C);
 #pragma unroll
-            for (int c = 0; c < NC + 2 * NS; ++c) {  // counts, then the score words
-                int32_t* sc = st + c * cap;
-                for (int j = tid; j < nx; j += nthr) tmp[j] = sc[anc[j]];
+            for (int c0 = 0; c0 < NW; c0 += 3) {
+                for (int j = tid; j < nx; j += nthr) {
+                    const int aj = anc[j];
+                    tmp[j] = st[c0 * cap + aj];
+                    if (c0 + 1 < NW) stage[j] = st[(c0 + 1) * cap + aj];
+                    if (c0 + 2 < NW) stage[cap + j] = st[(c0 + 2) * cap + aj];
+                }
                 __syncthreads();
-                for (int j = tid; j < nx; j += nthr) sc[j] = tmp[j];
+                for (int j = tid; j < nx; j += nthr) {
+                    st[c0 * cap + j] = tmp[j];
+                    if (c0 + 1 < NW) st[(c0 + 1) * cap + j] = stage[j];
+                    if (c0 + 2 < NW) st[(c0 + 2) * cap + j] = stage[cap + j];
+                }
             }
             for (int j = tid; j < nx; j += nthr) lw[j] = (real)0;
             log_prev = log_nx;
