@@ -60,11 +60,11 @@ KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_a
                   "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h",
                   "paper_2311_12973_amd/build.py"]
 MEASURED = {
-    "age_seir": dict(sha="e03c6167134131e1", valu_lane_instr_per_pstep=2413.0, hbm_bytes_per_launch=10292082366,
-                     valu_busy=0.9921,
+    "age_seir": dict(sha="b9e8b2eb2de00730", valu_lane_instr_per_pstep=2397.1, hbm_bytes_per_launch=10388810800,
+                     valu_busy=0.9936,
                      profile="profiles/pf_kernel_age_seir_n16384_nx2048_t365.txt"),
-    "seir": dict(sha="e03c6167134131e1", valu_lane_instr_per_pstep=1419.2, hbm_bytes_per_launch=1090429,
-                 valu_busy=0.9870,
+    "seir": dict(sha="b9e8b2eb2de00730", valu_lane_instr_per_pstep=1416.9, hbm_bytes_per_launch=1088381,
+                 valu_busy=0.9904,
                  profile="profiles/pf_kernel_seir_n1024_nx512_t100.txt"),
 }
 
