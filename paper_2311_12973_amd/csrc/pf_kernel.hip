@@ -640,7 +640,7 @@ __device__ __forceinline__ void multinomial_ancestors(const uint64_t* C, int n, 
 }
 
 // LDS layout of one filter (cap = particles rounded up to the block size):
-//   C   u64[cap]     quantised weights, then their inclusive scan
+//   C   u64[cap]     quantised weights, then their inclusive scan (then two gather staging rows)
 //   tmp i32[cap]     gather staging
 //   anc i32[cap]     ancestors            (C, tmp, anc hold the flows while drawing)
 //   red RedLds       reduction slots
