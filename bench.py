@@ -60,11 +60,11 @@ KERNEL_SOURCES = ["paper_2311_12973_amd/csrc/pf_kernel.hip", "paper_2311_12973_a
                   "paper_2311_12973_amd/csrc/device_common.h", "paper_2311_12973_amd/csrc/block_ops.h",
                   "paper_2311_12973_amd/build.py"]
 MEASURED = {
-    "age_seir": dict(sha="b9e8b2eb2de00730", valu_lane_instr_per_pstep=2397.1, hbm_bytes_per_launch=10388810800,
-                     valu_busy=0.9936,
+    "age_seir": dict(sha="44d6452744a009f5", valu_lane_instr_per_pstep=2397.1, hbm_bytes_per_launch=10341702729,
+                     valu_busy=0.9934,
                      profile="profiles/pf_kernel_age_seir_n16384_nx2048_t365.txt"),
-    "seir": dict(sha="b9e8b2eb2de00730", valu_lane_instr_per_pstep=1416.9, hbm_bytes_per_launch=1088381,
-                 valu_busy=0.9904,
+    "seir": dict(sha="44d6452744a009f5", valu_lane_instr_per_pstep=1416.9, hbm_bytes_per_launch=1088383,
+                 valu_busy=0.9889,
                  profile="profiles/pf_kernel_seir_n1024_nx512_t100.txt"),
 }
 
