@@ -186,7 +186,9 @@ __device__ __forceinline__ void progress_priority(int step, int total)
 
 // Draw groups of a particle-day, the steps of progress_priority: SIR's two draws, SEIR's
 // three, the age-structured model's four groups, the linear-Gaussian model's one normal.
-template <int MODEL> struct DrawGroups { static constexpr int G = MODEL == MODEL_SIR ? 2 : (MODEL == MODEL_SEIR ? 3 : (MODEL == MODEL_AGE ? 4 : 1)); };
+template <int MODEL> struct DrawGroups {
+    static constexpr int G = MODEL == MODEL_SIR ? 2 : (MODEL == MODEL_SEIR ? 3 : (MODEL == MODEL_AGE ? 4 : 1));
+};
 
 // One day of the chain-binomial model for particle j, whose counts live in LDS
 // (st[c * cap + j]); flows drawn from the previous day's state. Draw index b:
