@@ -329,6 +329,31 @@ def test_automatic_launch_is_persistent_beyond_one_round():
             assert np.array_equal(np.nan_to_num(a, neginf=-1e300), np.nan_to_num(b, neginf=-1e300))
 
 
+@pytest.mark.gpu
+@pytest.mark.parametrize("preset,over", [("seir", dict(schedule=1)), ("age_seir", {})])
+def test_filter_estimates_do_not_depend_on_the_issue_priority(preset, over):
+    """The per-draw filter's issue priority comes from the filter's remaining work when a
+    launch holds every filter at once, and from each wave's progress through its day when
+    it runs several rounds. Either only orders instruction issue: the first iteration's
+    estimates of samples 0..63 (their prior draws and streams do not depend on N) are the
+    same bits in a launch of 64 filters and in one of 32768."""
+    w = dict(W.preset(preset), T=12)
+    y = W.observations(w)
+    run = [dict(T=12, nx=48, seed=5, y=y)]
+    out = {}
+    for N in (64, 32768):
+        s = G.Sampler(w, run, N=N, K=1, **over)
+        s.step()
+        out[N] = (s.groups(), s.dump("ll_new")[:64])
+        s.close()
+    _log("%s groups: N=64 %s, N=32768 %s" % (preset, out[64][0], out[32768][0]))
+    assert all(g["persistent"] == 0 and g["schedule"] == 1 for g in out[64][0])
+    assert all(g["persistent"] == 1 and g["schedule"] == 1 for g in out[32768][0])
+    a, b = (np.nan_to_num(out[N][1], neginf=-1e300) for N in (64, 32768))
+    assert np.isfinite(out[64][1]).sum() >= 16  # prior draws far from the data give -inf
+    assert np.array_equal(a, b)
+
+
 def test_batched_matches_reference_per_run():
     """Two uneven runs of the batched workload against the reference run by run."""
     w = W.preset("seir_batched")
