@@ -772,8 +772,9 @@ __device__ __attribute__((always_inline)) inline void pf_filter(const PFArgs& a,
             }
         } else {
             // without the filter-level priority, each wave's from its progress through the day;
-            // not in score launches, whose two filters per CU ran 4% slower with it (the plain
-            // per-draw launch at four filters per CU ran 3-5% faster, one per CU 6-7%)
+            // not in score launches, whose two filters per CU ran 4% slower with it over 4096
+            // filters (1% faster over 40960; the plain per-draw launch at four filters per CU
+            // ran 3-5% faster, one per CU 6-7%)
             constexpr int G = DrawGroups<MODEL>::G;
             const int ptotal = (SCORE || a.prio_scale > 0.f) ? 0 : (cap / nthr) * G;
             for (int j = tid, pass = 0; j < nx; j += nthr, ++pass) {
